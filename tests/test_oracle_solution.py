@@ -1,0 +1,199 @@
+"""Pins of the oracle's matrix, right-hand side, preconditioner and solvers (CPU only)."""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from paper_2310_09204_amd import meshes
+from oracle.assemble import assemble, pair_matrix, rhs
+from oracle.precond import AdditiveSchwarz, classify_dofs, coarse_prolongation
+from oracle.solve import cholesky_solve, lanczos_cond, pcg, spectral_cond
+from oracle.topology import Topology
+
+NEAR = 10
+
+
+def _problem(m, g=(0, 0, 1)):
+    t = Topology(m.vertices, m.triangles)
+    W = assemble(m.vertices, m.triangles, t, NEAR)
+    L = rhs(t, g)[:, 0]
+    return t, W, L
+
+
+def test_W_symmetric_positive_definite_on_junctions():
+    for m in (meshes.book(4), meshes.crossed(4), meshes.bowtie(3)):
+        t, W, L = _problem(m, (0.3, -0.5, 0.8))
+        assert np.array_equal(W, W.T)
+        assert np.linalg.eigvalsh(W)[0] > 0.0      # coercivity, Thm. lemequivInner
+
+
+def test_flat_screen_is_four_times_standard_hypersingular():
+    # manifold case: the jump basis is 2 lambda_v, so W = 4 W_std with
+    # W_std[v,w] = sum_{T,T'} I(T,T') curl lambda_v^T . curl lambda_w^T'
+    m = meshes.unit_square(5)
+    t, W, L = _problem(m)
+    I = pair_matrix(m.vertices, m.triangles, NEAR)
+    interior = [v for v in range(t.nv) if t.q[v] == 2]
+    Cm = np.zeros((t.nt, 3, len(interior)))
+    idx = {v: k for k, v in enumerate(interior)}
+    for tr in range(t.nt):
+        for a in range(3):
+            v = int(t.T[tr, a])
+            if v in idx:
+                Cm[tr, :, idx[v]] = t.curl[tr, a]
+    Wstd = sum(Cm[:, k, :].T @ I @ Cm[:, k, :] for k in range(3))
+    perm = [t.dof_index[(v, 0)] for v in interior]
+    assert np.allclose(W[np.ix_(perm, perm)], 4.0 * Wstd, rtol=1e-12, atol=1e-14 * np.abs(W).max())
+    # and L = 2 L_std with L_std = -int (g.n) lambda_v
+    Lstd = np.zeros(len(interior))
+    for tr in range(t.nt):
+        for a in range(3):
+            v = int(t.T[tr, a])
+            if v in idx:
+                Lstd[idx[v]] -= t.normal[tr, 2] * t.area[tr] / 3.0
+    assert np.allclose(L[perm], 2.0 * Lstd, rtol=1e-14)
+
+
+def test_disk_energy_converges_to_closed_form_from_below():
+    # flat unit disk, g = e_z: the jump is -(4/pi) sqrt(1-r^2) and a(phi, phi) = 8/3
+    energies, errs = [], []
+    for rings in (4, 8, 12):
+        m = meshes.disk(rings)
+        t, W, L = _problem(m)
+        phi = cholesky_solve(W, L)
+        energies.append(float(L @ phi))
+        r = np.linalg.norm(m.vertices[[v for v, j in t.dofs]][:, :2], axis=1)
+        inner = r <= 0.5
+        errs.append(np.abs(phi - (-(2.0 / math.pi) * np.sqrt(1.0 - r ** 2)))[inner].max())
+    E = 8.0 / 3.0
+    assert all(e < E for e in energies)
+    assert energies[0] < energies[1] < energies[2]
+    # roughly first order in h
+    rate = math.log((E - energies[0]) / (E - energies[2])) / math.log(12 / 4)
+    assert 0.7 < rate < 1.5
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 0.01
+
+
+def test_symmetric_crossed_reduces_to_flat_square():
+    # reflection-symmetric mesh, g = e_z: zero jump on the xz and yz panels and the xy panel carries
+    # the flat-square solution
+    n = 6
+    mc = meshes.crossed(n, symmetric=True)
+    tc, Wc, Lc = _problem(mc)
+    phic = cholesky_solve(Wc, Lc)
+    jc = tc.jump_values(phic)
+    ms = meshes.square_symmetric(n)
+    ts, Ws, Ls = _problem(ms)
+    js = ts.jump_values(cholesky_solve(Ws, Ls))
+    on_xy = mc.tri_panel == 0
+    scale = np.abs(js).max()
+    assert np.abs(jc[~on_xy]).max() < 1e-9 * scale
+    assert np.abs(jc[on_xy] - js).max() < 1e-9 * scale
+
+
+def test_book_rotation_symmetry():
+    # rotating g by 120 degrees about the spine rotates the solution among the pages
+    m = meshes.book(4)
+    t = Topology(m.vertices, m.triangles)
+    W = assemble(m.vertices, m.triangles, t, NEAR)
+    g = np.array([0.3, 0.7, -0.2])
+    c, s = math.cos(2 * math.pi / 3), math.sin(2 * math.pi / 3)
+    Rz = np.array([[c, -s, 0], [s, c, 0], [0, 0, 1]])
+    j0 = t.jump_values(cholesky_solve(W, rhs(t, g)[:, 0]))
+    j1 = t.jump_values(cholesky_solve(W, rhs(t, Rz @ g)[:, 0]))
+    ntp = m.nt // 3
+    # page k rotated onto page k+1: same local triangle index, same corner
+    for k in range(3):
+        a = j0[k * ntp:(k + 1) * ntp]
+        b = j1[((k + 1) % 3) * ntp:((k + 1) % 3 + 1) * ntp]
+        assert np.abs(a - b).max() < 1e-10 * np.abs(j0).max()
+
+
+def test_pcg_matches_cholesky_and_lanczos():
+    w = meshes.workload("square16")
+    t, W, L = _problem(w.mesh)
+    P = AdditiveSchwarz(W, t, w.patch_of_triangle, w.coarse.vertices, w.coarse.triangles,
+                        w.coarse_of_triangle)
+    assert [len(f) for f in P.face_sets] == [49, 49, 49, 49] and len(P.wb) == 29
+    assert P.RH.shape == (1, 225)
+    x, it, rr, a, b = pcg(W, L, P.apply, tol=1e-12)
+    xs = cholesky_solve(W, L)
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) < 1e-10
+    Md = P.dense(t.N)
+    assert np.allclose(Md, Md.T, atol=1e-12)
+    k_dense = spectral_cond(W, 0.5 * (Md + Md.T))
+    # a symmetric right-hand side only excites the symmetric modes: Lanczos on a random one
+    brand = np.random.default_rng(5).standard_normal(t.N)
+    _, _, _, ar, br = pcg(W, brand, P.apply, tol=1e-14)
+    assert abs(lanczos_cond(ar, br) - k_dense) < 1e-3 * k_dense
+    # energy-norm error bound of the PCG remark: a(e_n,e_n)^1/2 <= 2 rho^n a(e_0,e_0)^1/2
+    rho = (math.sqrt(k_dense) - 1) / (math.sqrt(k_dense) + 1)
+    for n in range(1, it):
+        xn, _, _, _, _ = pcg(W, L, P.apply, tol=0.0, max_iter=n)
+        e = xn - xs
+        assert math.sqrt(e @ W @ e) <= 2 * rho ** n * math.sqrt(xs @ W @ xs) * (1 + 1e-9)
+
+
+def test_preconditioner_special_cases():
+    m = meshes.unit_square(8)
+    t, W, L = _problem(m)
+    # one patch holding every dof, no coarse space: M = W^{-1}, PCG converges in one step
+    P = AdditiveSchwarz(W, t, np.zeros(m.nt, dtype=np.int32), use_coarse=False)
+    assert len(P.wb) == 0
+    _, it, rr, _, _ = pcg(W, L, P.apply, tol=1e-10)
+    assert it == 1
+    # singleton blocks: M = diag(W)^{-1} (Jacobi)
+    P = AdditiveSchwarz(W, t, face_sets=[np.array([d]) for d in range(t.N)],
+                        wb=np.array([], dtype=np.int64), use_coarse=False)
+    r = np.random.default_rng(0).standard_normal(t.N)
+    assert np.allclose(P.apply(r), r / np.diag(W), rtol=1e-14)
+
+
+def test_coarse_prolongation_identity_and_jumps():
+    # coarse mesh = fine mesh: R_H is the identity (junction mesh included)
+    m = meshes.crossed(4)
+    t = Topology(m.vertices, m.triangles)
+    R, ct = coarse_prolongation(t, m.vertices, m.triangles, np.arange(m.nt))
+    assert np.abs(R - np.eye(t.N)).max() < 1e-14
+    # nested coarse mesh: the fine representation of each coarse basis function has, at every fine
+    # vertex and side, the jump lambda^H_i(x) * c^H of the coarse function
+    m = meshes.crossed(8)
+    cm, parent = meshes.coarse_mesh(m, 2)
+    t = Topology(m.vertices, m.triangles)
+    R, ct = coarse_prolongation(t, cm.vertices, cm.triangles, parent)
+    for cd in range(ct.N):
+        jf = t.jump_values(R[cd])
+        e = np.zeros(ct.N); e[cd] = 1.0
+        jcoarse = ct.jump_values(e)              # per coarse triangle and corner
+        for tr in range(m.nt):
+            tc = parent[tr]
+            P0, P1, P2 = cm.vertices[cm.triangles[tc]]
+            sgn = 1.0 if np.dot(t.normal[tr], ct.normal[tc]) > 0 else -1.0
+            for a in range(3):
+                x = m.vertices[m.triangles[tr, a]]
+                lam = np.linalg.lstsq(np.stack([P1 - P0, P2 - P0], 1), x - P0, rcond=None)[0]
+                bc = np.array([1 - lam.sum(), lam[0], lam[1]])
+                expect = sgn * float(bc @ jcoarse[tc])
+                assert abs(jf[tr, a] - expect) < 1e-12
+
+
+def test_condition_number_growth():
+    # kappa(W) ~ h^-1 (Experiment 2/3); kappa(P_ad) bounded by C (1 + log(H/h))^2 (Thm. main)
+    hs, kW, kP, ratio = [], [], [], []
+    for n in (8, 16, 32):
+        m = meshes.unit_square(n)
+        t, W, L = _problem(m)
+        patches = meshes.grid_patches(m, n // 2)
+        cm, par = meshes.coarse_mesh(m, n // 2)
+        P = AdditiveSchwarz(W, t, patches, cm.vertices, cm.triangles, par)
+        Md = P.dense(t.N)
+        hs.append(1.0 / n)
+        kW.append(spectral_cond(W))
+        kP.append(spectral_cond(W, 0.5 * (Md + Md.T)))
+        ratio.append(kP[-1] / (1 + math.log(n / 2)) ** 2)
+    slope = math.log(kW[-1] / kW[0]) / math.log(hs[-1] / hs[0])
+    assert -1.3 < slope < -0.7
+    assert kP[0] < kP[1] < kP[2]
+    assert max(ratio) / min(ratio) < 3.0
+    assert kP[-1] < kW[-1]

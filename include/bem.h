@@ -1,0 +1,216 @@
+/*
+ * bem.h - C-ABI of the MI355X hypersingular BEM library (libbem.so).
+ *
+ * Problem (Averseng, Claeys, Hiptmair, "Boundary Element Methods for the Laplace Hypersingular
+ * Integral Equation on Multiscreens: a two-level Substructuring Preconditioner"):
+ *   the exterior Laplace Neumann problem on a polygonal multiscreen Gamma (eq. PDE_intro,
+ *   Def. polygonalMS) is solved as U = DL(phi) with phi in the jump space H~^{1/2}([Gamma])
+ *   satisfying a(phi, psi) = l_g(psi) (Thm. thmBVP).  Its Galerkin discretisation on the
+ *   conforming space V~_h([Gamma]) of jumps of piecewise-linear functions (Section 4.2) is the
+ *   dense symmetric positive definite system  W Phi = L  (Section 4.1).
+ *
+ * Conventions shared by every call
+ *   - Meshes: vertices double[nv][3]; triangles int32[nt][3] (vertex order fixes n_T =
+ *     (x1-x0)x(x2-x0)/|.|).  The mesh must be conforming, with no point contacts (footnote in
+ *     Section 4.3) and no two triangles at an edge lying in the same half-plane.
+ *   - Degrees of freedom: one per generalized vertex x_{i,j} with j < q_i (eq.
+ *     defCurlyHtildeGamma), in canonical order (vertex index, then sector label); sector labels
+ *     at a vertex are ordered by their smallest member (triangle index, side + before side -),
+ *     the last sector is the reference one of eq. defYij.  Side + of T is where n_T points.
+ *   - Oriented triangles carry the outward normal of the sector they bound:
+ *     n_(T,+) = -n_T, n_(T,-) = +n_T.
+ *   - All host arrays are caller-owned and only read (inputs, copied during the call) or written
+ *     (outputs, caller-allocated) during the call.  Handles are freed with *_destroy.  A problem
+ *     must outlive its preconditioners.  All calls return 0 (BEM_OK) or a negative error code;
+ *     bem_last_error() gives the thread-local message of the last failing call.
+ *   - Every step of the compute path runs in HIP kernels on the context's device; there is no
+ *     CPU fallback.
+ */
+#ifndef BEM_H_
+#define BEM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    BEM_OK = 0,
+    BEM_PENDING = 1,                 /* bem_serve_poll: request still running */
+    BEM_E_INVALID_ARG = -1,
+    BEM_E_MESH_NONCONFORMING = -2,   /* repeated vertices/triangles, coincident pages at an edge */
+    BEM_E_DEGENERATE = -3,           /* zero-area triangle */
+    BEM_E_POINT_CONTACT = -4,        /* triangles at a vertex not connected through edges */
+    BEM_E_NOT_SPD = -5,              /* Cholesky pivot <= 0 in a preconditioner block */
+    BEM_E_BREAKDOWN = -6,            /* p.Wp <= 0 or NaN in (P)CG */
+    BEM_E_NOT_CONVERGED = -7,        /* max_iter reached; outputs are still written */
+    BEM_E_ADMISSION = -8,            /* request larger than the HBM budget */
+    BEM_E_OOM = -9,
+    BEM_E_DEVICE = -10,              /* HIP runtime error */
+    BEM_E_UNSUPPORTED = -11
+};
+
+typedef struct bem_ctx bem_ctx;
+typedef struct bem_problem bem_problem;
+typedef struct bem_precond bem_precond;
+typedef struct bem_server bem_server;
+
+typedef enum { BEM_FP64 = 0, BEM_FP32_REFINE = 1 } bem_precision;
+
+typedef struct {
+    bem_precision precision; /* BEM_FP32_REFINE also keeps an FP32 copy of W for inner solves */
+    int near_order;          /* Gauss-Legendre points per axis in the Duffy rules (default 10) */
+    int keep_pair_matrix;    /* 1: keep I(T,T') on the device for bem_problem_pair_integrals */
+} bem_assemble_opts;
+
+typedef struct {
+    int64_t n_dofs, n_tri, n_vert, n_near_pairs;
+    int64_t bytes_device;    /* device memory held by the problem */
+    int64_t q_hist[16];      /* number of vertices with q sectors (q >= 15 in the last bin) */
+    double t_assemble_s;     /* wall time of bem_assemble (device work, synchronised) */
+    double t_far_s, t_near_s, t_contract_s; /* device time of the three assembly phases */
+} bem_problem_info;
+
+typedef struct {
+    int use_coarse;          /* 1: add the coarse-space correction (default 1) */
+    int factor_fp32;         /* 1: store block inverses in FP32 (mixed-precision inner solves) */
+} bem_precond_opts;
+
+typedef struct {
+    double tol;              /* stop when ||L - W x||_2 <= tol ||L||_2 per column (1e-10) */
+    int max_iter;            /* total (P)CG iterations per column (default 2000) */
+    int use_precond;         /* 0: plain CG even if a preconditioner is passed */
+    bem_precision precision; /* BEM_FP32_REFINE: FP32 matrix/factors inside FP64 refinement */
+    double inner_tol;        /* relative tolerance of each inner FP32 solve (default 1e-6) */
+    int check_every;         /* iterations between host convergence checks (default 4) */
+    int use_graph;           /* 1: replay one captured iteration with hipGraphLaunch */
+} bem_solve_opts;
+
+typedef struct {
+    int iters;               /* (P)CG iterations (products with W) of this column */
+    int outer_iters;         /* FP64 residual recomputations (mixed precision) */
+    int status;              /* BEM_OK / BEM_E_NOT_CONVERGED / BEM_E_BREAKDOWN */
+    double relres;           /* final ||L - W x|| / ||L|| with the FP64 matrix */
+    double est_cond;         /* Lanczos estimate of kappa(M W) from the (P)CG coefficients */
+    double t_total_s;        /* wall time of the whole call */
+} bem_solve_info;
+
+/* ---- context ------------------------------------------------------------------------------ */
+/* Binds the calling library instance to HIP device `hip_device`.  hbm_budget_bytes limits the
+ * device memory the serving loop may hold (0 = 90% of free memory). */
+int bem_ctx_create(int hip_device, size_t hbm_budget_bytes, bem_ctx** out);
+void bem_ctx_destroy(bem_ctx* ctx);
+
+/* ---- host-side mesh analysis (no device work) --------------------------------------------- */
+/* Sectors and dofs of Section 4.2 for a mesh: returns the number of dofs in *n_dofs and, if the
+ * arrays are non-NULL, the dof table (dof_vertex[N], dof_sector[N]) and the per-vertex sector
+ * counts q[nv].  Validation errors as for bem_assemble. */
+int bem_mesh_analyze(const double* vertices, int64_t nv, const int32_t* triangles, int64_t nt,
+                     int64_t* n_dofs, int32_t* dof_vertex, int32_t* dof_sector, int32_t* q);
+
+/* ---- assembly (Section 4.3, eq. eval_a_phiij with Cor. corW) ------------------------------- */
+/* Builds the dense Galerkin matrix on the device:
+ *   W_{d,d'} = sum_{T,T'} I(T,T') J_{T,d} . J_{T',d'},  I(T,T') = 1/(4 pi) int_T int_T' |x-y|^{-1},
+ *   J_{T,d} = sum_a c_{T,a,d} (x_{a+1} - x_{a+2}) / (2|T|)   (surface curl of the trace jump).
+ * I uses a 7-point degree-5 rule on each triangle of pairs with no common vertex and
+ * Duffy-regularised Gauss-Legendre rules (near_order points per axis) on pairs with a common
+ * vertex, edge, or triangle.  W is stored FP64 row-major; with BEM_FP32_REFINE also as FP32.
+ * Errors: BEM_E_INVALID_ARG, BEM_E_DEGENERATE, BEM_E_MESH_NONCONFORMING, BEM_E_POINT_CONTACT,
+ * BEM_E_OOM, BEM_E_DEVICE. */
+int bem_assemble(bem_ctx* ctx, const double* vertices, int64_t nv, const int32_t* triangles,
+                 int64_t nt, const bem_assemble_opts* opts, bem_problem** out);
+void bem_problem_destroy(bem_problem* p);
+int bem_problem_get_info(const bem_problem* p, bem_problem_info* info);
+/* dof table in canonical order: vertex index and sector label of each dof */
+int bem_problem_dofs(const bem_problem* p, int32_t* dof_vertex, int32_t* dof_sector);
+/* rows row0 .. row0+nrows-1 of W (FP64) into out[nrows][N] */
+int bem_problem_copy_matrix(const bem_problem* p, int64_t row0, int64_t nrows, double* out);
+/* selected rows of W into out[nrows][N] */
+int bem_problem_copy_rows(const bem_problem* p, const int64_t* rows, int64_t nrows, double* out);
+/* I(T,T') for npairs index pairs (int32[npairs][2]); needs keep_pair_matrix = 1 */
+int bem_problem_pair_integrals(const bem_problem* p, const int32_t* pairs, int64_t npairs,
+                               double* out);
+/* right-hand side L (eq. defRhs, constant g): L_d = -sum_T (g.n_T) c_{T,a,d} |T|/3, k columns,
+ * out[k][N] (column-major, one column per g) */
+int bem_rhs(const bem_problem* p, const double* g, int32_t k, double* out);
+/* y = W x for k column vectors x[k][N] -> y[k][N] (FP64 matrix, or FP32 matrix if fp32 = 1) */
+int bem_matvec(const bem_problem* p, const double* x, int32_t k, int fp32, double* y);
+/* label-free view of phi[N]: jump[t][a] = sum_d c_{T,a,d} phi_d, the jump of the represented
+ * function across triangle t at corner a */
+int bem_jump_values(const bem_problem* p, const double* phi, double* jump_out);
+
+/* ---- preconditioner (eq. jumpSplit; Remark on PCG iterations) ------------------------------ */
+/* Two-level additive Schwarz operator
+ *   M r = sum_F R_F^T W_FF^{-1} R_F r + R_W^T W_WW^{-1} R_W r + R_H^T (R_H W R_H^T)^{-1} R_H r.
+ * Face dofs of patch P: dofs at vertices whose triangles all have patch_of_triangle == P and with
+ * q = 2; all other dofs form the wire basket.  The coarse space is the jump space of the nested
+ * coarse mesh (coarse_vertices, coarse_triangles); coarse_of_triangle[t] is the coarse triangle
+ * containing fine triangle t.  Pass ncv = 0 for no coarse space.  Patch ids < 0 put their
+ * vertices in the wire basket.  Errors: BEM_E_INVALID_ARG, BEM_E_NOT_SPD, mesh errors of the
+ * coarse mesh, BEM_E_OOM, BEM_E_DEVICE. */
+int bem_precond_setup(bem_problem* p, const int32_t* patch_of_triangle,
+                      const double* coarse_vertices, int64_t ncv, const int32_t* coarse_triangles,
+                      int64_t nct, const int32_t* coarse_of_triangle, const bem_precond_opts* opts,
+                      bem_precond** out);
+void bem_precond_destroy(bem_precond* m);
+/* sizes: number of face blocks, wire-basket size, coarse dofs, largest face block */
+int bem_precond_sizes(const bem_precond* m, int64_t* n_faces, int64_t* n_wb, int64_t* n_coarse,
+                      int64_t* max_face);
+/* z = M r for k columns r[k][N] -> z[k][N] (FP64 factors) */
+int bem_precond_apply(const bem_precond* m, const double* r, int32_t k, double* z);
+
+/* ---- solve (Remark "Bound on the number of Preconditioned Conjugate Gradient iterations") -- */
+/* Solves W Phi = L for k constant Neumann vectors g[k][3] by (P)CG with x0 = 0 (or opts->x0),
+ * preconditioned by M if m != NULL and opts->use_precond.  FP64 mode: W, vectors and factors in
+ * FP64.  BEM_FP32_REFINE: iterative refinement, residuals r = L - W x with the FP64 matrix, each
+ * correction from a PCG on the FP32 matrix and FP32 block inverses (FP64 dots, vector updates and
+ * coarse solve), until ||r|| <= tol ||L||.  phi_out[k][N] column-major.  Returns BEM_OK,
+ * BEM_E_NOT_CONVERGED or BEM_E_BREAKDOWN (outputs written in all three cases). */
+int bem_pcg_solve(bem_problem* p, const bem_precond* m, const double* g, int32_t k,
+                  const bem_solve_opts* opts, double* phi_out, bem_solve_info* info);
+/* Same for explicit right-hand sides rhs[k][N]. */
+int bem_pcg_solve_rhs(bem_problem* p, const bem_precond* m, const double* rhs, int32_t k,
+                      const bem_solve_opts* opts, double* phi_out, bem_solve_info* info);
+
+/* ---- serving loop ------------------------------------------------------------------------- */
+/* A background host thread takes solve requests on arbitrary multiscreens, keeps assembled
+ * problems and preconditioners resident (keyed by a hash of mesh + partition + coarse mesh),
+ * admits a request when its device footprint (N^2 x bytes per entry + blocks) fits the context's
+ * budget next to everything resident, merges queued requests on the same geometry and precision
+ * into one block PCG, and runs up to max_inflight requests on their own HIP streams. */
+int bem_server_create(bem_ctx* ctx, int max_inflight, bem_server** out);
+void bem_server_destroy(bem_server* s);
+typedef struct {
+    const double* vertices; int64_t nv;
+    const int32_t* triangles; int64_t nt;
+    const int32_t* patch_of_triangle;
+    const double* coarse_vertices; int64_t ncv;
+    const int32_t* coarse_triangles; int64_t nct;
+    const int32_t* coarse_of_triangle;
+    const double* g; int32_t k;
+    bem_precision precision;
+    double tol;
+} bem_request;
+/* Copies the request's arrays and queues it; *ticket identifies it.  BEM_E_ADMISSION if it can
+ * never fit the budget. */
+int bem_serve_submit(bem_server* s, const bem_request* req, uint64_t* ticket);
+/* Waits up to timeout_us (-1 = forever) for the request; BEM_PENDING if not finished.  On
+ * completion writes phi_out[k][N] and info[k] (if non-NULL) and releases the ticket. */
+int bem_serve_poll(bem_server* s, uint64_t ticket, int64_t timeout_us, double* phi_out,
+                   bem_solve_info* info);
+/* The number of dofs of a submitted request (so the caller can size phi_out). */
+int bem_serve_ndofs(bem_server* s, uint64_t ticket, int64_t* n_dofs);
+typedef struct {
+    int64_t submitted, completed, rejected, merged_batches, cache_hits, cache_misses;
+    int64_t resident_bytes, peak_resident_bytes, evictions;
+} bem_server_stats;
+int bem_server_get_stats(bem_server* s, bem_server_stats* st);
+
+const char* bem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BEM_H_ */

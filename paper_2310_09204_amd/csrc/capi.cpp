@@ -1,0 +1,380 @@
+// C-ABI entry points of libbem: argument checks, handle lifetimes, error codes, host<->device copies.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+
+namespace bem {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+[[noreturn]] void fail(int code, const std::string& msg) { throw Failure{code, msg}; }
+
+DeviceBuffer::DeviceBuffer(size_t b) : bytes(b) {
+    if (b == 0) return;
+    hipError_t e = hipMalloc(&ptr, b);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        ptr = nullptr;
+        fail(e == hipErrorOutOfMemory ? BEM_E_OOM : BEM_E_DEVICE,
+             "hipMalloc(" + std::to_string(b) + " bytes): " + hipGetErrorString(e));
+    }
+}
+
+DeviceBuffer::~DeviceBuffer() { reset(); }
+
+void DeviceBuffer::reset() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+DeviceBuffer& DeviceBuffer::operator=(DeviceBuffer&& o) noexcept {
+    if (this != &o) {
+        reset();
+        ptr = o.ptr;
+        bytes = o.bytes;
+        o.ptr = nullptr;
+        o.bytes = 0;
+    }
+    return *this;
+}
+
+void solve_device(bem_problem* p, const bem_precond* M, const double* b, double* x, int k, const bem_solve_opts& o,
+                  bem_solve_info* info);
+
+}  // namespace bem
+
+using namespace bem;
+
+#define BEM_TRY try {
+#define BEM_CATCH                                              \
+    }                                                          \
+    catch (const Failure& f) {                                 \
+        set_last_error(f.msg);                                 \
+        return f.code;                                         \
+    }                                                          \
+    catch (const std::bad_alloc&) {                            \
+        set_last_error("host out of memory");                  \
+        return BEM_E_OOM;                                      \
+    }                                                          \
+    catch (const std::exception& e) {                          \
+        set_last_error(e.what());                              \
+        return BEM_E_DEVICE;                                   \
+    }
+
+namespace {
+
+void set_device(const bem_ctx* ctx) { HIP_CHECK(hipSetDevice(ctx->device)); }
+
+bem_solve_opts default_solve_opts() {
+    bem_solve_opts o;
+    std::memset(&o, 0, sizeof(o));
+    o.tol = 1e-10;
+    o.max_iter = 2000;
+    o.use_precond = 1;
+    o.precision = BEM_FP64;
+    o.inner_tol = 1e-6;
+    o.check_every = 4;
+    o.use_graph = 1;
+    return o;
+}
+
+int solve_common(bem_problem* p, const bem_precond* m, const double* d_b, int32_t k, const bem_solve_opts* opts,
+                 double* phi_out, bem_solve_info* info) {
+    bem_solve_opts o = opts ? *opts : default_solve_opts();
+    if (o.tol <= 0) o.tol = 1e-10;
+    if (o.max_iter <= 0) o.max_iter = 2000;
+    if (o.check_every <= 0) o.check_every = 4;
+    if (m && m->p != p) fail(BEM_E_INVALID_ARG, "preconditioner belongs to another problem");
+    const int64_t N = p->N;
+    std::vector<bem_solve_info> inf(k);
+    DeviceBuffer x(sizeof(double) * std::max<int64_t>(1, N * k));
+    if (N > 0) solve_device(p, m, d_b, x.as<double>(), k, o, inf.data());
+    if (phi_out && N > 0) HIP_CHECK(hipMemcpy(phi_out, x.ptr, sizeof(double) * N * k, hipMemcpyDeviceToHost));
+    int rc = BEM_OK;
+    for (int c = 0; c < k; ++c) {
+        if (inf[c].status == BEM_E_BREAKDOWN) rc = BEM_E_BREAKDOWN;
+        else if (inf[c].status == BEM_E_NOT_CONVERGED && rc == BEM_OK) rc = BEM_E_NOT_CONVERGED;
+    }
+    if (info) std::memcpy(info, inf.data(), sizeof(bem_solve_info) * k);
+    if (rc == BEM_E_BREAKDOWN) set_last_error("(P)CG breakdown: p.Wp <= 0 or non-finite value");
+    if (rc == BEM_E_NOT_CONVERGED) set_last_error("(P)CG did not reach the tolerance within max_iter");
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* bem_last_error(void) { return g_last_error.c_str(); }
+
+int bem_ctx_create(int hip_device, size_t hbm_budget_bytes, bem_ctx** out) {
+    BEM_TRY
+    if (!out) fail(BEM_E_INVALID_ARG, "out is NULL");
+    int n = 0;
+    HIP_CHECK(hipGetDeviceCount(&n));
+    if (hip_device < 0 || hip_device >= n) fail(BEM_E_INVALID_ARG, "no such HIP device");
+    auto* c = new bem_ctx();
+    c->device = hip_device;
+    HIP_CHECK(hipSetDevice(hip_device));
+    size_t fr = 0, tot = 0;
+    HIP_CHECK(hipMemGetInfo(&fr, &tot));
+    c->budget = hbm_budget_bytes ? hbm_budget_bytes : size_t(0.9 * double(fr));
+    HIP_CHECK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    *out = c;
+    return BEM_OK;
+    BEM_CATCH
+}
+
+void bem_ctx_destroy(bem_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+int bem_mesh_analyze(const double* vertices, int64_t nv, const int32_t* triangles, int64_t nt, int64_t* n_dofs,
+                     int32_t* dof_vertex, int32_t* dof_sector, int32_t* q) {
+    BEM_TRY
+    MeshTopo m;
+    analyze_mesh(vertices, nv, triangles, nt, m);
+    if (n_dofs) *n_dofs = m.N;
+    if (dof_vertex && m.N) std::memcpy(dof_vertex, m.dof_vertex.data(), sizeof(int32_t) * m.N);
+    if (dof_sector && m.N) std::memcpy(dof_sector, m.dof_sector.data(), sizeof(int32_t) * m.N);
+    if (q) std::memcpy(q, m.q.data(), sizeof(int32_t) * nv);
+    return BEM_OK;
+    BEM_CATCH
+}
+
+int bem_assemble(bem_ctx* ctx, const double* vertices, int64_t nv, const int32_t* triangles, int64_t nt,
+                 const bem_assemble_opts* opts, bem_problem** out) {
+    BEM_TRY
+    if (!ctx || !out) fail(BEM_E_INVALID_ARG, "ctx/out is NULL");
+    *out = nullptr;
+    set_device(ctx);
+    auto t0 = std::chrono::steady_clock::now();
+    std::unique_ptr<bem_problem> p(new bem_problem());
+    p->ctx = ctx;
+    analyze_mesh(vertices, nv, triangles, nt, p->topo);
+    NearList near;
+    build_near_list(p->topo, near);
+    p->N = p->topo.N;
+    p->n_near = int64_t(near.t1.size());
+    p->near_order = (opts && opts->near_order > 0) ? opts->near_order : 10;
+    if (p->near_order > 64) fail(BEM_E_INVALID_ARG, "near_order above 64");
+    p->has_w32 = opts && opts->precision == BEM_FP32_REFINE;
+    p->has_pairs = opts && opts->keep_pair_matrix;
+    HIP_CHECK(hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking));
+    assemble_device(p.get(), near);
+    p->bytes = int64_t(p->W64.bytes + p->W32.bytes + p->I.bytes + p->normal.bytes + p->area.bytes + p->dof_ptr.bytes +
+                       p->dof_tri.bytes + p->dof_c.bytes + p->tri_ptr.bytes + p->tri_dof.bytes + p->tri_corner.bytes +
+                       p->tri_c.bytes);
+    p->t_assemble = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *out = p.release();
+    return BEM_OK;
+    BEM_CATCH
+}
+
+void bem_problem_destroy(bem_problem* p) {
+    if (!p) return;
+    (void)hipSetDevice(p->ctx->device);
+    if (p->stream) (void)hipStreamSynchronize(p->stream);
+    hipStream_t s = p->stream;
+    delete p;
+    if (s) (void)hipStreamDestroy(s);
+}
+
+int bem_problem_get_info(const bem_problem* p, bem_problem_info* info) {
+    BEM_TRY
+    if (!p || !info) fail(BEM_E_INVALID_ARG, "NULL argument");
+    std::memset(info, 0, sizeof(*info));
+    info->n_dofs = p->N;
+    info->n_tri = p->topo.nt;
+    info->n_vert = p->topo.nv;
+    info->n_near_pairs = p->n_near;
+    info->bytes_device = p->bytes;
+    for (int32_t q : p->topo.q) info->q_hist[std::min(q, 15)] += 1;
+    info->t_assemble_s = p->t_assemble;
+    info->t_far_s = p->t_far;
+    info->t_near_s = p->t_near;
+    info->t_contract_s = p->t_contract;
+    return BEM_OK;
+    BEM_CATCH
+}
+
+int bem_problem_dofs(const bem_problem* p, int32_t* dof_vertex, int32_t* dof_sector) {
+    BEM_TRY
+    if (!p) fail(BEM_E_INVALID_ARG, "NULL problem");
+    if (dof_vertex && p->N) std::memcpy(dof_vertex, p->topo.dof_vertex.data(), sizeof(int32_t) * p->N);
+    if (dof_sector && p->N) std::memcpy(dof_sector, p->topo.dof_sector.data(), sizeof(int32_t) * p->N);
+    return BEM_OK;
+    BEM_CATCH
+}
+
+int bem_problem_copy_matrix(const bem_problem* p, int64_t row0, int64_t nrows, double* out) {
+    BEM_TRY
+    if (!p || !out) fail(BEM_E_INVALID_ARG, "NULL argument");
+    if (row0 < 0 || nrows < 0 || row0 + nrows > p->N) fail(BEM_E_INVALID_ARG, "row range outside the matrix");
+    set_device(p->ctx);
+    if (nrows == 0) return BEM_OK;
+    HIP_CHECK(hipMemcpy2D(out, sizeof(double) * p->N, p->W64.as<double>() + row0 * p->ldw, sizeof(double) * p->ldw,
+                          sizeof(double) * p->N, size_t(nrows), hipMemcpyDeviceToHost));
+    return BEM_OK;
+    BEM_CATCH
+}
+
+int bem_problem_copy_rows(const bem_problem* p, const int64_t* rows, int64_t nrows, double* out) {
+    BEM_TRY
+    if (!p || (!rows && nrows) || (!out && nrows)) fail(BEM_E_INVALID_ARG, "NULL argument");
+    set_device(p->ctx);
+    for (int64_t i = 0; i < nrows; ++i) {
+        if (rows[i] < 0 || rows[i] >= p->N) fail(BEM_E_INVALID_ARG, "row index out of range");
+        HIP_CHECK(hipMemcpy(out + i * p->N, p->W64.as<double>() + rows[i] * p->ldw, sizeof(double) * p->N, hipMemcpyDeviceToHost));
+    }
+    return BEM_OK;
+    BEM_CATCH
+}
+
+int bem_problem_pair_integrals(const bem_problem* p, const int32_t* pairs, int64_t npairs, double* out) {
+    BEM_TRY
+    if (!p || (!pairs && npairs) || (!out && npairs)) fail(BEM_E_INVALID_ARG, "NULL argument");
+    if (!p->has_pairs || !p->I.ptr) fail(BEM_E_INVALID_ARG, "assemble with keep_pair_matrix = 1");
+    set_device(p->ctx);
+    const int64_t nt = p->topo.nt;
+    std::vector<double> row(nt);
+    for (int64_t i = 0; i < npairs; ++i) {
+        const int64_t a = pairs[2 * i], b = pairs[2 * i + 1];
+        if (a < 0 || a >= nt || b < 0 || b >= nt) fail(BEM_E_INVALID_ARG, "pair index out of range");
+        HIP_CHECK(hipMemcpy(out + i, p->I.as<double>() + a * nt + b, sizeof(double), hipMemcpyDeviceToHost));
+    }
+    return BEM_OK;
+    BEM_CATCH
+}
+
+int bem_rhs(const bem_problem* p, const double* g, int32_t k, double* out) {
+    BEM_TRY
+    if (!p || !g || !out || k <= 0) fail(BEM_E_INVALID_ARG, "bad argument");
+    set_device(p->ctx);
+    const int64_t N = p->N;
+    if (N == 0) return BEM_OK;
+    DeviceBuffer dg(sizeof(double) * 3 * k), dL(sizeof(double) * N * k);
+    HIP_CHECK(hipMemcpyAsync(dg.ptr, g, sizeof(double) * 3 * k, hipMemcpyHostToDevice, p->stream));
+    rhs_device(p, dg.as<double>(), k, dL.as<double>(), p->stream);
+    HIP_CHECK(hipMemcpyAsync(out, dL.ptr, sizeof(double) * N * k, hipMemcpyDeviceToHost, p->stream));
+    HIP_CHECK(hipStreamSynchronize(p->stream));
+    return BEM_OK;
+    BEM_CATCH
+}
+
+int bem_matvec(const bem_problem* p, const double* x, int32_t k, int fp32, double* y) {
+    BEM_TRY
+    if (!p || !x || !y || k <= 0) fail(BEM_E_INVALID_ARG, "bad argument");
+    set_device(p->ctx);
+    const int64_t N = p->N;
+    if (N == 0) return BEM_OK;
+    DeviceBuffer dx(sizeof(double) * N * k), dy(sizeof(double) * N * k);
+    HIP_CHECK(hipMemcpyAsync(dx.ptr, x, sizeof(double) * N * k, hipMemcpyHostToDevice, p->stream));
+    matvec_device(p, fp32 != 0, dx.as<double>(), N, k, dy.as<double>(), p->stream);
+    HIP_CHECK(hipMemcpyAsync(y, dy.ptr, sizeof(double) * N * k, hipMemcpyDeviceToHost, p->stream));
+    HIP_CHECK(hipStreamSynchronize(p->stream));
+    return BEM_OK;
+    BEM_CATCH
+}
+
+int bem_jump_values(const bem_problem* p, const double* phi, double* jump_out) {
+    BEM_TRY
+    if (!p || !phi || !jump_out) fail(BEM_E_INVALID_ARG, "bad argument");
+    set_device(p->ctx);
+    const int64_t N = p->N, nt = p->topo.nt;
+    DeviceBuffer dp(sizeof(double) * std::max<int64_t>(1, N)), dj(sizeof(double) * nt * 3);
+    if (N) HIP_CHECK(hipMemcpyAsync(dp.ptr, phi, sizeof(double) * N, hipMemcpyHostToDevice, p->stream));
+    jump_values_device(p, dp.as<double>(), dj.as<double>(), p->stream);
+    HIP_CHECK(hipMemcpyAsync(jump_out, dj.ptr, sizeof(double) * nt * 3, hipMemcpyDeviceToHost, p->stream));
+    HIP_CHECK(hipStreamSynchronize(p->stream));
+    return BEM_OK;
+    BEM_CATCH
+}
+
+int bem_precond_setup(bem_problem* p, const int32_t* patch_of_triangle, const double* coarse_vertices, int64_t ncv,
+                      const int32_t* coarse_triangles, int64_t nct, const int32_t* coarse_of_triangle,
+                      const bem_precond_opts* opts, bem_precond** out) {
+    BEM_TRY
+    if (!p || !out) fail(BEM_E_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    set_device(p->ctx);
+    std::unique_ptr<bem_precond> m(new bem_precond());
+    m->p = p;
+    m->use_coarse = opts ? opts->use_coarse != 0 : true;
+    m->fp32 = opts ? opts->factor_fp32 != 0 : false;
+    precond_setup_device(m.get(), patch_of_triangle, coarse_vertices, ncv, coarse_triangles, nct, coarse_of_triangle);
+    *out = m.release();
+    return BEM_OK;
+    BEM_CATCH
+}
+
+void bem_precond_destroy(bem_precond* m) {
+    if (!m) return;
+    (void)hipSetDevice(m->p->ctx->device);
+    (void)hipStreamSynchronize(m->p->stream);
+    delete m;
+}
+
+int bem_precond_sizes(const bem_precond* m, int64_t* n_faces, int64_t* n_wb, int64_t* n_coarse, int64_t* max_face) {
+    BEM_TRY
+    if (!m) fail(BEM_E_INVALID_ARG, "NULL preconditioner");
+    if (n_faces) *n_faces = m->n_faces;
+    if (n_wb) *n_wb = m->n_wb;
+    if (n_coarse) *n_coarse = m->nH;
+    if (max_face) *max_face = m->max_face;
+    return BEM_OK;
+    BEM_CATCH
+}
+
+int bem_precond_apply(const bem_precond* m, const double* r, int32_t k, double* z) {
+    BEM_TRY
+    if (!m || !r || !z || k <= 0) fail(BEM_E_INVALID_ARG, "bad argument");
+    const bem_problem* p = m->p;
+    set_device(p->ctx);
+    const int64_t N = p->N;
+    DeviceBuffer dr(sizeof(double) * N * k), dz(sizeof(double) * N * k);
+    DeviceBuffer scr(sizeof(double) * precond_scratch_size(m, std::min(k, 16)));
+    HIP_CHECK(hipMemcpyAsync(dr.ptr, r, sizeof(double) * N * k, hipMemcpyHostToDevice, p->stream));
+    precond_apply_device(m, false, dr.as<double>(), N, k, dz.as<double>(), p->stream, scr.as<double>());
+    HIP_CHECK(hipMemcpyAsync(z, dz.ptr, sizeof(double) * N * k, hipMemcpyDeviceToHost, p->stream));
+    HIP_CHECK(hipStreamSynchronize(p->stream));
+    return BEM_OK;
+    BEM_CATCH
+}
+
+int bem_pcg_solve(bem_problem* p, const bem_precond* m, const double* g, int32_t k, const bem_solve_opts* opts,
+                  double* phi_out, bem_solve_info* info) {
+    BEM_TRY
+    if (!p || !g || k <= 0) fail(BEM_E_INVALID_ARG, "bad argument");
+    set_device(p->ctx);
+    const int64_t N = p->N;
+    DeviceBuffer dg(sizeof(double) * 3 * k), dL(sizeof(double) * std::max<int64_t>(1, N * k));
+    HIP_CHECK(hipMemcpyAsync(dg.ptr, g, sizeof(double) * 3 * k, hipMemcpyHostToDevice, p->stream));
+    rhs_device(p, dg.as<double>(), k, dL.as<double>(), p->stream);
+    return solve_common(p, m, dL.as<double>(), k, opts, phi_out, info);
+    BEM_CATCH
+}
+
+int bem_pcg_solve_rhs(bem_problem* p, const bem_precond* m, const double* rhs, int32_t k, const bem_solve_opts* opts,
+                      double* phi_out, bem_solve_info* info) {
+    BEM_TRY
+    if (!p || !rhs || k <= 0) fail(BEM_E_INVALID_ARG, "bad argument");
+    set_device(p->ctx);
+    const int64_t N = p->N;
+    DeviceBuffer dL(sizeof(double) * std::max<int64_t>(1, N * k));
+    if (N) HIP_CHECK(hipMemcpyAsync(dL.ptr, rhs, sizeof(double) * N * k, hipMemcpyHostToDevice, p->stream));
+    return solve_common(p, m, dL.as<double>(), k, opts, phi_out, info);
+    BEM_CATCH
+}
+
+}  // extern "C"

@@ -1,0 +1,161 @@
+// Internal declarations of libbem (not part of the C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/bem.h"
+
+namespace bem {
+
+struct Failure {
+    int code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(int code, const std::string& msg);
+void set_last_error(const std::string& msg);
+
+#define HIP_CHECK(expr)                                                                   \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            ::bem::fail(BEM_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ------------------------------------------------------------------------------------------
+// Host topology of a multiscreen mesh (Section 4.2 / 4.3 of the paper)
+// ------------------------------------------------------------------------------------------
+struct MeshTopo {
+    int64_t nv = 0, nt = 0, N = 0;
+    std::vector<double> V;          // nv*3
+    std::vector<int32_t> T;         // nt*3
+    std::vector<double> normal;     // nt*3 unit normal n_T
+    std::vector<double> area;       // nt
+    std::vector<int32_t> q;         // nv sector counts
+    std::vector<int32_t> sector;    // nt*2*3: label of side s of triangle t at its corner a
+    std::vector<int64_t> first_dof; // nv+1: dofs of vertex v are first_dof[v] .. first_dof[v+1]-1
+    std::vector<int32_t> dof_vertex, dof_sector;
+    // triangle -> (dof, corner, c) with c = s_+ - s_- (jump coefficient), CSR over triangles
+    std::vector<int64_t> tri_ptr;
+    std::vector<int32_t> tri_dof;
+    std::vector<int8_t> tri_corner, tri_c;
+    // dof -> (triangle, corner, c), CSR over dofs
+    std::vector<int64_t> dof_ptr;
+    std::vector<int32_t> dof_tri;
+    std::vector<int8_t> dof_corner, dof_c;
+};
+
+// Validates and analyses a mesh; throws Failure with a BEM_E_* code on invalid input.
+void analyze_mesh(const double* V, int64_t nv, const int32_t* T, int64_t nt, MeshTopo& out);
+
+// Pairs of triangles with at least one common vertex, t1 <= t2, with the canonical vertex order
+// the Duffy rules expect: type 3 (same triangle) A,B,C; type 2 (common edge A-B) A,B,C,C';
+// type 1 (common vertex A) A,B,C,B',C'.
+struct NearList {
+    std::vector<int32_t> t1, t2;
+    std::vector<int8_t> type;
+    std::vector<int32_t> verts;     // 5 per pair (-1 where unused)
+    int64_t count[4] = {0, 0, 0, 0};
+};
+void build_near_list(const MeshTopo& m, NearList& out);
+
+// Quadrature tables computed from their definitions
+void triangle7_rule(double bary[7][3], double w[7]);
+void gauss_legendre01(int n, std::vector<double>& x, std::vector<double>& w);
+
+// ------------------------------------------------------------------------------------------
+// Device-side objects behind the opaque C handles
+// ------------------------------------------------------------------------------------------
+struct DeviceBuffer {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    DeviceBuffer() = default;
+    explicit DeviceBuffer(size_t b);
+    ~DeviceBuffer();
+    DeviceBuffer(const DeviceBuffer&) = delete;
+    DeviceBuffer& operator=(const DeviceBuffer&) = delete;
+    DeviceBuffer(DeviceBuffer&& o) noexcept : ptr(o.ptr), bytes(o.bytes) { o.ptr = nullptr; o.bytes = 0; }
+    DeviceBuffer& operator=(DeviceBuffer&& o) noexcept;
+    void reset();
+    template <class T> T* as() const { return static_cast<T*>(ptr); }
+};
+
+template <class T>
+DeviceBuffer upload(const std::vector<T>& v, hipStream_t s) {
+    DeviceBuffer b(std::max<size_t>(1, v.size()) * sizeof(T));
+    if (!v.empty()) HIP_CHECK(hipMemcpyAsync(b.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return b;
+}
+
+}  // namespace bem
+
+struct bem_ctx {
+    int device = 0;
+    size_t budget = 0;
+    hipStream_t stream = nullptr;
+};
+
+struct bem_problem {
+    bem_ctx* ctx = nullptr;
+    bem::MeshTopo topo;
+    int64_t N = 0, ldw = 0, n_near = 0;
+    bool has_w32 = false, has_pairs = false;
+    int near_order = 10;
+    hipStream_t stream = nullptr;
+    bem::DeviceBuffer W64, W32, I;          // W (N x ldw), optional FP32 copy, optional I (nt x nt)
+    bem::DeviceBuffer normal, area;         // per-triangle geometry for the right-hand side
+    bem::DeviceBuffer dof_ptr, dof_tri, dof_c;  // dof -> triangle CSR
+    bem::DeviceBuffer tri_ptr, tri_dof, tri_corner, tri_c;  // triangle -> dof CSR
+    double t_assemble = 0, t_far = 0, t_near = 0, t_contract = 0;
+    int64_t bytes = 0;
+};
+
+namespace bem {
+
+// assembly (assemble.hip)
+void assemble_device(bem_problem* p, const NearList& near);
+void rhs_device(const bem_problem* p, const double* d_g, int k, double* d_L, hipStream_t s);
+void jump_values_device(const bem_problem* p, const double* d_phi, double* d_jump, hipStream_t s);
+
+// dense products (solver.hip); x, y column-major [k][N] with leading dimension ldx
+void matvec_device(const bem_problem* p, bool fp32, const double* d_x, int64_t ldx, int k,
+                   double* d_y, hipStream_t s);
+
+}  // namespace bem
+
+// ------------------------------------------------------------------------------------------
+// Preconditioner (precond.hip)
+// ------------------------------------------------------------------------------------------
+struct bem_precond {
+    bem_problem* p = nullptr;
+    bool fp32 = false, use_coarse = true;
+    int64_t nblocks = 0, n_faces = 0, n_wb = 0, nH = 0, max_face = 0;
+    std::vector<int64_t> blk_n, blk_npad, blk_idx_off, blk_mat_off;
+    int64_t idx_total = 0, mat_total = 0;
+    bem::DeviceBuffer idx;          // concatenated dof indices of the blocks (int32)
+    bem::DeviceBuffer blk_meta;     // per block: n, npad, idx_off, mat_off (int64 x 4)
+    bem::DeviceBuffer inv64, inv32; // explicit block inverses, npad x npad row-major each
+    bem::DeviceBuffer tasks;        // apply tasks: (block, row0, nrows, 0) as int4
+    int64_t ntasks = 0;
+    // coarse space: R_H as CSR over coarse dofs and over fine dofs, and (R_H W R_H^T)^{-1}
+    bem::DeviceBuffer rh_ptr, rh_col, rh_val, rht_ptr, rht_row, rht_val, WHinv;
+    int64_t bytes = 0;
+    double t_setup = 0;
+};
+
+namespace bem {
+// Host construction of the dof classes and R_H, then device factorisation (precond.hip).
+void precond_setup_device(bem_precond* m, const int32_t* patch_of_triangle, const double* cV, int64_t ncv,
+                          const int32_t* cT, int64_t nct, const int32_t* coarse_of_triangle);
+// z = M r for k columns (column-major, leading dimension ld); fp32 selects the FP32 inverses.
+void precond_apply_device(const bem_precond* m, bool fp32, const double* r, int64_t ld, int k, double* z,
+                          hipStream_t s, double* coarse_scratch);
+// scratch (doubles) needed by precond_apply_device for k columns
+int64_t precond_scratch_size(const bem_precond* m, int k);
+}  // namespace bem

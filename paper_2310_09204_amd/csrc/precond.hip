@@ -1,0 +1,749 @@
+// Two-level substructuring additive Schwarz preconditioner (paper: eq. jumpSplit in Section 6.4,
+// the Remark on duplicate face copies after it, and the Remark "Bound on the number of
+// Preconditioned Conjugate Gradient iterations"):
+//
+//   M r = sum_F R_F^T W_FF^{-1} R_F r + R_W^T W_WW^{-1} R_W r + R_H^T (R_H W R_H^T)^{-1} R_H r.
+//
+// The face and wire-basket spaces are spanned by fine jump basis functions (the discrete harmonic
+// extensions omega_{i,j} keep the traces of phi_{i,j}, Lemma lemdof), so R_F, R_W are 0/1 dof
+// restrictions and their blocks are principal submatrices of W.  Face dofs of a patch: dofs at
+// vertices whose triangles all lie in that patch and with q = 2; the rest is the wire basket.
+// The coarse space is the jump space of a nested coarse mesh written in the fine basis.
+//
+// Device work: every block (faces, wire basket, coarse Galerkin matrix) is gathered into a padded
+// 64-multiple square, factorised by a tiled right-looking Cholesky, inverted through the inverse
+// of the factor, and multiplied out into an explicit inverse B = L^{-T} L^{-1}.  All blocks of
+// uneven sizes advance together: each launch carries one tile step of every block that still has
+// work (ragged batching).  Applying M is then a ragged batch of dense row-panel products.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <map>
+#include <numeric>
+
+#include "internal.h"
+
+namespace bem {
+
+namespace {
+
+constexpr int TBK = 64;     // tile edge
+constexpr int LDT = 65;     // LDS leading dimension (padding against bank conflicts)
+
+struct BlockMeta { int64_t n, npad, idx_off, mat_off; };
+
+__device__ __forceinline__ void tile_load(double* __restrict__ s, const double* __restrict__ g, int64_t ld) {
+    for (int e = threadIdx.x; e < TBK * TBK; e += blockDim.x) {
+        int r = e >> 6, c = e & 63;
+        s[r * LDT + c] = g[int64_t(r) * ld + c];
+    }
+}
+
+__device__ __forceinline__ void tile_store(const double* __restrict__ s, double* __restrict__ g, int64_t ld) {
+    for (int e = threadIdx.x; e < TBK * TBK; e += blockDim.x) {
+        int r = e >> 6, c = e & 63;
+        g[int64_t(r) * ld + c] = s[r * LDT + c];
+    }
+}
+
+// acc (this thread's 4x4 piece of a 64x64 tile) += op(A) op(B), 256 threads
+template <bool TA, bool TB>
+__device__ __forceinline__ void tile_mac(double (&acc)[4][4], const double* __restrict__ A, const double* __restrict__ B) {
+    const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
+#pragma unroll 4
+    for (int l = 0; l < TBK; ++l) {
+        double a[4], b[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = TA ? A[l * LDT + tr * 4 + i] : A[(tr * 4 + i) * LDT + l];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b[j] = TB ? B[(tc * 4 + j) * LDT + l] : B[l * LDT + tc * 4 + j];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+    }
+}
+
+__device__ __forceinline__ void acc_zero(double (&acc)[4][4]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+}
+
+__device__ __forceinline__ void acc_to_lds(const double (&acc)[4][4], double* __restrict__ s, double scale) {
+    const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) s[(tr * 4 + i) * LDT + tc * 4 + j] = scale * acc[i][j];
+}
+
+// --- gather: A_b = W[idx_b, idx_b] padded with the identity ---------------------------------
+__global__ __launch_bounds__(256) void k_gather(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
+                                                const int32_t* __restrict__ idx, const double* __restrict__ W,
+                                                int64_t ldw, double* __restrict__ A) {
+    const int4 t = tasks[blockIdx.x];
+    const BlockMeta m = meta[t.x];
+    const int32_t* id = idx + m.idx_off;
+    double* a = A + m.mat_off;
+    for (int e = threadIdx.x; e < TBK * TBK; e += blockDim.x) {
+        const int64_t r = int64_t(t.y) * TBK + (e >> 6), c = int64_t(t.z) * TBK + (e & 63);
+        double v;
+        if (r < m.n && c < m.n) v = W[int64_t(id[r]) * ldw + id[c]];
+        else v = (r == c) ? 1.0 : 0.0;
+        a[r * m.npad + c] = v;
+    }
+}
+
+// --- Cholesky of the diagonal tile of step k ------------------------------------------------
+__global__ __launch_bounds__(256) void k_potrf(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
+                                               double* __restrict__ A, int k, int* __restrict__ flags) {
+    __shared__ double L[TBK * LDT];
+    const int4 t = tasks[blockIdx.x];
+    const BlockMeta m = meta[t.x];
+    double* g = A + m.mat_off + int64_t(k) * TBK * m.npad + int64_t(k) * TBK;
+    tile_load(L, g, m.npad);
+    __syncthreads();
+    __shared__ double piv;
+    for (int j = 0; j < TBK; ++j) {
+        if (threadIdx.x == 0) {
+            double d = L[j * LDT + j];
+            if (!(d > 0.0) || !isfinite(d)) {
+                flags[t.x] = 1;
+                d = 1.0;
+            }
+            piv = sqrt(d);
+            L[j * LDT + j] = piv;
+        }
+        __syncthreads();
+        for (int i = j + 1 + threadIdx.x; i < TBK; i += blockDim.x) L[i * LDT + j] /= piv;
+        __syncthreads();
+        const int rem = TBK - j - 1;
+        for (int e = threadIdx.x; e < rem * rem; e += blockDim.x) {
+            int i = j + 1 + e / rem, c = j + 1 + e % rem;
+            if (c <= i) L[i * LDT + c] -= L[i * LDT + j] * L[c * LDT + j];
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < TBK * TBK; e += blockDim.x) {
+        int r = e >> 6, c = e & 63;
+        if (c > r) L[r * LDT + c] = 0.0;
+    }
+    __syncthreads();
+    tile_store(L, g, m.npad);
+}
+
+// --- A_ik <- A_ik L_kk^{-T} for the tiles below the diagonal of step k ----------------------
+__global__ __launch_bounds__(256) void k_trsm(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
+                                              double* __restrict__ A, int k) {
+    __shared__ double L[TBK * LDT];
+    __shared__ double X[TBK * LDT];
+    const int4 t = tasks[blockIdx.x];
+    const BlockMeta m = meta[t.x];
+    const int i = t.y;
+    double* a0 = A + m.mat_off;
+    tile_load(L, a0 + int64_t(k) * TBK * m.npad + int64_t(k) * TBK, m.npad);
+    double* gik = a0 + int64_t(i) * TBK * m.npad + int64_t(k) * TBK;
+    tile_load(X, gik, m.npad);
+    __syncthreads();
+    if (threadIdx.x < TBK) {
+        const int r = threadIdx.x;
+        for (int c = 0; c < TBK; ++c) {
+            double s = X[r * LDT + c];
+            for (int l = 0; l < c; ++l) s -= X[r * LDT + l] * L[c * LDT + l];
+            X[r * LDT + c] = s / L[c * LDT + c];
+        }
+    }
+    __syncthreads();
+    tile_store(X, gik, m.npad);
+}
+
+// --- trailing update A_ij -= A_ik A_jk^T, j <= i, of step k ---------------------------------
+__global__ __launch_bounds__(256) void k_update(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
+                                                double* __restrict__ A, int k) {
+    __shared__ double P[TBK * LDT];
+    __shared__ double Q[TBK * LDT];
+    const int4 t = tasks[blockIdx.x];
+    const BlockMeta m = meta[t.x];
+    const int i = t.y, j = t.z;
+    double* a0 = A + m.mat_off;
+    tile_load(P, a0 + int64_t(i) * TBK * m.npad + int64_t(k) * TBK, m.npad);
+    tile_load(Q, a0 + int64_t(j) * TBK * m.npad + int64_t(k) * TBK, m.npad);
+    __syncthreads();
+    double acc[4][4];
+    acc_zero(acc);
+    tile_mac<false, true>(acc, P, Q);
+    double* gij = a0 + int64_t(i) * TBK * m.npad + int64_t(j) * TBK;
+    const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) gij[int64_t(tr * 4 + a) * m.npad + tc * 4 + b] -= acc[a][b];
+}
+
+// --- inverse of the diagonal factor tiles: X_ii = L_ii^{-1} --------------------------------
+__global__ __launch_bounds__(256) void k_trtri_diag(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
+                                                    const double* __restrict__ A, double* __restrict__ X) {
+    __shared__ double L[TBK * LDT];
+    __shared__ double Y[TBK * LDT];
+    const int4 t = tasks[blockIdx.x];
+    const BlockMeta m = meta[t.x];
+    const int i = t.y;
+    const int64_t off = m.mat_off + int64_t(i) * TBK * m.npad + int64_t(i) * TBK;
+    tile_load(L, A + off, m.npad);
+    __syncthreads();
+    if (threadIdx.x < TBK) {
+        const int c = threadIdx.x;           // column of the inverse: solve L y = e_c
+        for (int r = 0; r < TBK; ++r) {
+            double s = (r == c) ? 1.0 : 0.0;
+            if (r < c) { Y[r * LDT + c] = 0.0; continue; }
+            for (int l = c; l < r; ++l) s -= L[r * LDT + l] * Y[l * LDT + c];
+            Y[r * LDT + c] = s / L[r * LDT + r];
+        }
+    }
+    __syncthreads();
+    tile_store(Y, X + off, m.npad);
+}
+
+// --- off-diagonal tiles of L^{-1}, row i: X_ij = -X_ii sum_{m=j}^{i-1} L_im X_mj -------------
+__global__ __launch_bounds__(256) void k_trtri_row(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
+                                                   const double* __restrict__ A, double* __restrict__ X, int i) {
+    __shared__ double P[TBK * LDT];
+    __shared__ double Q[TBK * LDT];
+    const int4 t = tasks[blockIdx.x];
+    const BlockMeta m = meta[t.x];
+    const int j = t.y;
+    const double* a0 = A + m.mat_off;
+    double* x0 = X + m.mat_off;
+    double acc[4][4];
+    acc_zero(acc);
+    for (int mm = j; mm < i; ++mm) {
+        tile_load(P, a0 + int64_t(i) * TBK * m.npad + int64_t(mm) * TBK, m.npad);
+        tile_load(Q, x0 + int64_t(mm) * TBK * m.npad + int64_t(j) * TBK, m.npad);
+        __syncthreads();
+        tile_mac<false, false>(acc, P, Q);
+        __syncthreads();
+    }
+    acc_to_lds(acc, Q, 1.0);
+    tile_load(P, x0 + int64_t(i) * TBK * m.npad + int64_t(i) * TBK, m.npad);
+    __syncthreads();
+    double acc2[4][4];
+    acc_zero(acc2);
+    tile_mac<false, false>(acc2, P, Q);
+    __syncthreads();
+    acc_to_lds(acc2, P, -1.0);
+    __syncthreads();
+    tile_store(P, x0 + int64_t(i) * TBK * m.npad + int64_t(j) * TBK, m.npad);
+}
+
+// --- B = X^T X (lower tiles computed, mirrored), written over A ------------------------------
+__global__ __launch_bounds__(256) void k_syrk_inverse(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
+                                                      const double* __restrict__ X, double* __restrict__ B) {
+    __shared__ double P[TBK * LDT];
+    __shared__ double Q[TBK * LDT];
+    const int4 t = tasks[blockIdx.x];
+    const BlockMeta m = meta[t.x];
+    const int i = t.y, j = t.z;     // i >= j
+    const int nt = int(m.npad / TBK);
+    const double* x0 = X + m.mat_off;
+    double acc[4][4];
+    acc_zero(acc);
+    for (int mm = i; mm < nt; ++mm) {
+        tile_load(P, x0 + int64_t(mm) * TBK * m.npad + int64_t(i) * TBK, m.npad);
+        tile_load(Q, x0 + int64_t(mm) * TBK * m.npad + int64_t(j) * TBK, m.npad);
+        __syncthreads();
+        tile_mac<true, false>(acc, P, Q);
+        __syncthreads();
+    }
+    double* b0 = B + m.mat_off;
+    const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int64_t r = int64_t(i) * TBK + tr * 4 + a, c = int64_t(j) * TBK + tc * 4 + b;
+            b0[r * m.npad + c] = acc[a][b];
+            if (i != j) b0[c * m.npad + r] = acc[a][b];
+        }
+}
+
+__global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
+    int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (; i < n; i += stride) b[i] = float(a[i]);
+}
+
+// --- coarse Galerkin matrix: Y = W R_H^T, then W_H = R_H Y (upper half, mirrored) ------------
+__global__ void k_coarse_Y(const double* __restrict__ W, int64_t ldw, int64_t N, const int64_t* __restrict__ rp,
+                           const int32_t* __restrict__ rc, const double* __restrict__ rv, int64_t nH,
+                           double* __restrict__ Y) {
+    const int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;   // fine row
+    const int64_t i = blockIdx.y;                                         // coarse dof
+    if (j >= N) return;
+    const double* w = W + j * ldw;
+    double s = 0.0;
+    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) s = fma(rv[e], w[rc[e]], s);
+    Y[j * nH + i] = s;
+}
+
+__global__ void k_coarse_WH(const double* __restrict__ Y, int64_t nH, const int64_t* __restrict__ rp,
+                            const int32_t* __restrict__ rc, const double* __restrict__ rv, double* __restrict__ A,
+                            int64_t npad) {
+    const int64_t i2 = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    const int64_t i1 = blockIdx.y;
+    if (i2 >= npad) return;
+    if (i1 >= nH || i2 >= nH) {
+        A[i1 * npad + i2] = (i1 == i2) ? 1.0 : 0.0;
+        return;
+    }
+    if (i2 < i1) return;
+    double s = 0.0;
+    for (int64_t e = rp[i1]; e < rp[i1 + 1]; ++e) s = fma(rv[e], Y[int64_t(rc[e]) * nH + i2], s);
+    A[i1 * npad + i2] = s;
+    A[i2 * npad + i1] = s;
+}
+
+__global__ void k_coarse_pad_rows(double* __restrict__ A, int64_t nH, int64_t npad) {
+    // rows nH .. npad-1 of the padded coarse block
+    const int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    const int64_t r = nH + blockIdx.y;
+    if (c < npad && r < npad) A[r * npad + c] = (r == c) ? 1.0 : 0.0;
+}
+
+// --- apply: z[idx] = B r[idx] for a 64-row panel of one block, k columns ---------------------
+template <typename MT, int K>
+__global__ __launch_bounds__(256) void k_block_apply(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
+                                                     const int32_t* __restrict__ idx, const MT* __restrict__ inv,
+                                                     const double* __restrict__ r, int64_t ld, int kcols,
+                                                     double* __restrict__ z) {
+    constexpr int CH = 256;
+    __shared__ MT xs[K][CH];
+    __shared__ MT zs[64][K];
+    const int4 t = tasks[blockIdx.x];
+    const BlockMeta m = meta[t.x];
+    const int32_t* id = idx + m.idx_off;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row0 = t.y, nr = t.z;
+    for (int e = threadIdx.x; e < 64 * K; e += blockDim.x) zs[e / K][e % K] = MT(0);
+    for (int64_t s0 = 0; s0 < m.n; s0 += CH) {
+        const int chunk = int(min<int64_t>(CH, m.n - s0));
+        __syncthreads();
+        for (int e = threadIdx.x; e < CH * K; e += blockDim.x) {
+            const int c = e / CH, s = e % CH;
+            xs[c][s] = (s < chunk && c < kcols) ? MT(r[int64_t(c) * ld + id[s0 + s]]) : MT(0);
+        }
+        __syncthreads();
+        for (int rr = wave; rr < nr; rr += 4) {
+            const MT* brow = inv + m.mat_off + int64_t(row0 + rr) * m.npad + s0;
+            MT acc[K];
+#pragma unroll
+            for (int c = 0; c < K; ++c) acc[c] = MT(0);
+            for (int s = lane; s < chunk; s += 64) {
+                const MT b = brow[s];
+#pragma unroll
+                for (int c = 0; c < K; ++c) acc[c] = fma(b, xs[c][s], acc[c]);
+            }
+#pragma unroll
+            for (int c = 0; c < K; ++c) {
+                MT v = acc[c];
+                for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+                acc[c] = v;
+            }
+            if (lane == 0)
+#pragma unroll
+                for (int c = 0; c < K; ++c) zs[rr][c] += acc[c];
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nr * K; e += blockDim.x) {
+        const int rr = e / K, c = e % K;
+        if (c < kcols) z[int64_t(c) * ld + id[row0 + rr]] = double(zs[rr][c]);
+    }
+}
+
+__global__ void k_restrict(const int64_t* __restrict__ rp, const int32_t* __restrict__ rc, const double* __restrict__ rv,
+                           int64_t nH, const double* __restrict__ r, int64_t ld, int k, double* __restrict__ out) {
+    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (i >= nH) return;
+    for (int c = 0; c < k; ++c) {
+        double s = 0.0;
+        for (int64_t e = rp[i]; e < rp[i + 1]; ++e) s = fma(rv[e], r[int64_t(c) * ld + rc[e]], s);
+        out[int64_t(c) * nH + i] = s;
+    }
+}
+
+__global__ void k_coarse_solve(const double* __restrict__ Binv, int64_t npad, int64_t nH, const double* __restrict__ x,
+                               int k, double* __restrict__ y) {
+    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (i >= nH) return;
+    for (int c = 0; c < k; ++c) {
+        double s = 0.0;
+        for (int64_t j = 0; j < nH; ++j) s = fma(Binv[i * npad + j], x[int64_t(c) * nH + j], s);
+        y[int64_t(c) * nH + i] = s;
+    }
+}
+
+__global__ void k_prolong_add(const int64_t* __restrict__ tp, const int32_t* __restrict__ tr, const double* __restrict__ tv,
+                              int64_t N, const double* __restrict__ zc, int64_t nH, int k, double* __restrict__ z,
+                              int64_t ld) {
+    const int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (j >= N) return;
+    for (int c = 0; c < k; ++c) {
+        double s = 0.0;
+        for (int64_t e = tp[j]; e < tp[j + 1]; ++e) s = fma(tv[e], zc[int64_t(c) * nH + tr[e]], s);
+        z[int64_t(c) * ld + j] += s;
+    }
+}
+
+inline unsigned nblk(int64_t n, int per) { return unsigned((n + per - 1) / per); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------
+// Host: dof classes and the coarse prolongation
+// ---------------------------------------------------------------------------------------------
+namespace {
+
+struct CoarseCSR {
+    int64_t nH = 0;
+    std::vector<int64_t> ptr;
+    std::vector<int32_t> col;
+    std::vector<double> val;
+};
+
+// Row (i,j) of R_H: fine coefficients of the coarse jump basis function psi^H_{i,j}.  At a fine
+// generalized vertex x_{k,l} the coarse split function phi^H_{i,j} equals lambda^H_i(x_k) when
+// the fine sector (k,l) lies in coarse sector j of coarse vertex i, else 0; the jump of the coarse
+// function is represented by u_{k,l} - mean_l u_{k,.} on the fine jump basis (l < q_k).
+void build_prolongation(const MeshTopo& f, const MeshTopo& c, const int32_t* parent, CoarseCSR& R) {
+    const int64_t nt = f.nt;
+    // representative side (t, a, s) of every fine sector
+    std::vector<int64_t> soff(f.nv + 1, 0);
+    for (int64_t v = 0; v < f.nv; ++v) soff[v + 1] = soff[v] + f.q[v];
+    std::vector<int64_t> rep(soff[f.nv], -1);
+    for (int64_t t = 0; t < nt; ++t)
+        for (int a = 0; a < 3; ++a)
+            for (int s = 0; s < 2; ++s) {
+                int64_t v = f.T[3 * t + a];
+                int64_t slot = soff[v] + f.sector[(t * 3 + a) * 2 + s];
+                if (rep[slot] < 0) rep[slot] = (t * 3 + a) * 2 + s;
+            }
+    std::vector<std::vector<std::pair<int32_t, double>>> rows(c.N);
+    std::map<int64_t, std::vector<double>> u;
+    for (int64_t k = 0; k < f.nv; ++k) {
+        const int qk = f.q[k];
+        if (qk < 2) continue;
+        u.clear();
+        const double xk[3] = {f.V[3 * k], f.V[3 * k + 1], f.V[3 * k + 2]};
+        for (int l = 0; l < qk; ++l) {
+            const int64_t node = rep[soff[k] + l];
+            const int64_t t = node / 6;
+            const int s = int(node % 2);
+            const int64_t tc = parent[t];
+            double nd = 0;
+            for (int d = 0; d < 3; ++d) nd += f.normal[3 * t + d] * c.normal[3 * tc + d];
+            const int sc = nd > 0 ? s : 1 - s;
+            const double* P0 = &c.V[3 * int64_t(c.T[3 * tc])];
+            const double* P1 = &c.V[3 * int64_t(c.T[3 * tc + 1])];
+            const double* P2 = &c.V[3 * int64_t(c.T[3 * tc + 2])];
+            double e1[3], e2[3], rr[3];
+            for (int d = 0; d < 3; ++d) { e1[d] = P1[d] - P0[d]; e2[d] = P2[d] - P0[d]; rr[d] = xk[d] - P0[d]; }
+            const double g11 = e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2];
+            const double g12 = e1[0] * e2[0] + e1[1] * e2[1] + e1[2] * e2[2];
+            const double g22 = e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2];
+            const double b1 = e1[0] * rr[0] + e1[1] * rr[1] + e1[2] * rr[2];
+            const double b2 = e2[0] * rr[0] + e2[1] * rr[1] + e2[2] * rr[2];
+            const double det = g11 * g22 - g12 * g12;
+            const double l1 = (b1 * g22 - b2 * g12) / det, l2 = (g11 * b2 - g12 * b1) / det;
+            const double lam[3] = {1.0 - l1 - l2, l1, l2};
+            double off = 0;   // distance of x_k from the plane of the coarse triangle
+            for (int d = 0; d < 3; ++d) { double p = rr[d] - l1 * e1[d] - l2 * e2[d]; off += p * p; }
+            if (lam[0] < -1e-9 || lam[1] < -1e-9 || lam[2] < -1e-9 || off > 1e-18 * (g11 + g22))
+                fail(BEM_E_INVALID_ARG, "fine triangle " + std::to_string(t) + " is not inside its coarse triangle");
+            for (int ac = 0; ac < 3; ++ac) {
+                if (std::fabs(lam[ac]) < 1e-12) continue;
+                const int64_t i = c.T[3 * tc + ac];
+                const int qi = c.q[i];
+                const int jc = c.sector[(tc * 3 + ac) * 2 + sc];
+                for (int j = 0; j + 1 < qi; ++j) {
+                    const double sign = (jc == j) ? 1.0 : (jc == qi - 1 ? -1.0 : 0.0);
+                    if (sign == 0.0) continue;
+                    auto& vec = u[c.first_dof[i] + j];
+                    if (vec.empty()) vec.assign(qk, 0.0);
+                    vec[l] += lam[ac] * sign;
+                }
+            }
+        }
+        for (auto& kv : u) {
+            double mean = 0;
+            for (double x : kv.second) mean += x;
+            mean /= qk;
+            for (int l = 0; l + 1 < qk; ++l) {
+                const double cv = kv.second[l] - mean;
+                if (cv != 0.0) rows[kv.first].push_back({int32_t(f.first_dof[k] + l), cv});
+            }
+        }
+    }
+    R.nH = c.N;
+    R.ptr.assign(c.N + 1, 0);
+    for (int64_t i = 0; i < c.N; ++i) {
+        std::sort(rows[i].begin(), rows[i].end());
+        R.ptr[i + 1] = R.ptr[i] + int64_t(rows[i].size());
+        for (auto& e : rows[i]) { R.col.push_back(e.first); R.val.push_back(e.second); }
+    }
+}
+
+}  // namespace
+
+void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV, int64_t ncv, const int32_t* cT,
+                          int64_t nct, const int32_t* parent) {
+    auto t0 = std::chrono::steady_clock::now();
+    bem_problem* p = M->p;
+    const MeshTopo& f = p->topo;
+    hipStream_t s = p->stream;
+    if (!patch) fail(BEM_E_INVALID_ARG, "patch_of_triangle is NULL");
+
+    // ---- dof classes ---------------------------------------------------------------------------
+    std::vector<int64_t> vpatch(f.nv, -1);   // -1 unseen, -2 several patches / no patch
+    for (int64_t t = 0; t < f.nt; ++t)
+        for (int a = 0; a < 3; ++a) {
+            const int64_t v = f.T[3 * t + a];
+            const int64_t pid = patch[t] < 0 ? -2 : patch[t];
+            if (vpatch[v] == -1) vpatch[v] = pid;
+            else if (vpatch[v] != pid) vpatch[v] = -2;
+        }
+    std::map<int64_t, std::vector<int32_t>> faces;
+    std::vector<int32_t> wb;
+    for (int64_t d = 0; d < f.N; ++d) {
+        const int64_t v = f.dof_vertex[d];
+        if (vpatch[v] >= 0 && f.q[v] == 2) faces[vpatch[v]].push_back(int32_t(d));
+        else wb.push_back(int32_t(d));
+    }
+    std::vector<std::vector<int32_t>> blocks;
+    for (auto& kv : faces) blocks.push_back(kv.second);
+    M->n_faces = int64_t(blocks.size());
+    M->n_wb = int64_t(wb.size());
+    if (!wb.empty()) blocks.push_back(wb);
+    M->max_face = 0;
+    for (int64_t b = 0; b < M->n_faces; ++b) M->max_face = std::max<int64_t>(M->max_face, blocks[b].size());
+    M->nblocks = int64_t(blocks.size());
+
+    // ---- coarse space -----------------------------------------------------------------------------
+    CoarseCSR R;
+    if (M->use_coarse && ncv > 0 && nct > 0) {
+        if (!cV || !cT || !parent) fail(BEM_E_INVALID_ARG, "coarse mesh arrays missing");
+        for (int64_t t = 0; t < f.nt; ++t)
+            if (parent[t] < 0 || parent[t] >= nct) fail(BEM_E_INVALID_ARG, "coarse_of_triangle out of range");
+        MeshTopo c;
+        analyze_mesh(cV, ncv, cT, nct, c);
+        build_prolongation(f, c, parent, R);
+    }
+    M->nH = R.nH;
+
+    // ---- block layout (faces, wire basket, then the coarse block) -----------------------------------
+    const int64_t nall = M->nblocks + (M->nH > 0 ? 1 : 0);
+    std::vector<BlockMeta> meta(nall);
+    std::vector<int32_t> idx;
+    int64_t moff = 0;
+    for (int64_t b = 0; b < nall; ++b) {
+        const int64_t n = (b < M->nblocks) ? int64_t(blocks[b].size()) : M->nH;
+        const int64_t npad = ((n + TBK - 1) / TBK) * TBK;
+        meta[b] = {n, npad, int64_t(idx.size()), moff};
+        if (b < M->nblocks) idx.insert(idx.end(), blocks[b].begin(), blocks[b].end());
+        moff += npad * npad;
+        M->blk_n.push_back(n);
+        M->blk_npad.push_back(npad);
+        M->blk_idx_off.push_back(meta[b].idx_off);
+        M->blk_mat_off.push_back(meta[b].mat_off);
+    }
+    M->idx_total = int64_t(idx.size());
+    M->mat_total = moff;
+    M->idx = upload(idx, s);
+    M->blk_meta = upload(meta, s);
+    DeviceBuffer A(sizeof(double) * std::max<int64_t>(moff, 1)), X(sizeof(double) * std::max<int64_t>(moff, 1));
+    DeviceBuffer dflags(sizeof(int) * std::max<int64_t>(nall, 1));
+    HIP_CHECK(hipMemsetAsync(dflags.ptr, 0, sizeof(int) * std::max<int64_t>(nall, 1), s));
+
+    auto launch_tasks = [&](const std::vector<int4>& tl, auto&& fn) {
+        if (tl.empty()) return;
+        DeviceBuffer dt = upload(tl, s);
+        fn(dt.as<int4>(), unsigned(tl.size()));
+        HIP_CHECK(hipGetLastError());
+        HIP_CHECK(hipStreamSynchronize(s));   // keeps dt alive until the launch has finished
+    };
+    const BlockMeta* dm = M->blk_meta.as<BlockMeta>();
+
+    // gather face / wire-basket blocks
+    {
+        std::vector<int4> tl;
+        for (int64_t b = 0; b < M->nblocks; ++b) {
+            const int nt = int(meta[b].npad / TBK);
+            for (int i = 0; i < nt; ++i)
+                for (int j = 0; j < nt; ++j) tl.push_back(make_int4(int(b), i, j, 0));
+        }
+        launch_tasks(tl, [&](const int4* d, unsigned n) {
+            hipLaunchKernelGGL(k_gather, dim3(n), dim3(256), 0, s, d, dm, M->idx.as<int32_t>(), p->W64.as<double>(), p->ldw, A.as<double>());
+        });
+    }
+    // coarse Galerkin block
+    if (M->nH > 0) {
+        M->rh_ptr = upload(R.ptr, s);
+        M->rh_col = upload(R.col, s);
+        M->rh_val = upload(R.val, s);
+        // transposed CSR (fine dof -> coarse dofs)
+        std::vector<int64_t> tp(f.N + 1, 0);
+        for (int32_t cidx : R.col) ++tp[cidx + 1];
+        for (int64_t j = 0; j < f.N; ++j) tp[j + 1] += tp[j];
+        std::vector<int32_t> trow(R.col.size());
+        std::vector<double> tval(R.col.size());
+        std::vector<int64_t> fill(tp.begin(), tp.end() - 1);
+        for (int64_t i = 0; i < R.nH; ++i)
+            for (int64_t e = R.ptr[i]; e < R.ptr[i + 1]; ++e) {
+                int64_t pos = fill[R.col[e]]++;
+                trow[pos] = int32_t(i);
+                tval[pos] = R.val[e];
+            }
+        M->rht_ptr = upload(tp, s);
+        M->rht_row = upload(trow, s);
+        M->rht_val = upload(tval, s);
+        DeviceBuffer Y(sizeof(double) * std::max<int64_t>(1, f.N * M->nH));
+        hipLaunchKernelGGL(k_coarse_Y, dim3(nblk(f.N, 256), unsigned(M->nH)), dim3(256), 0, s, p->W64.as<double>(), p->ldw, f.N,
+                           M->rh_ptr.as<int64_t>(), M->rh_col.as<int32_t>(), M->rh_val.as<double>(), M->nH, Y.as<double>());
+        HIP_CHECK(hipGetLastError());
+        const BlockMeta& cm = meta[nall - 1];
+        double* Ac = A.as<double>() + cm.mat_off;
+        hipLaunchKernelGGL(k_coarse_WH, dim3(nblk(cm.npad, 256), unsigned(M->nH)), dim3(256), 0, s, Y.as<double>(), M->nH,
+                           M->rh_ptr.as<int64_t>(), M->rh_col.as<int32_t>(), M->rh_val.as<double>(), Ac, cm.npad);
+        HIP_CHECK(hipGetLastError());
+        if (cm.npad > M->nH) {
+            hipLaunchKernelGGL(k_coarse_pad_rows, dim3(nblk(cm.npad, 256), unsigned(cm.npad - M->nH)), dim3(256), 0, s, Ac, M->nH, cm.npad);
+            HIP_CHECK(hipGetLastError());
+        }
+        HIP_CHECK(hipStreamSynchronize(s));
+    }
+
+    // ---- tiled Cholesky, all blocks together ---------------------------------------------------
+    int maxT = 0;
+    for (int64_t b = 0; b < nall; ++b) maxT = std::max<int>(maxT, int(meta[b].npad / TBK));
+    for (int k = 0; k < maxT; ++k) {
+        std::vector<int4> tp, tt, tu;
+        for (int64_t b = 0; b < nall; ++b) {
+            const int nt = int(meta[b].npad / TBK);
+            if (k >= nt) continue;
+            tp.push_back(make_int4(int(b), k, k, 0));
+            for (int i = k + 1; i < nt; ++i) {
+                tt.push_back(make_int4(int(b), i, k, 0));
+                for (int j = k + 1; j <= i; ++j) tu.push_back(make_int4(int(b), i, j, 0));
+            }
+        }
+        launch_tasks(tp, [&](const int4* d, unsigned n) {
+            hipLaunchKernelGGL(k_potrf, dim3(n), dim3(256), 0, s, d, dm, A.as<double>(), k, dflags.as<int>());
+        });
+        launch_tasks(tt, [&](const int4* d, unsigned n) {
+            hipLaunchKernelGGL(k_trsm, dim3(n), dim3(256), 0, s, d, dm, A.as<double>(), k);
+        });
+        launch_tasks(tu, [&](const int4* d, unsigned n) {
+            hipLaunchKernelGGL(k_update, dim3(n), dim3(256), 0, s, d, dm, A.as<double>(), k);
+        });
+    }
+    std::vector<int> flags(nall);
+    HIP_CHECK(hipMemcpy(flags.data(), dflags.ptr, sizeof(int) * nall, hipMemcpyDeviceToHost));
+    for (int64_t b = 0; b < nall; ++b)
+        if (flags[b]) fail(BEM_E_NOT_SPD, "preconditioner block " + std::to_string(b) + " is not positive definite");
+
+    // ---- inverse of the factor, then B = L^{-T} L^{-1} --------------------------------------------
+    {
+        std::vector<int4> td;
+        for (int64_t b = 0; b < nall; ++b)
+            for (int i = 0; i < int(meta[b].npad / TBK); ++i) td.push_back(make_int4(int(b), i, 0, 0));
+        launch_tasks(td, [&](const int4* d, unsigned n) {
+            hipLaunchKernelGGL(k_trtri_diag, dim3(n), dim3(256), 0, s, d, dm, A.as<double>(), X.as<double>());
+        });
+        for (int i = 1; i < maxT; ++i) {
+            std::vector<int4> tr;
+            for (int64_t b = 0; b < nall; ++b) {
+                const int nt = int(meta[b].npad / TBK);
+                if (i >= nt) continue;
+                for (int j = 0; j < i; ++j) tr.push_back(make_int4(int(b), j, 0, 0));
+            }
+            launch_tasks(tr, [&](const int4* d, unsigned n) {
+                hipLaunchKernelGGL(k_trtri_row, dim3(n), dim3(256), 0, s, d, dm, A.as<double>(), X.as<double>(), i);
+            });
+        }
+        std::vector<int4> ts;
+        for (int64_t b = 0; b < nall; ++b) {
+            const int nt = int(meta[b].npad / TBK);
+            for (int i = 0; i < nt; ++i)
+                for (int j = 0; j <= i; ++j) ts.push_back(make_int4(int(b), i, j, 0));
+        }
+        launch_tasks(ts, [&](const int4* d, unsigned n) {
+            hipLaunchKernelGGL(k_syrk_inverse, dim3(n), dim3(256), 0, s, d, dm, X.as<double>(), A.as<double>());
+        });
+    }
+    M->inv64 = std::move(A);
+    if (M->fp32) {
+        M->inv32 = DeviceBuffer(sizeof(float) * std::max<int64_t>(moff, 1));
+        hipLaunchKernelGGL(k_to_f32, dim3(2048), dim3(256), 0, s, M->inv64.as<double>(), M->inv32.as<float>(), moff);
+        HIP_CHECK(hipGetLastError());
+    }
+    // the coarse inverse lives in inv64 as the last block
+
+    // ---- apply tasks: 64-row panels of the face / wire-basket blocks ------------------------------
+    std::vector<int4> at;
+    for (int64_t b = 0; b < M->nblocks; ++b)
+        for (int64_t r0 = 0; r0 < meta[b].n; r0 += 64)
+            at.push_back(make_int4(int(b), int(r0), int(std::min<int64_t>(64, meta[b].n - r0)), 0));
+    M->ntasks = int64_t(at.size());
+    M->tasks = upload(at, s);
+    HIP_CHECK(hipStreamSynchronize(s));
+    M->bytes = int64_t(M->inv64.bytes + M->inv32.bytes + M->idx.bytes + M->rh_val.bytes * 3);
+    M->t_setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+int64_t precond_scratch_size(const bem_precond* m, int k) { return 2 * std::max<int64_t>(1, m->nH) * k; }
+
+void precond_apply_device(const bem_precond* M, bool fp32, const double* r, int64_t ld, int k, double* z,
+                          hipStream_t s, double* scratch) {
+    const BlockMeta* dm = M->blk_meta.as<BlockMeta>();
+    const bem_problem* p = M->p;
+    for (int c0 = 0; c0 < k; c0 += 16) {
+        const int kc = std::min(16, k - c0);
+        const double* rc = r + int64_t(c0) * ld;
+        double* zc = z + int64_t(c0) * ld;
+        if (M->ntasks > 0) {
+            dim3 grid(unsigned(M->ntasks)), block(256);
+#define APPLY(MT, KK, PTR)                                                                                          \
+    hipLaunchKernelGGL((k_block_apply<MT, KK>), grid, block, 0, s, M->tasks.as<int4>(), dm, M->idx.as<int32_t>(), \
+                       PTR, rc, ld, kc, zc)
+            if (fp32 && M->inv32.ptr) {
+                const float* ptr = M->inv32.as<float>();
+                if (kc == 1) APPLY(float, 1, ptr);
+                else if (kc <= 4) APPLY(float, 4, ptr);
+                else APPLY(float, 16, ptr);
+            } else {
+                const double* ptr = M->inv64.as<double>();
+                if (kc == 1) APPLY(double, 1, ptr);
+                else if (kc <= 4) APPLY(double, 4, ptr);
+                else APPLY(double, 16, ptr);
+            }
+#undef APPLY
+            HIP_CHECK(hipGetLastError());
+        }
+        if (M->nH > 0) {
+            const int64_t nH = M->nH;
+            double* rcoarse = scratch;
+            double* zcoarse = scratch + nH * kc;
+            hipLaunchKernelGGL(k_restrict, dim3(nblk(nH, 128)), dim3(128), 0, s, M->rh_ptr.as<int64_t>(), M->rh_col.as<int32_t>(),
+                               M->rh_val.as<double>(), nH, rc, ld, kc, rcoarse);
+            const int64_t cb = M->nblocks;
+            const double* Binv = M->inv64.as<double>() + M->blk_mat_off[cb];
+            hipLaunchKernelGGL(k_coarse_solve, dim3(nblk(nH, 64)), dim3(64), 0, s, Binv, M->blk_npad[cb], nH, rcoarse, kc, zcoarse);
+            hipLaunchKernelGGL(k_prolong_add, dim3(nblk(p->N, 256)), dim3(256), 0, s, M->rht_ptr.as<int64_t>(), M->rht_row.as<int32_t>(),
+                               M->rht_val.as<double>(), p->N, zcoarse, nH, kc, zc, ld);
+            HIP_CHECK(hipGetLastError());
+        }
+    }
+}
+
+}  // namespace bem

@@ -1,0 +1,551 @@
+// Preconditioned conjugate gradients for W Phi = L (paper: Remark "Bound on the number of
+// Preconditioned Conjugate Gradient iterations" -- PCG on P_ad = M A_h; x0 = 0; the stopping rule
+// ||L - W x||_2 <= tol ||L||_2 on the unpreconditioned residual is the build's choice).
+//
+// k right-hand sides run side by side: each iteration streams W once for all columns (row-panel
+// matvec), and every column keeps its own scalars (alpha, beta, r.z) in device memory, so an
+// iteration is a fixed sequence of kernels with no host round trip.  That sequence is captured
+// once into a hipGraph and replayed; the host only reads the per-column status every few
+// iterations.  Converged columns are frozen (their updates become no-ops), so iteration counts are
+// exact.  The mixed-precision mode is iterative refinement: residuals with the FP64 matrix, each
+// correction from a PCG on the FP32 copy of W with FP32 block inverses (FP64 dot products, vector
+// updates and coarse solve).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "internal.h"
+
+namespace bem {
+
+namespace {
+
+struct ColState {
+    double rz, pq, rr, alpha, beta, bb, tol2, pad;
+    int active, iters, flag, pad2;
+};
+
+constexpr int kStatBreakdown = 2;
+
+// ---------------------------------------------------------------------------------------------
+// dense row-panel matvec: one wave per row, 16-byte loads of W, k columns
+// ---------------------------------------------------------------------------------------------
+template <typename MT, typename AT, int K>
+__global__ __launch_bounds__(256) void k_matvec(const MT* __restrict__ W, int64_t ldw, int64_t N,
+                                                const double* __restrict__ x, int64_t ldx, int kc,
+                                                double* __restrict__ y, int64_t ldy) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (row >= N) return;
+    constexpr int VEC = 16 / sizeof(MT);
+    const MT* w = W + row * ldw;
+    AT acc[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) acc[c] = AT(0);
+    const int64_t step = 64 * VEC;
+    const int64_t nfull = (N / step) * step;
+    for (int64_t j = int64_t(lane) * VEC; j < nfull; j += step) {
+        MT wv[VEC];
+        if constexpr (VEC == 2) {
+            const double2 t = *reinterpret_cast<const double2*>(w + j);
+            wv[0] = t.x; wv[1] = t.y;
+        } else {
+            const float4 t = *reinterpret_cast<const float4*>(w + j);
+            wv[0] = t.x; wv[1] = t.y; wv[2] = t.z; wv[3] = t.w;
+        }
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            if (c >= kc) break;
+            const double* xc = x + int64_t(c) * ldx + j;
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) acc[c] = fma(AT(wv[v]), AT(xc[v]), acc[c]);
+        }
+    }
+    for (int64_t j = nfull + lane; j < N; j += 64) {
+        const AT wj = AT(w[j]);
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            if (c >= kc) break;
+            acc[c] = fma(wj, AT(x[int64_t(c) * ldx + j]), acc[c]);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        AT v = acc[c];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        acc[c] = v;
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int c = 0; c < K; ++c)
+            if (c < kc) y[int64_t(c) * ldy + row] = double(acc[c]);
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// vector kernels (grid: G blocks x k columns; block-partial sums reduced in a fixed order)
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum(double v) {
+    __shared__ double red[4];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) s = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+    return s;
+}
+
+__global__ __launch_bounds__(256) void k_dot_partial(const double* __restrict__ a, const double* __restrict__ b,
+                                                     int64_t ld, int64_t N, double* __restrict__ partial) {
+    const int c = blockIdx.y;
+    const double* ac = a + int64_t(c) * ld;
+    const double* bc = b + int64_t(c) * ld;
+    double s = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < N; i += int64_t(gridDim.x) * 256) s = fma(ac[i], bc[i], s);
+    s = block_sum(s);
+    if (threadIdx.x == 0) partial[int64_t(c) * gridDim.x + blockIdx.x] = s;
+}
+
+__device__ __forceinline__ double reduce_partials(const double* __restrict__ p, int G) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < G; i += 256) s += p[i];
+    return block_sum(s);
+}
+
+// p.q -> alpha
+__global__ __launch_bounds__(256) void k_alpha(const double* __restrict__ partial, int G, ColState* __restrict__ st,
+                                               double* __restrict__ hist, int max_hist) {
+    const int c = blockIdx.x;
+    const double pq = reduce_partials(partial + int64_t(c) * G, G);
+    if (threadIdx.x == 0) {
+        ColState& s = st[c];
+        s.pq = pq;
+        if (s.active) {
+            if (!(pq > 0.0) || !isfinite(pq)) {
+                s.active = 0;
+                s.flag = kStatBreakdown;
+                s.alpha = 0.0;
+            } else {
+                s.alpha = s.rz / pq;
+                if (s.iters < max_hist) hist[int64_t(c) * 2 * max_hist + s.iters] = s.alpha;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_update_xr(double* __restrict__ x, double* __restrict__ r,
+                                                   const double* __restrict__ p, const double* __restrict__ q,
+                                                   int64_t ld, int64_t N, const ColState* __restrict__ st,
+                                                   double* __restrict__ partial) {
+    const int c = blockIdx.y;
+    const ColState& s = st[c];
+    double acc = 0.0;
+    if (s.active) {
+        const double al = s.alpha;
+        double* xc = x + int64_t(c) * ld;
+        double* rc = r + int64_t(c) * ld;
+        const double* pc = p + int64_t(c) * ld;
+        const double* qc = q + int64_t(c) * ld;
+        for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < N; i += int64_t(gridDim.x) * 256) {
+            xc[i] = fma(al, pc[i], xc[i]);
+            const double ri = fma(-al, qc[i], rc[i]);
+            rc[i] = ri;
+            acc = fma(ri, ri, acc);
+        }
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partial[int64_t(c) * gridDim.x + blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_check(const double* __restrict__ partial, int G, ColState* __restrict__ st) {
+    const int c = blockIdx.x;
+    const double rr = reduce_partials(partial + int64_t(c) * G, G);
+    if (threadIdx.x == 0) {
+        ColState& s = st[c];
+        if (s.active) {
+            s.iters += 1;
+            s.rr = rr;
+            if (!isfinite(rr)) {
+                s.active = 0;
+                s.flag = kStatBreakdown;
+            } else if (rr <= s.tol2 * s.bb) {
+                s.active = 0;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_beta(const double* __restrict__ partial, int G, ColState* __restrict__ st,
+                                              double* __restrict__ hist, int max_hist) {
+    const int c = blockIdx.x;
+    const double rz = reduce_partials(partial + int64_t(c) * G, G);
+    if (threadIdx.x == 0) {
+        ColState& s = st[c];
+        if (s.active) {
+            s.beta = rz / s.rz;
+            s.rz = rz;
+            const int it = s.iters - 1;
+            if (it < max_hist) hist[int64_t(c) * 2 * max_hist + max_hist + it] = s.beta;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_update_p(double* __restrict__ p, const double* __restrict__ z, int64_t ld,
+                                                  int64_t N, const ColState* __restrict__ st) {
+    const int c = blockIdx.y;
+    const ColState& s = st[c];
+    if (!s.active) return;
+    const double be = s.beta;
+    double* pc = p + int64_t(c) * ld;
+    const double* zc = z + int64_t(c) * ld;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < N; i += int64_t(gridDim.x) * 256) pc[i] = fma(be, pc[i], zc[i]);
+}
+
+__global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, int64_t ld, int64_t N) {
+    const int c = blockIdx.y;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < N; i += int64_t(gridDim.x) * 256)
+        b[int64_t(c) * ld + i] = a[int64_t(c) * ld + i];
+}
+
+__global__ void k_fill(double* __restrict__ a, double v, int64_t n) {
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) a[i] = v;
+}
+
+// r = b - y
+__global__ void k_residual(const double* __restrict__ b, const double* __restrict__ y, double* __restrict__ r,
+                           int64_t ld, int64_t N) {
+    const int c = blockIdx.y;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < N; i += int64_t(gridDim.x) * 256)
+        r[int64_t(c) * ld + i] = b[int64_t(c) * ld + i] - y[int64_t(c) * ld + i];
+}
+
+__global__ void k_axpy_cols(double* __restrict__ x, const double* __restrict__ d, int64_t ld, int64_t N) {
+    const int c = blockIdx.y;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < N; i += int64_t(gridDim.x) * 256)
+        x[int64_t(c) * ld + i] += d[int64_t(c) * ld + i];
+}
+
+// state init from partials of b.b, r.r, r.z
+__global__ __launch_bounds__(256) void k_init_state(const double* __restrict__ pbb, const double* __restrict__ prr,
+                                                    const double* __restrict__ prz, int G, const double* __restrict__ tol2,
+                                                    ColState* __restrict__ st) {
+    const int c = blockIdx.x;
+    const double bb = reduce_partials(pbb + int64_t(c) * G, G);
+    const double rr = reduce_partials(prr + int64_t(c) * G, G);
+    const double rz = reduce_partials(prz + int64_t(c) * G, G);
+    if (threadIdx.x == 0) {
+        ColState s{};
+        s.bb = bb;
+        s.rr = rr;
+        s.rz = rz;
+        s.tol2 = tol2[c];
+        s.iters = 0;
+        s.flag = 0;
+        if (!isfinite(bb) || !isfinite(rr) || !isfinite(rz)) {
+            s.active = 0;
+            s.flag = kStatBreakdown;
+        } else {
+            s.active = (bb > 0.0 && rr > s.tol2 * bb) ? 1 : 0;
+        }
+        st[c] = s;
+    }
+}
+
+inline unsigned gblocks(int64_t N) { return unsigned(std::max<int64_t>(1, std::min<int64_t>(1024, (N + 255) / 256))); }
+
+template <typename MT, typename AT>
+void launch_matvec(const MT* W, int64_t ldw, int64_t N, const double* x, int64_t ldx, int k, double* y, int64_t ldy,
+                   hipStream_t s) {
+    const dim3 grid(unsigned((N + 3) / 4)), block(256);
+    for (int c0 = 0; c0 < k; c0 += 16) {
+        const int kc = std::min(16, k - c0);
+        const double* xc = x + int64_t(c0) * ldx;
+        double* yc = y + int64_t(c0) * ldy;
+        if (kc == 1) hipLaunchKernelGGL((k_matvec<MT, AT, 1>), grid, block, 0, s, W, ldw, N, xc, ldx, kc, yc, ldy);
+        else if (kc == 2) hipLaunchKernelGGL((k_matvec<MT, AT, 2>), grid, block, 0, s, W, ldw, N, xc, ldx, kc, yc, ldy);
+        else if (kc <= 4) hipLaunchKernelGGL((k_matvec<MT, AT, 4>), grid, block, 0, s, W, ldw, N, xc, ldx, kc, yc, ldy);
+        else if (kc <= 8) hipLaunchKernelGGL((k_matvec<MT, AT, 8>), grid, block, 0, s, W, ldw, N, xc, ldx, kc, yc, ldy);
+        else hipLaunchKernelGGL((k_matvec<MT, AT, 16>), grid, block, 0, s, W, ldw, N, xc, ldx, kc, yc, ldy);
+        HIP_CHECK(hipGetLastError());
+    }
+}
+
+// smallest / largest eigenvalue of a symmetric tridiagonal matrix by Sturm-sequence bisection
+double tridiag_extreme(const std::vector<double>& d, const std::vector<double>& e, bool largest) {
+    const int m = int(d.size());
+    double lo = 1e300, hi = -1e300;
+    for (int i = 0; i < m; ++i) {
+        double r = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < m ? std::fabs(e[i]) : 0.0);
+        lo = std::min(lo, d[i] - r);
+        hi = std::max(hi, d[i] + r);
+    }
+    auto count_below = [&](double x) {
+        int cnt = 0;
+        double q = 1.0;
+        for (int i = 0; i < m; ++i) {
+            double off = (i > 0) ? e[i - 1] * e[i - 1] : 0.0;
+            q = d[i] - x - (i > 0 ? off / q : 0.0);
+            if (q == 0.0) q = -1e-300;
+            if (q < 0) ++cnt;
+        }
+        return cnt;
+    };
+    const int target = largest ? m - 1 : 0;
+    for (int it = 0; it < 200 && hi - lo > 1e-14 * std::max(std::fabs(lo), std::fabs(hi)); ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (count_below(mid) > target) hi = mid; else lo = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+double lanczos_condition(const double* alpha, const double* beta, int m) {
+    if (m <= 0) return std::nan("");
+    std::vector<double> d(m), e(std::max(0, m - 1));
+    for (int j = 0; j < m; ++j) {
+        d[j] = 1.0 / alpha[j] + (j > 0 ? beta[j - 1] / alpha[j - 1] : 0.0);
+        if (j + 1 < m) e[j] = std::sqrt(std::max(0.0, beta[j])) / alpha[j];
+    }
+    const double lmin = tridiag_extreme(d, e, false), lmax = tridiag_extreme(d, e, true);
+    return lmax / lmin;
+}
+
+}  // namespace
+
+void matvec_device(const bem_problem* p, bool fp32, const double* d_x, int64_t ldx, int k, double* d_y, hipStream_t s) {
+    if (p->N == 0) return;
+    if (fp32) {
+        if (!p->W32.ptr) fail(BEM_E_INVALID_ARG, "problem has no FP32 matrix (assemble with BEM_FP32_REFINE)");
+        launch_matvec<float, float>(p->W32.as<float>(), p->ldw, p->N, d_x, ldx, k, d_y, ldx, s);
+    } else {
+        launch_matvec<double, double>(p->W64.as<double>(), p->ldw, p->N, d_x, ldx, k, d_y, ldx, s);
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// PCG on device buffers.  b, x: [k][ld].  x is used as the start vector (zero it for x0 = 0) and
+// receives the result.  Per-column tolerance tol[c] on ||r|| / ||b||.
+// ---------------------------------------------------------------------------------------------
+struct PcgResult {
+    std::vector<int> iters, flag, active;
+    std::vector<double> rr, bb, cond;
+};
+
+PcgResult pcg_device(bem_problem* p, const bem_precond* M, bool fp32, const double* b, double* x, bool x_nonzero,
+                     int k, int64_t ld, const std::vector<double>& tol, int max_iter, int check_every, bool use_graph,
+                     bool want_cond) {
+    hipStream_t s = p->stream;
+    const int64_t N = p->N;
+    const unsigned G = gblocks(N);
+    DeviceBuffer r(sizeof(double) * ld * k), z(sizeof(double) * ld * k), pp(sizeof(double) * ld * k), q(sizeof(double) * ld * k);
+    DeviceBuffer part(sizeof(double) * G * k * 3), dst(sizeof(ColState) * k), dtol(sizeof(double) * k);
+    const int max_hist = want_cond ? std::max(1, max_iter) : 1;
+    DeviceBuffer hist(sizeof(double) * 2 * max_hist * k);
+    DeviceBuffer cscr(sizeof(double) * (M ? precond_scratch_size(M, std::min(k, 16)) : 1));
+    std::vector<double> tol2(k);
+    for (int c = 0; c < k; ++c) tol2[c] = tol[c] * tol[c];
+    HIP_CHECK(hipMemcpyAsync(dtol.ptr, tol2.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
+    double* pa = part.as<double>();
+    double* pb = pa + int64_t(G) * k;
+    double* pc = pb + int64_t(G) * k;
+    const dim3 vg(G, unsigned(k)), vb(256);
+
+    auto apply_M = [&](const double* in, double* out) {
+        if (M) precond_apply_device(M, fp32, in, ld, k, out, s, cscr.as<double>());
+        else hipLaunchKernelGGL(k_copy, vg, vb, 0, s, in, out, ld, N);
+        HIP_CHECK(hipGetLastError());
+    };
+    auto matvec = [&](const double* in, double* out) { matvec_device(p, fp32, in, ld, k, out, s); };
+
+    // ---- initial state ----
+    if (x_nonzero) {
+        matvec(x, q.as<double>());
+        hipLaunchKernelGGL(k_residual, vg, vb, 0, s, b, q.as<double>(), r.as<double>(), ld, N);
+    } else {
+        hipLaunchKernelGGL(k_copy, vg, vb, 0, s, b, r.as<double>(), ld, N);
+    }
+    apply_M(r.as<double>(), z.as<double>());
+    hipLaunchKernelGGL(k_copy, vg, vb, 0, s, z.as<double>(), pp.as<double>(), ld, N);
+    hipLaunchKernelGGL(k_dot_partial, vg, vb, 0, s, b, b, ld, N, pa);
+    hipLaunchKernelGGL(k_dot_partial, vg, vb, 0, s, r.as<double>(), r.as<double>(), ld, N, pb);
+    hipLaunchKernelGGL(k_dot_partial, vg, vb, 0, s, r.as<double>(), z.as<double>(), ld, N, pc);
+    hipLaunchKernelGGL(k_init_state, dim3(k), vb, 0, s, pa, pb, pc, int(G), dtol.as<double>(), dst.as<ColState>());
+    HIP_CHECK(hipGetLastError());
+
+    ColState* st = dst.as<ColState>();
+    double* h = hist.as<double>();
+    auto iteration = [&]() {
+        matvec(pp.as<double>(), q.as<double>());
+        hipLaunchKernelGGL(k_dot_partial, vg, vb, 0, s, pp.as<double>(), q.as<double>(), ld, N, pa);
+        hipLaunchKernelGGL(k_alpha, dim3(k), vb, 0, s, pa, int(G), st, h, max_hist);
+        hipLaunchKernelGGL(k_update_xr, vg, vb, 0, s, x, r.as<double>(), pp.as<double>(), q.as<double>(), ld, N, st, pb);
+        hipLaunchKernelGGL(k_check, dim3(k), vb, 0, s, pb, int(G), st);
+        apply_M(r.as<double>(), z.as<double>());
+        hipLaunchKernelGGL(k_dot_partial, vg, vb, 0, s, r.as<double>(), z.as<double>(), ld, N, pc);
+        hipLaunchKernelGGL(k_beta, dim3(k), vb, 0, s, pc, int(G), st, h, max_hist);
+        hipLaunchKernelGGL(k_update_p, vg, vb, 0, s, pp.as<double>(), z.as<double>(), ld, N, st);
+        HIP_CHECK(hipGetLastError());
+    };
+
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    if (use_graph) {
+        HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        iteration();
+        HIP_CHECK(hipStreamEndCapture(s, &graph));
+        HIP_CHECK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    }
+    std::vector<ColState> hs(k);
+    int launched = 0;
+    const int every = std::max(1, check_every);
+    HIP_CHECK(hipMemcpyAsync(hs.data(), st, sizeof(ColState) * k, hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    auto any_active = [&]() {
+        for (auto& c : hs) if (c.active) return true;
+        return false;
+    };
+    while (any_active() && launched < max_iter) {
+        const int n = std::min(every, max_iter - launched);
+        for (int i = 0; i < n; ++i) {
+            if (use_graph) HIP_CHECK(hipGraphLaunch(exec, s));
+            else iteration();
+        }
+        launched += n;
+        HIP_CHECK(hipMemcpyAsync(hs.data(), st, sizeof(ColState) * k, hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+
+    PcgResult res;
+    res.iters.resize(k); res.flag.resize(k); res.active.resize(k); res.rr.resize(k); res.bb.resize(k); res.cond.assign(k, std::nan(""));
+    std::vector<double> hh;
+    if (want_cond) {
+        hh.resize(size_t(2) * max_hist * k);
+        HIP_CHECK(hipMemcpy(hh.data(), h, sizeof(double) * hh.size(), hipMemcpyDeviceToHost));
+    }
+    for (int c = 0; c < k; ++c) {
+        res.iters[c] = hs[c].iters;
+        res.flag[c] = hs[c].flag;
+        res.active[c] = hs[c].active;
+        res.rr[c] = hs[c].rr;
+        res.bb[c] = hs[c].bb;
+        if (want_cond && hs[c].iters > 0 && !hs[c].flag) {
+            const int m = std::min(hs[c].iters, max_hist);
+            res.cond[c] = lanczos_condition(&hh[size_t(c) * 2 * max_hist], &hh[size_t(c) * 2 * max_hist + max_hist], m);
+        }
+    }
+    return res;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Full solve: FP64 PCG, or FP32-matrix PCG corrections inside FP64 iterative refinement.
+// b: device [k][N]; x: device [k][N] (output).
+// ---------------------------------------------------------------------------------------------
+void solve_device(bem_problem* p, const bem_precond* M, const double* b, double* x, int k, const bem_solve_opts& o,
+                  bem_solve_info* info) {
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = p->stream;
+    const int64_t N = p->N, ld = N;
+    const unsigned G = gblocks(N);
+    const dim3 vg(G, unsigned(k)), vb(256);
+    const bool use_m = (M != nullptr) && o.use_precond;
+    const int check = o.check_every > 0 ? o.check_every : 4;
+    std::vector<int> iters(k, 0), outer(k, 0), status(k, BEM_OK);
+    std::vector<double> relres(k, 0.0), cond(k, std::nan(""));
+
+    hipLaunchKernelGGL(k_fill, dim3(256), vb, 0, s, x, 0.0, int64_t(k) * ld);
+    if (o.precision == BEM_FP64) {
+        std::vector<double> tol(k, o.tol);
+        PcgResult r = pcg_device(p, use_m ? M : nullptr, false, b, x, false, k, ld, tol, o.max_iter, check, o.use_graph != 0, true);
+        for (int c = 0; c < k; ++c) {
+            iters[c] = r.iters[c];
+            cond[c] = r.cond[c];
+            if (r.flag[c]) status[c] = BEM_E_BREAKDOWN;
+            else if (r.active[c]) status[c] = BEM_E_NOT_CONVERGED;
+        }
+    } else {
+        if (!p->W32.ptr) fail(BEM_E_INVALID_ARG, "mixed precision needs a problem assembled with BEM_FP32_REFINE");
+        if (use_m && !M->inv32.ptr) fail(BEM_E_INVALID_ARG, "mixed precision needs a preconditioner with factor_fp32 = 1");
+        DeviceBuffer r(sizeof(double) * ld * k), y(sizeof(double) * ld * k), dlt(sizeof(double) * ld * k);
+        DeviceBuffer part(sizeof(double) * G * k * 2);
+        std::vector<double> bb(k), rr(k);
+        std::vector<double> hp(size_t(G) * k);
+        auto norms = [&](const double* a, std::vector<double>& out) {
+            hipLaunchKernelGGL(k_dot_partial, vg, vb, 0, s, a, a, ld, N, part.as<double>());
+            HIP_CHECK(hipMemcpyAsync(hp.data(), part.ptr, sizeof(double) * G * k, hipMemcpyDeviceToHost, s));
+            HIP_CHECK(hipStreamSynchronize(s));
+            for (int c = 0; c < k; ++c) {
+                double acc = 0;
+                for (unsigned g = 0; g < G; ++g) acc += hp[size_t(c) * G + g];
+                out[c] = acc;
+            }
+        };
+        norms(b, bb);
+        std::vector<char> done(k, 0);
+        const int max_outer = 30;
+        for (int it = 0; it < max_outer; ++it) {
+            // FP64 residual r = b - W x
+            matvec_device(p, false, x, ld, k, y.as<double>(), s);
+            hipLaunchKernelGGL(k_residual, vg, vb, 0, s, b, y.as<double>(), r.as<double>(), ld, N);
+            norms(r.as<double>(), rr);
+            bool all = true;
+            std::vector<double> tol(k);
+            for (int c = 0; c < k; ++c) {
+                if (!done[c]) outer[c] += 1;
+                relres[c] = bb[c] > 0 ? std::sqrt(rr[c] / bb[c]) : 0.0;
+                if (!std::isfinite(relres[c])) { status[c] = BEM_E_BREAKDOWN; done[c] = 1; }
+                if (relres[c] <= o.tol || iters[c] >= o.max_iter) done[c] = 1;
+                if (!done[c]) all = false;
+                // inner target: the requested inner tolerance, but no tighter than the remaining gap
+                tol[c] = done[c] ? 1.0 : std::max(o.inner_tol > 0 ? o.inner_tol : 1e-6, 0.5 * o.tol / std::max(relres[c], 1e-300));
+            }
+            if (all) break;
+            // columns already done get a zero right-hand side (inactive from the start)
+            for (int c = 0; c < k; ++c)
+                if (done[c]) hipLaunchKernelGGL(k_fill, dim3(64), vb, 0, s, r.as<double>() + int64_t(c) * ld, 0.0, N);
+            hipLaunchKernelGGL(k_fill, dim3(256), vb, 0, s, dlt.as<double>(), 0.0, int64_t(k) * ld);
+            int budget = o.max_iter;
+            for (int c = 0; c < k; ++c) if (!done[c]) budget = std::min(budget, std::max(1, o.max_iter - iters[c]));
+            PcgResult pr = pcg_device(p, use_m ? M : nullptr, true, r.as<double>(), dlt.as<double>(), false, k, ld, tol, budget,
+                                      check, o.use_graph != 0, it == 0);
+            for (int c = 0; c < k; ++c) {
+                if (done[c]) continue;
+                iters[c] += pr.iters[c];
+                if (it == 0) cond[c] = pr.cond[c];
+                if (pr.flag[c]) { status[c] = BEM_E_BREAKDOWN; done[c] = 1; }
+            }
+            hipLaunchKernelGGL(k_axpy_cols, vg, vb, 0, s, x, dlt.as<double>(), ld, N);
+        }
+        for (int c = 0; c < k; ++c)
+            if (status[c] == BEM_OK && relres[c] > o.tol) status[c] = BEM_E_NOT_CONVERGED;
+    }
+    // true FP64 residual of the result
+    {
+        DeviceBuffer y(sizeof(double) * ld * k), r(sizeof(double) * ld * k), part(sizeof(double) * G * k * 2);
+        matvec_device(p, false, x, ld, k, y.as<double>(), s);
+        hipLaunchKernelGGL(k_residual, vg, vb, 0, s, b, y.as<double>(), r.as<double>(), ld, N);
+        hipLaunchKernelGGL(k_dot_partial, vg, vb, 0, s, r.as<double>(), r.as<double>(), ld, N, part.as<double>());
+        hipLaunchKernelGGL(k_dot_partial, vg, vb, 0, s, b, b, ld, N, part.as<double>() + int64_t(G) * k);
+        std::vector<double> hp(size_t(2) * G * k);
+        HIP_CHECK(hipMemcpyAsync(hp.data(), part.ptr, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        for (int c = 0; c < k; ++c) {
+            double a = 0, bsum = 0;
+            for (unsigned g = 0; g < G; ++g) { a += hp[size_t(c) * G + g]; bsum += hp[size_t(G) * k + size_t(c) * G + g]; }
+            relres[c] = bsum > 0 ? std::sqrt(a / bsum) : 0.0;
+        }
+    }
+    const double tt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info)
+        for (int c = 0; c < k; ++c) {
+            info[c].iters = iters[c];
+            info[c].outer_iters = outer[c];
+            info[c].status = status[c];
+            info[c].relres = relres[c];
+            info[c].est_cond = cond[c];
+            info[c].t_total_s = tt;
+        }
+}
+
+}  // namespace bem

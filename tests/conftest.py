@@ -18,3 +18,12 @@ def _oracle_built():
     from oracle import native
     native.lib()
     yield
+
+
+@pytest.fixture(scope="session")
+def ctx():
+    """One library context on device 0 for all GPU tests."""
+    from paper_2310_09204_amd import lib
+    c = lib.Context(0)
+    yield c
+    c.close()

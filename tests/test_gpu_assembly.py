@@ -1,0 +1,122 @@
+"""GPU assembly parity against the oracle (pair integrals, W, L, jump values), through the C-ABI."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2310_09204_amd import lib, meshes
+from oracle.assemble import W_rows, assemble, pair_matrix, rhs
+from oracle.topology import Topology
+
+pytestmark = pytest.mark.gpu
+NEAR = 10
+
+
+def small_meshes():
+    rng = np.random.default_rng(5)
+    ext, _ = meshes.random_extruded(rng, 3, "tree", 4)
+    return {
+        "square8": meshes.unit_square(8),
+        "book6": meshes.book(6),
+        "crossed6": meshes.crossed(6),
+        "bowtie5": meshes.bowtie(5),
+        "disk4": meshes.disk(4),
+        "extruded": ext,
+    }
+
+
+@pytest.mark.parametrize("name", list(small_meshes()))
+def test_pair_integrals_all_pairs(ctx, name):
+    m = small_meshes()[name]
+    print("case", name, m.nt, flush=True)
+    p = lib.Problem(ctx, m.vertices, m.triangles, near_order=NEAR, keep_pair_matrix=True)
+    nt = m.nt
+    pairs = np.array([[i, j] for i in range(nt) for j in range(nt)], dtype=np.int32)
+    Ig = p.pair_integrals(pairs).reshape(nt, nt)
+    Io = pair_matrix(m.vertices, m.triangles, NEAR)
+    assert np.array_equal(Ig, Ig.T)
+    rel = np.abs(Ig - Io) / np.abs(Io)
+    assert rel.max() < 1e-12, (name, rel.max())
+
+
+@pytest.mark.parametrize("name", list(small_meshes()))
+def test_matrix_rhs_jumps(ctx, name):
+    m = small_meshes()[name]
+    print("case", name, m.nt, flush=True)
+    t = Topology(m.vertices, m.triangles)
+    p = lib.Problem(ctx, m.vertices, m.triangles, near_order=NEAR)
+    assert p.N == t.N
+    dv, ds = p.dofs()
+    assert [(int(a), int(b)) for a, b in zip(dv, ds)] == t.dofs
+    Wg = p.matrix()
+    Wo = assemble(m.vertices, m.triangles, t, NEAR)
+    assert np.array_equal(Wg, Wg.T)                       # mirrored writes: exactly symmetric
+    err = np.abs(Wg - Wo).max() / np.abs(Wo).max()
+    assert err < 1e-12, (name, err)
+    g = np.array([[0.3, -0.5, 0.8], [0.0, 0.0, 1.0]])
+    Lg = p.rhs(g)
+    Lo = rhs(t, g).T
+    assert np.abs(Lg - Lo).max() <= 1e-14 * np.abs(Lo).max()
+    phi = np.random.default_rng(1).standard_normal(t.N)
+    assert np.allclose(p.jump_values(phi), t.jump_values(phi), rtol=0, atol=1e-13 * np.abs(phi).max())
+    # matvec against the FP64 product
+    x = np.random.default_rng(2).standard_normal((3, t.N))
+    y = p.matvec(x)
+    assert np.abs(y - x @ Wo).max() <= 1e-12 * np.abs(x @ Wo).max()
+
+
+def test_book48_sampled_rows(ctx):
+    w = meshes.workload("book48")
+    m = w.mesh
+    p = lib.Problem(ctx, m.vertices, m.triangles, near_order=NEAR)
+    assert p.N == 6721
+    rng = np.random.default_rng(0)
+    rows = np.sort(rng.choice(p.N, 48, replace=False))
+    # include spine dofs (q = 3) explicitly
+    dv, ds = p.dofs()
+    spine = np.nonzero(np.linalg.norm(m.vertices[dv][:, :2], axis=1) < 1e-12)[0]
+    rows = np.unique(np.concatenate([rows, spine[:8]]))
+    Wg = p.rows(rows)
+    Wo = W_rows(m.vertices, m.triangles, rows, near_order=NEAR)
+    scale = np.abs(Wo).max()
+    assert np.abs(Wg - Wo).max() < 1e-12 * scale
+    # symmetry of the full GPU matrix on the sampled rows
+    Wfull = p.matrix()
+    assert np.array_equal(Wfull[rows], Wg)
+    assert np.array_equal(Wfull, Wfull.T)
+
+
+def test_crossed96_sampled_rows_and_pairs(ctx):
+    m = meshes.crossed(96)
+    p = lib.Problem(ctx, m.vertices, m.triangles, near_order=NEAR, keep_pair_matrix=True)
+    assert p.N == 27361
+    rng = np.random.default_rng(1)
+    rows = np.sort(rng.choice(p.N, 24, replace=False))
+    dv, ds = p.dofs()
+    origin = np.nonzero(np.linalg.norm(m.vertices[dv], axis=1) < 1e-12)[0]
+    rows = np.unique(np.concatenate([rows, origin]))
+    Wg = p.rows(rows)
+    Wo = W_rows(m.vertices, m.triangles, rows, near_order=NEAR)
+    assert np.abs(Wg - Wo).max() < 1e-12 * np.abs(Wo).max()
+    from oracle.assemble import pair_integrals
+    pairs = rng.integers(0, m.nt, size=(4000, 2)).astype(np.int32)
+    Ig = p.pair_integrals(pairs)
+    Io = pair_integrals(m.vertices, m.triangles, pairs, NEAR)
+    assert (np.abs(Ig - Io) / np.abs(Io)).max() < 1e-12
+
+
+def test_fp32_copy_matches_rounding(ctx):
+    m = meshes.unit_square(8)
+    p = lib.Problem(ctx, m.vertices, m.triangles, precision=lib.FP32_REFINE, near_order=NEAR)
+    W = p.matrix()
+    x = np.random.default_rng(3).standard_normal((2, p.N))
+    y32 = p.matvec(x, fp32=True)
+    ref = x.astype(np.float32).astype(np.float64) @ W.astype(np.float32).astype(np.float64)
+    assert np.abs(y32 - ref).max() < 1e-5 * np.abs(ref).max()
+
+
+def test_invalid_meshes_rejected_before_device_work(ctx):
+    V = np.array([[0., 0, 0], [1, 0, 0], [0, 1, 0], [-1, 0, 0.3], [0, -1, 0.2]])
+    with pytest.raises(lib.BemError) as e:
+        lib.Problem(ctx, V, np.array([[0, 1, 2], [0, 3, 4]]))
+    assert e.value.name == "BEM_E_POINT_CONTACT"

@@ -1,0 +1,138 @@
+"""GPU preconditioner and (P)CG parity against the oracle, through the C-ABI."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2310_09204_amd import lib, meshes
+from oracle.assemble import assemble, rhs
+from oracle.precond import AdditiveSchwarz
+from oracle.solve import cholesky_solve, pcg
+from oracle.topology import Topology
+
+pytestmark = pytest.mark.gpu
+NEAR = 10
+
+
+def _setup(ctx, w, precision=lib.FP64):
+    m = w.mesh
+    p = lib.Problem(ctx, m.vertices, m.triangles, precision=precision, near_order=NEAR)
+    M = lib.Preconditioner(p, w.patch_of_triangle, w.coarse.vertices, w.coarse.triangles, w.coarse_of_triangle,
+                           factor_fp32=(precision == lib.FP32_REFINE))
+    return p, M
+
+
+def _oracle(w):
+    m = w.mesh
+    t = Topology(m.vertices, m.triangles)
+    W = assemble(m.vertices, m.triangles, t, NEAR)
+    P = AdditiveSchwarz(W, t, w.patch_of_triangle, w.coarse.vertices, w.coarse.triangles, w.coarse_of_triangle)
+    return t, W, P
+
+
+def small_workloads():
+    out = {"square16": meshes.workload("square16")}
+    m = meshes.crossed(16)
+    patches = meshes.grid_patches(m, 4, split_at=[8])
+    cm, par = meshes.coarse_mesh(m, 4)
+    out["crossed16"] = meshes.Workload("crossed16", m, patches, cm, par, np.array([[0.2, 0.5, -0.7]]), "")
+    m = meshes.book(12)
+    cm, par = meshes.coarse_mesh(m, 4)
+    out["book12"] = meshes.Workload("book12", m, meshes.grid_patches(m, 4), cm, par, np.array([[0.6, -0.3, 0.4]]), "")
+    return out
+
+
+@pytest.mark.parametrize("name", list(small_workloads()))
+def test_precond_apply_matches_oracle(ctx, name):
+    w = small_workloads()[name]
+    print("case", name, flush=True)
+    p, M = _setup(ctx, w)
+    t, W, P = _oracle(w)
+    s = M.sizes()
+    assert s["n_faces"] == len(P.face_sets) and s["n_wb"] == len(P.wb) and s["n_coarse"] == P.RH.shape[0]
+    r = np.random.default_rng(4).standard_normal((3, t.N))
+    zg = M.apply(r)
+    zo = np.stack([P.apply(ri) for ri in r])
+    assert np.abs(zg - zo).max() < 1e-11 * np.abs(zo).max()
+
+
+@pytest.mark.parametrize("name", list(small_workloads()))
+def test_pcg_matches_oracle(ctx, name):
+    w = small_workloads()[name]
+    print("case", name, flush=True)
+    p, M = _setup(ctx, w)
+    t, W, P = _oracle(w)
+    g = w.g
+    L = rhs(t, g)[:, 0]
+    xs = cholesky_solve(W, L)
+    # iteration counts: same algorithm, same tolerance
+    _, it_o, _, _, _ = pcg(W, L, P.apply, tol=1e-10)
+    phi, info, rc = p.solve(g=g, precond=M, tol=1e-10)
+    assert rc == 0 and abs(info[0]["iters"] - it_o) <= 1, (info[0]["iters"], it_o)
+    assert info[0]["relres"] <= 1e-10
+    # unpreconditioned CG
+    _, it_c, _, _, _ = pcg(W, L, None, tol=1e-10)
+    _, info_c, rc = p.solve(g=g, precond=None, tol=1e-10)
+    assert rc == 0 and abs(info_c[0]["iters"] - it_c) <= 1
+    # solution parity against the exact discrete solution
+    phi, info, rc = p.solve(g=g, precond=M, tol=1e-13)
+    assert np.linalg.norm(phi[0] - xs) / np.linalg.norm(xs) < 1e-10
+
+
+def test_multi_rhs_equals_single_and_graph_equals_eager(ctx):
+    w = small_workloads()["crossed16"]
+    p, M = _setup(ctx, w)
+    G = np.random.default_rng(8).standard_normal((5, 3))
+    phi_all, info_all, rc = p.solve(g=G, precond=M, tol=1e-11)
+    assert rc == 0
+    for i in range(5):
+        phi_i, info_i, _ = p.solve(g=G[i], precond=M, tol=1e-11)
+        assert info_i[0]["iters"] == info_all[i]["iters"]
+        assert np.abs(phi_i[0] - phi_all[i]).max() <= 1e-13 * np.abs(phi_all[i]).max()
+    phi_e, info_e, _ = p.solve(g=G, precond=M, tol=1e-11, use_graph=False)
+    assert np.array_equal(phi_e, phi_all)
+
+
+@pytest.mark.parametrize("name", ["square16", "crossed16"])
+def test_mixed_precision_reaches_1e8(ctx, name):
+    w = small_workloads()[name]
+    p, M = _setup(ctx, w, precision=lib.FP32_REFINE)
+    t, W, P = _oracle(w)
+    L = rhs(t, w.g)[:, 0]
+    xs = cholesky_solve(W, L)
+    phi, info, rc = p.solve(g=w.g, precond=M, tol=1e-11, precision=lib.FP32_REFINE, inner_tol=1e-5)
+    assert rc == 0
+    assert info[0]["outer_iters"] >= 2
+    err = np.linalg.norm(phi[0] - xs) / np.linalg.norm(xs)
+    e = phi[0] - xs
+    eerr = math.sqrt(e @ W @ e) / math.sqrt(xs @ W @ xs)
+    assert err < 1e-8 and eerr < 1e-8, (err, eerr)
+
+
+def test_failure_paths(ctx):
+    w = small_workloads()["square16"]
+    p, M = _setup(ctx, w)
+    # NaN in the Neumann data: breakdown, outputs still written
+    phi, info, rc = p.solve(g=np.array([[np.nan, 0.0, 1.0]]), precond=M, raise_on_error=False)
+    assert lib.ERRORS[rc] == "BEM_E_BREAKDOWN"
+    # iteration cap: not converged, the iterate is still returned
+    phi, info, rc = p.solve(g=w.g, precond=M, max_iter=1, raise_on_error=False)
+    assert lib.ERRORS[rc] == "BEM_E_NOT_CONVERGED" and info[0]["iters"] == 1 and np.isfinite(phi).all()
+    # zero right-hand side: zero solution, no iterations
+    phi, info, rc = p.solve(rhs=np.zeros((1, p.N)), precond=M)
+    assert rc == 0 and info[0]["iters"] == 0 and not phi.any()
+
+
+def test_book48_full_size(ctx):
+    w = meshes.workload("book48", seed=0)
+    p, M = _setup(ctx, w)
+    s = M.sizes()
+    assert s["n_faces"] == 48 and s["n_wb"] == 913 and s["n_coarse"] == 33
+    t, W, P = _oracle(w)
+    L = rhs(t, w.g)[:, 0]
+    _, it_o, _, _, _ = pcg(W, L, P.apply, tol=1e-10)
+    phi, info, rc = p.solve(g=w.g, precond=M, tol=1e-10)
+    assert rc == 0 and abs(info[0]["iters"] - it_o) <= 1
+    xs = cholesky_solve(W, L)
+    phi, info, rc = p.solve(g=w.g, precond=M, tol=1e-13)
+    assert np.linalg.norm(phi[0] - xs) / np.linalg.norm(xs) < 1e-10

@@ -1,0 +1,284 @@
+#!/usr/bin/env python3
+"""Benchmark of the whole hot path on one MI355X.
+
+One step = one pass of the path over one batch of synthetic input: host mesh analysis and near
+list, device assembly of W (far 7x7 tiles, Duffy near kernels, contraction, FP32 copy), right-hand
+sides, preconditioner set-up (batched block inverses, coarse Galerkin matrix), and the
+mixed-precision PCG solve of k right-hand sides to relative residual tol.  Every solved column is
+checked against an FP64 reference solution (FP64 GPU PCG at relative residual 1e-13, computed
+before the timed region); only columns with relative error <= 1e-8 count.
+
+Prints one JSON line (see the "metric"/"value" keys); per-phase timings, matvec bandwidths, the
+roofline of the dominant kernel and the oracle timed on the host cores ride along.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
+# algorithmic flops of one far-field kernel evaluation w / |x - y|: 3 subtractions, 3 products and
+# 2 sums for |x-y|^2, 1 reciprocal square root, 1 product and 1 sum for the weighted accumulation
+FLOPS_PER_EVAL = 11
+EVALS_PER_FAR_PAIR = 49
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def far_kernel_source_hash():
+    src = open(os.path.join(ROOT, "paper_2310_09204_amd", "csrc", "assemble.hip"), "rb").read()
+    return hashlib.sha256(src).hexdigest()[:16]
+
+
+def load_traffic(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if the kernel source is
+    unchanged since the counters were taken; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+        e = d.get(kernel, {}).get(workload)
+        if not e or e.get("source_hash") != far_kernel_source_hash():
+            return None
+        return float(e["bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def cpu_baseline(w, k, iters, gpu_info, budget_s):
+    """The oracle on the host cores, on a bounded sample of this workload, scaled to solves/s.
+
+    Sample: R random rows of the pair-integral matrix (all columns; far and near pairs exactly as
+    the oracle assembles them) timed with oracle_I_rows; the dense products of the PCG timed on a
+    slab of rows of a matrix of the workload's size; scaled to N_T rows and to the solve's
+    iteration count.  The oracle's contraction and preconditioner set-up are not included (so
+    the baseline is optimistic for the oracle)."""
+    from oracle import native
+    from oracle.assemble import _tables
+    import ctypes
+
+    V = np.ascontiguousarray(w.mesh.vertices, dtype=np.float64)
+    T = np.ascontiguousarray(w.mesh.triangles, dtype=np.int32)
+    nt = T.shape[0]
+    N = int(gpu_info["n_dofs"])
+    b7, w7, gx, gw = _tables(10)
+    L = native.lib()
+    rng = np.random.default_rng(0)
+    # calibrate: one row first
+    rows_done, t_rows = 0, 0.0
+    R = 1
+    buf = np.empty((64, nt))
+    while t_rows < 0.6 * budget_s and rows_done < nt:
+        R = min(R, 64)
+        r0 = int(rng.integers(0, nt - R))
+        t0 = time.perf_counter()
+        L.oracle_I_rows(native.dptr(V), native.iptr(T), nt, native.dptr(b7), native.dptr(w7), 10,
+                        native.dptr(gx), native.dptr(gw), r0, R, native.dptr(buf))
+        t_rows += time.perf_counter() - t0
+        rows_done += R
+        R *= 2
+    t_asm = t_rows / rows_done * nt
+    # dense matvec slab: W[rows, :] @ X, k columns
+    slab = 1024
+    Wslab = rng.standard_normal((slab, N))
+    X = rng.standard_normal((N, k))
+    reps, t_mv = 0, 0.0
+    while t_mv < 0.2 * budget_s and reps < 50:
+        t0 = time.perf_counter()
+        Wslab @ X
+        t_mv += time.perf_counter() - t0
+        reps += 1
+    t_matvec = t_mv / reps * (N / slab)
+    t_solve = iters * t_matvec
+    t_step = t_asm + t_solve
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": k / t_step,
+        "unit": "solves/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": "%d of %d rows of the pair-integral matrix (oracle_I_rows, all columns) and a %d-row slab "
+                  "of the dense %d-column product, scaled to one step of %d right-hand sides with %d PCG "
+                  "iterations; contraction and preconditioner set-up not counted" % (rows_done, nt, slab, k, k, iters),
+        "t_assembly_s": t_asm,
+        "t_solve_s": t_solve,
+        "pair_integrals_per_s": nt * (nt + 1) / 2 / t_asm,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="crossed96")
+    ap.add_argument("--k", type=int, default=16)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported (the multi-GPU "
+              "design is described, not built)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2310_09204_amd import lib, meshes
+
+    w = meshes.workload(args.workload, seed=0, k=args.k)
+    m = w.mesh
+    mixed = args.precision == "mixed"
+    prec = lib.FP32_REFINE if mixed else lib.FP64
+    log("bench: workload %s nt=%d k=%d precision=%s" % (args.workload, m.nt, args.k, args.precision))
+    ctx = lib.Context(0)
+
+    def step(precision, want_phi=False, tol=args.tol):
+        t0 = time.perf_counter()
+        p = lib.Problem(ctx, m.vertices, m.triangles, precision=precision, near_order=10)
+        t1 = time.perf_counter()
+        M = lib.Preconditioner(p, w.patch_of_triangle, w.coarse.vertices, w.coarse.triangles, w.coarse_of_triangle,
+                               factor_fp32=(precision == lib.FP32_REFINE))
+        t2 = time.perf_counter()
+        phi, info, rc = p.solve(g=w.g, precond=M, tol=tol, precision=precision, inner_tol=1e-6)
+        ctx.synchronize()
+        t3 = time.perf_counter()
+        pinfo = p.info
+        out = {"t_step": t3 - t0, "t_assemble": t1 - t0, "t_precond": t2 - t1, "t_solve": t3 - t2,
+               "t_far": pinfo["t_far_s"], "t_near": pinfo["t_near_s"], "t_contract": pinfo["t_contract_s"],
+               "iters": [i["iters"] for i in info], "outer": [i["outer_iters"] for i in info], "rc": rc,
+               "info": pinfo, "precond_sizes": M.sizes()}
+        if want_phi:
+            out["phi"] = phi
+            out["problem"], out["M"] = p, M
+        else:
+            M.close()
+            p.close()
+        return out
+
+    # reference solution (not timed)
+    log("bench: FP64 reference solve (tol 1e-13)")
+    ref = step(lib.FP64, want_phi=True, tol=1e-13)
+    phi_ref = ref["phi"]
+    pinfo = ref["info"]
+    N = pinfo["n_dofs"]
+    pref = ref["problem"]
+    t64_1 = pref.bench_matvec(fp32=False, k=1, reps=10)
+    t64_16 = pref.bench_matvec(fp32=False, k=16, reps=5)
+    ref["M"].close()
+    pref.close()
+
+    for i in range(args.warmup):
+        log("bench: warmup %d" % i)
+        step(prec)
+    ctx.synchronize()
+    res = []
+    t_begin = time.perf_counter()
+    for i in range(args.steps):
+        r = step(prec, want_phi=True)
+        phi = r.pop("phi")
+        err = np.linalg.norm(phi - phi_ref, axis=1) / np.linalg.norm(phi_ref, axis=1)
+        r["relerr"] = err.tolist()
+        r["solved"] = int((err <= 1e-8).sum())
+        if i == args.steps - 1:
+            pl = r["problem"]
+            t32_1 = pl.bench_matvec(fp32=True, k=1, reps=10) if mixed else None
+            t32_16 = pl.bench_matvec(fp32=True, k=16, reps=5) if mixed else None
+        r.pop("M").close()
+        r.pop("problem").close()
+        res.append(r)
+        log("bench: step %d %.3fs asm %.3f (far %.3f near %.4f contract %.3f) precond %.3f solve %.3f iters %s relerr max %.2e"
+            % (i, r["t_step"], r["t_assemble"], r["t_far"], r["t_near"], r["t_contract"], r["t_precond"], r["t_solve"],
+               r["iters"][:4], max(r["relerr"])))
+    ctx.synchronize()
+    elapsed = time.perf_counter() - t_begin
+    solved = sum(r["solved"] for r in res)
+    value = solved / elapsed
+    ms_per_step = elapsed / args.steps * 1e3
+
+    fp64_step = None
+    if not args.no_fp64_compare and mixed:
+        r64 = step(lib.FP64, want_phi=True)
+        err64 = np.linalg.norm(r64["phi"] - phi_ref, axis=1) / np.linalg.norm(phi_ref, axis=1)
+        r64["M"].close()
+        r64["problem"].close()
+        fp64_step = {"t_step_s": r64["t_step"], "t_solve_s": r64["t_solve"], "iters": r64["iters"],
+                     "solves_per_s": int((err64 <= 1e-8).sum()) / r64["t_step"],
+                     "solve_only_solves_per_s": int((err64 <= 1e-8).sum()) / r64["t_solve"]}
+
+    nt = pinfo["n_tri"]
+    pairs = nt * (nt + 1) // 2
+    t_asm = float(np.mean([r["t_assemble"] for r in res]))
+    t_far = float(np.mean([r["t_far"] for r in res]))
+    far_pairs = pairs - pinfo["n_near_pairs"]
+    far_tflops = far_pairs * EVALS_PER_FAR_PAIR * FLOPS_PER_EVAL / t_far / 1e12
+    mv = {"fp64_k1_GBs": N * N * 8 / t64_1 / 1e9, "fp64_k16_GBs": N * N * 8 / t64_16 / 1e9}
+    if mixed:
+        mv["fp32_k1_GBs"] = N * N * 4 / t32_1 / 1e9
+        mv["fp32_k16_GBs"] = N * N * 4 / t32_16 / 1e9
+    lat = sorted(r["t_step"] for r in res)
+    roofline = {
+        "kernel": "k_far",
+        "bound": "alu",
+        "achieved": round(far_tflops, 3),
+        "peak": PEAK_FP64_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": round(far_tflops / PEAK_FP64_TFLOPS, 4),
+        "traffic": load_traffic("k_far", args.workload),
+        "per_launch": "%d far pairs x %d evaluations x %d flops" % (far_pairs, EVALS_PER_FAR_PAIR, FLOPS_PER_EVAL),
+        "avg_launch_s": t_far,
+    }
+    out = {
+        "metric": "PCG solves/s + p50/p99 latency at rel.err 1e-8; pair-integrals/s; matvec GB/s",
+        "value": round(value, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if mixed else "f64",
+        "data": "synthetic",
+        "config": {"workload": "%s: %s; %d right-hand sides per step (block PCG), %s PCG to relative "
+                               "residual %.0e, rel.err <= 1e-8 vs FP64 reference" %
+                               (args.workload, w.description, args.k, "FP32-matrix + FP64-refinement" if mixed else "FP64",
+                                args.tol),
+                   "n_dofs": N, "n_tri": nt, "k": args.k, "precision": args.precision,
+                   "patches": ref["precond_sizes"]},
+        "roofline": roofline,
+        "pair_integrals_per_s": pairs / t_asm,
+        "pair_integrals_per_s_far_kernel": far_pairs / t_far,
+        "latency_s": {"p50": lat[len(lat) // 2], "p99": lat[min(len(lat) - 1, int(round(0.99 * (len(lat) - 1))))]},
+        "phases_s": {k_: float(np.mean([r[k_] for r in res])) for k_ in
+                     ("t_step", "t_assemble", "t_far", "t_near", "t_contract", "t_precond", "t_solve")},
+        "iters": res[-1]["iters"],
+        "outer_iters": res[-1]["outer"],
+        "relerr_max": max(max(r["relerr"]) for r in res),
+        "matvec": mv,
+        "fp64_compare": fp64_step,
+    }
+    if not args.no_cpu_baseline:
+        log("bench: oracle on host cores (bounded sample)")
+        out["cpu_baseline"] = cpu_baseline(w, args.k, int(np.mean(res[-1]["iters"])), pinfo, args.cpu_seconds)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

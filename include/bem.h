@@ -102,6 +102,8 @@ typedef struct {
  * device memory the serving loop may hold (0 = 90% of free memory). */
 int bem_ctx_create(int hip_device, size_t hbm_budget_bytes, bem_ctx** out);
 void bem_ctx_destroy(bem_ctx* ctx);
+/* Waits for all device work of the context's device (hipDeviceSynchronize). */
+int bem_ctx_synchronize(bem_ctx* ctx);
 
 /* ---- host-side mesh analysis (no device work) --------------------------------------------- */
 /* Sectors and dofs of Section 4.2 for a mesh: returns the number of dofs in *n_dofs and, if the
@@ -137,6 +139,10 @@ int bem_problem_pair_integrals(const bem_problem* p, const int32_t* pairs, int64
 int bem_rhs(const bem_problem* p, const double* g, int32_t k, double* out);
 /* y = W x for k column vectors x[k][N] -> y[k][N] (FP64 matrix, or FP32 matrix if fp32 = 1) */
 int bem_matvec(const bem_problem* p, const double* x, int32_t k, int fp32, double* y);
+/* Measurement: `reps` back-to-back products y = W x with k device-resident columns (FP64 matrix,
+ * or the FP32 copy if fp32 = 1), timed with HIP events on the problem's stream; writes the mean
+ * seconds per product.  W is streamed once per product (N^2 x 8 or 4 bytes). */
+int bem_problem_bench_matvec(const bem_problem* p, int fp32, int32_t k, int reps, double* seconds);
 /* label-free view of phi[N]: jump[t][a] = sum_d c_{T,a,d} phi_d, the jump of the represented
  * function across triangle t at corner a */
 int bem_jump_values(const bem_problem* p, const double* phi, double* jump_out);

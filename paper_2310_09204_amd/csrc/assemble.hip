@@ -448,6 +448,8 @@ void assemble_device(bem_problem* p, const NearList& near) {
         HIP_CHECK(hipGetLastError());
     }
     if (!p->has_pairs) p->I.reset();
+    p->mv_xt = DeviceBuffer(sizeof(double) * 16 * p->ldw);
+    p->mv_partial = DeviceBuffer(sizeof(double) * 16 * 16 * p->ldw);
     HIP_CHECK(hipStreamSynchronize(s));
 }
 

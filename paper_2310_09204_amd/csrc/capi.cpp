@@ -139,6 +139,42 @@ void bem_ctx_destroy(bem_ctx* ctx) {
     delete ctx;
 }
 
+int bem_ctx_synchronize(bem_ctx* ctx) {
+    BEM_TRY
+    if (!ctx) fail(BEM_E_INVALID_ARG, "NULL ctx");
+    set_device(ctx);
+    HIP_CHECK(hipDeviceSynchronize());
+    return BEM_OK;
+    BEM_CATCH
+}
+
+int bem_problem_bench_matvec(const bem_problem* p, int fp32, int32_t k, int reps, double* seconds) {
+    BEM_TRY
+    if (!p || !seconds || k <= 0 || reps <= 0) fail(BEM_E_INVALID_ARG, "bad argument");
+    set_device(p->ctx);
+    const int64_t N = p->N;
+    if (N == 0) { *seconds = 0; return BEM_OK; }
+    DeviceBuffer x(sizeof(double) * N * k), y(sizeof(double) * N * k);
+    std::vector<double> hx(size_t(N) * k);
+    for (size_t i = 0; i < hx.size(); ++i) hx[i] = 1.0 / double(1 + (i % 97));
+    HIP_CHECK(hipMemcpyAsync(x.ptr, hx.data(), sizeof(double) * hx.size(), hipMemcpyHostToDevice, p->stream));
+    matvec_device(p, fp32 != 0, x.as<double>(), N, k, y.as<double>(), p->stream);   // warm-up
+    hipEvent_t a, b;
+    HIP_CHECK(hipEventCreate(&a));
+    HIP_CHECK(hipEventCreate(&b));
+    HIP_CHECK(hipEventRecord(a, p->stream));
+    for (int r = 0; r < reps; ++r) matvec_device(p, fp32 != 0, x.as<double>(), N, k, y.as<double>(), p->stream);
+    HIP_CHECK(hipEventRecord(b, p->stream));
+    HIP_CHECK(hipEventSynchronize(b));
+    float ms = 0;
+    HIP_CHECK(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *seconds = double(ms) * 1e-3 / reps;
+    return BEM_OK;
+    BEM_CATCH
+}
+
 int bem_mesh_analyze(const double* vertices, int64_t nv, const int32_t* triangles, int64_t nt, int64_t* n_dofs,
                      int32_t* dof_vertex, int32_t* dof_sector, int32_t* q) {
     BEM_TRY

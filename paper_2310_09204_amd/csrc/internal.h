@@ -112,6 +112,9 @@ struct bem_problem {
     bem::DeviceBuffer normal, area;         // per-triangle geometry for the right-hand side
     bem::DeviceBuffer dof_ptr, dof_tri, dof_c;  // dof -> triangle CSR
     bem::DeviceBuffer tri_ptr, tri_dof, tri_corner, tri_c;  // triangle -> dof CSR
+    // scratch of the multi-column product: transposed right-hand sides (ldw x 16, FP64-sized) and
+    // per-split partial sums (16 splits x 16 columns x ldw).  Calls on one problem must not overlap.
+    bem::DeviceBuffer mv_xt, mv_partial;
     double t_assemble = 0, t_far = 0, t_near = 0, t_contract = 0;
     int64_t bytes = 0;
 };
@@ -142,7 +145,8 @@ struct bem_precond {
     bem::DeviceBuffer blk_meta;     // per block: n, npad, idx_off, mat_off (int64 x 4)
     bem::DeviceBuffer inv64, inv32; // explicit block inverses, npad x npad row-major each
     bem::DeviceBuffer tasks;        // apply tasks: (block, row0, nrows, 0) as int4
-    int64_t ntasks = 0;
+    int64_t ntasks = 0, max_npad = 0, xg_rows = 0;
+    bem::DeviceBuffer xg;           // apply scratch: gathered, transposed block right-hand sides
     // coarse space: R_H as CSR over coarse dofs and over fine dofs, and (R_H W R_H^T)^{-1}
     bem::DeviceBuffer rh_ptr, rh_col, rh_val, rht_ptr, rht_row, rht_val, WHinv;
     int64_t bytes = 0;

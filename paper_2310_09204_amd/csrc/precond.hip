@@ -22,6 +22,7 @@
 #include <numeric>
 
 #include "internal.h"
+#include "strips.h"
 
 namespace bem {
 
@@ -30,7 +31,7 @@ namespace {
 constexpr int TBK = 64;     // tile edge
 constexpr int LDT = 65;     // LDS leading dimension (padding against bank conflicts)
 
-struct BlockMeta { int64_t n, npad, idx_off, mat_off; };
+struct BlockMeta { int64_t n, npad, idx_off, mat_off, xoff; };
 
 __device__ __forceinline__ void tile_load(double* __restrict__ s, const double* __restrict__ g, int64_t ld) {
     for (int e = threadIdx.x; e < TBK * TBK; e += blockDim.x) {
@@ -275,16 +276,18 @@ __global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, in
 }
 
 // --- coarse Galerkin matrix: Y = W R_H^T, then W_H = R_H Y (upper half, mirrored) ------------
-__global__ void k_coarse_Y(const double* __restrict__ W, int64_t ldw, int64_t N, const int64_t* __restrict__ rp,
-                           const int32_t* __restrict__ rc, const double* __restrict__ rv, int64_t nH,
-                           double* __restrict__ Y) {
-    const int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;   // fine row
-    const int64_t i = blockIdx.y;                                         // coarse dof
-    if (j >= N) return;
+// Y[j][i] = sum_e R[i][e] W[j][col_e]: one block per fine row j (the row stays in cache), threads
+// over coarse dofs
+__global__ __launch_bounds__(256) void k_coarse_Y(const double* __restrict__ W, int64_t ldw, int64_t N,
+                                                  const int64_t* __restrict__ rp, const int32_t* __restrict__ rc,
+                                                  const double* __restrict__ rv, int64_t nH, double* __restrict__ Y) {
+    const int64_t j = blockIdx.x;
     const double* w = W + j * ldw;
-    double s = 0.0;
-    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) s = fma(rv[e], w[rc[e]], s);
-    Y[j * nH + i] = s;
+    for (int64_t i = threadIdx.x; i < nH; i += blockDim.x) {
+        double s = 0.0;
+        for (int64_t e = rp[i]; e < rp[i + 1]; ++e) s = fma(rv[e], w[rc[e]], s);
+        Y[j * nH + i] = s;
+    }
 }
 
 __global__ void k_coarse_WH(const double* __restrict__ Y, int64_t nH, const int64_t* __restrict__ rp,
@@ -311,76 +314,95 @@ __global__ void k_coarse_pad_rows(double* __restrict__ A, int64_t nH, int64_t np
     if (c < npad && r < npad) A[r * npad + c] = (r == c) ? 1.0 : 0.0;
 }
 
-// --- apply: z[idx] = B r[idx] for a 64-row panel of one block, k columns ---------------------
-template <typename MT, int K>
+// --- apply, step 1: the blocks' right-hand sides, gathered and transposed: Xg[xoff + s][n] ---------
+template <typename MT>
+__global__ void k_block_gather(const BlockMeta* __restrict__ meta, const int32_t* __restrict__ idx,
+                               const double* __restrict__ r, int64_t ld, int kc, MT* __restrict__ xg) {
+    const BlockMeta m = meta[blockIdx.y];
+    const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (e >= m.npad * 16) return;
+    const int64_t s = e >> 4;
+    const int n = int(e & 15);
+    xg[m.xoff * 16 + e] = (s < m.n && n < kc) ? MT(r[int64_t(n) * ld + idx[m.idx_off + s]]) : MT(0);
+}
+
+// --- apply, step 2: z[idx] = B Xg for a 64-row panel of one block (four 16-row strips) -------------
+template <typename MT>
 __global__ __launch_bounds__(256) void k_block_apply(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
                                                      const int32_t* __restrict__ idx, const MT* __restrict__ inv,
-                                                     const double* __restrict__ r, int64_t ld, int kcols,
+                                                     const MT* __restrict__ xg, int kc, int64_t ld,
                                                      double* __restrict__ z) {
-    constexpr int CH = 256;
-    __shared__ MT xs[K][CH];
-    __shared__ MT zs[64][K];
+    using MC = MatrixCore<MT>;
     const int4 t = tasks[blockIdx.x];
     const BlockMeta m = meta[t.x];
-    const int32_t* id = idx + m.idx_off;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int row0 = t.y, nr = t.z;
-    for (int e = threadIdx.x; e < 64 * K; e += blockDim.x) zs[e / K][e % K] = MT(0);
-    for (int64_t s0 = 0; s0 < m.n; s0 += CH) {
-        const int chunk = int(min<int64_t>(CH, m.n - s0));
-        __syncthreads();
-        for (int e = threadIdx.x; e < CH * K; e += blockDim.x) {
-            const int c = e / CH, s = e % CH;
-            xs[c][s] = (s < chunk && c < kcols) ? MT(r[int64_t(c) * ld + id[s0 + s]]) : MT(0);
+    const int i = lane & 15, kg = lane >> 4;
+    const int64_t row0 = int64_t(t.y) + 16 * wave;
+    if (row0 >= m.n) return;
+    const int64_t row = row0 + i;                 // < npad: padded rows exist in storage
+    typename MC::V acc = {0, 0, 0, 0};
+    strip_mfma<MT, 4>(inv + m.mat_off + row * m.npad, true, 0, m.npad, xg + m.xoff * 16, acc);
+    if (i < kc) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t rr = row0 + MC::out_row(kg, r);
+            if (rr < m.n) z[int64_t(i) * ld + idx[m.idx_off + rr]] = double(acc[r]);
         }
-        __syncthreads();
-        for (int rr = wave; rr < nr; rr += 4) {
-            const MT* brow = inv + m.mat_off + int64_t(row0 + rr) * m.npad + s0;
-            MT acc[K];
+    }
+}
+
+// one block per coarse dof: threads stride over its fine entries, block sums per column
+__global__ __launch_bounds__(256) void k_restrict(const int64_t* __restrict__ rp, const int32_t* __restrict__ rc,
+                                                  const double* __restrict__ rv, int64_t nH,
+                                                  const double* __restrict__ r, int64_t ld, int k,
+                                                  double* __restrict__ out) {
+    __shared__ double red[4][16];
+    const int64_t i = blockIdx.x;
+    double acc[16];
 #pragma unroll
-            for (int c = 0; c < K; ++c) acc[c] = MT(0);
-            for (int s = lane; s < chunk; s += 64) {
-                const MT b = brow[s];
+    for (int c = 0; c < 16; ++c) acc[c] = 0.0;
+    for (int64_t e = rp[i] + threadIdx.x; e < rp[i + 1]; e += blockDim.x) {
+        const double v = rv[e];
+        const int64_t col = rc[e];
 #pragma unroll
-                for (int c = 0; c < K; ++c) acc[c] = fma(b, xs[c][s], acc[c]);
-            }
+        for (int c = 0; c < 16; ++c)
+            if (c < k) acc[c] = fma(v, r[int64_t(c) * ld + col], acc[c]);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-            for (int c = 0; c < K; ++c) {
-                MT v = acc[c];
-                for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-                acc[c] = v;
-            }
-            if (lane == 0)
-#pragma unroll
-                for (int c = 0; c < K; ++c) zs[rr][c] += acc[c];
-        }
+    for (int c = 0; c < 16; ++c) {
+        double v = acc[c];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) red[wave][c] = v;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < nr * K; e += blockDim.x) {
-        const int rr = e / K, c = e % K;
-        if (c < kcols) z[int64_t(c) * ld + id[row0 + rr]] = double(zs[rr][c]);
+    if (threadIdx.x < k) {
+        const int c = threadIdx.x;
+        out[int64_t(c) * nH + i] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
     }
 }
 
-__global__ void k_restrict(const int64_t* __restrict__ rp, const int32_t* __restrict__ rc, const double* __restrict__ rv,
-                           int64_t nH, const double* __restrict__ r, int64_t ld, int k, double* __restrict__ out) {
-    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+// y = Binv x for the coarse block: one wave per row, lanes over columns
+__global__ __launch_bounds__(256) void k_coarse_solve(const double* __restrict__ Binv, int64_t npad, int64_t nH,
+                                                      const double* __restrict__ x, int k, double* __restrict__ y) {
+    const int lane = threadIdx.x & 63;
+    const int64_t i = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
     if (i >= nH) return;
-    for (int c = 0; c < k; ++c) {
-        double s = 0.0;
-        for (int64_t e = rp[i]; e < rp[i + 1]; ++e) s = fma(rv[e], r[int64_t(c) * ld + rc[e]], s);
-        out[int64_t(c) * nH + i] = s;
+    double acc[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) acc[c] = 0.0;
+    const double* b = Binv + i * npad;
+    for (int64_t j = lane; j < nH; j += 64) {
+        const double bij = b[j];
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+            if (c < k) acc[c] = fma(bij, x[int64_t(c) * nH + j], acc[c]);
     }
-}
-
-__global__ void k_coarse_solve(const double* __restrict__ Binv, int64_t npad, int64_t nH, const double* __restrict__ x,
-                               int k, double* __restrict__ y) {
-    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-    if (i >= nH) return;
-    for (int c = 0; c < k; ++c) {
-        double s = 0.0;
-        for (int64_t j = 0; j < nH; ++j) s = fma(Binv[i * npad + j], x[int64_t(c) * nH + j], s);
-        y[int64_t(c) * nH + i] = s;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        double v = acc[c];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0 && c < k) y[int64_t(c) * nH + i] = v;
     }
 }
 
@@ -545,11 +567,12 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
     const int64_t nall = M->nblocks + (M->nH > 0 ? 1 : 0);
     std::vector<BlockMeta> meta(nall);
     std::vector<int32_t> idx;
-    int64_t moff = 0;
+    int64_t moff = 0, xoff = 0;
     for (int64_t b = 0; b < nall; ++b) {
         const int64_t n = (b < M->nblocks) ? int64_t(blocks[b].size()) : M->nH;
         const int64_t npad = ((n + TBK - 1) / TBK) * TBK;
-        meta[b] = {n, npad, int64_t(idx.size()), moff};
+        meta[b] = {n, npad, int64_t(idx.size()), moff, xoff};
+        xoff += npad;
         if (b < M->nblocks) idx.insert(idx.end(), blocks[b].begin(), blocks[b].end());
         moff += npad * npad;
         M->blk_n.push_back(n);
@@ -558,6 +581,8 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
         M->blk_mat_off.push_back(meta[b].mat_off);
     }
     M->idx_total = int64_t(idx.size());
+    M->xg_rows = xoff;
+    M->xg = DeviceBuffer(sizeof(double) * 16 * std::max<int64_t>(1, xoff));
     M->mat_total = moff;
     M->idx = upload(idx, s);
     M->blk_meta = upload(meta, s);
@@ -608,7 +633,7 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
         M->rht_row = upload(trow, s);
         M->rht_val = upload(tval, s);
         DeviceBuffer Y(sizeof(double) * std::max<int64_t>(1, f.N * M->nH));
-        hipLaunchKernelGGL(k_coarse_Y, dim3(nblk(f.N, 256), unsigned(M->nH)), dim3(256), 0, s, p->W64.as<double>(), p->ldw, f.N,
+        hipLaunchKernelGGL(k_coarse_Y, dim3(unsigned(f.N)), dim3(256), 0, s, p->W64.as<double>(), p->ldw, f.N,
                            M->rh_ptr.as<int64_t>(), M->rh_col.as<int32_t>(), M->rh_val.as<double>(), M->nH, Y.as<double>());
         HIP_CHECK(hipGetLastError());
         const BlockMeta& cm = meta[nall - 1];
@@ -695,6 +720,8 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
         for (int64_t r0 = 0; r0 < meta[b].n; r0 += 64)
             at.push_back(make_int4(int(b), int(r0), int(std::min<int64_t>(64, meta[b].n - r0)), 0));
     M->ntasks = int64_t(at.size());
+    M->max_npad = 0;
+    for (int64_t b = 0; b < M->nblocks; ++b) M->max_npad = std::max<int64_t>(M->max_npad, meta[b].npad);
     M->tasks = upload(at, s);
     HIP_CHECK(hipStreamSynchronize(s));
     M->bytes = int64_t(M->inv64.bytes + M->inv32.bytes + M->idx.bytes + M->rh_val.bytes * 3);
@@ -712,33 +739,29 @@ void precond_apply_device(const bem_precond* M, bool fp32, const double* r, int6
         const double* rc = r + int64_t(c0) * ld;
         double* zc = z + int64_t(c0) * ld;
         if (M->ntasks > 0) {
-            dim3 grid(unsigned(M->ntasks)), block(256);
-#define APPLY(MT, KK, PTR)                                                                                          \
-    hipLaunchKernelGGL((k_block_apply<MT, KK>), grid, block, 0, s, M->tasks.as<int4>(), dm, M->idx.as<int32_t>(), \
-                       PTR, rc, ld, kc, zc)
+            unsigned gx = unsigned((M->max_npad * 16 + 255) / 256);
             if (fp32 && M->inv32.ptr) {
-                const float* ptr = M->inv32.as<float>();
-                if (kc == 1) APPLY(float, 1, ptr);
-                else if (kc <= 4) APPLY(float, 4, ptr);
-                else APPLY(float, 16, ptr);
+                float* xg = M->xg.as<float>();
+                hipLaunchKernelGGL(k_block_gather<float>, dim3(gx, unsigned(M->nblocks)), dim3(256), 0, s, dm, M->idx.as<int32_t>(), rc, ld, kc, xg);
+                hipLaunchKernelGGL(k_block_apply<float>, dim3(unsigned(M->ntasks)), dim3(256), 0, s, M->tasks.as<int4>(), dm,
+                                   M->idx.as<int32_t>(), M->inv32.as<float>(), xg, kc, ld, zc);
             } else {
-                const double* ptr = M->inv64.as<double>();
-                if (kc == 1) APPLY(double, 1, ptr);
-                else if (kc <= 4) APPLY(double, 4, ptr);
-                else APPLY(double, 16, ptr);
+                double* xg = M->xg.as<double>();
+                hipLaunchKernelGGL(k_block_gather<double>, dim3(gx, unsigned(M->nblocks)), dim3(256), 0, s, dm, M->idx.as<int32_t>(), rc, ld, kc, xg);
+                hipLaunchKernelGGL(k_block_apply<double>, dim3(unsigned(M->ntasks)), dim3(256), 0, s, M->tasks.as<int4>(), dm,
+                                   M->idx.as<int32_t>(), M->inv64.as<double>(), xg, kc, ld, zc);
             }
-#undef APPLY
             HIP_CHECK(hipGetLastError());
         }
         if (M->nH > 0) {
             const int64_t nH = M->nH;
             double* rcoarse = scratch;
             double* zcoarse = scratch + nH * kc;
-            hipLaunchKernelGGL(k_restrict, dim3(nblk(nH, 128)), dim3(128), 0, s, M->rh_ptr.as<int64_t>(), M->rh_col.as<int32_t>(),
+            hipLaunchKernelGGL(k_restrict, dim3(unsigned(nH)), dim3(256), 0, s, M->rh_ptr.as<int64_t>(), M->rh_col.as<int32_t>(),
                                M->rh_val.as<double>(), nH, rc, ld, kc, rcoarse);
             const int64_t cb = M->nblocks;
             const double* Binv = M->inv64.as<double>() + M->blk_mat_off[cb];
-            hipLaunchKernelGGL(k_coarse_solve, dim3(nblk(nH, 64)), dim3(64), 0, s, Binv, M->blk_npad[cb], nH, rcoarse, kc, zcoarse);
+            hipLaunchKernelGGL(k_coarse_solve, dim3(nblk(nH, 4)), dim3(256), 0, s, Binv, M->blk_npad[cb], nH, rcoarse, kc, zcoarse);
             hipLaunchKernelGGL(k_prolong_add, dim3(nblk(p->N, 256)), dim3(256), 0, s, M->rht_ptr.as<int64_t>(), M->rht_row.as<int32_t>(),
                                M->rht_val.as<double>(), p->N, zcoarse, nH, kc, zc, ld);
             HIP_CHECK(hipGetLastError());

@@ -15,6 +15,7 @@
 #include <cmath>
 
 #include "internal.h"
+#include "strips.h"
 
 namespace bem {
 
@@ -80,6 +81,60 @@ __global__ __launch_bounds__(256) void k_matvec(const MT* __restrict__ W, int64_
         for (int c = 0; c < K; ++c)
             if (c < kc) y[int64_t(c) * ldy + row] = double(acc[c]);
     }
+}
+
+// ---------------------------------------------------------------------------------------------
+// multi-column product Y = W X on the matrix cores (the strip routine in strips.h is shared with
+// the preconditioner apply): each wave owns a 16-row strip of W and a column range; X is
+// transposed once per product into Xt[j][16] so every B fragment is one coalesced read per 16 lanes.
+// ---------------------------------------------------------------------------------------------
+template <typename MT>
+__global__ void k_transpose_x(const double* __restrict__ x, int64_t ldx, int kc, int64_t N, int64_t rows,
+                              MT* __restrict__ xt) {
+    const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (e >= rows * 16) return;
+    const int64_t j = e >> 4;
+    const int n = int(e & 15);
+    xt[e] = (n < kc && j < N) ? MT(x[int64_t(n) * ldx + j]) : MT(0);
+}
+
+template <typename MT>
+__global__ __launch_bounds__(256) void k_matvec_mfma(const MT* __restrict__ W, int64_t ldw, int64_t N,
+                                                     const MT* __restrict__ xt, int64_t cols_per_split, int kc,
+                                                     double* __restrict__ y, int64_t ldy, MT* __restrict__ partial) {
+    using MC = MatrixCore<MT>;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = lane & 15, kg = lane >> 4;
+    const int64_t row0 = (int64_t(blockIdx.x) * 4 + wave) * 16;
+    if (row0 >= N) return;
+    const int64_t row = row0 + i;
+    const int split = blockIdx.y;
+    const int64_t c0 = int64_t(split) * cols_per_split;
+    const int64_t c1 = min<int64_t>(ldw, c0 + cols_per_split);
+    typename MC::V acc = {0, 0, 0, 0};
+    strip_mfma<MT, 8>(W + (row < N ? row : row0) * ldw, row < N, c0, c1, xt, acc);
+    if (i < kc) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t rr = row0 + MC::out_row(kg, r);
+            if (rr < N) {
+                if (partial) partial[(int64_t(split) * 16 + i) * ldw + rr] = acc[r];
+                else y[int64_t(i) * ldy + rr] = double(acc[r]);
+            }
+        }
+    }
+}
+
+template <typename MT>
+__global__ void k_reduce_splits(const MT* __restrict__ partial, int S, int kc, int64_t N, int64_t ldw,
+                                double* __restrict__ y, int64_t ldy) {
+    const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (e >= int64_t(kc) * N) return;
+    const int n = int(e / N);
+    const int64_t r = e % N;
+    double s = 0.0;
+    for (int q = 0; q < S; ++q) s += double(partial[(int64_t(q) * 16 + n) * ldw + r]);
+    y[int64_t(n) * ldy + r] = s;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -255,18 +310,33 @@ __global__ __launch_bounds__(256) void k_init_state(const double* __restrict__ p
 inline unsigned gblocks(int64_t N) { return unsigned(std::max<int64_t>(1, std::min<int64_t>(1024, (N + 255) / 256))); }
 
 template <typename MT, typename AT>
-void launch_matvec(const MT* W, int64_t ldw, int64_t N, const double* x, int64_t ldx, int k, double* y, int64_t ldy,
+void launch_matvec(const bem_problem* p, const MT* W, const double* x, int64_t ldx, int k, double* y, int64_t ldy,
                    hipStream_t s) {
-    const dim3 grid(unsigned((N + 3) / 4)), block(256);
+    const int64_t N = p->N, ldw = p->ldw;
     for (int c0 = 0; c0 < k; c0 += 16) {
         const int kc = std::min(16, k - c0);
         const double* xc = x + int64_t(c0) * ldx;
         double* yc = y + int64_t(c0) * ldy;
-        if (kc == 1) hipLaunchKernelGGL((k_matvec<MT, AT, 1>), grid, block, 0, s, W, ldw, N, xc, ldx, kc, yc, ldy);
-        else if (kc == 2) hipLaunchKernelGGL((k_matvec<MT, AT, 2>), grid, block, 0, s, W, ldw, N, xc, ldx, kc, yc, ldy);
-        else if (kc <= 4) hipLaunchKernelGGL((k_matvec<MT, AT, 4>), grid, block, 0, s, W, ldw, N, xc, ldx, kc, yc, ldy);
-        else if (kc <= 8) hipLaunchKernelGGL((k_matvec<MT, AT, 8>), grid, block, 0, s, W, ldw, N, xc, ldx, kc, yc, ldy);
-        else hipLaunchKernelGGL((k_matvec<MT, AT, 16>), grid, block, 0, s, W, ldw, N, xc, ldx, kc, yc, ldy);
+        if (kc == 1) {
+            // one column: a plain streaming dot product per row (one wave per row)
+            hipLaunchKernelGGL((k_matvec<MT, AT, 1>), dim3(unsigned((N + 3) / 4)), dim3(256), 0, s, W, ldw, N, xc, ldx, kc, yc, ldy);
+            HIP_CHECK(hipGetLastError());
+            continue;
+        }
+        MT* xt = static_cast<MT*>(p->mv_xt.ptr);
+        MT* part = static_cast<MT*>(p->mv_partial.ptr);
+        hipLaunchKernelGGL(k_transpose_x<MT>, dim3(unsigned((ldw * 16 + 255) / 256)), dim3(256), 0, s, xc, ldx, kc, N, ldw, xt);
+        // split the columns so that about eight waves per SIMD stream W
+        const int64_t strips = (N + 15) / 16;
+        int S = int(std::min<int64_t>(kMaxSplits, std::max<int64_t>(1, (8 * 1024 + strips - 1) / strips)));
+        const int64_t quantum = 128;      // a multiple of the columns one unrolled step covers
+        const int64_t cps = ((ldw + S - 1) / S + quantum - 1) / quantum * quantum;
+        S = int((ldw + cps - 1) / cps);
+        dim3 grid(unsigned((N + 63) / 64), unsigned(S));
+        hipLaunchKernelGGL(k_matvec_mfma<MT>, grid, dim3(256), 0, s, W, ldw, N, xt, cps, kc, yc, ldy, S > 1 ? part : nullptr);
+        if (S > 1)
+            hipLaunchKernelGGL(k_reduce_splits<MT>, dim3(unsigned((int64_t(kc) * N + 255) / 256)), dim3(256), 0, s, part, S, kc, N,
+                               ldw, yc, ldy);
         HIP_CHECK(hipGetLastError());
     }
 }
@@ -316,9 +386,9 @@ void matvec_device(const bem_problem* p, bool fp32, const double* d_x, int64_t l
     if (p->N == 0) return;
     if (fp32) {
         if (!p->W32.ptr) fail(BEM_E_INVALID_ARG, "problem has no FP32 matrix (assemble with BEM_FP32_REFINE)");
-        launch_matvec<float, float>(p->W32.as<float>(), p->ldw, p->N, d_x, ldx, k, d_y, ldx, s);
+        launch_matvec<float, float>(p, p->W32.as<float>(), d_x, ldx, k, d_y, ldx, s);
     } else {
-        launch_matvec<double, double>(p->W64.as<double>(), p->ldw, p->N, d_x, ldx, k, d_y, ldx, s);
+        launch_matvec<double, double>(p, p->W64.as<double>(), d_x, ldx, k, d_y, ldx, s);
     }
 }
 

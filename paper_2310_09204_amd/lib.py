@@ -86,6 +86,8 @@ _ci = ctypes.c_int
 SIGNATURES = {
     "bem_ctx_create": (_ci, [_ci, ctypes.c_size_t, ctypes.POINTER(_vp)]),
     "bem_ctx_destroy": (None, [_vp]),
+    "bem_ctx_synchronize": (_ci, [_vp]),
+    "bem_problem_bench_matvec": (_ci, [_vp, _ci, _i32, _ci, ctypes.POINTER(ctypes.c_double)]),
     "bem_mesh_analyze": (_ci, [_vp, _i64, _vp, _i64, ctypes.POINTER(_i64), _vp, _vp, _vp]),
     "bem_assemble": (_ci, [_vp, _vp, _i64, _vp, _i64, ctypes.POINTER(AssembleOpts), ctypes.POINTER(_vp)]),
     "bem_problem_destroy": (None, [_vp]),
@@ -170,6 +172,9 @@ class Context:
     def handle(self):
         return self._h
 
+    def synchronize(self):
+        _check(load().bem_ctx_synchronize(self._h))
+
     def close(self):
         if self._h:
             load().bem_ctx_destroy(self._h)
@@ -241,6 +246,12 @@ class Problem:
         y = np.empty_like(x)
         _check(load().bem_matvec(self._h, _p(x), x.shape[0], int(fp32), _p(y)))
         return y
+
+    def bench_matvec(self, fp32=False, k=1, reps=10):
+        """Mean seconds per device-resident product W x (k columns), timed with HIP events."""
+        t = ctypes.c_double()
+        _check(load().bem_problem_bench_matvec(self._h, int(fp32), k, reps, ctypes.byref(t)))
+        return t.value
 
     def jump_values(self, phi):
         phi = _f64(phi)

@@ -60,9 +60,10 @@ def test_matrix_rhs_jumps(ctx, name):
     phi = np.random.default_rng(1).standard_normal(t.N)
     assert np.allclose(p.jump_values(phi), t.jump_values(phi), rtol=0, atol=1e-13 * np.abs(phi).max())
     # matvec against the FP64 product
-    x = np.random.default_rng(2).standard_normal((3, t.N))
-    y = p.matvec(x)
-    assert np.abs(y - x @ Wo).max() <= 1e-12 * np.abs(x @ Wo).max()
+    for k in (1, 3, 16, 17):
+        x = np.random.default_rng(2 + k).standard_normal((k, t.N))
+        y = p.matvec(x)
+        assert np.abs(y - x @ Wo).max() <= 1e-12 * np.abs(x @ Wo).max(), k
 
 
 def test_book48_sampled_rows(ctx):
@@ -109,10 +110,11 @@ def test_fp32_copy_matches_rounding(ctx):
     m = meshes.unit_square(8)
     p = lib.Problem(ctx, m.vertices, m.triangles, precision=lib.FP32_REFINE, near_order=NEAR)
     W = p.matrix()
-    x = np.random.default_rng(3).standard_normal((2, p.N))
-    y32 = p.matvec(x, fp32=True)
-    ref = x.astype(np.float32).astype(np.float64) @ W.astype(np.float32).astype(np.float64)
-    assert np.abs(y32 - ref).max() < 1e-5 * np.abs(ref).max()
+    for k in (1, 2, 16, 19):
+        x = np.random.default_rng(3 + k).standard_normal((k, p.N))
+        y32 = p.matvec(x, fp32=True)
+        ref = x.astype(np.float32).astype(np.float64) @ W.astype(np.float32).astype(np.float64)
+        assert np.abs(y32 - ref).max() < 1e-5 * np.abs(ref).max(), k
 
 
 def test_invalid_meshes_rejected_before_device_work(ctx):

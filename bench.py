@@ -160,6 +160,7 @@ def main():
         pinfo = p.info
         out = {"t_step": t3 - t0, "t_assemble": t1 - t0, "t_precond": t2 - t1, "t_solve": t3 - t2,
                "t_far": pinfo["t_far_s"], "t_near": pinfo["t_near_s"], "t_contract": pinfo["t_contract_s"],
+               "t_host": pinfo["t_host_s"],
                "iters": [i["iters"] for i in info], "outer": [i["outer_iters"] for i in info], "rc": rc,
                "info": pinfo, "precond_sizes": M.sizes()}
         if want_phi:
@@ -201,8 +202,8 @@ def main():
         r.pop("M").close()
         r.pop("problem").close()
         res.append(r)
-        log("bench: step %d %.3fs asm %.3f (far %.3f near %.4f contract %.3f) precond %.3f solve %.3f iters %s relerr max %.2e"
-            % (i, r["t_step"], r["t_assemble"], r["t_far"], r["t_near"], r["t_contract"], r["t_precond"], r["t_solve"],
+        log("bench: step %d %.3fs asm %.3f (host %.3f far %.3f near %.4f contract %.3f) precond %.3f solve %.3f iters %s relerr max %.2e"
+            % (i, r["t_step"], r["t_assemble"], r["t_host"], r["t_far"], r["t_near"], r["t_contract"], r["t_precond"], r["t_solve"],
                r["iters"][:4], max(r["relerr"])))
     ctx.synchronize()
     elapsed = time.perf_counter() - t_begin
@@ -266,7 +267,7 @@ def main():
         "pair_integrals_per_s_far_kernel": far_pairs / t_far,
         "latency_s": {"p50": lat[len(lat) // 2], "p99": lat[min(len(lat) - 1, int(round(0.99 * (len(lat) - 1))))]},
         "phases_s": {k_: float(np.mean([r[k_] for r in res])) for k_ in
-                     ("t_step", "t_assemble", "t_far", "t_near", "t_contract", "t_precond", "t_solve")},
+                     ("t_step", "t_assemble", "t_host", "t_far", "t_near", "t_contract", "t_precond", "t_solve")},
         "iters": res[-1]["iters"],
         "outer_iters": res[-1]["outer"],
         "relerr_max": max(max(r["relerr"]) for r in res),

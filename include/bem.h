@@ -71,6 +71,7 @@ typedef struct {
     int64_t q_hist[16];      /* number of vertices with q sectors (q >= 15 in the last bin) */
     double t_assemble_s;     /* wall time of bem_assemble (device work, synchronised) */
     double t_far_s, t_near_s, t_contract_s; /* device time of the three assembly phases */
+    double t_host_s;         /* host time of the mesh analysis and near-pair list */
 } bem_problem_info;
 
 typedef struct {

@@ -18,7 +18,12 @@
 // the coincident and edge cases, the anchor variables) integrated exactly: for the kernel
 // 1/|x-y| the integrand is a polynomial of degree <= 2 in those variables, which Gauss-Legendre
 // integrates exactly from 2 points on, so dropping them changes nothing but rounding.
+#include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <functional>
 
 #include "internal.h"
 
@@ -76,12 +81,20 @@ __global__ void k_jump_vectors(const double* __restrict__ V, const int32_t* __re
     for (int k = 0; k < 3; ++k) J[3 * e + k] = s * (V[3 * int64_t(v1) + k] - V[3 * int64_t(v2) + k]);
 }
 
-// One wave per 64x64 tile (rb <= cb); 4 waves per block.
+// One wave per 64x64 tile (rb <= cb); 4 waves per block.  Lane t keeps its row triangle's 7 Gauss
+// points in registers; the wave walks the tile's column triangles tp, whose points arrive through
+// scalar loads.  Results go out in chunks of 16 columns: row tp of I directly (64 consecutive
+// entries), and row t of I through an LDS transpose so that each store instruction writes eight
+// complete 128-byte rows segments instead of 64 scattered 8-byte pieces.
+constexpr int kChunk = 16;
+
 __global__ __launch_bounds__(256) void k_far(const double* __restrict__ geo, int32_t nt, int64_t ld,
                                              const int2* __restrict__ tiles, int64_t ntiles,
                                              double* __restrict__ I) {
+    __shared__ double stage[4][kTile][kChunk + 1];
     const int lane = threadIdx.x & 63;
-    const int64_t tile = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    const int wave = threadIdx.x >> 6;
+    const int64_t tile = int64_t(blockIdx.x) * 4 + wave;
     if (tile >= ntiles) return;
     const int2 tc = tiles[tile];
     const int rb = __builtin_amdgcn_readfirstlane(tc.x);
@@ -99,25 +112,57 @@ __global__ __launch_bounds__(256) void k_far(const double* __restrict__ geo, int
     }
     const int c0 = cb * kTile;
     const int c1 = min(c0 + kTile, nt);
-    for (int tp = c0; tp < c1; ++tp) {
-        const double* h = geo + int64_t(tp) * kGeo;
-        double acc = 0.0;
+    // row stride ld is a multiple of 8 doubles, so the paired stores below are 16-byte aligned
+    // full off-diagonal tiles use the staged stores; diagonal and ragged tiles store directly
+    const bool staged = (rb != cb) && (c1 - c0 == kTile) && (rb * kTile + kTile <= nt);
+    for (int j0 = c0; j0 < c1; j0 += kChunk) {
+        double val[kChunk];
 #pragma unroll
-        for (int q = 0; q < 7; ++q) {
-            const double yx = h[3 * q], yy = h[3 * q + 1], yz = h[3 * q + 2];
-            double s = 0.0;
+        for (int j = 0; j < kChunk; ++j) {
+            const int tp = j0 + j;
+            double acc = 0.0;
+            if (tp < c1) {
+                const double* h = geo + int64_t(tp) * kGeo;
 #pragma unroll
-            for (int p = 0; p < 7; ++p) {
-                const double dx = px[p] - yx, dy = py[p] - yy, dz = pz[p] - yz;
-                const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-                s = fma(pw[p], rsqrt_refined(r2), s);
+                for (int q = 0; q < 7; ++q) {
+                    const double yx = h[3 * q], yy = h[3 * q + 1], yz = h[3 * q + 2];
+                    double sacc = 0.0;
+#pragma unroll
+                    for (int p = 0; p < 7; ++p) {
+                        const double dx = px[p] - yx, dy = py[p] - yy, dz = pz[p] - yz;
+                        const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                        sacc = fma(pw[p], rsqrt_refined(r2), sacc);
+                    }
+                    acc = fma(h[21 + q], sacc, acc);
+                }
             }
-            acc = fma(h[21 + q], s, acc);
+            val[j] = acc * kInv4Pi;
         }
-        const double val = acc * kInv4Pi;
-        if (valid && (rb != cb || t < tp)) {
-            I[int64_t(tp) * ld + t] = val;
-            I[int64_t(t) * ld + tp] = val;
+        if (staged) {
+#pragma unroll
+            for (int j = 0; j < kChunk; ++j) {
+                I[int64_t(j0 + j) * ld + t] = val[j];       // row tp: 64 consecutive entries
+                stage[wave][lane][j] = val[j];
+            }
+            __builtin_amdgcn_wave_barrier();   // stage[wave] is private to this wave; order write -> read
+            // row t: lanes 8r .. 8r+7 write row (8 pass + r) of the tile, 16 bytes each
+#pragma unroll
+            for (int pass = 0; pass < 8; ++pass) {
+                const int row = pass * 8 + (lane >> 3);
+                const int col = (lane & 7) * 2;
+                const double2 v = make_double2(stage[wave][row][col], stage[wave][row][col + 1]);
+                *reinterpret_cast<double2*>(I + int64_t(rb * kTile + row) * ld + j0 + col) = v;
+            }
+            __builtin_amdgcn_wave_barrier();   // reads done before the next chunk overwrites stage
+        } else {
+#pragma unroll
+            for (int j = 0; j < kChunk; ++j) {
+                const int tp = j0 + j;
+                if (valid && tp < c1 && (rb != cb || t < tp)) {
+                    I[int64_t(tp) * ld + t] = val[j];
+                    I[int64_t(t) * ld + tp] = val[j];
+                }
+            }
         }
     }
 }
@@ -258,29 +303,202 @@ __global__ void k_near_vertex(const double* __restrict__ V, const int32_t* __res
     I[b * ld + a] = val;
 }
 
-// W[d][e] for d <= e over the stars of d and e, written to both halves (exactly symmetric).
-__global__ __launch_bounds__(256) void k_contract(const double* __restrict__ I, int64_t ldI,
-                                                  const int64_t* __restrict__ dof_ptr,
-                                                  const int32_t* __restrict__ dof_tri,
-                                                  const double* __restrict__ dof_J, int64_t N,
-                                                  double* __restrict__ W, int64_t ldw) {
-    const int64_t bx = blockIdx.x, by = blockIdx.y;
-    if (by > bx) return;
-    const int64_t d = by * 16 + threadIdx.y;
-    const int64_t e = bx * 16 + threadIdx.x;
-    if (d >= N || e >= N || d > e) return;
-    double sum = 0.0;
-    const int64_t e0 = dof_ptr[e], e1 = dof_ptr[e + 1];
-    for (int64_t i = dof_ptr[d]; i < dof_ptr[d + 1]; ++i) {
-        const double* Irow = I + int64_t(dof_tri[i]) * ldI;
-        const double j0 = dof_J[3 * i], j1 = dof_J[3 * i + 1], j2 = dof_J[3 * i + 2];
-        for (int64_t k = e0; k < e1; ++k) {
-            const double dj = j0 * dof_J[3 * k] + j1 * dof_J[3 * k + 1] + j2 * dof_J[3 * k + 2];
-            sum = fma(Irow[dof_tri[k]], dj, sum);
-        }
+// W over 64 x 64 dof tiles above the diagonal.  Wave w of the block takes rows d0 + 16w .. +15 one
+// at a time; lane l takes column e = e0 + l.  The row dof's star (triangle T_i, J_i) is
+// wave-uniform and comes through scalar loads; each lane keeps its column dof's star (T'_k, J_k) in
+// registers.  For a row, all of its I(T_i, T'_k) loads (up to kReg x kReg, neighbouring columns of
+// a few rows of I) are issued before any is consumed, so a wave keeps dozens of loads in flight;
+// stars longer than kReg (junction dofs) finish in a slower loop.  Each W entry is computed once
+// and written to both halves (exactly symmetric); the mirrored tile is transposed through LDS so
+// both writes are coalesced.
+constexpr int kCT = 64;    // tile edge (dofs)
+constexpr int kReg = 6;    // star entries handled in the unrolled path (a flat interior star has 6)
+
+__global__ __launch_bounds__(256) void k_contract(const double* __restrict__ I, int64_t ldI, int64_t N,
+                                                  const int64_t* __restrict__ dof_ptr, const int32_t* __restrict__ dof_tri,
+                                                  const double* __restrict__ dof_J, const int2* __restrict__ tiles,
+                                                  int64_t ntiles, double* __restrict__ W, int64_t ldw) {
+    __shared__ double tileT[kCT][kCT + 1];
+    // blocks of one XCD (blockIdx % 8) walk a contiguous run of tiles, so neighbouring tiles that
+    // re-read the same rows of I meet in that XCD's L2
+    const int64_t per = (ntiles + 7) / 8;
+    const int64_t t = int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (t >= ntiles) return;
+    const int2 tl = tiles[t];
+    const int bd = tl.x, be = tl.y;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t e = int64_t(be) * kCT + lane;
+    const bool ev = e < N;
+    const int64_t kb = ev ? dof_ptr[e] : 0;
+    const int ne = ev ? int(dof_ptr[e + 1] - kb) : 0;
+    int Tk[kReg];
+    double Jx[kReg], Jy[kReg], Jz[kReg];
+#pragma unroll
+    for (int k = 0; k < kReg; ++k) {
+        const bool h = k < ne;
+        Tk[k] = h ? dof_tri[kb + k] : 0;
+        Jx[k] = h ? dof_J[3 * (kb + k)] : 0.0;
+        Jy[k] = h ? dof_J[3 * (kb + k) + 1] : 0.0;
+        Jz[k] = h ? dof_J[3 * (kb + k) + 2] : 0.0;
     }
-    W[d * ldw + e] = sum;
-    W[e * ldw + d] = sum;
+    for (int r = 0; r < 16; ++r) {
+        const int64_t d = int64_t(bd) * kCT + wave * 16 + r;
+        double acc = 0.0;
+        if (d < N) {
+            const int64_t i0 = dof_ptr[d];
+            const int ni = int(dof_ptr[d + 1] - i0);
+            const double* Ir[kReg];
+            double ja[kReg], jb[kReg], jc[kReg];
+#pragma unroll
+            for (int i = 0; i < kReg; ++i) {
+                const bool h = i < ni;
+                Ir[i] = I + int64_t(h ? dof_tri[i0 + i] : 0) * ldI;
+                ja[i] = h ? dof_J[3 * (i0 + i)] : 0.0;
+                jb[i] = h ? dof_J[3 * (i0 + i) + 1] : 0.0;
+                jc[i] = h ? dof_J[3 * (i0 + i) + 2] : 0.0;
+            }
+            double v[kReg][kReg];
+#pragma unroll
+            for (int i = 0; i < kReg; ++i)
+#pragma unroll
+                for (int k = 0; k < kReg; ++k) v[i][k] = (i < ni && k < ne) ? Ir[i][Tk[k]] : 0.0;
+#pragma unroll
+            for (int i = 0; i < kReg; ++i)
+#pragma unroll
+                for (int k = 0; k < kReg; ++k) acc = fma(v[i][k], ja[i] * Jx[k] + jb[i] * Jy[k] + jc[i] * Jz[k], acc);
+            // junction stars: the entries beyond the unrolled ones
+            if (ni > kReg || ne > kReg) {
+                for (int i = 0; i < ni; ++i) {
+                    const int64_t qi = i0 + i;
+                    const double* Irow = I + int64_t(dof_tri[qi]) * ldI;
+                    const double j0 = dof_J[3 * qi], j1 = dof_J[3 * qi + 1], j2 = dof_J[3 * qi + 2];
+                    for (int k = (i < kReg ? kReg : 0); k < ne; ++k) {
+                        const int64_t q = kb + k;
+                        acc = fma(Irow[dof_tri[q]], j0 * dof_J[3 * q] + j1 * dof_J[3 * q + 1] + j2 * dof_J[3 * q + 2], acc);
+                    }
+                }
+            }
+            if (bd != be || e >= d) W[d * ldw + e] = acc;   // columns past N: zero padding
+        }
+        tileT[wave * 16 + r][lane] = acc;
+    }
+    __syncthreads();
+    // mirrored half: W[e'][d'] = entry (d', e') for the tile's rows d' and columns e'
+    for (int q = threadIdx.x; q < kCT * kCT; q += 256) {
+        const int re = q / kCT, cd = q % kCT;
+        const int64_t em = int64_t(be) * kCT + re, dm = int64_t(bd) * kCT + cd;
+        if (em < N && dm < N && (bd != be || dm < em)) W[em * ldw + dm] = tileT[cd][re];
+    }
+}
+
+// Staged form of the same contraction, for column blocks whose stars together hold at most kCap
+// triangles.  With y_T(e) = sum over the star of e of J(T',e) I(T,T'), an entry is
+// W(d,e) = sum over T in the star of d of J(T,d) . y_T(e).  The 64 columns of a tile share one
+// sorted list C of the triangles in their stars (at most kCap), and each lane holds the first kRegC
+// entries of its column's star as positions in C (longer junction stars finish from memory).  Wave w of the block owns 16 rows; it walks the triangles T of their stars
+// (one group per triangle, prepared on the host), loads I(T, C) once with neighbouring lanes on
+// neighbouring list entries, stages it in LDS, forms y_T for all 64 columns from LDS and adds
+// J(T,d) . y_T into the rows d whose star holds T.  The next group's I(T, C) is in flight while the
+// current one is used.  Accumulators live in LDS, which then feeds both the direct and the
+// mirrored (transposed) coalesced write.  Columns past N (the padding of W) are written as zero.
+constexpr int kRegC = 8;
+constexpr int kCap = kCT * kRegC;
+
+__global__ __launch_bounds__(256) void k_contract_staged(
+    const double* __restrict__ I, int64_t ldI, int64_t N, const int32_t* __restrict__ cb_ptr,
+    const int32_t* __restrict__ cb_tri, const int64_t* __restrict__ dof_ptr, const int32_t* __restrict__ col_loc,
+    const double* __restrict__ dof_J, const int32_t* __restrict__ rg_ptr, const int4* __restrict__ rg,
+    const int2* __restrict__ rg_ent, const int2* __restrict__ tiles, int64_t ntiles, double* __restrict__ W,
+    int64_t ldw) {
+    __shared__ double acc[kCT][kCT + 1];
+    __shared__ double seg[4][kCap];
+    const int64_t per = (ntiles + 7) / 8;
+    const int64_t t = int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (t >= ntiles) return;
+    const int2 tl = tiles[t];
+    const int bd = __builtin_amdgcn_readfirstlane(tl.x), be = __builtin_amdgcn_readfirstlane(tl.y);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t e = int64_t(be) * kCT + lane;
+    const bool ev = e < N;
+    const int64_t kb = ev ? dof_ptr[e] : 0;
+    const int ne = ev ? int(dof_ptr[e + 1] - kb) : 0;
+    int loc[kRegC];
+    double Jx[kRegC], Jy[kRegC], Jz[kRegC];
+#pragma unroll
+    for (int k = 0; k < kRegC; ++k) {
+        const bool h = k < ne;
+        loc[k] = h ? col_loc[kb + k] : 0;
+        Jx[k] = h ? dof_J[3 * (kb + k)] : 0.0;
+        Jy[k] = h ? dof_J[3 * (kb + k) + 1] : 0.0;
+        Jz[k] = h ? dof_J[3 * (kb + k) + 2] : 0.0;
+    }
+    const int c0 = cb_ptr[be];
+    const int nc = cb_ptr[be + 1] - c0;
+    int cidx[kRegC];
+#pragma unroll
+    for (int m = 0; m < kRegC; ++m) {
+        const int j = m * kCT + lane;
+        cidx[m] = j < nc ? cb_tri[c0 + j] : 0;
+    }
+    double* arow = &acc[wave * 16][0];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) arow[r * (kCT + 1) + lane] = 0.0;
+    const int rb = bd * 4 + wave;
+    const int g0 = rg_ptr[rb], g1 = rg_ptr[rb + 1];
+    double nxt[kRegC];
+    // chunk 0 is always fetched and staged so that position 0 of the list holds a finite value
+    auto fetch = [&](int T) {
+        const double* row = I + int64_t(T) * ldI;
+#pragma unroll
+        for (int m = 0; m < kRegC; ++m)
+            if (m == 0 || m * kCT < nc) nxt[m] = row[cidx[m]];
+    };
+    if (g0 < g1) fetch(rg[g0].x);
+    for (int g = g0; g < g1; ++g) {
+        const int4 G = rg[g];   // (triangle, rows, first entry, -)
+#pragma unroll
+        for (int m = 0; m < kRegC; ++m)
+            if (m == 0 || m * kCT < nc) seg[wave][m * kCT + lane] = nxt[m];
+        if (g + 1 < g1) fetch(rg[g + 1].x);
+        __builtin_amdgcn_wave_barrier();   // seg[wave] belongs to this wave: order write -> read
+        double yx = 0.0, yy = 0.0, yz = 0.0;
+#pragma unroll
+        for (int k = 0; k < kRegC; ++k) {
+            const double v = seg[wave][loc[k]];
+            yx = fma(Jx[k], v, yx);
+            yy = fma(Jy[k], v, yy);
+            yz = fma(Jz[k], v, yz);
+        }
+        if (ne > kRegC) {   // junction columns: star entries past the registers, from memory
+            for (int k = kRegC; k < ne; ++k) {
+                const int64_t q = kb + k;
+                const double v = seg[wave][col_loc[q]];
+                yx = fma(dof_J[3 * q], v, yx);
+                yy = fma(dof_J[3 * q + 1], v, yy);
+                yz = fma(dof_J[3 * q + 2], v, yz);
+            }
+        }
+        for (int i = 0; i < G.y; ++i) {
+            const int2 en = rg_ent[G.z + i];   // (row in the wave's 16, star entry of that row)
+            const double* j = dof_J + 3 * int64_t(en.y);
+            double& a = arow[en.x * (kCT + 1) + lane];
+            a = fma(j[0], yx, fma(j[1], yy, fma(j[2], yz, a)));
+        }
+        __builtin_amdgcn_wave_barrier();   // reads of seg done before the next group overwrites it
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int64_t d = int64_t(bd) * kCT + wave * 16 + r;
+        if (d < N && (bd != be || e >= d)) W[d * ldw + e] = arow[r * (kCT + 1) + lane];
+    }
+    for (int q = threadIdx.x; q < kCT * kCT; q += 256) {
+        const int re = q / kCT, cd = q % kCT;
+        const int64_t em = int64_t(be) * kCT + re, dm = int64_t(bd) * kCT + cd;
+        if (em < N && dm < N && (bd != be || dm < em)) W[em * ldw + dm] = acc[cd][re];
+    }
 }
 
 __global__ void k_f64_to_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
@@ -319,48 +537,198 @@ __global__ void k_jump_values(const int64_t* __restrict__ tri_ptr, const int32_t
 
 inline unsigned blocks_for(int64_t n, int per) { return unsigned((n + per - 1) / per); }
 
+// Brackets device work on a stream with two events; the elapsed time is read once the work is done,
+// so timing never stalls the host in the middle of the pipeline.
 struct EventTimer {
-    hipEvent_t a, b;
+    hipEvent_t a = nullptr, b = nullptr;
     hipStream_t s;
     explicit EventTimer(hipStream_t st) : s(st) {
         HIP_CHECK(hipEventCreate(&a));
         HIP_CHECK(hipEventCreate(&b));
         HIP_CHECK(hipEventRecord(a, s));
     }
-    double stop() {
-        HIP_CHECK(hipEventRecord(b, s));
+    void stop() { HIP_CHECK(hipEventRecord(b, s)); }
+    double seconds() {
         HIP_CHECK(hipEventSynchronize(b));
         float ms = 0.f;
         HIP_CHECK(hipEventElapsedTime(&ms, a, b));
         return ms * 1e-3;
     }
+    EventTimer(const EventTimer&) = delete;
+    EventTimer& operator=(const EventTimer&) = delete;
     ~EventTimer() {
         (void)hipEventDestroy(a);
         (void)hipEventDestroy(b);
     }
 };
 
+// Host side of the staged contraction.  Column blocks are 64 consecutive dofs: the sorted union
+// of their stars' triangles and, per star entry, its position in that union.  Row blocks are 16
+// consecutive dofs: one group per triangle of their stars, listing the (row, star entry) pairs
+// that hold it.  Tiles whose column block's union exceeds kCap triangles take the general kernel.
+struct ContractPlan {
+    std::vector<int32_t> cb_ptr, cb_tri, col_loc, rg_ptr;
+    std::vector<int4> rg;
+    std::vector<int2> rg_ent, fast, slow;
+};
+
+ContractPlan contract_plan(const MeshTopo& m) {
+    const int64_t N = m.N;
+    const int64_t ncb = (N + kCT - 1) / kCT, nrb = ncb * 4;
+    const int64_t nnz = m.dof_ptr[N];
+    if (nnz > INT32_MAX) fail(BEM_E_UNSUPPORTED, "more than 2^31 star entries");
+    ContractPlan P;
+    P.col_loc.assign(size_t(nnz), 0);
+    P.cb_ptr.assign(size_t(ncb) + 1, 0);
+    std::vector<uint8_t> ok(static_cast<size_t>(ncb), 1);
+    std::vector<std::vector<int32_t>> lists(static_cast<size_t>(ncb));
+    parallel_for(ncb, [&](int64_t lo, int64_t hi) {
+        for (int64_t b = lo; b < hi; ++b) {
+            const int64_t e0 = b * kCT, e1 = std::min<int64_t>(N, e0 + kCT);
+            std::vector<int32_t>& L = lists[size_t(b)];
+            for (int64_t e = e0; e < e1; ++e) {
+                for (int64_t q = m.dof_ptr[e]; q < m.dof_ptr[e + 1]; ++q) L.push_back(m.dof_tri[q]);
+            }
+            std::sort(L.begin(), L.end());
+            L.erase(std::unique(L.begin(), L.end()), L.end());
+            if (int64_t(L.size()) > kCap) ok[size_t(b)] = 0;
+            for (int64_t q = m.dof_ptr[e0]; q < m.dof_ptr[e1]; ++q)
+                P.col_loc[size_t(q)] = int32_t(std::lower_bound(L.begin(), L.end(), m.dof_tri[q]) - L.begin());
+        }
+    });
+    for (int64_t b = 0; b < ncb; ++b) P.cb_ptr[size_t(b) + 1] = P.cb_ptr[size_t(b)] + int32_t(lists[size_t(b)].size());
+    P.cb_tri.reserve(size_t(P.cb_ptr.back()));
+    for (auto& L : lists) P.cb_tri.insert(P.cb_tri.end(), L.begin(), L.end());
+
+    // row groups: (triangle, row, entry) sorted by triangle then row
+    std::vector<std::vector<int4>> groups(static_cast<size_t>(nrb));
+    std::vector<std::vector<int2>> ents(static_cast<size_t>(nrb));
+    parallel_for(nrb, [&](int64_t lo, int64_t hi) {
+        std::vector<int4> key;   // (triangle, row, entry, -)
+        for (int64_t b = lo; b < hi; ++b) {
+            key.clear();
+            for (int r = 0; r < 16; ++r) {
+                const int64_t d = b * 16 + r;
+                if (d >= N) break;
+                for (int64_t q = m.dof_ptr[d]; q < m.dof_ptr[d + 1]; ++q) key.push_back(make_int4(m.dof_tri[q], r, int(q), 0));
+            }
+            std::sort(key.begin(), key.end(), [](const int4& a, const int4& c) { return a.x != c.x ? a.x < c.x : a.y < c.y; });
+            std::vector<int4>& G = groups[size_t(b)];
+            std::vector<int2>& E = ents[size_t(b)];
+            for (size_t i = 0; i < key.size();) {
+                size_t j = i;
+                while (j < key.size() && key[j].x == key[i].x) ++j;
+                G.push_back(make_int4(key[i].x, int(j - i), int(E.size()), 0));
+                for (size_t k = i; k < j; ++k) E.push_back(make_int2(key[k].y, key[k].z));
+                i = j;
+            }
+        }
+    });
+    P.rg_ptr.assign(size_t(nrb) + 1, 0);
+    for (int64_t b = 0; b < nrb; ++b) P.rg_ptr[size_t(b) + 1] = P.rg_ptr[size_t(b)] + int32_t(groups[size_t(b)].size());
+    P.rg.reserve(size_t(P.rg_ptr.back()));
+    for (int64_t b = 0; b < nrb; ++b) {
+        const int32_t base = int32_t(P.rg_ent.size());
+        for (int4 g : groups[size_t(b)]) P.rg.push_back(make_int4(g.x, g.y, g.z + base, 0));
+        P.rg_ent.insert(P.rg_ent.end(), ents[size_t(b)].begin(), ents[size_t(b)].end());
+    }
+    for (int64_t gd = 0; gd < ncb; ++gd)
+        for (int64_t ge = gd; ge < ncb; ++ge) (ok[size_t(ge)] ? P.fast : P.slow).push_back(make_int2(int(gd), int(ge)));
+    return P;
+}
+
 }  // namespace
 
-void assemble_device(bem_problem* p, const NearList& near) {
+void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_t* Tin, int64_t nt,
+                     const std::function<void(NearList&)>& analyse) {
     const MeshTopo& m = p->topo;
     hipStream_t s = p->stream;
-    const int64_t nt = m.nt, N = m.N;
+    // BEM_TRACE=1: synchronise and print the wall time of each assembly phase to stderr
+    const bool trace = std::getenv("BEM_TRACE") != nullptr;
+    auto tlast = std::chrono::steady_clock::now();
+    auto mark = [&](const char* what) {
+        if (!trace) return;
+        HIP_CHECK(hipStreamSynchronize(s));
+        auto now = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "bem-trace assemble %-18s %8.3f ms\n", what, std::chrono::duration<double>(now - tlast).count() * 1e3);
+        tlast = now;
+    };
+    // The geometry and far-field kernels need only coordinates and in-range indices.  They go first,
+    // and the host's mesh analysis (sectors, dofs, near list) runs while the device integrates; a
+    // mesh the analysis rejects leaves only discarded device work behind.  Indices and referenced
+    // coordinates are checked here so that no kernel can read outside the vertex array.
+    bool launchable = Vin && Tin && nv > 0 && nt > 0 && nt <= (int64_t(1) << 30);
+    for (int64_t i = 0; launchable && i < 3 * nt; ++i) {
+        const int32_t v = Tin[i];
+        launchable = v >= 0 && v < nv && std::isfinite(Vin[3 * v]) && std::isfinite(Vin[3 * v + 1]) &&
+                     std::isfinite(Vin[3 * v + 2]);
+    }
+    if (!launchable) {
+        NearList unused;
+        analyse(unused);   // reports the specific validation error
+        fail(BEM_E_INVALID_ARG, "mesh rejected");
+    }
 
     double bary[7][3], w7[7];
     triangle7_rule(bary, w7);
     std::vector<double> hb(&bary[0][0], &bary[0][0] + 21), hw(w7, w7 + 7);
-    std::vector<double> gx, gw;
-    gauss_legendre01(p->near_order, gx, gw);
 
-    DeviceBuffer dV = upload(m.V, s), dT = upload(m.T, s);
-    DeviceBuffer db = upload(hb, s), dw = upload(hw, s), dgx = upload(gx, s), dgw = upload(gw, s);
+    DeviceBuffer dV(sizeof(double) * 3 * nv), dT(sizeof(int32_t) * 3 * nt);
+    HIP_CHECK(hipMemcpyAsync(dV.ptr, Vin, dV.bytes, hipMemcpyHostToDevice, s));
+    HIP_CHECK(hipMemcpyAsync(dT.ptr, Tin, dT.bytes, hipMemcpyHostToDevice, s));
+    DeviceBuffer db = upload(hb, s), dw = upload(hw, s);
     DeviceBuffer geo(sizeof(double) * nt * kGeo);
     p->normal = DeviceBuffer(sizeof(double) * nt * 3);
     p->area = DeviceBuffer(sizeof(double) * nt);
     hipLaunchKernelGGL(k_geometry, dim3(blocks_for(nt, 256)), dim3(256), 0, s, dV.as<double>(), dT.as<int32_t>(), nt,
                        db.as<double>(), dw.as<double>(), geo.as<double>(), p->normal.as<double>(), p->area.as<double>());
     HIP_CHECK(hipGetLastError());
+
+    // pair integrals I (nt x ldI), rows padded to 64 bytes so the far kernel's paired stores stay aligned
+    const int64_t ldI = (nt + 7) / 8 * 8;
+    p->ldI = ldI;
+    p->I = DeviceBuffer(sizeof(double) * nt * ldI);
+    const int nb = int((nt + kTile - 1) / kTile);
+    std::vector<int2> tiles;
+    tiles.reserve(size_t(nb) * (nb + 1) / 2);
+    for (int rb = 0; rb < nb; ++rb)
+        for (int cb = rb; cb < nb; ++cb) tiles.push_back(make_int2(rb, cb));
+    DeviceBuffer dtiles = upload(tiles, s);
+    EventTimer t_far(s);
+    {
+        const int64_t nti = int64_t(tiles.size());
+        hipLaunchKernelGGL(k_far, dim3(blocks_for(nti, 4)), dim3(256), 0, s, geo.as<double>(), int32_t(nt), ldI,
+                           dtiles.as<int2>(), nti, p->I.as<double>());
+        HIP_CHECK(hipGetLastError());
+    }
+    t_far.stop();
+    mark("geometry+far");
+
+    // host: mesh analysis, near list, and the plans of the near and contraction passes.  If the
+    // analysis rejects the mesh, the queued kernels finish before their buffers are released.
+    const auto h0 = std::chrono::steady_clock::now();
+    NearList near;
+    std::vector<int32_t> nv_[4], na_[4], nb_[4];
+    ContractPlan plan;
+    std::vector<double> gx, gw;
+    try {
+        analyse(near);
+        for (size_t i = 0; i < near.t1.size(); ++i) {
+            const int ty = near.type[i];
+            na_[ty].push_back(near.t1[i]);
+            nb_[ty].push_back(near.t2[i]);
+            nv_[ty].insert(nv_[ty].end(), &near.verts[5 * i], &near.verts[5 * i] + 5);
+        }
+        if (m.N > 0) plan = contract_plan(m);
+        gauss_legendre01(p->near_order, gx, gw);
+    } catch (...) {
+        (void)hipStreamSynchronize(s);
+        throw;
+    }
+    const int64_t N = m.N;
+    p->t_host = std::chrono::duration<double>(std::chrono::steady_clock::now() - h0).count();
+    p->n_near = int64_t(near.t1.size());
+    mark("host analysis");
 
     // incidence tables and jump vectors
     p->dof_ptr = upload(m.dof_ptr, s);
@@ -380,77 +748,74 @@ void assemble_device(bem_problem* p, const NearList& near) {
         HIP_CHECK(hipGetLastError());
     }
 
-    // pair integrals I (nt x nt)
-    const int64_t ldI = nt;
-    p->I = DeviceBuffer(sizeof(double) * nt * ldI);
-    const int nb = int((nt + kTile - 1) / kTile);
-    std::vector<int2> tiles;
-    tiles.reserve(size_t(nb) * (nb + 1) / 2);
-    for (int rb = 0; rb < nb; ++rb)
-        for (int cb = rb; cb < nb; ++cb) tiles.push_back(make_int2(rb, cb));
-    DeviceBuffer dtiles = upload(tiles, s);
-    {
-        EventTimer tm(s);
-        int64_t nti = int64_t(tiles.size());
-        hipLaunchKernelGGL(k_far, dim3(blocks_for(nti, 4)), dim3(256), 0, s, geo.as<double>(), int32_t(nt), ldI,
-                           dtiles.as<int2>(), nti, p->I.as<double>());
-        HIP_CHECK(hipGetLastError());
-        p->t_far = tm.stop();
-    }
-
     // near pairs, one kernel per kind
-    {
-        std::vector<int32_t> v[4], a[4], b[4];
-        for (size_t i = 0; i < near.t1.size(); ++i) {
-            int ty = near.type[i];
-            a[ty].push_back(near.t1[i]);
-            b[ty].push_back(near.t2[i]);
-            v[ty].insert(v[ty].end(), &near.verts[5 * i], &near.verts[5 * i] + 5);
-        }
-        EventTimer tm(s);
-        DeviceBuffer dv[4], da[4], dbb[4];
-        for (int ty = 1; ty <= 3; ++ty) {
-            const int64_t n = int64_t(a[ty].size());
-            if (n == 0) continue;
-            dv[ty] = upload(v[ty], s);
-            da[ty] = upload(a[ty], s);
-            dbb[ty] = upload(b[ty], s);
-            dim3 grid(blocks_for(n, 64)), block(64);
-            if (ty == 3)
-                hipLaunchKernelGGL(k_near_coincident, grid, block, 0, s, dV.as<double>(), dv[ty].as<int32_t>(), da[ty].as<int32_t>(), n,
-                                   p->near_order, dgx.as<double>(), dgw.as<double>(), p->I.as<double>(), ldI);
-            else if (ty == 2)
-                hipLaunchKernelGGL(k_near_edge, grid, block, 0, s, dV.as<double>(), dv[ty].as<int32_t>(), da[ty].as<int32_t>(),
-                                   dbb[ty].as<int32_t>(), n, p->near_order, dgx.as<double>(), dgw.as<double>(), p->I.as<double>(), ldI);
-            else
-                hipLaunchKernelGGL(k_near_vertex, grid, block, 0, s, dV.as<double>(), dv[ty].as<int32_t>(), da[ty].as<int32_t>(),
-                                   dbb[ty].as<int32_t>(), n, p->near_order, dgx.as<double>(), dgw.as<double>(), p->I.as<double>(), ldI);
-            HIP_CHECK(hipGetLastError());
-        }
-        p->t_near = tm.stop();
+    DeviceBuffer dgx = upload(gx, s), dgw = upload(gw, s);
+    DeviceBuffer dv[4], da[4], dbb[4];
+    for (int ty = 1; ty <= 3; ++ty) {
+        if (na_[ty].empty()) continue;
+        dv[ty] = upload(nv_[ty], s);
+        da[ty] = upload(na_[ty], s);
+        dbb[ty] = upload(nb_[ty], s);
     }
-
-    // contraction into W
+    EventTimer t_near(s);
+    for (int ty = 1; ty <= 3; ++ty) {
+        const int64_t n = int64_t(na_[ty].size());
+        if (n == 0) continue;
+        dim3 grid(blocks_for(n, 64)), block(64);
+        if (ty == 3)
+            hipLaunchKernelGGL(k_near_coincident, grid, block, 0, s, dV.as<double>(), dv[ty].as<int32_t>(), da[ty].as<int32_t>(), n,
+                               p->near_order, dgx.as<double>(), dgw.as<double>(), p->I.as<double>(), ldI);
+        else if (ty == 2)
+            hipLaunchKernelGGL(k_near_edge, grid, block, 0, s, dV.as<double>(), dv[ty].as<int32_t>(), da[ty].as<int32_t>(),
+                               dbb[ty].as<int32_t>(), n, p->near_order, dgx.as<double>(), dgw.as<double>(), p->I.as<double>(), ldI);
+        else
+            hipLaunchKernelGGL(k_near_vertex, grid, block, 0, s, dV.as<double>(), dv[ty].as<int32_t>(), da[ty].as<int32_t>(),
+                               dbb[ty].as<int32_t>(), n, p->near_order, dgx.as<double>(), dgw.as<double>(), p->I.as<double>(), ldI);
+        HIP_CHECK(hipGetLastError());
+    }
+    t_near.stop();
+    mark("near");
+    // contraction into W; every entry of W, padding columns included, is written by one tile
     p->ldw = ((N + 63) / 64) * 64;
     p->W64 = DeviceBuffer(sizeof(double) * std::max<int64_t>(N, 1) * p->ldw);
-    HIP_CHECK(hipMemsetAsync(p->W64.ptr, 0, p->W64.bytes, s));   // padding columns stay zero
+    EventTimer t_contract(s);
     if (N > 0) {
-        EventTimer tm(s);
-        dim3 grid(blocks_for(N, 16), blocks_for(N, 16)), block(16, 16);
-        hipLaunchKernelGGL(k_contract, grid, block, 0, s, p->I.as<double>(), ldI, p->dof_ptr.as<int64_t>(), p->dof_tri.as<int32_t>(),
-                           dofJ.as<double>(), N, p->W64.as<double>(), p->ldw);
-        HIP_CHECK(hipGetLastError());
-        p->t_contract = tm.stop();
+        DeviceBuffer d_cb_ptr = upload(plan.cb_ptr, s), d_cb_tri = upload(plan.cb_tri, s);
+        DeviceBuffer d_col_loc = upload(plan.col_loc, s), d_rg_ptr = upload(plan.rg_ptr, s);
+        DeviceBuffer d_rg = upload(plan.rg, s), d_rg_ent = upload(plan.rg_ent, s);
+        DeviceBuffer d_fast = upload(plan.fast, s), d_slow = upload(plan.slow, s);
+        HIP_CHECK(hipEventRecord(t_contract.a, s));
+        const int64_t nf = int64_t(plan.fast.size()), ns = int64_t(plan.slow.size());
+        if (nf > 0) {
+            hipLaunchKernelGGL(k_contract_staged, dim3(unsigned((nf + 7) / 8 * 8)), dim3(256), 0, s, p->I.as<double>(), ldI, N,
+                               d_cb_ptr.as<int32_t>(), d_cb_tri.as<int32_t>(), p->dof_ptr.as<int64_t>(),
+                               d_col_loc.as<int32_t>(), dofJ.as<double>(), d_rg_ptr.as<int32_t>(), d_rg.as<int4>(),
+                               d_rg_ent.as<int2>(), d_fast.as<int2>(), nf, p->W64.as<double>(), p->ldw);
+            HIP_CHECK(hipGetLastError());
+        }
+        if (ns > 0) {
+            hipLaunchKernelGGL(k_contract, dim3(unsigned((ns + 7) / 8 * 8)), dim3(256), 0, s, p->I.as<double>(), ldI, N,
+                               p->dof_ptr.as<int64_t>(), p->dof_tri.as<int32_t>(), dofJ.as<double>(), d_slow.as<int2>(), ns,
+                               p->W64.as<double>(), p->ldw);
+            HIP_CHECK(hipGetLastError());
+        }
     }
+    t_contract.stop();
+    mark("contract");
     if (p->has_w32) {
         p->W32 = DeviceBuffer(sizeof(float) * std::max<int64_t>(N, 1) * p->ldw);
         hipLaunchKernelGGL(k_f64_to_f32, dim3(4096), dim3(256), 0, s, p->W64.as<double>(), p->W32.as<float>(), N * p->ldw);
         HIP_CHECK(hipGetLastError());
     }
+    mark("fp32 copy");
     if (!p->has_pairs) p->I.reset();
+    mark("free I");
     p->mv_xt = DeviceBuffer(sizeof(double) * 16 * p->ldw);
     p->mv_partial = DeviceBuffer(sizeof(double) * 16 * 16 * p->ldw);
     HIP_CHECK(hipStreamSynchronize(s));
+    p->t_far = t_far.seconds();
+    p->t_near = t_near.seconds();
+    p->t_contract = t_contract.seconds();
 }
 
 void rhs_device(const bem_problem* p, const double* d_g, int k, double* d_L, hipStream_t s) {

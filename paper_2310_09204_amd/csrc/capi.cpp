@@ -197,17 +197,25 @@ int bem_assemble(bem_ctx* ctx, const double* vertices, int64_t nv, const int32_t
     auto t0 = std::chrono::steady_clock::now();
     std::unique_ptr<bem_problem> p(new bem_problem());
     p->ctx = ctx;
-    analyze_mesh(vertices, nv, triangles, nt, p->topo);
-    NearList near;
-    build_near_list(p->topo, near);
-    p->N = p->topo.N;
-    p->n_near = int64_t(near.t1.size());
     p->near_order = (opts && opts->near_order > 0) ? opts->near_order : 10;
     if (p->near_order > 64) fail(BEM_E_INVALID_ARG, "near_order above 64");
     p->has_w32 = opts && opts->precision == BEM_FP32_REFINE;
     p->has_pairs = opts && opts->keep_pair_matrix;
     HIP_CHECK(hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking));
-    assemble_device(p.get(), near);
+    try {
+        assemble_device(p.get(), vertices, nv, triangles, nt, [&](NearList& near) {
+            analyze_mesh(vertices, nv, triangles, nt, p->topo);
+            build_near_list(p->topo, near);
+            p->N = p->topo.N;
+        });
+    } catch (...) {
+        // device work already queued must end before its buffers go
+        (void)hipStreamSynchronize(p->stream);
+        hipStream_t s = p->stream;
+        p.reset();
+        (void)hipStreamDestroy(s);
+        throw;
+    }
     p->bytes = int64_t(p->W64.bytes + p->W32.bytes + p->I.bytes + p->normal.bytes + p->area.bytes + p->dof_ptr.bytes +
                        p->dof_tri.bytes + p->dof_c.bytes + p->tri_ptr.bytes + p->tri_dof.bytes + p->tri_corner.bytes +
                        p->tri_c.bytes);
@@ -240,6 +248,7 @@ int bem_problem_get_info(const bem_problem* p, bem_problem_info* info) {
     info->t_far_s = p->t_far;
     info->t_near_s = p->t_near;
     info->t_contract_s = p->t_contract;
+    info->t_host_s = p->t_host;
     return BEM_OK;
     BEM_CATCH
 }
@@ -287,7 +296,7 @@ int bem_problem_pair_integrals(const bem_problem* p, const int32_t* pairs, int64
     for (int64_t i = 0; i < npairs; ++i) {
         const int64_t a = pairs[2 * i], b = pairs[2 * i + 1];
         if (a < 0 || a >= nt || b < 0 || b >= nt) fail(BEM_E_INVALID_ARG, "pair index out of range");
-        HIP_CHECK(hipMemcpy(out + i, p->I.as<double>() + a * nt + b, sizeof(double), hipMemcpyDeviceToHost));
+        HIP_CHECK(hipMemcpy(out + i, p->I.as<double>() + a * p->ldI + b, sizeof(double), hipMemcpyDeviceToHost));
     }
     return BEM_OK;
     BEM_CATCH

@@ -3,10 +3,13 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
+#include <functional>
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/bem.h"
@@ -93,6 +96,25 @@ DeviceBuffer upload(const std::vector<T>& v, hipStream_t s) {
     return b;
 }
 
+// Runs fn(begin, end) over [0, n) split across a few host threads (at most 16); every range but
+// the last starts at a multiple of grain.  fn must not throw.
+template <class Fn>
+void parallel_for(int64_t n, Fn&& fn, int64_t grain = 2048) {
+    const int64_t hw = std::max<int64_t>(1, std::min<int64_t>(16, std::thread::hardware_concurrency()));
+    const int64_t nth = std::max<int64_t>(1, std::min<int64_t>(hw, n / grain));
+    if (nth == 1) {
+        fn(int64_t(0), n);
+        return;
+    }
+    std::vector<std::thread> th;
+    const int64_t chunk = ((n + nth - 1) / nth + grain - 1) / grain * grain;
+    for (int64_t k = 0; k < nth; ++k) {
+        const int64_t b = k * chunk, e = std::min(n, b + chunk);
+        if (b < e) th.emplace_back([&fn, b, e] { fn(b, e); });
+    }
+    for (auto& t : th) t.join();
+}
+
 }  // namespace bem
 
 struct bem_ctx {
@@ -104,25 +126,28 @@ struct bem_ctx {
 struct bem_problem {
     bem_ctx* ctx = nullptr;
     bem::MeshTopo topo;
-    int64_t N = 0, ldw = 0, n_near = 0;
+    int64_t N = 0, ldw = 0, ldI = 0, n_near = 0;
     bool has_w32 = false, has_pairs = false;
     int near_order = 10;
     hipStream_t stream = nullptr;
-    bem::DeviceBuffer W64, W32, I;          // W (N x ldw), optional FP32 copy, optional I (nt x nt)
+    bem::DeviceBuffer W64, W32, I;          // W (N x ldw), optional FP32 copy, optional I (nt x ldI)
     bem::DeviceBuffer normal, area;         // per-triangle geometry for the right-hand side
     bem::DeviceBuffer dof_ptr, dof_tri, dof_c;  // dof -> triangle CSR
     bem::DeviceBuffer tri_ptr, tri_dof, tri_corner, tri_c;  // triangle -> dof CSR
     // scratch of the multi-column product: transposed right-hand sides (ldw x 16, FP64-sized) and
     // per-split partial sums (16 splits x 16 columns x ldw).  Calls on one problem must not overlap.
     bem::DeviceBuffer mv_xt, mv_partial;
-    double t_assemble = 0, t_far = 0, t_near = 0, t_contract = 0;
+    double t_assemble = 0, t_far = 0, t_near = 0, t_contract = 0, t_host = 0;
     int64_t bytes = 0;
 };
 
 namespace bem {
 
 // assembly (assemble.hip)
-void assemble_device(bem_problem* p, const NearList& near);
+// Assembles W for the mesh (V, T).  analyse(near) runs on the host while the far-field pass is on
+// the device: it must fill p->topo (and the near list) or throw the mesh's validation error.
+void assemble_device(bem_problem* p, const double* V, int64_t nv, const int32_t* T, int64_t nt,
+                     const std::function<void(NearList&)>& analyse);
 void rhs_device(const bem_problem* p, const double* d_g, int k, double* d_L, hipStream_t s);
 void jump_values_device(const bem_problem* p, const double* d_phi, double* d_jump, hipStream_t s);
 

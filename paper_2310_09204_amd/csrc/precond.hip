@@ -207,35 +207,52 @@ __global__ __launch_bounds__(256) void k_trtri_diag(const int4* __restrict__ tas
     tile_store(Y, X + off, m.npad);
 }
 
-// --- off-diagonal tiles of L^{-1}, row i: X_ij = -X_ii sum_{m=j}^{i-1} L_im X_mj -------------
-__global__ __launch_bounds__(256) void k_trtri_row(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
-                                                   const double* __restrict__ A, double* __restrict__ X, int i) {
+// --- off-diagonal tiles of X = L^{-1}, right-looking: X_ij accumulates S_ij = sum_{m<i} L_im X_mj
+//     as soon as each X_mj is final; at step i the row is finished with X_ij = -X_ii S_ij ---------
+__global__ __launch_bounds__(256) void k_trtri_finish(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
+                                                      double* __restrict__ X, int i) {
     __shared__ double P[TBK * LDT];
     __shared__ double Q[TBK * LDT];
     const int4 t = tasks[blockIdx.x];
     const BlockMeta m = meta[t.x];
     const int j = t.y;
-    const double* a0 = A + m.mat_off;
     double* x0 = X + m.mat_off;
+    tile_load(P, x0 + int64_t(i) * TBK * m.npad + int64_t(i) * TBK, m.npad);
+    tile_load(Q, x0 + int64_t(i) * TBK * m.npad + int64_t(j) * TBK, m.npad);
+    __syncthreads();
     double acc[4][4];
     acc_zero(acc);
-    for (int mm = j; mm < i; ++mm) {
-        tile_load(P, a0 + int64_t(i) * TBK * m.npad + int64_t(mm) * TBK, m.npad);
-        tile_load(Q, x0 + int64_t(mm) * TBK * m.npad + int64_t(j) * TBK, m.npad);
-        __syncthreads();
-        tile_mac<false, false>(acc, P, Q);
-        __syncthreads();
-    }
-    acc_to_lds(acc, Q, 1.0);
-    tile_load(P, x0 + int64_t(i) * TBK * m.npad + int64_t(i) * TBK, m.npad);
+    tile_mac<false, false>(acc, P, Q);
     __syncthreads();
-    double acc2[4][4];
-    acc_zero(acc2);
-    tile_mac<false, false>(acc2, P, Q);
-    __syncthreads();
-    acc_to_lds(acc2, P, -1.0);
+    acc_to_lds(acc, P, -1.0);
     __syncthreads();
     tile_store(P, x0 + int64_t(i) * TBK * m.npad + int64_t(j) * TBK, m.npad);
+}
+
+// S_{i'j} += L_{i'i} X_ij for all i' > i, j <= i (tasks carry i', j)
+__global__ __launch_bounds__(256) void k_trtri_update(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
+                                                      const double* __restrict__ A, double* __restrict__ X, int i) {
+    __shared__ double P[TBK * LDT];
+    __shared__ double Q[TBK * LDT];
+    const int4 t = tasks[blockIdx.x];
+    const BlockMeta m = meta[t.x];
+    const int ip = t.y, j = t.z;
+    tile_load(P, A + m.mat_off + int64_t(ip) * TBK * m.npad + int64_t(i) * TBK, m.npad);
+    tile_load(Q, X + m.mat_off + int64_t(i) * TBK * m.npad + int64_t(j) * TBK, m.npad);
+    __syncthreads();
+    double acc[4][4];
+    acc_zero(acc);
+    tile_mac<false, false>(acc, P, Q);
+    double* g = X + m.mat_off + int64_t(ip) * TBK * m.npad + int64_t(j) * TBK;
+    const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) g[int64_t(tr * 4 + a) * m.npad + tc * 4 + b] += acc[a][b];
+}
+
+__global__ void k_zero(double* __restrict__ a, int64_t n) {
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) a[i] = 0.0;
 }
 
 // --- B = X^T X (lower tiles computed, mirrored), written over A ------------------------------
@@ -276,21 +293,32 @@ __global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, in
 }
 
 // --- coarse Galerkin matrix: Y = W R_H^T, then W_H = R_H Y (upper half, mirrored) ------------
-// Y[j][i] = sum_e R[i][e] W[j][col_e]: one block per fine row j (the row stays in cache), threads
-// over coarse dofs
-__global__ __launch_bounds__(256) void k_coarse_Y(const double* __restrict__ W, int64_t ldw, int64_t N,
+// Z = R_H W, one coarse dof per blockIdx.y and a 1024-column slice per blockIdx.x: the block sums
+// the W rows of the coarse function's fine support, weighted by R_H, with coalesced row reads.
+// (W is symmetric, so Z^T = W R_H^T.)
+__global__ __launch_bounds__(256) void k_coarse_Z(const double* __restrict__ W, int64_t ldw, int64_t N,
                                                   const int64_t* __restrict__ rp, const int32_t* __restrict__ rc,
-                                                  const double* __restrict__ rv, int64_t nH, double* __restrict__ Y) {
-    const int64_t j = blockIdx.x;
-    const double* w = W + j * ldw;
-    for (int64_t i = threadIdx.x; i < nH; i += blockDim.x) {
-        double s = 0.0;
-        for (int64_t e = rp[i]; e < rp[i + 1]; ++e) s = fma(rv[e], w[rc[e]], s);
-        Y[j * nH + i] = s;
+                                                  const double* __restrict__ rv, double* __restrict__ Z) {
+    const int64_t i = blockIdx.y;
+    const int64_t c0 = int64_t(blockIdx.x) * 1024 + threadIdx.x;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+        const double v = rv[e];
+        const double* w = W + int64_t(rc[e]) * ldw;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t c = c0 + 256 * u;
+            if (c < N) acc[u] = fma(v, w[c], acc[u]);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int64_t c = c0 + 256 * u;
+        if (c < N) Z[i * N + c] = acc[u];
     }
 }
 
-__global__ void k_coarse_WH(const double* __restrict__ Y, int64_t nH, const int64_t* __restrict__ rp,
+__global__ void k_coarse_WH(const double* __restrict__ Z, int64_t N, int64_t nH, const int64_t* __restrict__ rp,
                             const int32_t* __restrict__ rc, const double* __restrict__ rv, double* __restrict__ A,
                             int64_t npad) {
     const int64_t i2 = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
@@ -301,8 +329,10 @@ __global__ void k_coarse_WH(const double* __restrict__ Y, int64_t nH, const int6
         return;
     }
     if (i2 < i1) return;
+    // W_H[i1][i2] = sum_e R[i2][e] Z[i1][col_e]
     double s = 0.0;
-    for (int64_t e = rp[i1]; e < rp[i1 + 1]; ++e) s = fma(rv[e], Y[int64_t(rc[e]) * nH + i2], s);
+    const double* z = Z + i1 * N;
+    for (int64_t e = rp[i2]; e < rp[i2 + 1]; ++e) s = fma(rv[e], z[rc[e]], s);
     A[i1 * npad + i2] = s;
     A[i2 * npad + i1] = s;
 }
@@ -590,27 +620,88 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
     DeviceBuffer dflags(sizeof(int) * std::max<int64_t>(nall, 1));
     HIP_CHECK(hipMemsetAsync(dflags.ptr, 0, sizeof(int) * std::max<int64_t>(nall, 1), s));
 
-    auto launch_tasks = [&](const std::vector<int4>& tl, auto&& fn) {
-        if (tl.empty()) return;
-        DeviceBuffer dt = upload(tl, s);
-        fn(dt.as<int4>(), unsigned(tl.size()));
-        HIP_CHECK(hipGetLastError());
-        HIP_CHECK(hipStreamSynchronize(s));   // keeps dt alive until the launch has finished
-    };
     const BlockMeta* dm = M->blk_meta.as<BlockMeta>();
 
-    // gather face / wire-basket blocks
+    // ---- every tile task of the set-up, planned on the host and uploaded once ------------------
+    enum Kind { GATHER, POTRF, TRSM, UPDATE, TRTRI_DIAG, TRTRI_FINISH, TRTRI_UPDATE, SYRK };
+    struct Launch { Kind kind; int param; int64_t off, n; };
+    std::vector<int4> all;
+    std::vector<Launch> plan;
+    auto add = [&](Kind kind, int param, const std::vector<int4>& tl) {
+        if (tl.empty()) return;
+        plan.push_back({kind, param, int64_t(all.size()), int64_t(tl.size())});
+        all.insert(all.end(), tl.begin(), tl.end());
+    };
+    std::vector<int> ntile(nall);
+    int maxT = 0;
+    for (int64_t b = 0; b < nall; ++b) {
+        ntile[b] = int(meta[b].npad / TBK);
+        maxT = std::max(maxT, ntile[b]);
+    }
     {
         std::vector<int4> tl;
-        for (int64_t b = 0; b < M->nblocks; ++b) {
-            const int nt = int(meta[b].npad / TBK);
-            for (int i = 0; i < nt; ++i)
-                for (int j = 0; j < nt; ++j) tl.push_back(make_int4(int(b), i, j, 0));
-        }
-        launch_tasks(tl, [&](const int4* d, unsigned n) {
-            hipLaunchKernelGGL(k_gather, dim3(n), dim3(256), 0, s, d, dm, M->idx.as<int32_t>(), p->W64.as<double>(), p->ldw, A.as<double>());
-        });
+        for (int64_t b = 0; b < M->nblocks; ++b)
+            for (int i = 0; i < ntile[b]; ++i)
+                for (int j = 0; j < ntile[b]; ++j) tl.push_back(make_int4(int(b), i, j, 0));
+        add(GATHER, 0, tl);
     }
+    for (int k = 0; k < maxT; ++k) {   // right-looking tiled Cholesky
+        std::vector<int4> tp, tt, tu;
+        for (int64_t b = 0; b < nall; ++b) {
+            if (k >= ntile[b]) continue;
+            tp.push_back(make_int4(int(b), k, k, 0));
+            for (int i = k + 1; i < ntile[b]; ++i) {
+                tt.push_back(make_int4(int(b), i, k, 0));
+                for (int j = k + 1; j <= i; ++j) tu.push_back(make_int4(int(b), i, j, 0));
+            }
+        }
+        add(POTRF, k, tp);
+        add(TRSM, k, tt);
+        add(UPDATE, k, tu);
+    }
+    {
+        std::vector<int4> td;
+        for (int64_t b = 0; b < nall; ++b)
+            for (int i = 0; i < ntile[b]; ++i) td.push_back(make_int4(int(b), i, 0, 0));
+        add(TRTRI_DIAG, 0, td);
+    }
+    for (int i = 0; i < maxT; ++i) {   // X = L^{-1}, right-looking
+        std::vector<int4> tf, tu;
+        for (int64_t b = 0; b < nall; ++b) {
+            if (i >= ntile[b]) continue;
+            for (int j = 0; j < i; ++j) tf.push_back(make_int4(int(b), j, 0, 0));
+            for (int ip = i + 1; ip < ntile[b]; ++ip)
+                for (int j = 0; j <= i; ++j) tu.push_back(make_int4(int(b), ip, j, 0));
+        }
+        add(TRTRI_FINISH, i, tf);
+        add(TRTRI_UPDATE, i, tu);
+    }
+    {
+        std::vector<int4> ts;
+        for (int64_t b = 0; b < nall; ++b)
+            for (int i = 0; i < ntile[b]; ++i)
+                for (int j = 0; j <= i; ++j) ts.push_back(make_int4(int(b), i, j, 0));
+        add(SYRK, 0, ts);
+    }
+    DeviceBuffer dtasks = upload(all, s);
+    const int4* T0 = dtasks.as<int4>();
+    auto run = [&](const Launch& L) {
+        const int4* d = T0 + L.off;
+        const dim3 g(unsigned(L.n)), bl(256);
+        switch (L.kind) {
+            case GATHER: hipLaunchKernelGGL(k_gather, g, bl, 0, s, d, dm, M->idx.as<int32_t>(), p->W64.as<double>(), p->ldw, A.as<double>()); break;
+            case POTRF: hipLaunchKernelGGL(k_potrf, g, bl, 0, s, d, dm, A.as<double>(), L.param, dflags.as<int>()); break;
+            case TRSM: hipLaunchKernelGGL(k_trsm, g, bl, 0, s, d, dm, A.as<double>(), L.param); break;
+            case UPDATE: hipLaunchKernelGGL(k_update, g, bl, 0, s, d, dm, A.as<double>(), L.param); break;
+            case TRTRI_DIAG: hipLaunchKernelGGL(k_trtri_diag, g, bl, 0, s, d, dm, A.as<double>(), X.as<double>()); break;
+            case TRTRI_FINISH: hipLaunchKernelGGL(k_trtri_finish, g, bl, 0, s, d, dm, X.as<double>(), L.param); break;
+            case TRTRI_UPDATE: hipLaunchKernelGGL(k_trtri_update, g, bl, 0, s, d, dm, A.as<double>(), X.as<double>(), L.param); break;
+            case SYRK: hipLaunchKernelGGL(k_syrk_inverse, g, bl, 0, s, d, dm, X.as<double>(), A.as<double>()); break;
+        }
+        HIP_CHECK(hipGetLastError());
+    };
+    size_t li = 0;
+    if (li < plan.size() && plan[li].kind == GATHER) run(plan[li++]);
     // coarse Galerkin block
     if (M->nH > 0) {
         M->rh_ptr = upload(R.ptr, s);
@@ -632,13 +723,13 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
         M->rht_ptr = upload(tp, s);
         M->rht_row = upload(trow, s);
         M->rht_val = upload(tval, s);
-        DeviceBuffer Y(sizeof(double) * std::max<int64_t>(1, f.N * M->nH));
-        hipLaunchKernelGGL(k_coarse_Y, dim3(unsigned(f.N)), dim3(256), 0, s, p->W64.as<double>(), p->ldw, f.N,
-                           M->rh_ptr.as<int64_t>(), M->rh_col.as<int32_t>(), M->rh_val.as<double>(), M->nH, Y.as<double>());
+        DeviceBuffer Z(sizeof(double) * std::max<int64_t>(1, f.N * M->nH));
+        hipLaunchKernelGGL(k_coarse_Z, dim3(nblk(f.N, 1024), unsigned(M->nH)), dim3(256), 0, s, p->W64.as<double>(), p->ldw, f.N,
+                           M->rh_ptr.as<int64_t>(), M->rh_col.as<int32_t>(), M->rh_val.as<double>(), Z.as<double>());
         HIP_CHECK(hipGetLastError());
         const BlockMeta& cm = meta[nall - 1];
         double* Ac = A.as<double>() + cm.mat_off;
-        hipLaunchKernelGGL(k_coarse_WH, dim3(nblk(cm.npad, 256), unsigned(M->nH)), dim3(256), 0, s, Y.as<double>(), M->nH,
+        hipLaunchKernelGGL(k_coarse_WH, dim3(nblk(cm.npad, 256), unsigned(M->nH)), dim3(256), 0, s, Z.as<double>(), f.N, M->nH,
                            M->rh_ptr.as<int64_t>(), M->rh_col.as<int32_t>(), M->rh_val.as<double>(), Ac, cm.npad);
         HIP_CHECK(hipGetLastError());
         if (cm.npad > M->nH) {
@@ -648,64 +739,15 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
         HIP_CHECK(hipStreamSynchronize(s));
     }
 
-    // ---- tiled Cholesky, all blocks together ---------------------------------------------------
-    int maxT = 0;
-    for (int64_t b = 0; b < nall; ++b) maxT = std::max<int>(maxT, int(meta[b].npad / TBK));
-    for (int k = 0; k < maxT; ++k) {
-        std::vector<int4> tp, tt, tu;
-        for (int64_t b = 0; b < nall; ++b) {
-            const int nt = int(meta[b].npad / TBK);
-            if (k >= nt) continue;
-            tp.push_back(make_int4(int(b), k, k, 0));
-            for (int i = k + 1; i < nt; ++i) {
-                tt.push_back(make_int4(int(b), i, k, 0));
-                for (int j = k + 1; j <= i; ++j) tu.push_back(make_int4(int(b), i, j, 0));
-            }
-        }
-        launch_tasks(tp, [&](const int4* d, unsigned n) {
-            hipLaunchKernelGGL(k_potrf, dim3(n), dim3(256), 0, s, d, dm, A.as<double>(), k, dflags.as<int>());
-        });
-        launch_tasks(tt, [&](const int4* d, unsigned n) {
-            hipLaunchKernelGGL(k_trsm, dim3(n), dim3(256), 0, s, d, dm, A.as<double>(), k);
-        });
-        launch_tasks(tu, [&](const int4* d, unsigned n) {
-            hipLaunchKernelGGL(k_update, dim3(n), dim3(256), 0, s, d, dm, A.as<double>(), k);
-        });
-    }
+    // off-diagonal tiles of X accumulate partial sums: start from zero
+    hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, s, X.as<double>(), std::max<int64_t>(moff, 1));
+    HIP_CHECK(hipGetLastError());
+    while (li < plan.size()) run(plan[li++]);
     std::vector<int> flags(nall);
-    HIP_CHECK(hipMemcpy(flags.data(), dflags.ptr, sizeof(int) * nall, hipMemcpyDeviceToHost));
+    HIP_CHECK(hipMemcpyAsync(flags.data(), dflags.ptr, sizeof(int) * nall, hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
     for (int64_t b = 0; b < nall; ++b)
         if (flags[b]) fail(BEM_E_NOT_SPD, "preconditioner block " + std::to_string(b) + " is not positive definite");
-
-    // ---- inverse of the factor, then B = L^{-T} L^{-1} --------------------------------------------
-    {
-        std::vector<int4> td;
-        for (int64_t b = 0; b < nall; ++b)
-            for (int i = 0; i < int(meta[b].npad / TBK); ++i) td.push_back(make_int4(int(b), i, 0, 0));
-        launch_tasks(td, [&](const int4* d, unsigned n) {
-            hipLaunchKernelGGL(k_trtri_diag, dim3(n), dim3(256), 0, s, d, dm, A.as<double>(), X.as<double>());
-        });
-        for (int i = 1; i < maxT; ++i) {
-            std::vector<int4> tr;
-            for (int64_t b = 0; b < nall; ++b) {
-                const int nt = int(meta[b].npad / TBK);
-                if (i >= nt) continue;
-                for (int j = 0; j < i; ++j) tr.push_back(make_int4(int(b), j, 0, 0));
-            }
-            launch_tasks(tr, [&](const int4* d, unsigned n) {
-                hipLaunchKernelGGL(k_trtri_row, dim3(n), dim3(256), 0, s, d, dm, A.as<double>(), X.as<double>(), i);
-            });
-        }
-        std::vector<int4> ts;
-        for (int64_t b = 0; b < nall; ++b) {
-            const int nt = int(meta[b].npad / TBK);
-            for (int i = 0; i < nt; ++i)
-                for (int j = 0; j <= i; ++j) ts.push_back(make_int4(int(b), i, j, 0));
-        }
-        launch_tasks(ts, [&](const int4* d, unsigned n) {
-            hipLaunchKernelGGL(k_syrk_inverse, dim3(n), dim3(256), 0, s, d, dm, X.as<double>(), A.as<double>());
-        });
-    }
     M->inv64 = std::move(A);
     if (M->fp32) {
         M->inv32 = DeviceBuffer(sizeof(float) * std::max<int64_t>(moff, 1));

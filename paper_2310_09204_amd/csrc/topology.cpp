@@ -7,17 +7,19 @@
 // evaluates everything on oriented triangles (T, side); which sides share a sector at a vertex
 // is what the sets alpha_{k,l} (eq. defAlphaij) record.
 //
-// Surface-only construction used here: every (triangle, corner, side) is a node of one global
-// union-find.  Around each edge the incident triangles are ordered by angle; the side of a
-// triangle facing the next triangle is merged with that triangle's side facing back (at both
-// endpoints of the edge); at a free edge the two sides of its triangle are merged.  The classes
-// at a vertex are its sectors.  Because the union keeps the smaller node as root, each root is
-// the smallest member, i.e. the (triangle index, + before -) first side of the sector, which is
-// the canonical label order.
+// Surface-only construction used here, vertex by vertex (vertices are independent, so they are
+// processed on a few host threads): the sides (T, +/-) of the triangles of the vertex star are the
+// nodes of a small union-find.  Around each edge at the vertex the incident triangles are ordered
+// by angle; the side of a triangle facing the next triangle is merged with that triangle's side
+// facing back; at a free edge the two sides of its triangle are merged.  The classes are the
+// sectors.  Because the union keeps the smaller node as root and the star lists triangles in
+// increasing index order, each root is the sector's (triangle index, + before -) first side,
+// which is the canonical label order.
 #include <algorithm>
 #include <array>
 #include <cmath>
 #include <numeric>
+#include <thread>
 
 #include "internal.h"
 
@@ -53,11 +55,23 @@ inline Vec3 cross3(const Vec3& a, const Vec3& b) {
 }
 inline double norm3(const Vec3& a) { return std::sqrt(dot3(a, a)); }
 
-// node ids of the two union-finds
+// index of (triangle, corner, side) in the per-mesh sector table
 inline int64_t side_node(int64_t t, int a, int s) { return (t * 3 + a) * 2 + s; }
-inline int64_t corner_node(int64_t t, int a) { return t * 3 + a; }
 
 }  // namespace
+
+// First failure of a parallel pass, kept by smallest position so the reported error does not depend
+// on thread timing.
+struct FirstFailure {
+    std::mutex mu;
+    int64_t pos = -1;
+    Failure f{0, ""};
+    void record(int64_t where, const Failure& x) {
+        std::lock_guard<std::mutex> lk(mu);
+        if (pos < 0 || where < pos) { pos = where; f = x; }
+    }
+    void rethrow() const { if (pos >= 0) throw f; }
+};
 
 void analyze_mesh(const double* Vin, int64_t nv, const int32_t* Tin, int64_t nt, MeshTopo& m) {
     if (!Vin || !Tin || nv <= 0 || nt <= 0) fail(BEM_E_INVALID_ARG, "empty mesh");
@@ -95,7 +109,7 @@ void analyze_mesh(const double* Vin, int64_t nv, const int32_t* Tin, int64_t nt,
         m.area[t] = 0.5 * tw;
     }
 
-    // ---- repeated vertices (by coordinates) and repeated triangles ------------------------------
+    // ---- repeated vertices (by coordinates) ------------------------------------------------------
     {
         std::vector<char> used(nv, 0);
         for (int64_t i = 0; i < 3 * nt; ++i) used[T[i]] = 1;
@@ -111,130 +125,133 @@ void analyze_mesh(const double* Vin, int64_t nv, const int32_t* Tin, int64_t nt,
             if (V[3 * a] == V[3 * b] && V[3 * a + 1] == V[3 * b + 1] && V[3 * a + 2] == V[3 * b + 2])
                 fail(BEM_E_MESH_NONCONFORMING, "vertices " + std::to_string(a) + " and " + std::to_string(b) + " coincide");
         }
-        std::vector<std::array<int32_t, 3>> tri(nt);
-        for (int64_t t = 0; t < nt; ++t) {
-            tri[t] = {T[3 * t], T[3 * t + 1], T[3 * t + 2]};
-            std::sort(tri[t].begin(), tri[t].end());
-        }
-        std::sort(tri.begin(), tri.end());
-        for (int64_t t = 1; t < nt; ++t)
-            if (tri[t] == tri[t - 1]) fail(BEM_E_MESH_NONCONFORMING, "repeated triangle");
     }
 
-    // ---- edges --------------------------------------------------------------------------------
-    struct EdgeRec { int32_t lo, hi; int32_t t; };
-    std::vector<EdgeRec> edges;
-    edges.reserve(3 * nt);
-    for (int64_t t = 0; t < nt; ++t)
-        for (int a = 0; a < 3; ++a) {
-            int32_t i = T[3 * t + a], j = T[3 * t + (a + 1) % 3];
-            edges.push_back({std::min(i, j), std::max(i, j), int32_t(t)});
-        }
-    std::sort(edges.begin(), edges.end(), [](const EdgeRec& x, const EdgeRec& y) {
-        if (x.lo != y.lo) return x.lo < y.lo;
-        if (x.hi != y.hi) return x.hi < y.hi;
-        return x.t < y.t;
-    });
-
-    auto corner_of = [&](int64_t t, int32_t v) -> int {
+    // ---- vertex stars (counting sort; triangles of a star in increasing index order) -------------
+    std::vector<int64_t> vptr(nv + 1, 0);
+    for (int64_t i = 0; i < 3 * nt; ++i) ++vptr[T[i] + 1];
+    for (int64_t v = 0; v < nv; ++v) vptr[v + 1] += vptr[v];
+    std::vector<int32_t> vtri(3 * nt);
+    {
+        std::vector<int64_t> fill(vptr.begin(), vptr.end() - 1);
+        for (int64_t t = 0; t < nt; ++t)
+            for (int a = 0; a < 3; ++a) vtri[fill[T[3 * t + a]]++] = int32_t(t);
+    }
+    auto corner_of = [&](int64_t t, int64_t v) -> int {
         for (int a = 0; a < 3; ++a) if (T[3 * t + a] == v) return a;
         return -1;
     };
 
-    DisjointSets sides(6 * nt), corners(3 * nt);
-    struct Item { double theta; int32_t t; Vec3 d; };
-    std::vector<Item> fan;
-    for (size_t b = 0; b < edges.size();) {
-        size_t e = b;
-        while (e < edges.size() && edges[e].lo == edges[b].lo && edges[e].hi == edges[b].hi) ++e;
-        const int32_t lo = edges[b].lo, hi = edges[b].hi;
-        const int32_t ends[2] = {lo, hi};
-        for (size_t k = b + 1; k < e; ++k)
-            for (int32_t v : ends) corners.join(corner_node(edges[b].t, corner_of(edges[b].t, v)),
-                                                corner_node(edges[k].t, corner_of(edges[k].t, v)));
-        if (e - b == 1) {
-            int32_t t = edges[b].t;
-            for (int32_t v : ends) {
-                int a = corner_of(t, v);
-                sides.join(side_node(t, a, 0), side_node(t, a, 1));
-            }
-        } else {
-            Vec3 axis = minus(at(V, hi), at(V, lo));
-            double al = norm3(axis);
-            for (auto& c : axis) c /= al;
-            fan.clear();
-            for (size_t k = b; k < e; ++k) {
-                int32_t t = edges[k].t;
-                int32_t third = T[3 * t] + T[3 * t + 1] + T[3 * t + 2] - lo - hi;
-                Vec3 d = minus(at(V, third), at(V, lo));
-                double along = dot3(d, axis);
-                for (int c = 0; c < 3; ++c) d[c] -= along * axis[c];
-                double dn = norm3(d);
-                for (auto& c : d) c /= dn;
-                fan.push_back({0.0, t, d});
-            }
-            const Vec3 b1 = fan[0].d;
-            const Vec3 b2 = cross3(axis, b1);
-            for (auto& it : fan) {
-                double th = std::atan2(dot3(it.d, b2), dot3(it.d, b1));
-                it.theta = th < 0 ? th + 2.0 * M_PI : th;
-            }
-            std::sort(fan.begin(), fan.end(), [](const Item& x, const Item& y) { return x.theta < y.theta; });
-            const size_t nf = fan.size();
-            for (size_t k = 0; k < nf; ++k) {
-                double gap = (k + 1 < nf) ? fan[k + 1].theta - fan[k].theta : fan[0].theta + 2.0 * M_PI - fan[k].theta;
-                if (gap < 1e-9) fail(BEM_E_MESH_NONCONFORMING, "two triangles at edge (" + std::to_string(lo) + "," + std::to_string(hi) + ") lie in the same half-plane");
-            }
-            for (size_t k = 0; k < nf; ++k) {
-                const Item& A = fan[k];
-                const Item& B = fan[(k + 1) % nf];
-                // side facing increasing angle: '+' (0) iff n_T . (axis x d_T) > 0
-                Vec3 na = {m.normal[3 * A.t], m.normal[3 * A.t + 1], m.normal[3 * A.t + 2]};
-                Vec3 nb = {m.normal[3 * B.t], m.normal[3 * B.t + 1], m.normal[3 * B.t + 2]};
-                int inc_a = dot3(na, cross3(axis, A.d)) > 0 ? 0 : 1;
-                int inc_b = dot3(nb, cross3(axis, B.d)) > 0 ? 0 : 1;
-                int dec_b = 1 - inc_b;
-                for (int32_t v : ends)
-                    sides.join(side_node(A.t, corner_of(A.t, v), inc_a), side_node(B.t, corner_of(B.t, v), dec_b));
-            }
-        }
-        b = e;
-    }
-
-    // ---- per-vertex corners (counting sort) -----------------------------------------------------
-    std::vector<int64_t> vptr(nv + 1, 0);
-    for (int64_t i = 0; i < 3 * nt; ++i) ++vptr[T[i] + 1];
-    for (int64_t v = 0; v < nv; ++v) vptr[v + 1] += vptr[v];
-    std::vector<int64_t> vcorner(3 * nt);
-    {
-        std::vector<int64_t> fill(vptr.begin(), vptr.end() - 1);
-        for (int64_t t = 0; t < nt; ++t)
-            for (int a = 0; a < 3; ++a) vcorner[fill[T[3 * t + a]]++] = corner_node(t, a);
-    }
-
+    // ---- sectors, vertex by vertex (independent: only the fans of the vertex's own edges matter) --
     m.q.assign(nv, 0);
     m.sector.assign(6 * nt, -1);
-    std::vector<int64_t> roots;
-    for (int64_t v = 0; v < nv; ++v) {
-        if (vptr[v] == vptr[v + 1]) continue;
-        int64_t r0 = corners.root(vcorner[vptr[v]]);
-        for (int64_t k = vptr[v]; k < vptr[v + 1]; ++k)
-            if (corners.root(vcorner[k]) != r0)
-                fail(BEM_E_POINT_CONTACT, "point contact at vertex " + std::to_string(v));
-        roots.clear();
-        for (int64_t k = vptr[v]; k < vptr[v + 1]; ++k)
-            for (int s = 0; s < 2; ++s) roots.push_back(sides.root(vcorner[k] * 2 + s));
-        std::sort(roots.begin(), roots.end());
-        roots.erase(std::unique(roots.begin(), roots.end()), roots.end());
-        m.q[v] = int32_t(roots.size());
-        for (int64_t k = vptr[v]; k < vptr[v + 1]; ++k) {
-            int64_t c = vcorner[k];
-            for (int s = 0; s < 2; ++s) {
-                int64_t r = sides.root(c * 2 + s);
-                m.sector[c * 2 + s] = int32_t(std::lower_bound(roots.begin(), roots.end(), r) - roots.begin());
+    FirstFailure err;
+    parallel_for(nv, [&](int64_t vb, int64_t ve) {
+        struct EdgeEnd { int32_t w; int32_t lt; };
+        struct Item { double theta; int32_t lt; Vec3 d; };
+        std::vector<EdgeEnd> ends;
+        std::vector<Item> fan;
+        std::vector<int64_t> roots;
+        std::vector<std::array<int32_t, 2>> pairs;
+        for (int64_t v = vb; v < ve; ++v) {
+            const int64_t s0 = vptr[v], ns = vptr[v + 1] - s0;
+            if (ns == 0) continue;
+            try {
+                // repeated triangles meet at their smallest vertex with the same other two vertices
+                pairs.clear();
+                for (int64_t k = 0; k < ns; ++k) {
+                    const int64_t t = vtri[s0 + k];
+                    int32_t o[2], c = 0;
+                    for (int a = 0; a < 3; ++a) if (T[3 * t + a] != v) o[c++] = T[3 * t + a];
+                    if (o[0] > o[1]) std::swap(o[0], o[1]);
+                    pairs.push_back({o[0], o[1]});
+                }
+                {
+                    auto sp = pairs;
+                    std::sort(sp.begin(), sp.end());
+                    for (size_t k = 1; k < sp.size(); ++k)
+                        if (sp[k] == sp[k - 1]) fail(BEM_E_MESH_NONCONFORMING, "repeated triangle");
+                }
+                ends.clear();
+                for (int64_t k = 0; k < ns; ++k) {
+                    ends.push_back({pairs[k][0], int32_t(k)});
+                    ends.push_back({pairs[k][1], int32_t(k)});
+                }
+                std::sort(ends.begin(), ends.end(), [](const EdgeEnd& x, const EdgeEnd& y) {
+                    return x.w != y.w ? x.w < y.w : x.lt < y.lt;
+                });
+                DisjointSets sides(2 * ns), tris(ns);
+                for (size_t b = 0; b < ends.size();) {
+                    size_t e = b;
+                    while (e < ends.size() && ends[e].w == ends[b].w) ++e;
+                    const int64_t w = ends[b].w;
+                    for (size_t k = b + 1; k < e; ++k) tris.join(ends[b].lt, ends[k].lt);
+                    if (e - b == 1) {
+                        sides.join(2 * ends[b].lt, 2 * ends[b].lt + 1);
+                    } else {
+                        Vec3 axis = minus(at(V, w), at(V, v));
+                        const double al = norm3(axis);
+                        for (auto& c : axis) c /= al;
+                        fan.clear();
+                        for (size_t k = b; k < e; ++k) {
+                            const int64_t t = vtri[s0 + ends[k].lt];
+                            const int64_t third = int64_t(T[3 * t]) + T[3 * t + 1] + T[3 * t + 2] - v - w;
+                            Vec3 d = minus(at(V, third), at(V, v));
+                            const double along = dot3(d, axis);
+                            for (int c = 0; c < 3; ++c) d[c] -= along * axis[c];
+                            const double dn = norm3(d);
+                            for (auto& c : d) c /= dn;
+                            fan.push_back({0.0, ends[k].lt, d});
+                        }
+                        const Vec3 b1 = fan[0].d;
+                        const Vec3 b2 = cross3(axis, b1);
+                        for (auto& it : fan) {
+                            const double th = std::atan2(dot3(it.d, b2), dot3(it.d, b1));
+                            it.theta = th < 0 ? th + 2.0 * M_PI : th;
+                        }
+                        std::sort(fan.begin(), fan.end(), [](const Item& x, const Item& y) { return x.theta < y.theta; });
+                        const size_t nf = fan.size();
+                        for (size_t k = 0; k < nf; ++k) {
+                            const double gap = (k + 1 < nf) ? fan[k + 1].theta - fan[k].theta : fan[0].theta + 2.0 * M_PI - fan[k].theta;
+                            if (gap < 1e-9)
+                                fail(BEM_E_MESH_NONCONFORMING, "two triangles at edge (" + std::to_string(std::min<int64_t>(v, w)) + "," +
+                                                                   std::to_string(std::max<int64_t>(v, w)) + ") lie in the same half-plane");
+                        }
+                        for (size_t k = 0; k < nf; ++k) {
+                            const Item& A = fan[k];
+                            const Item& B = fan[(k + 1) % nf];
+                            const int64_t ta = vtri[s0 + A.lt], tb = vtri[s0 + B.lt];
+                            // side facing increasing angle: '+' (0) iff n_T . (axis x d_T) > 0
+                            const Vec3 na = {m.normal[3 * ta], m.normal[3 * ta + 1], m.normal[3 * ta + 2]};
+                            const Vec3 nb = {m.normal[3 * tb], m.normal[3 * tb + 1], m.normal[3 * tb + 2]};
+                            const int inc_a = dot3(na, cross3(axis, A.d)) > 0 ? 0 : 1;
+                            const int inc_b = dot3(nb, cross3(axis, B.d)) > 0 ? 0 : 1;
+                            sides.join(2 * A.lt + inc_a, 2 * B.lt + (1 - inc_b));
+                        }
+                    }
+                    b = e;
+                }
+                for (int64_t k = 1; k < ns; ++k)
+                    if (tris.root(k) != tris.root(0)) fail(BEM_E_POINT_CONTACT, "point contact at vertex " + std::to_string(v));
+                // sectors labelled by their smallest member (local order = triangle index order)
+                roots.clear();
+                for (int64_t k = 0; k < 2 * ns; ++k) roots.push_back(sides.root(k));
+                std::sort(roots.begin(), roots.end());
+                roots.erase(std::unique(roots.begin(), roots.end()), roots.end());
+                m.q[v] = int32_t(roots.size());
+                for (int64_t k = 0; k < ns; ++k) {
+                    const int64_t t = vtri[s0 + k];
+                    const int a = corner_of(t, v);
+                    for (int sd = 0; sd < 2; ++sd)
+                        m.sector[side_node(t, a, sd)] =
+                            int32_t(std::lower_bound(roots.begin(), roots.end(), sides.root(2 * k + sd)) - roots.begin());
+                }
+            } catch (const Failure& f) {
+                err.record(v, f);
             }
         }
-    }
+    });
+    err.rethrow();
 
     // ---- dofs -----------------------------------------------------------------------------------
     m.first_dof.assign(nv + 1, 0);
@@ -250,24 +267,39 @@ void analyze_mesh(const double* Vin, int64_t nv, const int32_t* Tin, int64_t nt,
 
     // ---- jump coefficients: trace of psi_{v,j} on side s at the corner is +1 if the side is in
     //      sector j, -1 if it is in the reference sector q_v - 1, else 0; c = s_+ - s_-  ---------
+    auto coeff = [&](int64_t t, int a, int32_t j) {
+        const int32_t qv = m.q[T[3 * t + a]];
+        const int32_t sp = m.sector[side_node(t, a, 0)], sm = m.sector[side_node(t, a, 1)];
+        return ((sp == j) ? 1 : (sp == qv - 1 ? -1 : 0)) - ((sm == j) ? 1 : (sm == qv - 1 ? -1 : 0));
+    };
     m.tri_ptr.assign(nt + 1, 0);
-    m.tri_dof.clear(); m.tri_corner.clear(); m.tri_c.clear();
-    for (int64_t t = 0; t < nt; ++t) {
-        for (int a = 0; a < 3; ++a) {
-            int32_t v = T[3 * t + a];
-            int32_t qv = m.q[v];
-            int32_t sp = m.sector[side_node(t, a, 0)], sm = m.sector[side_node(t, a, 1)];
-            for (int32_t j = 0; j + 1 < qv; ++j) {
-                int c = ((sp == j) ? 1 : (sp == qv - 1 ? -1 : 0)) - ((sm == j) ? 1 : (sm == qv - 1 ? -1 : 0));
-                if (c == 0) continue;
-                m.tri_dof.push_back(int32_t(m.first_dof[v] + j));
-                m.tri_corner.push_back(int8_t(a));
-                m.tri_c.push_back(int8_t(c));
+    parallel_for(nt, [&](int64_t tb, int64_t te) {
+        for (int64_t t = tb; t < te; ++t) {
+            int64_t cnt = 0;
+            for (int a = 0; a < 3; ++a)
+                for (int32_t j = 0; j + 1 < m.q[T[3 * t + a]]; ++j) cnt += coeff(t, a, j) != 0;
+            m.tri_ptr[t + 1] = cnt;
+        }
+    });
+    for (int64_t t = 0; t < nt; ++t) m.tri_ptr[t + 1] += m.tri_ptr[t];
+    const int64_t ne = m.tri_ptr[nt];
+    m.tri_dof.resize(ne); m.tri_corner.resize(ne); m.tri_c.resize(ne);
+    parallel_for(nt, [&](int64_t tb, int64_t te) {
+        for (int64_t t = tb; t < te; ++t) {
+            int64_t pos = m.tri_ptr[t];
+            for (int a = 0; a < 3; ++a) {
+                const int32_t v = T[3 * t + a];
+                for (int32_t j = 0; j + 1 < m.q[v]; ++j) {
+                    const int c = coeff(t, a, j);
+                    if (c == 0) continue;
+                    m.tri_dof[pos] = int32_t(m.first_dof[v] + j);
+                    m.tri_corner[pos] = int8_t(a);
+                    m.tri_c[pos] = int8_t(c);
+                    ++pos;
+                }
             }
         }
-        m.tri_ptr[t + 1] = int64_t(m.tri_dof.size());
-    }
-    const int64_t ne = int64_t(m.tri_dof.size());
+    });
     m.dof_ptr.assign(m.N + 1, 0);
     for (int64_t e = 0; e < ne; ++e) ++m.dof_ptr[m.tri_dof[e] + 1];
     for (int64_t d = 0; d < m.N; ++d) m.dof_ptr[d + 1] += m.dof_ptr[d];
@@ -297,46 +329,62 @@ void build_near_list(const MeshTopo& m, NearList& out) {
         for (int64_t t = 0; t < nt; ++t)
             for (int a = 0; a < 3; ++a) vtri[fill[T[3 * t + a]]++] = int32_t(t);
     }
-    std::vector<int32_t> cand;
-    for (int64_t t1 = 0; t1 < nt; ++t1) {
-        cand.clear();
-        for (int a = 0; a < 3; ++a) {
-            int32_t v = T[3 * t1 + a];
-            for (int64_t k = vptr[v]; k < vptr[v + 1]; ++k)
-                if (vtri[k] >= t1) cand.push_back(vtri[k]);
-        }
-        std::sort(cand.begin(), cand.end());
-        cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
-        const int32_t* a = &T[3 * t1];
-        for (int32_t t2 : cand) {
-            const int32_t* b = &T[3 * t2];
-            int ia[3], ib[3], ns = 0;
-            for (int i = 0; i < 3; ++i)
-                for (int j = 0; j < 3; ++j)
-                    if (a[i] == b[j]) { ia[ns] = i; ib[ns] = j; ++ns; }
-            int32_t vs[5] = {-1, -1, -1, -1, -1};
-            int8_t type;
-            if (ns == 3) {
-                type = 3;
-                vs[0] = a[0]; vs[1] = a[1]; vs[2] = a[2];
-            } else if (ns == 2) {
-                type = 2;
-                // shared edge A-B in t1's vertex order, then the two opposite vertices
-                vs[0] = a[ia[0]]; vs[1] = a[ia[1]];
-                vs[2] = a[3 - ia[0] - ia[1]];
-                vs[3] = b[3 - ib[0] - ib[1]];
-            } else {
-                type = 1;
-                vs[0] = a[ia[0]];
-                vs[1] = a[(ia[0] + 1) % 3]; vs[2] = a[(ia[0] + 2) % 3];
-                vs[3] = b[(ib[0] + 1) % 3]; vs[4] = b[(ib[0] + 2) % 3];
+    // triangles in chunks of 2048; each chunk fills its own list, joined in chunk order
+    const int64_t csz = 2048;
+    const int64_t nchunk = (nt + csz - 1) / csz;
+    std::vector<NearList> parts(nchunk);
+    parallel_for(nt, [&](int64_t tb, int64_t te) {
+        std::vector<int32_t> cand;
+        for (int64_t c = (tb + csz - 1) / csz; c * csz < te; ++c) {
+            NearList& o = parts[c];
+            for (int64_t t1 = c * csz; t1 < std::min(nt, (c + 1) * csz); ++t1) {
+                cand.clear();
+                for (int a = 0; a < 3; ++a) {
+                    const int32_t v = T[3 * t1 + a];
+                    for (int64_t k = vptr[v]; k < vptr[v + 1]; ++k)
+                        if (vtri[k] >= t1) cand.push_back(vtri[k]);
+                }
+                std::sort(cand.begin(), cand.end());
+                cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+                const int32_t* a = &T[3 * t1];
+                for (int32_t t2 : cand) {
+                    const int32_t* b = &T[3 * t2];
+                    int ia[3], ib[3], ns = 0;
+                    for (int i = 0; i < 3; ++i)
+                        for (int j = 0; j < 3; ++j)
+                            if (a[i] == b[j]) { ia[ns] = i; ib[ns] = j; ++ns; }
+                    int32_t vs[5] = {-1, -1, -1, -1, -1};
+                    int8_t type;
+                    if (ns == 3) {
+                        type = 3;
+                        vs[0] = a[0]; vs[1] = a[1]; vs[2] = a[2];
+                    } else if (ns == 2) {
+                        type = 2;
+                        // shared edge A-B in t1's vertex order, then the two opposite vertices
+                        vs[0] = a[ia[0]]; vs[1] = a[ia[1]];
+                        vs[2] = a[3 - ia[0] - ia[1]];
+                        vs[3] = b[3 - ib[0] - ib[1]];
+                    } else {
+                        type = 1;
+                        vs[0] = a[ia[0]];
+                        vs[1] = a[(ia[0] + 1) % 3]; vs[2] = a[(ia[0] + 2) % 3];
+                        vs[3] = b[(ib[0] + 1) % 3]; vs[4] = b[(ib[0] + 2) % 3];
+                    }
+                    o.t1.push_back(int32_t(t1));
+                    o.t2.push_back(t2);
+                    o.type.push_back(type);
+                    o.verts.insert(o.verts.end(), vs, vs + 5);
+                    ++o.count[type];
+                }
             }
-            out.t1.push_back(int32_t(t1));
-            out.t2.push_back(t2);
-            out.type.push_back(type);
-            out.verts.insert(out.verts.end(), vs, vs + 5);
-            ++out.count[type];
         }
+    });
+    for (auto& o : parts) {
+        out.t1.insert(out.t1.end(), o.t1.begin(), o.t1.end());
+        out.t2.insert(out.t2.end(), o.t2.begin(), o.t2.end());
+        out.type.insert(out.type.end(), o.type.begin(), o.type.end());
+        out.verts.insert(out.verts.end(), o.verts.begin(), o.verts.end());
+        for (int k = 0; k < 4; ++k) out.count[k] += o.count[k];
     }
 }
 

@@ -39,7 +39,8 @@ class ProblemInfo(ctypes.Structure):
     _fields_ = [("n_dofs", ctypes.c_int64), ("n_tri", ctypes.c_int64), ("n_vert", ctypes.c_int64),
                 ("n_near_pairs", ctypes.c_int64), ("bytes_device", ctypes.c_int64),
                 ("q_hist", ctypes.c_int64 * 16), ("t_assemble_s", ctypes.c_double),
-                ("t_far_s", ctypes.c_double), ("t_near_s", ctypes.c_double), ("t_contract_s", ctypes.c_double)]
+                ("t_far_s", ctypes.c_double), ("t_near_s", ctypes.c_double), ("t_contract_s", ctypes.c_double),
+                ("t_host_s", ctypes.c_double)]
 
 
 class PrecondOpts(ctypes.Structure):

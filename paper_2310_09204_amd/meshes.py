@@ -198,6 +198,33 @@ def bowtie(n: int) -> Mesh:
                 np.zeros(nt, bool), [])
 
 
+def fan(m: int, rings: int = 2) -> Mesh:
+    """Unit disk in the plane z=0 meshed by m spokes: every ring k = 1..rings holds m vertices, so the
+    centre vertex sits in m thin triangles (a star far longer than a structured mesh's)."""
+    vlist: List[Tuple[float, float, float]] = [(0.0, 0.0, 0.0)]
+    for k in range(1, rings + 1):
+        r = k / rings
+        for i in range(m):
+            th = 2.0 * math.pi * i / m
+            vlist.append((r * math.cos(th), r * math.sin(th), 0.0))
+
+    def ring(k, i):
+        return 0 if k == 0 else 1 + (k - 1) * m + (i % m)
+
+    tris: List[Tuple[int, int, int]] = []
+    for i in range(m):
+        tris.append((0, ring(1, i), ring(1, i + 1)))
+    for k in range(1, rings):
+        for i in range(m):
+            a0, a1, b0, b1 = ring(k, i), ring(k, i + 1), ring(k + 1, i), ring(k + 1, i + 1)
+            tris.append((a0, b0, b1))
+            tris.append((a0, b1, a1))
+    V = np.asarray(vlist, dtype=np.float64)
+    T = np.asarray(tris, dtype=np.int32)
+    nt = T.shape[0]
+    return Mesh(V, T, np.zeros(nt, np.int32), np.zeros((nt, 2), np.int32), np.zeros(nt, bool), [])
+
+
 def disk(m: int) -> Mesh:
     """Unit disk in the plane z=0: m concentric rings, ring k holding 6k vertices (normal +z)."""
     vlist: List[Tuple[float, float, float]] = [(0.0, 0.0, 0.0)]

@@ -66,6 +66,22 @@ def test_matrix_rhs_jumps(ctx, name):
         assert np.abs(y - x @ Wo).max() <= 1e-12 * np.abs(x @ Wo).max(), k
 
 
+def test_long_star_general_contraction(ctx):
+    # 520 triangles meet at the centre: the first column block's star union exceeds the staged
+    # kernel's capacity (512 triangles), so its tiles take the general contraction; the others are
+    # staged.  Low near order keeps the oracle's 135k vertex-adjacent pairs quick.
+    m = meshes.fan(520)
+    order = 4
+    print("case fan520", m.nt, flush=True)
+    t = Topology(m.vertices, m.triangles)
+    p = lib.Problem(ctx, m.vertices, m.triangles, near_order=order)
+    Wg = p.matrix()
+    Wo = assemble(m.vertices, m.triangles, t, order)
+    assert np.array_equal(Wg, Wg.T)
+    err = np.abs(Wg - Wo).max() / np.abs(Wo).max()
+    assert err < 1e-12, err
+
+
 def test_book48_sampled_rows(ctx):
     w = meshes.workload("book48")
     m = w.mesh

@@ -28,9 +28,11 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
-# algorithmic flops of one far-field kernel evaluation w / |x - y|: 3 subtractions, 3 products and
-# 2 sums for |x-y|^2, 1 reciprocal square root, 1 product and 1 sum for the weighted accumulation
-FLOPS_PER_EVAL = 11
+# algorithmic FP64 flops of one far-field kernel evaluation w / |x - y| as the far kernel issues it
+# (counted in its gfx950 ISA): 3 subtractions, 1 product and 2 FMAs for |x-y|^2, 2 products and 1
+# FMA for the Newton step of the reciprocal square root, 1 FMA into the inner sum, and 1 FMA per
+# 7 evaluations into the outer sum; an FMA counts 2, the v_rsq_f64 estimate is not counted
+FLOPS_PER_EVAL = 14.0 + 2.0 / 7.0
 EVALS_PER_FAR_PAIR = 49
 
 
@@ -120,6 +122,80 @@ def cpu_baseline(w, k, iters, gpu_info, budget_s):
     }
 
 
+def _replay(lib, reqs, ctx, scale, max_inflight):
+    """Submits reqs at t_arrival * scale (scale 0: all at once) and polls them in order."""
+    import threading
+    srv = lib.Server(ctx, max_inflight=max_inflight)
+    tickets = [None] * len(reqs)
+    t0 = time.perf_counter()
+
+    def feeder():
+        for i, r in enumerate(reqs):
+            dt = r.t_arrival * scale - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            tickets[i] = srv.submit(r.mesh.vertices, r.mesh.triangles, r.patch_of_triangle, r.coarse.vertices,
+                                    r.coarse.triangles, r.coarse_of_triangle, r.g,
+                                    precision=lib.FP32_REFINE if r.mixed else lib.FP64, tol=1e-10)
+
+    th = threading.Thread(target=feeder)
+    th.start()
+    results = []
+    for i in range(len(reqs)):
+        while tickets[i] is None:
+            time.sleep(1e-4)
+        results.append(srv.poll(tickets[i]))
+    t_end = time.perf_counter()
+    th.join()
+    stats = srv.stats()
+    srv.close()
+    return results, t_end - t0, stats
+
+
+def serving_leg(lib, meshes, ctx, n_requests, load, seed=0, max_inflight=4):
+    """Seeded Poisson stream of solve requests on random multiscreens (N ~ U[2k, 30k], 1-16 g per
+    request, FP64 or mixed), replayed in real time into the serving loop.
+
+    Capacity is measured first by submitting the whole stream at once; the timed replay then
+    scales the seeded arrival times to `load` x capacity.  Latency is submit -> completion as the
+    server measures it; solves/s counts right-hand sides within rel.err 1e-8 of an FP64 solve of
+    the same request (computed after the stream, not timed)."""
+    reqs = meshes.serving_stream(seed, n_requests, rate=1.0)    # arrival times for rate 1/s
+    _, t_burst, _ = _replay(lib, reqs, ctx, 0.0, max_inflight)
+    capacity = n_requests / t_burst                              # requests/s
+    rate = load * capacity
+    results, t_run, stats = _replay(lib, reqs, ctx, 1.0 / rate, max_inflight)
+    solved, total, worst = 0, 0, 0.0
+    by_geo = {}
+    for r, res in zip(reqs, results):
+        by_geo.setdefault(r.geometry, []).append((r, res))
+    for items in by_geo.values():
+        r0 = items[0][0]
+        p = lib.Problem(ctx, r0.mesh.vertices, r0.mesh.triangles)
+        M = lib.Preconditioner(p, r0.patch_of_triangle, r0.coarse.vertices, r0.coarse.triangles,
+                               r0.coarse_of_triangle)
+        for r, (phi, info, rc) in items:
+            ref, _, _ = p.solve(g=r.g, precond=M, tol=1e-13)
+            err = np.linalg.norm(phi - ref, axis=1) / np.linalg.norm(ref, axis=1)
+            solved += int((err <= 1e-8).sum())
+            total += r.g.shape[0]
+            worst = max(worst, float(err.max()))
+        M.close()
+        p.close()
+    lat = sorted(info[0]["t_total_s"] for (_, info, _) in results)
+    n_dofs = [int(res[0].shape[1]) for res in results]
+    return {
+        "requests": len(reqs), "rhs": total, "rhs_within_1e-8": solved, "relerr_max": worst,
+        "capacity_requests_per_s": capacity, "load": load, "arrival_rate_per_s": rate,
+        "max_inflight": max_inflight,
+        "solves_per_s": solved / t_run,
+        "latency_s": {"p50": lat[len(lat) // 2], "p99": lat[min(len(lat) - 1, int(round(0.99 * (len(lat) - 1))))]},
+        "n_dofs_range": [min(n_dofs), max(n_dofs)],
+        "mixed_requests": int(sum(r.mixed for r in reqs)),
+        "server": stats,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,11 +208,28 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--serve-requests", type=int, default=24,
+                    help="requests in the serving-stream leg (0 skips it)")
+    ap.add_argument("--serve-load", type=float, default=0.7,
+                    help="arrival rate of the serving leg as a fraction of its measured capacity")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy 1 GiB device-to-device three times (the reference launch that scales "
+                         "rocprofv3 FETCH_SIZE / WRITE_SIZE readings to bytes) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported (the multi-GPU "
               "design is described, not built)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        import torch
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "device-to-device copy", "bytes_read": src.numel() * 8,
+                          "bytes_written": dst.numel() * 8, "launches": 3}))
+        return
 
     from paper_2310_09204_amd import lib, meshes
 
@@ -240,7 +333,7 @@ def main():
         "unit": "TFLOP/s",
         "frac": round(far_tflops / PEAK_FP64_TFLOPS, 4),
         "traffic": load_traffic("k_far", args.workload),
-        "per_launch": "%d far pairs x %d evaluations x %d flops" % (far_pairs, EVALS_PER_FAR_PAIR, FLOPS_PER_EVAL),
+        "per_launch": "%d far pairs x %d evaluations x %.4f flops" % (far_pairs, EVALS_PER_FAR_PAIR, FLOPS_PER_EVAL),
         "avg_launch_s": t_far,
     }
     out = {
@@ -274,6 +367,9 @@ def main():
         "matvec": mv,
         "fp64_compare": fp64_step,
     }
+    if args.serve_requests > 0:
+        log("bench: serving stream (%d requests, load %.2f)" % (args.serve_requests, args.serve_load))
+        out["serving"] = serving_leg(lib, meshes, ctx, args.serve_requests, args.serve_load)
     if not args.no_cpu_baseline:
         log("bench: oracle on host cores (bounded sample)")
         out["cpu_baseline"] = cpu_baseline(w, args.k, int(np.mean(res[-1]["iters"])), pinfo, args.cpu_seconds)

@@ -108,7 +108,7 @@ __global__ __launch_bounds__(256) void k_far(const double* __restrict__ geo, int
         px[p] = g[3 * p];
         py[p] = g[3 * p + 1];
         pz[p] = g[3 * p + 2];
-        pw[p] = g[21 + p];
+        pw[p] = 0.5 * g[21 + p];   // the 1/2 of the Newton step below, folded into the weight (exact)
     }
     const int c0 = cb * kTile;
     const int c1 = min(c0 + kTile, nt);
@@ -131,7 +131,9 @@ __global__ __launch_bounds__(256) void k_far(const double* __restrict__ geo, int
                     for (int p = 0; p < 7; ++p) {
                         const double dx = px[p] - yx, dy = py[p] - yy, dz = pz[p] - yz;
                         const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-                        sacc = fma(pw[p], rsqrt_refined(r2), sacc);
+                        // 1/r = y (3 - r2 y^2) / 2 after one Newton step from the hardware estimate y
+                        const double y = __builtin_amdgcn_rsq(r2);
+                        sacc = fma(pw[p] * y, fma(-r2, y * y, 3.0), sacc);
                     }
                     acc = fma(h[21 + q], sacc, acc);
                 }

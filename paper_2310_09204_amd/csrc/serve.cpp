@@ -19,6 +19,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <new>
 #include <thread>
 
 #include "internal.h"
@@ -41,6 +42,7 @@ struct Request {
     Clock::time_point t_submit, t_done;
     bool done = false;
     int rc = BEM_OK;
+    std::string err;              // message of a failed request, handed to the polling thread
     std::vector<double> phi;
     std::vector<bem_solve_info> info;
 };
@@ -208,6 +210,10 @@ void worker_main(bem_server* s) {
             rc = f.code;
             err = f.msg;
             for (Request* r : batch) r->rc = rc;
+        } catch (const std::bad_alloc&) {
+            rc = BEM_E_OOM;
+            err = "host allocation failed";
+            for (Request* r : batch) r->rc = rc;
         }
         {
             std::lock_guard<std::mutex> lk(s->mu);
@@ -222,6 +228,7 @@ void worker_main(bem_server* s) {
             for (Request* r : batch) {
                 r->t_done = now;
                 r->done = true;
+                if (r->rc < 0) r->err = err.empty() ? "request failed" : err;
                 const double lat = std::chrono::duration<double>(r->t_done - r->t_submit).count();
                 for (auto& in : r->info) in.t_total_s = lat;
                 if (r->info.empty()) {
@@ -234,7 +241,6 @@ void worker_main(bem_server* s) {
             s->stats.resident_bytes = res;
             s->stats.peak_resident_bytes = std::max(s->stats.peak_resident_bytes, res);
         }
-        if (!err.empty()) set_last_error(err);
         s->cv_done.notify_all();
         s->cv_work.notify_all();
     }
@@ -359,6 +365,7 @@ int bem_serve_poll(bem_server* s, uint64_t ticket, int64_t timeout_us, double* p
     if (phi_out && !r->phi.empty()) std::memcpy(phi_out, r->phi.data(), sizeof(double) * r->phi.size());
     if (info) std::memcpy(info, r->info.data(), sizeof(bem_solve_info) * r->info.size());
     const int rc = r->rc;
+    if (rc < 0) set_last_error(r->err);
     s->requests.erase(it);
     delete r;
     return rc;

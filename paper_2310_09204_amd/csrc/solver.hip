@@ -16,6 +16,7 @@
 
 #include "internal.h"
 #include "strips.h"
+#include <type_traits>
 
 namespace bem {
 
@@ -98,25 +99,59 @@ __global__ void k_transpose_x(const double* __restrict__ x, int64_t ldx, int kc,
     xt[e] = (n < kc && j < N) ? MT(x[int64_t(n) * ldx + j]) : MT(0);
 }
 
+// Y = W X for up to 16 columns on the matrix cores.  A block owns 64 rows of W and a range of
+// columns (split-K over blockIdx.y).  Per tile of TC columns (256 bytes of each row), every wave
+// loads 16 of the 64 rows with 16 lanes on one row's contiguous 256 bytes, so each load
+// instruction reads four whole row segments; the tile and the matching X tile (TC x 16, from the
+// transposed right-hand sides) go to LDS, and wave w then runs the TC/4 MFMAs of rows 16w .. 16w+15
+// from LDS.  Two LDS buffers: the next tile's loads are in flight while the current one is used,
+// one barrier per tile.  Results go to y directly (one split) or to per-split partial sums.
 template <typename MT>
 __global__ __launch_bounds__(256) void k_matvec_mfma(const MT* __restrict__ W, int64_t ldw, int64_t N,
                                                      const MT* __restrict__ xt, int64_t cols_per_split, int kc,
                                                      double* __restrict__ y, int64_t ldy, MT* __restrict__ partial) {
     using MC = MatrixCore<MT>;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    using V16 = typename std::conditional<sizeof(MT) == 4, float4, double2>::type;
+    constexpr int VEC = 16 / sizeof(MT);
+    constexpr int TC = 256 / sizeof(MT);
+    __shared__ MT tA[2][64][TC + VEC];
+    __shared__ MT tX[2][TC * 16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int i = lane & 15, kg = lane >> 4;
-    const int64_t row0 = (int64_t(blockIdx.x) * 4 + wave) * 16;
-    if (row0 >= N) return;
-    const int64_t row = row0 + i;
+    const int64_t row0 = int64_t(blockIdx.x) * 64;
     const int split = blockIdx.y;
     const int64_t c0 = int64_t(split) * cols_per_split;
     const int64_t c1 = min<int64_t>(ldw, c0 + cols_per_split);
+    const int lr = tid >> 4;           // row of a 16-row load group
+    const int lc = (tid & 15) * VEC;   // column within the tile
     typename MC::V acc = {0, 0, 0, 0};
-    strip_mfma<MT, 8>(W + (row < N ? row : row0) * ldw, row < N, c0, c1, xt, acc);
+    V16 va[4], vx;
+    auto fetch = [&](int64_t jc) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t row = row0 + q * 16 + lr;
+            if (row < N) va[q] = *reinterpret_cast<const V16*>(W + row * ldw + jc + lc);
+            else va[q] = V16{};
+        }
+        vx = reinterpret_cast<const V16*>(xt + jc * 16)[tid];
+    };
+    if (c0 < c1) fetch(c0);
+    int buf = 0;
+    for (int64_t jc = c0; jc < c1; jc += TC) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) *reinterpret_cast<V16*>(&tA[buf][q * 16 + lr][lc]) = va[q];
+        reinterpret_cast<V16*>(&tX[buf][0])[tid] = vx;
+        __syncthreads();
+        if (jc + TC < c1) fetch(jc + TC);
+#pragma unroll
+        for (int st = 0; st < TC / 4; ++st)
+            acc = MC::mac(tA[buf][wave * 16 + i][4 * st + kg], tX[buf][(4 * st + kg) * 16 + i], acc);
+        buf ^= 1;
+    }
     if (i < kc) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int64_t rr = row0 + MC::out_row(kg, r);
+            const int64_t rr = row0 + wave * 16 + MC::out_row(kg, r);
             if (rr < N) {
                 if (partial) partial[(int64_t(split) * 16 + i) * ldw + rr] = acc[r];
                 else y[int64_t(i) * ldy + rr] = double(acc[r]);
@@ -326,13 +361,17 @@ void launch_matvec(const bem_problem* p, const MT* W, const double* x, int64_t l
         MT* xt = static_cast<MT*>(p->mv_xt.ptr);
         MT* part = static_cast<MT*>(p->mv_partial.ptr);
         hipLaunchKernelGGL(k_transpose_x<MT>, dim3(unsigned((ldw * 16 + 255) / 256)), dim3(256), 0, s, xc, ldx, kc, N, ldw, xt);
-        // split the columns so that about eight waves per SIMD stream W
-        const int64_t strips = (N + 15) / 16;
-        int S = int(std::min<int64_t>(kMaxSplits, std::max<int64_t>(1, (8 * 1024 + strips - 1) / strips)));
-        const int64_t quantum = 128;      // a multiple of the columns one unrolled step covers
+        // split the columns when there are too few 64-row blocks to keep every CU streaming
+        const int64_t blocks = (N + 63) / 64;
+        int S = 1;
+        if (blocks < 1500) {
+            S = 4;
+            while (S < kMaxSplits && blocks * S < 3000) S *= 2;
+        }
+        const int64_t quantum = 256 / int64_t(sizeof(MT));   // one LDS tile of columns
         const int64_t cps = ((ldw + S - 1) / S + quantum - 1) / quantum * quantum;
         S = int((ldw + cps - 1) / cps);
-        dim3 grid(unsigned((N + 63) / 64), unsigned(S));
+        const dim3 grid{unsigned(blocks), unsigned(S), 1u};
         hipLaunchKernelGGL(k_matvec_mfma<MT>, grid, dim3(256), 0, s, W, ldw, N, xt, cps, kc, yc, ldy, S > 1 ? part : nullptr);
         if (S > 1)
             hipLaunchKernelGGL(k_reduce_splits<MT>, dim3(unsigned((int64_t(kc) * N + 255) / 256)), dim3(256), 0, s, part, S, kc, N,

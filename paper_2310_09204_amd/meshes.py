@@ -535,3 +535,57 @@ def workload(name: str, seed: int = 0, k: int = 1) -> Workload:
     else:
         raise KeyError(name)
     return Workload(name, m, patches, cm, par, g, desc)
+
+
+# ----------------------------------------------------------------------------------------------
+# Serving stream: seeded Poisson arrivals of solve requests on random multiscreens
+# ----------------------------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class ServeRequest:
+    t_arrival: float              # seconds after the start of the stream
+    geometry: int                 # index of the geometry (requests on one geometry share it)
+    mesh: Mesh
+    patch_of_triangle: np.ndarray
+    coarse: Mesh
+    coarse_of_triangle: np.ndarray
+    g: np.ndarray                 # (k, 3) unit vectors
+    mixed: bool                   # FP32 matrix + FP64 refinement, else plain FP64
+
+
+def serving_stream(seed: int, n_requests: int, rate: float, n_range: Tuple[int, int] = (2000, 30000),
+                   k_range: Tuple[int, int] = (1, 16), cells_per_patch: int = 15,
+                   reuse: float = 0.5) -> List[ServeRequest]:
+    """Requests arriving as a Poisson process of the given rate (per second).
+
+    Each new geometry is 1-6 unit squares joined at shared edges (book, chain or tree layout,
+    dihedral angles uniform in [30, 330] deg) with m x m square patches of cells_per_patch cells
+    per panel, m chosen so that the dof count is near a target drawn uniformly from n_range, and a
+    nested coarse mesh with one coarse cell per patch.  With probability ``reuse`` a request
+    reuses an earlier geometry (new right-hand sides on a resident problem).  Each request has
+    k ~ U{k_range} random unit g and is FP64 or mixed precision with equal probability.
+    """
+    rng = np.random.default_rng(seed)
+    geos: List[Tuple[Mesh, np.ndarray, Mesh, np.ndarray]] = []
+    out: List[ServeRequest] = []
+    t = 0.0
+    c = cells_per_patch
+    for _ in range(n_requests):
+        t += float(rng.exponential(1.0 / rate))
+        if geos and rng.uniform() < reuse:
+            gi = int(rng.integers(0, len(geos)))
+        else:
+            n_sq = int(rng.integers(1, 7))
+            layout = str(rng.choice(["book", "chain", "tree"]))
+            target = float(rng.uniform(*n_range))
+            m_side = max(2, int(round(math.sqrt(target / n_sq) / c)))
+            mesh, _ = random_extruded(rng, n_sq, layout, c * m_side)
+            cm, par = coarse_mesh(mesh, c)
+            geos.append((mesh, grid_patches(mesh, c), cm, par))
+            gi = len(geos) - 1
+        mesh, patches, cm, par = geos[gi]
+        k = int(rng.integers(k_range[0], k_range[1] + 1))
+        g = rng.standard_normal((k, 3))
+        g /= np.linalg.norm(g, axis=1, keepdims=True)
+        out.append(ServeRequest(t, gi, mesh, patches, cm, par, g, bool(rng.integers(0, 2))))
+    return out

@@ -84,7 +84,8 @@ typedef struct {
     int max_iter;            /* total (P)CG iterations per column (default 2000) */
     int use_precond;         /* 0: plain CG even if a preconditioner is passed */
     bem_precision precision; /* BEM_FP32_REFINE: FP32 matrix/factors inside FP64 refinement */
-    double inner_tol;        /* relative tolerance of each inner FP32 solve (default 1e-6) */
+    double refresh_factor;   /* mixed precision: replace the recurrence residual by the FP64 residual
+                              * b - W x each time it has fallen by this factor (default 1e-3) */
     int check_every;         /* iterations between host convergence checks (default 4) */
     int use_graph;           /* 1: replay one captured iteration with hipGraphLaunch */
 } bem_solve_opts;
@@ -171,9 +172,11 @@ int bem_precond_apply(const bem_precond* m, const double* r, int32_t k, double* 
 /* ---- solve (Remark "Bound on the number of Preconditioned Conjugate Gradient iterations") -- */
 /* Solves W Phi = L for k constant Neumann vectors g[k][3] by (P)CG with x0 = 0 (or opts->x0),
  * preconditioned by M if m != NULL and opts->use_precond.  FP64 mode: W, vectors and factors in
- * FP64.  BEM_FP32_REFINE: iterative refinement, residuals r = L - W x with the FP64 matrix, each
- * correction from a PCG on the FP32 matrix and FP32 block inverses (FP64 dots, vector updates and
- * coarse solve), until ||r|| <= tol ||L||.  phi_out[k][N] column-major.  Returns BEM_OK,
+ * FP64.  BEM_FP32_REFINE: PCG with products by the FP32 matrix and FP32 block inverses (FP64
+ * vectors, dots, updates and coarse solve) and reliable updates: the recurrence residual is replaced
+ * by the true residual L - W x with the FP64 matrix each time it has fallen by refresh_factor, and
+ * a column counts as converged only when a true residual satisfies ||r|| <= tol ||L||
+ * (info.outer_iters = number of replacements).  phi_out[k][N] column-major.  Returns BEM_OK,
  * BEM_E_NOT_CONVERGED or BEM_E_BREAKDOWN (outputs written in all three cases). */
 int bem_pcg_solve(bem_problem* p, const bem_precond* m, const double* g, int32_t k,
                   const bem_solve_opts* opts, double* phi_out, bem_solve_info* info);

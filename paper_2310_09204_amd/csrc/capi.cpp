@@ -79,7 +79,7 @@ bem_solve_opts default_solve_opts() {
     o.max_iter = 2000;
     o.use_precond = 1;
     o.precision = BEM_FP64;
-    o.inner_tol = 1e-6;
+    o.refresh_factor = 1e-3;
     o.check_every = 4;
     o.use_graph = 1;
     return o;

@@ -381,35 +381,22 @@ __global__ __launch_bounds__(256) void k_block_apply(const int4* __restrict__ ta
     }
 }
 
-// one block per coarse dof: threads stride over its fine entries, block sums per column
+// (R_H r)[i][c]: one block per (coarse dof i, column c); threads stride over the fine entries of row
+// i of R_H, block sum in a fixed order
 __global__ __launch_bounds__(256) void k_restrict(const int64_t* __restrict__ rp, const int32_t* __restrict__ rc,
                                                   const double* __restrict__ rv, int64_t nH,
-                                                  const double* __restrict__ r, int64_t ld, int k,
+                                                  const double* __restrict__ r, int64_t ld,
                                                   double* __restrict__ out) {
-    __shared__ double red[4][16];
+    __shared__ double red[4];
     const int64_t i = blockIdx.x;
-    double acc[16];
-#pragma unroll
-    for (int c = 0; c < 16; ++c) acc[c] = 0.0;
-    for (int64_t e = rp[i] + threadIdx.x; e < rp[i + 1]; e += blockDim.x) {
-        const double v = rv[e];
-        const int64_t col = rc[e];
-#pragma unroll
-        for (int c = 0; c < 16; ++c)
-            if (c < k) acc[c] = fma(v, r[int64_t(c) * ld + col], acc[c]);
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int c = 0; c < 16; ++c) {
-        double v = acc[c];
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        if (lane == 0) red[wave][c] = v;
-    }
+    const int c = blockIdx.y;
+    const double* rcol = r + int64_t(c) * ld;
+    double acc = 0.0;
+    for (int64_t e = rp[i] + threadIdx.x; e < rp[i + 1]; e += blockDim.x) acc = fma(rv[e], rcol[rc[e]], acc);
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
     __syncthreads();
-    if (threadIdx.x < k) {
-        const int c = threadIdx.x;
-        out[int64_t(c) * nH + i] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
-    }
+    if (threadIdx.x == 0) out[int64_t(c) * nH + i] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // y = Binv x for the coarse block: one wave per row, lanes over columns
@@ -436,16 +423,17 @@ __global__ __launch_bounds__(256) void k_coarse_solve(const double* __restrict__
     }
 }
 
+// z[c] += R_H^T zc[c]: one thread per (fine dof, column), grid (N / 256, columns)
 __global__ void k_prolong_add(const int64_t* __restrict__ tp, const int32_t* __restrict__ tr, const double* __restrict__ tv,
-                              int64_t N, const double* __restrict__ zc, int64_t nH, int k, double* __restrict__ z,
+                              int64_t N, const double* __restrict__ zc, int64_t nH, double* __restrict__ z,
                               int64_t ld) {
     const int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    const int c = blockIdx.y;
     if (j >= N) return;
-    for (int c = 0; c < k; ++c) {
-        double s = 0.0;
-        for (int64_t e = tp[j]; e < tp[j + 1]; ++e) s = fma(tv[e], zc[int64_t(c) * nH + tr[e]], s);
-        z[int64_t(c) * ld + j] += s;
-    }
+    const double* u = zc + int64_t(c) * nH;
+    double s = 0.0;
+    for (int64_t e = tp[j]; e < tp[j + 1]; ++e) s = fma(tv[e], u[tr[e]], s);
+    z[int64_t(c) * ld + j] += s;
 }
 
 inline unsigned nblk(int64_t n, int per) { return unsigned((n + per - 1) / per); }
@@ -799,13 +787,13 @@ void precond_apply_device(const bem_precond* M, bool fp32, const double* r, int6
             const int64_t nH = M->nH;
             double* rcoarse = scratch;
             double* zcoarse = scratch + nH * kc;
-            hipLaunchKernelGGL(k_restrict, dim3(unsigned(nH)), dim3(256), 0, s, M->rh_ptr.as<int64_t>(), M->rh_col.as<int32_t>(),
-                               M->rh_val.as<double>(), nH, rc, ld, kc, rcoarse);
+            hipLaunchKernelGGL(k_restrict, dim3(unsigned(nH), unsigned(kc)), dim3(256), 0, s, M->rh_ptr.as<int64_t>(),
+                               M->rh_col.as<int32_t>(), M->rh_val.as<double>(), nH, rc, ld, rcoarse);
             const int64_t cb = M->nblocks;
             const double* Binv = M->inv64.as<double>() + M->blk_mat_off[cb];
             hipLaunchKernelGGL(k_coarse_solve, dim3(nblk(nH, 4)), dim3(256), 0, s, Binv, M->blk_npad[cb], nH, rcoarse, kc, zcoarse);
-            hipLaunchKernelGGL(k_prolong_add, dim3(nblk(p->N, 256)), dim3(256), 0, s, M->rht_ptr.as<int64_t>(), M->rht_row.as<int32_t>(),
-                               M->rht_val.as<double>(), p->N, zcoarse, nH, kc, zc, ld);
+            hipLaunchKernelGGL(k_prolong_add, dim3(nblk(p->N, 256), unsigned(kc)), dim3(256), 0, s, M->rht_ptr.as<int64_t>(),
+                               M->rht_row.as<int32_t>(), M->rht_val.as<double>(), p->N, zcoarse, nH, zc, ld);
             HIP_CHECK(hipGetLastError());
         }
     }

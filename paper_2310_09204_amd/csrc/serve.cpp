@@ -186,7 +186,7 @@ void worker_main(bem_server* s) {
             o.max_iter = 2000;
             o.use_precond = 1;
             o.precision = r0->precision;
-            o.inner_tol = 1e-6;
+            o.refresh_factor = 1e-3;
             o.check_every = 4;
             o.use_graph = 1;
             const int64_t N = entry->problem->N;

@@ -22,9 +22,12 @@ namespace bem {
 
 namespace {
 
+// Per-column scalars of the block (P)CG, kept on the device.  `near` marks a column whose recurrence
+// residual has reached the tolerance but still awaits confirmation by a true residual; `refreshes`
+// counts the FP64 residual replacements of the mixed-precision iteration.
 struct ColState {
     double rz, pq, rr, alpha, beta, bb, tol2, pad;
-    int active, iters, flag, pad2;
+    int active, iters, flag, near, refreshes, pad2;
 };
 
 constexpr int kStatBreakdown = 2;
@@ -248,7 +251,11 @@ __global__ __launch_bounds__(256) void k_update_xr(double* __restrict__ x, doubl
     if (threadIdx.x == 0) partial[int64_t(c) * gridDim.x + blockIdx.x] = acc;
 }
 
-__global__ __launch_bounds__(256) void k_check(const double* __restrict__ partial, int G, ColState* __restrict__ st) {
+// rr from block partials.  true_res = 1: rr is the true residual of x (FP64 iteration, or a residual
+// replacement of the mixed one) and decides convergence; true_res = 0: rr is the FP32-driven
+// recurrence residual, which only marks the column `near` so that the host schedules a replacement.
+__global__ __launch_bounds__(256) void k_check(const double* __restrict__ partial, int G, ColState* __restrict__ st,
+                                               int true_res, int refresh) {
     const int c = blockIdx.x;
     const double rr = reduce_partials(partial + int64_t(c) * G, G);
     if (threadIdx.x == 0) {
@@ -256,11 +263,15 @@ __global__ __launch_bounds__(256) void k_check(const double* __restrict__ partia
         if (s.active) {
             s.iters += 1;
             s.rr = rr;
+            s.refreshes += refresh;
             if (!isfinite(rr)) {
                 s.active = 0;
                 s.flag = kStatBreakdown;
             } else if (rr <= s.tol2 * s.bb) {
-                s.active = 0;
+                if (true_res) s.active = 0;
+                else s.near = 1;
+            } else if (true_res) {
+                s.near = 0;
             }
         }
     }
@@ -310,6 +321,26 @@ __global__ void k_residual(const double* __restrict__ b, const double* __restric
         r[int64_t(c) * ld + i] = b[int64_t(c) * ld + i] - y[int64_t(c) * ld + i];
 }
 
+// r = b - y for the active columns, with the partial sums of r.r (as k_update_xr leaves them)
+__global__ __launch_bounds__(256) void k_residual_active(const double* __restrict__ b, const double* __restrict__ y,
+                                                         double* __restrict__ r, int64_t ld, int64_t N,
+                                                         const ColState* __restrict__ st, double* __restrict__ partial) {
+    const int c = blockIdx.y;
+    double acc = 0.0;
+    if (st[c].active) {
+        const double* bc = b + int64_t(c) * ld;
+        const double* yc = y + int64_t(c) * ld;
+        double* rc = r + int64_t(c) * ld;
+        for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < N; i += int64_t(gridDim.x) * 256) {
+            const double ri = bc[i] - yc[i];
+            rc[i] = ri;
+            acc = fma(ri, ri, acc);
+        }
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partial[int64_t(c) * gridDim.x + blockIdx.x] = acc;
+}
+
 __global__ void k_axpy_cols(double* __restrict__ x, const double* __restrict__ d, int64_t ld, int64_t N) {
     const int c = blockIdx.y;
     for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < N; i += int64_t(gridDim.x) * 256)
@@ -332,6 +363,8 @@ __global__ __launch_bounds__(256) void k_init_state(const double* __restrict__ p
         s.tol2 = tol2[c];
         s.iters = 0;
         s.flag = 0;
+        s.near = 0;
+        s.refreshes = 0;
         if (!isfinite(bb) || !isfinite(rr) || !isfinite(rz)) {
             s.active = 0;
             s.flag = kStatBreakdown;
@@ -436,16 +469,24 @@ void matvec_device(const bem_problem* p, bool fp32, const double* d_x, int64_t l
 // receives the result.  Per-column tolerance tol[c] on ||r|| / ||b||.
 // ---------------------------------------------------------------------------------------------
 struct PcgResult {
-    std::vector<int> iters, flag, active;
+    std::vector<int> iters, flag, active, refreshes;
     std::vector<double> rr, bb, cond;
 };
 
-PcgResult pcg_device(bem_problem* p, const bem_precond* M, bool fp32, const double* b, double* x, bool x_nonzero,
+// Block (P)CG on device buffers.  b, x: [k][ld]; x is the start vector (zero it for x0 = 0) and
+// receives the result; per-column tolerance tol[c] on ||r|| / ||b||.
+// mixed = false: FP64 matrix and factors; the recurrence residual decides convergence.
+// mixed = true: products with the FP32 matrix and FP32 block inverses (FP64 vectors, dots and coarse
+// solve), with reliable updates: the recurrence residual is replaced by the true residual
+// b - W x with the FP64 matrix whenever it has fallen by `refresh` since the last replacement, and
+// before any column is declared converged, so convergence is always judged on a true residual.
+PcgResult pcg_device(bem_problem* p, const bem_precond* M, bool mixed, const double* b, double* x, bool x_nonzero,
                      int k, int64_t ld, const std::vector<double>& tol, int max_iter, int check_every, bool use_graph,
-                     bool want_cond) {
+                     bool want_cond, double refresh) {
     hipStream_t s = p->stream;
     const int64_t N = p->N;
     const unsigned G = gblocks(N);
+    const bool fp32 = mixed;
     DeviceBuffer r(sizeof(double) * ld * k), z(sizeof(double) * ld * k), pp(sizeof(double) * ld * k), q(sizeof(double) * ld * k);
     DeviceBuffer part(sizeof(double) * G * k * 3), dst(sizeof(ColState) * k), dtol(sizeof(double) * k);
     const int max_hist = want_cond ? std::max(1, max_iter) : 1;
@@ -468,7 +509,7 @@ PcgResult pcg_device(bem_problem* p, const bem_precond* M, bool fp32, const doub
 
     // ---- initial state ----
     if (x_nonzero) {
-        matvec(x, q.as<double>());
+        matvec_device(p, false, x, ld, k, q.as<double>(), s);
         hipLaunchKernelGGL(k_residual, vg, vb, 0, s, b, q.as<double>(), r.as<double>(), ld, N);
     } else {
         hipLaunchKernelGGL(k_copy, vg, vb, 0, s, b, r.as<double>(), ld, N);
@@ -483,12 +524,18 @@ PcgResult pcg_device(bem_problem* p, const bem_precond* M, bool fp32, const doub
 
     ColState* st = dst.as<ColState>();
     double* h = hist.as<double>();
-    auto iteration = [&]() {
+    // one (P)CG iteration; with replace, the residual is recomputed as b - W x in FP64 after the
+    // update of x (q is free by then and holds W x)
+    auto iteration = [&](bool replace) {
         matvec(pp.as<double>(), q.as<double>());
         hipLaunchKernelGGL(k_dot_partial, vg, vb, 0, s, pp.as<double>(), q.as<double>(), ld, N, pa);
         hipLaunchKernelGGL(k_alpha, dim3(k), vb, 0, s, pa, int(G), st, h, max_hist);
         hipLaunchKernelGGL(k_update_xr, vg, vb, 0, s, x, r.as<double>(), pp.as<double>(), q.as<double>(), ld, N, st, pb);
-        hipLaunchKernelGGL(k_check, dim3(k), vb, 0, s, pb, int(G), st);
+        if (replace) {
+            matvec_device(p, false, x, ld, k, q.as<double>(), s);
+            hipLaunchKernelGGL(k_residual_active, vg, vb, 0, s, b, q.as<double>(), r.as<double>(), ld, N, st, pb);
+        }
+        hipLaunchKernelGGL(k_check, dim3(k), vb, 0, s, pb, int(G), st, (!mixed || replace) ? 1 : 0, replace ? 1 : 0);
         apply_M(r.as<double>(), z.as<double>());
         hipLaunchKernelGGL(k_dot_partial, vg, vb, 0, s, r.as<double>(), z.as<double>(), ld, N, pc);
         hipLaunchKernelGGL(k_beta, dim3(k), vb, 0, s, pc, int(G), st, h, max_hist);
@@ -496,38 +543,58 @@ PcgResult pcg_device(bem_problem* p, const bem_precond* M, bool fp32, const doub
         HIP_CHECK(hipGetLastError());
     };
 
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
     if (use_graph) {
-        HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        iteration();
-        HIP_CHECK(hipStreamEndCapture(s, &graph));
-        HIP_CHECK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        for (int v = 0; v < (mixed ? 2 : 1); ++v) {
+            HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            iteration(v == 1);
+            HIP_CHECK(hipStreamEndCapture(s, &graph[v]));
+            HIP_CHECK(hipGraphInstantiate(&exec[v], graph[v], nullptr, nullptr, 0));
+        }
     }
+    auto launch = [&](bool replace) {
+        if (use_graph) HIP_CHECK(hipGraphLaunch(exec[replace ? 1 : 0], s));
+        else iteration(replace);
+    };
     std::vector<ColState> hs(k);
     int launched = 0;
     const int every = std::max(1, check_every);
     HIP_CHECK(hipMemcpyAsync(hs.data(), st, sizeof(ColState) * k, hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
+    std::vector<double> rr_ref(k);
+    for (int c = 0; c < k; ++c) rr_ref[c] = hs[c].rr;
+    const double refresh2 = refresh * refresh;
     auto any_active = [&]() {
         for (auto& c : hs) if (c.active) return true;
         return false;
     };
     while (any_active() && launched < max_iter) {
-        const int n = std::min(every, max_iter - launched);
-        for (int i = 0; i < n; ++i) {
-            if (use_graph) HIP_CHECK(hipGraphLaunch(exec, s));
-            else iteration();
-        }
+        // mixed: replace the residual now if a column may have converged (then check right after)
+        // or if a column's residual has fallen by `refresh` since its last replacement
+        bool near = false, fallen = false;
+        if (mixed)
+            for (int c = 0; c < k; ++c)
+                if (hs[c].active) {
+                    near = near || hs[c].near;
+                    fallen = fallen || hs[c].rr < refresh2 * rr_ref[c];
+                }
+        const int n = near ? 1 : std::min(every, max_iter - launched);
+        for (int i = 0; i < n; ++i) launch(i == 0 && (near || fallen));
         launched += n;
         HIP_CHECK(hipMemcpyAsync(hs.data(), st, sizeof(ColState) * k, hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
+        if (near || fallen)
+            for (int c = 0; c < k; ++c) rr_ref[c] = hs[c].rr;
     }
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
+    for (int v = 0; v < 2; ++v) {
+        if (exec[v]) (void)hipGraphExecDestroy(exec[v]);
+        if (graph[v]) (void)hipGraphDestroy(graph[v]);
+    }
 
     PcgResult res;
     res.iters.resize(k); res.flag.resize(k); res.active.resize(k); res.rr.resize(k); res.bb.resize(k); res.cond.assign(k, std::nan(""));
+    res.refreshes.resize(k);
     std::vector<double> hh;
     if (want_cond) {
         hh.resize(size_t(2) * max_hist * k);
@@ -539,6 +606,7 @@ PcgResult pcg_device(bem_problem* p, const bem_precond* M, bool fp32, const doub
         res.active[c] = hs[c].active;
         res.rr[c] = hs[c].rr;
         res.bb[c] = hs[c].bb;
+        res.refreshes[c] = hs[c].refreshes;
         if (want_cond && hs[c].iters > 0 && !hs[c].flag) {
             const int m = std::min(hs[c].iters, max_hist);
             res.cond[c] = lanczos_condition(&hh[size_t(c) * 2 * max_hist], &hh[size_t(c) * 2 * max_hist + max_hist], m);
@@ -564,9 +632,11 @@ void solve_device(bem_problem* p, const bem_precond* M, const double* b, double*
     std::vector<double> relres(k, 0.0), cond(k, std::nan(""));
 
     hipLaunchKernelGGL(k_fill, dim3(256), vb, 0, s, x, 0.0, int64_t(k) * ld);
+    bool final_check = true;
     if (o.precision == BEM_FP64) {
         std::vector<double> tol(k, o.tol);
-        PcgResult r = pcg_device(p, use_m ? M : nullptr, false, b, x, false, k, ld, tol, o.max_iter, check, o.use_graph != 0, true);
+        PcgResult r = pcg_device(p, use_m ? M : nullptr, false, b, x, false, k, ld, tol, o.max_iter, check, o.use_graph != 0, true,
+                                 0.0);
         for (int c = 0; c < k; ++c) {
             iters[c] = r.iters[c];
             cond[c] = r.cond[c];
@@ -576,61 +646,24 @@ void solve_device(bem_problem* p, const bem_precond* M, const double* b, double*
     } else {
         if (!p->W32.ptr) fail(BEM_E_INVALID_ARG, "mixed precision needs a problem assembled with BEM_FP32_REFINE");
         if (use_m && !M->inv32.ptr) fail(BEM_E_INVALID_ARG, "mixed precision needs a preconditioner with factor_fp32 = 1");
-        DeviceBuffer r(sizeof(double) * ld * k), y(sizeof(double) * ld * k), dlt(sizeof(double) * ld * k);
-        DeviceBuffer part(sizeof(double) * G * k * 2);
-        std::vector<double> bb(k), rr(k);
-        std::vector<double> hp(size_t(G) * k);
-        auto norms = [&](const double* a, std::vector<double>& out) {
-            hipLaunchKernelGGL(k_dot_partial, vg, vb, 0, s, a, a, ld, N, part.as<double>());
-            HIP_CHECK(hipMemcpyAsync(hp.data(), part.ptr, sizeof(double) * G * k, hipMemcpyDeviceToHost, s));
-            HIP_CHECK(hipStreamSynchronize(s));
-            for (int c = 0; c < k; ++c) {
-                double acc = 0;
-                for (unsigned g = 0; g < G; ++g) acc += hp[size_t(c) * G + g];
-                out[c] = acc;
-            }
-        };
-        norms(b, bb);
-        std::vector<char> done(k, 0);
-        const int max_outer = 30;
-        for (int it = 0; it < max_outer; ++it) {
-            // FP64 residual r = b - W x
-            matvec_device(p, false, x, ld, k, y.as<double>(), s);
-            hipLaunchKernelGGL(k_residual, vg, vb, 0, s, b, y.as<double>(), r.as<double>(), ld, N);
-            norms(r.as<double>(), rr);
-            bool all = true;
-            std::vector<double> tol(k);
-            for (int c = 0; c < k; ++c) {
-                if (!done[c]) outer[c] += 1;
-                relres[c] = bb[c] > 0 ? std::sqrt(rr[c] / bb[c]) : 0.0;
-                if (!std::isfinite(relres[c])) { status[c] = BEM_E_BREAKDOWN; done[c] = 1; }
-                if (relres[c] <= o.tol || iters[c] >= o.max_iter) done[c] = 1;
-                if (!done[c]) all = false;
-                // inner target: the requested inner tolerance, but no tighter than the remaining gap
-                tol[c] = done[c] ? 1.0 : std::max(o.inner_tol > 0 ? o.inner_tol : 1e-6, 0.5 * o.tol / std::max(relres[c], 1e-300));
-            }
-            if (all) break;
-            // columns already done get a zero right-hand side (inactive from the start)
-            for (int c = 0; c < k; ++c)
-                if (done[c]) hipLaunchKernelGGL(k_fill, dim3(64), vb, 0, s, r.as<double>() + int64_t(c) * ld, 0.0, N);
-            hipLaunchKernelGGL(k_fill, dim3(256), vb, 0, s, dlt.as<double>(), 0.0, int64_t(k) * ld);
-            int budget = o.max_iter;
-            for (int c = 0; c < k; ++c) if (!done[c]) budget = std::min(budget, std::max(1, o.max_iter - iters[c]));
-            PcgResult pr = pcg_device(p, use_m ? M : nullptr, true, r.as<double>(), dlt.as<double>(), false, k, ld, tol, budget,
-                                      check, o.use_graph != 0, it == 0);
-            for (int c = 0; c < k; ++c) {
-                if (done[c]) continue;
-                iters[c] += pr.iters[c];
-                if (it == 0) cond[c] = pr.cond[c];
-                if (pr.flag[c]) { status[c] = BEM_E_BREAKDOWN; done[c] = 1; }
-            }
-            hipLaunchKernelGGL(k_axpy_cols, vg, vb, 0, s, x, dlt.as<double>(), ld, N);
+        std::vector<double> tol(k, o.tol);
+        const double refresh = (o.refresh_factor > 0 && o.refresh_factor < 1) ? o.refresh_factor : 1e-3;
+        PcgResult r = pcg_device(p, use_m ? M : nullptr, true, b, x, false, k, ld, tol, o.max_iter, check, o.use_graph != 0, true,
+                                 refresh);
+        final_check = false;
+        for (int c = 0; c < k; ++c) {
+            iters[c] = r.iters[c];
+            outer[c] = r.refreshes[c];
+            cond[c] = r.cond[c];
+            // a converged column stopped on a true FP64 residual: its relres is already exact
+            relres[c] = r.bb[c] > 0 ? std::sqrt(r.rr[c] / r.bb[c]) : 0.0;
+            if (r.flag[c]) status[c] = BEM_E_BREAKDOWN;
+            else if (r.active[c]) status[c] = BEM_E_NOT_CONVERGED;
+            if (status[c] != BEM_OK) final_check = true;
         }
-        for (int c = 0; c < k; ++c)
-            if (status[c] == BEM_OK && relres[c] > o.tol) status[c] = BEM_E_NOT_CONVERGED;
     }
     // true FP64 residual of the result
-    {
+    if (final_check) {
         DeviceBuffer y(sizeof(double) * ld * k), r(sizeof(double) * ld * k), part(sizeof(double) * G * k * 2);
         matvec_device(p, false, x, ld, k, y.as<double>(), s);
         hipLaunchKernelGGL(k_residual, vg, vb, 0, s, b, y.as<double>(), r.as<double>(), ld, N);

@@ -49,7 +49,7 @@ class PrecondOpts(ctypes.Structure):
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("use_precond", ctypes.c_int),
-                ("precision", ctypes.c_int), ("inner_tol", ctypes.c_double), ("check_every", ctypes.c_int),
+                ("precision", ctypes.c_int), ("refresh_factor", ctypes.c_double), ("check_every", ctypes.c_int),
                 ("use_graph", ctypes.c_int)]
 
 
@@ -261,9 +261,9 @@ class Problem:
         return out
 
     def solve(self, g=None, rhs=None, precond=None, tol=1e-10, max_iter=2000, use_precond=True,
-              precision=FP64, inner_tol=1e-6, check_every=4, use_graph=True, raise_on_error=True):
+              precision=FP64, refresh_factor=1e-3, check_every=4, use_graph=True, raise_on_error=True):
         """Returns (phi[k][N], [info dict per column], status code)."""
-        o = SolveOpts(tol, max_iter, int(use_precond), precision, inner_tol, check_every, int(use_graph))
+        o = SolveOpts(tol, max_iter, int(use_precond), precision, refresh_factor, check_every, int(use_graph))
         L = load()
         m = precond.handle if precond is not None else None
         if g is not None:

@@ -100,7 +100,7 @@ def test_mixed_precision_reaches_1e8(ctx, name):
     t, W, P = _oracle(w)
     L = rhs(t, w.g)[:, 0]
     xs = cholesky_solve(W, L)
-    phi, info, rc = p.solve(g=w.g, precond=M, tol=1e-11, precision=lib.FP32_REFINE, inner_tol=1e-5)
+    phi, info, rc = p.solve(g=w.g, precond=M, tol=1e-11, precision=lib.FP32_REFINE, refresh_factor=1e-2)
     assert rc == 0
     assert info[0]["outer_iters"] >= 2
     err = np.linalg.norm(phi[0] - xs) / np.linalg.norm(xs)
@@ -121,6 +121,22 @@ def test_failure_paths(ctx):
     # zero right-hand side: zero solution, no iterations
     phi, info, rc = p.solve(rhs=np.zeros((1, p.N)), precond=M)
     assert rc == 0 and info[0]["iters"] == 0 and not phi.any()
+
+
+def test_failure_paths_mixed(ctx):
+    w = small_workloads()["square16"]
+    p, M = _setup(ctx, w, precision=lib.FP32_REFINE)
+    mixed = dict(precond=M, precision=lib.FP32_REFINE, raise_on_error=False)
+    phi, info, rc = p.solve(g=np.array([[np.nan, 0.0, 1.0]]), **mixed)
+    assert lib.ERRORS[rc] == "BEM_E_BREAKDOWN"
+    phi, info, rc = p.solve(g=w.g, max_iter=1, **mixed)
+    assert lib.ERRORS[rc] == "BEM_E_NOT_CONVERGED" and info[0]["iters"] == 1 and np.isfinite(phi).all()
+    # the reported residual is the true FP64 one and meets the tolerance
+    phi, info, rc = p.solve(g=w.g, tol=1e-10, **mixed)
+    assert rc == 0 and info[0]["relres"] <= 1e-10
+    W = p.matrix()
+    L = p.rhs(w.g)[0]
+    assert np.linalg.norm(L - W @ phi[0]) / np.linalg.norm(L) <= 1.01e-10
 
 
 def test_book48_full_size(ctx):

@@ -675,13 +675,13 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
     triangle7_rule(bary, w7);
     std::vector<double> hb(&bary[0][0], &bary[0][0] + 21), hw(w7, w7 + 7);
 
-    DeviceBuffer dV(sizeof(double) * 3 * nv), dT(sizeof(int32_t) * 3 * nt);
+    DeviceBuffer dV(sizeof(double) * 3 * nv, s), dT(sizeof(int32_t) * 3 * nt, s);
     HIP_CHECK(hipMemcpyAsync(dV.ptr, Vin, dV.bytes, hipMemcpyHostToDevice, s));
     HIP_CHECK(hipMemcpyAsync(dT.ptr, Tin, dT.bytes, hipMemcpyHostToDevice, s));
     DeviceBuffer db = upload(hb, s), dw = upload(hw, s);
-    DeviceBuffer geo(sizeof(double) * nt * kGeo);
-    p->normal = DeviceBuffer(sizeof(double) * nt * 3);
-    p->area = DeviceBuffer(sizeof(double) * nt);
+    DeviceBuffer geo(sizeof(double) * nt * kGeo, s);
+    p->normal = DeviceBuffer(sizeof(double) * nt * 3, s);
+    p->area = DeviceBuffer(sizeof(double) * nt, s);
     hipLaunchKernelGGL(k_geometry, dim3(blocks_for(nt, 256)), dim3(256), 0, s, dV.as<double>(), dT.as<int32_t>(), nt,
                        db.as<double>(), dw.as<double>(), geo.as<double>(), p->normal.as<double>(), p->area.as<double>());
     HIP_CHECK(hipGetLastError());
@@ -689,7 +689,7 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
     // pair integrals I (nt x ldI), rows padded to 64 bytes so the far kernel's paired stores stay aligned
     const int64_t ldI = (nt + 7) / 8 * 8;
     p->ldI = ldI;
-    p->I = DeviceBuffer(sizeof(double) * nt * ldI);
+    p->I = DeviceBuffer(sizeof(double) * nt * ldI, s);
     const int nb = int((nt + kTile - 1) / kTile);
     std::vector<int2> tiles;
     tiles.reserve(size_t(nb) * (nb + 1) / 2);
@@ -742,7 +742,7 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
     p->tri_corner = upload(m.tri_corner, s);
     p->tri_c = upload(m.tri_c, s);
     const int64_t ne = int64_t(m.dof_tri.size());
-    DeviceBuffer dofJ(sizeof(double) * 3 * std::max<int64_t>(ne, 1));
+    DeviceBuffer dofJ(sizeof(double) * 3 * std::max<int64_t>(ne, 1), s);
     if (ne > 0) {
         hipLaunchKernelGGL(k_jump_vectors, dim3(blocks_for(ne, 256)), dim3(256), 0, s, dV.as<double>(), dT.as<int32_t>(),
                            p->dof_tri.as<int32_t>(), dof_corner.as<int8_t>(), p->dof_c.as<int8_t>(), p->area.as<double>(), ne,
@@ -779,7 +779,7 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
     mark("near");
     // contraction into W; every entry of W, padding columns included, is written by one tile
     p->ldw = ((N + 63) / 64) * 64;
-    p->W64 = DeviceBuffer(sizeof(double) * std::max<int64_t>(N, 1) * p->ldw);
+    p->W64 = DeviceBuffer(sizeof(double) * std::max<int64_t>(N, 1) * p->ldw, s);
     EventTimer t_contract(s);
     if (N > 0) {
         DeviceBuffer d_cb_ptr = upload(plan.cb_ptr, s), d_cb_tri = upload(plan.cb_tri, s);
@@ -805,16 +805,15 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
     t_contract.stop();
     mark("contract");
     if (p->has_w32) {
-        p->W32 = DeviceBuffer(sizeof(float) * std::max<int64_t>(N, 1) * p->ldw);
+        p->W32 = DeviceBuffer(sizeof(float) * std::max<int64_t>(N, 1) * p->ldw, s);
         hipLaunchKernelGGL(k_f64_to_f32, dim3(4096), dim3(256), 0, s, p->W64.as<double>(), p->W32.as<float>(), N * p->ldw);
         HIP_CHECK(hipGetLastError());
     }
     mark("fp32 copy");
-    if (!p->has_pairs) p->I.reset();
-    mark("free I");
-    p->mv_xt = DeviceBuffer(sizeof(double) * 16 * p->ldw);
-    p->mv_partial = DeviceBuffer(sizeof(double) * 16 * 16 * p->ldw);
+    p->mv_xt = DeviceBuffer(sizeof(double) * 16 * p->ldw, s);
+    p->mv_partial = DeviceBuffer(sizeof(double) * 16 * 16 * p->ldw, s);
     HIP_CHECK(hipStreamSynchronize(s));
+    if (!p->has_pairs) p->I.reset();   // idle now: back to the cache
     p->t_far = t_far.seconds();
     p->t_near = t_near.seconds();
     p->t_contract = t_contract.seconds();

@@ -2,6 +2,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
 
 #include "internal.h"
 
@@ -15,23 +16,134 @@ void set_last_error(const std::string& msg) { g_last_error = msg; }
 
 [[noreturn]] void fail(int code, const std::string& msg) { throw Failure{code, msg}; }
 
-DeviceBuffer::DeviceBuffer(size_t b) : bytes(b) {
+namespace {
+struct Pending {
+    size_t cap;
+    void* ptr;
+    hipEvent_t ev;
+};
+struct MemPool {
+    std::mutex mu;
+    std::multimap<size_t, void*> free;   // capacity -> buffer
+    std::vector<Pending> pending;        // released, waiting for their stream
+    std::vector<hipEvent_t> events;      // spare events
+};
+MemPool& mem_pool(int device) {
+    static MemPool pools[64];
+    return pools[device & 63];
+}
+size_t size_class(size_t b) {
+    if (b >= kPooledBytes) return b;
+    size_t c = 256;
+    while (c < b) c <<= 1;
+    return c;
+}
+// moves released buffers whose stream has passed the release point to the free list (lock held);
+// leaves an error already pending on this thread untouched
+void collect(MemPool& P) {
+    if (P.pending.empty() || hipPeekAtLastError() != hipSuccess) return;
+    for (size_t i = 0; i < P.pending.size();) {
+        const hipError_t q = hipEventQuery(P.pending[i].ev);
+        if (q == hipSuccess) {
+            P.free.emplace(P.pending[i].cap, P.pending[i].ptr);
+            P.events.push_back(P.pending[i].ev);
+            P.pending[i] = P.pending.back();
+            P.pending.pop_back();
+        } else {
+            (void)hipGetLastError();   // not ready: no error to keep
+            ++i;
+        }
+    }
+}
+}  // namespace
+
+std::mutex& capture_mutex() {
+    static std::mutex mu;
+    return mu;
+}
+
+void release_cached_device_memory(int device) {
+    MemPool& P = mem_pool(device);
+    std::lock_guard<std::mutex> cap(capture_mutex());
+    std::lock_guard<std::mutex> lk(P.mu);
+    for (auto& q : P.pending) {
+        (void)hipEventSynchronize(q.ev);
+        P.free.emplace(q.cap, q.ptr);
+        P.events.push_back(q.ev);
+    }
+    P.pending.clear();
+    for (auto& kv : P.free) (void)hipFree(kv.second);
+    P.free.clear();
+    for (hipEvent_t e : P.events) (void)hipEventDestroy(e);
+    P.events.clear();
+}
+
+DeviceBuffer::DeviceBuffer(size_t b, hipStream_t s) : bytes(b), stream(s) {
     if (b == 0) return;
-    hipError_t e = hipMalloc(&ptr, b);
+    (void)hipGetDevice(&dev);
+    const size_t want = size_class(b);
+    {
+        MemPool& P = mem_pool(dev);
+        std::lock_guard<std::mutex> lk(P.mu);
+        collect(P);
+        auto it = P.free.lower_bound(want);
+        if (it != P.free.end() && (want < kPooledBytes ? it->first == want : it->first <= want + want / 4)) {
+            ptr = it->second;
+            cap = it->first;
+            pooled = true;
+            P.free.erase(it);
+            return;
+        }
+    }
+    hipError_t e = hipMalloc(&ptr, want);
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        release_cached_device_memory(dev);
+        e = hipMalloc(&ptr, want);
+    }
     if (e != hipSuccess) {
         (void)hipGetLastError();
         ptr = nullptr;
         fail(e == hipErrorOutOfMemory ? BEM_E_OOM : BEM_E_DEVICE,
-             "hipMalloc(" + std::to_string(b) + " bytes): " + hipGetErrorString(e));
+             "hipMalloc(" + std::to_string(want) + " bytes): " + hipGetErrorString(e));
     }
+    cap = want;
+    pooled = true;
 }
 
 DeviceBuffer::~DeviceBuffer() { reset(); }
 
 void DeviceBuffer::reset() {
-    if (ptr) (void)hipFree(ptr);
+    if (ptr && pooled) {
+        MemPool& P = mem_pool(dev);
+        std::lock_guard<std::mutex> lk(P.mu);
+        hipEvent_t ev = nullptr;
+        if (stream) {
+            if (!P.events.empty()) {
+                ev = P.events.back();
+                P.events.pop_back();
+            } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+                ev = nullptr;
+            }
+            if (ev && hipEventRecord(ev, stream) != hipSuccess) {
+                P.events.push_back(ev);
+                ev = nullptr;
+            }
+        }
+        if (ev) {
+            P.pending.push_back({cap, ptr, ev});
+        } else if (stream) {
+            // no event: wait for the stream here rather than hand out memory still in use
+            (void)hipStreamSynchronize(stream);
+            P.free.emplace(cap, ptr);
+        } else {
+            P.free.emplace(cap, ptr);
+        }
+    }
     ptr = nullptr;
-    bytes = 0;
+    bytes = cap = 0;
+    pooled = false;
+    stream = nullptr;
 }
 
 DeviceBuffer& DeviceBuffer::operator=(DeviceBuffer&& o) noexcept {
@@ -39,8 +151,14 @@ DeviceBuffer& DeviceBuffer::operator=(DeviceBuffer&& o) noexcept {
         reset();
         ptr = o.ptr;
         bytes = o.bytes;
+        cap = o.cap;
+        dev = o.dev;
+        pooled = o.pooled;
+        stream = o.stream;
         o.ptr = nullptr;
-        o.bytes = 0;
+        o.bytes = o.cap = 0;
+        o.pooled = false;
+        o.stream = nullptr;
     }
     return *this;
 }
@@ -52,7 +170,7 @@ void solve_device(bem_problem* p, const bem_precond* M, const double* b, double*
 
 using namespace bem;
 
-#define BEM_TRY try {
+#define BEM_TRY try { ::bem::RelaxedCapture relaxed_capture_guard_;
 #define BEM_CATCH                                              \
     }                                                          \
     catch (const Failure& f) {                                 \
@@ -94,9 +212,12 @@ int solve_common(bem_problem* p, const bem_precond* m, const double* d_b, int32_
     if (m && m->p != p) fail(BEM_E_INVALID_ARG, "preconditioner belongs to another problem");
     const int64_t N = p->N;
     std::vector<bem_solve_info> inf(k);
-    DeviceBuffer x(sizeof(double) * std::max<int64_t>(1, N * k));
+    DeviceBuffer x(sizeof(double) * std::max<int64_t>(1, N * k), p->stream);
     if (N > 0) solve_device(p, m, d_b, x.as<double>(), k, o, inf.data());
-    if (phi_out && N > 0) HIP_CHECK(hipMemcpy(phi_out, x.ptr, sizeof(double) * N * k, hipMemcpyDeviceToHost));
+    if (phi_out && N > 0) {
+        HIP_CHECK(hipMemcpyAsync(phi_out, x.ptr, sizeof(double) * N * k, hipMemcpyDeviceToHost, p->stream));
+        HIP_CHECK(hipStreamSynchronize(p->stream));
+    }
     int rc = BEM_OK;
     for (int c = 0; c < k; ++c) {
         if (inf[c].status == BEM_E_BREAKDOWN) rc = BEM_E_BREAKDOWN;
@@ -135,7 +256,12 @@ int bem_ctx_create(int hip_device, size_t hbm_budget_bytes, bem_ctx** out) {
 void bem_ctx_destroy(bem_ctx* ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
-    if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    {
+        std::lock_guard<std::mutex> cap(capture_mutex());
+        if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+        (void)hipDeviceSynchronize();
+    }
+    release_cached_device_memory(ctx->device);
     delete ctx;
 }
 
@@ -154,7 +280,7 @@ int bem_problem_bench_matvec(const bem_problem* p, int fp32, int32_t k, int reps
     set_device(p->ctx);
     const int64_t N = p->N;
     if (N == 0) { *seconds = 0; return BEM_OK; }
-    DeviceBuffer x(sizeof(double) * N * k), y(sizeof(double) * N * k);
+    DeviceBuffer x(sizeof(double) * N * k, p->stream), y(sizeof(double) * N * k, p->stream);
     std::vector<double> hx(size_t(N) * k);
     for (size_t i = 0; i < hx.size(); ++i) hx[i] = 1.0 / double(1 + (i % 97));
     HIP_CHECK(hipMemcpyAsync(x.ptr, hx.data(), sizeof(double) * hx.size(), hipMemcpyHostToDevice, p->stream));
@@ -213,6 +339,7 @@ int bem_assemble(bem_ctx* ctx, const double* vertices, int64_t nv, const int32_t
         (void)hipStreamSynchronize(p->stream);
         hipStream_t s = p->stream;
         p.reset();
+        std::lock_guard<std::mutex> cap(capture_mutex());
         (void)hipStreamDestroy(s);
         throw;
     }
@@ -231,7 +358,10 @@ void bem_problem_destroy(bem_problem* p) {
     if (p->stream) (void)hipStreamSynchronize(p->stream);
     hipStream_t s = p->stream;
     delete p;
-    if (s) (void)hipStreamDestroy(s);
+    if (s) {
+        std::lock_guard<std::mutex> cap(capture_mutex());
+        (void)hipStreamDestroy(s);
+    }
 }
 
 int bem_problem_get_info(const bem_problem* p, bem_problem_info* info) {
@@ -308,7 +438,7 @@ int bem_rhs(const bem_problem* p, const double* g, int32_t k, double* out) {
     set_device(p->ctx);
     const int64_t N = p->N;
     if (N == 0) return BEM_OK;
-    DeviceBuffer dg(sizeof(double) * 3 * k), dL(sizeof(double) * N * k);
+    DeviceBuffer dg(sizeof(double) * 3 * k, p->stream), dL(sizeof(double) * N * k, p->stream);
     HIP_CHECK(hipMemcpyAsync(dg.ptr, g, sizeof(double) * 3 * k, hipMemcpyHostToDevice, p->stream));
     rhs_device(p, dg.as<double>(), k, dL.as<double>(), p->stream);
     HIP_CHECK(hipMemcpyAsync(out, dL.ptr, sizeof(double) * N * k, hipMemcpyDeviceToHost, p->stream));
@@ -323,7 +453,7 @@ int bem_matvec(const bem_problem* p, const double* x, int32_t k, int fp32, doubl
     set_device(p->ctx);
     const int64_t N = p->N;
     if (N == 0) return BEM_OK;
-    DeviceBuffer dx(sizeof(double) * N * k), dy(sizeof(double) * N * k);
+    DeviceBuffer dx(sizeof(double) * N * k, p->stream), dy(sizeof(double) * N * k, p->stream);
     HIP_CHECK(hipMemcpyAsync(dx.ptr, x, sizeof(double) * N * k, hipMemcpyHostToDevice, p->stream));
     matvec_device(p, fp32 != 0, dx.as<double>(), N, k, dy.as<double>(), p->stream);
     HIP_CHECK(hipMemcpyAsync(y, dy.ptr, sizeof(double) * N * k, hipMemcpyDeviceToHost, p->stream));
@@ -337,7 +467,7 @@ int bem_jump_values(const bem_problem* p, const double* phi, double* jump_out) {
     if (!p || !phi || !jump_out) fail(BEM_E_INVALID_ARG, "bad argument");
     set_device(p->ctx);
     const int64_t N = p->N, nt = p->topo.nt;
-    DeviceBuffer dp(sizeof(double) * std::max<int64_t>(1, N)), dj(sizeof(double) * nt * 3);
+    DeviceBuffer dp(sizeof(double) * std::max<int64_t>(1, N), p->stream), dj(sizeof(double) * nt * 3, p->stream);
     if (N) HIP_CHECK(hipMemcpyAsync(dp.ptr, phi, sizeof(double) * N, hipMemcpyHostToDevice, p->stream));
     jump_values_device(p, dp.as<double>(), dj.as<double>(), p->stream);
     HIP_CHECK(hipMemcpyAsync(jump_out, dj.ptr, sizeof(double) * nt * 3, hipMemcpyDeviceToHost, p->stream));
@@ -387,8 +517,8 @@ int bem_precond_apply(const bem_precond* m, const double* r, int32_t k, double* 
     const bem_problem* p = m->p;
     set_device(p->ctx);
     const int64_t N = p->N;
-    DeviceBuffer dr(sizeof(double) * N * k), dz(sizeof(double) * N * k);
-    DeviceBuffer scr(sizeof(double) * precond_scratch_size(m, std::min(k, 16)));
+    DeviceBuffer dr(sizeof(double) * N * k, m->p->stream), dz(sizeof(double) * N * k, m->p->stream);
+    DeviceBuffer scr(sizeof(double) * precond_scratch_size(m, std::min(k, 16)), m->p->stream);
     HIP_CHECK(hipMemcpyAsync(dr.ptr, r, sizeof(double) * N * k, hipMemcpyHostToDevice, p->stream));
     precond_apply_device(m, false, dr.as<double>(), N, k, dz.as<double>(), p->stream, scr.as<double>());
     HIP_CHECK(hipMemcpyAsync(z, dz.ptr, sizeof(double) * N * k, hipMemcpyDeviceToHost, p->stream));
@@ -403,7 +533,7 @@ int bem_pcg_solve(bem_problem* p, const bem_precond* m, const double* g, int32_t
     if (!p || !g || k <= 0) fail(BEM_E_INVALID_ARG, "bad argument");
     set_device(p->ctx);
     const int64_t N = p->N;
-    DeviceBuffer dg(sizeof(double) * 3 * k), dL(sizeof(double) * std::max<int64_t>(1, N * k));
+    DeviceBuffer dg(sizeof(double) * 3 * k, p->stream), dL(sizeof(double) * std::max<int64_t>(1, N * k), p->stream);
     HIP_CHECK(hipMemcpyAsync(dg.ptr, g, sizeof(double) * 3 * k, hipMemcpyHostToDevice, p->stream));
     rhs_device(p, dg.as<double>(), k, dL.as<double>(), p->stream);
     return solve_common(p, m, dL.as<double>(), k, opts, phi_out, info);
@@ -416,7 +546,7 @@ int bem_pcg_solve_rhs(bem_problem* p, const bem_precond* m, const double* rhs, i
     if (!p || !rhs || k <= 0) fail(BEM_E_INVALID_ARG, "bad argument");
     set_device(p->ctx);
     const int64_t N = p->N;
-    DeviceBuffer dL(sizeof(double) * std::max<int64_t>(1, N * k));
+    DeviceBuffer dL(sizeof(double) * std::max<int64_t>(1, N * k), p->stream);
     if (N) HIP_CHECK(hipMemcpyAsync(dL.ptr, rhs, sizeof(double) * N * k, hipMemcpyHostToDevice, p->stream));
     return solve_common(p, m, dL.as<double>(), k, opts, phi_out, info);
     BEM_CATCH

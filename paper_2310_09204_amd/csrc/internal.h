@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <functional>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -75,15 +76,55 @@ void gauss_legendre01(int n, std::vector<double>& x, std::vector<double>& w);
 // ------------------------------------------------------------------------------------------
 // Device-side objects behind the opaque C handles
 // ------------------------------------------------------------------------------------------
+// Device allocation through a per-device cache: a released buffer is kept for reuse instead of
+// being given back with hipFree, which synchronises the whole device (and can stall for hundreds
+// of milliseconds on tens of GB).  Buffers below kPooledBytes are rounded up to a power of two and
+// reused by exact size class; larger ones are reused if at most 25 % larger than the request.
+// A buffer allocated for a stream is released stream-ordered: an event is recorded on that
+// stream and the memory is handed out again only once the event has completed, so queued kernels
+// that still read it are safe even when another thread allocates meanwhile.  A buffer with no
+// stream must only be released when no queued work uses it.  Cached memory is given back when an
+// allocation runs out of memory and when a context of the device is destroyed.
+//
+// Device-wide synchronising calls (hipFree, hipStreamDestroy) invalidate a HIP graph capture in
+// progress on any stream, so they and the capture of a PCG iteration hold capture_mutex().
+std::mutex& capture_mutex();
+
+// Puts the calling thread in relaxed stream-capture interaction mode for its lifetime (restoring
+// the previous mode after).  Library calls run concurrently on several host threads (the serving
+// loop's workers, or callers' own threads) while one of them captures a PCG iteration into a HIP
+// graph; in the default global mode the runtime may refuse allocations and synchronous copies on
+// the other threads during such a capture.
+struct RelaxedCapture {
+    hipStreamCaptureMode prev = hipStreamCaptureModeRelaxed;
+    RelaxedCapture() { (void)hipThreadExchangeStreamCaptureMode(&prev); }
+    ~RelaxedCapture() { (void)hipThreadExchangeStreamCaptureMode(&prev); }
+    RelaxedCapture(const RelaxedCapture&) = delete;
+    RelaxedCapture& operator=(const RelaxedCapture&) = delete;
+};
+
+constexpr size_t kPooledBytes = size_t(64) << 20;
+void release_cached_device_memory(int device);
+
 struct DeviceBuffer {
     void* ptr = nullptr;
-    size_t bytes = 0;
+    size_t bytes = 0;     // requested size
+    size_t cap = 0;       // allocated size (>= bytes for a buffer reused from the cache)
+    int dev = 0;
+    bool pooled = false;
+    hipStream_t stream = nullptr;   // stream whose queued work may use the buffer (release is ordered after it)
     DeviceBuffer() = default;
-    explicit DeviceBuffer(size_t b);
+    DeviceBuffer(size_t b, hipStream_t s);
     ~DeviceBuffer();
     DeviceBuffer(const DeviceBuffer&) = delete;
     DeviceBuffer& operator=(const DeviceBuffer&) = delete;
-    DeviceBuffer(DeviceBuffer&& o) noexcept : ptr(o.ptr), bytes(o.bytes) { o.ptr = nullptr; o.bytes = 0; }
+    DeviceBuffer(DeviceBuffer&& o) noexcept
+        : ptr(o.ptr), bytes(o.bytes), cap(o.cap), dev(o.dev), pooled(o.pooled), stream(o.stream) {
+        o.ptr = nullptr;
+        o.bytes = o.cap = 0;
+        o.pooled = false;
+        o.stream = nullptr;
+    }
     DeviceBuffer& operator=(DeviceBuffer&& o) noexcept;
     void reset();
     template <class T> T* as() const { return static_cast<T*>(ptr); }
@@ -91,7 +132,7 @@ struct DeviceBuffer {
 
 template <class T>
 DeviceBuffer upload(const std::vector<T>& v, hipStream_t s) {
-    DeviceBuffer b(std::max<size_t>(1, v.size()) * sizeof(T));
+    DeviceBuffer b(std::max<size_t>(1, v.size()) * sizeof(T), s);
     if (!v.empty()) HIP_CHECK(hipMemcpyAsync(b.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
     return b;
 }

@@ -18,6 +18,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <map>
 #include <numeric>
 
@@ -80,6 +82,46 @@ __device__ __forceinline__ void acc_to_lds(const double (&acc)[4][4], double* __
         for (int j = 0; j < 4; ++j) s[(tr * 4 + i) * LDT + tc * 4 + j] = scale * acc[i][j];
 }
 
+// C (64 x 64) = op(A) op(B) on the FP64 matrix cores, from two LDS tiles.  Wave w computes rows
+// 16w .. 16w+15 as four 16x16 output tiles n = 0..3; lane l = 16 kk + i supplies A[16w+i][k0+kk] and
+// B[k0+kk][16n+i] to each 16x16x4 step, and register r of acc[n] holds C[16w + kk + 4r][16n + i].
+template <bool TA, bool TB>
+__device__ __forceinline__ void tile_mfma(f64x4 (&acc)[4], const double* __restrict__ A, const double* __restrict__ B) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i = lane & 15, kk = lane >> 4;
+    const int row = 16 * w + i;
+#pragma unroll 4
+    for (int k0 = 0; k0 < TBK; k0 += 4) {
+        const int k = k0 + kk;
+        const double a = TA ? A[k * LDT + row] : A[row * LDT + k];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            const int col = 16 * n + i;
+            const double b = TB ? B[col * LDT + k] : B[k * LDT + col];
+            acc[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[n], 0, 0, 0);
+        }
+    }
+}
+
+__device__ __forceinline__ void mfma_zero(f64x4 (&acc)[4]) {
+#pragma unroll
+    for (int n = 0; n < 4; ++n) acc[n] = f64x4{0.0, 0.0, 0.0, 0.0};
+}
+
+// g[r][c] (row stride ld) = scale * acc (+ g[r][c] if accumulate)
+__device__ __forceinline__ void mfma_store(const f64x4 (&acc)[4], double* __restrict__ g, int64_t ld, double scale,
+                                           bool accumulate) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i = lane & 15, kk = lane >> 4;
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            double* e = g + int64_t(16 * w + kk + 4 * r) * ld + 16 * n + i;
+            *e = accumulate ? fma(scale, acc[n][r], *e) : scale * acc[n][r];
+        }
+}
+
 // --- gather: A_b = W[idx_b, idx_b] padded with the identity ---------------------------------
 __global__ __launch_bounds__(256) void k_gather(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
                                                 const int32_t* __restrict__ idx, const double* __restrict__ W,
@@ -97,67 +139,94 @@ __global__ __launch_bounds__(256) void k_gather(const int4* __restrict__ tasks, 
     }
 }
 
-// --- Cholesky of the diagonal tile of step k ------------------------------------------------
+// --- Cholesky of the diagonal tile of step k and the inverse of its factor --------------------
+// Factor: the first wave alone, lane i owning row i, left-looking (Crout) column by column, so the
+// column sweep needs no block barrier: L_ij = (A_ij - sum_{l<j} L_il L_jl) / L_jj.  Inverse
+// Y = L^{-1}: all 256 threads, four lanes per column c splitting each row's dot product, rows in
+// order (Y_rc = (delta_rc - sum_{c<=l<r} L_rl Y_lc) / L_rr).  L_kk goes back to A, Y to X (the
+// diagonal tiles of the inverse factor, used by this step's triangular solves and the inversion).
 __global__ __launch_bounds__(256) void k_potrf(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
-                                               double* __restrict__ A, int k, int* __restrict__ flags) {
+                                               double* __restrict__ A, double* __restrict__ X, int k, int* __restrict__ flags) {
     __shared__ double L[TBK * LDT];
+    __shared__ double Y[TBK * LDT];
+    __shared__ double rinv[TBK];
     const int4 t = tasks[blockIdx.x];
     const BlockMeta m = meta[t.x];
-    double* g = A + m.mat_off + int64_t(k) * TBK * m.npad + int64_t(k) * TBK;
-    tile_load(L, g, m.npad);
+    const int64_t off = m.mat_off + int64_t(k) * TBK * m.npad + int64_t(k) * TBK;
+    tile_load(L, A + off, m.npad);
     __syncthreads();
-    __shared__ double piv;
-    for (int j = 0; j < TBK; ++j) {
-        if (threadIdx.x == 0) {
-            double d = L[j * LDT + j];
-            if (!(d > 0.0) || !isfinite(d)) {
-                flags[t.x] = 1;
-                d = 1.0;
+    if (threadIdx.x < TBK) {
+        const int i = threadIdx.x;
+        bool bad = false;
+        for (int j = 0; j < TBK; ++j) {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            if (i >= j) {
+                int l = 0;
+                for (; l + 3 < j; l += 4) {
+                    s0 = fma(L[i * LDT + l], L[j * LDT + l], s0);
+                    s1 = fma(L[i * LDT + l + 1], L[j * LDT + l + 1], s1);
+                    s2 = fma(L[i * LDT + l + 2], L[j * LDT + l + 2], s2);
+                    s3 = fma(L[i * LDT + l + 3], L[j * LDT + l + 3], s3);
+                }
+                for (; l < j; ++l) s0 = fma(L[i * LDT + l], L[j * LDT + l], s0);
             }
-            piv = sqrt(d);
-            L[j * LDT + j] = piv;
+            const double sij = L[i * LDT + j] - ((s0 + s1) + (s2 + s3));
+            if (i == j) {
+                double d = sij;
+                if (!(d > 0.0) || !isfinite(d)) {
+                    bad = true;
+                    d = 1.0;
+                }
+                L[j * LDT + j] = sqrt(d);
+            }
+            __builtin_amdgcn_wave_barrier();   // the pivot written by lane j is read below (same wave)
+            const double piv = L[j * LDT + j];
+            if (i > j) L[i * LDT + j] = sij / piv;
+            __builtin_amdgcn_wave_barrier();
         }
-        __syncthreads();
-        for (int i = j + 1 + threadIdx.x; i < TBK; i += blockDim.x) L[i * LDT + j] /= piv;
-        __syncthreads();
-        const int rem = TBK - j - 1;
-        for (int e = threadIdx.x; e < rem * rem; e += blockDim.x) {
-            int i = j + 1 + e / rem, c = j + 1 + e % rem;
-            if (c <= i) L[i * LDT + c] -= L[i * LDT + j] * L[c * LDT + j];
-        }
-        __syncthreads();
-    }
-    for (int e = threadIdx.x; e < TBK * TBK; e += blockDim.x) {
-        int r = e >> 6, c = e & 63;
-        if (c > r) L[r * LDT + c] = 0.0;
+        if (bad) flags[t.x] = 1;
+        rinv[i] = 1.0 / L[i * LDT + i];
     }
     __syncthreads();
-    tile_store(L, g, m.npad);
+    for (int e = threadIdx.x; e < TBK * TBK; e += blockDim.x) {
+        const int r = e >> 6, c = e & 63;
+        if (c > r) L[r * LDT + c] = 0.0;
+        if (r < c) Y[r * LDT + c] = 0.0;
+    }
+    __syncthreads();
+    {
+        const int c = threadIdx.x >> 2, q = threadIdx.x & 3;   // the four lanes of a column share a wave
+        for (int r = c; r < TBK; ++r) {
+            double sacc = 0.0;
+            for (int l = c + q; l < r; l += 4) sacc = fma(-L[r * LDT + l], Y[l * LDT + c], sacc);
+            sacc += __shfl_xor(sacc, 1, 64);
+            sacc += __shfl_xor(sacc, 2, 64);
+            if (q == 0) Y[r * LDT + c] = ((r == c ? 1.0 : 0.0) + sacc) * rinv[r];
+            __builtin_amdgcn_wave_barrier();   // Y[r][c] is read by the other lanes of the quad next
+        }
+    }
+    __syncthreads();
+    tile_store(L, A + off, m.npad);
+    tile_store(Y, X + off, m.npad);
 }
 
-// --- A_ik <- A_ik L_kk^{-T} for the tiles below the diagonal of step k ----------------------
+// --- A_ik <- A_ik L_kk^{-T} for the tiles below the diagonal of step k (a product with the
+//     inverse factor tile from k_potrf) ----------------------------------------------------------
 __global__ __launch_bounds__(256) void k_trsm(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
-                                              double* __restrict__ A, int k) {
-    __shared__ double L[TBK * LDT];
-    __shared__ double X[TBK * LDT];
+                                              double* __restrict__ A, const double* __restrict__ X, int k) {
+    __shared__ double P[TBK * LDT];
+    __shared__ double Q[TBK * LDT];
     const int4 t = tasks[blockIdx.x];
     const BlockMeta m = meta[t.x];
     const int i = t.y;
-    double* a0 = A + m.mat_off;
-    tile_load(L, a0 + int64_t(k) * TBK * m.npad + int64_t(k) * TBK, m.npad);
-    double* gik = a0 + int64_t(i) * TBK * m.npad + int64_t(k) * TBK;
-    tile_load(X, gik, m.npad);
+    double* gik = A + m.mat_off + int64_t(i) * TBK * m.npad + int64_t(k) * TBK;
+    tile_load(P, gik, m.npad);
+    tile_load(Q, X + m.mat_off + int64_t(k) * TBK * m.npad + int64_t(k) * TBK, m.npad);
     __syncthreads();
-    if (threadIdx.x < TBK) {
-        const int r = threadIdx.x;
-        for (int c = 0; c < TBK; ++c) {
-            double s = X[r * LDT + c];
-            for (int l = 0; l < c; ++l) s -= X[r * LDT + l] * L[c * LDT + l];
-            X[r * LDT + c] = s / L[c * LDT + c];
-        }
-    }
-    __syncthreads();
-    tile_store(X, gik, m.npad);
+    f64x4 acc[4];
+    mfma_zero(acc);
+    tile_mfma<false, true>(acc, P, Q);
+    mfma_store(acc, gik, m.npad, 1.0, false);
 }
 
 // --- trailing update A_ij -= A_ik A_jk^T, j <= i, of step k ---------------------------------
@@ -172,39 +241,10 @@ __global__ __launch_bounds__(256) void k_update(const int4* __restrict__ tasks, 
     tile_load(P, a0 + int64_t(i) * TBK * m.npad + int64_t(k) * TBK, m.npad);
     tile_load(Q, a0 + int64_t(j) * TBK * m.npad + int64_t(k) * TBK, m.npad);
     __syncthreads();
-    double acc[4][4];
-    acc_zero(acc);
-    tile_mac<false, true>(acc, P, Q);
-    double* gij = a0 + int64_t(i) * TBK * m.npad + int64_t(j) * TBK;
-    const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) gij[int64_t(tr * 4 + a) * m.npad + tc * 4 + b] -= acc[a][b];
-}
-
-// --- inverse of the diagonal factor tiles: X_ii = L_ii^{-1} --------------------------------
-__global__ __launch_bounds__(256) void k_trtri_diag(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
-                                                    const double* __restrict__ A, double* __restrict__ X) {
-    __shared__ double L[TBK * LDT];
-    __shared__ double Y[TBK * LDT];
-    const int4 t = tasks[blockIdx.x];
-    const BlockMeta m = meta[t.x];
-    const int i = t.y;
-    const int64_t off = m.mat_off + int64_t(i) * TBK * m.npad + int64_t(i) * TBK;
-    tile_load(L, A + off, m.npad);
-    __syncthreads();
-    if (threadIdx.x < TBK) {
-        const int c = threadIdx.x;           // column of the inverse: solve L y = e_c
-        for (int r = 0; r < TBK; ++r) {
-            double s = (r == c) ? 1.0 : 0.0;
-            if (r < c) { Y[r * LDT + c] = 0.0; continue; }
-            for (int l = c; l < r; ++l) s -= L[r * LDT + l] * Y[l * LDT + c];
-            Y[r * LDT + c] = s / L[r * LDT + r];
-        }
-    }
-    __syncthreads();
-    tile_store(Y, X + off, m.npad);
+    f64x4 acc[4];
+    mfma_zero(acc);
+    tile_mfma<false, true>(acc, P, Q);
+    mfma_store(acc, a0 + int64_t(i) * TBK * m.npad + int64_t(j) * TBK, m.npad, -1.0, true);
 }
 
 // --- off-diagonal tiles of X = L^{-1}, right-looking: X_ij accumulates S_ij = sum_{m<i} L_im X_mj
@@ -217,16 +257,14 @@ __global__ __launch_bounds__(256) void k_trtri_finish(const int4* __restrict__ t
     const BlockMeta m = meta[t.x];
     const int j = t.y;
     double* x0 = X + m.mat_off;
+    double* gij = x0 + int64_t(i) * TBK * m.npad + int64_t(j) * TBK;
     tile_load(P, x0 + int64_t(i) * TBK * m.npad + int64_t(i) * TBK, m.npad);
-    tile_load(Q, x0 + int64_t(i) * TBK * m.npad + int64_t(j) * TBK, m.npad);
+    tile_load(Q, gij, m.npad);
     __syncthreads();
-    double acc[4][4];
-    acc_zero(acc);
-    tile_mac<false, false>(acc, P, Q);
-    __syncthreads();
-    acc_to_lds(acc, P, -1.0);
-    __syncthreads();
-    tile_store(P, x0 + int64_t(i) * TBK * m.npad + int64_t(j) * TBK, m.npad);
+    f64x4 acc[4];
+    mfma_zero(acc);
+    tile_mfma<false, false>(acc, P, Q);
+    mfma_store(acc, gij, m.npad, -1.0, false);
 }
 
 // S_{i'j} += L_{i'i} X_ij for all i' > i, j <= i (tasks carry i', j)
@@ -240,15 +278,10 @@ __global__ __launch_bounds__(256) void k_trtri_update(const int4* __restrict__ t
     tile_load(P, A + m.mat_off + int64_t(ip) * TBK * m.npad + int64_t(i) * TBK, m.npad);
     tile_load(Q, X + m.mat_off + int64_t(i) * TBK * m.npad + int64_t(j) * TBK, m.npad);
     __syncthreads();
-    double acc[4][4];
-    acc_zero(acc);
-    tile_mac<false, false>(acc, P, Q);
-    double* g = X + m.mat_off + int64_t(ip) * TBK * m.npad + int64_t(j) * TBK;
-    const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) g[int64_t(tr * 4 + a) * m.npad + tc * 4 + b] += acc[a][b];
+    f64x4 acc[4];
+    mfma_zero(acc);
+    tile_mfma<false, false>(acc, P, Q);
+    mfma_store(acc, X + m.mat_off + int64_t(ip) * TBK * m.npad + int64_t(j) * TBK, m.npad, 1.0, true);
 }
 
 __global__ void k_zero(double* __restrict__ a, int64_t n) {
@@ -265,25 +298,28 @@ __global__ __launch_bounds__(256) void k_syrk_inverse(const int4* __restrict__ t
     const int i = t.y, j = t.z;     // i >= j
     const int nt = int(m.npad / TBK);
     const double* x0 = X + m.mat_off;
-    double acc[4][4];
-    acc_zero(acc);
+    f64x4 acc[4];
+    mfma_zero(acc);
     for (int mm = i; mm < nt; ++mm) {
         tile_load(P, x0 + int64_t(mm) * TBK * m.npad + int64_t(i) * TBK, m.npad);
         tile_load(Q, x0 + int64_t(mm) * TBK * m.npad + int64_t(j) * TBK, m.npad);
         __syncthreads();
-        tile_mac<true, false>(acc, P, Q);
+        tile_mfma<true, false>(acc, P, Q);
         __syncthreads();
     }
     double* b0 = B + m.mat_off;
-    const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
+    // tile (i, j) directly; its transpose through LDS (P is free after the loop) for (j, i)
+    mfma_store(acc, b0 + int64_t(i) * TBK * m.npad + int64_t(j) * TBK, m.npad, 1.0, false);
+    if (i != j) {
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        const int ii = lane & 15, kk = lane >> 4;
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+        for (int n = 0; n < 4; ++n)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int64_t r = int64_t(i) * TBK + tr * 4 + a, c = int64_t(j) * TBK + tc * 4 + b;
-            b0[r * m.npad + c] = acc[a][b];
-            if (i != j) b0[c * m.npad + r] = acc[a][b];
-        }
+            for (int r = 0; r < 4; ++r) P[(16 * n + ii) * LDT + 16 * w + kk + 4 * r] = acc[n][r];
+        __syncthreads();
+        tile_store(P, b0 + int64_t(j) * TBK * m.npad + int64_t(i) * TBK, m.npad);
+    }
 }
 
 __global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
@@ -542,6 +578,16 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
     bem_problem* p = M->p;
     const MeshTopo& f = p->topo;
     hipStream_t s = p->stream;
+    // BEM_TRACE=1: synchronise and print the wall time of each set-up phase to stderr
+    const bool trace = std::getenv("BEM_TRACE") != nullptr;
+    auto tlast = t0;
+    auto mark = [&](const char* what) {
+        if (!trace) return;
+        HIP_CHECK(hipStreamSynchronize(s));
+        auto now = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "bem-trace precond  %-18s %8.3f ms\n", what, std::chrono::duration<double>(now - tlast).count() * 1e3);
+        tlast = now;
+    };
     if (!patch) fail(BEM_E_INVALID_ARG, "patch_of_triangle is NULL");
 
     // ---- dof classes ---------------------------------------------------------------------------
@@ -580,6 +626,7 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
         build_prolongation(f, c, parent, R);
     }
     M->nH = R.nH;
+    mark("classes+coarse host");
 
     // ---- block layout (faces, wire basket, then the coarse block) -----------------------------------
     const int64_t nall = M->nblocks + (M->nH > 0 ? 1 : 0);
@@ -600,18 +647,18 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
     }
     M->idx_total = int64_t(idx.size());
     M->xg_rows = xoff;
-    M->xg = DeviceBuffer(sizeof(double) * 16 * std::max<int64_t>(1, xoff));
+    M->xg = DeviceBuffer(sizeof(double) * 16 * std::max<int64_t>(1, xoff), s);
     M->mat_total = moff;
     M->idx = upload(idx, s);
     M->blk_meta = upload(meta, s);
-    DeviceBuffer A(sizeof(double) * std::max<int64_t>(moff, 1)), X(sizeof(double) * std::max<int64_t>(moff, 1));
-    DeviceBuffer dflags(sizeof(int) * std::max<int64_t>(nall, 1));
+    DeviceBuffer A(sizeof(double) * std::max<int64_t>(moff, 1), s), X(sizeof(double) * std::max<int64_t>(moff, 1), s);
+    DeviceBuffer dflags(sizeof(int) * std::max<int64_t>(nall, 1), s);
     HIP_CHECK(hipMemsetAsync(dflags.ptr, 0, sizeof(int) * std::max<int64_t>(nall, 1), s));
 
     const BlockMeta* dm = M->blk_meta.as<BlockMeta>();
 
     // ---- every tile task of the set-up, planned on the host and uploaded once ------------------
-    enum Kind { GATHER, POTRF, TRSM, UPDATE, TRTRI_DIAG, TRTRI_FINISH, TRTRI_UPDATE, SYRK };
+    enum Kind { GATHER, POTRF, TRSM, UPDATE, TRTRI_FINISH, TRTRI_UPDATE, SYRK };
     struct Launch { Kind kind; int param; int64_t off, n; };
     std::vector<int4> all;
     std::vector<Launch> plan;
@@ -647,13 +694,7 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
         add(TRSM, k, tt);
         add(UPDATE, k, tu);
     }
-    {
-        std::vector<int4> td;
-        for (int64_t b = 0; b < nall; ++b)
-            for (int i = 0; i < ntile[b]; ++i) td.push_back(make_int4(int(b), i, 0, 0));
-        add(TRTRI_DIAG, 0, td);
-    }
-    for (int i = 0; i < maxT; ++i) {   // X = L^{-1}, right-looking
+    for (int i = 0; i < maxT; ++i) {   // X = L^{-1}, right-looking (diagonal tiles come from k_potrf)
         std::vector<int4> tf, tu;
         for (int64_t b = 0; b < nall; ++b) {
             if (i >= ntile[b]) continue;
@@ -673,15 +714,15 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
     }
     DeviceBuffer dtasks = upload(all, s);
     const int4* T0 = dtasks.as<int4>();
+    mark("layout+plan+upload");
     auto run = [&](const Launch& L) {
         const int4* d = T0 + L.off;
         const dim3 g(unsigned(L.n)), bl(256);
         switch (L.kind) {
             case GATHER: hipLaunchKernelGGL(k_gather, g, bl, 0, s, d, dm, M->idx.as<int32_t>(), p->W64.as<double>(), p->ldw, A.as<double>()); break;
-            case POTRF: hipLaunchKernelGGL(k_potrf, g, bl, 0, s, d, dm, A.as<double>(), L.param, dflags.as<int>()); break;
-            case TRSM: hipLaunchKernelGGL(k_trsm, g, bl, 0, s, d, dm, A.as<double>(), L.param); break;
+            case POTRF: hipLaunchKernelGGL(k_potrf, g, bl, 0, s, d, dm, A.as<double>(), X.as<double>(), L.param, dflags.as<int>()); break;
+            case TRSM: hipLaunchKernelGGL(k_trsm, g, bl, 0, s, d, dm, A.as<double>(), X.as<double>(), L.param); break;
             case UPDATE: hipLaunchKernelGGL(k_update, g, bl, 0, s, d, dm, A.as<double>(), L.param); break;
-            case TRTRI_DIAG: hipLaunchKernelGGL(k_trtri_diag, g, bl, 0, s, d, dm, A.as<double>(), X.as<double>()); break;
             case TRTRI_FINISH: hipLaunchKernelGGL(k_trtri_finish, g, bl, 0, s, d, dm, X.as<double>(), L.param); break;
             case TRTRI_UPDATE: hipLaunchKernelGGL(k_trtri_update, g, bl, 0, s, d, dm, A.as<double>(), X.as<double>(), L.param); break;
             case SYRK: hipLaunchKernelGGL(k_syrk_inverse, g, bl, 0, s, d, dm, X.as<double>(), A.as<double>()); break;
@@ -690,6 +731,7 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
     };
     size_t li = 0;
     if (li < plan.size() && plan[li].kind == GATHER) run(plan[li++]);
+    mark("gather");
     // coarse Galerkin block
     if (M->nH > 0) {
         M->rh_ptr = upload(R.ptr, s);
@@ -711,7 +753,7 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
         M->rht_ptr = upload(tp, s);
         M->rht_row = upload(trow, s);
         M->rht_val = upload(tval, s);
-        DeviceBuffer Z(sizeof(double) * std::max<int64_t>(1, f.N * M->nH));
+        DeviceBuffer Z(sizeof(double) * std::max<int64_t>(1, f.N * M->nH), s);
         hipLaunchKernelGGL(k_coarse_Z, dim3(nblk(f.N, 1024), unsigned(M->nH)), dim3(256), 0, s, p->W64.as<double>(), p->ldw, f.N,
                            M->rh_ptr.as<int64_t>(), M->rh_col.as<int32_t>(), M->rh_val.as<double>(), Z.as<double>());
         HIP_CHECK(hipGetLastError());
@@ -727,10 +769,12 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
         HIP_CHECK(hipStreamSynchronize(s));
     }
 
+    mark("coarse block");
     // off-diagonal tiles of X accumulate partial sums: start from zero
     hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, s, X.as<double>(), std::max<int64_t>(moff, 1));
     HIP_CHECK(hipGetLastError());
     while (li < plan.size()) run(plan[li++]);
+    mark("factor+invert");
     std::vector<int> flags(nall);
     HIP_CHECK(hipMemcpyAsync(flags.data(), dflags.ptr, sizeof(int) * nall, hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
@@ -738,7 +782,7 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
         if (flags[b]) fail(BEM_E_NOT_SPD, "preconditioner block " + std::to_string(b) + " is not positive definite");
     M->inv64 = std::move(A);
     if (M->fp32) {
-        M->inv32 = DeviceBuffer(sizeof(float) * std::max<int64_t>(moff, 1));
+        M->inv32 = DeviceBuffer(sizeof(float) * std::max<int64_t>(moff, 1), s);
         hipLaunchKernelGGL(k_to_f32, dim3(2048), dim3(256), 0, s, M->inv64.as<double>(), M->inv32.as<float>(), moff);
         HIP_CHECK(hipGetLastError());
     }
@@ -755,6 +799,7 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
     M->tasks = upload(at, s);
     HIP_CHECK(hipStreamSynchronize(s));
     M->bytes = int64_t(M->inv64.bytes + M->inv32.bytes + M->idx.bytes + M->rh_val.bytes * 3);
+    mark("fp32+apply tasks");
     M->t_setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 

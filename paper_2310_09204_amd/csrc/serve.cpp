@@ -109,6 +109,7 @@ bool make_room(bem_server* s, int64_t need, uint64_t keep_key) {
 
 void worker_main(bem_server* s) {
     (void)hipSetDevice(s->ctx->device);
+    RelaxedCapture relaxed;   // other workers capture PCG iterations concurrently
     for (;;) {
         std::vector<Request*> batch;
         bool hit = false;

@@ -487,11 +487,11 @@ PcgResult pcg_device(bem_problem* p, const bem_precond* M, bool mixed, const dou
     const int64_t N = p->N;
     const unsigned G = gblocks(N);
     const bool fp32 = mixed;
-    DeviceBuffer r(sizeof(double) * ld * k), z(sizeof(double) * ld * k), pp(sizeof(double) * ld * k), q(sizeof(double) * ld * k);
-    DeviceBuffer part(sizeof(double) * G * k * 3), dst(sizeof(ColState) * k), dtol(sizeof(double) * k);
+    DeviceBuffer r(sizeof(double) * ld * k, s), z(sizeof(double) * ld * k, s), pp(sizeof(double) * ld * k, s), q(sizeof(double) * ld * k, s);
+    DeviceBuffer part(sizeof(double) * G * k * 3, s), dst(sizeof(ColState) * k, s), dtol(sizeof(double) * k, s);
     const int max_hist = want_cond ? std::max(1, max_iter) : 1;
-    DeviceBuffer hist(sizeof(double) * 2 * max_hist * k);
-    DeviceBuffer cscr(sizeof(double) * (M ? precond_scratch_size(M, std::min(k, 16)) : 1));
+    DeviceBuffer hist(sizeof(double) * 2 * max_hist * k, s);
+    DeviceBuffer cscr(sizeof(double) * (M ? precond_scratch_size(M, std::min(k, 16)) : 1), s);
     std::vector<double> tol2(k);
     for (int c = 0; c < k; ++c) tol2[c] = tol[c] * tol[c];
     HIP_CHECK(hipMemcpyAsync(dtol.ptr, tol2.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
@@ -546,8 +546,9 @@ PcgResult pcg_device(bem_problem* p, const bem_precond* M, bool mixed, const dou
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t exec[2] = {nullptr, nullptr};
     if (use_graph) {
+        std::lock_guard<std::mutex> lk(capture_mutex());   // no device-wide synchronisation meanwhile
         for (int v = 0; v < (mixed ? 2 : 1); ++v) {
-            HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
             iteration(v == 1);
             HIP_CHECK(hipStreamEndCapture(s, &graph[v]));
             HIP_CHECK(hipGraphInstantiate(&exec[v], graph[v], nullptr, nullptr, 0));
@@ -598,7 +599,8 @@ PcgResult pcg_device(bem_problem* p, const bem_precond* M, bool mixed, const dou
     std::vector<double> hh;
     if (want_cond) {
         hh.resize(size_t(2) * max_hist * k);
-        HIP_CHECK(hipMemcpy(hh.data(), h, sizeof(double) * hh.size(), hipMemcpyDeviceToHost));
+        HIP_CHECK(hipMemcpyAsync(hh.data(), h, sizeof(double) * hh.size(), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
     }
     for (int c = 0; c < k; ++c) {
         res.iters[c] = hs[c].iters;
@@ -664,7 +666,7 @@ void solve_device(bem_problem* p, const bem_precond* M, const double* b, double*
     }
     // true FP64 residual of the result
     if (final_check) {
-        DeviceBuffer y(sizeof(double) * ld * k), r(sizeof(double) * ld * k), part(sizeof(double) * G * k * 2);
+        DeviceBuffer y(sizeof(double) * ld * k, s), r(sizeof(double) * ld * k, s), part(sizeof(double) * G * k * 2, s);
         matvec_device(p, false, x, ld, k, y.as<double>(), s);
         hipLaunchKernelGGL(k_residual, vg, vb, 0, s, b, y.as<double>(), r.as<double>(), ld, N);
         hipLaunchKernelGGL(k_dot_partial, vg, vb, 0, s, r.as<double>(), r.as<double>(), ld, N, part.as<double>());

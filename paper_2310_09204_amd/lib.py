@@ -364,6 +364,7 @@ class Server:
         if rc == BEM_PENDING:
             return None
         del self._keep[ticket]
+        self.last_message = load().bem_last_error().decode() if rc < 0 else ""
         return phi, [i.as_dict() for i in info], rc
 
     def stats(self):

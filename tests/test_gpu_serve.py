@@ -47,12 +47,15 @@ def test_mix_equals_solo(ctx):
     alone = [solo(ctx, r) for r in reqs]
     srv = lib.Server(ctx, max_inflight=3)
     tickets = [submit(srv, r) for r in reqs]
-    results = [srv.poll(t) for t in tickets]
+    results, messages = [], []
+    for t in tickets:
+        results.append(srv.poll(t))
+        messages.append(srv.last_message)
     st = srv.stats()
     srv.close()
     assert st["submitted"] == len(reqs) and st["completed"] == len(reqs) and st["rejected"] == 0
-    for r, (phi_solo, ref), (phi, info, rc) in zip(reqs, alone, results):
-        assert rc == 0
+    for r, (phi_solo, ref), (phi, info, rc), msg in zip(reqs, alone, results, messages):
+        assert rc == 0, msg
         assert phi.shape == phi_solo.shape
         assert all(i["t_total_s"] > 0 for i in info)
         if r.mixed:

@@ -319,7 +319,8 @@ constexpr int kReg = 6;    // star entries handled in the unrolled path (a flat 
 __global__ __launch_bounds__(256) void k_contract(const double* __restrict__ I, int64_t ldI, int64_t N,
                                                   const int64_t* __restrict__ dof_ptr, const int32_t* __restrict__ dof_tri,
                                                   const double* __restrict__ dof_J, const int2* __restrict__ tiles,
-                                                  int64_t ntiles, double* __restrict__ W, int64_t ldw) {
+                                                  int64_t ntiles, double* __restrict__ W, float* __restrict__ W32,
+                                                  int64_t ldw) {
     __shared__ double tileT[kCT][kCT + 1];
     // blocks of one XCD (blockIdx % 8) walk a contiguous run of tiles, so neighbouring tiles that
     // re-read the same rows of I meet in that XCD's L2
@@ -381,7 +382,10 @@ __global__ __launch_bounds__(256) void k_contract(const double* __restrict__ I, 
                     }
                 }
             }
-            if (bd != be || e >= d) W[d * ldw + e] = acc;   // columns past N: zero padding
+            if (bd != be || e >= d) {   // columns past N: zero padding
+                W[d * ldw + e] = acc;
+                if (W32) W32[d * ldw + e] = float(acc);
+            }
         }
         tileT[wave * 16 + r][lane] = acc;
     }
@@ -390,7 +394,10 @@ __global__ __launch_bounds__(256) void k_contract(const double* __restrict__ I, 
     for (int q = threadIdx.x; q < kCT * kCT; q += 256) {
         const int re = q / kCT, cd = q % kCT;
         const int64_t em = int64_t(be) * kCT + re, dm = int64_t(bd) * kCT + cd;
-        if (em < N && dm < N && (bd != be || dm < em)) W[em * ldw + dm] = tileT[cd][re];
+        if (em < N && dm < N && (bd != be || dm < em)) {
+            W[em * ldw + dm] = tileT[cd][re];
+            if (W32) W32[em * ldw + dm] = float(tileT[cd][re]);
+        }
     }
 }
 
@@ -412,7 +419,7 @@ __global__ __launch_bounds__(256) void k_contract_staged(
     const int32_t* __restrict__ cb_tri, const int64_t* __restrict__ dof_ptr, const int32_t* __restrict__ col_loc,
     const double* __restrict__ dof_J, const int32_t* __restrict__ rg_ptr, const int4* __restrict__ rg,
     const int2* __restrict__ rg_ent, const int2* __restrict__ tiles, int64_t ntiles, double* __restrict__ W,
-    int64_t ldw) {
+    float* __restrict__ W32, int64_t ldw) {
     __shared__ double acc[kCT][kCT + 1];
     __shared__ double seg[4][kCap];
     const int64_t per = (ntiles + 7) / 8;
@@ -494,19 +501,21 @@ __global__ __launch_bounds__(256) void k_contract_staged(
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const int64_t d = int64_t(bd) * kCT + wave * 16 + r;
-        if (d < N && (bd != be || e >= d)) W[d * ldw + e] = arow[r * (kCT + 1) + lane];
+        if (d < N && (bd != be || e >= d)) {
+            const double v = arow[r * (kCT + 1) + lane];
+            W[d * ldw + e] = v;
+            if (W32) W32[d * ldw + e] = float(v);
+        }
     }
     for (int q = threadIdx.x; q < kCT * kCT; q += 256) {
         const int re = q / kCT, cd = q % kCT;
         const int64_t em = int64_t(be) * kCT + re, dm = int64_t(bd) * kCT + cd;
-        if (em < N && dm < N && (bd != be || dm < em)) W[em * ldw + dm] = acc[cd][re];
+        if (em < N && dm < N && (bd != be || dm < em)) {
+            const double v = acc[cd][re];
+            W[em * ldw + dm] = v;
+            if (W32) W32[em * ldw + dm] = float(v);
+        }
     }
-}
-
-__global__ void k_f64_to_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
-    int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-    int64_t stride = int64_t(gridDim.x) * blockDim.x;
-    for (; i < n; i += stride) b[i] = float(a[i]);
 }
 
 // L[k][d] = -sum over the star of d of c (g_k . n_T) |T| / 3
@@ -780,6 +789,8 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
     // contraction into W; every entry of W, padding columns included, is written by one tile
     p->ldw = ((N + 63) / 64) * 64;
     p->W64 = DeviceBuffer(sizeof(double) * std::max<int64_t>(N, 1) * p->ldw, s);
+    if (p->has_w32) p->W32 = DeviceBuffer(sizeof(float) * std::max<int64_t>(N, 1) * p->ldw, s);
+    float* w32 = p->has_w32 ? p->W32.as<float>() : nullptr;   // the contraction writes both copies
     EventTimer t_contract(s);
     if (N > 0) {
         DeviceBuffer d_cb_ptr = upload(plan.cb_ptr, s), d_cb_tri = upload(plan.cb_tri, s);
@@ -792,24 +803,18 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
             hipLaunchKernelGGL(k_contract_staged, dim3(unsigned((nf + 7) / 8 * 8)), dim3(256), 0, s, p->I.as<double>(), ldI, N,
                                d_cb_ptr.as<int32_t>(), d_cb_tri.as<int32_t>(), p->dof_ptr.as<int64_t>(),
                                d_col_loc.as<int32_t>(), dofJ.as<double>(), d_rg_ptr.as<int32_t>(), d_rg.as<int4>(),
-                               d_rg_ent.as<int2>(), d_fast.as<int2>(), nf, p->W64.as<double>(), p->ldw);
+                               d_rg_ent.as<int2>(), d_fast.as<int2>(), nf, p->W64.as<double>(), w32, p->ldw);
             HIP_CHECK(hipGetLastError());
         }
         if (ns > 0) {
             hipLaunchKernelGGL(k_contract, dim3(unsigned((ns + 7) / 8 * 8)), dim3(256), 0, s, p->I.as<double>(), ldI, N,
                                p->dof_ptr.as<int64_t>(), p->dof_tri.as<int32_t>(), dofJ.as<double>(), d_slow.as<int2>(), ns,
-                               p->W64.as<double>(), p->ldw);
+                               p->W64.as<double>(), w32, p->ldw);
             HIP_CHECK(hipGetLastError());
         }
     }
     t_contract.stop();
     mark("contract");
-    if (p->has_w32) {
-        p->W32 = DeviceBuffer(sizeof(float) * std::max<int64_t>(N, 1) * p->ldw, s);
-        hipLaunchKernelGGL(k_f64_to_f32, dim3(4096), dim3(256), 0, s, p->W64.as<double>(), p->W32.as<float>(), N * p->ldw);
-        HIP_CHECK(hipGetLastError());
-    }
-    mark("fp32 copy");
     p->mv_xt = DeviceBuffer(sizeof(double) * 16 * p->ldw, s);
     p->mv_partial = DeviceBuffer(sizeof(double) * 16 * 16 * p->ldw, s);
     HIP_CHECK(hipStreamSynchronize(s));

@@ -356,8 +356,13 @@ void bem_problem_destroy(bem_problem* p) {
     if (!p) return;
     (void)hipSetDevice(p->ctx->device);
     if (p->stream) (void)hipStreamSynchronize(p->stream);
-    hipStream_t s = p->stream;
+    if (p->aux_stream) (void)hipStreamSynchronize(p->aux_stream);
+    hipStream_t s = p->stream, s2 = p->aux_stream;
     delete p;
+    if (s2) {
+        std::lock_guard<std::mutex> cap(capture_mutex());
+        (void)hipStreamDestroy(s2);
+    }
     if (s) {
         std::lock_guard<std::mutex> cap(capture_mutex());
         (void)hipStreamDestroy(s);

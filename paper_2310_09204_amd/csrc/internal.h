@@ -137,6 +137,19 @@ DeviceBuffer upload(const std::vector<T>& v, hipStream_t s) {
     return b;
 }
 
+// First failure of a parallel pass, kept by smallest position so the reported error does not depend
+// on thread timing.
+struct FirstFailure {
+    std::mutex mu;
+    int64_t pos = -1;
+    Failure f{0, ""};
+    void record(int64_t where, const Failure& x) {
+        std::lock_guard<std::mutex> lk(mu);
+        if (pos < 0 || where < pos) { pos = where; f = x; }
+    }
+    void rethrow() const { if (pos >= 0) throw f; }
+};
+
 // Runs fn(begin, end) over [0, n) split across a few host threads (at most 16); every range but
 // the last starts at a multiple of grain.  fn must not throw.
 template <class Fn>
@@ -168,6 +181,7 @@ struct bem_problem {
     bem_ctx* ctx = nullptr;
     bem::MeshTopo topo;
     int64_t N = 0, ldw = 0, ldI = 0, n_near = 0;
+    hipStream_t aux_stream = nullptr;   // second stream of the preconditioner set-up (created on first use)
     bool has_w32 = false, has_pairs = false;
     int near_order = 10;
     hipStream_t stream = nullptr;

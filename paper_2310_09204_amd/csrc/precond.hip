@@ -49,39 +49,6 @@ __device__ __forceinline__ void tile_store(const double* __restrict__ s, double*
     }
 }
 
-// acc (this thread's 4x4 piece of a 64x64 tile) += op(A) op(B), 256 threads
-template <bool TA, bool TB>
-__device__ __forceinline__ void tile_mac(double (&acc)[4][4], const double* __restrict__ A, const double* __restrict__ B) {
-    const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
-#pragma unroll 4
-    for (int l = 0; l < TBK; ++l) {
-        double a[4], b[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) a[i] = TA ? A[l * LDT + tr * 4 + i] : A[(tr * 4 + i) * LDT + l];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) b[j] = TB ? B[(tc * 4 + j) * LDT + l] : B[l * LDT + tc * 4 + j];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
-    }
-}
-
-__device__ __forceinline__ void acc_zero(double (&acc)[4][4]) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-}
-
-__device__ __forceinline__ void acc_to_lds(const double (&acc)[4][4], double* __restrict__ s, double scale) {
-    const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) s[(tr * 4 + i) * LDT + tc * 4 + j] = scale * acc[i][j];
-}
-
 // C (64 x 64) = op(A) op(B) on the FP64 matrix cores, from two LDS tiles.  Wave w computes rows
 // 16w .. 16w+15 as four 16x16 output tiles n = 0..3; lane l = 16 kk + i supplies A[16w+i][k0+kk] and
 // B[k0+kk][16n+i] to each 16x16x4 step, and register r of acc[n] holds C[16w + kk + 4r][16n + i].
@@ -139,187 +106,206 @@ __global__ __launch_bounds__(256) void k_gather(const int4* __restrict__ tasks, 
     }
 }
 
-// --- Cholesky of the diagonal tile of step k and the inverse of its factor --------------------
-// Factor: the first wave alone, lane i owning row i, left-looking (Crout) column by column, so the
-// column sweep needs no block barrier: L_ij = (A_ij - sum_{l<j} L_il L_jl) / L_jj.  Inverse
-// Y = L^{-1}: all 256 threads, four lanes per column c splitting each row's dot product, rows in
-// order (Y_rc = (delta_rc - sum_{c<=l<r} L_rl Y_lc) / L_rr).  L_kk goes back to A, Y to X (the
-// diagonal tiles of the inverse factor, used by this step's triangular solves and the inversion).
-__global__ __launch_bounds__(256) void k_potrf(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
-                                               double* __restrict__ A, double* __restrict__ X, int k, int* __restrict__ flags) {
-    __shared__ double L[TBK * LDT];
-    __shared__ double Y[TBK * LDT];
-    __shared__ double rinv[TBK];
-    const int4 t = tasks[blockIdx.x];
-    const BlockMeta m = meta[t.x];
-    const int64_t off = m.mat_off + int64_t(k) * TBK * m.npad + int64_t(k) * TBK;
-    tile_load(L, A + off, m.npad);
-    __syncthreads();
-    if (threadIdx.x < TBK) {
-        const int i = threadIdx.x;
-        bool bad = false;
-        for (int j = 0; j < TBK; ++j) {
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-            if (i >= j) {
-                int l = 0;
-                for (; l + 3 < j; l += 4) {
-                    s0 = fma(L[i * LDT + l], L[j * LDT + l], s0);
-                    s1 = fma(L[i * LDT + l + 1], L[j * LDT + l + 1], s1);
-                    s2 = fma(L[i * LDT + l + 2], L[j * LDT + l + 2], s2);
-                    s3 = fma(L[i * LDT + l + 3], L[j * LDT + l + 3], s3);
-                }
-                for (; l < j; ++l) s0 = fma(L[i * LDT + l], L[j * LDT + l], s0);
+// --- block Gauss-Jordan inversion ---------------------------------------------------------------
+// Each block B (a face, the wire basket, the coarse Galerkin matrix; SPD, padded with the identity)
+// is overwritten by its inverse.  Step k of the elimination, with P = (S_kk)^{-1} of the current
+// state S:  S_kj <- P S_kj (row k),  S_ik <- -S_ik P (column k),  S_ij <- S_ij - S_ik P S_kj
+// (i, j != k),  S_kk <- P.  Pivot blocks of an SPD matrix stay SPD, so no pivoting is needed.
+// The state keeps a signed symmetry: S_ij = s S_ji^T with s = -1 exactly when one of i, j has been
+// eliminated, so only the lower tiles (i >= j) are stored and updated; an upper tile is read as the
+// signed transpose of its mirror.  At the end every index is eliminated and the lower tiles hold
+// the (symmetric) inverse, which is then mirrored into the upper tiles.
+// A step is two launches.  k_gj_row stages, for every j != k, the old column value C_j = S_jk and
+// the new row value R_j = P S_kj, and the new column tile -S_jk P for j > k.  k_gj_update applies
+// S_ij -= C_i R_j to the lower tiles off row and column k and copies the new row / column / pivot
+// tiles in; the block that updates tile (k+1, k+1) also inverts it, so the next step's pivot
+// inverse is ready when its row launch starts.  No launch writes a tile that it also reads.
+
+// In-place inverse of the 64 x 64 tile T (LDS, row stride LDT) by scalar Gauss-Jordan without
+// pivoting.  Thread (tr, tc) keeps rows 4tr..4tr+3 x columns 4tc..4tc+3 in registers; each step
+// publishes the pivot row and column through LDS (double-buffered, one barrier per step).  Returns
+// false if a pivot was not positive and finite (then the tile is not SPD).
+__device__ bool tile_inverse_gj(double* __restrict__ T, double* __restrict__ rowbuf, double* __restrict__ colbuf) {
+    const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
+    double a[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) a[r][c] = T[(4 * tr + r) * LDT + 4 * tc + c];
+    bool ok = true;
+    for (int q = 0; q < TBK / 4; ++q) {
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int kk = 4 * q + rr;
+            double* rb = rowbuf + (kk & 1) * TBK;
+            double* cb = colbuf + (kk & 1) * TBK;
+            if (tr == q) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) rb[4 * tc + c] = a[rr][c];
             }
-            const double sij = L[i * LDT + j] - ((s0 + s1) + (s2 + s3));
-            if (i == j) {
-                double d = sij;
-                if (!(d > 0.0) || !isfinite(d)) {
-                    bad = true;
-                    d = 1.0;
-                }
-                L[j * LDT + j] = sqrt(d);
+            if (tc == q) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) cb[4 * tr + r] = a[r][rr];
             }
-            __builtin_amdgcn_wave_barrier();   // the pivot written by lane j is read below (same wave)
-            const double piv = L[j * LDT + j];
-            if (i > j) L[i * LDT + j] = sij / piv;
-            __builtin_amdgcn_wave_barrier();
-        }
-        if (bad) flags[t.x] = 1;
-        rinv[i] = 1.0 / L[i * LDT + i];
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < TBK * TBK; e += blockDim.x) {
-        const int r = e >> 6, c = e & 63;
-        if (c > r) L[r * LDT + c] = 0.0;
-        if (r < c) Y[r * LDT + c] = 0.0;
-    }
-    __syncthreads();
-    {
-        const int c = threadIdx.x >> 2, q = threadIdx.x & 3;   // the four lanes of a column share a wave
-        for (int r = c; r < TBK; ++r) {
-            double sacc = 0.0;
-            for (int l = c + q; l < r; l += 4) sacc = fma(-L[r * LDT + l], Y[l * LDT + c], sacc);
-            sacc += __shfl_xor(sacc, 1, 64);
-            sacc += __shfl_xor(sacc, 2, 64);
-            if (q == 0) Y[r * LDT + c] = ((r == c ? 1.0 : 0.0) + sacc) * rinv[r];
-            __builtin_amdgcn_wave_barrier();   // Y[r][c] is read by the other lanes of the quad next
+            __syncthreads();
+            const double piv = rb[kk];
+            ok = ok && (piv > 0.0) && isfinite(piv);
+            const double pinv = 1.0 / piv;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = 4 * tr + r;
+                const double aik = cb[i] * pinv;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int j = 4 * tc + c;
+                    const double akj = rb[j];
+                    double v;
+                    if (i == kk) v = (j == kk) ? pinv : akj * pinv;
+                    else if (j == kk) v = -aik;
+                    else v = fma(-aik, akj, a[r][c]);
+                    a[r][c] = v;
+                }
+            }
         }
     }
     __syncthreads();
-    tile_store(L, A + off, m.npad);
-    tile_store(Y, X + off, m.npad);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) T[(4 * tr + r) * LDT + 4 * tc + c] = a[r][c];
+    __syncthreads();
+    return ok;
 }
 
-// --- A_ik <- A_ik L_kk^{-T} for the tiles below the diagonal of step k (a product with the
-//     inverse factor tile from k_potrf) ----------------------------------------------------------
-__global__ __launch_bounds__(256) void k_trsm(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
-                                              double* __restrict__ A, const double* __restrict__ X, int k) {
+// tile (row i, column j) of block m, row stride npad
+__device__ __forceinline__ double* tile_at(double* a0, const BlockMeta& m, int i, int j) {
+    return a0 + int64_t(i) * TBK * m.npad + int64_t(j) * TBK;
+}
+
+// LDS tile <- sign * G^T (G a 64 x 64 tile in global memory with row stride ld)
+__device__ __forceinline__ void tile_load_t(double* __restrict__ s, const double* __restrict__ g, int64_t ld, double sign) {
+    for (int e = threadIdx.x; e < TBK * TBK; e += blockDim.x) {
+        const int r = e >> 6, c = e & 63;
+        s[c * LDT + r] = sign * g[int64_t(r) * ld + c];
+    }
+}
+
+// scratch of block b: C_j (old column values), R_j (new row values), D_j (new column tiles), and
+// the pivot inverse, at 3 npad x 64 per block, then one pivot tile per block
+__device__ __forceinline__ double* gj_C(double* scr, const BlockMeta& m, int j) { return scr + 3 * m.xoff * TBK + int64_t(j) * TBK * TBK; }
+__device__ __forceinline__ double* gj_R(double* scr, const BlockMeta& m, int j) { return scr + (3 * m.xoff + m.npad) * TBK + int64_t(j) * TBK * TBK; }
+__device__ __forceinline__ double* gj_D(double* scr, const BlockMeta& m, int j) { return scr + (3 * m.xoff + 2 * m.npad) * TBK + int64_t(j) * TBK * TBK; }
+
+// the pivot inverse of step k lives in slot k % 2 of the block's two pivot tiles (the update
+// launch of step k copies slot k % 2 while it writes slot (k+1) % 2)
+__device__ __forceinline__ double* gj_piv(double* scr, int64_t pivot_off, int b, int k) {
+    return scr + pivot_off + (int64_t(b) * 2 + (k & 1)) * TBK * TBK;
+}
+
+// step k, task (b, k, j), j != k (step 0 also has j = k): the staging for column j.  The pivot
+// inverse comes from the previous update launch; at step 0 every task inverts the first pivot
+// tile itself and task j = 0 keeps it.
+__global__ __launch_bounds__(256) void k_gj_row(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
+                                                double* __restrict__ A, double* __restrict__ scr, int64_t pivot_off,
+                                                int k, int* __restrict__ flags) {
     __shared__ double P[TBK * LDT];
     __shared__ double Q[TBK * LDT];
+    __shared__ double rowbuf[2 * TBK], colbuf[2 * TBK];
     const int4 t = tasks[blockIdx.x];
     const BlockMeta m = meta[t.x];
-    const int i = t.y;
-    double* gik = A + m.mat_off + int64_t(i) * TBK * m.npad + int64_t(k) * TBK;
-    tile_load(P, gik, m.npad);
-    tile_load(Q, X + m.mat_off + int64_t(k) * TBK * m.npad + int64_t(k) * TBK, m.npad);
+    const int j = t.z;
+    double* a0 = A + m.mat_off;
+    double* piv = gj_piv(scr, pivot_off, t.x, k);
+    if (k == 0) {
+        tile_load(P, tile_at(a0, m, 0, 0), m.npad);
+        __syncthreads();
+        const bool ok = tile_inverse_gj(P, rowbuf, colbuf);
+        if (j == 0) {
+            if (!ok && threadIdx.x == 0) flags[t.x] = 1;
+            tile_store(P, piv, TBK);
+            return;
+        }
+    } else {
+        tile_load(P, piv, TBK);
+    }
+    // S_kj (row value) and S_jk (old column value) from the stored lower tile of the pair
+    if (j < k) tile_load(Q, tile_at(a0, m, k, j), m.npad);           // S_kj stored
+    else tile_load_t(Q, tile_at(a0, m, j, k), m.npad, 1.0);           // S_kj = S_jk^T (both uneliminated)
     __syncthreads();
     f64x4 acc[4];
     mfma_zero(acc);
-    tile_mfma<false, true>(acc, P, Q);
-    mfma_store(acc, gik, m.npad, 1.0, false);
+    tile_mfma<false, false>(acc, P, Q);                                // R_j = P S_kj
+    mfma_store(acc, gj_R(scr, m, j), TBK, 1.0, false);
+    __syncthreads();
+    if (j < k) tile_load_t(Q, tile_at(a0, m, k, j), m.npad, -1.0);   // S_jk = -S_kj^T (j eliminated)
+    else tile_load(Q, tile_at(a0, m, j, k), m.npad);                  // S_jk stored
+    __syncthreads();
+    tile_store(Q, gj_C(scr, m, j), TBK);
+    if (j > k) {
+        mfma_zero(acc);
+        tile_mfma<false, false>(acc, Q, P);                            // new column tile -S_jk P
+        mfma_store(acc, gj_D(scr, m, j), TBK, -1.0, false);
+    }
 }
 
-// --- trailing update A_ij -= A_ik A_jk^T, j <= i, of step k ---------------------------------
-__global__ __launch_bounds__(256) void k_update(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
-                                                double* __restrict__ A, int k) {
+// step k, task (b, i, j), i >= j: trailing update S_ij -= C_i R_j (i, j != k), or the copy of the new
+// row tile (i = k > j), column tile (i > k = j) or pivot inverse (i = j = k).  The task for tile
+// (k+1, k+1) also inverts the updated tile: the pivot inverse of step k+1.
+__global__ __launch_bounds__(256) void k_gj_update(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
+                                                   double* __restrict__ A, double* __restrict__ scr, int64_t pivot_off,
+                                                   int k, int* __restrict__ flags) {
     __shared__ double P[TBK * LDT];
     __shared__ double Q[TBK * LDT];
+    __shared__ double rowbuf[2 * TBK], colbuf[2 * TBK];
     const int4 t = tasks[blockIdx.x];
     const BlockMeta m = meta[t.x];
     const int i = t.y, j = t.z;
     double* a0 = A + m.mat_off;
-    tile_load(P, a0 + int64_t(i) * TBK * m.npad + int64_t(k) * TBK, m.npad);
-    tile_load(Q, a0 + int64_t(j) * TBK * m.npad + int64_t(k) * TBK, m.npad);
-    __syncthreads();
-    f64x4 acc[4];
-    mfma_zero(acc);
-    tile_mfma<false, true>(acc, P, Q);
-    mfma_store(acc, a0 + int64_t(i) * TBK * m.npad + int64_t(j) * TBK, m.npad, -1.0, true);
-}
-
-// --- off-diagonal tiles of X = L^{-1}, right-looking: X_ij accumulates S_ij = sum_{m<i} L_im X_mj
-//     as soon as each X_mj is final; at step i the row is finished with X_ij = -X_ii S_ij ---------
-__global__ __launch_bounds__(256) void k_trtri_finish(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
-                                                      double* __restrict__ X, int i) {
-    __shared__ double P[TBK * LDT];
-    __shared__ double Q[TBK * LDT];
-    const int4 t = tasks[blockIdx.x];
-    const BlockMeta m = meta[t.x];
-    const int j = t.y;
-    double* x0 = X + m.mat_off;
-    double* gij = x0 + int64_t(i) * TBK * m.npad + int64_t(j) * TBK;
-    tile_load(P, x0 + int64_t(i) * TBK * m.npad + int64_t(i) * TBK, m.npad);
-    tile_load(Q, gij, m.npad);
-    __syncthreads();
-    f64x4 acc[4];
-    mfma_zero(acc);
-    tile_mfma<false, false>(acc, P, Q);
-    mfma_store(acc, gij, m.npad, -1.0, false);
-}
-
-// S_{i'j} += L_{i'i} X_ij for all i' > i, j <= i (tasks carry i', j)
-__global__ __launch_bounds__(256) void k_trtri_update(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
-                                                      const double* __restrict__ A, double* __restrict__ X, int i) {
-    __shared__ double P[TBK * LDT];
-    __shared__ double Q[TBK * LDT];
-    const int4 t = tasks[blockIdx.x];
-    const BlockMeta m = meta[t.x];
-    const int ip = t.y, j = t.z;
-    tile_load(P, A + m.mat_off + int64_t(ip) * TBK * m.npad + int64_t(i) * TBK, m.npad);
-    tile_load(Q, X + m.mat_off + int64_t(i) * TBK * m.npad + int64_t(j) * TBK, m.npad);
-    __syncthreads();
-    f64x4 acc[4];
-    mfma_zero(acc);
-    tile_mfma<false, false>(acc, P, Q);
-    mfma_store(acc, X + m.mat_off + int64_t(ip) * TBK * m.npad + int64_t(j) * TBK, m.npad, 1.0, true);
-}
-
-__global__ void k_zero(double* __restrict__ a, int64_t n) {
-    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) a[i] = 0.0;
-}
-
-// --- B = X^T X (lower tiles computed, mirrored), written over A ------------------------------
-__global__ __launch_bounds__(256) void k_syrk_inverse(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
-                                                      const double* __restrict__ X, double* __restrict__ B) {
-    __shared__ double P[TBK * LDT];
-    __shared__ double Q[TBK * LDT];
-    const int4 t = tasks[blockIdx.x];
-    const BlockMeta m = meta[t.x];
-    const int i = t.y, j = t.z;     // i >= j
-    const int nt = int(m.npad / TBK);
-    const double* x0 = X + m.mat_off;
-    f64x4 acc[4];
-    mfma_zero(acc);
-    for (int mm = i; mm < nt; ++mm) {
-        tile_load(P, x0 + int64_t(mm) * TBK * m.npad + int64_t(i) * TBK, m.npad);
-        tile_load(Q, x0 + int64_t(mm) * TBK * m.npad + int64_t(j) * TBK, m.npad);
-        __syncthreads();
-        tile_mfma<true, false>(acc, P, Q);
-        __syncthreads();
+    double* gij = tile_at(a0, m, i, j);
+    if (i == k || j == k) {
+        const double* src = (i == k && j == k) ? gj_piv(scr, pivot_off, t.x, k) : (i == k) ? gj_R(scr, m, j) : gj_D(scr, m, i);
+        for (int e = threadIdx.x; e < TBK * TBK; e += blockDim.x) gij[int64_t(e >> 6) * m.npad + (e & 63)] = src[e];
+        return;
     }
-    double* b0 = B + m.mat_off;
-    // tile (i, j) directly; its transpose through LDS (P is free after the loop) for (j, i)
-    mfma_store(acc, b0 + int64_t(i) * TBK * m.npad + int64_t(j) * TBK, m.npad, 1.0, false);
-    if (i != j) {
+    tile_load(P, gj_C(scr, m, i), TBK);
+    tile_load(Q, gj_R(scr, m, j), TBK);
+    __syncthreads();
+    f64x4 acc[4];
+    mfma_zero(acc);
+    tile_mfma<false, false>(acc, P, Q);
+    if (!(i == k + 1 && j == k + 1)) {
+        mfma_store(acc, gij, m.npad, -1.0, true);
+        return;
+    }
+    // next pivot: update the tile in LDS, store it, and invert it into slot (k+1) % 2
+    __syncthreads();
+    tile_load(P, gij, m.npad);
+    __syncthreads();
+    {
         const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
         const int ii = lane & 15, kk = lane >> 4;
 #pragma unroll
         for (int n = 0; n < 4; ++n)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) P[(16 * n + ii) * LDT + 16 * w + kk + 4 * r] = acc[n][r];
-        __syncthreads();
-        tile_store(P, b0 + int64_t(j) * TBK * m.npad + int64_t(i) * TBK, m.npad);
+            for (int r = 0; r < 4; ++r) P[(16 * w + kk + 4 * r) * LDT + 16 * n + ii] -= acc[n][r];
     }
+    __syncthreads();
+    tile_store(P, gij, m.npad);
+    const bool ok = tile_inverse_gj(P, rowbuf, colbuf);
+    if (!ok && threadIdx.x == 0) flags[t.x] = 1;
+    tile_store(P, gj_piv(scr, pivot_off, t.x, k + 1), TBK);
+}
+
+// the inverse is symmetric: upper tiles (i < j) from the lower ones
+__global__ __launch_bounds__(256) void k_mirror(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
+                                                double* __restrict__ A) {
+    __shared__ double Q[TBK * LDT];
+    const int4 t = tasks[blockIdx.x];
+    const BlockMeta m = meta[t.x];
+    double* a0 = A + m.mat_off;
+    tile_load_t(Q, tile_at(a0, m, t.y, t.z), m.npad, 1.0);
+    __syncthreads();
+    tile_store(Q, tile_at(a0, m, t.z, t.y), m.npad);
 }
 
 __global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
@@ -329,26 +315,33 @@ __global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, in
 }
 
 // --- coarse Galerkin matrix: Y = W R_H^T, then W_H = R_H Y (upper half, mirrored) ------------
-// Z = R_H W, one coarse dof per blockIdx.y and a 1024-column slice per blockIdx.x: the block sums
-// the W rows of the coarse function's fine support, weighted by R_H, with coalesced row reads.
-// (W is symmetric, so Z^T = W R_H^T.)
-__global__ __launch_bounds__(256) void k_coarse_Z(const double* __restrict__ W, int64_t ldw, int64_t N,
-                                                  const int64_t* __restrict__ rp, const int32_t* __restrict__ rc,
-                                                  const double* __restrict__ rv, double* __restrict__ Z) {
-    const int64_t i = blockIdx.y;
-    const int64_t c0 = int64_t(blockIdx.x) * 1024 + threadIdx.x;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+// Z = R_H W: block t takes coarse dof i and a 512-column slice c of W and sums the W rows of the
+// coarse function's fine support, weighted by R_H, with coalesced row reads.  Blocks of one XCD
+// (blockIdx % 8) walk a contiguous run of t, and t runs over the coarse dofs of one slice before
+// the next slice, so coarse functions with overlapping supports (neighbouring coarse vertices)
+// re-read the same W rows from that XCD's L2.  (W is symmetric, so Z^T = W R_H^T.)
+constexpr int kZCols = 512;
+__global__ __launch_bounds__(256) void k_coarse_Z(const double* __restrict__ W, int64_t ldw, int64_t N, int64_t nH,
+                                                  int64_t nblocks, const int64_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ rc, const double* __restrict__ rv,
+                                                  double* __restrict__ Z) {
+    const int64_t per = (nblocks + 7) / 8;
+    const int64_t t = int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (t >= nblocks) return;
+    const int64_t i = t % nH;
+    const int64_t c0 = (t / nH) * kZCols + threadIdx.x;
+    double acc[2] = {0.0, 0.0};
     for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
         const double v = rv[e];
         const double* w = W + int64_t(rc[e]) * ldw;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 2; ++u) {
             const int64_t c = c0 + 256 * u;
             if (c < N) acc[u] = fma(v, w[c], acc[u]);
         }
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < 2; ++u) {
         const int64_t c = c0 + 256 * u;
         if (c < N) Z[i * N + c] = acc[u];
     }
@@ -505,69 +498,102 @@ void build_prolongation(const MeshTopo& f, const MeshTopo& c, const int32_t* par
                 int64_t slot = soff[v] + f.sector[(t * 3 + a) * 2 + s];
                 if (rep[slot] < 0) rep[slot] = (t * 3 + a) * 2 + s;
             }
-    std::vector<std::vector<std::pair<int32_t, double>>> rows(c.N);
-    std::map<int64_t, std::vector<double>> u;
-    for (int64_t k = 0; k < f.nv; ++k) {
-        const int qk = f.q[k];
-        if (qk < 2) continue;
-        u.clear();
-        const double xk[3] = {f.V[3 * k], f.V[3 * k + 1], f.V[3 * k + 2]};
-        for (int l = 0; l < qk; ++l) {
-            const int64_t node = rep[soff[k] + l];
-            const int64_t t = node / 6;
-            const int s = int(node % 2);
-            const int64_t tc = parent[t];
-            double nd = 0;
-            for (int d = 0; d < 3; ++d) nd += f.normal[3 * t + d] * c.normal[3 * tc + d];
-            const int sc = nd > 0 ? s : 1 - s;
-            const double* P0 = &c.V[3 * int64_t(c.T[3 * tc])];
-            const double* P1 = &c.V[3 * int64_t(c.T[3 * tc + 1])];
-            const double* P2 = &c.V[3 * int64_t(c.T[3 * tc + 2])];
-            double e1[3], e2[3], rr[3];
-            for (int d = 0; d < 3; ++d) { e1[d] = P1[d] - P0[d]; e2[d] = P2[d] - P0[d]; rr[d] = xk[d] - P0[d]; }
-            const double g11 = e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2];
-            const double g12 = e1[0] * e2[0] + e1[1] * e2[1] + e1[2] * e2[2];
-            const double g22 = e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2];
-            const double b1 = e1[0] * rr[0] + e1[1] * rr[1] + e1[2] * rr[2];
-            const double b2 = e2[0] * rr[0] + e2[1] * rr[1] + e2[2] * rr[2];
-            const double det = g11 * g22 - g12 * g12;
-            const double l1 = (b1 * g22 - b2 * g12) / det, l2 = (g11 * b2 - g12 * b1) / det;
-            const double lam[3] = {1.0 - l1 - l2, l1, l2};
-            double off = 0;   // distance of x_k from the plane of the coarse triangle
-            for (int d = 0; d < 3; ++d) { double p = rr[d] - l1 * e1[d] - l2 * e2[d]; off += p * p; }
-            if (lam[0] < -1e-9 || lam[1] < -1e-9 || lam[2] < -1e-9 || off > 1e-18 * (g11 + g22))
-                fail(BEM_E_INVALID_ARG, "fine triangle " + std::to_string(t) + " is not inside its coarse triangle");
-            for (int ac = 0; ac < 3; ++ac) {
-                if (std::fabs(lam[ac]) < 1e-12) continue;
-                const int64_t i = c.T[3 * tc + ac];
-                const int qi = c.q[i];
-                const int jc = c.sector[(tc * 3 + ac) * 2 + sc];
-                for (int j = 0; j + 1 < qi; ++j) {
-                    const double sign = (jc == j) ? 1.0 : (jc == qi - 1 ? -1.0 : 0.0);
-                    if (sign == 0.0) continue;
-                    auto& vec = u[c.first_dof[i] + j];
-                    if (vec.empty()) vec.assign(qk, 0.0);
-                    vec[l] += lam[ac] * sign;
+    // entries (coarse dof, fine dof, value), produced per fine vertex on parallel threads; each
+    // thread range keeps vertex order, so concatenating the ranges keeps it too
+    struct Entry { int32_t i, col; double v; };
+    const int64_t grain = 512;
+    const int64_t nchunk = (f.nv + grain - 1) / grain;
+    std::vector<std::vector<Entry>> part(size_t(std::max<int64_t>(nchunk, 1)));
+    FirstFailure ff;
+    parallel_for(nchunk, [&](int64_t cb, int64_t ce) {
+        struct Acc { int64_t dof; double u[64]; };
+        std::vector<Acc> u;
+        for (int64_t ch = cb; ch < ce; ++ch) {
+            std::vector<Entry>& out = part[size_t(ch)];
+            for (int64_t k = ch * grain; k < std::min<int64_t>(f.nv, (ch + 1) * grain); ++k) {
+                const int qk = f.q[k];
+                if (qk < 2) continue;
+                try {
+                    if (qk > 64) fail(BEM_E_UNSUPPORTED, "more than 64 sectors at a vertex");
+                    u.clear();
+                    const double xk[3] = {f.V[3 * k], f.V[3 * k + 1], f.V[3 * k + 2]};
+                    for (int l = 0; l < qk; ++l) {
+                        const int64_t node = rep[soff[k] + l];
+                        const int64_t t = node / 6;
+                        const int s = int(node % 2);
+                        const int64_t tc = parent[t];
+                        double nd = 0;
+                        for (int d = 0; d < 3; ++d) nd += f.normal[3 * t + d] * c.normal[3 * tc + d];
+                        const int sc = nd > 0 ? s : 1 - s;
+                        const double* P0 = &c.V[3 * int64_t(c.T[3 * tc])];
+                        const double* P1 = &c.V[3 * int64_t(c.T[3 * tc + 1])];
+                        const double* P2 = &c.V[3 * int64_t(c.T[3 * tc + 2])];
+                        double e1[3], e2[3], rr[3];
+                        for (int d = 0; d < 3; ++d) { e1[d] = P1[d] - P0[d]; e2[d] = P2[d] - P0[d]; rr[d] = xk[d] - P0[d]; }
+                        const double g11 = e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2];
+                        const double g12 = e1[0] * e2[0] + e1[1] * e2[1] + e1[2] * e2[2];
+                        const double g22 = e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2];
+                        const double b1 = e1[0] * rr[0] + e1[1] * rr[1] + e1[2] * rr[2];
+                        const double b2 = e2[0] * rr[0] + e2[1] * rr[1] + e2[2] * rr[2];
+                        const double det = g11 * g22 - g12 * g12;
+                        const double l1 = (b1 * g22 - b2 * g12) / det, l2 = (g11 * b2 - g12 * b1) / det;
+                        const double lam[3] = {1.0 - l1 - l2, l1, l2};
+                        double off = 0;   // distance of x_k from the plane of the coarse triangle
+                        for (int d = 0; d < 3; ++d) { double pp = rr[d] - l1 * e1[d] - l2 * e2[d]; off += pp * pp; }
+                        if (lam[0] < -1e-9 || lam[1] < -1e-9 || lam[2] < -1e-9 || off > 1e-18 * (g11 + g22))
+                            fail(BEM_E_INVALID_ARG, "fine triangle " + std::to_string(t) + " is not inside its coarse triangle");
+                        for (int ac = 0; ac < 3; ++ac) {
+                            if (std::fabs(lam[ac]) < 1e-12) continue;
+                            const int64_t i = c.T[3 * tc + ac];
+                            const int qi = c.q[i];
+                            const int jc = c.sector[(tc * 3 + ac) * 2 + sc];
+                            for (int j = 0; j + 1 < qi; ++j) {
+                                const double sign = (jc == j) ? 1.0 : (jc == qi - 1 ? -1.0 : 0.0);
+                                if (sign == 0.0) continue;
+                                const int64_t dof = c.first_dof[i] + j;
+                                Acc* a = nullptr;
+                                for (auto& x : u) if (x.dof == dof) { a = &x; break; }
+                                if (!a) {
+                                    u.push_back(Acc{dof, {}});
+                                    a = &u.back();
+                                    for (int q = 0; q < qk; ++q) a->u[q] = 0.0;
+                                }
+                                a->u[l] += lam[ac] * sign;
+                            }
+                        }
+                    }
+                    std::sort(u.begin(), u.end(), [](const Acc& x, const Acc& y) { return x.dof < y.dof; });
+                    for (auto& a : u) {
+                        double mean = 0;
+                        for (int q = 0; q < qk; ++q) mean += a.u[q];
+                        mean /= qk;
+                        for (int l = 0; l + 1 < qk; ++l) {
+                            const double cv = a.u[l] - mean;
+                            if (cv != 0.0) out.push_back(Entry{int32_t(a.dof), int32_t(f.first_dof[k] + l), cv});
+                        }
+                    }
+                } catch (const Failure& x) {
+                    ff.record(k, x);
                 }
             }
         }
-        for (auto& kv : u) {
-            double mean = 0;
-            for (double x : kv.second) mean += x;
-            mean /= qk;
-            for (int l = 0; l + 1 < qk; ++l) {
-                const double cv = kv.second[l] - mean;
-                if (cv != 0.0) rows[kv.first].push_back({int32_t(f.first_dof[k] + l), cv});
-            }
-        }
-    }
+    }, 1);
+    ff.rethrow();
+    // CSR by coarse dof; within a row the fine dofs come in vertex (hence dof) order
     R.nH = c.N;
     R.ptr.assign(c.N + 1, 0);
-    for (int64_t i = 0; i < c.N; ++i) {
-        std::sort(rows[i].begin(), rows[i].end());
-        R.ptr[i + 1] = R.ptr[i] + int64_t(rows[i].size());
-        for (auto& e : rows[i]) { R.col.push_back(e.first); R.val.push_back(e.second); }
-    }
+    for (auto& pv : part)
+        for (auto& e : pv) R.ptr[e.i + 1] += 1;
+    for (int64_t i = 0; i < c.N; ++i) R.ptr[i + 1] += R.ptr[i];
+    R.col.assign(size_t(R.ptr[c.N]), 0);
+    R.val.assign(size_t(R.ptr[c.N]), 0.0);
+    std::vector<int64_t> fill(R.ptr.begin(), R.ptr.end() - 1);
+    for (auto& pv : part)
+        for (auto& e : pv) {
+            const int64_t at = fill[e.i]++;
+            R.col[size_t(at)] = e.col;
+            R.val[size_t(at)] = e.v;
+        }
 }
 
 }  // namespace
@@ -606,6 +632,7 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
         if (vpatch[v] >= 0 && f.q[v] == 2) faces[vpatch[v]].push_back(int32_t(d));
         else wb.push_back(int32_t(d));
     }
+    mark("dof classes");
     std::vector<std::vector<int32_t>> blocks;
     for (auto& kv : faces) blocks.push_back(kv.second);
     M->n_faces = int64_t(blocks.size());
@@ -615,18 +642,21 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
     for (int64_t b = 0; b < M->n_faces; ++b) M->max_face = std::max<int64_t>(M->max_face, blocks[b].size());
     M->nblocks = int64_t(blocks.size());
 
-    // ---- coarse space -----------------------------------------------------------------------------
+    // ---- coarse mesh (its sectors give the coarse dimension; the prolongation is built later,
+    //      while the device works on the faces and the wire basket) ----------------------------------
     CoarseCSR R;
-    if (M->use_coarse && ncv > 0 && nct > 0) {
+    MeshTopo c;
+    const bool coarse = M->use_coarse && ncv > 0 && nct > 0;
+    if (coarse) {
         if (!cV || !cT || !parent) fail(BEM_E_INVALID_ARG, "coarse mesh arrays missing");
         for (int64_t t = 0; t < f.nt; ++t)
             if (parent[t] < 0 || parent[t] >= nct) fail(BEM_E_INVALID_ARG, "coarse_of_triangle out of range");
-        MeshTopo c;
         analyze_mesh(cV, ncv, cT, nct, c);
-        build_prolongation(f, c, parent, R);
+        M->nH = c.N;
+    } else {
+        M->nH = 0;
     }
-    M->nH = R.nH;
-    mark("classes+coarse host");
+    mark("coarse mesh analysis");
 
     // ---- block layout (faces, wire basket, then the coarse block) -----------------------------------
     const int64_t nall = M->nblocks + (M->nH > 0 ? 1 : 0);
@@ -651,92 +681,93 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
     M->mat_total = moff;
     M->idx = upload(idx, s);
     M->blk_meta = upload(meta, s);
-    DeviceBuffer A(sizeof(double) * std::max<int64_t>(moff, 1), s), X(sizeof(double) * std::max<int64_t>(moff, 1), s);
+    DeviceBuffer A(sizeof(double) * std::max<int64_t>(moff, 1), s);
+    // Gauss-Jordan scratch: per block its staged tiles (3 x npad x 64), then two pivot tiles each
+    const int64_t pivot_off = 3 * xoff * TBK;
+    DeviceBuffer scr(sizeof(double) * (pivot_off + nall * 2 * TBK * TBK), s);
     DeviceBuffer dflags(sizeof(int) * std::max<int64_t>(nall, 1), s);
     HIP_CHECK(hipMemsetAsync(dflags.ptr, 0, sizeof(int) * std::max<int64_t>(nall, 1), s));
 
     const BlockMeta* dm = M->blk_meta.as<BlockMeta>();
 
-    // ---- every tile task of the set-up, planned on the host and uploaded once ------------------
-    enum Kind { GATHER, POTRF, TRSM, UPDATE, TRTRI_FINISH, TRTRI_UPDATE, SYRK };
+    // ---- every tile task of the set-up, planned on the host and uploaded once.  Two plans: the
+    //      faces and the wire basket (problem stream), and the coarse block (second stream, after
+    //      its Galerkin matrix) -----------------------------------------------------------------------
+    enum Kind { GATHER, GJ_ROW, GJ_UPDATE, MIRROR };
     struct Launch { Kind kind; int param; int64_t off, n; };
     std::vector<int4> all;
-    std::vector<Launch> plan;
-    auto add = [&](Kind kind, int param, const std::vector<int4>& tl) {
+    std::vector<Launch> plan_fw, plan_c;
+    auto add = [&](std::vector<Launch>& plan, Kind kind, int param, const std::vector<int4>& tl) {
         if (tl.empty()) return;
         plan.push_back({kind, param, int64_t(all.size()), int64_t(tl.size())});
         all.insert(all.end(), tl.begin(), tl.end());
     };
     std::vector<int> ntile(nall);
-    int maxT = 0;
-    for (int64_t b = 0; b < nall; ++b) {
-        ntile[b] = int(meta[b].npad / TBK);
-        maxT = std::max(maxT, ntile[b]);
-    }
+    for (int64_t b = 0; b < nall; ++b) ntile[b] = int(meta[b].npad / TBK);
+    auto plan_blocks = [&](std::vector<Launch>& plan, int64_t b0, int64_t b1) {
+        int maxT = 0;
+        for (int64_t b = b0; b < b1; ++b) maxT = std::max(maxT, ntile[b]);
+        for (int k = 0; k < maxT; ++k) {   // block Gauss-Jordan, all blocks with a step k together
+            std::vector<int4> tr, tu;
+            for (int64_t b = b0; b < b1; ++b) {
+                if (k >= ntile[b]) continue;
+                for (int j = 0; j < ntile[b]; ++j)
+                    if (j != k || k == 0) tr.push_back(make_int4(int(b), k, j, 0));
+                for (int i = 0; i < ntile[b]; ++i)
+                    for (int j = 0; j <= i; ++j) tu.push_back(make_int4(int(b), i, j, 0));
+            }
+            add(plan, GJ_ROW, k, tr);
+            add(plan, GJ_UPDATE, k, tu);
+        }
+        std::vector<int4> tm;
+        for (int64_t b = b0; b < b1; ++b)
+            for (int i = 1; i < ntile[b]; ++i)
+                for (int j = 0; j < i; ++j) tm.push_back(make_int4(int(b), i, j, 0));
+        add(plan, MIRROR, 0, tm);
+    };
     {
         std::vector<int4> tl;
         for (int64_t b = 0; b < M->nblocks; ++b)
             for (int i = 0; i < ntile[b]; ++i)
                 for (int j = 0; j < ntile[b]; ++j) tl.push_back(make_int4(int(b), i, j, 0));
-        add(GATHER, 0, tl);
+        add(plan_fw, GATHER, 0, tl);
     }
-    for (int k = 0; k < maxT; ++k) {   // right-looking tiled Cholesky
-        std::vector<int4> tp, tt, tu;
-        for (int64_t b = 0; b < nall; ++b) {
-            if (k >= ntile[b]) continue;
-            tp.push_back(make_int4(int(b), k, k, 0));
-            for (int i = k + 1; i < ntile[b]; ++i) {
-                tt.push_back(make_int4(int(b), i, k, 0));
-                for (int j = k + 1; j <= i; ++j) tu.push_back(make_int4(int(b), i, j, 0));
-            }
-        }
-        add(POTRF, k, tp);
-        add(TRSM, k, tt);
-        add(UPDATE, k, tu);
-    }
-    for (int i = 0; i < maxT; ++i) {   // X = L^{-1}, right-looking (diagonal tiles come from k_potrf)
-        std::vector<int4> tf, tu;
-        for (int64_t b = 0; b < nall; ++b) {
-            if (i >= ntile[b]) continue;
-            for (int j = 0; j < i; ++j) tf.push_back(make_int4(int(b), j, 0, 0));
-            for (int ip = i + 1; ip < ntile[b]; ++ip)
-                for (int j = 0; j <= i; ++j) tu.push_back(make_int4(int(b), ip, j, 0));
-        }
-        add(TRTRI_FINISH, i, tf);
-        add(TRTRI_UPDATE, i, tu);
-    }
-    {
-        std::vector<int4> ts;
-        for (int64_t b = 0; b < nall; ++b)
-            for (int i = 0; i < ntile[b]; ++i)
-                for (int j = 0; j <= i; ++j) ts.push_back(make_int4(int(b), i, j, 0));
-        add(SYRK, 0, ts);
-    }
+    plan_blocks(plan_fw, 0, M->nblocks);
+    plan_blocks(plan_c, M->nblocks, nall);
     DeviceBuffer dtasks = upload(all, s);
     const int4* T0 = dtasks.as<int4>();
     mark("layout+plan+upload");
-    auto run = [&](const Launch& L) {
+    auto run = [&](const Launch& L, hipStream_t st) {
         const int4* d = T0 + L.off;
         const dim3 g(unsigned(L.n)), bl(256);
         switch (L.kind) {
-            case GATHER: hipLaunchKernelGGL(k_gather, g, bl, 0, s, d, dm, M->idx.as<int32_t>(), p->W64.as<double>(), p->ldw, A.as<double>()); break;
-            case POTRF: hipLaunchKernelGGL(k_potrf, g, bl, 0, s, d, dm, A.as<double>(), X.as<double>(), L.param, dflags.as<int>()); break;
-            case TRSM: hipLaunchKernelGGL(k_trsm, g, bl, 0, s, d, dm, A.as<double>(), X.as<double>(), L.param); break;
-            case UPDATE: hipLaunchKernelGGL(k_update, g, bl, 0, s, d, dm, A.as<double>(), L.param); break;
-            case TRTRI_FINISH: hipLaunchKernelGGL(k_trtri_finish, g, bl, 0, s, d, dm, X.as<double>(), L.param); break;
-            case TRTRI_UPDATE: hipLaunchKernelGGL(k_trtri_update, g, bl, 0, s, d, dm, A.as<double>(), X.as<double>(), L.param); break;
-            case SYRK: hipLaunchKernelGGL(k_syrk_inverse, g, bl, 0, s, d, dm, X.as<double>(), A.as<double>()); break;
+            case GATHER: hipLaunchKernelGGL(k_gather, g, bl, 0, st, d, dm, M->idx.as<int32_t>(), p->W64.as<double>(), p->ldw, A.as<double>()); break;
+            case GJ_ROW: hipLaunchKernelGGL(k_gj_row, g, bl, 0, st, d, dm, A.as<double>(), scr.as<double>(), pivot_off, L.param, dflags.as<int>()); break;
+            case GJ_UPDATE: hipLaunchKernelGGL(k_gj_update, g, bl, 0, st, d, dm, A.as<double>(), scr.as<double>(), pivot_off, L.param, dflags.as<int>()); break;
+            case MIRROR: hipLaunchKernelGGL(k_mirror, g, bl, 0, st, d, dm, A.as<double>()); break;
         }
         HIP_CHECK(hipGetLastError());
     };
-    size_t li = 0;
-    if (li < plan.size() && plan[li].kind == GATHER) run(plan[li++]);
-    mark("gather");
-    // coarse Galerkin block
+    // the coarse block's work (second stream) starts after the layout uploads queued so far
+    hipStream_t s2 = s;
     if (M->nH > 0) {
-        M->rh_ptr = upload(R.ptr, s);
-        M->rh_col = upload(R.col, s);
-        M->rh_val = upload(R.val, s);
+        if (!p->aux_stream) HIP_CHECK(hipStreamCreateWithFlags(&p->aux_stream, hipStreamNonBlocking));
+        s2 = p->aux_stream;
+        hipEvent_t ready;
+        HIP_CHECK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+        const hipError_t e1 = hipEventRecord(ready, s);
+        const hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(s2, ready, 0) : e1;
+        (void)hipEventDestroy(ready);
+        HIP_CHECK(e2);
+    }
+    // faces and wire basket: all of their work is queued now
+    for (const Launch& L : plan_fw) run(L, s);
+
+    // coarse Galerkin block on the second stream, while the first one eliminates
+    DeviceBuffer Z;
+    if (M->nH > 0) {
+        build_prolongation(f, c, parent, R);
+        mark("prolongation");
         // transposed CSR (fine dof -> coarse dofs)
         std::vector<int64_t> tp(f.N + 1, 0);
         for (int32_t cidx : R.col) ++tp[cidx + 1];
@@ -750,30 +781,31 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
                 trow[pos] = int32_t(i);
                 tval[pos] = R.val[e];
             }
-        M->rht_ptr = upload(tp, s);
-        M->rht_row = upload(trow, s);
-        M->rht_val = upload(tval, s);
-        DeviceBuffer Z(sizeof(double) * std::max<int64_t>(1, f.N * M->nH), s);
-        hipLaunchKernelGGL(k_coarse_Z, dim3(nblk(f.N, 1024), unsigned(M->nH)), dim3(256), 0, s, p->W64.as<double>(), p->ldw, f.N,
-                           M->rh_ptr.as<int64_t>(), M->rh_col.as<int32_t>(), M->rh_val.as<double>(), Z.as<double>());
+        M->rh_ptr = upload(R.ptr, s2);
+        M->rh_col = upload(R.col, s2);
+        M->rh_val = upload(R.val, s2);
+        M->rht_ptr = upload(tp, s2);
+        M->rht_row = upload(trow, s2);
+        M->rht_val = upload(tval, s2);
+        Z = DeviceBuffer(sizeof(double) * std::max<int64_t>(1, f.N * M->nH), s2);
+        const int64_t zblocks = int64_t(nblk(f.N, kZCols)) * M->nH;
+        hipLaunchKernelGGL(k_coarse_Z, dim3(unsigned((zblocks + 7) / 8 * 8)), dim3(256), 0, s2, p->W64.as<double>(), p->ldw, f.N,
+                           M->nH, zblocks, M->rh_ptr.as<int64_t>(), M->rh_col.as<int32_t>(), M->rh_val.as<double>(), Z.as<double>());
         HIP_CHECK(hipGetLastError());
         const BlockMeta& cm = meta[nall - 1];
         double* Ac = A.as<double>() + cm.mat_off;
-        hipLaunchKernelGGL(k_coarse_WH, dim3(nblk(cm.npad, 256), unsigned(M->nH)), dim3(256), 0, s, Z.as<double>(), f.N, M->nH,
+        hipLaunchKernelGGL(k_coarse_WH, dim3(nblk(cm.npad, 256), unsigned(M->nH)), dim3(256), 0, s2, Z.as<double>(), f.N, M->nH,
                            M->rh_ptr.as<int64_t>(), M->rh_col.as<int32_t>(), M->rh_val.as<double>(), Ac, cm.npad);
         HIP_CHECK(hipGetLastError());
         if (cm.npad > M->nH) {
-            hipLaunchKernelGGL(k_coarse_pad_rows, dim3(nblk(cm.npad, 256), unsigned(cm.npad - M->nH)), dim3(256), 0, s, Ac, M->nH, cm.npad);
+            hipLaunchKernelGGL(k_coarse_pad_rows, dim3(nblk(cm.npad, 256), unsigned(cm.npad - M->nH)), dim3(256), 0, s2, Ac, M->nH, cm.npad);
             HIP_CHECK(hipGetLastError());
         }
-        HIP_CHECK(hipStreamSynchronize(s));
+        for (const Launch& L : plan_c) run(L, s2);
+        // the host vectors of the uploads above must outlive the copies
+        HIP_CHECK(hipStreamSynchronize(s2));
     }
-
-    mark("coarse block");
-    // off-diagonal tiles of X accumulate partial sums: start from zero
-    hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, s, X.as<double>(), std::max<int64_t>(moff, 1));
-    HIP_CHECK(hipGetLastError());
-    while (li < plan.size()) run(plan[li++]);
+    HIP_CHECK(hipStreamSynchronize(s));
     mark("factor+invert");
     std::vector<int> flags(nall);
     HIP_CHECK(hipMemcpyAsync(flags.data(), dflags.ptr, sizeof(int) * nall, hipMemcpyDeviceToHost, s));

@@ -60,19 +60,6 @@ inline int64_t side_node(int64_t t, int a, int s) { return (t * 3 + a) * 2 + s; 
 
 }  // namespace
 
-// First failure of a parallel pass, kept by smallest position so the reported error does not depend
-// on thread timing.
-struct FirstFailure {
-    std::mutex mu;
-    int64_t pos = -1;
-    Failure f{0, ""};
-    void record(int64_t where, const Failure& x) {
-        std::lock_guard<std::mutex> lk(mu);
-        if (pos < 0 || where < pos) { pos = where; f = x; }
-    }
-    void rethrow() const { if (pos >= 0) throw f; }
-};
-
 void analyze_mesh(const double* Vin, int64_t nv, const int32_t* Tin, int64_t nt, MeshTopo& m) {
     if (!Vin || !Tin || nv <= 0 || nt <= 0) fail(BEM_E_INVALID_ARG, "empty mesh");
     if (nt > (int64_t(1) << 30)) fail(BEM_E_INVALID_ARG, "too many triangles");

@@ -63,6 +63,9 @@ typedef struct {
     bem_precision precision; /* BEM_FP32_REFINE also keeps an FP32 copy of W for inner solves */
     int near_order;          /* Gauss-Legendre points per axis in the Duffy rules (default 10) */
     int keep_pair_matrix;    /* 1: keep I(T,T') on the device for bem_problem_pair_integrals */
+    int64_t pair_panel_rows; /* 0: automatic; > 0: assemble through panels of the pair matrix with at
+                              * most this many triangle rows (the automatic choice uses panels only
+                              * when the whole N_T x N_T pair matrix does not fit next to W) */
 } bem_assemble_opts;
 
 typedef struct {
@@ -72,6 +75,7 @@ typedef struct {
     double t_assemble_s;     /* wall time of bem_assemble (device work, synchronised) */
     double t_far_s, t_near_s, t_contract_s; /* device time of the three assembly phases */
     double t_host_s;         /* host time of the mesh analysis and near-pair list */
+    int64_t n_pair_panels;   /* panels the pair matrix was built in (0: in one piece) */
 } bem_problem_info;
 
 typedef struct {

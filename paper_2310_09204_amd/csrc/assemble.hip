@@ -24,6 +24,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <functional>
+#include <memory>
 
 #include "internal.h"
 
@@ -169,6 +170,52 @@ __global__ __launch_bounds__(256) void k_far(const double* __restrict__ geo, int
     }
 }
 
+// Panel form of the far-field pass: I_P[r][c - col0] for the rows r of a list of triangles (the
+// panel's rows) and the columns c in [col0, nt).  One wave per tile of 64 listed rows x 64 columns;
+// lane l takes column c = col0 + 64 cb + l with its Gauss points in registers and walks the tile's
+// rows, whose points come through scalar loads, so every store covers 64 consecutive columns.
+__global__ __launch_bounds__(256) void k_far_rect(const double* __restrict__ geo, int32_t nt, const int32_t* __restrict__ rows,
+                                                  int64_t nrows, int64_t col0, int64_t ld, const int2* __restrict__ tiles,
+                                                  int64_t ntiles, double* __restrict__ I) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t tile = int64_t(blockIdx.x) * 4 + wave;
+    if (tile >= ntiles) return;
+    const int2 tc = tiles[tile];
+    const int rb = __builtin_amdgcn_readfirstlane(tc.x);
+    const int cb = __builtin_amdgcn_readfirstlane(tc.y);
+    const int64_t c = col0 + int64_t(cb) * kTile + lane;
+    const bool valid = c < nt;
+    const double* g = geo + (valid ? c : col0) * kGeo;
+    double px[7], py[7], pz[7], pw[7];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+        px[q] = g[3 * q];
+        py[q] = g[3 * q + 1];
+        pz[q] = g[3 * q + 2];
+        pw[q] = 0.5 * g[21 + q];   // the 1/2 of the Newton step, folded into the weight
+    }
+    const int64_t r1 = min<int64_t>(nrows, int64_t(rb + 1) * kTile);
+    for (int64_t r = int64_t(rb) * kTile; r < r1; ++r) {
+        const double* h = geo + int64_t(rows[r]) * kGeo;
+        double acc = 0.0;
+#pragma unroll
+        for (int p = 0; p < 7; ++p) {
+            const double xx = h[3 * p], xy = h[3 * p + 1], xz = h[3 * p + 2];
+            double sacc = 0.0;
+#pragma unroll
+            for (int q = 0; q < 7; ++q) {
+                const double dx = xx - px[q], dy = xy - py[q], dz = xz - pz[q];
+                const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                const double y = __builtin_amdgcn_rsq(r2);
+                sacc = fma(pw[q] * y, fma(-r2, y * y, 3.0), sacc);
+            }
+            acc = fma(h[21 + p], sacc, acc);
+        }
+        if (valid) I[r * ld + (c - col0)] = acc * kInv4Pi;
+    }
+}
+
 __device__ __forceinline__ void load3(const double* __restrict__ V, int32_t i, double* o) {
     o[0] = V[3 * int64_t(i)];
     o[1] = V[3 * int64_t(i) + 1];
@@ -194,7 +241,7 @@ __device__ __forceinline__ double tri_area2(const double* a, const double* b, co
 __global__ void k_near_coincident(const double* __restrict__ V, const int32_t* __restrict__ vs,
                                   const int32_t* __restrict__ t1, int64_t n, int ng,
                                   const double* __restrict__ gx, const double* __restrict__ gw,
-                                  double* __restrict__ I, int64_t ld) {
+                                  double* __restrict__ I, int64_t ld, const int64_t* __restrict__ tgt) {
     int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (i >= n) return;
     double A[3], B[3], C[3];
@@ -214,7 +261,12 @@ __global__ void k_near_coincident(const double* __restrict__ V, const int32_t* _
         }
     double ar = tri_area2(A, B, C);
     int64_t t = t1[i];
-    I[t * ld + t] = acc * (1.0 / 3.0) * 4.0 * ar * ar * kInv4Pi;
+    const double val = acc * (1.0 / 3.0) * 4.0 * ar * ar * kInv4Pi;
+    if (tgt) {
+        if (tgt[2 * i] >= 0) I[tgt[2 * i]] = val;
+    } else {
+        I[t * ld + t] = val;
+    }
 }
 
 // Common edge A-B: x - y = w1 (B-A) + w2 (C-B) - w3 (C'-B) with w = (s - s', t, t').  The cone
@@ -224,7 +276,7 @@ __global__ void k_near_coincident(const double* __restrict__ V, const int32_t* _
 __global__ void k_near_edge(const double* __restrict__ V, const int32_t* __restrict__ vs,
                             const int32_t* __restrict__ t1, const int32_t* __restrict__ t2, int64_t n,
                             int ng, const double* __restrict__ gx, const double* __restrict__ gw,
-                            double* __restrict__ I, int64_t ld) {
+                            double* __restrict__ I, int64_t ld, const int64_t* __restrict__ tgt) {
     int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (i >= n) return;
     double A[3], B[3], C[3], C2[3];
@@ -260,8 +312,13 @@ __global__ void k_near_edge(const double* __restrict__ V, const int32_t* __restr
     }
     double val = acc * (1.0 / 6.0) * 4.0 * tri_area2(A, B, C) * tri_area2(A, B, C2) * kInv4Pi;
     int64_t a = t1[i], b = t2[i];
-    I[a * ld + b] = val;
-    I[b * ld + a] = val;
+    if (tgt) {   // panel of the pair matrix: the positions this pair has in it (-1: outside)
+        if (tgt[2 * i] >= 0) I[tgt[2 * i]] = val;
+        if (tgt[2 * i + 1] >= 0) I[tgt[2 * i + 1]] = val;
+    } else {
+        I[a * ld + b] = val;
+        I[b * ld + a] = val;
+    }
 }
 
 // Common vertex A: x^ = xi (1, eta1), y^ = xi (eta2, eta2 eta3) on {s' <= s} and the mirror piece;
@@ -269,7 +326,7 @@ __global__ void k_near_edge(const double* __restrict__ V, const int32_t* __restr
 __global__ void k_near_vertex(const double* __restrict__ V, const int32_t* __restrict__ vs,
                               const int32_t* __restrict__ t1, const int32_t* __restrict__ t2, int64_t n,
                               int ng, const double* __restrict__ gx, const double* __restrict__ gw,
-                              double* __restrict__ I, int64_t ld) {
+                              double* __restrict__ I, int64_t ld, const int64_t* __restrict__ tgt) {
     int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (i >= n) return;
     double A[3], B[3], C[3], B2[3], C2[3];
@@ -301,8 +358,13 @@ __global__ void k_near_vertex(const double* __restrict__ V, const int32_t* __res
     }
     double val = acc * (1.0 / 3.0) * 4.0 * tri_area2(A, B, C) * tri_area2(A, B2, C2) * kInv4Pi;
     int64_t a = t1[i], b = t2[i];
-    I[a * ld + b] = val;
-    I[b * ld + a] = val;
+    if (tgt) {   // panel of the pair matrix: the positions this pair has in it (-1: outside)
+        if (tgt[2 * i] >= 0) I[tgt[2 * i]] = val;
+        if (tgt[2 * i + 1] >= 0) I[tgt[2 * i + 1]] = val;
+    } else {
+        I[a * ld + b] = val;
+        I[b * ld + a] = val;
+    }
 }
 
 // W over 64 x 64 dof tiles above the diagonal.  Wave w of the block takes rows d0 + 16w .. +15 one
@@ -316,7 +378,8 @@ __global__ void k_near_vertex(const double* __restrict__ V, const int32_t* __res
 constexpr int kCT = 64;    // tile edge (dofs)
 constexpr int kReg = 6;    // star entries handled in the unrolled path (a flat interior star has 6)
 
-__global__ __launch_bounds__(256) void k_contract(const double* __restrict__ I, int64_t ldI, int64_t N,
+__global__ __launch_bounds__(256) void k_contract(const double* __restrict__ I, int64_t ldI, const int32_t* __restrict__ rowmap,
+                                                  int64_t col0, int64_t N,
                                                   const int64_t* __restrict__ dof_ptr, const int32_t* __restrict__ dof_tri,
                                                   const double* __restrict__ dof_J, const int2* __restrict__ tiles,
                                                   int64_t ntiles, double* __restrict__ W, float* __restrict__ W32,
@@ -340,7 +403,7 @@ __global__ __launch_bounds__(256) void k_contract(const double* __restrict__ I, 
 #pragma unroll
     for (int k = 0; k < kReg; ++k) {
         const bool h = k < ne;
-        Tk[k] = h ? dof_tri[kb + k] : 0;
+        Tk[k] = h ? dof_tri[kb + k] - int32_t(col0) : 0;   // column within I (>= 0 by the choice of col0)
         Jx[k] = h ? dof_J[3 * (kb + k)] : 0.0;
         Jy[k] = h ? dof_J[3 * (kb + k) + 1] : 0.0;
         Jz[k] = h ? dof_J[3 * (kb + k) + 2] : 0.0;
@@ -356,7 +419,8 @@ __global__ __launch_bounds__(256) void k_contract(const double* __restrict__ I, 
 #pragma unroll
             for (int i = 0; i < kReg; ++i) {
                 const bool h = i < ni;
-                Ir[i] = I + int64_t(h ? dof_tri[i0 + i] : 0) * ldI;
+                const int32_t T = h ? dof_tri[i0 + i] : -1;
+                Ir[i] = I + int64_t(T < 0 ? 0 : (rowmap ? rowmap[T] : T)) * ldI;
                 ja[i] = h ? dof_J[3 * (i0 + i)] : 0.0;
                 jb[i] = h ? dof_J[3 * (i0 + i) + 1] : 0.0;
                 jc[i] = h ? dof_J[3 * (i0 + i) + 2] : 0.0;
@@ -374,7 +438,8 @@ __global__ __launch_bounds__(256) void k_contract(const double* __restrict__ I, 
             if (ni > kReg || ne > kReg) {
                 for (int i = 0; i < ni; ++i) {
                     const int64_t qi = i0 + i;
-                    const double* Irow = I + int64_t(dof_tri[qi]) * ldI;
+                    const int32_t T = dof_tri[qi];
+                    const double* Irow = I + int64_t(rowmap ? rowmap[T] : T) * ldI - col0;
                     const double j0 = dof_J[3 * qi], j1 = dof_J[3 * qi + 1], j2 = dof_J[3 * qi + 2];
                     for (int k = (i < kReg ? kReg : 0); k < ne; ++k) {
                         const int64_t q = kb + k;
@@ -415,7 +480,8 @@ constexpr int kRegC = 8;
 constexpr int kCap = kCT * kRegC;
 
 __global__ __launch_bounds__(256) void k_contract_staged(
-    const double* __restrict__ I, int64_t ldI, int64_t N, const int32_t* __restrict__ cb_ptr,
+    const double* __restrict__ I, int64_t ldI, const int32_t* __restrict__ rowmap, int64_t col0, int64_t N,
+    const int32_t* __restrict__ cb_ptr,
     const int32_t* __restrict__ cb_tri, const int64_t* __restrict__ dof_ptr, const int32_t* __restrict__ col_loc,
     const double* __restrict__ dof_J, const int32_t* __restrict__ rg_ptr, const int4* __restrict__ rg,
     const int2* __restrict__ rg_ent, const int2* __restrict__ tiles, int64_t ntiles, double* __restrict__ W,
@@ -449,7 +515,7 @@ __global__ __launch_bounds__(256) void k_contract_staged(
 #pragma unroll
     for (int m = 0; m < kRegC; ++m) {
         const int j = m * kCT + lane;
-        cidx[m] = j < nc ? cb_tri[c0 + j] : 0;
+        cidx[m] = cb_tri[c0 + min(j, nc - 1)] - int32_t(col0);   // lanes past the list repeat its last entry
     }
     double* arow = &acc[wave * 16][0];
 #pragma unroll
@@ -459,7 +525,7 @@ __global__ __launch_bounds__(256) void k_contract_staged(
     double nxt[kRegC];
     // chunk 0 is always fetched and staged so that position 0 of the list holds a finite value
     auto fetch = [&](int T) {
-        const double* row = I + int64_t(T) * ldI;
+        const double* row = I + int64_t(rowmap ? rowmap[T] : T) * ldI;
 #pragma unroll
         for (int m = 0; m < kRegC; ++m)
             if (m == 0 || m * kCT < nc) nxt[m] = row[cidx[m]];
@@ -648,6 +714,168 @@ ContractPlan contract_plan(const MeshTopo& m) {
     return P;
 }
 
+// ---- panel-by-panel assembly -------------------------------------------------------------------
+// For meshes whose N_T x N_T pair matrix does not fit next to W: the dof row blocks (64 dofs) are
+// grouped into panels whose rows' star triangles number at most maxrows.  A panel computes
+// I_P = I(R, [tmin, N_T)) for its row triangles R and every column triangle that a tile
+// (bd, be >= bd) of its rows can read (tmin = smallest triangle of the column blocks from its first
+// row block on), the near pairs that fall in it, and then contracts its tiles of the upper half of W
+// (the mirrored writes fill the lower half).  Far work is about half of N_T^2 pairs in total, as in
+// the one-shot path.  Host-side filtering of the next panel overlaps the device work of this one.
+struct PanelTimes { double far = 0, near = 0, contract = 0; int panels = 0; };
+
+template <class Mark>
+PanelTimes assemble_panels(bem_problem* p, const MeshTopo& m, const NearList& near, const ContractPlan& plan,
+                           const double* geo, const double* dV, const double* dgx, const double* dgw, const double* dofJ,
+                           float* w32, Mark&& mark) {
+    hipStream_t s = p->stream;
+    const int64_t nt = m.nt, N = m.N;
+    PanelTimes out;
+    if (N == 0) return out;
+    const int64_t ncb = (N + kCT - 1) / kCT;
+    std::vector<int64_t> sufmin(ncb + 1, nt);
+    for (int64_t be = ncb - 1; be >= 0; --be) {
+        int64_t mn = nt;
+        if (plan.cb_ptr[be] < plan.cb_ptr[be + 1]) mn = plan.cb_tri[plan.cb_ptr[be]];   // lists are sorted
+        sufmin[be] = std::min(sufmin[be + 1], mn);
+    }
+    int64_t maxrows = p->panel_rows;
+    if (maxrows <= 0) {
+        size_t fb = 0, tb = 0;
+        HIP_CHECK(hipMemGetInfo(&fb, &tb));
+        maxrows = int64_t(0.6 * double(fb) / (8.0 * double(nt)));
+    }
+    maxrows = std::max<int64_t>(maxrows, kTile);
+    DeviceBuffer d_cb_ptr = upload(plan.cb_ptr, s), d_cb_tri = upload(plan.cb_tri, s);
+    DeviceBuffer d_col_loc = upload(plan.col_loc, s), d_rg_ptr = upload(plan.rg_ptr, s);
+    DeviceBuffer d_rg = upload(plan.rg, s), d_rg_ent = upload(plan.rg_ent, s);
+    DeviceBuffer d_fast = upload(plan.fast, s), d_slow = upload(plan.slow, s);
+
+    struct Panel {   // host arrays stay alive until the end: their uploads are asynchronous
+        std::vector<int32_t> rows, rowmap, nv[4], na[4], nb[4];
+        std::vector<int64_t> tgt[4];
+        std::vector<int2> ftiles;
+        std::unique_ptr<EventTimer> ef, en, ec;
+    };
+    std::vector<std::unique_ptr<Panel>> done;
+    std::vector<int32_t> stamp(size_t(nt), -1);
+    int64_t bd0 = 0;
+    int pid = 0;
+    while (bd0 < ncb) {
+        auto P = std::make_unique<Panel>();
+        // grow the panel by whole 64-dof row blocks
+        int64_t bd1 = bd0;
+        while (bd1 < ncb) {
+            std::vector<int32_t> add;
+            for (int64_t rb = 4 * bd1; rb < 4 * bd1 + 4; ++rb)
+                for (int32_t g = plan.rg_ptr[rb]; g < plan.rg_ptr[rb + 1]; ++g) {
+                    const int32_t T = plan.rg[g].x;
+                    if (stamp[T] != pid) {
+                        stamp[T] = pid;
+                        add.push_back(T);
+                    }
+                }
+            if (bd1 > bd0 && int64_t(P->rows.size() + add.size()) > maxrows) {
+                for (int32_t T : add) stamp[T] = -1;
+                break;
+            }
+            P->rows.insert(P->rows.end(), add.begin(), add.end());
+            ++bd1;
+        }
+        std::sort(P->rows.begin(), P->rows.end());
+        const int64_t nrows = int64_t(P->rows.size());
+        const int64_t tmin = sufmin[bd0];
+        const int64_t ncol = nt - tmin;
+        const int64_t ldP = (ncol + 7) / 8 * 8;
+        P->rowmap.assign(size_t(nt), -1);
+        for (int64_t r = 0; r < nrows; ++r) P->rowmap[P->rows[r]] = int32_t(r);
+        // near pairs with a position in this panel
+        for (size_t i = 0; i < near.t1.size(); ++i) {
+            const int ty = near.type[i];
+            const int32_t a = near.t1[i], b = near.t2[i];
+            int64_t g1 = -1, g2 = -1;
+            if (P->rowmap[a] >= 0 && b >= tmin) g1 = int64_t(P->rowmap[a]) * ldP + (b - tmin);
+            if (a != b && P->rowmap[b] >= 0 && a >= tmin) g2 = int64_t(P->rowmap[b]) * ldP + (a - tmin);
+            if (g1 < 0 && g2 < 0) continue;
+            P->na[ty].push_back(a);
+            P->nb[ty].push_back(b);
+            P->nv[ty].insert(P->nv[ty].end(), &near.verts[5 * i], &near.verts[5 * i] + 5);
+            P->tgt[ty].push_back(g1);
+            P->tgt[ty].push_back(g2);
+        }
+        for (int64_t rb = 0; rb < (nrows + kTile - 1) / kTile; ++rb)
+            for (int64_t cb = 0; cb < (ncol + kTile - 1) / kTile; ++cb) P->ftiles.push_back(make_int2(int(rb), int(cb)));
+
+        DeviceBuffer d_rows = upload(P->rows, s), d_rowmap = upload(P->rowmap, s), d_ft = upload(P->ftiles, s);
+        DeviceBuffer Ip(sizeof(double) * std::max<int64_t>(1, nrows * ldP), s);
+        P->ef = std::make_unique<EventTimer>(s);
+        const int64_t nft = int64_t(P->ftiles.size());
+        hipLaunchKernelGGL(k_far_rect, dim3(blocks_for(nft, 4)), dim3(256), 0, s, geo, int32_t(nt), d_rows.as<int32_t>(), nrows,
+                           tmin, ldP, d_ft.as<int2>(), nft, Ip.as<double>());
+        HIP_CHECK(hipGetLastError());
+        P->ef->stop();
+        DeviceBuffer dv[4], da[4], dbb[4], dt[4];
+        for (int ty = 1; ty <= 3; ++ty) {
+            if (P->na[ty].empty()) continue;
+            dv[ty] = upload(P->nv[ty], s);
+            da[ty] = upload(P->na[ty], s);
+            dbb[ty] = upload(P->nb[ty], s);
+            dt[ty] = upload(P->tgt[ty], s);
+        }
+        P->en = std::make_unique<EventTimer>(s);
+        for (int ty = 1; ty <= 3; ++ty) {
+            const int64_t n = int64_t(P->na[ty].size());
+            if (n == 0) continue;
+            dim3 grid(blocks_for(n, 64)), block(64);
+            if (ty == 3)
+                hipLaunchKernelGGL(k_near_coincident, grid, block, 0, s, dV, dv[ty].as<int32_t>(), da[ty].as<int32_t>(), n,
+                                   p->near_order, dgx, dgw, Ip.as<double>(), ldP, dt[ty].as<int64_t>());
+            else if (ty == 2)
+                hipLaunchKernelGGL(k_near_edge, grid, block, 0, s, dV, dv[ty].as<int32_t>(), da[ty].as<int32_t>(),
+                                   dbb[ty].as<int32_t>(), n, p->near_order, dgx, dgw, Ip.as<double>(), ldP, dt[ty].as<int64_t>());
+            else
+                hipLaunchKernelGGL(k_near_vertex, grid, block, 0, s, dV, dv[ty].as<int32_t>(), da[ty].as<int32_t>(),
+                                   dbb[ty].as<int32_t>(), n, p->near_order, dgx, dgw, Ip.as<double>(), ldP, dt[ty].as<int64_t>());
+            HIP_CHECK(hipGetLastError());
+        }
+        P->en->stop();
+        // this panel's tiles of the upper half (the tile lists are sorted by row block)
+        auto range = [&](const std::vector<int2>& v) {
+            auto lo = std::lower_bound(v.begin(), v.end(), int(bd0), [](const int2& x, int b) { return x.x < b; });
+            auto hi = std::lower_bound(v.begin(), v.end(), int(bd1), [](const int2& x, int b) { return x.x < b; });
+            return std::make_pair(int64_t(lo - v.begin()), int64_t(hi - lo));
+        };
+        const auto rf = range(plan.fast), rs = range(plan.slow);
+        P->ec = std::make_unique<EventTimer>(s);
+        if (rf.second > 0) {
+            hipLaunchKernelGGL(k_contract_staged, dim3(unsigned((rf.second + 7) / 8 * 8)), dim3(256), 0, s, Ip.as<double>(), ldP,
+                               d_rowmap.as<int32_t>(), tmin, N, d_cb_ptr.as<int32_t>(), d_cb_tri.as<int32_t>(),
+                               p->dof_ptr.as<int64_t>(), d_col_loc.as<int32_t>(), dofJ, d_rg_ptr.as<int32_t>(),
+                               d_rg.as<int4>(), d_rg_ent.as<int2>(), d_fast.as<int2>() + rf.first, rf.second,
+                               p->W64.as<double>(), w32, p->ldw);
+            HIP_CHECK(hipGetLastError());
+        }
+        if (rs.second > 0) {
+            hipLaunchKernelGGL(k_contract, dim3(unsigned((rs.second + 7) / 8 * 8)), dim3(256), 0, s, Ip.as<double>(), ldP,
+                               d_rowmap.as<int32_t>(), tmin, N, p->dof_ptr.as<int64_t>(), p->dof_tri.as<int32_t>(), dofJ,
+                               d_slow.as<int2>() + rs.first, rs.second, p->W64.as<double>(), w32, p->ldw);
+            HIP_CHECK(hipGetLastError());
+        }
+        P->ec->stop();
+        done.push_back(std::move(P));
+        ++pid;
+        bd0 = bd1;
+        mark("panel");
+    }
+    for (auto& P : done) {
+        out.far += P->ef->seconds();
+        out.near += P->en->seconds();
+        out.contract += P->ec->seconds();
+    }
+    out.panels = pid;
+    return out;
+}
+
 }  // namespace
 
 void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_t* Tin, int64_t nt,
@@ -695,18 +923,26 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
                        db.as<double>(), dw.as<double>(), geo.as<double>(), p->normal.as<double>(), p->area.as<double>());
     HIP_CHECK(hipGetLastError());
 
-    // pair integrals I (nt x ldI), rows padded to 64 bytes so the far kernel's paired stores stay aligned
+    // pair integrals I (nt x ldI), rows padded to 64 bytes so the far kernel's paired stores stay aligned.
+    // When the whole matrix does not fit next to W (about 8 N_T^2 + 3 N_T^2 bytes with N ~ N_T / 2),
+    // or panels are requested, it is built and contracted panel by panel after the mesh analysis.
     const int64_t ldI = (nt + 7) / 8 * 8;
-    p->ldI = ldI;
-    p->I = DeviceBuffer(sizeof(double) * nt * ldI, s);
-    const int nb = int((nt + kTile - 1) / kTile);
-    std::vector<int2> tiles;
-    tiles.reserve(size_t(nb) * (nb + 1) / 2);
-    for (int rb = 0; rb < nb; ++rb)
-        for (int cb = rb; cb < nb; ++cb) tiles.push_back(make_int2(rb, cb));
-    DeviceBuffer dtiles = upload(tiles, s);
+    size_t free_b = 0, total_b = 0;
+    HIP_CHECK(hipMemGetInfo(&free_b, &total_b));
+    const double full_bytes = 8.0 * double(nt) * double(ldI) + 3.0 * double(nt) * double(nt);
+    const bool paneled = p->panel_rows > 0 || full_bytes > 0.85 * double(free_b);
+    if (paneled && p->has_pairs) fail(BEM_E_INVALID_ARG, "keep_pair_matrix needs the whole pair matrix on the device");
     EventTimer t_far(s);
-    {
+    if (!paneled) {
+        p->ldI = ldI;
+        p->I = DeviceBuffer(sizeof(double) * nt * ldI, s);
+        const int nb = int((nt + kTile - 1) / kTile);
+        std::vector<int2> tiles;
+        tiles.reserve(size_t(nb) * (nb + 1) / 2);
+        for (int rb = 0; rb < nb; ++rb)
+            for (int cb = rb; cb < nb; ++cb) tiles.push_back(make_int2(rb, cb));
+        DeviceBuffer dtiles = upload(tiles, s);
+        HIP_CHECK(hipEventRecord(t_far.a, s));
         const int64_t nti = int64_t(tiles.size());
         hipLaunchKernelGGL(k_far, dim3(blocks_for(nti, 4)), dim3(256), 0, s, geo.as<double>(), int32_t(nt), ldI,
                            dtiles.as<int2>(), nti, p->I.as<double>());
@@ -759,69 +995,79 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
         HIP_CHECK(hipGetLastError());
     }
 
-    // near pairs, one kernel per kind
     DeviceBuffer dgx = upload(gx, s), dgw = upload(gw, s);
-    DeviceBuffer dv[4], da[4], dbb[4];
-    for (int ty = 1; ty <= 3; ++ty) {
-        if (na_[ty].empty()) continue;
-        dv[ty] = upload(nv_[ty], s);
-        da[ty] = upload(na_[ty], s);
-        dbb[ty] = upload(nb_[ty], s);
-    }
-    EventTimer t_near(s);
-    for (int ty = 1; ty <= 3; ++ty) {
-        const int64_t n = int64_t(na_[ty].size());
-        if (n == 0) continue;
-        dim3 grid(blocks_for(n, 64)), block(64);
-        if (ty == 3)
-            hipLaunchKernelGGL(k_near_coincident, grid, block, 0, s, dV.as<double>(), dv[ty].as<int32_t>(), da[ty].as<int32_t>(), n,
-                               p->near_order, dgx.as<double>(), dgw.as<double>(), p->I.as<double>(), ldI);
-        else if (ty == 2)
-            hipLaunchKernelGGL(k_near_edge, grid, block, 0, s, dV.as<double>(), dv[ty].as<int32_t>(), da[ty].as<int32_t>(),
-                               dbb[ty].as<int32_t>(), n, p->near_order, dgx.as<double>(), dgw.as<double>(), p->I.as<double>(), ldI);
-        else
-            hipLaunchKernelGGL(k_near_vertex, grid, block, 0, s, dV.as<double>(), dv[ty].as<int32_t>(), da[ty].as<int32_t>(),
-                               dbb[ty].as<int32_t>(), n, p->near_order, dgx.as<double>(), dgw.as<double>(), p->I.as<double>(), ldI);
-        HIP_CHECK(hipGetLastError());
-    }
-    t_near.stop();
-    mark("near");
-    // contraction into W; every entry of W, padding columns included, is written by one tile
+    // W: every entry, padding columns included, is written by one contraction tile
     p->ldw = ((N + 63) / 64) * 64;
     p->W64 = DeviceBuffer(sizeof(double) * std::max<int64_t>(N, 1) * p->ldw, s);
     if (p->has_w32) p->W32 = DeviceBuffer(sizeof(float) * std::max<int64_t>(N, 1) * p->ldw, s);
     float* w32 = p->has_w32 ? p->W32.as<float>() : nullptr;   // the contraction writes both copies
-    EventTimer t_contract(s);
-    if (N > 0) {
-        DeviceBuffer d_cb_ptr = upload(plan.cb_ptr, s), d_cb_tri = upload(plan.cb_tri, s);
-        DeviceBuffer d_col_loc = upload(plan.col_loc, s), d_rg_ptr = upload(plan.rg_ptr, s);
-        DeviceBuffer d_rg = upload(plan.rg, s), d_rg_ent = upload(plan.rg_ent, s);
-        DeviceBuffer d_fast = upload(plan.fast, s), d_slow = upload(plan.slow, s);
+    EventTimer t_near(s), t_contract(s);
+    PanelTimes ptimes;
+    if (!paneled) {
+        // near pairs, one kernel per kind
+        DeviceBuffer dv[4], da[4], dbb[4];
+        for (int ty = 1; ty <= 3; ++ty) {
+            if (na_[ty].empty()) continue;
+            dv[ty] = upload(nv_[ty], s);
+            da[ty] = upload(na_[ty], s);
+            dbb[ty] = upload(nb_[ty], s);
+        }
+        HIP_CHECK(hipEventRecord(t_near.a, s));
+        for (int ty = 1; ty <= 3; ++ty) {
+            const int64_t n = int64_t(na_[ty].size());
+            if (n == 0) continue;
+            dim3 grid(blocks_for(n, 64)), block(64);
+            if (ty == 3)
+                hipLaunchKernelGGL(k_near_coincident, grid, block, 0, s, dV.as<double>(), dv[ty].as<int32_t>(), da[ty].as<int32_t>(), n,
+                                   p->near_order, dgx.as<double>(), dgw.as<double>(), p->I.as<double>(), ldI, nullptr);
+            else if (ty == 2)
+                hipLaunchKernelGGL(k_near_edge, grid, block, 0, s, dV.as<double>(), dv[ty].as<int32_t>(), da[ty].as<int32_t>(),
+                                   dbb[ty].as<int32_t>(), n, p->near_order, dgx.as<double>(), dgw.as<double>(), p->I.as<double>(), ldI, nullptr);
+            else
+                hipLaunchKernelGGL(k_near_vertex, grid, block, 0, s, dV.as<double>(), dv[ty].as<int32_t>(), da[ty].as<int32_t>(),
+                                   dbb[ty].as<int32_t>(), n, p->near_order, dgx.as<double>(), dgw.as<double>(), p->I.as<double>(), ldI, nullptr);
+            HIP_CHECK(hipGetLastError());
+        }
+        t_near.stop();
+        mark("near");
         HIP_CHECK(hipEventRecord(t_contract.a, s));
-        const int64_t nf = int64_t(plan.fast.size()), ns = int64_t(plan.slow.size());
-        if (nf > 0) {
-            hipLaunchKernelGGL(k_contract_staged, dim3(unsigned((nf + 7) / 8 * 8)), dim3(256), 0, s, p->I.as<double>(), ldI, N,
-                               d_cb_ptr.as<int32_t>(), d_cb_tri.as<int32_t>(), p->dof_ptr.as<int64_t>(),
-                               d_col_loc.as<int32_t>(), dofJ.as<double>(), d_rg_ptr.as<int32_t>(), d_rg.as<int4>(),
-                               d_rg_ent.as<int2>(), d_fast.as<int2>(), nf, p->W64.as<double>(), w32, p->ldw);
-            HIP_CHECK(hipGetLastError());
+        if (N > 0) {
+            DeviceBuffer d_cb_ptr = upload(plan.cb_ptr, s), d_cb_tri = upload(plan.cb_tri, s);
+            DeviceBuffer d_col_loc = upload(plan.col_loc, s), d_rg_ptr = upload(plan.rg_ptr, s);
+            DeviceBuffer d_rg = upload(plan.rg, s), d_rg_ent = upload(plan.rg_ent, s);
+            DeviceBuffer d_fast = upload(plan.fast, s), d_slow = upload(plan.slow, s);
+            HIP_CHECK(hipEventRecord(t_contract.a, s));
+            const int64_t nf = int64_t(plan.fast.size()), ns = int64_t(plan.slow.size());
+            if (nf > 0) {
+                hipLaunchKernelGGL(k_contract_staged, dim3(unsigned((nf + 7) / 8 * 8)), dim3(256), 0, s, p->I.as<double>(), ldI,
+                                   nullptr, int64_t(0), N,
+                                   d_cb_ptr.as<int32_t>(), d_cb_tri.as<int32_t>(), p->dof_ptr.as<int64_t>(),
+                                   d_col_loc.as<int32_t>(), dofJ.as<double>(), d_rg_ptr.as<int32_t>(), d_rg.as<int4>(),
+                                   d_rg_ent.as<int2>(), d_fast.as<int2>(), nf, p->W64.as<double>(), w32, p->ldw);
+                HIP_CHECK(hipGetLastError());
+            }
+            if (ns > 0) {
+                hipLaunchKernelGGL(k_contract, dim3(unsigned((ns + 7) / 8 * 8)), dim3(256), 0, s, p->I.as<double>(), ldI,
+                                   nullptr, int64_t(0), N,
+                                   p->dof_ptr.as<int64_t>(), p->dof_tri.as<int32_t>(), dofJ.as<double>(), d_slow.as<int2>(), ns,
+                                   p->W64.as<double>(), w32, p->ldw);
+                HIP_CHECK(hipGetLastError());
+            }
         }
-        if (ns > 0) {
-            hipLaunchKernelGGL(k_contract, dim3(unsigned((ns + 7) / 8 * 8)), dim3(256), 0, s, p->I.as<double>(), ldI, N,
-                               p->dof_ptr.as<int64_t>(), p->dof_tri.as<int32_t>(), dofJ.as<double>(), d_slow.as<int2>(), ns,
-                               p->W64.as<double>(), w32, p->ldw);
-            HIP_CHECK(hipGetLastError());
-        }
+        t_contract.stop();
+        mark("contract");
+    } else {
+        ptimes = assemble_panels(p, m, near, plan, geo.as<double>(), dV.as<double>(), dgx.as<double>(), dgw.as<double>(),
+                                 dofJ.as<double>(), w32, mark);
     }
-    t_contract.stop();
-    mark("contract");
     p->mv_xt = DeviceBuffer(sizeof(double) * 16 * p->ldw, s);
     p->mv_partial = DeviceBuffer(sizeof(double) * 16 * 16 * p->ldw, s);
     HIP_CHECK(hipStreamSynchronize(s));
     if (!p->has_pairs) p->I.reset();   // idle now: back to the cache
-    p->t_far = t_far.seconds();
-    p->t_near = t_near.seconds();
-    p->t_contract = t_contract.seconds();
+    p->t_far = paneled ? ptimes.far : t_far.seconds();
+    p->t_near = paneled ? ptimes.near : t_near.seconds();
+    p->t_contract = paneled ? ptimes.contract : t_contract.seconds();
+    p->n_panels = paneled ? ptimes.panels : 0;
 }
 
 void rhs_device(const bem_problem* p, const double* d_g, int k, double* d_L, hipStream_t s) {

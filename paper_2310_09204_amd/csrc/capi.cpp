@@ -327,6 +327,7 @@ int bem_assemble(bem_ctx* ctx, const double* vertices, int64_t nv, const int32_t
     if (p->near_order > 64) fail(BEM_E_INVALID_ARG, "near_order above 64");
     p->has_w32 = opts && opts->precision == BEM_FP32_REFINE;
     p->has_pairs = opts && opts->keep_pair_matrix;
+    p->panel_rows = (opts && opts->pair_panel_rows > 0) ? opts->pair_panel_rows : 0;
     HIP_CHECK(hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking));
     try {
         assemble_device(p.get(), vertices, nv, triangles, nt, [&](NearList& near) {
@@ -384,6 +385,7 @@ int bem_problem_get_info(const bem_problem* p, bem_problem_info* info) {
     info->t_near_s = p->t_near;
     info->t_contract_s = p->t_contract;
     info->t_host_s = p->t_host;
+    info->n_pair_panels = p->n_panels;
     return BEM_OK;
     BEM_CATCH
 }

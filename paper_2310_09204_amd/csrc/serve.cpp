@@ -160,7 +160,7 @@ void worker_main(bem_server* s) {
         }
         try {
             if (!entry->problem) {
-                bem_assemble_opts ao{r0->precision, 10, 0};
+                bem_assemble_opts ao{r0->precision, 10, 0, 0};
                 bem_problem* p = nullptr;
                 int c = bem_assemble(s->ctx, r0->V.data(), int64_t(r0->V.size() / 3), r0->T.data(), r0->nt, &ao, &p);
                 if (c != BEM_OK) fail(c, bem_last_error());

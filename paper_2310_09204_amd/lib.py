@@ -32,7 +32,8 @@ class BemError(RuntimeError):
 
 
 class AssembleOpts(ctypes.Structure):
-    _fields_ = [("precision", ctypes.c_int), ("near_order", ctypes.c_int), ("keep_pair_matrix", ctypes.c_int)]
+    _fields_ = [("precision", ctypes.c_int), ("near_order", ctypes.c_int), ("keep_pair_matrix", ctypes.c_int),
+                ("pair_panel_rows", ctypes.c_int64)]
 
 
 class ProblemInfo(ctypes.Structure):
@@ -40,7 +41,7 @@ class ProblemInfo(ctypes.Structure):
                 ("n_near_pairs", ctypes.c_int64), ("bytes_device", ctypes.c_int64),
                 ("q_hist", ctypes.c_int64 * 16), ("t_assemble_s", ctypes.c_double),
                 ("t_far_s", ctypes.c_double), ("t_near_s", ctypes.c_double), ("t_contract_s", ctypes.c_double),
-                ("t_host_s", ctypes.c_double)]
+                ("t_host_s", ctypes.c_double), ("n_pair_panels", ctypes.c_int64)]
 
 
 class PrecondOpts(ctypes.Structure):
@@ -191,10 +192,10 @@ class Context:
 class Problem:
     """bem_assemble: W resident on the device."""
 
-    def __init__(self, ctx: Context, V, T, precision=FP64, near_order=10, keep_pair_matrix=False):
+    def __init__(self, ctx: Context, V, T, precision=FP64, near_order=10, keep_pair_matrix=False, pair_panel_rows=0):
         self.ctx = ctx
         self.V, self.T = _f64(V), _i32a(T)
-        o = AssembleOpts(precision, near_order, int(keep_pair_matrix))
+        o = AssembleOpts(precision, near_order, int(keep_pair_matrix), int(pair_panel_rows))
         self._h = ctypes.c_void_p()
         _check(load().bem_assemble(ctx.handle, _p(self.V), self.V.shape[0], _p(self.T), self.T.shape[0],
                                    ctypes.byref(o), ctypes.byref(self._h)))

@@ -82,6 +82,53 @@ def test_long_star_general_contraction(ctx):
     assert err < 1e-12, err
 
 
+@pytest.mark.parametrize("name", ["book6", "crossed6", "extruded"])
+def test_panelled_assembly_matches(ctx, name):
+    # the pair matrix built and contracted in panels of at most 64 triangle rows gives the same W
+    m = small_meshes()[name]
+    print("case panels", name, m.nt, flush=True)
+    t = Topology(m.vertices, m.triangles)
+    p = lib.Problem(ctx, m.vertices, m.triangles, near_order=NEAR, precision=lib.FP32_REFINE, pair_panel_rows=64)
+    assert p.info["n_pair_panels"] > (1 if t.N > 64 else 0)
+    Wg = p.matrix()
+    Wo = assemble(m.vertices, m.triangles, t, NEAR)
+    assert np.array_equal(Wg, Wg.T)
+    assert np.abs(Wg - Wo).max() / np.abs(Wo).max() < 1e-12
+    full = lib.Problem(ctx, m.vertices, m.triangles, near_order=NEAR)
+    assert full.info["n_pair_panels"] == 0
+    assert np.abs(Wg - full.matrix()).max() <= 1e-14 * np.abs(Wo).max()
+    # the FP32 copy written by the panel contraction
+    x = np.random.default_rng(3).standard_normal((2, t.N))
+    assert np.allclose(p.matvec(x, fp32=True), x @ Wg.astype(np.float32).astype(np.float64), rtol=1e-5, atol=1e-6 * np.abs(x @ Wg).max())
+
+
+def test_panelled_long_star(ctx):
+    # panels with the general contraction kernel (the centre dof's star holds 520 triangles)
+    m = meshes.fan(520)
+    print("case panels fan520", m.nt, flush=True)
+    t = Topology(m.vertices, m.triangles)
+    p = lib.Problem(ctx, m.vertices, m.triangles, near_order=4, pair_panel_rows=64)
+    assert p.info["n_pair_panels"] > 1
+    Wg = p.matrix()
+    Wo = assemble(m.vertices, m.triangles, t, 4)
+    assert np.array_equal(Wg, Wg.T)
+    assert np.abs(Wg - Wo).max() / np.abs(Wo).max() < 1e-12
+
+
+def test_panelled_book48_rows(ctx):
+    w = meshes.workload("book48")
+    m = w.mesh
+    print("case panels book48", m.nt, flush=True)
+    pp = lib.Problem(ctx, m.vertices, m.triangles, near_order=NEAR, pair_panel_rows=3000)
+    pf = lib.Problem(ctx, m.vertices, m.triangles, near_order=NEAR)
+    assert pp.info["n_pair_panels"] >= 4
+    rows = np.random.default_rng(4).choice(pp.N, 24, replace=False)
+    a, b = pp.rows(rows), pf.rows(rows)
+    assert np.abs(a - b).max() <= 1e-13 * np.abs(b).max()
+    Wp = pp.matrix()
+    assert np.array_equal(Wp, Wp.T)
+
+
 def test_book48_sampled_rows(ctx):
     w = meshes.workload("book48")
     m = w.mesh

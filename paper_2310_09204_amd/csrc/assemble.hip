@@ -759,30 +759,51 @@ PanelTimes assemble_panels(bem_problem* p, const MeshTopo& m, const NearList& ne
     };
     std::vector<std::unique_ptr<Panel>> done;
     std::vector<int32_t> stamp(size_t(nt), -1);
-    int64_t bd0 = 0;
-    int pid = 0;
-    while (bd0 < ncb) {
-        auto P = std::make_unique<Panel>();
-        // grow the panel by whole 64-dof row blocks
-        int64_t bd1 = bd0;
-        while (bd1 < ncb) {
-            std::vector<int32_t> add;
-            for (int64_t rb = 4 * bd1; rb < 4 * bd1 + 4; ++rb)
-                for (int32_t g = plan.rg_ptr[rb]; g < plan.rg_ptr[rb + 1]; ++g) {
-                    const int32_t T = plan.rg[g].x;
-                    if (stamp[T] != pid) {
-                        stamp[T] = pid;
-                        add.push_back(T);
+    // panel boundaries first (whole 64-dof row blocks), so that one buffer of the largest panel's
+    // size serves all of them (a fresh allocation of tens of GB per panel costs seconds)
+    std::vector<int64_t> starts;
+    std::vector<std::vector<int32_t>> rowsets;
+    {
+        int64_t b0 = 0;
+        int id = 0;
+        while (b0 < ncb) {
+            std::vector<int32_t> rows;
+            int64_t b1 = b0;
+            while (b1 < ncb) {
+                std::vector<int32_t> add;
+                for (int64_t rb = 4 * b1; rb < 4 * b1 + 4; ++rb)
+                    for (int32_t g = plan.rg_ptr[rb]; g < plan.rg_ptr[rb + 1]; ++g) {
+                        const int32_t T = plan.rg[g].x;
+                        if (stamp[T] != id) {
+                            stamp[T] = id;
+                            add.push_back(T);
+                        }
                     }
+                if (b1 > b0 && int64_t(rows.size() + add.size()) > maxrows) {
+                    for (int32_t T : add) stamp[T] = -1;
+                    break;
                 }
-            if (bd1 > bd0 && int64_t(P->rows.size() + add.size()) > maxrows) {
-                for (int32_t T : add) stamp[T] = -1;
-                break;
+                rows.insert(rows.end(), add.begin(), add.end());
+                ++b1;
             }
-            P->rows.insert(P->rows.end(), add.begin(), add.end());
-            ++bd1;
+            std::sort(rows.begin(), rows.end());
+            starts.push_back(b0);
+            rowsets.push_back(std::move(rows));
+            b0 = b1;
+            ++id;
         }
-        std::sort(P->rows.begin(), P->rows.end());
+        starts.push_back(ncb);
+    }
+    int64_t max_elems = 1;
+    for (size_t q = 0; q < rowsets.size(); ++q) {
+        const int64_t ldq = (nt - sufmin[starts[q]] + 7) / 8 * 8;
+        max_elems = std::max<int64_t>(max_elems, int64_t(rowsets[q].size()) * ldq);
+    }
+    DeviceBuffer Ip(sizeof(double) * max_elems, s);
+    for (size_t pid = 0; pid < rowsets.size(); ++pid) {
+        auto P = std::make_unique<Panel>();
+        const int64_t bd0 = starts[pid], bd1 = starts[pid + 1];
+        P->rows = std::move(rowsets[pid]);
         const int64_t nrows = int64_t(P->rows.size());
         const int64_t tmin = sufmin[bd0];
         const int64_t ncol = nt - tmin;
@@ -807,7 +828,6 @@ PanelTimes assemble_panels(bem_problem* p, const MeshTopo& m, const NearList& ne
             for (int64_t cb = 0; cb < (ncol + kTile - 1) / kTile; ++cb) P->ftiles.push_back(make_int2(int(rb), int(cb)));
 
         DeviceBuffer d_rows = upload(P->rows, s), d_rowmap = upload(P->rowmap, s), d_ft = upload(P->ftiles, s);
-        DeviceBuffer Ip(sizeof(double) * std::max<int64_t>(1, nrows * ldP), s);
         P->ef = std::make_unique<EventTimer>(s);
         const int64_t nft = int64_t(P->ftiles.size());
         hipLaunchKernelGGL(k_far_rect, dim3(blocks_for(nft, 4)), dim3(256), 0, s, geo, int32_t(nt), d_rows.as<int32_t>(), nrows,
@@ -863,8 +883,6 @@ PanelTimes assemble_panels(bem_problem* p, const MeshTopo& m, const NearList& ne
         }
         P->ec->stop();
         done.push_back(std::move(P));
-        ++pid;
-        bd0 = bd1;
         mark("panel");
     }
     for (auto& P : done) {
@@ -872,7 +890,7 @@ PanelTimes assemble_panels(bem_problem* p, const MeshTopo& m, const NearList& ne
         out.near += P->en->seconds();
         out.contract += P->ec->seconds();
     }
-    out.panels = pid;
+    out.panels = int(rowsets.size());
     return out;
 }
 

@@ -399,13 +399,20 @@ __global__ __launch_bounds__(256) void k_block_apply(const int4* __restrict__ ta
     const int64_t row0 = int64_t(t.y) + 16 * wave;
     if (row0 >= m.n) return;
     const int64_t row = row0 + i;                 // < npad: padded rows exist in storage
-    typename MC::V acc = {0, 0, 0, 0};
-    strip_mfma<MT, 4>(inv + m.mat_off + row * m.npad, true, 0, m.npad, xg + m.xoff * 16, acc);
+    // matrix-core sums over chunks of at most 1024 columns, added up in FP64 (for FP32 inverses of
+    // large blocks the rounding stays at the level of one chunk)
+    double acc64[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t cc = 0; cc < m.npad; cc += 1024) {
+        typename MC::V acc = {0, 0, 0, 0};
+        strip_mfma<MT, 4>(inv + m.mat_off + row * m.npad, true, cc, min<int64_t>(m.npad, cc + 1024), xg + m.xoff * 16, acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc64[r] += double(acc[r]);
+    }
     if (i < kc) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int64_t rr = row0 + MC::out_row(kg, r);
-            if (rr < m.n) z[int64_t(i) * ld + idx[m.idx_off + rr]] = double(acc[r]);
+            if (rr < m.n) z[int64_t(i) * ld + idx[m.idx_off + rr]] = acc64[r];
         }
     }
 }

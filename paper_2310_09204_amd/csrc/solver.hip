@@ -112,7 +112,7 @@ __global__ void k_transpose_x(const double* __restrict__ x, int64_t ldx, int kc,
 template <typename MT>
 __global__ __launch_bounds__(256) void k_matvec_mfma(const MT* __restrict__ W, int64_t ldw, int64_t N,
                                                      const MT* __restrict__ xt, int64_t cols_per_split, int kc,
-                                                     double* __restrict__ y, int64_t ldy, MT* __restrict__ partial) {
+                                                     double* __restrict__ y, int64_t ldy, double* __restrict__ partial) {
     using MC = MatrixCore<MT>;
     using V16 = typename std::conditional<sizeof(MT) == 4, float4, double2>::type;
     constexpr int VEC = 16 / sizeof(MT);
@@ -128,6 +128,11 @@ __global__ __launch_bounds__(256) void k_matvec_mfma(const MT* __restrict__ W, i
     const int lr = tid >> 4;           // row of a 16-row load group
     const int lc = (tid & 15) * VEC;   // column within the tile
     typename MC::V acc = {0, 0, 0, 0};
+    // FP32 matrices: the matrix-core sums run over at most kFlushTiles tiles (1024 columns) and are
+    // then added into FP64, so the rounding of long rows (N ~ 1e5) stays at the level of one chunk
+    constexpr int kFlushTiles = 1024 / TC;
+    double acc64[4] = {0.0, 0.0, 0.0, 0.0};
+    int since_flush = 0;
     V16 va[4], vx;
     auto fetch = [&](int64_t jc) {
 #pragma unroll
@@ -150,28 +155,37 @@ __global__ __launch_bounds__(256) void k_matvec_mfma(const MT* __restrict__ W, i
         for (int st = 0; st < TC / 4; ++st)
             acc = MC::mac(tA[buf][wave * 16 + i][4 * st + kg], tX[buf][(4 * st + kg) * 16 + i], acc);
         buf ^= 1;
+        if constexpr (sizeof(MT) == 4) {
+            if (++since_flush == kFlushTiles) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc64[r] += double(acc[r]);
+                acc = typename MC::V{0, 0, 0, 0};
+                since_flush = 0;
+            }
+        }
     }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc64[r] += double(acc[r]);
     if (i < kc) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int64_t rr = row0 + wave * 16 + MC::out_row(kg, r);
             if (rr < N) {
-                if (partial) partial[(int64_t(split) * 16 + i) * ldw + rr] = acc[r];
-                else y[int64_t(i) * ldy + rr] = double(acc[r]);
+                if (partial) partial[(int64_t(split) * 16 + i) * ldw + rr] = acc64[r];
+                else y[int64_t(i) * ldy + rr] = acc64[r];
             }
         }
     }
 }
 
-template <typename MT>
-__global__ void k_reduce_splits(const MT* __restrict__ partial, int S, int kc, int64_t N, int64_t ldw,
+__global__ void k_reduce_splits(const double* __restrict__ partial, int S, int kc, int64_t N, int64_t ldw,
                                 double* __restrict__ y, int64_t ldy) {
     const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (e >= int64_t(kc) * N) return;
     const int n = int(e / N);
     const int64_t r = e % N;
     double s = 0.0;
-    for (int q = 0; q < S; ++q) s += double(partial[(int64_t(q) * 16 + n) * ldw + r]);
+    for (int q = 0; q < S; ++q) s += partial[(int64_t(q) * 16 + n) * ldw + r];
     y[int64_t(n) * ldy + r] = s;
 }
 
@@ -392,7 +406,7 @@ void launch_matvec(const bem_problem* p, const MT* W, const double* x, int64_t l
             continue;
         }
         MT* xt = static_cast<MT*>(p->mv_xt.ptr);
-        MT* part = static_cast<MT*>(p->mv_partial.ptr);
+        double* part = p->mv_partial.as<double>();
         hipLaunchKernelGGL(k_transpose_x<MT>, dim3(unsigned((ldw * 16 + 255) / 256)), dim3(256), 0, s, xc, ldx, kc, N, ldw, xt);
         // split the columns when there are too few 64-row blocks to keep every CU streaming
         const int64_t blocks = (N + 63) / 64;
@@ -407,7 +421,7 @@ void launch_matvec(const bem_problem* p, const MT* W, const double* x, int64_t l
         const dim3 grid{unsigned(blocks), unsigned(S), 1u};
         hipLaunchKernelGGL(k_matvec_mfma<MT>, grid, dim3(256), 0, s, W, ldw, N, xt, cps, kc, yc, ldy, S > 1 ? part : nullptr);
         if (S > 1)
-            hipLaunchKernelGGL(k_reduce_splits<MT>, dim3(unsigned((int64_t(kc) * N + 255) / 256)), dim3(256), 0, s, part, S, kc, N,
+            hipLaunchKernelGGL(k_reduce_splits, dim3(unsigned((int64_t(kc) * N + 255) / 256)), dim3(256), 0, s, part, S, kc, N,
                                ldw, yc, ldy);
         HIP_CHECK(hipGetLastError());
     }
@@ -458,7 +472,7 @@ void matvec_device(const bem_problem* p, bool fp32, const double* d_x, int64_t l
     if (p->N == 0) return;
     if (fp32) {
         if (!p->W32.ptr) fail(BEM_E_INVALID_ARG, "problem has no FP32 matrix (assemble with BEM_FP32_REFINE)");
-        launch_matvec<float, float>(p, p->W32.as<float>(), d_x, ldx, k, d_y, ldx, s);
+        launch_matvec<float, double>(p, p->W32.as<float>(), d_x, ldx, k, d_y, ldx, s);
     } else {
         launch_matvec<double, double>(p, p->W64.as<double>(), d_x, ldx, k, d_y, ldx, s);
     }

@@ -148,7 +148,7 @@ def _replay(lib, reqs, ctx, scale, max_inflight):
     for i in range(len(reqs)):
         while tickets[i] is None:
             time.sleep(1e-4)
-        results.append(srv.poll(tickets[i]))
+        results.append(srv.poll(tickets[i]) + (srv.last_message,))
     t_end = time.perf_counter()
     th.join()
     stats = srv.stats()
@@ -165,14 +165,22 @@ def serving_leg(lib, meshes, ctx, n_requests, load, seed=0, max_inflight=4):
     server measures it; solves/s counts right-hand sides within rel.err 1e-8 of an FP64 solve of
     the same request (computed after the stream, not timed)."""
     reqs = meshes.serving_stream(seed, n_requests, rate=1.0)    # arrival times for rate 1/s
-    _, t_burst, _ = _replay(lib, reqs, ctx, 0.0, max_inflight)
+    res_b, t_burst, _ = _replay(lib, reqs, ctx, 0.0, max_inflight)
+    for i, res in enumerate(res_b):
+        if res[2] < 0:
+            log("bench: serving request %d failed in the burst: rc %d %s" % (i, res[2], res[3]))
     capacity = n_requests / t_burst                              # requests/s
     rate = load * capacity
     results, t_run, stats = _replay(lib, reqs, ctx, 1.0 / rate, max_inflight)
-    solved, total, worst = 0, 0, 0.0
+    solved, worst = 0, 0.0
     by_geo = {}
+    total = sum(r.g.shape[0] for r in reqs)
+    failed = [(i, res[2], res[3]) for i, res in enumerate(results) if res[2] < 0]
+    for i, rc, msg in failed:
+        log("bench: serving request %d failed: rc %d %s" % (i, rc, msg))
     for r, res in zip(reqs, results):
-        by_geo.setdefault(r.geometry, []).append((r, res))
+        if res[2] >= 0:
+            by_geo.setdefault(r.geometry, []).append((r, res[:3]))
     for items in by_geo.values():
         r0 = items[0][0]
         p = lib.Problem(ctx, r0.mesh.vertices, r0.mesh.triangles)
@@ -182,14 +190,14 @@ def serving_leg(lib, meshes, ctx, n_requests, load, seed=0, max_inflight=4):
             ref, _, _ = p.solve(g=r.g, precond=M, tol=1e-13)
             err = np.linalg.norm(phi - ref, axis=1) / np.linalg.norm(ref, axis=1)
             solved += int((err <= 1e-8).sum())
-            total += r.g.shape[0]
             worst = max(worst, float(err.max()))
         M.close()
         p.close()
-    lat = sorted(info[0]["t_total_s"] for (_, info, _) in results)
+    lat = sorted(res[1][0]["t_total_s"] for res in results)
     n_dofs = [int(res[0].shape[1]) for res in results]
     return {
-        "requests": len(reqs), "rhs": total, "rhs_within_1e-8": solved, "relerr_max": worst,
+        "requests": len(reqs), "failed_requests": len(failed),
+        "direct_launch_requests": sum(1 for res in results if res[2] >= 0 and res[1][0]["graph"] == 0), "rhs": total, "rhs_within_1e-8": solved, "relerr_max": worst,
         "capacity_requests_per_s": capacity, "load": load, "arrival_rate_per_s": rate,
         "max_inflight": max_inflight,
         "solves_per_s": solved / t_run,
@@ -198,6 +206,64 @@ def serving_leg(lib, meshes, ctx, n_requests, load, seed=0, max_inflight=4):
         "mixed_requests": int(sum(r.mixed for r in reqs)),
         "server": stats,
     }
+
+
+def large_leg(lib, meshes, ctx, k=16):
+    """crossed192 (N = 110,017; W 48 GB FP32 + 97 GB FP64, the pair matrix built in panels): a
+    warm-up step, then one timed step (assembly, set-up, mixed-precision solve of k right-hand
+    sides to relative residual 1e-10), the FP64 PCG solve of the same system beside it, and an
+    FP64 reference (tol 1e-13) for the errors."""
+    w = meshes.workload("crossed192", seed=0, k=k)
+    m = w.mesh
+    ctx.release_cached()
+
+    def one_step():
+        t0 = time.perf_counter()
+        p = lib.Problem(ctx, m.vertices, m.triangles, precision=lib.FP32_REFINE, near_order=10)
+        t1 = time.perf_counter()
+        M = lib.Preconditioner(p, w.patch_of_triangle, w.coarse.vertices, w.coarse.triangles,
+                               w.coarse_of_triangle, factor_fp32=True)
+        t2 = time.perf_counter()
+        phi, info, rc = p.solve(g=w.g, precond=M, tol=1e-10, precision=lib.FP32_REFINE)
+        t3 = time.perf_counter()
+        return p, M, phi, info, (t0, t1, t2, t3)
+
+    p, M, _, _, (t0, t1, t2, t3) = one_step()
+    first = t3 - t0
+    M.close()
+    p.close()
+    p, M, phi, info, (t0, t1, t2, t3) = one_step()
+    pinfo = p.info
+    t4 = time.perf_counter()
+    phi64, info64, _ = p.solve(g=w.g, precond=M, tol=1e-10, precision=lib.FP64)
+    t5 = time.perf_counter()
+    ref, _, _ = p.solve(g=w.g, precond=M, tol=1e-13, precision=lib.FP64)
+    err = np.linalg.norm(phi - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    err64 = np.linalg.norm(phi64 - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    N = pinfo["n_dofs"]
+    t32 = p.bench_matvec(fp32=True, k=16, reps=3)
+    t64 = p.bench_matvec(fp32=False, k=16, reps=3)
+    nt = m.nt
+    step = t3 - t0
+    out = {
+        "workload": "crossed192: " + w.description, "n_dofs": N, "n_tri": nt, "k": k,
+        "pair_panels": pinfo["n_pair_panels"],
+        "t_step_s": step, "t_first_step_s": first, "t_assemble_s": t1 - t0, "t_precond_s": t2 - t1,
+        "t_solve_s": t3 - t2, "t_far_s": pinfo["t_far_s"], "t_near_s": pinfo["t_near_s"],
+        "t_contract_s": pinfo["t_contract_s"], "t_host_s": pinfo["t_host_s"],
+        "solves_per_s": int((err <= 1e-8).sum()) / step,
+        "iters": [i["iters"] for i in info], "relerr_max": float(err.max()),
+        "fp64_solve": {"t_solve_s": t5 - t4, "iters": [i["iters"] for i in info64], "relerr_max": float(err64.max())},
+        "pair_integrals_per_s": nt * (nt + 1) / 2 / (t1 - t0),
+        "matvec": {"fp32_k16_GBs": N * N * 4 / t32 / 1e9, "fp64_k16_GBs": N * N * 8 / t64 / 1e9},
+        "patches": M.sizes(),
+    }
+    M.close()
+    p.close()
+    ctx.release_cached()
+    log("bench: crossed192 step %.3fs (first %.3fs) asm %.3f precond %.3f solve %.3f iters %s relerr %.2e"
+        % (step, first, t1 - t0, t2 - t1, t3 - t2, out["iters"][:4], out["relerr_max"]))
+    return out
 
 
 def main():
@@ -214,6 +280,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--serve-requests", type=int, default=24,
                     help="requests in the serving-stream leg (0 skips it)")
+    ap.add_argument("--no-large", action="store_true", help="skip the crossed192 leg")
     ap.add_argument("--serve-load", type=float, default=0.7,
                     help="arrival rate of the serving leg as a fraction of its measured capacity")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -371,6 +438,9 @@ def main():
         "matvec": mv,
         "fp64_compare": fp64_step,
     }
+    if not args.no_large and args.workload != "crossed192":
+        log("bench: crossed192 leg")
+        out["crossed192"] = large_leg(lib, meshes, ctx)
     if args.serve_requests > 0:
         log("bench: serving stream (%d requests, load %.2f)" % (args.serve_requests, args.serve_load))
         out["serving"] = serving_leg(lib, meshes, ctx, args.serve_requests, args.serve_load)

@@ -98,6 +98,9 @@ typedef struct {
     int iters;               /* (P)CG iterations (products with W) of this column */
     int outer_iters;         /* FP64 residual recomputations (mixed precision) */
     int status;              /* BEM_OK / BEM_E_NOT_CONVERGED / BEM_E_BREAKDOWN */
+    int graph;               /* 1: iterations replayed from captured graphs; 0: launched directly
+                              * (use_graph = 0, or a capture the HIP runtime broke off because of a
+                              * call elsewhere in the process; same kernels, same results) */
     double relres;           /* final ||L - W x|| / ||L|| with the FP64 matrix */
     double est_cond;         /* Lanczos estimate of kappa(M W) from the (P)CG coefficients */
     double t_total_s;        /* wall time of the whole call */
@@ -110,6 +113,11 @@ int bem_ctx_create(int hip_device, size_t hbm_budget_bytes, bem_ctx** out);
 void bem_ctx_destroy(bem_ctx* ctx);
 /* Waits for all device work of the context's device (hipDeviceSynchronize). */
 int bem_ctx_synchronize(bem_ctx* ctx);
+/* Device buffers the library frees are kept per device for reuse (a stream-ordered cache, shared
+ * by all contexts of the device).  This returns them to the HIP runtime; it waits for the
+ * buffers' last users and serialises with graph captures of concurrent solves.  Only memory no
+ * live problem or preconditioner holds is released.  Returns BEM_OK or BEM_E_DEVICE. */
+int bem_ctx_release_cached(bem_ctx* ctx);
 
 /* ---- host-side mesh analysis (no device work) --------------------------------------------- */
 /* Sectors and dofs of Section 4.2 for a mesh: returns the number of dofs in *n_dofs and, if the

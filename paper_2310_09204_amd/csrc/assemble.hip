@@ -741,9 +741,10 @@ PanelTimes assemble_panels(bem_problem* p, const MeshTopo& m, const NearList& ne
     }
     int64_t maxrows = p->panel_rows;
     if (maxrows <= 0) {
-        size_t fb = 0, tb = 0;
-        HIP_CHECK(hipMemGetInfo(&fb, &tb));
-        maxrows = int64_t(0.6 * double(fb) / (8.0 * double(nt)));
+        maxrows = int64_t(0.6 * double(available_device_bytes(p->ctx->device)) / (8.0 * double(nt)));
+        // in steps of 2048 rows, so that a repeat of the same mesh plans the same panels and gets
+        // the panel buffer of its predecessor back from the pool
+        maxrows = maxrows / 2048 * 2048;
     }
     maxrows = std::max<int64_t>(maxrows, kTile);
     DeviceBuffer d_cb_ptr = upload(plan.cb_ptr, s), d_cb_tri = upload(plan.cb_tri, s);
@@ -945,8 +946,7 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
     // When the whole matrix does not fit next to W (about 8 N_T^2 + 3 N_T^2 bytes with N ~ N_T / 2),
     // or panels are requested, it is built and contracted panel by panel after the mesh analysis.
     const int64_t ldI = (nt + 7) / 8 * 8;
-    size_t free_b = 0, total_b = 0;
-    HIP_CHECK(hipMemGetInfo(&free_b, &total_b));
+    const size_t free_b = available_device_bytes(p->ctx->device);
     const double full_bytes = 8.0 * double(nt) * double(ldI) + 3.0 * double(nt) * double(nt);
     const bool paneled = p->panel_rows > 0 || full_bytes > 0.85 * double(free_b);
     if (paneled && p->has_pairs) fail(BEM_E_INVALID_ARG, "keep_pair_matrix needs the whole pair matrix on the device");

@@ -78,6 +78,19 @@ void release_cached_device_memory(int device) {
     P.events.clear();
 }
 
+size_t available_device_bytes(int device) {
+    size_t fb = 0, tb = 0;
+    {
+        std::lock_guard<std::mutex> cap(capture_mutex());
+        HIP_CHECK(hipMemGetInfo(&fb, &tb));
+    }
+    MemPool& P = mem_pool(device);
+    std::lock_guard<std::mutex> lk(P.mu);
+    for (auto& kv : P.free) fb += kv.first;
+    for (auto& q : P.pending) fb += q.cap;
+    return fb;
+}
+
 DeviceBuffer::DeviceBuffer(size_t b, hipStream_t s) : bytes(b), stream(s) {
     if (b == 0) return;
     (void)hipGetDevice(&dev);
@@ -95,11 +108,17 @@ DeviceBuffer::DeviceBuffer(size_t b, hipStream_t s) : bytes(b), stream(s) {
             return;
         }
     }
-    hipError_t e = hipMalloc(&ptr, want);
+    // fresh allocations are rare (the pool serves repeats) and are kept apart from graph captures
+    // of concurrent solves, like every other call that may synchronise the device
+    auto fresh = [&]() {
+        std::lock_guard<std::mutex> cap(capture_mutex());
+        return hipMalloc(&ptr, want);
+    };
+    hipError_t e = fresh();
     if (e == hipErrorOutOfMemory) {
         (void)hipGetLastError();
         release_cached_device_memory(dev);
-        e = hipMalloc(&ptr, want);
+        e = fresh();
     }
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -123,9 +142,11 @@ void DeviceBuffer::reset() {
                 ev = P.events.back();
                 P.events.pop_back();
             } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+                (void)hipGetLastError();
                 ev = nullptr;
             }
             if (ev && hipEventRecord(ev, stream) != hipSuccess) {
+                (void)hipGetLastError();
                 P.events.push_back(ev);
                 ev = nullptr;
             }
@@ -133,9 +154,10 @@ void DeviceBuffer::reset() {
         if (ev) {
             P.pending.push_back({cap, ptr, ev});
         } else if (stream) {
-            // no event: wait for the stream here rather than hand out memory still in use
-            (void)hipStreamSynchronize(stream);
-            P.free.emplace(cap, ptr);
+            // no event: wait for the stream here rather than hand out memory still in use; if
+            // even that fails the buffer is not reused
+            if (hipStreamSynchronize(stream) == hipSuccess) P.free.emplace(cap, ptr);
+            else (void)hipGetLastError();
         } else {
             P.free.emplace(cap, ptr);
         }
@@ -170,7 +192,8 @@ void solve_device(bem_problem* p, const bem_precond* M, const double* b, double*
 
 using namespace bem;
 
-#define BEM_TRY try { ::bem::RelaxedCapture relaxed_capture_guard_;
+// an error left pending by calls made before this entry point belongs to those calls
+#define BEM_TRY try { ::bem::RelaxedCapture relaxed_capture_guard_; (void)hipGetLastError();
 #define BEM_CATCH                                              \
     }                                                          \
     catch (const Failure& f) {                                 \
@@ -263,6 +286,17 @@ void bem_ctx_destroy(bem_ctx* ctx) {
     }
     release_cached_device_memory(ctx->device);
     delete ctx;
+    (void)hipGetLastError();   // nothing to report to: failures here leave no pending error
+}
+
+int bem_ctx_release_cached(bem_ctx* ctx) {
+    BEM_TRY
+    if (!ctx) fail(BEM_E_INVALID_ARG, "NULL ctx");
+    set_device(ctx);
+    release_cached_device_memory(ctx->device);
+    HIP_CHECK(hipGetLastError());
+    return BEM_OK;
+    BEM_CATCH
 }
 
 int bem_ctx_synchronize(bem_ctx* ctx) {
@@ -328,7 +362,10 @@ int bem_assemble(bem_ctx* ctx, const double* vertices, int64_t nv, const int32_t
     p->has_w32 = opts && opts->precision == BEM_FP32_REFINE;
     p->has_pairs = opts && opts->keep_pair_matrix;
     p->panel_rows = (opts && opts->pair_panel_rows > 0) ? opts->pair_panel_rows : 0;
-    HIP_CHECK(hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking));
+    {
+        std::lock_guard<std::mutex> cap(capture_mutex());
+        HIP_CHECK(hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking));
+    }
     try {
         assemble_device(p.get(), vertices, nv, triangles, nt, [&](NearList& near) {
             analyze_mesh(vertices, nv, triangles, nt, p->topo);
@@ -368,6 +405,7 @@ void bem_problem_destroy(bem_problem* p) {
         std::lock_guard<std::mutex> cap(capture_mutex());
         (void)hipStreamDestroy(s);
     }
+    (void)hipGetLastError();
 }
 
 int bem_problem_get_info(const bem_problem* p, bem_problem_info* info) {
@@ -505,6 +543,7 @@ void bem_precond_destroy(bem_precond* m) {
     (void)hipSetDevice(m->p->ctx->device);
     (void)hipStreamSynchronize(m->p->stream);
     delete m;
+    (void)hipGetLastError();
 }
 
 int bem_precond_sizes(const bem_precond* m, int64_t* n_faces, int64_t* n_wb, int64_t* n_coarse, int64_t* max_face) {

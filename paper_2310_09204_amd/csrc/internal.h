@@ -105,6 +105,9 @@ struct RelaxedCapture {
 
 constexpr size_t kPooledBytes = size_t(64) << 20;
 void release_cached_device_memory(int device);
+// free device memory as the runtime reports it plus what the pool holds for reuse (which a
+// large allocation gets back by releasing the cache when the runtime runs out)
+size_t available_device_bytes(int device);
 
 struct DeviceBuffer {
     void* ptr = nullptr;

@@ -758,7 +758,10 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
     // the coarse block's work (second stream) starts after the layout uploads queued so far
     hipStream_t s2 = s;
     if (M->nH > 0) {
-        if (!p->aux_stream) HIP_CHECK(hipStreamCreateWithFlags(&p->aux_stream, hipStreamNonBlocking));
+        if (!p->aux_stream) {
+            std::lock_guard<std::mutex> cap(capture_mutex());
+            HIP_CHECK(hipStreamCreateWithFlags(&p->aux_stream, hipStreamNonBlocking));
+        }
         s2 = p->aux_stream;
         hipEvent_t ready;
         HIP_CHECK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));

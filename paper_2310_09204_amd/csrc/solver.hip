@@ -485,6 +485,7 @@ void matvec_device(const bem_problem* p, bool fp32, const double* d_x, int64_t l
 struct PcgResult {
     std::vector<int> iters, flag, active, refreshes;
     std::vector<double> rr, bb, cond;
+    bool graphed = false;
 };
 
 // Block (P)CG on device buffers.  b, x: [k][ld]; x is the start vector (zero it for x0 = 0) and
@@ -554,23 +555,71 @@ PcgResult pcg_device(bem_problem* p, const bem_precond* M, bool mixed, const dou
         hipLaunchKernelGGL(k_dot_partial, vg, vb, 0, s, r.as<double>(), z.as<double>(), ld, N, pc);
         hipLaunchKernelGGL(k_beta, dim3(k), vb, 0, s, pc, int(G), st, h, max_hist);
         hipLaunchKernelGGL(k_update_p, vg, vb, 0, s, pp.as<double>(), z.as<double>(), ld, N, st);
-        HIP_CHECK(hipGetLastError());
     };
 
-    hipGraph_t graph[2] = {nullptr, nullptr};
-    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    // the captured iterations; an exception between begin and end of a capture still ends it, so
+    // the stream never stays in capture mode
+    struct Graphs {
+        hipStream_t s;
+        bool capturing = false;
+        hipGraph_t graph[2] = {nullptr, nullptr};
+        hipGraphExec_t exec[2] = {nullptr, nullptr};
+        ~Graphs() {
+            if (capturing) {
+                hipGraph_t g = nullptr;
+                if (hipStreamEndCapture(s, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+                (void)hipGetLastError();
+            }
+            for (int v = 0; v < 2; ++v) {
+                if (exec[v]) (void)hipGraphExecDestroy(exec[v]);
+                if (graph[v]) (void)hipGraphDestroy(graph[v]);
+            }
+        }
+    } gr{s};
+    // A capture that fails with a capture error (the runtime ends a capture when a call elsewhere
+    // in the process is not permitted alongside it) queued no work: the solve then launches its
+    // iterations directly, with the same kernels and results.
+    auto capture_error = [](hipError_t e) {
+        return e == hipErrorStreamCaptureUnsupported || e == hipErrorStreamCaptureInvalidated ||
+               e == hipErrorStreamCaptureMerge || e == hipErrorStreamCaptureUnmatched ||
+               e == hipErrorStreamCaptureUnjoined || e == hipErrorStreamCaptureIsolation ||
+               e == hipErrorStreamCaptureImplicit || e == hipErrorCapturedEvent ||
+               e == hipErrorStreamCaptureWrongThread;
+    };
+    bool graphed = false;
     if (use_graph) {
         std::lock_guard<std::mutex> lk(capture_mutex());   // no device-wide synchronisation meanwhile
-        for (int v = 0; v < (mixed ? 2 : 1); ++v) {
-            HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
-            iteration(v == 1);
-            HIP_CHECK(hipStreamEndCapture(s, &graph[v]));
-            HIP_CHECK(hipGraphInstantiate(&exec[v], graph[v], nullptr, nullptr, 0));
+        graphed = true;
+        for (int v = 0; v < (mixed ? 2 : 1) && graphed; ++v) {
+            hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
+            if (e == hipSuccess) {
+                gr.capturing = true;
+                iteration(v == 1);
+                e = hipGetLastError();
+                hipGraph_t g = nullptr;
+                const hipError_t e_end = hipStreamEndCapture(s, &g);
+                gr.capturing = false;
+                gr.graph[v] = g;
+                if (e == hipSuccess) e = e_end;
+                if (e == hipSuccess && !g) e = hipErrorStreamCaptureInvalidated;
+            }
+            if (e == hipSuccess) {
+                HIP_CHECK(hipGraphInstantiate(&gr.exec[v], gr.graph[v], nullptr, nullptr, 0));
+            } else if (capture_error(e)) {
+                (void)hipGetLastError();
+                graphed = false;
+            } else {
+                HIP_CHECK(e);
+            }
         }
     }
     auto launch = [&](bool replace) {
-        if (use_graph) HIP_CHECK(hipGraphLaunch(exec[replace ? 1 : 0], s));
-        else iteration(replace);
+        if (graphed) {
+            HIP_CHECK(hipGraphLaunch(gr.exec[replace ? 1 : 0], s));
+        } else {
+            iteration(replace);
+            HIP_CHECK(hipGetLastError());
+        }
     };
     std::vector<ColState> hs(k);
     int launched = 0;
@@ -602,12 +651,8 @@ PcgResult pcg_device(bem_problem* p, const bem_precond* M, bool mixed, const dou
         if (near || fallen)
             for (int c = 0; c < k; ++c) rr_ref[c] = hs[c].rr;
     }
-    for (int v = 0; v < 2; ++v) {
-        if (exec[v]) (void)hipGraphExecDestroy(exec[v]);
-        if (graph[v]) (void)hipGraphDestroy(graph[v]);
-    }
-
     PcgResult res;
+    res.graphed = graphed;
     res.iters.resize(k); res.flag.resize(k); res.active.resize(k); res.rr.resize(k); res.bb.resize(k); res.cond.assign(k, std::nan(""));
     res.refreshes.resize(k);
     std::vector<double> hh;
@@ -648,11 +693,12 @@ void solve_device(bem_problem* p, const bem_precond* M, const double* b, double*
     std::vector<double> relres(k, 0.0), cond(k, std::nan(""));
 
     hipLaunchKernelGGL(k_fill, dim3(256), vb, 0, s, x, 0.0, int64_t(k) * ld);
-    bool final_check = true;
+    bool final_check = true, graphed = false;
     if (o.precision == BEM_FP64) {
         std::vector<double> tol(k, o.tol);
         PcgResult r = pcg_device(p, use_m ? M : nullptr, false, b, x, false, k, ld, tol, o.max_iter, check, o.use_graph != 0, true,
                                  0.0);
+        graphed = r.graphed;
         for (int c = 0; c < k; ++c) {
             iters[c] = r.iters[c];
             cond[c] = r.cond[c];
@@ -666,6 +712,7 @@ void solve_device(bem_problem* p, const bem_precond* M, const double* b, double*
         const double refresh = (o.refresh_factor > 0 && o.refresh_factor < 1) ? o.refresh_factor : 1e-3;
         PcgResult r = pcg_device(p, use_m ? M : nullptr, true, b, x, false, k, ld, tol, o.max_iter, check, o.use_graph != 0, true,
                                  refresh);
+        graphed = r.graphed;
         final_check = false;
         for (int c = 0; c < k; ++c) {
             iters[c] = r.iters[c];
@@ -700,6 +747,7 @@ void solve_device(bem_problem* p, const bem_precond* M, const double* b, double*
             info[c].iters = iters[c];
             info[c].outer_iters = outer[c];
             info[c].status = status[c];
+            info[c].graph = graphed ? 1 : 0;
             info[c].relres = relres[c];
             info[c].est_cond = cond[c];
             info[c].t_total_s = tt;

@@ -56,7 +56,7 @@ class SolveOpts(ctypes.Structure):
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("outer_iters", ctypes.c_int), ("status", ctypes.c_int),
-                ("relres", ctypes.c_double), ("est_cond", ctypes.c_double), ("t_total_s", ctypes.c_double)]
+                ("graph", ctypes.c_int), ("relres", ctypes.c_double), ("est_cond", ctypes.c_double), ("t_total_s", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -89,6 +89,7 @@ SIGNATURES = {
     "bem_ctx_create": (_ci, [_ci, ctypes.c_size_t, ctypes.POINTER(_vp)]),
     "bem_ctx_destroy": (None, [_vp]),
     "bem_ctx_synchronize": (_ci, [_vp]),
+    "bem_ctx_release_cached": (_ci, [_vp]),
     "bem_problem_bench_matvec": (_ci, [_vp, _ci, _i32, _ci, ctypes.POINTER(ctypes.c_double)]),
     "bem_mesh_analyze": (_ci, [_vp, _i64, _vp, _i64, ctypes.POINTER(_i64), _vp, _vp, _vp]),
     "bem_assemble": (_ci, [_vp, _vp, _i64, _vp, _i64, ctypes.POINTER(AssembleOpts), ctypes.POINTER(_vp)]),
@@ -176,6 +177,10 @@ class Context:
 
     def synchronize(self):
         _check(load().bem_ctx_synchronize(self._h))
+
+    def release_cached(self):
+        """Returns the device buffers the library keeps for reuse to the HIP runtime."""
+        _check(load().bem_ctx_release_cached(self._h))
 
     def close(self):
         if self._h:

@@ -91,6 +91,7 @@ def test_multi_rhs_equals_single_and_graph_equals_eager(ctx):
         assert np.abs(phi_i[0] - phi_all[i]).max() <= 1e-13 * np.abs(phi_all[i]).max()
     phi_e, info_e, _ = p.solve(g=G, precond=M, tol=1e-11, use_graph=False)
     assert np.array_equal(phi_e, phi_all)
+    assert all(i["graph"] == 1 for i in info_all) and all(i["graph"] == 0 for i in info_e)
 
 
 @pytest.mark.parametrize("name", ["square16", "crossed16"])

@@ -422,7 +422,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "%s: %s; %d right-hand sides per step (block PCG), %s PCG to relative "
                                "residual %.0e, rel.err <= 1e-8 vs FP64 reference" %
-                               (args.workload, w.description, args.k, "FP32-matrix + FP64-refinement" if mixed else "FP64",
+                               (args.workload, w.description, args.k, "mixed-precision (FP32 products, reliable FP64 residual updates)" if mixed else "FP64",
                                 args.tol),
                    "n_dofs": N, "n_tri": nt, "k": args.k, "precision": args.precision,
                    "patches": ref["precond_sizes"]},

@@ -41,10 +41,10 @@ def log(*a):
 
 
 def far_kernel_source_hash():
-    """Hash of the far-field kernel's own source text (its constants through its closing brace),
-    so that counters taken on an older version of the kernel are not reported."""
+    """Hash of the far-field pass's own source text (its constants and its three kernels, through
+    the far kernel's closing brace), so that counters taken on an older version are not reported."""
     src = open(os.path.join(ROOT, "paper_2310_09204_amd", "csrc", "assemble.hip")).read()
-    a = src.index("constexpr int kChunk")
+    a = src.index("constexpr int kGrp")
     b = src.index("\n}\n", src.index("void k_far(", a)) + 3
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 

@@ -7,9 +7,12 @@
 // Pipeline (all on the device):
 //   k_geometry      per triangle: unit normal, area, the 7 Gauss points and area-weights
 //   k_jump_vectors  per (dof, triangle) incidence: J_{T,d}
+//   k_group_bounds  per group of 16 triangles: bounding sphere of their Gauss points
+//   k_col_records   per triangle: its Gauss points about its group's centre, scaled by 1/w^2
 //   k_far           7x7 product rule for every pair in 64x64 triangle tiles above the diagonal;
 //                   each lane keeps its row triangle's Gauss points in registers while the wave
-//                   walks the tile's column triangles, whose points come in through scalar loads
+//                   walks the tile's column triangles, whose data come in through scalar loads;
+//                   separated groups use a centred form of |x - y|^2 (fewer instructions)
 //   k_near_*        Duffy-regularised Gauss-Legendre rules for pairs sharing a triangle, an edge
 //                   or a vertex (overwrite the far-rule values of those pairs)
 //   k_contract      W = sum over the stars of the two dofs, upper triangle, mirrored
@@ -82,16 +85,93 @@ __global__ void k_jump_vectors(const double* __restrict__ V, const int32_t* __re
     for (int k = 0; k < 3; ++k) J[3 * e + k] = s * (V[3 * int64_t(v1) + k] - V[3 * int64_t(v2) + k]);
 }
 
-// One wave per 64x64 tile (rb <= cb); 4 waves per block.  Lane t keeps its row triangle's 7 Gauss
-// points in registers; the wave walks the tile's column triangles tp, whose points arrive through
-// scalar loads.  Results go out in chunks of 16 columns: row tp of I directly (64 consecutive
-// entries), and row t of I through an LDS transpose so that each store instruction writes eight
-// complete 128-byte rows segments instead of 64 scattered 8-byte pieces.
-constexpr int kChunk = 16;
+// ---------------------------------------------------------------------------------------------
+// Far field.  For the Gauss points x (row triangle) and y (column triangle, area-weight w), centred
+// on a point c with u = -2 (x - c), alpha = |x - c|^2 and v = y - c,
+//
+//   |x - y|^2 / w^2 = alpha (1/w^2) + |v|^2/w^2 + u . (v/w^2),
+//
+// so with the column point stored as the record (v/w^2, 1/w^2, |v|^2/w^2) one fused multiply-add
+// and three more give |x - y|^2 / w^2, whose reciprocal square root is w / |x - y| itself: the
+// column weight costs nothing and the distance costs four instructions instead of six.  With the
+// Newton step y (3 - s y^2) / 2 and the sum, an evaluation is 7 FP64 instructions and the
+// reciprocal square root (a quarter-rate instruction), against 10 and the same root for the
+// differences x - y.
+//
+// Rounding: the terms are bounded by (|x - c| + |y - c|)^2, so the relative error of |x - y|^2
+// grows like ((|x - c| + |y - c|) / |x - y|)^2.  c is the centre of the column triangle's group of
+// 16 (consecutive triangles); a group of columns takes this form only if its centre is at least
+// kSep (rho_R + rho_C) from the centre of the row tile (rho the radii of the Gauss points about
+// the centres), which bounds that ratio by (kSep + 1) / (kSep - 1) = 5.  Closer groups take the
+// differences.  Pairs that share a vertex are overwritten by the near rules in either case.
+// ---------------------------------------------------------------------------------------------
+constexpr int kGrp = 16;
+constexpr double kSep = 1.5;
+constexpr int kRec = 35;   // 7 points x (v/w^2, 1/w^2, |v|^2/w^2)
 
-__global__ __launch_bounds__(256) void k_far(const double* __restrict__ geo, int32_t nt, int64_t ld,
-                                             const int2* __restrict__ tiles, int64_t ntiles,
-                                             double* __restrict__ I) {
+// per group of 16 consecutive triangles: centre of the bounding box of their Gauss points, and the
+// largest distance of one of those points from it
+__global__ void k_group_bounds(const double* __restrict__ geo, int32_t nt, double* __restrict__ gb) {
+    const int64_t g = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    const int64_t ng = (int64_t(nt) + kGrp - 1) / kGrp;
+    if (g >= ng) return;
+    const int64_t t0 = g * kGrp, t1 = min<int64_t>(nt, t0 + kGrp);
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t t = t0; t < t1; ++t)
+        for (int p = 0; p < 7; ++p)
+            for (int k = 0; k < 3; ++k) {
+                const double v = geo[t * kGeo + 3 * p + k];
+                lo[k] = fmin(lo[k], v);
+                hi[k] = fmax(hi[k], v);
+            }
+    double c[3], r2 = 0.0;
+    for (int k = 0; k < 3; ++k) c[k] = 0.5 * (lo[k] + hi[k]);
+    for (int64_t t = t0; t < t1; ++t)
+        for (int p = 0; p < 7; ++p) {
+            double d2 = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                const double d = geo[t * kGeo + 3 * p + k] - c[k];
+                d2 = fma(d, d, d2);
+            }
+            r2 = fmax(r2, d2);
+        }
+    gb[4 * g] = c[0];
+    gb[4 * g + 1] = c[1];
+    gb[4 * g + 2] = c[2];
+    gb[4 * g + 3] = sqrt(r2) * (1.0 + 1e-12);
+}
+
+// per triangle: its 7 column records about the centre of its group
+__global__ void k_col_records(const double* __restrict__ geo, const double* __restrict__ gb, int32_t nt,
+                              double* __restrict__ rec) {
+    const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (t >= nt) return;
+    const double* c = gb + 4 * (t / kGrp);
+    for (int q = 0; q < 7; ++q) {
+        const double w = geo[t * kGeo + 21 + q];
+        const double iw2 = 1.0 / (w * w);
+        const double v0 = geo[t * kGeo + 3 * q] - c[0], v1 = geo[t * kGeo + 3 * q + 1] - c[1],
+                     v2 = geo[t * kGeo + 3 * q + 2] - c[2];
+        double* r = rec + t * kRec + 5 * q;
+        r[0] = v0 * iw2;
+        r[1] = v1 * iw2;
+        r[2] = v2 * iw2;
+        r[3] = iw2;
+        r[4] = fma(v0, v0, fma(v1, v1, v2 * v2)) * iw2;
+    }
+}
+
+// One wave per 64x64 tile (rb <= cb); 4 waves per block.  Lane t keeps its row triangle's 7 Gauss
+// points in registers; the wave walks the tile's column triangles in chunks of 16 (one group),
+// whose data arrive through scalar loads, each chunk in the centred form above or by differences.
+// Results go out per chunk: row tp of I directly (64 consecutive entries), and row t of I through
+// an LDS transpose so that each store instruction writes eight complete 128-byte row segments
+// instead of 64 scattered 8-byte pieces.
+constexpr int kChunk = kGrp;
+
+__global__ __launch_bounds__(256) void k_far(const double* __restrict__ geo, const double* __restrict__ gb,
+                                             const double* __restrict__ rec, int32_t nt, int64_t ld,
+                                             const int2* __restrict__ tiles, int64_t ntiles, double* __restrict__ I) {
     __shared__ double stage[4][kTile][kChunk + 1];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -103,50 +183,114 @@ __global__ __launch_bounds__(256) void k_far(const double* __restrict__ geo, int
     const int t = rb * kTile + lane;
     const bool valid = t < nt;
     const double* g = geo + int64_t(valid ? t : 0) * kGeo;
-    double px[7], py[7], pz[7], pw[7];
-#pragma unroll
-    for (int p = 0; p < 7; ++p) {
-        px[p] = g[3 * p];
-        py[p] = g[3 * p + 1];
-        pz[p] = g[3 * p + 2];
-        pw[p] = 0.5 * g[21 + p];   // the 1/2 of the Newton step below, folded into the weight (exact)
+    // bounding sphere of the row tile's Gauss points, from those of its (up to 4) groups
+    double cR[3], rhoR = 0.0;
+    {
+        const int g0 = rb * (kTile / kGrp), g1 = min((nt + kGrp - 1) / kGrp, g0 + kTile / kGrp);
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int gg = g0; gg < g1; ++gg)
+            for (int k = 0; k < 3; ++k) {
+                lo[k] = fmin(lo[k], gb[4 * gg + k] - gb[4 * gg + 3]);
+                hi[k] = fmax(hi[k], gb[4 * gg + k] + gb[4 * gg + 3]);
+            }
+        for (int k = 0; k < 3; ++k) cR[k] = 0.5 * (lo[k] + hi[k]);
+        for (int gg = g0; gg < g1; ++gg) {
+            const double d0 = gb[4 * gg] - cR[0], d1 = gb[4 * gg + 1] - cR[1], d2 = gb[4 * gg + 2] - cR[2];
+            rhoR = fmax(rhoR, sqrt(fma(d0, d0, fma(d1, d1, d2 * d2))) + gb[4 * gg + 3]);
+        }
+        rhoR *= 1.0 + 1e-12;
     }
     const int c0 = cb * kTile;
     const int c1 = min(c0 + kTile, nt);
     // row stride ld is a multiple of 8 doubles, so the paired stores below are 16-byte aligned
     // full off-diagonal tiles use the staged stores; diagonal and ragged tiles store directly
     const bool staged = (rb != cb) && (c1 - c0 == kTile) && (rb * kTile + kTile <= nt);
+    // I(t, tp) for the lane's row t: row tp of I directly; row t later, from the staging tile
+    auto put = [&](int j, int tp, double v) {
+        if (staged) {
+            I[int64_t(tp) * ld + t] = v;   // row tp: 64 consecutive entries
+            stage[wave][lane][j] = v;
+        } else if (valid && tp < c1 && (rb != cb || t < tp)) {
+            I[int64_t(tp) * ld + t] = v;
+            I[int64_t(t) * ld + tp] = v;
+        }
+    };
     for (int j0 = c0; j0 < c1; j0 += kChunk) {
-        double val[kChunk];
+        // the row triangle's points are read again per chunk (cache hits), so that only one of
+        // the two forms' register sets is live at a time
+        double pw[7];
 #pragma unroll
-        for (int j = 0; j < kChunk; ++j) {
-            const int tp = j0 + j;
-            double acc = 0.0;
-            if (tp < c1) {
-                const double* h = geo + int64_t(tp) * kGeo;
+        for (int p = 0; p < 7; ++p) pw[p] = 0.5 * g[21 + p];   // the 1/2 of the Newton step (exact)
+        const double* gC = gb + 4 * (j0 / kGrp);
+        const double e0 = gC[0] - cR[0], e1 = gC[1] - cR[1], e2 = gC[2] - cR[2];
+        const double sep = kSep * (rhoR + gC[3]);
+        if (fma(e0, e0, fma(e1, e1, e2 * e2)) >= sep * sep) {
+            // centred form about the group centre c: u = -2 (x - c), alpha = |x - c|^2
+            double ux[7], uy[7], uz[7], al[7];
 #pragma unroll
-                for (int q = 0; q < 7; ++q) {
-                    const double yx = h[3 * q], yy = h[3 * q + 1], yz = h[3 * q + 2];
-                    double sacc = 0.0;
+            for (int p = 0; p < 7; ++p) {
+                const double a0 = g[3 * p] - gC[0], a1 = g[3 * p + 1] - gC[1], a2 = g[3 * p + 2] - gC[2];
+                ux[p] = -2.0 * a0;
+                uy[p] = -2.0 * a1;
+                uz[p] = -2.0 * a2;
+                al[p] = fma(a0, a0, fma(a1, a1, a2 * a2));
+            }
+#pragma unroll 1
+            for (int j = 0; j < kChunk; ++j) {
+                const int tp = j0 + j;
+                double acc = 0.0;
+                if (tp < c1) {
+                    const double* h = rec + int64_t(tp) * kRec;
 #pragma unroll
                     for (int p = 0; p < 7; ++p) {
-                        const double dx = px[p] - yx, dy = py[p] - yy, dz = pz[p] - yz;
-                        const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-                        // 1/r = y (3 - r2 y^2) / 2 after one Newton step from the hardware estimate y
-                        const double y = __builtin_amdgcn_rsq(r2);
-                        sacc = fma(pw[p] * y, fma(-r2, y * y, 3.0), sacc);
+                        double sacc = 0.0;
+#pragma unroll
+                        for (int q = 0; q < 7; ++q) {
+                            // s = |x - y|^2 / w^2 and 1/sqrt(s) = w / |x - y|, one Newton step from
+                            // the hardware estimate y: y (3 - s y^2) / 2
+                            const double* r = h + 5 * q;
+                            const double s2 = fma(ux[p], r[0], fma(uy[p], r[1], fma(uz[p], r[2], fma(al[p], r[3], r[4]))));
+                            const double y = __builtin_amdgcn_rsq(s2);
+                            sacc = fma(y, fma(-s2, y * y, 3.0), sacc);
+                        }
+                        acc = fma(pw[p], sacc, acc);
                     }
-                    acc = fma(h[21 + q], sacc, acc);
                 }
+                put(j, tp, acc * kInv4Pi);
             }
-            val[j] = acc * kInv4Pi;
+        } else {
+            double px[7], py[7], pz[7];
+#pragma unroll
+            for (int p = 0; p < 7; ++p) {
+                px[p] = g[3 * p];
+                py[p] = g[3 * p + 1];
+                pz[p] = g[3 * p + 2];
+            }
+#pragma unroll 1
+            for (int j = 0; j < kChunk; ++j) {
+                const int tp = j0 + j;
+                double acc = 0.0;
+                if (tp < c1) {
+                    const double* h = geo + int64_t(tp) * kGeo;
+#pragma unroll
+                    for (int q = 0; q < 7; ++q) {
+                        const double yx = h[3 * q], yy = h[3 * q + 1], yz = h[3 * q + 2];
+                        double sacc = 0.0;
+#pragma unroll
+                        for (int p = 0; p < 7; ++p) {
+                            const double dx = px[p] - yx, dy = py[p] - yy, dz = pz[p] - yz;
+                            const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                            // 1/r = y (3 - r2 y^2) / 2 after one Newton step from the hardware estimate y
+                            const double y = __builtin_amdgcn_rsq(r2);
+                            sacc = fma(pw[p] * y, fma(-r2, y * y, 3.0), sacc);
+                        }
+                        acc = fma(h[21 + q], sacc, acc);
+                    }
+                }
+                put(j, tp, acc * kInv4Pi);
+            }
         }
         if (staged) {
-#pragma unroll
-            for (int j = 0; j < kChunk; ++j) {
-                I[int64_t(j0 + j) * ld + t] = val[j];       // row tp: 64 consecutive entries
-                stage[wave][lane][j] = val[j];
-            }
             __builtin_amdgcn_wave_barrier();   // stage[wave] is private to this wave; order write -> read
             // row t: lanes 8r .. 8r+7 write row (8 pass + r) of the tile, 16 bytes each
 #pragma unroll
@@ -157,26 +301,32 @@ __global__ __launch_bounds__(256) void k_far(const double* __restrict__ geo, int
                 *reinterpret_cast<double2*>(I + int64_t(rb * kTile + row) * ld + j0 + col) = v;
             }
             __builtin_amdgcn_wave_barrier();   // reads done before the next chunk overwrites stage
-        } else {
-#pragma unroll
-            for (int j = 0; j < kChunk; ++j) {
-                const int tp = j0 + j;
-                if (valid && tp < c1 && (rb != cb || t < tp)) {
-                    I[int64_t(tp) * ld + t] = val[j];
-                    I[int64_t(t) * ld + tp] = val[j];
-                }
-            }
         }
     }
 }
 
 // Panel form of the far-field pass: I_P[r][c - col0] for the rows r of a list of triangles (the
-// panel's rows) and the columns c in [col0, nt).  One wave per tile of 64 listed rows x 64 columns;
-// lane l takes column c = col0 + 64 cb + l with its Gauss points in registers and walks the tile's
-// rows, whose points come through scalar loads, so every store covers 64 consecutive columns.
-__global__ __launch_bounds__(256) void k_far_rect(const double* __restrict__ geo, int32_t nt, const int32_t* __restrict__ rows,
-                                                  int64_t nrows, int64_t col0, int64_t ld, const int2* __restrict__ tiles,
-                                                  int64_t ntiles, double* __restrict__ I) {
+// panel's rows) and the columns c in [col0, nt), col0 a multiple of 16.  One wave per tile of 64
+// listed rows x 64 columns: as in k_far, lane l keeps listed row 64 rb + l in registers and walks
+// the tile's columns in groups of 16, each in the centred form or by differences (the separation
+// test uses the bounding sphere of the tile's rows, reduced across the wave), and each group's
+// 64 x 16 block goes out through an LDS transpose as 128-byte row segments.
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_far_rect(const double* __restrict__ geo, const double* __restrict__ gb,
+                                                  const double* __restrict__ rec, int32_t nt,
+                                                  const int32_t* __restrict__ rows, int64_t nrows, int64_t col0, int64_t ld,
+                                                  const int2* __restrict__ tiles, int64_t ntiles, double* __restrict__ I) {
+    __shared__ double stage[4][kTile][kChunk + 1];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int64_t tile = int64_t(blockIdx.x) * 4 + wave;
@@ -184,35 +334,116 @@ __global__ __launch_bounds__(256) void k_far_rect(const double* __restrict__ geo
     const int2 tc = tiles[tile];
     const int rb = __builtin_amdgcn_readfirstlane(tc.x);
     const int cb = __builtin_amdgcn_readfirstlane(tc.y);
-    const int64_t c = col0 + int64_t(cb) * kTile + lane;
-    const bool valid = c < nt;
-    const double* g = geo + (valid ? c : col0) * kGeo;
-    double px[7], py[7], pz[7], pw[7];
-#pragma unroll
-    for (int q = 0; q < 7; ++q) {
-        px[q] = g[3 * q];
-        py[q] = g[3 * q + 1];
-        pz[q] = g[3 * q + 2];
-        pw[q] = 0.5 * g[21 + q];   // the 1/2 of the Newton step, folded into the weight
-    }
-    const int64_t r1 = min<int64_t>(nrows, int64_t(rb + 1) * kTile);
-    for (int64_t r = int64_t(rb) * kTile; r < r1; ++r) {
-        const double* h = geo + int64_t(rows[r]) * kGeo;
-        double acc = 0.0;
-#pragma unroll
-        for (int p = 0; p < 7; ++p) {
-            const double xx = h[3 * p], xy = h[3 * p + 1], xz = h[3 * p + 2];
-            double sacc = 0.0;
-#pragma unroll
-            for (int q = 0; q < 7; ++q) {
-                const double dx = xx - px[q], dy = xy - py[q], dz = xz - pz[q];
-                const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-                const double y = __builtin_amdgcn_rsq(r2);
-                sacc = fma(pw[q] * y, fma(-r2, y * y, 3.0), sacc);
+    const int64_t r = int64_t(rb) * kTile + lane;   // listed row of this lane
+    const bool valid = r < nrows;
+    const double* g = geo + int64_t(rows[valid ? r : 0]) * kGeo;
+    // bounding sphere of the tile's rows
+    double cR[3], rhoR = 0.0;
+    {
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        if (valid)
+            for (int p = 0; p < 7; ++p)
+                for (int k = 0; k < 3; ++k) {
+                    lo[k] = fmin(lo[k], g[3 * p + k]);
+                    hi[k] = fmax(hi[k], g[3 * p + k]);
+                }
+        for (int k = 0; k < 3; ++k) cR[k] = 0.5 * (wave_min(lo[k]) + wave_max(hi[k]));
+        double d2 = 0.0;
+        if (valid)
+            for (int p = 0; p < 7; ++p) {
+                const double a0 = g[3 * p] - cR[0], a1 = g[3 * p + 1] - cR[1], a2 = g[3 * p + 2] - cR[2];
+                d2 = fmax(d2, fma(a0, a0, fma(a1, a1, a2 * a2)));
             }
-            acc = fma(h[21 + p], sacc, acc);
+        rhoR = sqrt(wave_max(d2)) * (1.0 + 1e-12);
+    }
+    const int64_t c0 = col0 + int64_t(cb) * kTile;
+    const int64_t c1 = min<int64_t>(c0 + kTile, nt);
+    const bool staged = (c1 - c0 == kTile) && (int64_t(rb) * kTile + kTile <= nrows);
+    auto put = [&](int j, int64_t tp, double v) {
+        if (staged) stage[wave][lane][j] = v;
+        else if (valid && tp < c1) I[r * ld + (tp - col0)] = v;
+    };
+    for (int64_t j0 = c0; j0 < c1; j0 += kChunk) {
+        double pw[7];
+#pragma unroll
+        for (int p = 0; p < 7; ++p) pw[p] = 0.5 * g[21 + p];   // the 1/2 of the Newton step (exact)
+        const double* gC = gb + 4 * (j0 / kGrp);
+        const double e0 = gC[0] - cR[0], e1 = gC[1] - cR[1], e2 = gC[2] - cR[2];
+        const double sep = kSep * (rhoR + gC[3]);
+        if (fma(e0, e0, fma(e1, e1, e2 * e2)) >= sep * sep) {
+            double ux[7], uy[7], uz[7], al[7];
+#pragma unroll
+            for (int p = 0; p < 7; ++p) {
+                const double a0 = g[3 * p] - gC[0], a1 = g[3 * p + 1] - gC[1], a2 = g[3 * p + 2] - gC[2];
+                ux[p] = -2.0 * a0;
+                uy[p] = -2.0 * a1;
+                uz[p] = -2.0 * a2;
+                al[p] = fma(a0, a0, fma(a1, a1, a2 * a2));
+            }
+#pragma unroll 1
+            for (int j = 0; j < kChunk; ++j) {
+                const int64_t tp = j0 + j;
+                double acc = 0.0;
+                if (tp < c1) {
+                    const double* h = rec + tp * kRec;
+#pragma unroll
+                    for (int p = 0; p < 7; ++p) {
+                        double sacc = 0.0;
+#pragma unroll
+                        for (int q = 0; q < 7; ++q) {
+                            const double* rq = h + 5 * q;
+                            const double s2 = fma(ux[p], rq[0], fma(uy[p], rq[1], fma(uz[p], rq[2], fma(al[p], rq[3], rq[4]))));
+                            const double y = __builtin_amdgcn_rsq(s2);
+                            sacc = fma(y, fma(-s2, y * y, 3.0), sacc);
+                        }
+                        acc = fma(pw[p], sacc, acc);
+                    }
+                }
+                put(j, tp, acc * kInv4Pi);
+            }
+        } else {
+            double px[7], py[7], pz[7];
+#pragma unroll
+            for (int p = 0; p < 7; ++p) {
+                px[p] = g[3 * p];
+                py[p] = g[3 * p + 1];
+                pz[p] = g[3 * p + 2];
+            }
+#pragma unroll 1
+            for (int j = 0; j < kChunk; ++j) {
+                const int64_t tp = j0 + j;
+                double acc = 0.0;
+                if (tp < c1) {
+                    const double* h = geo + tp * kGeo;
+#pragma unroll
+                    for (int q = 0; q < 7; ++q) {
+                        const double yx = h[3 * q], yy = h[3 * q + 1], yz = h[3 * q + 2];
+                        double sacc = 0.0;
+#pragma unroll
+                        for (int p = 0; p < 7; ++p) {
+                            const double dx = px[p] - yx, dy = py[p] - yy, dz = pz[p] - yz;
+                            const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                            const double y = __builtin_amdgcn_rsq(r2);
+                            sacc = fma(pw[p] * y, fma(-r2, y * y, 3.0), sacc);
+                        }
+                        acc = fma(h[21 + q], sacc, acc);
+                    }
+                }
+                put(j, tp, acc * kInv4Pi);
+            }
         }
-        if (valid) I[r * ld + (c - col0)] = acc * kInv4Pi;
+        if (staged) {
+            __builtin_amdgcn_wave_barrier();   // stage[wave] is private to this wave; order write -> read
+            // lanes 8i .. 8i+7 write listed row (8 pass + i) of the tile, 16 bytes each
+#pragma unroll
+            for (int pass = 0; pass < 8; ++pass) {
+                const int row = pass * 8 + (lane >> 3);
+                const int col = (lane & 7) * 2;
+                const double2 v = make_double2(stage[wave][row][col], stage[wave][row][col + 1]);
+                *reinterpret_cast<double2*>(I + (int64_t(rb) * kTile + row) * ld + (j0 - col0) + col) = v;
+            }
+            __builtin_amdgcn_wave_barrier();   // reads done before the next chunk overwrites stage
+        }
     }
 }
 
@@ -719,14 +950,14 @@ ContractPlan contract_plan(const MeshTopo& m) {
 // grouped into panels whose rows' star triangles number at most maxrows.  A panel computes
 // I_P = I(R, [tmin, N_T)) for its row triangles R and every column triangle that a tile
 // (bd, be >= bd) of its rows can read (tmin = smallest triangle of the column blocks from its first
-// row block on), the near pairs that fall in it, and then contracts its tiles of the upper half of W
+// row block on, rounded down to a multiple of 16), the near pairs that fall in it, and then contracts its tiles of the upper half of W
 // (the mirrored writes fill the lower half).  Far work is about half of N_T^2 pairs in total, as in
 // the one-shot path.  Host-side filtering of the next panel overlaps the device work of this one.
 struct PanelTimes { double far = 0, near = 0, contract = 0; int panels = 0; };
 
 template <class Mark>
 PanelTimes assemble_panels(bem_problem* p, const MeshTopo& m, const NearList& near, const ContractPlan& plan,
-                           const double* geo, const double* dV, const double* dgx, const double* dgw, const double* dofJ,
+                           const double* geo, const double* gbounds, const double* crec, const double* dV, const double* dgx, const double* dgw, const double* dofJ,
                            float* w32, Mark&& mark) {
     hipStream_t s = p->stream;
     const int64_t nt = m.nt, N = m.N;
@@ -795,9 +1026,12 @@ PanelTimes assemble_panels(bem_problem* p, const MeshTopo& m, const NearList& ne
         }
         starts.push_back(ncb);
     }
+    // a panel's columns start at a multiple of 16, so that its column groups are those of the
+    // far-field records
+    auto first_col = [&](int64_t bd) { return sufmin[bd] / kGrp * kGrp; };
     int64_t max_elems = 1;
     for (size_t q = 0; q < rowsets.size(); ++q) {
-        const int64_t ldq = (nt - sufmin[starts[q]] + 7) / 8 * 8;
+        const int64_t ldq = (nt - first_col(starts[q]) + 7) / 8 * 8;
         max_elems = std::max<int64_t>(max_elems, int64_t(rowsets[q].size()) * ldq);
     }
     DeviceBuffer Ip(sizeof(double) * max_elems, s);
@@ -806,7 +1040,7 @@ PanelTimes assemble_panels(bem_problem* p, const MeshTopo& m, const NearList& ne
         const int64_t bd0 = starts[pid], bd1 = starts[pid + 1];
         P->rows = std::move(rowsets[pid]);
         const int64_t nrows = int64_t(P->rows.size());
-        const int64_t tmin = sufmin[bd0];
+        const int64_t tmin = first_col(bd0);
         const int64_t ncol = nt - tmin;
         const int64_t ldP = (ncol + 7) / 8 * 8;
         P->rowmap.assign(size_t(nt), -1);
@@ -831,8 +1065,8 @@ PanelTimes assemble_panels(bem_problem* p, const MeshTopo& m, const NearList& ne
         DeviceBuffer d_rows = upload(P->rows, s), d_rowmap = upload(P->rowmap, s), d_ft = upload(P->ftiles, s);
         P->ef = std::make_unique<EventTimer>(s);
         const int64_t nft = int64_t(P->ftiles.size());
-        hipLaunchKernelGGL(k_far_rect, dim3(blocks_for(nft, 4)), dim3(256), 0, s, geo, int32_t(nt), d_rows.as<int32_t>(), nrows,
-                           tmin, ldP, d_ft.as<int2>(), nft, Ip.as<double>());
+        hipLaunchKernelGGL(k_far_rect, dim3(blocks_for(nft, 4)), dim3(256), 0, s, geo, gbounds, crec, int32_t(nt),
+                           d_rows.as<int32_t>(), nrows, tmin, ldP, d_ft.as<int2>(), nft, Ip.as<double>());
         HIP_CHECK(hipGetLastError());
         P->ef->stop();
         DeviceBuffer dv[4], da[4], dbb[4], dt[4];
@@ -951,6 +1185,16 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
     const bool paneled = p->panel_rows > 0 || full_bytes > 0.85 * double(free_b);
     if (paneled && p->has_pairs) fail(BEM_E_INVALID_ARG, "keep_pair_matrix needs the whole pair matrix on the device");
     EventTimer t_far(s);
+    // group bounds and column records of the far-field pass (both modes)
+    const int64_t ng = (int64_t(nt) + kGrp - 1) / kGrp;
+    DeviceBuffer gbounds(sizeof(double) * 4 * std::max<int64_t>(ng, 1), s), crec(sizeof(double) * kRec * std::max<int64_t>(nt, 1), s);
+    if (nt > 0) {
+        hipLaunchKernelGGL(k_group_bounds, dim3(blocks_for(ng, 256)), dim3(256), 0, s, geo.as<double>(), int32_t(nt),
+                           gbounds.as<double>());
+        hipLaunchKernelGGL(k_col_records, dim3(blocks_for(nt, 256)), dim3(256), 0, s, geo.as<double>(), gbounds.as<double>(),
+                           int32_t(nt), crec.as<double>());
+        HIP_CHECK(hipGetLastError());
+    }
     if (!paneled) {
         p->ldI = ldI;
         p->I = DeviceBuffer(sizeof(double) * nt * ldI, s);
@@ -962,8 +1206,8 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
         DeviceBuffer dtiles = upload(tiles, s);
         HIP_CHECK(hipEventRecord(t_far.a, s));
         const int64_t nti = int64_t(tiles.size());
-        hipLaunchKernelGGL(k_far, dim3(blocks_for(nti, 4)), dim3(256), 0, s, geo.as<double>(), int32_t(nt), ldI,
-                           dtiles.as<int2>(), nti, p->I.as<double>());
+        hipLaunchKernelGGL(k_far, dim3(blocks_for(nti, 4)), dim3(256), 0, s, geo.as<double>(), gbounds.as<double>(),
+                           crec.as<double>(), int32_t(nt), ldI, dtiles.as<int2>(), nti, p->I.as<double>());
         HIP_CHECK(hipGetLastError());
     }
     t_far.stop();
@@ -1075,8 +1319,8 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
         t_contract.stop();
         mark("contract");
     } else {
-        ptimes = assemble_panels(p, m, near, plan, geo.as<double>(), dV.as<double>(), dgx.as<double>(), dgw.as<double>(),
-                                 dofJ.as<double>(), w32, mark);
+        ptimes = assemble_panels(p, m, near, plan, geo.as<double>(), gbounds.as<double>(), crec.as<double>(), dV.as<double>(),
+                                 dgx.as<double>(), dgw.as<double>(), dofJ.as<double>(), w32, mark);
     }
     p->mv_xt = DeviceBuffer(sizeof(double) * 16 * p->ldw, s);
     p->mv_partial = DeviceBuffer(sizeof(double) * 16 * 16 * p->ldw, s);

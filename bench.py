@@ -208,6 +208,38 @@ def serving_leg(lib, meshes, ctx, n_requests, load, seed=0, max_inflight=4):
     }
 
 
+def kappa_study(lib, meshes, ctx):
+    """Lanczos estimate of kappa(P_ad W) on the paper's three-dimensional experiment (two
+    perpendicular equilateral triangles sharing a median) with faces = coarse triangles, over coarse
+    sizes H = (1/2, 1/4, 1/8) x edge and H/h = 2..16, next to kappa(W) (unpreconditioned CG) and
+    the iteration counts; a seeded generic right-hand side, PCG to 1e-12."""
+    rows = []
+    for nc in (2, 4, 8):
+        for ratio in (2, 4, 8, 16):
+            n = nc * ratio
+            if n > 128:
+                continue
+            m = meshes.bowtie(n)
+            cm, par = meshes.bowtie_coarse(n, ratio)
+            p = lib.Problem(ctx, m.vertices, m.triangles, near_order=10)
+            M = lib.Preconditioner(p, par, cm.vertices, cm.triangles, par)
+            b = np.random.default_rng(n * 100 + ratio).standard_normal((1, p.N))
+            _, info, _ = p.solve(rhs=b, precond=M, tol=1e-12)
+            _, info_cg, _ = p.solve(rhs=b, precond=None, tol=1e-12)
+            _, info_g, _ = p.solve(g=meshes.BOWTIE_G, precond=M, tol=1e-10)
+            sz = M.sizes()
+            rows.append({"coarse_n": nc, "H_over_h": ratio, "n": n, "n_dofs": p.N, "n_faces": sz["n_faces"],
+                         "n_wb": sz["n_wb"], "n_coarse": sz["n_coarse"],
+                         "kappa_pad": info[0]["est_cond"], "kappa_W": info_cg[0]["est_cond"],
+                         "pcg_iters": info[0]["iters"], "cg_iters": info_cg[0]["iters"],
+                         "pcg_iters_g_1e-10": info_g[0]["iters"]})
+            M.close()
+            p.close()
+            log("bench: kappa study n=%d H/h=%d N=%d kappa(P W)=%.3f kappa(W)=%.1f" %
+                (n, ratio, rows[-1]["n_dofs"], rows[-1]["kappa_pad"], rows[-1]["kappa_W"]))
+    return rows
+
+
 def large_leg(lib, meshes, ctx, k=16):
     """crossed192 (N = 110,017; W 48 GB FP32 + 97 GB FP64, the pair matrix built in panels): a
     warm-up step, then one timed step (assembly, set-up, mixed-precision solve of k right-hand
@@ -281,6 +313,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=24,
                     help="requests in the serving-stream leg (0 skips it)")
     ap.add_argument("--no-large", action="store_true", help="skip the crossed192 leg")
+    ap.add_argument("--no-kappa", action="store_true", help="skip the condition-number study")
     ap.add_argument("--serve-load", type=float, default=0.7,
                     help="arrival rate of the serving leg as a fraction of its measured capacity")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -438,6 +471,9 @@ def main():
         "matvec": mv,
         "fp64_compare": fp64_step,
     }
+    if not args.no_kappa:
+        log("bench: condition-number study")
+        out["kappa_study"] = kappa_study(lib, meshes, ctx)
     if not args.no_large and args.workload != "crossed192":
         log("bench: crossed192 leg")
         out["crossed192"] = large_leg(lib, meshes, ctx)

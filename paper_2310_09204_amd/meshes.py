@@ -169,6 +169,8 @@ def bowtie(n: int) -> Mesh:
     vlist: List[Tuple[float, float, float]] = []
     tris: List[Tuple[int, int, int]] = []
     pan: List[int] = []
+    cell: List[Tuple[int, int]] = []
+    low: List[bool] = []
 
     def vid(pt):
         key = tuple(int(round(c * 1e9)) for c in pt)
@@ -188,14 +190,40 @@ def bowtie(n: int) -> Mesh:
         for i in range(n):
             for j in range(n - i):
                 a, b, c = vid(pt(i, j)), vid(pt(i + 1, j)), vid(pt(i, j + 1))
-                tris.append((a, b, c)); pan.append(pid)
+                tris.append((a, b, c)); pan.append(pid); cell.append((i, j)); low.append(True)
                 if i + j + 1 < n:
                     d2 = vid(pt(i + 1, j + 1))
-                    tris.append((b, d2, c)); pan.append(pid)
-    nt = len(tris)
+                    tris.append((b, d2, c)); pan.append(pid); cell.append((i, j)); low.append(False)
     return Mesh(np.asarray(vlist, dtype=np.float64), np.asarray(tris, dtype=np.int32),
-                np.asarray(pan, dtype=np.int32), np.zeros((nt, 2), np.int32),
-                np.zeros(nt, bool), [])
+                np.asarray(pan, dtype=np.int32), np.asarray(cell, dtype=np.int32).reshape(-1, 2),
+                np.asarray(low, dtype=bool), [])
+
+
+def bowtie_coarse(n: int, ratio: int) -> Tuple[Mesh, np.ndarray]:
+    """Nested coarse mesh of bowtie(n): bowtie(n // ratio), and the coarse triangle of each fine one.
+
+    Cells are split on their (i+1, j)-(i, j+1) diagonal at both levels, so a fine triangle of cell
+    (i, j) lies in coarse cell (i // ratio, j // ratio), below the coarse diagonal when its offsets
+    (a, b) in that cell have a + b < ratio - 1, or a + b = ratio - 1 and it is the lower fine one.
+    """
+    if n % ratio:
+        raise ValueError("ratio must divide n")
+    fine, cm = bowtie(n), bowtie(n // ratio)
+    lookup = {}
+    for t in range(cm.nt):
+        lookup[(int(cm.tri_panel[t]), int(cm.tri_cell[t, 0]), int(cm.tri_cell[t, 1]), bool(cm.tri_lower[t]))] = t
+    parent = np.empty(fine.nt, dtype=np.int32)
+    for t in range(fine.nt):
+        i, j = int(fine.tri_cell[t, 0]), int(fine.tri_cell[t, 1])
+        I, J = i // ratio, j // ratio
+        s = (i - I * ratio) + (j - J * ratio)
+        lower = s < ratio - 1 or (s == ratio - 1 and bool(fine.tri_lower[t]))
+        parent[t] = lookup[(int(fine.tri_panel[t]), I, J, lower)]
+    return cm, parent
+
+
+# Neumann data of the paper's three-dimensional experiment (two perpendicular triangles)
+BOWTIE_G = np.array([1.0, 0.5, 0.25])
 
 
 def fan(m: int, rings: int = 2) -> Mesh:

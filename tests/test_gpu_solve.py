@@ -7,7 +7,7 @@ import pytest
 from paper_2310_09204_amd import lib, meshes
 from oracle.assemble import assemble, rhs
 from oracle.precond import AdditiveSchwarz
-from oracle.solve import cholesky_solve, pcg
+from oracle.solve import cholesky_solve, lanczos_cond, pcg
 from oracle.topology import Topology
 
 pytestmark = pytest.mark.gpu
@@ -153,3 +153,25 @@ def test_book48_full_size(ctx):
     xs = cholesky_solve(W, L)
     phi, info, rc = p.solve(g=w.g, precond=M, tol=1e-13)
     assert np.linalg.norm(phi[0] - xs) / np.linalg.norm(xs) < 1e-10
+
+
+@pytest.mark.parametrize("n,ratio", [(16, 4), (16, 8)])
+def test_bowtie_paper_splitting_matches_oracle(ctx, n, ratio):
+    # the paper's three-dimensional experiment with faces = coarse triangles: block sizes, iteration
+    # counts and the Lanczos estimate of kappa(P_ad W) as the oracle's
+    m = meshes.bowtie(n)
+    cm, par = meshes.bowtie_coarse(n, ratio)
+    print("case bowtie", n, ratio, flush=True)
+    p = lib.Problem(ctx, m.vertices, m.triangles, near_order=NEAR)
+    M = lib.Preconditioner(p, par, cm.vertices, cm.triangles, par)
+    t = Topology(m.vertices, m.triangles)
+    W = assemble(m.vertices, m.triangles, t, NEAR)
+    P = AdditiveSchwarz(W, t, par, cm.vertices, cm.triangles, par)
+    s = M.sizes()
+    assert s["n_faces"] == len(P.face_sets) and s["n_wb"] == len(P.wb) and s["n_coarse"] == P.RH.shape[0]
+    b = np.random.default_rng(ratio).standard_normal(t.N)
+    _, it_o, _, al, be = pcg(W, b, P.apply, tol=1e-12)
+    phi, info, rc = p.solve(rhs=b[None, :], precond=M, tol=1e-12)
+    assert rc == 0 and abs(info[0]["iters"] - it_o) <= 1
+    k_o = lanczos_cond(al, be)
+    assert abs(info[0]["est_cond"] - k_o) < 1e-3 * k_o, (info[0]["est_cond"], k_o)

@@ -197,3 +197,34 @@ def test_condition_number_growth():
     assert kP[0] < kP[1] < kP[2]
     assert max(ratio) / min(ratio) < 3.0
     assert kP[-1] < kW[-1]
+
+
+def test_bowtie_paper_splitting_condition_growth():
+    # The paper's three-dimensional experiment: two perpendicular equilateral triangles sharing a
+    # median, with the splitting of the analysis: one face per coarse triangle (its interior
+    # vertices), the coarse edges, vertices and the junction in the wire basket, and the coarse
+    # jump space.  kappa(P_ad W) stays within C (1 + log(H/h))^2 (Thm. main) and grows with H/h.
+    nc = 2
+    ks, logs = [], []
+    for ratio in (2, 4, 8):
+        n = nc * ratio
+        m = meshes.bowtie(n)
+        cm, par = meshes.bowtie_coarse(n, ratio)
+        t, W, L = _problem(m, meshes.BOWTIE_G)
+        P = AdditiveSchwarz(W, t, par, cm.vertices, cm.triangles, par)
+        # faces: the coarse triangles with fine vertices inside (none at ratio 2)
+        inner = (ratio - 1) * (ratio - 2) // 2
+        assert len(P.face_sets) == (cm.nt if inner > 0 else 0)
+        assert all(len(f) == inner for f in P.face_sets)
+        Md = P.dense(t.N)
+        k = spectral_cond(W, 0.5 * (Md + Md.T))
+        # the Lanczos estimate from a PCG run with a generic right-hand side (the symmetric data
+        # of the experiment leave part of the spectrum unexcited)
+        b = np.random.default_rng(ratio).standard_normal(t.N)
+        _, it, _, al, be = pcg(W, b, P.apply, tol=1e-12)
+        assert abs(lanczos_cond(al, be) - k) < 1e-2 * k
+        ks.append(k)
+        logs.append((1 + math.log(ratio)) ** 2)
+    assert ks[0] < ks[1] < ks[2]
+    r = [k / l for k, l in zip(ks, logs)]
+    assert max(r) / min(r) < 2.5

@@ -272,6 +272,15 @@ def large_leg(lib, meshes, ctx, k=16):
     ref, _, _ = p.solve(g=w.g, precond=M, tol=1e-13, precision=lib.FP64)
     err = np.linalg.norm(phi - ref, axis=1) / np.linalg.norm(ref, axis=1)
     err64 = np.linalg.norm(phi64 - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    # the diagonal wire basket (Remark "Approximate solvers") on the same matrix
+    t6 = time.perf_counter()
+    Md = lib.Preconditioner(p, w.patch_of_triangle, w.coarse.vertices, w.coarse.triangles, w.coarse_of_triangle,
+                            factor_fp32=True, wirebasket="diagonal")
+    t7 = time.perf_counter()
+    phid, infod, _ = p.solve(g=w.g, precond=Md, tol=1e-10, precision=lib.FP32_REFINE)
+    t8 = time.perf_counter()
+    errd = np.linalg.norm(phid - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    Md.close()
     N = pinfo["n_dofs"]
     t32 = p.bench_matvec(fp32=True, k=16, reps=3)
     t64 = p.bench_matvec(fp32=False, k=16, reps=3)
@@ -286,6 +295,9 @@ def large_leg(lib, meshes, ctx, k=16):
         "solves_per_s": int((err <= 1e-8).sum()) / step,
         "iters": [i["iters"] for i in info], "relerr_max": float(err.max()),
         "fp64_solve": {"t_solve_s": t5 - t4, "iters": [i["iters"] for i in info64], "relerr_max": float(err64.max())},
+        "diagonal_wirebasket": {"t_precond_s": t7 - t6, "t_solve_s": t8 - t7, "iters": [i["iters"] for i in infod],
+                                "relerr_max": float(errd.max()),
+                                "solves_per_s": int((errd <= 1e-8).sum()) / ((t1 - t0) + (t7 - t6) + (t8 - t7))},
         "pair_integrals_per_s": nt * (nt + 1) / 2 / (t1 - t0),
         "matvec": {"fp32_k16_GBs": N * N * 4 / t32 / 1e9, "fp64_k16_GBs": N * N * 8 / t64 / 1e9},
         "patches": M.sizes(),
@@ -344,12 +356,12 @@ def main():
     log("bench: workload %s nt=%d k=%d precision=%s" % (args.workload, m.nt, args.k, args.precision))
     ctx = lib.Context(0)
 
-    def step(precision, want_phi=False, tol=args.tol):
+    def step(precision, want_phi=False, tol=args.tol, wirebasket="exact"):
         t0 = time.perf_counter()
         p = lib.Problem(ctx, m.vertices, m.triangles, precision=precision, near_order=10)
         t1 = time.perf_counter()
         M = lib.Preconditioner(p, w.patch_of_triangle, w.coarse.vertices, w.coarse.triangles, w.coarse_of_triangle,
-                               factor_fp32=(precision == lib.FP32_REFINE))
+                               factor_fp32=(precision == lib.FP32_REFINE), wirebasket=wirebasket)
         t2 = time.perf_counter()
         phi, info, rc = p.solve(g=w.g, precond=M, tol=tol, precision=precision)
         ctx.synchronize()
@@ -418,6 +430,17 @@ def main():
                      "solves_per_s": int((err64 <= 1e-8).sum()) / r64["t_step"],
                      "solve_only_solves_per_s": int((err64 <= 1e-8).sum()) / r64["t_solve"]}
 
+    # the same step with the diagonal wire basket (Remark "Approximate solvers")
+    rd = step(prec, want_phi=True, wirebasket="diagonal")
+    errd = np.linalg.norm(rd["phi"] - phi_ref, axis=1) / np.linalg.norm(phi_ref, axis=1)
+    rd["M"].close()
+    rd["problem"].close()
+    diag_step = {"t_step_s": rd["t_step"], "t_precond_s": rd["t_precond"], "t_solve_s": rd["t_solve"],
+                 "iters": rd["iters"], "relerr_max": float(errd.max()),
+                 "solves_per_s": int((errd <= 1e-8).sum()) / rd["t_step"]}
+    log("bench: diagonal wire basket: step %.3fs precond %.4f solve %.3f iters %s" %
+        (rd["t_step"], rd["t_precond"], rd["t_solve"], rd["iters"][:4]))
+
     nt = pinfo["n_tri"]
     pairs = nt * (nt + 1) // 2
     t_asm = float(np.mean([r["t_assemble"] for r in res]))
@@ -470,6 +493,7 @@ def main():
         "relerr_max": max(max(r["relerr"]) for r in res),
         "matvec": mv,
         "fp64_compare": fp64_step,
+        "diagonal_wirebasket": diag_step,
     }
     if not args.no_kappa:
         log("bench: condition-number study")

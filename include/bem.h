@@ -81,6 +81,9 @@ typedef struct {
 typedef struct {
     int use_coarse;          /* 1: add the coarse-space correction (default 1) */
     int factor_fp32;         /* 1: store block inverses in FP32 (mixed-precision inner solves) */
+    int wirebasket;          /* 0: exact Galerkin block of the wire basket (default); 1: its
+                              * diagonal, the pointwise product of Remark "Approximate solvers"
+                              * (Section 2), applied as R_W^T diag(W_WW)^{-1} R_W */
 } bem_precond_opts;
 
 typedef struct {

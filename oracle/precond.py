@@ -98,16 +98,26 @@ def coarse_prolongation(topo: Topology, coarse_V, coarse_T, coarse_of_triangle):
 
 
 class AdditiveSchwarz:
-    """M = sum_F R_F^T W_FF^{-1} R_F + R_W^T W_WW^{-1} R_W + R_H^T (R_H W R_H^T)^{-1} R_H."""
+    """M = sum_F R_F^T W_FF^{-1} R_F + R_W^T W_WW^{-1} R_W + R_H^T (R_H W R_H^T)^{-1} R_H.
+
+    wirebasket="diagonal" replaces the Galerkin form on the wire-basket space by the pointwise
+    (coefficient-wise) product weighted with the diagonal of W, so its subspace solver is
+    R_W^T diag(W_WW)^{-1} R_W (Remark "Approximate solvers", Section 2: the bound of Thm. main
+    survives a pointwise scalar product on the wire basket)."""
 
     def __init__(self, W, topo: Topology, patch_of_triangle=None, coarse_V=None, coarse_T=None,
-                 coarse_of_triangle=None, face_sets=None, wb=None, use_coarse=True):
+                 coarse_of_triangle=None, face_sets=None, wb=None, use_coarse=True, wirebasket="exact"):
         if face_sets is None:
             face_sets, wb = classify_dofs(topo, patch_of_triangle)
+        if wirebasket not in ("exact", "diagonal"):
+            raise ValueError("wirebasket must be 'exact' or 'diagonal'")
         self.face_sets, self.wb = face_sets, wb
         self.blocks = []
-        for idx in list(face_sets) + ([wb] if len(wb) else []):
+        for idx in list(face_sets) + ([wb] if len(wb) and wirebasket == "exact" else []):
             self.blocks.append((idx, sla.cho_factor(W[np.ix_(idx, idx)], lower=True)))
+        self.wb_diag = None
+        if wirebasket == "diagonal" and len(wb):
+            self.wb_diag = (np.asarray(wb), 1.0 / np.diag(W)[wb])
         self.RH = None
         if use_coarse and coarse_V is not None:
             self.RH, self.coarse_topo = coarse_prolongation(topo, coarse_V, coarse_T, coarse_of_triangle)
@@ -121,6 +131,9 @@ class AdditiveSchwarz:
         z = np.zeros_like(r)
         for idx, f in self.blocks:
             z[idx] += sla.cho_solve(f, r[idx])
+        if self.wb_diag is not None:
+            idx, dinv = self.wb_diag
+            z[idx] += dinv * r[idx]
         if self.RH is not None:
             z += self.RH.T @ sla.cho_solve(self.WH_f, self.RH @ r)
         return z

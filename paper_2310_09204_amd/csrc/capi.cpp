@@ -532,6 +532,8 @@ int bem_precond_setup(bem_problem* p, const int32_t* patch_of_triangle, const do
     m->p = p;
     m->use_coarse = opts ? opts->use_coarse != 0 : true;
     m->fp32 = opts ? opts->factor_fp32 != 0 : false;
+    if (opts && (opts->wirebasket < 0 || opts->wirebasket > 1)) fail(BEM_E_INVALID_ARG, "wirebasket must be 0 or 1");
+    m->wb_diag = opts ? opts->wirebasket == 1 : false;
     precond_setup_device(m.get(), patch_of_triangle, coarse_vertices, ncv, coarse_triangles, nct, coarse_of_triangle);
     *out = m.release();
     return BEM_OK;

@@ -233,6 +233,9 @@ struct bem_precond {
     bem::DeviceBuffer xg;           // apply scratch: gathered, transposed block right-hand sides
     // coarse space: R_H as CSR over coarse dofs and over fine dofs, and (R_H W R_H^T)^{-1}
     bem::DeviceBuffer rh_ptr, rh_col, rh_val, rht_ptr, rht_row, rht_val, WHinv;
+    // diagonal wire basket: its dofs and 1 / W_dd (then the wire basket is not one of the blocks)
+    bool wb_diag = false;
+    bem::DeviceBuffer wb_idx, wb_dinv;
     int64_t bytes = 0;
     double t_setup = 0;
 };

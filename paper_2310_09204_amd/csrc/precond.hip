@@ -11,10 +11,11 @@
 // The coarse space is the jump space of a nested coarse mesh written in the fine basis.
 //
 // Device work: every block (faces, wire basket, coarse Galerkin matrix) is gathered into a padded
-// 64-multiple square, factorised by a tiled right-looking Cholesky, inverted through the inverse
-// of the factor, and multiplied out into an explicit inverse B = L^{-T} L^{-1}.  All blocks of
-// uneven sizes advance together: each launch carries one tile step of every block that still has
-// work (ragged batching).  Applying M is then a ragged batch of dense row-panel products.
+// 64-multiple square and inverted explicitly by symmetric block Gauss-Jordan elimination on 64x64
+// tiles (FP64 matrix cores for the trailing updates).  All blocks of uneven sizes advance together:
+// each launch carries one tile step of every block that still has work (ragged batching).
+// Applying M is then a ragged batch of dense row-panel products.  With the diagonal wire basket
+// (Remark "Approximate solvers") that block is replaced by 1 / W_dd on its dofs.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -373,6 +374,26 @@ __global__ void k_coarse_pad_rows(double* __restrict__ A, int64_t nH, int64_t np
     if (c < npad && r < npad) A[r * npad + c] = (r == c) ? 1.0 : 0.0;
 }
 
+// --- diagonal wire basket: dinv[e] = 1 / W[d][d] for its dofs d = idx[e]; flag if W_dd <= 0 ---
+__global__ void k_wb_diag_setup(const int32_t* __restrict__ idx, int64_t n, const double* __restrict__ W, int64_t ldw,
+                                double* __restrict__ dinv, int* __restrict__ flag) {
+    const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (e >= n) return;
+    const int64_t d = idx[e];
+    const double w = W[d * ldw + d];
+    if (!(w > 0.0)) *flag = 1;
+    dinv[e] = 1.0 / w;
+}
+
+// z[c][d] = dinv[e] r[c][d] for the wire-basket dofs d = idx[e] (each dof is in no block then)
+__global__ void k_wb_diag_apply(const int32_t* __restrict__ idx, const double* __restrict__ dinv, int64_t n,
+                                const double* __restrict__ r, int64_t ld, double* __restrict__ z) {
+    const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (e >= n) return;
+    const int64_t off = int64_t(blockIdx.y) * ld + idx[e];
+    z[off] = dinv[e] * r[off];
+}
+
 // --- apply, step 1: the blocks' right-hand sides, gathered and transposed: Xg[xoff + s][n] ---------
 template <typename MT>
 __global__ void k_block_gather(const BlockMeta* __restrict__ meta, const int32_t* __restrict__ idx,
@@ -644,7 +665,7 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
     for (auto& kv : faces) blocks.push_back(kv.second);
     M->n_faces = int64_t(blocks.size());
     M->n_wb = int64_t(wb.size());
-    if (!wb.empty()) blocks.push_back(wb);
+    if (!wb.empty() && !M->wb_diag) blocks.push_back(wb);
     M->max_face = 0;
     for (int64_t b = 0; b < M->n_faces; ++b) M->max_face = std::max<int64_t>(M->max_face, blocks[b].size());
     M->nblocks = int64_t(blocks.size());
@@ -822,6 +843,19 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
     HIP_CHECK(hipStreamSynchronize(s));
     for (int64_t b = 0; b < nall; ++b)
         if (flags[b]) fail(BEM_E_NOT_SPD, "preconditioner block " + std::to_string(b) + " is not positive definite");
+    if (M->wb_diag && M->n_wb > 0) {
+        M->wb_idx = upload(wb, s);
+        M->wb_dinv = DeviceBuffer(sizeof(double) * M->n_wb, s);
+        DeviceBuffer wflag(sizeof(int), s);
+        HIP_CHECK(hipMemsetAsync(wflag.ptr, 0, sizeof(int), s));
+        hipLaunchKernelGGL(k_wb_diag_setup, dim3(nblk(M->n_wb, 256)), dim3(256), 0, s, M->wb_idx.as<int32_t>(), M->n_wb,
+                           p->W64.as<double>(), p->ldw, M->wb_dinv.as<double>(), wflag.as<int>());
+        HIP_CHECK(hipGetLastError());
+        int hf = 0;
+        HIP_CHECK(hipMemcpyAsync(&hf, wflag.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        if (hf) fail(BEM_E_NOT_SPD, "a diagonal entry of W on the wire basket is not positive");
+    }
     M->inv64 = std::move(A);
     if (M->fp32) {
         M->inv32 = DeviceBuffer(sizeof(float) * std::max<int64_t>(moff, 1), s);
@@ -840,7 +874,8 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
     for (int64_t b = 0; b < M->nblocks; ++b) M->max_npad = std::max<int64_t>(M->max_npad, meta[b].npad);
     M->tasks = upload(at, s);
     HIP_CHECK(hipStreamSynchronize(s));
-    M->bytes = int64_t(M->inv64.bytes + M->inv32.bytes + M->idx.bytes + M->rh_val.bytes * 3);
+    M->bytes = int64_t(M->inv64.bytes + M->inv32.bytes + M->idx.bytes + M->rh_val.bytes * 3 + M->wb_idx.bytes +
+                       M->wb_dinv.bytes);
     mark("fp32+apply tasks");
     M->t_setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
@@ -868,6 +903,11 @@ void precond_apply_device(const bem_precond* M, bool fp32, const double* r, int6
                 hipLaunchKernelGGL(k_block_apply<double>, dim3(unsigned(M->ntasks)), dim3(256), 0, s, M->tasks.as<int4>(), dm,
                                    M->idx.as<int32_t>(), M->inv64.as<double>(), xg, kc, ld, zc);
             }
+            HIP_CHECK(hipGetLastError());
+        }
+        if (M->wb_diag && M->n_wb > 0) {
+            hipLaunchKernelGGL(k_wb_diag_apply, dim3(nblk(M->n_wb, 256), unsigned(kc)), dim3(256), 0, s,
+                               M->wb_idx.as<int32_t>(), M->wb_dinv.as<double>(), M->n_wb, rc, ld, zc);
             HIP_CHECK(hipGetLastError());
         }
         if (M->nH > 0) {

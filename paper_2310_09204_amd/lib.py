@@ -45,7 +45,7 @@ class ProblemInfo(ctypes.Structure):
 
 
 class PrecondOpts(ctypes.Structure):
-    _fields_ = [("use_coarse", ctypes.c_int), ("factor_fp32", ctypes.c_int)]
+    _fields_ = [("use_coarse", ctypes.c_int), ("factor_fp32", ctypes.c_int), ("wirebasket", ctypes.c_int)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -302,7 +302,7 @@ class Problem:
 
 class Preconditioner:
     def __init__(self, problem: Problem, patch_of_triangle, coarse_V=None, coarse_T=None, coarse_of_triangle=None,
-                 use_coarse=True, factor_fp32=False):
+                 use_coarse=True, factor_fp32=False, wirebasket="exact"):
         self.problem = problem
         self.patch = _i32a(patch_of_triangle)
         if coarse_V is None:
@@ -311,7 +311,9 @@ class Preconditioner:
         else:
             self.cV, self.cT, self.par = _f64(coarse_V), _i32a(coarse_T), _i32a(coarse_of_triangle)
             ncv, nct = self.cV.shape[0], self.cT.shape[0]
-        o = PrecondOpts(int(use_coarse), int(factor_fp32))
+        if wirebasket not in ("exact", "diagonal"):
+            raise ValueError("wirebasket must be 'exact' or 'diagonal'")
+        o = PrecondOpts(int(use_coarse), int(factor_fp32), int(wirebasket == "diagonal"))
         self._h = ctypes.c_void_p()
         _check(load().bem_precond_setup(problem.handle, _p(self.patch), _p(self.cV), ncv, _p(self.cT), nct,
                                         _p(self.par), ctypes.byref(o), ctypes.byref(self._h)))

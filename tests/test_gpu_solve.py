@@ -14,19 +14,20 @@ pytestmark = pytest.mark.gpu
 NEAR = 10
 
 
-def _setup(ctx, w, precision=lib.FP64):
+def _setup(ctx, w, precision=lib.FP64, wirebasket="exact"):
     m = w.mesh
     p = lib.Problem(ctx, m.vertices, m.triangles, precision=precision, near_order=NEAR)
     M = lib.Preconditioner(p, w.patch_of_triangle, w.coarse.vertices, w.coarse.triangles, w.coarse_of_triangle,
-                           factor_fp32=(precision == lib.FP32_REFINE))
+                           factor_fp32=(precision == lib.FP32_REFINE), wirebasket=wirebasket)
     return p, M
 
 
-def _oracle(w):
+def _oracle(w, wirebasket="exact"):
     m = w.mesh
     t = Topology(m.vertices, m.triangles)
     W = assemble(m.vertices, m.triangles, t, NEAR)
-    P = AdditiveSchwarz(W, t, w.patch_of_triangle, w.coarse.vertices, w.coarse.triangles, w.coarse_of_triangle)
+    P = AdditiveSchwarz(W, t, w.patch_of_triangle, w.coarse.vertices, w.coarse.triangles, w.coarse_of_triangle,
+                        wirebasket=wirebasket)
     return t, W, P
 
 
@@ -175,3 +176,36 @@ def test_bowtie_paper_splitting_matches_oracle(ctx, n, ratio):
     assert rc == 0 and abs(info[0]["iters"] - it_o) <= 1
     k_o = lanczos_cond(al, be)
     assert abs(info[0]["est_cond"] - k_o) < 1e-3 * k_o, (info[0]["est_cond"], k_o)
+
+
+@pytest.mark.parametrize("name", list(small_workloads()))
+def test_diagonal_wirebasket_matches_oracle(ctx, name):
+    # Remark "Approximate solvers": the wire basket through the diagonal of W
+    w = small_workloads()[name]
+    print("case", name, flush=True)
+    p, M = _setup(ctx, w, wirebasket="diagonal")
+    t, W, P = _oracle(w, wirebasket="diagonal")
+    s = M.sizes()
+    assert s["n_faces"] == len(P.face_sets) and s["n_wb"] == len(P.wb)
+    r = np.random.default_rng(4).standard_normal((3, t.N))
+    zg = M.apply(r)
+    zo = np.stack([P.apply(ri) for ri in r])
+    assert np.abs(zg - zo).max() < 1e-11 * np.abs(zo).max()
+    L = rhs(t, w.g)[:, 0]
+    _, it_o, _, _, _ = pcg(W, L, P.apply, tol=1e-10)
+    phi, info, rc = p.solve(g=w.g, precond=M, tol=1e-10)
+    assert rc == 0 and abs(info[0]["iters"] - it_o) <= 1, (info[0]["iters"], it_o)
+    xs = cholesky_solve(W, L)
+    phi, info, rc = p.solve(g=w.g, precond=M, tol=1e-13)
+    assert np.linalg.norm(phi[0] - xs) / np.linalg.norm(xs) < 1e-10
+    # mixed precision with the diagonal wire basket
+    pm, Mm = _setup(ctx, w, precision=lib.FP32_REFINE, wirebasket="diagonal")
+    phi, info, rc = pm.solve(g=w.g, precond=Mm, tol=1e-11, precision=lib.FP32_REFINE)
+    assert rc == 0 and np.linalg.norm(phi[0] - xs) / np.linalg.norm(xs) < 1e-8
+
+
+def test_wirebasket_option_rejected(ctx):
+    w = small_workloads()["square16"]
+    p = lib.Problem(ctx, w.mesh.vertices, w.mesh.triangles, near_order=NEAR)
+    with pytest.raises(ValueError):
+        lib.Preconditioner(p, w.patch_of_triangle, wirebasket="cheap")

@@ -18,6 +18,7 @@ Modules
   precond      face / wire-basket / coarse additive Schwarz operator M          (eq. jumpSplit,
                Remark "Bound on the number of PCG iterations")
   solve        dense Cholesky solve, PCG, Lanczos condition estimate
+  potential    double-layer potential of a discrete jump at points off the screen (Lemma repDL)
 
 Parity status of each function is stated in its docstring; everything here is pinned by the
 ``-m "not gpu"`` tests in ``tests/test_oracle_*.py`` except where a docstring says

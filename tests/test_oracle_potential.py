@@ -53,3 +53,32 @@ def test_rigid_motion_and_columns():
     assert np.abs(U0 - U[0]).max() < 1e-15 * np.abs(U).max()
     Us = double_layer(m.vertices, m.triangles, jump[0] + 2 * jump[1], Xb)
     assert np.abs(Us - (U[0] + 2 * U[1])).max() < 1e-14 * np.abs(Us).max()
+
+
+def _disk_axis_exact(z):
+    # U(0, 0, z) = (z / 2) int_0^1 [u](r) r / (r^2 + z^2)^(3/2) dr for the exact jump of the flat
+    # unit disk with g = e_z, [u](r) = -(4/pi) sqrt(1 - r^2)
+    f = lambda r: -(4.0 / math.pi) * math.sqrt(1.0 - r * r) * r / (r * r + z * z) ** 1.5
+    return 0.5 * z * integrate.quad(f, 0.0, 1.0, epsabs=1e-14, epsrel=1e-13)[0]
+
+
+def test_disk_solution_on_the_axis():
+    # the potential of the discrete disk solution converges to the exact one at first order in h
+    # (the jump has a square-root edge singularity), and is odd in z
+    from oracle.assemble import assemble, rhs
+    from oracle.solve import cholesky_solve
+    from oracle.topology import Topology
+    zs = np.array([0.5, 1.0, 2.0, -1.0])
+    exact = np.array([_disk_axis_exact(z) for z in zs])
+    X = np.stack([np.zeros_like(zs), np.zeros_like(zs), zs], axis=1)
+    errs = []
+    for rings in (4, 8, 12):
+        m = meshes.disk(rings)
+        t = Topology(m.vertices, m.triangles)
+        W = assemble(m.vertices, m.triangles, t, 10)
+        phi = cholesky_solve(W, rhs(t, (0.0, 0.0, 1.0))[:, 0])
+        U = double_layer(m.vertices, m.triangles, t.jump_values(phi), X)
+        assert abs(U[1] + U[3]) < 1e-14
+        errs.append(np.abs(U - exact).max() / np.abs(exact).max())
+    rate = math.log(errs[0] / errs[2]) / math.log(12 / 4)
+    assert 0.8 < rate < 1.4 and errs[2] < 0.02, (errs, rate)

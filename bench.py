@@ -208,6 +208,39 @@ def serving_leg(lib, meshes, ctx, n_requests, load, seed=0, max_inflight=4):
     }
 
 
+def double_layer_leg(lib, w, ctx, m_targets=16384, k=16):
+    """Double-layer potential (Lemma repDL) of k crossed96 solutions at seeded targets in [-1, 1]^3
+    at least 0.05 (about 5 h) from every panel plane: evaluations (target x Gauss point) per second
+    and the FP64 rate, counting 16 + 2 k flops per evaluation (distance 8, Newton step 4, cube 2,
+    normal projection 2, one FMA per column; the reciprocal square root not counted)."""
+    m = w.mesh
+    p = lib.Problem(ctx, m.vertices, m.triangles, precision=lib.FP32_REFINE, near_order=10)
+    M = lib.Preconditioner(p, w.patch_of_triangle, w.coarse.vertices, w.coarse.triangles, w.coarse_of_triangle,
+                           factor_fp32=True)
+    g = w.g[:k] if w.g.shape[0] >= k else np.resize(w.g, (k, 3))
+    phi, _, _ = p.solve(g=g, precond=M, tol=1e-10, precision=lib.FP32_REFINE)
+    rng = np.random.default_rng(11)
+    X = []
+    while len(X) < m_targets:
+        x = rng.uniform(-1.0, 1.0, size=(m_targets, 3))
+        X.extend(x[np.abs(x).min(axis=1) >= 0.05])
+    X = np.array(X[:m_targets])
+    p.double_layer(phi, X)     # builds the per-triangle records
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        U = p.double_layer(phi, X)
+    t = (time.perf_counter() - t0) / reps
+    evals = m_targets * 7 * m.nt
+    out = {"targets": m_targets, "k": k, "t_s": t, "evals_per_s": evals / t,
+           "tflops": evals * (16 + 2 * k) / t / 1e12, "finite": bool(np.isfinite(U).all())}
+    M.close()
+    p.close()
+    log("bench: double layer %d targets x %d points, k=%d: %.2f ms, %.1f TFLOP/s" %
+        (m_targets, 7 * m.nt, k, t * 1e3, out["tflops"]))
+    return out
+
+
 def kappa_study(lib, meshes, ctx):
     """Lanczos estimate of kappa(P_ad W) on the paper's three-dimensional experiment (two
     perpendicular equilateral triangles sharing a median) with faces = coarse triangles, over coarse
@@ -326,6 +359,7 @@ def main():
                     help="requests in the serving-stream leg (0 skips it)")
     ap.add_argument("--no-large", action="store_true", help="skip the crossed192 leg")
     ap.add_argument("--no-kappa", action="store_true", help="skip the condition-number study")
+    ap.add_argument("--no-potential", action="store_true", help="skip the double-layer potential leg")
     ap.add_argument("--serve-load", type=float, default=0.7,
                     help="arrival rate of the serving leg as a fraction of its measured capacity")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -495,6 +529,8 @@ def main():
         "fp64_compare": fp64_step,
         "diagonal_wirebasket": diag_step,
     }
+    if not args.no_potential:
+        out["double_layer"] = double_layer_leg(lib, w, ctx)
     if not args.no_kappa:
         log("bench: condition-number study")
         out["kappa_study"] = kappa_study(lib, meshes, ctx)

@@ -164,6 +164,19 @@ int bem_problem_bench_matvec(const bem_problem* p, int fp32, int32_t k, int reps
  * function across triangle t at corner a */
 int bem_jump_values(const bem_problem* p, const double* phi, double* jump_out);
 
+/* ---- double-layer potential (Lemma repDL, eq. formulaDL) --------------------------------- */
+/* U_c(x_i) = sum_T int_T n_T . (x_i - y) / (4 pi |x_i - y|^3) [u_c]_T(y) dsigma(y) for the solution
+ * columns phi[c] (c < k) of this problem, where [u_c]_T is the jump across T of sum_d phi[c][d]
+ * psi_d (the per-corner values of bem_jump_values, linear on T).  The sides' normals follow the
+ * orientation of bem_pcg_solve (side + has the outward normal -n_T), so U jumps by [u] across the
+ * screen.  The integral is the 7-point rule on every triangle: accurate for targets at least a few
+ * mesh sizes from the screen, with no refinement closer in.  phi: host [k][N]; targets: host
+ * [m][3]; u_out: host [k][m].  Per-triangle data are built on the first call and kept with the
+ * problem.  Returns BEM_OK, or BEM_E_INVALID_ARG (NULL pointer, k < 1, m < 0, non-finite target),
+ * BEM_E_OOM, BEM_E_DEVICE. */
+int bem_double_layer(bem_problem* p, const double* phi, int32_t k, const double* targets, int64_t m,
+                     double* u_out);
+
 /* ---- preconditioner (eq. jumpSplit; Remark on PCG iterations) ------------------------------ */
 /* Two-level additive Schwarz operator
  *   M r = sum_F R_F^T W_FF^{-1} R_F r + R_W^T W_WW^{-1} R_W r + R_H^T (R_H W R_H^T)^{-1} R_H r.

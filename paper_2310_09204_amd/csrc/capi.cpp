@@ -521,6 +521,25 @@ int bem_jump_values(const bem_problem* p, const double* phi, double* jump_out) {
     BEM_CATCH
 }
 
+int bem_double_layer(bem_problem* p, const double* phi, int32_t k, const double* targets, int64_t m, double* u_out) {
+    BEM_TRY
+    if (!p || !phi || !targets || !u_out || k < 1 || m < 0) fail(BEM_E_INVALID_ARG, "bad argument");
+    for (int64_t i = 0; i < 3 * m; ++i)
+        if (!std::isfinite(targets[i])) fail(BEM_E_INVALID_ARG, "non-finite target coordinate");
+    set_device(p->ctx);
+    if (m == 0) return BEM_OK;
+    const int64_t N = p->N;
+    DeviceBuffer dp(sizeof(double) * std::max<int64_t>(1, N * k), p->stream), dx(sizeof(double) * 3 * m, p->stream),
+        du(sizeof(double) * k * m, p->stream);
+    if (N) HIP_CHECK(hipMemcpyAsync(dp.ptr, phi, sizeof(double) * N * k, hipMemcpyHostToDevice, p->stream));
+    HIP_CHECK(hipMemcpyAsync(dx.ptr, targets, sizeof(double) * 3 * m, hipMemcpyHostToDevice, p->stream));
+    double_layer_device(p, dp.as<double>(), k, dx.as<double>(), m, du.as<double>(), p->stream);
+    HIP_CHECK(hipMemcpyAsync(u_out, du.ptr, sizeof(double) * k * m, hipMemcpyDeviceToHost, p->stream));
+    HIP_CHECK(hipStreamSynchronize(p->stream));
+    return BEM_OK;
+    BEM_CATCH
+}
+
 int bem_precond_setup(bem_problem* p, const int32_t* patch_of_triangle, const double* coarse_vertices, int64_t ncv,
                       const int32_t* coarse_triangles, int64_t nct, const int32_t* coarse_of_triangle,
                       const bem_precond_opts* opts, bem_precond** out) {

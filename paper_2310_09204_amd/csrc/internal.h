@@ -196,6 +196,9 @@ struct bem_problem {
     // scratch of the multi-column product: transposed right-hand sides (ldw x 16, FP64-sized) and
     // per-split partial sums (16 splits x 16 columns x ldw).  Calls on one problem must not overlap.
     bem::DeviceBuffer mv_xt, mv_partial;
+    // double-layer potential: per-triangle records (normal, Gauss points, n . y) and the 7-point rule,
+    // built on the first evaluation
+    bem::DeviceBuffer dl_rec, dl_rule;
     double t_assemble = 0, t_far = 0, t_near = 0, t_contract = 0, t_host = 0;
     int64_t bytes = 0;
 };
@@ -209,6 +212,9 @@ void assemble_device(bem_problem* p, const double* V, int64_t nv, const int32_t*
                      const std::function<void(NearList&)>& analyse);
 void rhs_device(const bem_problem* p, const double* d_g, int k, double* d_L, hipStream_t s);
 void jump_values_device(const bem_problem* p, const double* d_phi, double* d_jump, hipStream_t s);
+// double-layer potential (potential.hip): U [k][m] at targets X [m][3] for phi [k][N], all on the device
+void double_layer_device(bem_problem* p, const double* d_phi, int k, const double* d_X, int64_t m, double* d_U,
+                         hipStream_t s);
 
 // dense products (solver.hip); x, y column-major [k][N] with leading dimension ldx
 void matvec_device(const bem_problem* p, bool fp32, const double* d_x, int64_t ldx, int k,

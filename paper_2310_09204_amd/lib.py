@@ -90,6 +90,7 @@ SIGNATURES = {
     "bem_ctx_destroy": (None, [_vp]),
     "bem_ctx_synchronize": (_ci, [_vp]),
     "bem_ctx_release_cached": (_ci, [_vp]),
+    "bem_double_layer": (_ci, [_vp, _vp, _i32, _vp, _i64, _vp]),
     "bem_problem_bench_matvec": (_ci, [_vp, _ci, _i32, _ci, ctypes.POINTER(ctypes.c_double)]),
     "bem_mesh_analyze": (_ci, [_vp, _i64, _vp, _i64, ctypes.POINTER(_i64), _vp, _vp, _vp]),
     "bem_assemble": (_ci, [_vp, _vp, _i64, _vp, _i64, ctypes.POINTER(AssembleOpts), ctypes.POINTER(_vp)]),
@@ -264,6 +265,16 @@ class Problem:
         phi = _f64(phi)
         out = np.empty((self.T.shape[0], 3))
         _check(load().bem_jump_values(self._h, _p(phi), _p(out)))
+        return out
+
+    def double_layer(self, phi, targets):
+        """U[k][m]: double-layer potential of the solutions phi[k][N] at targets[m][3]."""
+        phi = _f64(np.atleast_2d(phi))
+        X = _f64(np.atleast_2d(targets))
+        if X.shape[1] != 3:
+            raise ValueError("targets must be m x 3")
+        out = np.empty((phi.shape[0], X.shape[0]))
+        _check(load().bem_double_layer(self._h, _p(phi), phi.shape[0], _p(X), X.shape[0], _p(out)))
         return out
 
     def solve(self, g=None, rhs=None, precond=None, tol=1e-10, max_iter=2000, use_precond=True,

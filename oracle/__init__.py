@@ -19,6 +19,7 @@ Modules
                Remark "Bound on the number of PCG iterations")
   solve        dense Cholesky solve, PCG, Lanczos condition estimate
   potential    double-layer potential of a discrete jump at points off the screen (Lemma repDL)
+  twod         the method on segment multiscreens in the plane (Section 2, Experiments 1 and 2)
 
 Parity status of each function is stated in its docstring; everything here is pinned by the
 ``-m "not gpu"`` tests in ``tests/test_oracle_*.py`` except where a docstring says

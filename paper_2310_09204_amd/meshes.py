@@ -617,3 +617,42 @@ def serving_stream(seed: int, n_requests: int, rate: float, n_range: Tuple[int, 
         g /= np.linalg.norm(g, axis=1, keepdims=True)
         out.append(ServeRequest(t, gi, mesh, patches, cm, par, g, bool(rng.integers(0, 2))))
     return out
+
+
+# ---- two-dimensional multiscreens (segment meshes in the plane) ----------------------------------
+
+def _arms_mesh(center, tips, n, grading=1.0):
+    """Segments from a common centre to each tip, n per arm; grading > 1 refines towards the tips
+    (node k at 1 - (1 - k/n)^grading of the arm)."""
+    V = [tuple(center)]
+    S = []
+    for tip in tips:
+        prev = 0
+        for k in range(1, n + 1):
+            s = 1.0 - (1.0 - k / n) ** grading
+            V.append(tuple(np.asarray(center) + s * (np.asarray(tip) - np.asarray(center))))
+            S.append((prev, len(V) - 1))
+            prev = len(V) - 1
+    return np.asarray(V, dtype=np.float64), np.asarray(S, dtype=np.int32)
+
+
+def plus2d(n: int, grading: float = 1.0):
+    """Experiment 1: the cross [-1, 1] x {0} u {0} x [-1, 1], n segments per arm."""
+    return _arms_mesh((0.0, 0.0), [(1.0, 0.0), (0.0, 1.0), (-1.0, 0.0), (0.0, -1.0)], n, grading)
+
+
+def threefold2d(n: int):
+    """Experiment 2: three segments from the centre of gravity of an equilateral triangle (side 1)
+    to its vertices, n segments each."""
+    r = 1.0 / math.sqrt(3.0)
+    tips = [(r * math.cos(a), r * math.sin(a)) for a in (math.pi / 2, math.pi / 2 + 2 * math.pi / 3,
+                                                         math.pi / 2 + 4 * math.pi / 3)]
+    return _arms_mesh((0.0, 0.0), tips, n)
+
+
+def slit2d(n: int):
+    """The segment [-1, 1] x {0} with 2n segments (nodes at the cross's horizontal-arm nodes)."""
+    x = np.linspace(-1.0, 1.0, 2 * n + 1)
+    V = np.stack([x, np.zeros_like(x)], axis=1)
+    S = np.stack([np.arange(2 * n), np.arange(1, 2 * n + 1)], axis=1).astype(np.int32)
+    return V, S

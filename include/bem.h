@@ -76,6 +76,7 @@ typedef struct {
     double t_far_s, t_near_s, t_contract_s; /* device time of the three assembly phases */
     double t_host_s;         /* host time of the mesh analysis and near-pair list */
     int64_t n_pair_panels;   /* panels the pair matrix was built in (0: in one piece) */
+    int64_t dim;             /* 3: triangle mesh (n_tri triangles); 2: segment mesh (n_tri segments) */
 } bem_problem_info;
 
 typedef struct {
@@ -161,8 +162,34 @@ int bem_matvec(const bem_problem* p, const double* x, int32_t k, int fp32, doubl
  * seconds per product.  W is streamed once per product (N^2 x 8 or 4 bytes). */
 int bem_problem_bench_matvec(const bem_problem* p, int fp32, int32_t k, int reps, double* seconds);
 /* label-free view of phi[N]: jump[t][a] = sum_d c_{T,a,d} phi_d, the jump of the represented
- * function across triangle t at corner a */
+ * function across triangle t at corner a (jump_out[nt][3]); for a segment mesh across segment s
+ * at its end a (jump_out[ns][2]) */
 int bem_jump_values(const bem_problem* p, const double* phi, double* jump_out);
+
+/* ---- two-dimensional variant (Section 2, Experiments 1 and 2) ---------------------------- */
+/* Segment multiscreens in the plane: vertices[nv][2], segments[ns][2]; the order of a segment's
+ * ends fixes its tangent tau_s and normal n_s = (-tau_y, tau_x).  Sectors at a vertex are the
+ * angular regions between its segments (a segment end no other segment meets has q = 1 and no
+ * dof); dofs, the jump basis and the coefficients c_{s,a,d} follow Section 4.2 with segments for
+ * triangles.  W_{d,d'} = sum_{s,s'} D_{s,d} D_{s',d'} K(s,s') with D_{s,d} = (c_{s,1,d} -
+ * c_{s,0,d}) / |s| (derivative of the jump along s) and K(s,s') = -1/(2 pi) int_s int_s' log|x-y|:
+ * 8-point Gauss-Legendre on both segments of a disjoint pair, a closed form for a segment with
+ * itself, and for segments with a common end the split of the parameter square along its
+ * diagonal with the singular factor integrated exactly.  The problem works with bem_pcg_solve
+ * (g[k][3] with g_z ignored: L_d = -sum_s (g . n_s) |s| / 2 (c_{s,0,d} + c_{s,1,d})),
+ * bem_pcg_solve_rhs, bem_rhs, bem_matvec, bem_problem_copy_matrix, bem_problem_rows,
+ * bem_jump_values, bem_problem_bench_matvec and bem_precond_setup_sets; bem_precond_setup and
+ * bem_double_layer reject it.  opts: precision as for bem_assemble (near_order is not used).
+ * Errors: BEM_E_INVALID_ARG (NULL, index out of range, non-finite coordinate), BEM_E_DEGENERATE
+ * (zero length), BEM_E_MESH_NONCONFORMING (repeated or overlapping segments), BEM_E_OOM,
+ * BEM_E_DEVICE.  K takes ns^2 x 8 bytes of device memory during the call. */
+/* Host-only analysis of a segment mesh: *n_dofs, and if non-NULL the dof table (dof_vertex[N],
+ * dof_sector[N]), the per-vertex sector counts q[nv] and the jump coefficients as a dense
+ * array c[ns][2][N] (c_{s,a,d}; only for small meshes).  Validation errors as bem_assemble_2d. */
+int bem_mesh_analyze_2d(const double* vertices, int64_t nv, const int32_t* segments, int64_t ns, int64_t* n_dofs,
+                        int32_t* dof_vertex, int32_t* dof_sector, int32_t* q, double* c);
+int bem_assemble_2d(bem_ctx* ctx, const double* vertices, int64_t nv, const int32_t* segments, int64_t ns,
+                    const bem_assemble_opts* opts, bem_problem** out);
 
 /* ---- double-layer potential (Lemma repDL, eq. formulaDL) --------------------------------- */
 /* U_c(x_i) = sum_T int_T n_T . (x_i - y) / (4 pi |x_i - y|^3) [u_c]_T(y) dsigma(y) for the solution

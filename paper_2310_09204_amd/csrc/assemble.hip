@@ -833,14 +833,33 @@ __global__ void k_rhs(const int64_t* __restrict__ dof_ptr, const int32_t* __rest
     }
 }
 
+// per element (triangle: 3 corners, segment: 2 ends) the jump of sum_d phi_d psi_d at its corners
 __global__ void k_jump_values(const int64_t* __restrict__ tri_ptr, const int32_t* __restrict__ tri_dof,
                               const int8_t* __restrict__ tri_corner, const int8_t* __restrict__ tri_c,
-                              int64_t nt, const double* __restrict__ phi, double* __restrict__ out) {
+                              int64_t nt, int corners, const double* __restrict__ phi, double* __restrict__ out) {
     int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (t >= nt) return;
     double j[3] = {0.0, 0.0, 0.0};
     for (int64_t e = tri_ptr[t]; e < tri_ptr[t + 1]; ++e) j[tri_corner[e]] += double(tri_c[e]) * phi[tri_dof[e]];
-    for (int a = 0; a < 3; ++a) out[3 * t + a] = j[a];
+    for (int a = 0; a < corners; ++a) out[corners * t + a] = j[a];
+}
+
+// two-dimensional right-hand side: L[k][d] = -sum over the star of d of c (g_k . n_s) |s| / 2
+__global__ void k_rhs2d(const int64_t* __restrict__ dof_ptr, const int32_t* __restrict__ dof_seg,
+                        const int8_t* __restrict__ dof_c, const double* __restrict__ normal,
+                        const double* __restrict__ length, int64_t N, const double* __restrict__ g, int k,
+                        double* __restrict__ L) {
+    int64_t d = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (d >= N) return;
+    for (int c = 0; c < k; ++c) {
+        double s = 0.0;
+        for (int64_t e = dof_ptr[d]; e < dof_ptr[d + 1]; ++e) {
+            const int64_t t = dof_seg[e];
+            const double gn = g[3 * c] * normal[3 * t] + g[3 * c + 1] * normal[3 * t + 1];
+            s -= double(dof_c[e]) * gn * length[t] * 0.5;
+        }
+        L[int64_t(c) * N + d] = s;
+    }
 }
 
 inline unsigned blocks_for(int64_t n, int per) { return unsigned((n + per - 1) / per); }
@@ -1335,15 +1354,19 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
 void rhs_device(const bem_problem* p, const double* d_g, int k, double* d_L, hipStream_t s) {
     const int64_t N = p->N;
     if (N == 0) return;
-    hipLaunchKernelGGL(k_rhs, dim3(blocks_for(N, 256)), dim3(256), 0, s, p->dof_ptr.as<int64_t>(), p->dof_tri.as<int32_t>(),
-                       p->dof_c.as<int8_t>(), p->normal.as<double>(), p->area.as<double>(), N, d_g, k, d_L);
+    if (p->topo.dim == 2)
+        hipLaunchKernelGGL(k_rhs2d, dim3(blocks_for(N, 256)), dim3(256), 0, s, p->dof_ptr.as<int64_t>(), p->dof_tri.as<int32_t>(),
+                           p->dof_c.as<int8_t>(), p->normal.as<double>(), p->area.as<double>(), N, d_g, k, d_L);
+    else
+        hipLaunchKernelGGL(k_rhs, dim3(blocks_for(N, 256)), dim3(256), 0, s, p->dof_ptr.as<int64_t>(), p->dof_tri.as<int32_t>(),
+                           p->dof_c.as<int8_t>(), p->normal.as<double>(), p->area.as<double>(), N, d_g, k, d_L);
     HIP_CHECK(hipGetLastError());
 }
 
 void jump_values_device(const bem_problem* p, const double* d_phi, double* d_jump, hipStream_t s) {
     const int64_t nt = p->topo.nt;
     hipLaunchKernelGGL(k_jump_values, dim3(blocks_for(nt, 256)), dim3(256), 0, s, p->tri_ptr.as<int64_t>(), p->tri_dof.as<int32_t>(),
-                       p->tri_corner.as<int8_t>(), p->tri_c.as<int8_t>(), nt, d_phi, d_jump);
+                       p->tri_corner.as<int8_t>(), p->tri_c.as<int8_t>(), nt, p->topo.dim == 2 ? 2 : 3, d_phi, d_jump);
     HIP_CHECK(hipGetLastError());
 }
 

@@ -390,6 +390,59 @@ int bem_assemble(bem_ctx* ctx, const double* vertices, int64_t nv, const int32_t
     BEM_CATCH
 }
 
+int bem_mesh_analyze_2d(const double* vertices, int64_t nv, const int32_t* segments, int64_t ns, int64_t* n_dofs,
+                        int32_t* dof_vertex, int32_t* dof_sector, int32_t* q, double* c) {
+    BEM_TRY
+    MeshTopo m;
+    analyze_segments(vertices, nv, segments, ns, m);
+    if (n_dofs) *n_dofs = m.N;
+    if (dof_vertex && m.N) std::memcpy(dof_vertex, m.dof_vertex.data(), sizeof(int32_t) * m.N);
+    if (dof_sector && m.N) std::memcpy(dof_sector, m.dof_sector.data(), sizeof(int32_t) * m.N);
+    if (q) std::memcpy(q, m.q.data(), sizeof(int32_t) * nv);
+    if (c) {
+        std::memset(c, 0, sizeof(double) * ns * 2 * m.N);
+        for (int64_t t = 0; t < ns; ++t)
+            for (int64_t e = m.tri_ptr[t]; e < m.tri_ptr[t + 1]; ++e)
+                c[(t * 2 + m.tri_corner[e]) * m.N + m.tri_dof[e]] = double(m.tri_c[e]);
+    }
+    return BEM_OK;
+    BEM_CATCH
+}
+
+int bem_assemble_2d(bem_ctx* ctx, const double* vertices, int64_t nv, const int32_t* segments, int64_t ns,
+                    const bem_assemble_opts* opts, bem_problem** out) {
+    BEM_TRY
+    if (!ctx || !out) fail(BEM_E_INVALID_ARG, "ctx/out is NULL");
+    *out = nullptr;
+    set_device(ctx);
+    auto t0 = std::chrono::steady_clock::now();
+    std::unique_ptr<bem_problem> p(new bem_problem());
+    p->ctx = ctx;
+    p->has_w32 = opts && opts->precision == BEM_FP32_REFINE;
+    if (opts && opts->keep_pair_matrix) fail(BEM_E_INVALID_ARG, "keep_pair_matrix is for triangle meshes");
+    {
+        std::lock_guard<std::mutex> cap(capture_mutex());
+        HIP_CHECK(hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking));
+    }
+    try {
+        assemble_2d_device(p.get(), vertices, nv, segments, ns);
+    } catch (...) {
+        (void)hipStreamSynchronize(p->stream);
+        hipStream_t s = p->stream;
+        p.reset();
+        std::lock_guard<std::mutex> cap(capture_mutex());
+        (void)hipStreamDestroy(s);
+        throw;
+    }
+    p->bytes = int64_t(p->W64.bytes + p->W32.bytes + p->normal.bytes + p->area.bytes + p->dof_ptr.bytes +
+                       p->dof_tri.bytes + p->dof_c.bytes + p->tri_ptr.bytes + p->tri_dof.bytes + p->tri_corner.bytes +
+                       p->tri_c.bytes);
+    p->t_assemble = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *out = p.release();
+    return BEM_OK;
+    BEM_CATCH
+}
+
 void bem_problem_destroy(bem_problem* p) {
     if (!p) return;
     (void)hipSetDevice(p->ctx->device);
@@ -424,6 +477,7 @@ int bem_problem_get_info(const bem_problem* p, bem_problem_info* info) {
     info->t_contract_s = p->t_contract;
     info->t_host_s = p->t_host;
     info->n_pair_panels = p->n_panels;
+    info->dim = p->topo.dim;
     return BEM_OK;
     BEM_CATCH
 }
@@ -511,11 +565,11 @@ int bem_jump_values(const bem_problem* p, const double* phi, double* jump_out) {
     BEM_TRY
     if (!p || !phi || !jump_out) fail(BEM_E_INVALID_ARG, "bad argument");
     set_device(p->ctx);
-    const int64_t N = p->N, nt = p->topo.nt;
-    DeviceBuffer dp(sizeof(double) * std::max<int64_t>(1, N), p->stream), dj(sizeof(double) * nt * 3, p->stream);
+    const int64_t N = p->N, nt = p->topo.nt, corners = p->topo.dim == 2 ? 2 : 3;
+    DeviceBuffer dp(sizeof(double) * std::max<int64_t>(1, N), p->stream), dj(sizeof(double) * nt * corners, p->stream);
     if (N) HIP_CHECK(hipMemcpyAsync(dp.ptr, phi, sizeof(double) * N, hipMemcpyHostToDevice, p->stream));
     jump_values_device(p, dp.as<double>(), dj.as<double>(), p->stream);
-    HIP_CHECK(hipMemcpyAsync(jump_out, dj.ptr, sizeof(double) * nt * 3, hipMemcpyDeviceToHost, p->stream));
+    HIP_CHECK(hipMemcpyAsync(jump_out, dj.ptr, sizeof(double) * nt * corners, hipMemcpyDeviceToHost, p->stream));
     HIP_CHECK(hipStreamSynchronize(p->stream));
     return BEM_OK;
     BEM_CATCH
@@ -524,6 +578,7 @@ int bem_jump_values(const bem_problem* p, const double* phi, double* jump_out) {
 int bem_double_layer(bem_problem* p, const double* phi, int32_t k, const double* targets, int64_t m, double* u_out) {
     BEM_TRY
     if (!p || !phi || !targets || !u_out || k < 1 || m < 0) fail(BEM_E_INVALID_ARG, "bad argument");
+    if (p->topo.dim != 3) fail(BEM_E_INVALID_ARG, "the double-layer potential is for triangle meshes");
     for (int64_t i = 0; i < 3 * m; ++i)
         if (!std::isfinite(targets[i])) fail(BEM_E_INVALID_ARG, "non-finite target coordinate");
     set_device(p->ctx);
@@ -546,6 +601,7 @@ int bem_precond_setup(bem_problem* p, const int32_t* patch_of_triangle, const do
     BEM_TRY
     if (!p || !out) fail(BEM_E_INVALID_ARG, "NULL argument");
     *out = nullptr;
+    if (p->topo.dim != 3) fail(BEM_E_INVALID_ARG, "bem_precond_setup needs a triangle mesh; use bem_precond_setup_sets");
     set_device(p->ctx);
     std::unique_ptr<bem_precond> m(new bem_precond());
     m->p = p;

@@ -36,9 +36,11 @@ void set_last_error(const std::string& msg);
 // Host topology of a multiscreen mesh (Section 4.2 / 4.3 of the paper)
 // ------------------------------------------------------------------------------------------
 struct MeshTopo {
+    int dim = 3;                    // 3: triangles in space; 2: segments in the plane (nt counts segments)
     int64_t nv = 0, nt = 0, N = 0;
-    std::vector<double> V;          // nv*3
-    std::vector<int32_t> T;         // nt*3
+    std::vector<double> V;          // nv*3 (z = 0 in the plane)
+    std::vector<int32_t> T;         // nt*3 (triangles)
+    std::vector<int32_t> S;         // nt*2 (segments)
     std::vector<double> normal;     // nt*3 unit normal n_T
     std::vector<double> area;       // nt
     std::vector<int32_t> q;         // nv sector counts
@@ -57,6 +59,10 @@ struct MeshTopo {
 
 // Validates and analyses a mesh; throws Failure with a BEM_E_* code on invalid input.
 void analyze_mesh(const double* V, int64_t nv, const int32_t* T, int64_t nt, MeshTopo& out);
+// The same for a segment mesh in the plane (V: nv*2, S: ns*2): sectors are the angular regions
+// between the segments at a vertex; normal (nt*3) holds n_s = (-tau_y, tau_x, 0), area the lengths,
+// and the element CSR (tri_*) has corners 0 and 1.
+void analyze_segments(const double* V, int64_t nv, const int32_t* S, int64_t ns, MeshTopo& out);
 
 // Pairs of triangles with at least one common vertex, t1 <= t2, with the canonical vertex order
 // the Duffy rules expect: type 3 (same triangle) A,B,C; type 2 (common edge A-B) A,B,C,C';
@@ -211,6 +217,8 @@ namespace bem {
 void assemble_device(bem_problem* p, const double* V, int64_t nv, const int32_t* T, int64_t nt,
                      const std::function<void(NearList&)>& analyse);
 void rhs_device(const bem_problem* p, const double* d_g, int k, double* d_L, hipStream_t s);
+// two-dimensional variant (twod.hip): analyses the segment mesh into p->topo and assembles W
+void assemble_2d_device(bem_problem* p, const double* V2, int64_t nv, const int32_t* S, int64_t ns);
 void jump_values_device(const bem_problem* p, const double* d_phi, double* d_jump, hipStream_t s);
 // double-layer potential (potential.hip): U [k][m] at targets X [m][3] for phi [k][N], all on the device
 void double_layer_device(bem_problem* p, const double* d_phi, int k, const double* d_X, int64_t m, double* d_U,

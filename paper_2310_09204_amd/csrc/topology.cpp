@@ -303,6 +303,140 @@ void analyze_mesh(const double* Vin, int64_t nv, const int32_t* Tin, int64_t nt,
     }
 }
 
+void analyze_segments(const double* Vin, int64_t nv, const int32_t* Sin, int64_t ns, MeshTopo& m) {
+    if (!Vin || !Sin || nv <= 0 || ns <= 0) fail(BEM_E_INVALID_ARG, "empty mesh");
+    if (ns > (int64_t(1) << 30)) fail(BEM_E_INVALID_ARG, "too many segments");
+    m = MeshTopo();
+    m.dim = 2;
+    m.nv = nv;
+    m.nt = ns;
+    m.V.assign(size_t(nv) * 3, 0.0);
+    for (int64_t v = 0; v < nv; ++v) {
+        if (!std::isfinite(Vin[2 * v]) || !std::isfinite(Vin[2 * v + 1])) fail(BEM_E_INVALID_ARG, "non-finite vertex coordinate");
+        m.V[3 * v] = Vin[2 * v];
+        m.V[3 * v + 1] = Vin[2 * v + 1];
+    }
+    m.S.assign(Sin, Sin + 2 * ns);
+    m.normal.assign(size_t(ns) * 3, 0.0);
+    m.area.assign(size_t(ns), 0.0);
+    double extent = 0.0;
+    for (int64_t i = 0; i < 2 * nv; ++i) extent = std::max(extent, std::fabs(Vin[i]));
+    for (int64_t s = 0; s < ns; ++s) {
+        const int32_t a = Sin[2 * s], b = Sin[2 * s + 1];
+        if (a < 0 || a >= nv || b < 0 || b >= nv) fail(BEM_E_INVALID_ARG, "segment " + std::to_string(s) + " has a vertex index out of range");
+        const double dx = Vin[2 * b] - Vin[2 * a], dy = Vin[2 * b + 1] - Vin[2 * a + 1];
+        const double len = std::sqrt(dx * dx + dy * dy);
+        if (a == b || !(len > 1e-12 * std::max(extent, 1e-300))) fail(BEM_E_DEGENERATE, "segment " + std::to_string(s) + " has zero length");
+        m.area[s] = len;
+        m.normal[3 * s] = -dy / len;
+        m.normal[3 * s + 1] = dx / len;
+    }
+    // incident segment ends per vertex, sorted by the angle of the direction leaving the vertex
+    std::vector<int64_t> vptr(nv + 1, 0);
+    for (int64_t i = 0; i < 2 * ns; ++i) ++vptr[Sin[i] + 1];
+    for (int64_t v = 0; v < nv; ++v) vptr[v + 1] += vptr[v];
+    std::vector<int64_t> ends(2 * ns);   // 2 s + a
+    {
+        std::vector<int64_t> fill(vptr.begin(), vptr.end() - 1);
+        for (int64_t s = 0; s < ns; ++s)
+            for (int a = 0; a < 2; ++a) ends[fill[Sin[2 * s + a]]++] = 2 * s + a;
+    }
+    // sector label of side (s, end a, side sd): index [4 s + 2 a + sd], sd 0 = side +, 1 = side -
+    m.sector.assign(size_t(ns) * 4, -1);
+    m.q.assign(nv, 0);
+    for (int64_t v = 0; v < nv; ++v) {
+        const int64_t deg = vptr[v + 1] - vptr[v];
+        if (deg == 0) continue;
+        std::vector<std::pair<double, int64_t>> dir;
+        for (int64_t k = vptr[v]; k < vptr[v + 1]; ++k) {
+            const int64_t s = ends[k] / 2;
+            const int a = int(ends[k] % 2);
+            const int32_t o = Sin[2 * s + 1 - a];   // the other end
+            dir.emplace_back(std::atan2(Vin[2 * o + 1] - Vin[2 * v + 1], Vin[2 * o] - Vin[2 * v]), ends[k]);
+        }
+        std::sort(dir.begin(), dir.end());
+        for (size_t k = 0; k + 1 < dir.size(); ++k)
+            if (dir[k + 1].first - dir[k].first < 1e-9) {
+                const int64_t s1 = dir[k].second / 2, s2 = dir[k + 1].second / 2;
+                fail(BEM_E_MESH_NONCONFORMING, s1 == s2 ? "repeated segment" :
+                     "segments " + std::to_string(s1) + " and " + std::to_string(s2) + " overlap at vertex " + std::to_string(v));
+            }
+        // sector k: the counter-clockwise hand of direction k and the clockwise hand of direction
+        // k + 1.  Leaving v along segment s, the counter-clockwise hand is side + if s starts at v
+        // (n_s is tau_s turned counter-clockwise) and side - if it ends there.
+        const int64_t mdeg = int64_t(dir.size());
+        std::vector<std::array<int64_t, 2>> mem(mdeg);   // members as 2 s + side
+        for (int64_t k = 0; k < mdeg; ++k) {
+            const int64_t e1 = dir[k].second, e2 = dir[(k + 1) % mdeg].second;
+            const int64_t ccw = 2 * (e1 / 2) + ((e1 % 2 == 0) ? 0 : 1);
+            const int64_t cw = 2 * (e2 / 2) + ((e2 % 2 == 0) ? 1 : 0);
+            mem[k] = {std::min(ccw, cw), std::max(ccw, cw)};
+        }
+        std::vector<int64_t> order(mdeg);
+        for (int64_t k = 0; k < mdeg; ++k) order[k] = k;
+        std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return mem[x][0] < mem[y][0]; });
+        for (int64_t lab = 0; lab < mdeg; ++lab)
+            for (int64_t node : mem[order[lab]]) {
+                const int64_t s = node / 2;
+                const int sd = int(node % 2);
+                const int a = (Sin[2 * s] == v) ? 0 : 1;
+                m.sector[4 * s + 2 * a + sd] = int32_t(lab);
+            }
+        m.q[v] = int32_t(mdeg);
+    }
+    // dofs and jump coefficients, as for triangles
+    m.first_dof.assign(nv + 1, 0);
+    for (int64_t v = 0; v < nv; ++v) m.first_dof[v + 1] = m.first_dof[v] + std::max(0, m.q[v] - 1);
+    m.N = m.first_dof[nv];
+    m.dof_vertex.resize(m.N);
+    m.dof_sector.resize(m.N);
+    for (int64_t v = 0; v < nv; ++v)
+        for (int64_t d = m.first_dof[v]; d < m.first_dof[v + 1]; ++d) {
+            m.dof_vertex[d] = int32_t(v);
+            m.dof_sector[d] = int32_t(d - m.first_dof[v]);
+        }
+    auto coeff = [&](int64_t s, int a, int32_t j) {
+        const int32_t qv = m.q[Sin[2 * s + a]];
+        const int32_t sp = m.sector[4 * s + 2 * a], sm = m.sector[4 * s + 2 * a + 1];
+        return ((sp == j) ? 1 : (sp == qv - 1 ? -1 : 0)) - ((sm == j) ? 1 : (sm == qv - 1 ? -1 : 0));
+    };
+    m.tri_ptr.assign(ns + 1, 0);
+    for (int64_t s = 0; s < ns; ++s) {
+        int64_t cnt = 0;
+        for (int a = 0; a < 2; ++a)
+            for (int32_t j = 0; j + 1 < m.q[Sin[2 * s + a]]; ++j) cnt += coeff(s, a, j) != 0;
+        m.tri_ptr[s + 1] = m.tri_ptr[s] + cnt;
+    }
+    const int64_t ne = m.tri_ptr[ns];
+    m.tri_dof.resize(ne); m.tri_corner.resize(ne); m.tri_c.resize(ne);
+    for (int64_t s = 0; s < ns; ++s) {
+        int64_t pos = m.tri_ptr[s];
+        for (int a = 0; a < 2; ++a) {
+            const int32_t v = Sin[2 * s + a];
+            for (int32_t j = 0; j + 1 < m.q[v]; ++j) {
+                const int c = coeff(s, a, j);
+                if (c == 0) continue;
+                m.tri_dof[pos] = int32_t(m.first_dof[v] + j);
+                m.tri_corner[pos] = int8_t(a);
+                m.tri_c[pos] = int8_t(c);
+                ++pos;
+            }
+        }
+    }
+    m.dof_ptr.assign(m.N + 1, 0);
+    for (int64_t e = 0; e < ne; ++e) ++m.dof_ptr[m.tri_dof[e] + 1];
+    for (int64_t d = 0; d < m.N; ++d) m.dof_ptr[d + 1] += m.dof_ptr[d];
+    m.dof_tri.resize(ne); m.dof_corner.resize(ne); m.dof_c.resize(ne);
+    std::vector<int64_t> fill(m.dof_ptr.begin(), m.dof_ptr.end() - 1);
+    for (int64_t s = 0; s < ns; ++s)
+        for (int64_t e = m.tri_ptr[s]; e < m.tri_ptr[s + 1]; ++e) {
+            const int64_t pos = fill[m.tri_dof[e]]++;
+            m.dof_tri[pos] = int32_t(s);
+            m.dof_corner[pos] = m.tri_corner[e];
+            m.dof_c[pos] = m.tri_c[e];
+        }
+}
+
 void build_near_list(const MeshTopo& m, NearList& out) {
     out = NearList();
     const int64_t nt = m.nt, nv = m.nv;

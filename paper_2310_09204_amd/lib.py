@@ -41,7 +41,7 @@ class ProblemInfo(ctypes.Structure):
                 ("n_near_pairs", ctypes.c_int64), ("bytes_device", ctypes.c_int64),
                 ("q_hist", ctypes.c_int64 * 16), ("t_assemble_s", ctypes.c_double),
                 ("t_far_s", ctypes.c_double), ("t_near_s", ctypes.c_double), ("t_contract_s", ctypes.c_double),
-                ("t_host_s", ctypes.c_double), ("n_pair_panels", ctypes.c_int64)]
+                ("t_host_s", ctypes.c_double), ("n_pair_panels", ctypes.c_int64), ("dim", ctypes.c_int64)]
 
 
 class PrecondOpts(ctypes.Structure):
@@ -91,6 +91,8 @@ SIGNATURES = {
     "bem_ctx_synchronize": (_ci, [_vp]),
     "bem_ctx_release_cached": (_ci, [_vp]),
     "bem_double_layer": (_ci, [_vp, _vp, _i32, _vp, _i64, _vp]),
+    "bem_assemble_2d": (_ci, [_vp, _vp, _i64, _vp, _i64, _vp, ctypes.POINTER(_vp)]),
+    "bem_mesh_analyze_2d": (_ci, [_vp, _i64, _vp, _i64, ctypes.POINTER(_i64), _vp, _vp, _vp, _vp]),
     "bem_problem_bench_matvec": (_ci, [_vp, _ci, _i32, _ci, ctypes.POINTER(ctypes.c_double)]),
     "bem_mesh_analyze": (_ci, [_vp, _i64, _vp, _i64, ctypes.POINTER(_i64), _vp, _vp, _vp]),
     "bem_assemble": (_ci, [_vp, _vp, _i64, _vp, _i64, ctypes.POINTER(AssembleOpts), ctypes.POINTER(_vp)]),
@@ -263,7 +265,7 @@ class Problem:
 
     def jump_values(self, phi):
         phi = _f64(phi)
-        out = np.empty((self.T.shape[0], 3))
+        out = np.empty((self.T.shape[0], self.T.shape[1]))   # corners of a triangle / ends of a segment
         _check(load().bem_jump_values(self._h, _p(phi), _p(out)))
         return out
 
@@ -309,6 +311,51 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+
+def mesh_analyze_2d(V, S, coefficients=False):
+    """Host-only segment-mesh analysis: dict(n_dofs, dof_vertex, dof_sector, q[, c[ns][2][N]])."""
+    V, S = _f64(V), _i32a(S)
+    n = ctypes.c_int64()
+    _check(load().bem_mesh_analyze_2d(_p(V), V.shape[0], _p(S), S.shape[0], ctypes.byref(n), None, None, None, None))
+    dv, ds, q = np.empty(n.value, np.int32), np.empty(n.value, np.int32), np.empty(V.shape[0], np.int32)
+    c = np.empty((S.shape[0], 2, n.value)) if coefficients else None
+    _check(load().bem_mesh_analyze_2d(_p(V), V.shape[0], _p(S), S.shape[0], ctypes.byref(n), _p(dv), _p(ds), _p(q),
+                                      _p(c) if coefficients else None))
+    out = {"n_dofs": n.value, "dof_vertex": dv, "dof_sector": ds, "q": q}
+    if coefficients:
+        out["c"] = c
+    return out
+
+
+class Problem2D(Problem):
+    """bem_assemble_2d: a segment multiscreen in the plane (vertices nv x 2, segments ns x 2)."""
+
+    def __init__(self, ctx: Context, V, S, precision=FP64):
+        self.ctx = ctx
+        self.V, self.T = _f64(V), _i32a(S)
+        if self.V.shape[1] != 2 or self.T.shape[1] != 2:
+            raise ValueError("vertices must be nv x 2 and segments ns x 2")
+        o = AssembleOpts(precision, 0, 0, 0)
+        self._h = ctypes.c_void_p()
+        _check(load().bem_assemble_2d(ctx.handle, _p(self.V), self.V.shape[0], _p(self.T), self.T.shape[0],
+                                      ctypes.byref(o), ctypes.byref(self._h)))
+        self.info = self.get_info()
+        self.N = self.info["n_dofs"]
+
+    def solve(self, g=None, **kw):
+        """As Problem.solve; g may be given as 2-vectors."""
+        if g is not None:
+            g = np.atleast_2d(np.asarray(g, dtype=np.float64))
+            if g.shape[1] == 2:
+                g = np.concatenate([g, np.zeros((g.shape[0], 1))], axis=1)
+        return super().solve(g=g, **kw)
+
+    def rhs(self, g):
+        g = np.atleast_2d(np.asarray(g, dtype=np.float64))
+        if g.shape[1] == 2:
+            g = np.concatenate([g, np.zeros((g.shape[0], 1))], axis=1)
+        return super().rhs(g)
 
 
 class Preconditioner:

@@ -1,0 +1,77 @@
+"""GPU two-dimensional variant (segment multiscreens) against the oracle, through the C-ABI."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2310_09204_amd import lib, meshes
+from oracle.solve import cholesky_solve
+from oracle.twod import Topology2D, assemble, cross_exact, double_layer, rhs
+
+pytestmark = pytest.mark.gpu
+
+
+def _tree():
+    V = np.array([[0, 0], [1, 0], [0.3, 0.9], [-0.8, 0.4], [-0.5, -0.7], [0.6, -0.6], [1.5, 0.4], [2.0, 0.0]], float)
+    S = np.array([[0, 1], [2, 0], [0, 3], [4, 0], [0, 5], [1, 6], [7, 6]], np.int32)
+    return V, S
+
+
+MESHES = {"plus6": lambda: meshes.plus2d(6), "threefold5": lambda: meshes.threefold2d(5),
+          "graded": lambda: meshes.plus2d(6, grading=2.0), "tree": _tree}
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_matrix_rhs_and_solution_match_oracle(ctx, name):
+    V, S = MESHES[name]()
+    print("case", name, flush=True)
+    p = lib.Problem2D(ctx, V, S)
+    t = Topology2D(V, S)
+    Wo = assemble(t)
+    Wg = p.matrix()
+    assert p.N == t.N and p.info["dim"] == 2
+    assert np.array_equal(Wg, Wg.T)
+    assert np.abs(Wg - Wo).max() < 1e-12 * np.abs(Wo).max()
+    g = np.array([[0.3, -0.8], [1.0, 2.0]])
+    Lo = rhs(t, g).T
+    assert np.abs(p.rhs(g) - Lo).max() < 1e-13 * np.abs(Lo).max()
+    phi, info, rc = p.solve(g=g, precond=None, tol=1e-13)
+    assert rc == 0
+    for c in range(2):
+        xs = cholesky_solve(Wo, Lo[c])
+        assert np.linalg.norm(phi[c] - xs) / np.linalg.norm(xs) < 1e-10
+        assert np.abs(p.jump_values(phi[c]) - t.jump_values(phi[c])).max() < 1e-13 * np.abs(phi[c]).max()
+
+
+
+
+def test_experiment1_field_error_first_order(ctx):
+    # Experiment 1 (plus-shaped cross, g = (0, -1/2)): the vertical arm carries no jump, and the
+    # discrete l2 error of U_h on a grid around the cross falls at first order in h
+    grid = np.linspace(-1.5, 1.5, 31) + 0.0123
+    X = np.array([(a, b) for a in grid for b in grid])
+    exact = cross_exact(X)
+    errs = []
+    for n in (8, 16, 32, 64):
+        V, S = meshes.plus2d(n)
+        p = lib.Problem2D(ctx, V, S)
+        phi, info, rc = p.solve(g=np.array([0.0, -0.5]), precond=None, tol=1e-12)
+        assert rc == 0
+        t = Topology2D(V, S)
+        J = p.jump_values(phi[0])
+        vert = np.abs(V[S[:, 0], 0]) + np.abs(V[S[:, 1], 0]) < 1e-12
+        assert np.abs(J[vert]).max() < 1e-9 * np.abs(J).max()
+        U = double_layer(t, J, X)
+        errs.append(math.sqrt(np.mean((U - exact) ** 2)))
+        p.close()
+    rates = [math.log(errs[i] / errs[i + 1]) / math.log(2.0) for i in range(3)]
+    assert all(0.8 < r < 1.5 for r in rates) and errs[-1] < 2e-3, (errs, rates)
+
+
+def test_mixed_precision_2d(ctx):
+    V, S = meshes.threefold2d(40)
+    p = lib.Problem2D(ctx, V, S, precision=lib.FP32_REFINE)
+    ref, _, _ = p.solve(g=np.array([1.0, 2.0]), precond=None, tol=1e-13)
+    phi, info, rc = p.solve(g=np.array([1.0, 2.0]), precond=None, tol=1e-11, precision=lib.FP32_REFINE)
+    assert rc == 0
+    assert np.linalg.norm(phi - ref) / np.linalg.norm(ref) < 1e-8

@@ -106,7 +106,7 @@ class AdditiveSchwarz:
     survives a pointwise scalar product on the wire basket)."""
 
     def __init__(self, W, topo: Topology, patch_of_triangle=None, coarse_V=None, coarse_T=None,
-                 coarse_of_triangle=None, face_sets=None, wb=None, use_coarse=True, wirebasket="exact"):
+                 coarse_of_triangle=None, face_sets=None, wb=None, use_coarse=True, wirebasket="exact", RH=None):
         if face_sets is None:
             face_sets, wb = classify_dofs(topo, patch_of_triangle)
         if wirebasket not in ("exact", "diagonal"):
@@ -119,7 +119,11 @@ class AdditiveSchwarz:
         if wirebasket == "diagonal" and len(wb):
             self.wb_diag = (np.asarray(wb), 1.0 / np.diag(W)[wb])
         self.RH = None
-        if use_coarse and coarse_V is not None:
+        if use_coarse and RH is not None:           # a coarse space given directly (segment meshes)
+            self.RH = np.asarray(RH)
+            self.WH = self.RH @ W @ self.RH.T
+            self.WH_f = sla.cho_factor(self.WH, lower=True)
+        elif use_coarse and coarse_V is not None:
             self.RH, self.coarse_topo = coarse_prolongation(topo, coarse_V, coarse_T, coarse_of_triangle)
             if self.RH.shape[0] > 0:
                 self.WH = self.RH @ W @ self.RH.T

@@ -212,3 +212,68 @@ def cross_exact(X):
     z = X[:, 0] + 1j * X[:, 1]
     w = z + np.sqrt(z - 1) * np.sqrt(z + 1)
     return np.real(-1.0 / (2j * w))
+
+
+def classify_dofs_2d(topo: Topology2D, patch_of_segment):
+    """Face dofs of patch P: dofs at vertices whose segments all lie in P and with q = 2; the rest
+    form the wire basket (eq. jumpSplit in two dimensions)."""
+    patch = np.asarray(patch_of_segment)
+    seen = {}
+    for s in range(topo.ns):
+        for a in range(2):
+            v = int(topo.S[s, a])
+            p = int(patch[s]) if patch[s] >= 0 else -2
+            seen[v] = p if seen.get(v, p) == p else -2
+    faces = defaultdict(list)
+    wb = []
+    for d, (v, j) in enumerate(topo.dofs):
+        if seen.get(v, -2) >= 0 and topo.q[v] == 2:
+            faces[seen[v]].append(d)
+        else:
+            wb.append(d)
+    return [faces[k] for k in sorted(faces)], wb
+
+
+def coarse_prolongation_2d(fine: Topology2D, coarse: Topology2D, parent):
+    """R_H (n_H x N): row (i, j) holds the fine coefficients of the coarse jump basis function
+    psi^H_{i,j}.  On a coarse segment its traces are the coarse hat functions times the trace signs
+    of psi^H_{i,j} at that end; at a fine vertex the per-sector values u_l give the coefficients
+    u_l - mean(u) (the representative of the jump with sector values summing to zero)."""
+    parent = np.asarray(parent)
+    R = np.zeros((coarse.N, fine.N))
+    # sector values of every coarse dof at every fine vertex
+    vals = defaultdict(lambda: np.zeros(coarse.N))   # (fine vertex, fine sector) -> row over coarse dofs
+    for s in range(fine.ns):
+        S = int(parent[s])
+        C0, C1 = coarse.V[coarse.S[S, 0]], coarse.V[coarse.S[S, 1]]
+        same = float(fine.tangent[s] @ coarse.tangent[S]) > 0
+        for a in range(2):
+            v = int(fine.S[s, a])
+            x = fine.V[v]
+            l1 = float((x - C0) @ (C1 - C0)) / float((C1 - C0) @ (C1 - C0))
+            lam = (1.0 - l1, l1)
+            for side in range(2):
+                key = (v, int(fine.side_sector[s, a, side]))
+                if key in vals and vals[key].any():
+                    continue
+                cs = side if same else 1 - side
+                row = np.zeros(coarse.N)
+                for A in range(2):
+                    if abs(lam[A]) < 1e-12:
+                        continue
+                    i = int(coarse.S[S, A])
+                    qi = int(coarse.q[i])
+                    jc = int(coarse.side_sector[S, A, cs])
+                    for j in range(qi - 1):
+                        sign = 1.0 if jc == j else (-1.0 if jc == qi - 1 else 0.0)
+                        row[int(coarse.first_dof[i]) + j] += lam[A] * sign
+                vals[key] = row
+    for v in range(fine.nv):
+        q = int(fine.q[v])
+        if q < 2:
+            continue
+        U = np.stack([vals[(v, l)] if (v, l) in vals else np.zeros(coarse.N) for l in range(q)])   # q x nH
+        coef = U - U.mean(axis=0)[None, :]
+        for l in range(q - 1):
+            R[:, int(fine.first_dof[v]) + l] = coef[l]
+    return R

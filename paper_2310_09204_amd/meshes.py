@@ -656,3 +656,16 @@ def slit2d(n: int):
     V = np.stack([x, np.zeros_like(x)], axis=1)
     S = np.stack([np.arange(2 * n), np.arange(1, 2 * n + 1)], axis=1).astype(np.int32)
     return V, S
+
+
+def arms2d_coarse(kind: str, n: int, ratio: int):
+    """Nested coarse mesh of plus2d(n) / threefold2d(n): the same arms with n // ratio segments,
+    and coarse_of_segment (fine segment k of an arm lies in coarse segment k // ratio)."""
+    if n % ratio:
+        raise ValueError("ratio must divide n")
+    gen = {"plus": plus2d, "threefold": threefold2d}[kind]
+    V, S = gen(n)
+    cV, cS = gen(n // ratio)
+    arms = S.shape[0] // n
+    parent = np.array([a * (n // ratio) + k // ratio for a in range(arms) for k in range(n)], dtype=np.int32)
+    return (V, S), (cV, cS), parent

@@ -111,3 +111,55 @@ def test_double_layer_constant_jump_is_the_angle():
     U = double_layer(t, np.ones((t.ns, 2)), X)
     ang = np.array([math.atan2(x[1], x[0] - 1.0) - math.atan2(x[1], x[0] + 1.0) for x in X])
     assert np.abs(U - ang / (2 * math.pi)).max() < 1e-9
+
+
+def test_coarse_prolongation_2d():
+    # the fine jumps of a prolongated coarse basis function are the coarse jumps interpolated by the
+    # coarse hat functions (taken towards each fine segment's normal); with ratio 1 R_H = identity
+    from oracle.twod import coarse_prolongation_2d
+    for kind, n, r in (("threefold", 8, 4), ("plus", 6, 2)):
+        (V, S), (cV, cS), par = meshes.arms2d_coarse(kind, n, r)
+        f, c = Topology2D(V, S), Topology2D(cV, cS)
+        R = coarse_prolongation_2d(f, c, par)
+        for i in range(c.N):
+            Jf = f.jump_values(R[i])
+            e = np.zeros(c.N)
+            e[i] = 1.0
+            Jc = c.jump_values(e)
+            for s in range(f.ns):
+                C0, C1 = cV[cS[par[s], 0]], cV[cS[par[s], 1]]
+                sg = 1.0 if f.tangent[s] @ c.tangent[par[s]] > 0 else -1.0
+                for a in range(2):
+                    l1 = (V[S[s, a]] - C0) @ (C1 - C0) / ((C1 - C0) @ (C1 - C0))
+                    assert abs(Jf[s, a] - sg * ((1 - l1) * Jc[par[s], 0] + l1 * Jc[par[s], 1])) < 1e-12
+    (V, S), (cV, cS), par = meshes.arms2d_coarse("threefold", 4, 1)
+    R = coarse_prolongation_2d(Topology2D(V, S), Topology2D(cV, cS), par)
+    assert np.abs(R - np.eye(R.shape[0])).max() < 1e-14
+
+
+def test_experiment2_condition_growth():
+    # threefold junction, faces = coarse segments: kappa(P_ad W) grows with H/h no faster than
+    # (1 + log(H/h))^2 and hardly depends on H at fixed H/h; kappa(W) grows like 1/h
+    from oracle.precond import AdditiveSchwarz
+    from oracle.solve import spectral_cond
+    from oracle.twod import classify_dofs_2d, coarse_prolongation_2d
+    k = {}
+    for nc in (2, 4):
+        for r in (2, 4, 8, 16):
+            (V, S), (cV, cS), par = meshes.arms2d_coarse("threefold", nc * r, r)
+            f, c = Topology2D(V, S), Topology2D(cV, cS)
+            W = assemble(f)
+            faces, wb = classify_dofs_2d(f, par)
+            assert len(faces) == 3 * nc and len(wb) == 3 * (nc - 1) + 2
+            P = AdditiveSchwarz(W, None, face_sets=faces, wb=wb, RH=coarse_prolongation_2d(f, c, par))
+            Md = P.dense(f.N)
+            k[(nc, r)] = (spectral_cond(W, 0.5 * (Md + Md.T)), spectral_cond(W))
+    for nc in (2, 4):
+        kp = [k[(nc, r)][0] for r in (2, 4, 8, 16)]
+        assert kp[1] <= kp[2] <= kp[3]
+        ratio = [kp[i] / (1 + math.log(r)) ** 2 for i, r in enumerate((2, 4, 8, 16))]
+        assert max(ratio) < 1.0
+    for r in (2, 4, 8, 16):
+        assert abs(k[(2, r)][0] - k[(4, r)][0]) < 0.1 * k[(2, r)][0]
+    slope = math.log(k[(2, 16)][1] / k[(2, 2)][1]) / math.log(8.0)
+    assert 0.7 < slope < 1.2

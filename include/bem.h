@@ -178,7 +178,7 @@ int bem_jump_values(const bem_problem* p, const double* phi, double* jump_out);
  * diagonal with the singular factor integrated exactly.  The problem works with bem_pcg_solve
  * (g[k][3] with g_z ignored: L_d = -sum_s (g . n_s) |s| / 2 (c_{s,0,d} + c_{s,1,d})),
  * bem_pcg_solve_rhs, bem_rhs, bem_matvec, bem_problem_copy_matrix, bem_problem_rows,
- * bem_jump_values, bem_problem_bench_matvec and bem_precond_setup_sets; bem_precond_setup and
+ * bem_jump_values, bem_problem_bench_matvec and bem_precond_setup_2d; bem_precond_setup and
  * bem_double_layer reject it.  opts: precision as for bem_assemble (near_order is not used).
  * Errors: BEM_E_INVALID_ARG (NULL, index out of range, non-finite coordinate), BEM_E_DEGENERATE
  * (zero length), BEM_E_MESH_NONCONFORMING (repeated or overlapping segments), BEM_E_OOM,
@@ -190,6 +190,18 @@ int bem_mesh_analyze_2d(const double* vertices, int64_t nv, const int32_t* segme
                         int32_t* dof_vertex, int32_t* dof_sector, int32_t* q, double* c);
 int bem_assemble_2d(bem_ctx* ctx, const double* vertices, int64_t nv, const int32_t* segments, int64_t ns,
                     const bem_assemble_opts* opts, bem_problem** out);
+
+/* The substructuring preconditioner of bem_precond_setup for a segment mesh (eq. jumpSplit in two
+ * dimensions): face dofs of patch P are the dofs at vertices whose segments all have
+ * patch_of_segment == P and with q = 2, the rest is the wire basket, and the coarse space is the
+ * jump space of the nested coarse segment mesh (coarse_vertices[ncv][2], coarse_segments[ncs][2]),
+ * coarse_of_segment[s] being the coarse segment that contains fine segment s.  The coarse jump
+ * basis is written in the fine basis from the coarse hat functions, minus the mean over the
+ * sectors at each fine vertex.  Options, errors and the result as for bem_precond_setup; the
+ * problem must come from bem_assemble_2d. */
+int bem_precond_setup_2d(bem_problem* p, const int32_t* patch_of_segment, const double* coarse_vertices, int64_t ncv,
+                         const int32_t* coarse_segments, int64_t ncs, const int32_t* coarse_of_segment,
+                         const bem_precond_opts* opts, bem_precond** out);
 
 /* ---- double-layer potential (Lemma repDL, eq. formulaDL) --------------------------------- */
 /* U_c(x_i) = sum_T int_T n_T . (x_i - y) / (4 pi |x_i - y|^3) [u_c]_T(y) dsigma(y) for the solution

@@ -601,7 +601,7 @@ int bem_precond_setup(bem_problem* p, const int32_t* patch_of_triangle, const do
     BEM_TRY
     if (!p || !out) fail(BEM_E_INVALID_ARG, "NULL argument");
     *out = nullptr;
-    if (p->topo.dim != 3) fail(BEM_E_INVALID_ARG, "bem_precond_setup needs a triangle mesh; use bem_precond_setup_sets");
+    if (p->topo.dim != 3) fail(BEM_E_INVALID_ARG, "bem_precond_setup needs a triangle mesh; use bem_precond_setup_2d");
     set_device(p->ctx);
     std::unique_ptr<bem_precond> m(new bem_precond());
     m->p = p;
@@ -610,6 +610,26 @@ int bem_precond_setup(bem_problem* p, const int32_t* patch_of_triangle, const do
     if (opts && (opts->wirebasket < 0 || opts->wirebasket > 1)) fail(BEM_E_INVALID_ARG, "wirebasket must be 0 or 1");
     m->wb_diag = opts ? opts->wirebasket == 1 : false;
     precond_setup_device(m.get(), patch_of_triangle, coarse_vertices, ncv, coarse_triangles, nct, coarse_of_triangle);
+    *out = m.release();
+    return BEM_OK;
+    BEM_CATCH
+}
+
+int bem_precond_setup_2d(bem_problem* p, const int32_t* patch_of_segment, const double* coarse_vertices, int64_t ncv,
+                         const int32_t* coarse_segments, int64_t ncs, const int32_t* coarse_of_segment,
+                         const bem_precond_opts* opts, bem_precond** out) {
+    BEM_TRY
+    if (!p || !out) fail(BEM_E_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    if (p->topo.dim != 2) fail(BEM_E_INVALID_ARG, "bem_precond_setup_2d needs a segment mesh");
+    set_device(p->ctx);
+    std::unique_ptr<bem_precond> m(new bem_precond());
+    m->p = p;
+    m->use_coarse = opts ? opts->use_coarse != 0 : true;
+    m->fp32 = opts ? opts->factor_fp32 != 0 : false;
+    if (opts && (opts->wirebasket < 0 || opts->wirebasket > 1)) fail(BEM_E_INVALID_ARG, "wirebasket must be 0 or 1");
+    m->wb_diag = opts ? opts->wirebasket == 1 : false;
+    precond_setup_device(m.get(), patch_of_segment, coarse_vertices, ncv, coarse_segments, ncs, coarse_of_segment);
     *out = m.release();
     return BEM_OK;
     BEM_CATCH

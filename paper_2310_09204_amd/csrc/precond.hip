@@ -624,6 +624,92 @@ void build_prolongation(const MeshTopo& f, const MeshTopo& c, const int32_t* par
         }
 }
 
+// Segment meshes: the same rows of R_H, with the coarse hat function on the coarse segment that
+// contains the fine vertex (its two ends' barycentric weights) in place of the triangle's three.
+void build_prolongation_2d(const MeshTopo& f, const MeshTopo& c, const int32_t* parent, CoarseCSR& R) {
+    const int64_t ns = f.nt;
+    std::vector<int64_t> soff(f.nv + 1, 0);
+    for (int64_t v = 0; v < f.nv; ++v) soff[v + 1] = soff[v] + f.q[v];
+    std::vector<int64_t> rep(soff[f.nv], -1);   // representative side (s, end a, side) per fine sector
+    for (int64_t t = 0; t < ns; ++t)
+        for (int a = 0; a < 2; ++a)
+            for (int sd = 0; sd < 2; ++sd) {
+                const int64_t v = f.S[2 * t + a];
+                const int64_t slot = soff[v] + f.sector[4 * t + 2 * a + sd];
+                if (rep[slot] < 0) rep[slot] = 4 * t + 2 * a + sd;
+            }
+    struct Entry { int32_t i, col; double v; };
+    std::vector<Entry> out;
+    struct Acc { int64_t dof; double u[64]; };
+    std::vector<Acc> u;
+    for (int64_t k = 0; k < f.nv; ++k) {
+        const int qk = f.q[k];
+        if (qk < 2) continue;
+        if (qk > 64) fail(BEM_E_UNSUPPORTED, "more than 64 sectors at a vertex");
+        u.clear();
+        for (int l = 0; l < qk; ++l) {
+            const int64_t node = rep[soff[k] + l];
+            const int64_t t = node / 4;
+            const int sd = int(node % 2);
+            const int64_t tc = parent[t];
+            // fine and coarse tangents agree or are opposite; the side labels follow the normal
+            const double dot = f.normal[3 * t] * c.normal[3 * tc] + f.normal[3 * t + 1] * c.normal[3 * tc + 1];
+            const int sc = dot > 0 ? sd : 1 - sd;
+            const double* P0 = &c.V[3 * int64_t(c.S[2 * tc])];
+            const double* P1 = &c.V[3 * int64_t(c.S[2 * tc + 1])];
+            const double e0 = P1[0] - P0[0], e1 = P1[1] - P0[1];
+            const double L2 = e0 * e0 + e1 * e1;
+            const double r0 = f.V[3 * k] - P0[0], r1 = f.V[3 * k + 1] - P0[1];
+            const double l1 = (r0 * e0 + r1 * e1) / L2;
+            const double off = r0 * e1 - r1 * e0;   // distance from the coarse segment's line, times its length
+            if (l1 < -1e-9 || l1 > 1.0 + 1e-9 || off * off > 1e-18 * L2 * L2)
+                fail(BEM_E_INVALID_ARG, "fine segment " + std::to_string(t) + " is not inside its coarse segment");
+            const double lam[2] = {1.0 - l1, l1};
+            for (int ac = 0; ac < 2; ++ac) {
+                if (std::fabs(lam[ac]) < 1e-12) continue;
+                const int64_t i = c.S[2 * tc + ac];
+                const int qi = c.q[i];
+                const int jc = c.sector[4 * tc + 2 * ac + sc];
+                for (int j = 0; j + 1 < qi; ++j) {
+                    const double sign = (jc == j) ? 1.0 : (jc == qi - 1 ? -1.0 : 0.0);
+                    if (sign == 0.0) continue;
+                    const int64_t dof = c.first_dof[i] + j;
+                    Acc* a = nullptr;
+                    for (auto& x : u) if (x.dof == dof) { a = &x; break; }
+                    if (!a) {
+                        u.push_back(Acc{dof, {}});
+                        a = &u.back();
+                        for (int q = 0; q < qk; ++q) a->u[q] = 0.0;
+                    }
+                    a->u[l] += lam[ac] * sign;
+                }
+            }
+        }
+        std::sort(u.begin(), u.end(), [](const Acc& x, const Acc& y) { return x.dof < y.dof; });
+        for (auto& a : u) {
+            double mean = 0;
+            for (int q = 0; q < qk; ++q) mean += a.u[q];
+            mean /= qk;
+            for (int l = 0; l + 1 < qk; ++l) {
+                const double cv = a.u[l] - mean;
+                if (cv != 0.0) out.push_back(Entry{int32_t(a.dof), int32_t(f.first_dof[k] + l), cv});
+            }
+        }
+    }
+    R.nH = c.N;
+    R.ptr.assign(c.N + 1, 0);
+    for (auto& e : out) R.ptr[e.i + 1] += 1;
+    for (int64_t i = 0; i < c.N; ++i) R.ptr[i + 1] += R.ptr[i];
+    R.col.assign(size_t(R.ptr[c.N]), 0);
+    R.val.assign(size_t(R.ptr[c.N]), 0.0);
+    std::vector<int64_t> fill(R.ptr.begin(), R.ptr.end() - 1);
+    for (auto& e : out) {
+        const int64_t at = fill[e.i]++;
+        R.col[size_t(at)] = e.col;
+        R.val[size_t(at)] = e.v;
+    }
+}
+
 }  // namespace
 
 void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV, int64_t ncv, const int32_t* cT,
@@ -646,9 +732,11 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
 
     // ---- dof classes ---------------------------------------------------------------------------
     std::vector<int64_t> vpatch(f.nv, -1);   // -1 unseen, -2 several patches / no patch
+    const bool seg = f.dim == 2;              // segment mesh: 2 vertices per element
+    const int corners = seg ? 2 : 3;
     for (int64_t t = 0; t < f.nt; ++t)
-        for (int a = 0; a < 3; ++a) {
-            const int64_t v = f.T[3 * t + a];
+        for (int a = 0; a < corners; ++a) {
+            const int64_t v = seg ? f.S[2 * t + a] : f.T[3 * t + a];
             const int64_t pid = patch[t] < 0 ? -2 : patch[t];
             if (vpatch[v] == -1) vpatch[v] = pid;
             else if (vpatch[v] != pid) vpatch[v] = -2;
@@ -679,7 +767,8 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
         if (!cV || !cT || !parent) fail(BEM_E_INVALID_ARG, "coarse mesh arrays missing");
         for (int64_t t = 0; t < f.nt; ++t)
             if (parent[t] < 0 || parent[t] >= nct) fail(BEM_E_INVALID_ARG, "coarse_of_triangle out of range");
-        analyze_mesh(cV, ncv, cT, nct, c);
+        if (seg) analyze_segments(cV, ncv, cT, nct, c);   // cV: ncv x 2, cT: coarse segments nct x 2
+        else analyze_mesh(cV, ncv, cT, nct, c);
         M->nH = c.N;
     } else {
         M->nH = 0;
@@ -797,7 +886,8 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
     // coarse Galerkin block on the second stream, while the first one eliminates
     DeviceBuffer Z;
     if (M->nH > 0) {
-        build_prolongation(f, c, parent, R);
+        if (seg) build_prolongation_2d(f, c, parent, R);
+        else build_prolongation(f, c, parent, R);
         mark("prolongation");
         // transposed CSR (fine dof -> coarse dofs)
         std::vector<int64_t> tp(f.N + 1, 0);

@@ -106,6 +106,7 @@ SIGNATURES = {
     "bem_matvec": (_ci, [_vp, _vp, _i32, _ci, _vp]),
     "bem_jump_values": (_ci, [_vp, _vp, _vp]),
     "bem_precond_setup": (_ci, [_vp, _vp, _vp, _i64, _vp, _i64, _vp, ctypes.POINTER(PrecondOpts), ctypes.POINTER(_vp)]),
+    "bem_precond_setup_2d": (_ci, [_vp, _vp, _vp, _i64, _vp, _i64, _vp, ctypes.POINTER(PrecondOpts), ctypes.POINTER(_vp)]),
     "bem_precond_destroy": (None, [_vp]),
     "bem_precond_sizes": (_ci, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "bem_precond_apply": (_ci, [_vp, _vp, _i32, _vp]),
@@ -373,8 +374,11 @@ class Preconditioner:
             raise ValueError("wirebasket must be 'exact' or 'diagonal'")
         o = PrecondOpts(int(use_coarse), int(factor_fp32), int(wirebasket == "diagonal"))
         self._h = ctypes.c_void_p()
-        _check(load().bem_precond_setup(problem.handle, _p(self.patch), _p(self.cV), ncv, _p(self.cT), nct,
-                                        _p(self.par), ctypes.byref(o), ctypes.byref(self._h)))
+        # a segment-mesh problem takes coarse vertices n x 2 and coarse segments, patch and parent
+        # per segment
+        setup = load().bem_precond_setup_2d if isinstance(problem, Problem2D) else load().bem_precond_setup
+        _check(setup(problem.handle, _p(self.patch), _p(self.cV), ncv, _p(self.cT), nct,
+                     _p(self.par), ctypes.byref(o), ctypes.byref(self._h)))
 
     @property
     def handle(self):

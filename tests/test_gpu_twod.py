@@ -1,4 +1,5 @@
 """GPU two-dimensional variant (segment multiscreens) against the oracle, through the C-ABI."""
+import ctypes
 import math
 
 import numpy as np
@@ -75,3 +76,34 @@ def test_mixed_precision_2d(ctx):
     phi, info, rc = p.solve(g=np.array([1.0, 2.0]), precond=None, tol=1e-11, precision=lib.FP32_REFINE)
     assert rc == 0
     assert np.linalg.norm(phi - ref) / np.linalg.norm(ref) < 1e-8
+
+
+@pytest.mark.parametrize("kind,n,r", [("threefold", 16, 4), ("plus", 12, 3), ("threefold", 32, 16)])
+def test_precond_2d_matches_oracle(ctx, kind, n, r):
+    from oracle.precond import AdditiveSchwarz
+    from oracle.solve import lanczos_cond, pcg
+    from oracle.twod import classify_dofs_2d, coarse_prolongation_2d
+    (V, S), (cV, cS), par = meshes.arms2d_coarse(kind, n, r)
+    print("case", kind, n, r, flush=True)
+    p = lib.Problem2D(ctx, V, S)
+    M = lib.Preconditioner(p, par, cV, cS, par)
+    f, c = Topology2D(V, S), Topology2D(cV, cS)
+    W = assemble(f)
+    faces, wb = classify_dofs_2d(f, par)
+    P = AdditiveSchwarz(W, None, face_sets=faces, wb=wb, RH=coarse_prolongation_2d(f, c, par))
+    s = M.sizes()
+    assert s["n_faces"] == len(faces) and s["n_wb"] == len(wb) and s["n_coarse"] == c.N
+    rr = np.random.default_rng(3).standard_normal((2, f.N))
+    zg = M.apply(rr)
+    zo = np.stack([P.apply(x) for x in rr])
+    assert np.abs(zg - zo).max() < 1e-11 * np.abs(zo).max()
+    b = np.random.default_rng(4).standard_normal(f.N)
+    _, it_o, _, al, be = pcg(W, b, P.apply, tol=1e-12)
+    phi, info, rc = p.solve(rhs=b[None, :], precond=M, tol=1e-12)
+    assert rc == 0 and abs(info[0]["iters"] - it_o) <= 1
+    assert abs(info[0]["est_cond"] - lanczos_cond(al, be)) < 1e-3 * lanczos_cond(al, be)
+    # the triangle-mesh set-up refuses a segment mesh
+    o, h = lib.PrecondOpts(1, 0, 0), ctypes.c_void_p()
+    rc = lib.load().bem_precond_setup(p.handle, lib._p(np.asarray(par, np.int32)), None, 0, None, 0, None,
+                                      ctypes.byref(o), ctypes.byref(h))
+    assert lib.ERRORS[rc] == "BEM_E_INVALID_ARG"

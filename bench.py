@@ -241,6 +241,52 @@ def double_layer_leg(lib, w, ctx, m_targets=16384, k=16):
     return out
 
 
+def planar_leg(lib, meshes, ctx):
+    """Section 2's planar experiments on the GPU path.  Experiment 1: the plus-shaped cross with
+    g = (0, -1/2) on uniform and tip-graded meshes (grading 2, node k at 1 - (1 - k/n)^2 of an arm);
+    discrete l2 error of U_h against the exact field on a 61 x 61 grid over [-1.5, 1.5]^2 (shifted off
+    the arms), CG iterations and the time of assembly + solve.  Experiment 2: the threefold junction
+    with faces = coarse segments; Lanczos estimates of kappa(P_ad W) and kappa(W) over H and H/h."""
+    g = np.linspace(-1.5, 1.5, 61) + 0.0123
+    X = np.array([(a, b) for a in g for b in g])
+    exact = meshes.cross_solution(X)
+    exp1 = []
+    for grading in (1.0, 2.0):
+        for n in (16, 32, 64, 128, 256, 512):
+            V, S = meshes.plus2d(n, grading)
+            t0 = time.perf_counter()
+            p = lib.Problem2D(ctx, V, S)
+            phi, info, rc = p.solve(g=np.array([0.0, -0.5]), precond=None, tol=1e-12)
+            t1 = time.perf_counter()
+            U = p.double_layer(phi, X)[0]
+            exp1.append({"grading": grading, "segments_per_arm": n, "n_dofs": p.N, "cg_iters": info[0]["iters"],
+                         "t_assemble_solve_s": t1 - t0, "l2_error": float(np.sqrt(np.mean((U - exact) ** 2)))})
+            p.close()
+    exp2 = []
+    for nc in (2, 4, 8):
+        for r in (2, 4, 8, 16, 32):
+            if nc * r > 256:
+                continue
+            (V, S), (cV, cS), par = meshes.arms2d_coarse("threefold", nc * r, r)
+            p = lib.Problem2D(ctx, V, S)
+            M = lib.Preconditioner(p, par, cV, cS, par)
+            b = np.random.default_rng(nc * 100 + r).standard_normal((1, p.N))
+            _, info, _ = p.solve(rhs=b, precond=M, tol=1e-12)
+            _, info_cg, _ = p.solve(rhs=b, precond=None, tol=1e-12)
+            exp2.append({"coarse_segments_per_arm": nc, "H_over_h": r, "n_dofs": p.N,
+                         "kappa_pad": info[0]["est_cond"], "kappa_W": info_cg[0]["est_cond"],
+                         "pcg_iters": info[0]["iters"], "cg_iters": info_cg[0]["iters"]})
+            M.close()
+            p.close()
+    for e in exp1:
+        log("bench: planar cross grading %.0f n=%d N=%d error %.3e (%d CG iterations, %.1f ms)" %
+            (e["grading"], e["segments_per_arm"], e["n_dofs"], e["l2_error"], e["cg_iters"], e["t_assemble_solve_s"] * 1e3))
+    for e in exp2:
+        log("bench: threefold junction nH=%d H/h=%d kappa(P W)=%.3f kappa(W)=%.1f" %
+            (e["coarse_segments_per_arm"], e["H_over_h"], e["kappa_pad"], e["kappa_W"]))
+    return {"experiment1_cross": exp1, "experiment2_threefold": exp2}
+
+
 def kappa_study(lib, meshes, ctx):
     """Lanczos estimate of kappa(P_ad W) on the paper's three-dimensional experiment (two
     perpendicular equilateral triangles sharing a median) with faces = coarse triangles, over coarse
@@ -360,6 +406,7 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the crossed192 leg")
     ap.add_argument("--no-kappa", action="store_true", help="skip the condition-number study")
     ap.add_argument("--no-potential", action="store_true", help="skip the double-layer potential leg")
+    ap.add_argument("--no-planar", action="store_true", help="skip the two-dimensional experiments")
     ap.add_argument("--serve-load", type=float, default=0.7,
                     help="arrival rate of the serving leg as a fraction of its measured capacity")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -535,6 +582,8 @@ def main():
     }
     if not args.no_potential:
         out["double_layer"] = double_layer_leg(lib, w, ctx)
+    if not args.no_planar:
+        out["planar"] = planar_leg(lib, meshes, ctx)
     if not args.no_kappa:
         log("bench: condition-number study")
         out["kappa_study"] = kappa_study(lib, meshes, ctx)

@@ -178,8 +178,8 @@ int bem_jump_values(const bem_problem* p, const double* phi, double* jump_out);
  * diagonal with the singular factor integrated exactly.  The problem works with bem_pcg_solve
  * (g[k][3] with g_z ignored: L_d = -sum_s (g . n_s) |s| / 2 (c_{s,0,d} + c_{s,1,d})),
  * bem_pcg_solve_rhs, bem_rhs, bem_matvec, bem_problem_copy_matrix, bem_problem_rows,
- * bem_jump_values, bem_problem_bench_matvec and bem_precond_setup_2d; bem_precond_setup and
- * bem_double_layer reject it.  opts: precision as for bem_assemble (near_order is not used).
+ * bem_jump_values, bem_problem_bench_matvec, bem_double_layer and bem_precond_setup_2d;
+ * bem_precond_setup rejects it.  opts: precision as for bem_assemble (near_order is not used).
  * Errors: BEM_E_INVALID_ARG (NULL, index out of range, non-finite coordinate), BEM_E_DEGENERATE
  * (zero length), BEM_E_MESH_NONCONFORMING (repeated or overlapping segments), BEM_E_OOM,
  * BEM_E_DEVICE.  K takes ns^2 x 8 bytes of device memory during the call. */
@@ -211,8 +211,10 @@ int bem_precond_setup_2d(bem_problem* p, const int32_t* patch_of_segment, const 
  * screen.  The integral is the 7-point rule on every triangle: accurate for targets at least a few
  * mesh sizes from the screen, with no refinement closer in.  phi: host [k][N]; targets: host
  * [m][3]; u_out: host [k][m].  Per-triangle data are built on the first call and kept with the
- * problem.  Returns BEM_OK, or BEM_E_INVALID_ARG (NULL pointer, k < 1, m < 0, non-finite target),
- * BEM_E_OOM, BEM_E_DEVICE. */
+ * problem.  For a segment mesh (bem_assemble_2d): U_c(x) = sum_s int_s n_s . (x - y) /
+ * (2 pi |x - y|^2) [u_c]_s(y) dy with 8-point Gauss-Legendre on every segment, targets[m][3] with
+ * the third coordinate ignored.  Returns BEM_OK, or BEM_E_INVALID_ARG (NULL pointer, k < 1, m < 0,
+ * non-finite target), BEM_E_OOM, BEM_E_DEVICE. */
 int bem_double_layer(bem_problem* p, const double* phi, int32_t k, const double* targets, int64_t m,
                      double* u_out);
 

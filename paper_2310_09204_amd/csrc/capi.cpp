@@ -578,7 +578,6 @@ int bem_jump_values(const bem_problem* p, const double* phi, double* jump_out) {
 int bem_double_layer(bem_problem* p, const double* phi, int32_t k, const double* targets, int64_t m, double* u_out) {
     BEM_TRY
     if (!p || !phi || !targets || !u_out || k < 1 || m < 0) fail(BEM_E_INVALID_ARG, "bad argument");
-    if (p->topo.dim != 3) fail(BEM_E_INVALID_ARG, "the double-layer potential is for triangle meshes");
     for (int64_t i = 0; i < 3 * m; ++i)
         if (!std::isfinite(targets[i])) fail(BEM_E_INVALID_ARG, "non-finite target coordinate");
     set_device(p->ctx);

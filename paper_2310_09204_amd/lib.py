@@ -358,6 +358,13 @@ class Problem2D(Problem):
             g = np.concatenate([g, np.zeros((g.shape[0], 1))], axis=1)
         return super().rhs(g)
 
+    def double_layer(self, phi, targets):
+        """U[k][m] at plane targets[m][2]."""
+        X = np.atleast_2d(np.asarray(targets, dtype=np.float64))
+        if X.shape[1] == 2:
+            X = np.concatenate([X, np.zeros((X.shape[0], 1))], axis=1)
+        return super().double_layer(phi, X)
+
 
 class Preconditioner:
     def __init__(self, problem: Problem, patch_of_triangle, coarse_V=None, coarse_T=None, coarse_of_triangle=None,

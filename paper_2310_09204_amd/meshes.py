@@ -669,3 +669,13 @@ def arms2d_coarse(kind: str, n: int, ratio: int):
     arms = S.shape[0] // n
     parent = np.array([a * (n // ratio) + k // ratio for a in range(arms) for k in range(n)], dtype=np.int32)
     return (V, S), (cV, cS), parent
+
+
+def cross_solution(X):
+    """Experiment 1's reference field on the plus-shaped cross: U = Re(-1 / (2 i w)) with
+    z = x1 + i x2 = (w + 1/w) / 2, |w| > 1 (the potential of the dipole density sqrt(1 - x1^2) on the
+    horizontal arm; its Neumann data on the cross are those of the constant field g = (0, -1/2))."""
+    X = np.atleast_2d(np.asarray(X, dtype=np.float64))
+    z = X[:, 0] + 1j * X[:, 1]
+    w = z + np.sqrt(z - 1.0) * np.sqrt(z + 1.0)
+    return np.real(-1.0 / (2j * w))

@@ -107,3 +107,23 @@ def test_precond_2d_matches_oracle(ctx, kind, n, r):
     rc = lib.load().bem_precond_setup(p.handle, lib._p(np.asarray(par, np.int32)), None, 0, None, 0, None,
                                       ctypes.byref(o), ctypes.byref(h))
     assert lib.ERRORS[rc] == "BEM_E_INVALID_ARG"
+
+
+@pytest.mark.parametrize("name", ["plus6", "tree"])
+def test_double_layer_2d_matches_oracle(ctx, name):
+    V, S = MESHES[name]()
+    p = lib.Problem2D(ctx, V, S)
+    t = Topology2D(V, S)
+    phi = np.random.default_rng(2).standard_normal((3, p.N))
+    rng = np.random.default_rng(5)
+    X = []
+    while len(X) < 120:
+        x = rng.uniform(-2.5, 2.5, 2)
+        if np.linalg.norm(V - x, axis=1).min() > 0.2:
+            X.append(x)
+    X = np.array(X)
+    Ug = p.double_layer(phi, X)
+    Uo = np.stack([double_layer(t, t.jump_values(ph), X) for ph in phi])
+    assert np.abs(Ug - Uo).max() < 1e-12 * np.abs(Uo).max()
+    # the library's reference field of Experiment 1 is the oracle's
+    assert np.array_equal(meshes.cross_solution(X), cross_exact(X))

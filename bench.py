@@ -49,6 +49,23 @@ def far_kernel_source_hash():
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
+def symv_bytes(N, size):
+    """HBM bytes of one symmetric product with two or more columns: the upper block triangle of W
+    (64 x 64 blocks) plus the block-row partials written and read back (super-blocks of 8 blocks
+    for FP32 and 4 for FP64 matrices; one partial of 64 rows x 16 columns per block row and
+    super-tile, plus one)."""
+    nb = (N + 63) // 64
+    ks = 8 if size == 4 else 4
+    nst = (nb + ks - 1) // ks
+    return nb * (nb + 1) // 2 * 64 * 64 * size + 2 * nb * (nst + 1) * 1024 * size
+
+
+def matvec_rates(N, size, t, key):
+    """A k = 16 product's time, its HBM rate and the full-matrix equivalent rate (N^2 entries / t)."""
+    return {key + "_ms": t * 1e3, key + "_hbm_GBs": symv_bytes(N, size) / t / 1e9,
+            key + "_equiv_GBs": N * N * size / t / 1e9}
+
+
 def load_traffic(kernel, workload):
     """HBM bytes per launch from the committed rocprofv3 --pmc summary, if the kernel source is
     unchanged since the counters were taken; else None."""
@@ -378,7 +395,7 @@ def large_leg(lib, meshes, ctx, k=16):
                                 "relerr_max": float(errd.max()),
                                 "solves_per_s": int((errd <= 1e-8).sum()) / ((t1 - t0) + (t7 - t6) + (t8 - t7))},
         "pair_integrals_per_s": nt * (nt + 1) / 2 / (t1 - t0),
-        "matvec": {"fp32_k16_GBs": N * N * 4 / t32 / 1e9, "fp64_k16_GBs": N * N * 8 / t64 / 1e9},
+        "matvec": {**matvec_rates(N, 4, t32, "fp32_k16"), **matvec_rates(N, 8, t64, "fp64_k16")},
         "patches": M.sizes(),
     }
     M.close()
@@ -532,10 +549,10 @@ def main():
     t_far = float(np.mean([r["t_far"] for r in res]))
     far_pairs = pairs - pinfo["n_near_pairs"]
     far_tflops = far_pairs * EVALS_PER_FAR_PAIR * FLOPS_PER_EVAL / t_far / 1e12
-    mv = {"fp64_k1_GBs": N * N * 8 / t64_1 / 1e9, "fp64_k16_GBs": N * N * 8 / t64_16 / 1e9}
+    mv = {"fp64_k1_GBs": N * N * 8 / t64_1 / 1e9, **matvec_rates(N, 8, t64_16, "fp64_k16")}
     if mixed:
         mv["fp32_k1_GBs"] = N * N * 4 / t32_1 / 1e9
-        mv["fp32_k16_GBs"] = N * N * 4 / t32_16 / 1e9
+        mv.update(matvec_rates(N, 4, t32_16, "fp32_k16"))
     lat = sorted(r["t_step"] for r in res)
     roofline = {
         "kernel": "k_far",

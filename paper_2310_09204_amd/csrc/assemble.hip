@@ -1341,8 +1341,7 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
         ptimes = assemble_panels(p, m, near, plan, geo.as<double>(), gbounds.as<double>(), crec.as<double>(), dV.as<double>(),
                                  dgx.as<double>(), dgw.as<double>(), dofJ.as<double>(), w32, mark);
     }
-    p->mv_xt = DeviceBuffer(sizeof(double) * 16 * p->ldw, s);
-    p->mv_partial = DeviceBuffer(sizeof(double) * 16 * 16 * p->ldw, s);
+    matvec_setup(p, s);
     HIP_CHECK(hipStreamSynchronize(s));
     if (!p->has_pairs) p->I.reset();   // idle now: back to the cache
     p->t_far = paneled ? ptimes.far : t_far.seconds();

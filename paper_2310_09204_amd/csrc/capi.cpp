@@ -383,7 +383,7 @@ int bem_assemble(bem_ctx* ctx, const double* vertices, int64_t nv, const int32_t
     }
     p->bytes = int64_t(p->W64.bytes + p->W32.bytes + p->I.bytes + p->normal.bytes + p->area.bytes + p->dof_ptr.bytes +
                        p->dof_tri.bytes + p->dof_c.bytes + p->tri_ptr.bytes + p->tri_dof.bytes + p->tri_corner.bytes +
-                       p->tri_c.bytes);
+                       p->tri_c.bytes + p->mv_xt.bytes + p->mv_partial.bytes + p->mv_tiles[0].bytes + p->mv_tiles[1].bytes + p->mv_sym.bytes);
     p->t_assemble = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     *out = p.release();
     return BEM_OK;
@@ -436,7 +436,7 @@ int bem_assemble_2d(bem_ctx* ctx, const double* vertices, int64_t nv, const int3
     }
     p->bytes = int64_t(p->W64.bytes + p->W32.bytes + p->normal.bytes + p->area.bytes + p->dof_ptr.bytes +
                        p->dof_tri.bytes + p->dof_c.bytes + p->tri_ptr.bytes + p->tri_dof.bytes + p->tri_corner.bytes +
-                       p->tri_c.bytes);
+                       p->tri_c.bytes + p->mv_xt.bytes + p->mv_partial.bytes + p->mv_tiles[0].bytes + p->mv_tiles[1].bytes + p->mv_sym.bytes);
     p->t_assemble = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     *out = p.release();
     return BEM_OK;

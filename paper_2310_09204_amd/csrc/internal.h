@@ -199,9 +199,12 @@ struct bem_problem {
     bem::DeviceBuffer normal, area;         // per-triangle geometry for the right-hand side
     bem::DeviceBuffer dof_ptr, dof_tri, dof_c;  // dof -> triangle CSR
     bem::DeviceBuffer tri_ptr, tri_dof, tri_corner, tri_c;  // triangle -> dof CSR
-    // scratch of the multi-column product: transposed right-hand sides (ldw x 16, FP64-sized) and
-    // per-split partial sums (16 splits x 16 columns x ldw).  Calls on one problem must not overlap.
-    bem::DeviceBuffer mv_xt, mv_partial;
+    // scratch of the multi-column product: transposed right-hand sides (ldw x 16, FP64-sized),
+    // per-split partial sums (16 splits x 16 columns x ldw), and for the symmetric product the
+    // super-tile lists ([0] FP32, [1] FP64 matrix) and the block-row partials
+    // (ldw / 64 x (mv_nst + 1) x 1024 values).  Calls on one problem must not overlap.
+    bem::DeviceBuffer mv_xt, mv_partial, mv_tiles[2], mv_sym;
+    int64_t mv_nst[2] = {0, 0}, mv_ntiles[2] = {0, 0};
     // double-layer potential: per-triangle records (normal, Gauss points, n . y) and the 7-point rule,
     // built on the first evaluation
     bem::DeviceBuffer dl_rec, dl_rule;
@@ -225,6 +228,7 @@ void double_layer_device(bem_problem* p, const double* d_phi, int k, const doubl
                          hipStream_t s);
 
 // dense products (solver.hip); x, y column-major [k][N] with leading dimension ldx
+void matvec_setup(bem_problem* p, hipStream_t s);   // after W is allocated (ldw set)
 void matvec_device(const bem_problem* p, bool fp32, const double* d_x, int64_t ldx, int k,
                    double* d_y, hipStream_t s);
 

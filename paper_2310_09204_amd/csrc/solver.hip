@@ -178,6 +178,133 @@ __global__ __launch_bounds__(256) void k_matvec_mfma(const MT* __restrict__ W, i
     }
 }
 
+// Symmetric product Y = W X for up to 16 columns that reads only the upper half of W (the Galerkin
+// matrix of a symmetric bilinear form is symmetric).  The 64-row blocks are grouped into super-blocks
+// of KS = SymTile<MT>::K; a workgroup takes one super-tile (I, J), I <= J, and walks it column by
+// column (on a diagonal super-tile only the blocks on and above the diagonal).  Each 64 x 64 block
+// is read from HBM once and used twice:
+//  * rows of bi, W_bi,bj X_bj: through LDS as in the plain product (wave w: rows 16w .. 16w+15);
+//  * rows of bj, W_bi,bj^T X_bi (bi < bj): straight from the registers of the coalesced load.  Lane
+//    16 kg + j holds VEC consecutive columns of row r(kg); with the row as the summation index (k
+//    slot kg) and the column as the output index (lane j) every loaded vector feeds VEC matrix-core
+//    products, one per class of output columns.  Each wave sums over its own 16 rows of the block;
+//    the four wave sums are added through LDS once per block column.
+// Row sums of the super-tile's block rows are kept in LDS (one accumulator fragment per thread and
+// block row, carried through the matrix cores block after block) and column sums in registers,
+// each over at most KS * 64 products; each leaves once as a partial of its block row, in MT (exact
+// for FP32 accumulators).  k_symv_reduce adds the nst + 1 partials of each block row in FP64 in a
+// fixed order.  HBM traffic: half of W plus 1/KS of it in partials, written and read back.
+template <typename MT> struct SymTile { static constexpr int K = sizeof(MT) == 4 ? 8 : 4; };
+
+template <typename MT>
+__global__ __launch_bounds__(256) void k_symv_mfma(const MT* __restrict__ W, int64_t ldw, int64_t N, const MT* __restrict__ xt,
+                                                   int64_t nb, int64_t nst, const int2* __restrict__ tiles,
+                                                   MT* __restrict__ part) {
+    using MC = MatrixCore<MT>;
+    using V = typename MC::V;
+    using V16 = typename std::conditional<sizeof(MT) == 4, float4, double2>::type;
+    constexpr int KS = SymTile<MT>::K;
+    constexpr int VEC = 16 / sizeof(MT);
+    constexpr int HV = 64 / (16 * VEC);   // 16-lane segments per 64-column block row
+    constexpr int NL = 4 * HV * VEC;      // values of one block held by a thread
+    __shared__ MT tA[64][64 + VEC];
+    __shared__ V accl[KS][256];
+    const int2 tile = tiles[blockIdx.x];
+    const int64_t I = tile.x, J = tile.y;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int i = lane & 15, kg = lane >> 4;
+    const int64_t bi0 = I * KS, bi1 = min<int64_t>(nb, bi0 + KS);
+    const int64_t bj0 = J * KS, bj1 = min<int64_t>(nb, bj0 + KS);
+#pragma unroll
+    for (int p = 0; p < KS; ++p) accl[p][tid] = V{0, 0, 0, 0};   // own slots: no barrier needed
+    // thread (w, kg, i) loads rows 16 q + 4 w + kg (q < 4), columns 16 VEC h + VEC i .. + VEC - 1 (h < HV)
+    MT a[NL], xc[4];
+    auto fetch = [&](int64_t bi, int64_t bj) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t row = bi * 64 + 16 * q + 4 * w + kg;
+#pragma unroll
+            for (int h = 0; h < HV; ++h) {
+                V16 v{};
+                if (row < N) v = *reinterpret_cast<const V16*>(W + row * ldw + bj * 64 + 16 * VEC * h + VEC * i);
+                MT* d = a + (q * HV + h) * VEC;
+                if constexpr (VEC == 4) { d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w; }
+                else { d[0] = v.x; d[1] = v.y; }
+            }
+            xc[q] = xt[row * 16 + i];
+        }
+    };
+    fetch(bi0, bj0);
+    for (int64_t bj = bj0; bj < bj1; ++bj) {
+        MT xr[16];   // X_bj as the B operand of the row product
+#pragma unroll
+        for (int st = 0; st < 16; ++st) xr[st] = xt[(bj * 64 + 4 * st + kg) * 16 + i];
+        V accc[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) accc[t] = V{0, 0, 0, 0};
+        const int64_t last = I == J ? bj : bi1 - 1;
+        for (int64_t bi = bi0; bi <= last; ++bi) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int h = 0; h < HV; ++h) {
+                    const MT* d = a + (q * HV + h) * VEC;
+                    V16 v;
+                    if constexpr (VEC == 4) v = V16{d[0], d[1], d[2], d[3]};
+                    else v = V16{d[0], d[1]};
+                    *reinterpret_cast<V16*>(&tA[16 * q + 4 * w + kg][16 * VEC * h + VEC * i]) = v;
+                }
+            __syncthreads();
+            if (bi != bj) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) accc[t] = MC::mac(xc[q], a[(q * HV + t / VEC) * VEC + t % VEC], accc[t]);
+            }
+            // the next block in flight while this one's row product runs
+            if (bi < last) fetch(bi + 1, bj);
+            else if (bj + 1 < bj1) fetch(bi0, bj + 1);
+            V acc = accl[bi - bi0][tid];
+#pragma unroll
+            for (int st = 0; st < 16; ++st) acc = MC::mac(tA[16 * w + i][4 * st + kg], xr[st], acc);
+            accl[bi - bi0][tid] = acc;
+            __syncthreads();
+        }
+        // column partial of block column bj: the four waves' sums, through the tile's LDS
+        MT* red = &tA[0][0];   // [wave][16 right-hand sides][64 columns]
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                red[(w * 16 + MC::out_row(kg, r)) * 64 + 16 * VEC * (t / VEC) + VEC * i + t % VEC] = accc[t][r];
+        __syncthreads();
+        MT* dst = part + (bj * (nst + 1) + (nst - bj / KS) + I) * 1024;
+#pragma unroll
+        for (int o = tid; o < 1024; o += 256) dst[o] = (red[o] + red[1024 + o]) + (red[2048 + o] + red[3072 + o]);
+        __syncthreads();
+    }
+    // row partials of the super-tile's block rows
+    for (int64_t bi = bi0; bi < bi1; ++bi) {
+        MT* dst = part + (bi * (nst + 1) + (J - bi / KS)) * 1024;
+        const V acc = accl[bi - bi0][tid];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dst[i * 64 + 16 * w + MC::out_row(kg, r)] = acc[r];
+    }
+}
+
+// y[c][e] = the nst + 1 partials of block row b = e / 64 added in FP64: row partials J = b / KS ..
+// nst - 1, then column partials I = 0 .. b / KS (slot order)
+template <typename MT>
+__global__ void k_symv_reduce(const MT* __restrict__ part, int64_t nst, int64_t N, double* __restrict__ y, int64_t ldy) {
+    const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    const int c = blockIdx.y;
+    if (e >= N) return;
+    const MT* p = part + (e >> 6) * (nst + 1) * 1024 + c * 64 + (e & 63);
+    double s = 0.0;
+    for (int64_t q = 0; q <= nst; ++q) s += double(p[q * 1024]);
+    y[int64_t(c) * ldy + e] = s;
+}
+
 __global__ void k_reduce_splits(const double* __restrict__ partial, int S, int kc, int64_t N, int64_t ldw,
                                 double* __restrict__ y, int64_t ldy) {
     const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
@@ -408,6 +535,17 @@ void launch_matvec(const bem_problem* p, const MT* W, const double* x, int64_t l
         MT* xt = static_cast<MT*>(p->mv_xt.ptr);
         double* part = p->mv_partial.as<double>();
         hipLaunchKernelGGL(k_transpose_x<MT>, dim3(unsigned((ldw * 16 + 255) / 256)), dim3(256), 0, s, xc, ldx, kc, N, ldw, xt);
+        const int ty = sizeof(MT) == 4 ? 0 : 1;
+        if (p->mv_ntiles[ty] > 0) {
+            // W is symmetric: read its upper half once and apply every block to both sides
+            MT* sp = static_cast<MT*>(p->mv_sym.ptr);
+            hipLaunchKernelGGL(k_symv_mfma<MT>, dim3(unsigned(p->mv_ntiles[ty])), dim3(256), 0, s, W, ldw, N, xt, ldw / 64,
+                               p->mv_nst[ty], p->mv_tiles[ty].as<int2>(), sp);
+            hipLaunchKernelGGL(k_symv_reduce<MT>, dim3(unsigned((N + 255) / 256), unsigned(kc)), dim3(256), 0, s, sp,
+                               p->mv_nst[ty], N, yc, ldy);
+            HIP_CHECK(hipGetLastError());
+            continue;
+        }
         // split the columns when there are too few 64-row blocks to keep every CU streaming
         const int64_t blocks = (N + 63) / 64;
         int S = 1;
@@ -467,6 +605,32 @@ double lanczos_condition(const double* alpha, const double* beta, int m) {
 }
 
 }  // namespace
+
+// scratch of the multi-column products, sized for the problem: transposed right-hand sides, split
+// partials of the plain product, and per matrix type the super-tile list of the symmetric product
+// and its block-row partials (one buffer, sized for the larger of the two)
+void matvec_setup(bem_problem* p, hipStream_t s) {
+    p->mv_xt = DeviceBuffer(sizeof(double) * 16 * p->ldw, s);
+    p->mv_partial = DeviceBuffer(sizeof(double) * 16 * 16 * p->ldw, s);
+    const int64_t nb = p->ldw / 64;
+    if (nb < 2) return;   // one block: the plain product
+    std::vector<int2> tiles[2];
+    size_t sym_bytes = 0;
+    for (int ty = 0; ty < 2; ++ty) {
+        const int64_t ks = ty == 0 ? SymTile<float>::K : SymTile<double>::K;
+        const int64_t nst = (nb + ks - 1) / ks;
+        // off-diagonal super-tiles first: the half-size diagonal ones fill the tail of the launch
+        for (int64_t I = 0; I < nst; ++I)
+            for (int64_t J = I + 1; J < nst; ++J) tiles[ty].push_back(int2{int(I), int(J)});
+        for (int64_t I = 0; I < nst; ++I) tiles[ty].push_back(int2{int(I), int(I)});
+        p->mv_tiles[ty] = upload(tiles[ty], s);
+        p->mv_nst[ty] = nst;
+        sym_bytes = std::max(sym_bytes, size_t(nb * (nst + 1) * 1024) * (ty == 0 ? sizeof(float) : sizeof(double)));
+    }
+    p->mv_sym = DeviceBuffer(sym_bytes, s);
+    HIP_CHECK(hipStreamSynchronize(s));   // the host lists must outlive their uploads
+    for (int ty = 0; ty < 2; ++ty) p->mv_ntiles[ty] = int64_t(tiles[ty].size());
+}
 
 void matvec_device(const bem_problem* p, bool fp32, const double* d_x, int64_t ldx, int k, double* d_y, hipStream_t s) {
     if (p->N == 0) return;

@@ -154,8 +154,7 @@ void assemble_2d_device(bem_problem* p, const double* V2, int64_t nv, const int3
                            p->has_w32 ? p->W32.as<float>() : nullptr, p->ldw);
         HIP_CHECK(hipGetLastError());
     }
-    p->mv_xt = DeviceBuffer(sizeof(double) * 16 * p->ldw, s);
-    p->mv_partial = DeviceBuffer(sizeof(double) * 16 * 16 * p->ldw, s);
+    matvec_setup(p, s);
     HIP_CHECK(hipStreamSynchronize(s));   // host vectors above must outlive their uploads
 }
 

@@ -293,7 +293,7 @@ __global__ __launch_bounds__(256) void k_symv_mfma(const MT* __restrict__ W, int
 }
 
 // y[c][e] = the nst + 1 partials of block row b = e / 64 added in FP64: row partials J = b / KS ..
-// nst - 1, then column partials I = 0 .. b / KS (slot order)
+// nst - 1, then column partials I = 0 .. b / KS (slot order; loads issued eight at a time)
 template <typename MT>
 __global__ void k_symv_reduce(const MT* __restrict__ part, int64_t nst, int64_t N, double* __restrict__ y, int64_t ldy) {
     const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
@@ -301,7 +301,15 @@ __global__ void k_symv_reduce(const MT* __restrict__ part, int64_t nst, int64_t 
     if (e >= N) return;
     const MT* p = part + (e >> 6) * (nst + 1) * 1024 + c * 64 + (e & 63);
     double s = 0.0;
-    for (int64_t q = 0; q <= nst; ++q) s += double(p[q * 1024]);
+    int64_t q = 0;
+    for (; q + 8 <= nst + 1; q += 8) {
+        MT v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = p[(q + u) * 1024];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += double(v[u]);
+    }
+    for (; q <= nst; ++q) s += double(p[q * 1024]);
     y[int64_t(c) * ldy + e] = s;
 }
 

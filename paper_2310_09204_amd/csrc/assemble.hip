@@ -922,7 +922,7 @@ ContractPlan contract_plan(const MeshTopo& m) {
             for (int64_t q = m.dof_ptr[e0]; q < m.dof_ptr[e1]; ++q)
                 P.col_loc[size_t(q)] = int32_t(std::lower_bound(L.begin(), L.end(), m.dof_tri[q]) - L.begin());
         }
-    });
+    }, 8);
     for (int64_t b = 0; b < ncb; ++b) P.cb_ptr[size_t(b) + 1] = P.cb_ptr[size_t(b)] + int32_t(lists[size_t(b)].size());
     P.cb_tri.reserve(size_t(P.cb_ptr.back()));
     for (auto& L : lists) P.cb_tri.insert(P.cb_tri.end(), L.begin(), L.end());
@@ -950,7 +950,7 @@ ContractPlan contract_plan(const MeshTopo& m) {
                 i = j;
             }
         }
-    });
+    }, 32);
     P.rg_ptr.assign(size_t(nrb) + 1, 0);
     for (int64_t b = 0; b < nrb; ++b) P.rg_ptr[size_t(b) + 1] = P.rg_ptr[size_t(b)] + int32_t(groups[size_t(b)].size());
     P.rg.reserve(size_t(P.rg_ptr.back()));

@@ -62,6 +62,27 @@ std::mutex& capture_mutex() {
     return mu;
 }
 
+hipStream_t acquire_stream(bem_ctx* c) {
+    {
+        std::lock_guard<std::mutex> lk(c->stream_mu);
+        if (!c->free_streams.empty()) {
+            hipStream_t st = c->free_streams.back();
+            c->free_streams.pop_back();
+            return st;
+        }
+    }
+    hipStream_t st = nullptr;
+    std::lock_guard<std::mutex> cap(capture_mutex());
+    HIP_CHECK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    return st;
+}
+
+void release_stream(bem_ctx* c, hipStream_t st) {
+    if (!st) return;
+    std::lock_guard<std::mutex> lk(c->stream_mu);
+    c->free_streams.push_back(st);
+}
+
 void release_cached_device_memory(int device) {
     MemPool& P = mem_pool(device);
     std::lock_guard<std::mutex> cap(capture_mutex());
@@ -282,6 +303,8 @@ void bem_ctx_destroy(bem_ctx* ctx) {
     {
         std::lock_guard<std::mutex> cap(capture_mutex());
         if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+        for (hipStream_t st : ctx->free_streams) (void)hipStreamDestroy(st);
+        ctx->free_streams.clear();
         (void)hipDeviceSynchronize();
     }
     release_cached_device_memory(ctx->device);
@@ -362,10 +385,7 @@ int bem_assemble(bem_ctx* ctx, const double* vertices, int64_t nv, const int32_t
     p->has_w32 = opts && opts->precision == BEM_FP32_REFINE;
     p->has_pairs = opts && opts->keep_pair_matrix;
     p->panel_rows = (opts && opts->pair_panel_rows > 0) ? opts->pair_panel_rows : 0;
-    {
-        std::lock_guard<std::mutex> cap(capture_mutex());
-        HIP_CHECK(hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking));
-    }
+    p->stream = acquire_stream(ctx);
     try {
         assemble_device(p.get(), vertices, nv, triangles, nt, [&](NearList& near) {
             analyze_mesh(vertices, nv, triangles, nt, p->topo);
@@ -375,10 +395,11 @@ int bem_assemble(bem_ctx* ctx, const double* vertices, int64_t nv, const int32_t
     } catch (...) {
         // device work already queued must end before its buffers go
         (void)hipStreamSynchronize(p->stream);
-        hipStream_t s = p->stream;
+        hipStream_t s = p->stream, s2 = p->aux_stream;
+        if (s2) (void)hipStreamSynchronize(s2);
         p.reset();
-        std::lock_guard<std::mutex> cap(capture_mutex());
-        (void)hipStreamDestroy(s);
+        release_stream(ctx, s);
+        release_stream(ctx, s2);
         throw;
     }
     p->bytes = int64_t(p->W64.bytes + p->W32.bytes + p->I.bytes + p->normal.bytes + p->area.bytes + p->dof_ptr.bytes +
@@ -420,18 +441,16 @@ int bem_assemble_2d(bem_ctx* ctx, const double* vertices, int64_t nv, const int3
     p->ctx = ctx;
     p->has_w32 = opts && opts->precision == BEM_FP32_REFINE;
     if (opts && opts->keep_pair_matrix) fail(BEM_E_INVALID_ARG, "keep_pair_matrix is for triangle meshes");
-    {
-        std::lock_guard<std::mutex> cap(capture_mutex());
-        HIP_CHECK(hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking));
-    }
+    p->stream = acquire_stream(ctx);
     try {
         assemble_2d_device(p.get(), vertices, nv, segments, ns);
     } catch (...) {
         (void)hipStreamSynchronize(p->stream);
-        hipStream_t s = p->stream;
+        hipStream_t s = p->stream, s2 = p->aux_stream;
+        if (s2) (void)hipStreamSynchronize(s2);
         p.reset();
-        std::lock_guard<std::mutex> cap(capture_mutex());
-        (void)hipStreamDestroy(s);
+        release_stream(ctx, s);
+        release_stream(ctx, s2);
         throw;
     }
     p->bytes = int64_t(p->W64.bytes + p->W32.bytes + p->normal.bytes + p->area.bytes + p->dof_ptr.bytes +
@@ -449,15 +468,10 @@ void bem_problem_destroy(bem_problem* p) {
     if (p->stream) (void)hipStreamSynchronize(p->stream);
     if (p->aux_stream) (void)hipStreamSynchronize(p->aux_stream);
     hipStream_t s = p->stream, s2 = p->aux_stream;
+    bem_ctx* ctx = p->ctx;
     delete p;
-    if (s2) {
-        std::lock_guard<std::mutex> cap(capture_mutex());
-        (void)hipStreamDestroy(s2);
-    }
-    if (s) {
-        std::lock_guard<std::mutex> cap(capture_mutex());
-        (void)hipStreamDestroy(s);
-    }
+    release_stream(ctx, s2);
+    release_stream(ctx, s);
     (void)hipGetLastError();
 }
 

@@ -184,6 +184,10 @@ struct bem_ctx {
     int device = 0;
     size_t budget = 0;
     hipStream_t stream = nullptr;
+    // streams of destroyed problems, handed to new ones (creating a stream costs about 0.3 ms and
+    // destroying one synchronises the device)
+    std::mutex stream_mu;
+    std::vector<hipStream_t> free_streams;
 };
 
 struct bem_problem {
@@ -226,6 +230,11 @@ void jump_values_device(const bem_problem* p, const double* d_phi, double* d_jum
 // double-layer potential (potential.hip): U [k][m] at targets X [m][3] for phi [k][N], all on the device
 void double_layer_device(bem_problem* p, const double* d_phi, int k, const double* d_X, int64_t m, double* d_U,
                          hipStream_t s);
+
+// a non-blocking stream of the context's device: a released one, or a new one
+hipStream_t acquire_stream(bem_ctx* c);
+// gives back a stream with no queued work (the caller has synchronised it)
+void release_stream(bem_ctx* c, hipStream_t s);
 
 // dense products (solver.hip); x, y column-major [k][N] with leading dimension ldx
 void matvec_setup(bem_problem* p, hipStream_t s);   // after W is allocated (ldw set)

@@ -868,10 +868,7 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
     // the coarse block's work (second stream) starts after the layout uploads queued so far
     hipStream_t s2 = s;
     if (M->nH > 0) {
-        if (!p->aux_stream) {
-            std::lock_guard<std::mutex> cap(capture_mutex());
-            HIP_CHECK(hipStreamCreateWithFlags(&p->aux_stream, hipStreamNonBlocking));
-        }
+        if (!p->aux_stream) p->aux_stream = acquire_stream(p->ctx);
         s2 = p->aux_stream;
         hipEvent_t ready;
         HIP_CHECK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
@@ -880,21 +877,30 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
         (void)hipEventDestroy(ready);
         HIP_CHECK(e2);
     }
-    // faces and wire basket: all of their work is queued now
+    // faces and wire basket: all of their work is queued now.  (Queueing the coarse path ahead of
+    // most of it was slower: the memory-bound coarse product then takes the CUs that the
+    // latency-bound elimination steps wait for.)
     for (const Launch& L : plan_fw) run(L, s);
 
     // coarse Galerkin block on the second stream, while the first one eliminates
     DeviceBuffer Z;
+    std::vector<int64_t> tp;   // host sides of the coarse uploads: they must outlive the copies
+    std::vector<int32_t> trow;
+    std::vector<double> tval;
     if (M->nH > 0) {
+        const auto hp0 = std::chrono::steady_clock::now();
         if (seg) build_prolongation_2d(f, c, parent, R);
         else build_prolongation(f, c, parent, R);
+        if (trace)
+            std::fprintf(stderr, "bem-trace precond  %-18s %8.3f ms (host only)\n", "prolongation build",
+                         std::chrono::duration<double>(std::chrono::steady_clock::now() - hp0).count() * 1e3);
         mark("prolongation");
         // transposed CSR (fine dof -> coarse dofs)
-        std::vector<int64_t> tp(f.N + 1, 0);
+        tp.assign(size_t(f.N) + 1, 0);
         for (int32_t cidx : R.col) ++tp[cidx + 1];
         for (int64_t j = 0; j < f.N; ++j) tp[j + 1] += tp[j];
-        std::vector<int32_t> trow(R.col.size());
-        std::vector<double> tval(R.col.size());
+        trow.assign(R.col.size(), 0);
+        tval.assign(R.col.size(), 0.0);
         std::vector<int64_t> fill(tp.begin(), tp.end() - 1);
         for (int64_t i = 0; i < R.nH; ++i)
             for (int64_t e = R.ptr[i]; e < R.ptr[i + 1]; ++e) {
@@ -923,9 +929,8 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
             HIP_CHECK(hipGetLastError());
         }
         for (const Launch& L : plan_c) run(L, s2);
-        // the host vectors of the uploads above must outlive the copies
-        HIP_CHECK(hipStreamSynchronize(s2));
     }
+    if (M->nH > 0) HIP_CHECK(hipStreamSynchronize(s2));
     HIP_CHECK(hipStreamSynchronize(s));
     mark("factor+invert");
     std::vector<int> flags(nall);

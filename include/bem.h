@@ -156,14 +156,14 @@ int bem_problem_pair_integrals(const bem_problem* p, const int32_t* pairs, int64
  * out[k][N] (column-major, one column per g) */
 int bem_rhs(const bem_problem* p, const double* g, int32_t k, double* out);
 /* y = W x for k column vectors x[k][N] -> y[k][N] (FP64 matrix, or FP32 matrix if fp32 = 1).
- * Columns go in groups of 16; a group of two or more reads only the upper block triangle of the
- * symmetric W (each 64 x 64 block applied to both sides), a single column streams the full rows.
+ * Columns go in groups of 16; each group reads only the upper block triangle of the symmetric W
+ * (each 64 x 64 block applied to both sides); a matrix of a single 64-row block is streamed whole.
  * Sums run in a fixed order: equal inputs give bit-identical outputs. */
 int bem_matvec(const bem_problem* p, const double* x, int32_t k, int fp32, double* y);
 /* Measurement: `reps` back-to-back products y = W x with k device-resident columns (FP64 matrix,
  * or the FP32 copy if fp32 = 1), timed with HIP events on the problem's stream; writes the mean
- * seconds per product.  A one-column product streams W (N^2 x 8 or 4 bytes); with k >= 2 the
- * upper block triangle of W is read plus the block-row partials of the symmetric product. */
+ * seconds per product.  The upper block triangle of W is read plus the block-row partials of the
+ * symmetric product, for any k (a matrix of one 64-row block: N^2 x 8 or 4 bytes). */
 int bem_problem_bench_matvec(const bem_problem* p, int fp32, int32_t k, int reps, double* seconds);
 /* label-free view of phi[N]: jump[t][a] = sum_d c_{T,a,d} phi_d, the jump of the represented
  * function across triangle t at corner a (jump_out[nt][3]); for a segment mesh across segment s

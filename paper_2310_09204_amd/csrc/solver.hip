@@ -534,8 +534,9 @@ void launch_matvec(const bem_problem* p, const MT* W, const double* x, int64_t l
         const int kc = std::min(16, k - c0);
         const double* xc = x + int64_t(c0) * ldx;
         double* yc = y + int64_t(c0) * ldy;
-        if (kc == 1) {
-            // one column: a plain streaming dot product per row (one wave per row)
+        const int ty = sizeof(MT) == 4 ? 0 : 1;
+        if (kc == 1 && p->mv_ntiles[ty] == 0) {
+            // one column of a one-block matrix: a plain streaming dot product per row (one wave per row)
             hipLaunchKernelGGL((k_matvec<MT, AT, 1>), dim3(unsigned((N + 3) / 4)), dim3(256), 0, s, W, ldw, N, xc, ldx, kc, yc, ldy);
             HIP_CHECK(hipGetLastError());
             continue;
@@ -543,9 +544,9 @@ void launch_matvec(const bem_problem* p, const MT* W, const double* x, int64_t l
         MT* xt = static_cast<MT*>(p->mv_xt.ptr);
         double* part = p->mv_partial.as<double>();
         hipLaunchKernelGGL(k_transpose_x<MT>, dim3(unsigned((ldw * 16 + 255) / 256)), dim3(256), 0, s, xc, ldx, kc, N, ldw, xt);
-        const int ty = sizeof(MT) == 4 ? 0 : 1;
         if (p->mv_ntiles[ty] > 0) {
-            // W is symmetric: read its upper half once and apply every block to both sides
+            // W is symmetric: read its upper half once and apply every block to both sides (also
+            // for a single column: half the bytes outweigh the idle matrix-core columns)
             MT* sp = static_cast<MT*>(p->mv_sym.ptr);
             hipLaunchKernelGGL(k_symv_mfma<MT>, dim3(unsigned(p->mv_ntiles[ty])), dim3(256), 0, s, W, ldw, N, xt, ldw / 64,
                                p->mv_nst[ty], p->mv_tiles[ty].as<int2>(), sp);

@@ -1,6 +1,6 @@
-"""Multi-column products y = W x through the C-ABI: the symmetric upper-half product (two or more
-columns) against a plain FP64 product of the same matrix and against the one-column row product,
-at sizes that span several super-tiles with ragged last super-blocks and a ragged last 64-row block."""
+"""Products y = W x through the C-ABI: the symmetric upper-half product against a plain FP64
+product of the same matrix, and a block of columns against the same columns one at a time, at sizes
+that span several super-tiles with ragged last super-blocks and a ragged last 64-row block."""
 import numpy as np
 import pytest
 
@@ -25,7 +25,7 @@ def problem(request, ctx):
     p.close()
 
 
-@pytest.mark.parametrize("k", [2, 5, 16, 17, 33])
+@pytest.mark.parametrize("k", [1, 2, 5, 16, 17, 33])
 def test_fp64_product(problem, k):
     name, p = problem
     W = p.matrix()
@@ -46,7 +46,7 @@ def test_fp64_matches_single_columns(problem):
     assert err < 1e-13, (name, err)
 
 
-@pytest.mark.parametrize("k", [2, 16, 19])
+@pytest.mark.parametrize("k", [1, 2, 16, 19])
 def test_fp32_product(problem, k):
     name, p = problem
     W32 = p.matrix().astype(np.float32).astype(np.float64)

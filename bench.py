@@ -454,14 +454,21 @@ def main():
     log("bench: workload %s nt=%d k=%d precision=%s" % (args.workload, m.nt, args.k, args.precision))
     ctx = lib.Context(0)
 
-    def step(precision, want_phi=False, tol=args.tol, wirebasket="exact"):
+    # the timed steps take the mesh from device memory and leave the solutions there (inputs resident
+    # in HBM); host copies of the mesh still feed the host-side analysis
+    d_mesh = (lib.DeviceArray(np.asarray(m.vertices, dtype=np.float64)),
+              lib.DeviceArray(np.asarray(m.triangles, dtype=np.int32)))
+
+    def step(precision, want_phi=False, tol=args.tol, wirebasket="exact", device_out=None):
         t0 = time.perf_counter()
-        p = lib.Problem(ctx, m.vertices, m.triangles, precision=precision, near_order=10)
+        p = lib.Problem(ctx, m.vertices, m.triangles, precision=precision, near_order=10,
+                        device_mesh=(d_mesh[0].ptr, d_mesh[1].ptr) if device_out is not None else None)
         t1 = time.perf_counter()
         M = lib.Preconditioner(p, w.patch_of_triangle, w.coarse.vertices, w.coarse.triangles, w.coarse_of_triangle,
                                factor_fp32=(precision == lib.FP32_REFINE), wirebasket=wirebasket)
         t2 = time.perf_counter()
-        phi, info, rc = p.solve(g=w.g, precond=M, tol=tol, precision=precision)
+        phi, info, rc = p.solve(g=w.g, precond=M, tol=tol, precision=precision,
+                                device_out=device_out.ptr if device_out is not None else None)
         ctx.synchronize()
         t3 = time.perf_counter()
         pinfo = p.info
@@ -490,21 +497,26 @@ def main():
     ref["M"].close()
     pref.close()
 
+    # one device buffer per timed step for its solutions, allocated before the timed region
+    d_out = [lib.DeviceArray(shape=(w.g.shape[0], N)) for _ in range(max(args.steps, 1))]
     for i in range(args.warmup):
         log("bench: warmup %d" % i)
-        step(prec)
+        step(prec, device_out=d_out[0])
     ctx.synchronize()
-    res, phis = [], []
+    res = []
     t_begin = time.perf_counter()
     for i in range(args.steps):
-        r = step(prec, want_phi=True)
-        phis.append(r.pop("phi"))
+        r = step(prec, want_phi=True, device_out=d_out[i])
+        r.pop("phi")
         r.pop("M").close()
         r.pop("problem").close()
         res.append(r)
     ctx.synchronize()
     elapsed = time.perf_counter() - t_begin
     # checks and side measurements, outside the timed region
+    phis = [d.get() for d in d_out[:args.steps]]
+    for d in d_out:
+        d.close()
     for i, (r, phi) in enumerate(zip(res, phis)):
         err = np.linalg.norm(phi - phi_ref, axis=1) / np.linalg.norm(phi_ref, axis=1)
         r["relerr"] = err.tolist()
@@ -542,6 +554,20 @@ def main():
                  "solves_per_s": int((errd <= 1e-8).sum()) / rd["t_step"]}
     log("bench: diagonal wire basket: step %.3fs precond %.4f solve %.3f iters %s" %
         (rd["t_step"], rd["t_precond"], rd["t_solve"], rd["iters"][:4]))
+
+    # the same step with host buffers (mesh uploaded, solutions downloaded in the step): the
+    # PCIe-inclusive rate, reported beside the value, never as it
+    t_h0 = time.perf_counter()
+    n_h, solved_h = 2, 0
+    for _ in range(n_h):
+        rh = step(prec, want_phi=True)
+        errh = np.linalg.norm(rh["phi"] - phi_ref, axis=1) / np.linalg.norm(phi_ref, axis=1)
+        solved_h += int((errh <= 1e-8).sum())
+        rh["M"].close()
+        rh["problem"].close()
+    t_h = time.perf_counter() - t_h0
+    host_io = {"steps": n_h, "ms_per_step": t_h / n_h * 1e3, "solves_per_s": solved_h / t_h}
+    log("bench: host-buffer steps (PCIe-inclusive): %.1f ms per step" % (t_h / n_h * 1e3))
 
     nt = pinfo["n_tri"]
     pairs = nt * (nt + 1) // 2
@@ -596,6 +622,7 @@ def main():
         "matvec": mv,
         "fp64_compare": fp64_step,
         "diagonal_wirebasket": diag_step,
+        "pcie_inclusive": host_io,
     }
     if not args.no_potential:
         out["double_layer"] = double_layer_leg(lib, w, ctx)

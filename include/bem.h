@@ -141,6 +141,15 @@ int bem_mesh_analyze(const double* vertices, int64_t nv, const int32_t* triangle
  * BEM_E_OOM, BEM_E_DEVICE. */
 int bem_assemble(bem_ctx* ctx, const double* vertices, int64_t nv, const int32_t* triangles,
                  int64_t nt, const bem_assemble_opts* opts, bem_problem** out);
+/* The same assembly with the mesh also resident on the device: vertices / triangles (host) feed
+ * the host-side analysis (sectors, dofs, near pairs, plans), d_vertices / d_triangles (device
+ * memory of the context's device, same layout and values) feed the kernels, so no mesh upload
+ * happens in the call.  The device arrays are read on the library's streams: the caller's writes
+ * to them must be complete before the call (e.g. a device synchronisation); they may be freed
+ * after it returns.  Errors as for bem_assemble; values identical to bem_assemble's. */
+int bem_assemble_dev(bem_ctx* ctx, const double* vertices, const double* d_vertices, int64_t nv,
+                     const int32_t* triangles, const int32_t* d_triangles, int64_t nt,
+                     const bem_assemble_opts* opts, bem_problem** out);
 void bem_problem_destroy(bem_problem* p);
 int bem_problem_get_info(const bem_problem* p, bem_problem_info* info);
 /* dof table in canonical order: vertex index and sector label of each dof */
@@ -256,6 +265,11 @@ int bem_pcg_solve(bem_problem* p, const bem_precond* m, const double* g, int32_t
 /* Same for explicit right-hand sides rhs[k][N]. */
 int bem_pcg_solve_rhs(bem_problem* p, const bem_precond* m, const double* rhs, int32_t k,
                       const bem_solve_opts* opts, double* phi_out, bem_solve_info* info);
+/* bem_pcg_solve with the solution left on the device: d_phi_out is device memory of the
+ * context's device holding k x N doubles (column c at d_phi_out + c N), written when the call
+ * returns (the problem's stream is synchronised).  info, g and the errors as for bem_pcg_solve. */
+int bem_pcg_solve_dev(bem_problem* p, const bem_precond* m, const double* g, int32_t k,
+                      const bem_solve_opts* opts, double* d_phi_out, bem_solve_info* info);
 
 /* ---- serving loop ------------------------------------------------------------------------- */
 /* A background host thread takes solve requests on arbitrary multiscreens, keeps assembled

@@ -1151,7 +1151,7 @@ PanelTimes assemble_panels(bem_problem* p, const MeshTopo& m, const NearList& ne
 }  // namespace
 
 void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_t* Tin, int64_t nt,
-                     const std::function<void(NearList&)>& analyse) {
+                     const std::function<void(NearList&)>& analyse, const double* dVin, const int32_t* dTin) {
     const MeshTopo& m = p->topo;
     hipStream_t s = p->stream;
     // BEM_TRACE=1: synchronise and print the wall time of each assembly phase to stderr
@@ -1184,14 +1184,23 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
     triangle7_rule(bary, w7);
     std::vector<double> hb(&bary[0][0], &bary[0][0] + 21), hw(w7, w7 + 7);
 
-    DeviceBuffer dV(sizeof(double) * 3 * nv, s), dT(sizeof(int32_t) * 3 * nt, s);
-    HIP_CHECK(hipMemcpyAsync(dV.ptr, Vin, dV.bytes, hipMemcpyHostToDevice, s));
-    HIP_CHECK(hipMemcpyAsync(dT.ptr, Tin, dT.bytes, hipMemcpyHostToDevice, s));
+    // the kernels read the device copies of the mesh: the caller's, or uploaded here
+    DeviceBuffer dVbuf, dTbuf;
+    if (!dVin) {
+        dVbuf = DeviceBuffer(sizeof(double) * 3 * nv, s);
+        HIP_CHECK(hipMemcpyAsync(dVbuf.ptr, Vin, dVbuf.bytes, hipMemcpyHostToDevice, s));
+    }
+    if (!dTin) {
+        dTbuf = DeviceBuffer(sizeof(int32_t) * 3 * nt, s);
+        HIP_CHECK(hipMemcpyAsync(dTbuf.ptr, Tin, dTbuf.bytes, hipMemcpyHostToDevice, s));
+    }
+    const double* dVp = dVin ? dVin : dVbuf.as<double>();
+    const int32_t* dTp = dTin ? dTin : dTbuf.as<int32_t>();
     DeviceBuffer db = upload(hb, s), dw = upload(hw, s);
     DeviceBuffer geo(sizeof(double) * nt * kGeo, s);
     p->normal = DeviceBuffer(sizeof(double) * nt * 3, s);
     p->area = DeviceBuffer(sizeof(double) * nt, s);
-    hipLaunchKernelGGL(k_geometry, dim3(blocks_for(nt, 256)), dim3(256), 0, s, dV.as<double>(), dT.as<int32_t>(), nt,
+    hipLaunchKernelGGL(k_geometry, dim3(blocks_for(nt, 256)), dim3(256), 0, s, dVp, dTp, nt,
                        db.as<double>(), dw.as<double>(), geo.as<double>(), p->normal.as<double>(), p->area.as<double>());
     HIP_CHECK(hipGetLastError());
 
@@ -1270,7 +1279,7 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
     const int64_t ne = int64_t(m.dof_tri.size());
     DeviceBuffer dofJ(sizeof(double) * 3 * std::max<int64_t>(ne, 1), s);
     if (ne > 0) {
-        hipLaunchKernelGGL(k_jump_vectors, dim3(blocks_for(ne, 256)), dim3(256), 0, s, dV.as<double>(), dT.as<int32_t>(),
+        hipLaunchKernelGGL(k_jump_vectors, dim3(blocks_for(ne, 256)), dim3(256), 0, s, dVp, dTp,
                            p->dof_tri.as<int32_t>(), dof_corner.as<int8_t>(), p->dof_c.as<int8_t>(), p->area.as<double>(), ne,
                            dofJ.as<double>());
         HIP_CHECK(hipGetLastError());
@@ -1299,13 +1308,13 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
             if (n == 0) continue;
             dim3 grid(blocks_for(n, 64)), block(64);
             if (ty == 3)
-                hipLaunchKernelGGL(k_near_coincident, grid, block, 0, s, dV.as<double>(), dv[ty].as<int32_t>(), da[ty].as<int32_t>(), n,
+                hipLaunchKernelGGL(k_near_coincident, grid, block, 0, s, dVp, dv[ty].as<int32_t>(), da[ty].as<int32_t>(), n,
                                    p->near_order, dgx.as<double>(), dgw.as<double>(), p->I.as<double>(), ldI, nullptr);
             else if (ty == 2)
-                hipLaunchKernelGGL(k_near_edge, grid, block, 0, s, dV.as<double>(), dv[ty].as<int32_t>(), da[ty].as<int32_t>(),
+                hipLaunchKernelGGL(k_near_edge, grid, block, 0, s, dVp, dv[ty].as<int32_t>(), da[ty].as<int32_t>(),
                                    dbb[ty].as<int32_t>(), n, p->near_order, dgx.as<double>(), dgw.as<double>(), p->I.as<double>(), ldI, nullptr);
             else
-                hipLaunchKernelGGL(k_near_vertex, grid, block, 0, s, dV.as<double>(), dv[ty].as<int32_t>(), da[ty].as<int32_t>(),
+                hipLaunchKernelGGL(k_near_vertex, grid, block, 0, s, dVp, dv[ty].as<int32_t>(), da[ty].as<int32_t>(),
                                    dbb[ty].as<int32_t>(), n, p->near_order, dgx.as<double>(), dgw.as<double>(), p->I.as<double>(), ldI, nullptr);
             HIP_CHECK(hipGetLastError());
         }
@@ -1338,7 +1347,7 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
         t_contract.stop();
         mark("contract");
     } else {
-        ptimes = assemble_panels(p, m, near, plan, geo.as<double>(), gbounds.as<double>(), crec.as<double>(), dV.as<double>(),
+        ptimes = assemble_panels(p, m, near, plan, geo.as<double>(), gbounds.as<double>(), crec.as<double>(), dVp,
                                  dgx.as<double>(), dgw.as<double>(), dofJ.as<double>(), w32, mark);
     }
     matvec_setup(p, s);

@@ -248,7 +248,7 @@ bem_solve_opts default_solve_opts() {
 }
 
 int solve_common(bem_problem* p, const bem_precond* m, const double* d_b, int32_t k, const bem_solve_opts* opts,
-                 double* phi_out, bem_solve_info* info) {
+                 double* phi_out, bem_solve_info* info, double* d_phi_out = nullptr) {
     bem_solve_opts o = opts ? *opts : default_solve_opts();
     if (o.tol <= 0) o.tol = 1e-10;
     if (o.max_iter <= 0) o.max_iter = 2000;
@@ -256,12 +256,16 @@ int solve_common(bem_problem* p, const bem_precond* m, const double* d_b, int32_
     if (m && m->p != p) fail(BEM_E_INVALID_ARG, "preconditioner belongs to another problem");
     const int64_t N = p->N;
     std::vector<bem_solve_info> inf(k);
-    DeviceBuffer x(sizeof(double) * std::max<int64_t>(1, N * k), p->stream);
-    if (N > 0) solve_device(p, m, d_b, x.as<double>(), k, o, inf.data());
-    if (phi_out && N > 0) {
+    // the iterate lives in the caller's device buffer when one is given
+    DeviceBuffer x;
+    if (!d_phi_out) x = DeviceBuffer(sizeof(double) * std::max<int64_t>(1, N * k), p->stream);
+    double* dx = d_phi_out ? d_phi_out : x.as<double>();
+    if (N > 0) solve_device(p, m, d_b, dx, k, o, inf.data());
+    if (phi_out && !d_phi_out && N > 0) {
         HIP_CHECK(hipMemcpyAsync(phi_out, x.ptr, sizeof(double) * N * k, hipMemcpyDeviceToHost, p->stream));
         HIP_CHECK(hipStreamSynchronize(p->stream));
     }
+    if (d_phi_out) HIP_CHECK(hipStreamSynchronize(p->stream));   // the caller may read it on any stream
     int rc = BEM_OK;
     for (int c = 0; c < k; ++c) {
         if (inf[c].status == BEM_E_BREAKDOWN) rc = BEM_E_BREAKDOWN;
@@ -373,6 +377,12 @@ int bem_mesh_analyze(const double* vertices, int64_t nv, const int32_t* triangle
 
 int bem_assemble(bem_ctx* ctx, const double* vertices, int64_t nv, const int32_t* triangles, int64_t nt,
                  const bem_assemble_opts* opts, bem_problem** out) {
+    return bem_assemble_dev(ctx, vertices, nullptr, nv, triangles, nullptr, nt, opts, out);
+}
+
+int bem_assemble_dev(bem_ctx* ctx, const double* vertices, const double* d_vertices, int64_t nv,
+                     const int32_t* triangles, const int32_t* d_triangles, int64_t nt,
+                     const bem_assemble_opts* opts, bem_problem** out) {
     BEM_TRY
     if (!ctx || !out) fail(BEM_E_INVALID_ARG, "ctx/out is NULL");
     *out = nullptr;
@@ -391,7 +401,7 @@ int bem_assemble(bem_ctx* ctx, const double* vertices, int64_t nv, const int32_t
             analyze_mesh(vertices, nv, triangles, nt, p->topo);
             build_near_list(p->topo, near);
             p->N = p->topo.N;
-        });
+        }, d_vertices, d_triangles);
     } catch (...) {
         // device work already queued must end before its buffers go
         (void)hipStreamSynchronize(p->stream);
@@ -693,6 +703,19 @@ int bem_pcg_solve(bem_problem* p, const bem_precond* m, const double* g, int32_t
     HIP_CHECK(hipMemcpyAsync(dg.ptr, g, sizeof(double) * 3 * k, hipMemcpyHostToDevice, p->stream));
     rhs_device(p, dg.as<double>(), k, dL.as<double>(), p->stream);
     return solve_common(p, m, dL.as<double>(), k, opts, phi_out, info);
+    BEM_CATCH
+}
+
+int bem_pcg_solve_dev(bem_problem* p, const bem_precond* m, const double* g, int32_t k, const bem_solve_opts* opts,
+                      double* d_phi_out, bem_solve_info* info) {
+    BEM_TRY
+    if (!p || !g || k <= 0 || !d_phi_out) fail(BEM_E_INVALID_ARG, "bad argument");
+    set_device(p->ctx);
+    const int64_t N = p->N;
+    DeviceBuffer dg(sizeof(double) * 3 * k, p->stream), dL(sizeof(double) * std::max<int64_t>(1, N * k), p->stream);
+    HIP_CHECK(hipMemcpyAsync(dg.ptr, g, sizeof(double) * 3 * k, hipMemcpyHostToDevice, p->stream));
+    rhs_device(p, dg.as<double>(), k, dL.as<double>(), p->stream);
+    return solve_common(p, m, dL.as<double>(), k, opts, nullptr, info, d_phi_out);
     BEM_CATCH
 }
 

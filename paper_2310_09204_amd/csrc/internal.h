@@ -221,8 +221,10 @@ namespace bem {
 // assembly (assemble.hip)
 // Assembles W for the mesh (V, T).  analyse(near) runs on the host while the far-field pass is on
 // the device: it must fill p->topo (and the near list) or throw the mesh's validation error.
+// dV, dT: optional device copies of V and T, which the kernels then read instead of an upload.
 void assemble_device(bem_problem* p, const double* V, int64_t nv, const int32_t* T, int64_t nt,
-                     const std::function<void(NearList&)>& analyse);
+                     const std::function<void(NearList&)>& analyse, const double* dV = nullptr,
+                     const int32_t* dT = nullptr);
 void rhs_device(const bem_problem* p, const double* d_g, int k, double* d_L, hipStream_t s);
 // two-dimensional variant (twod.hip): analyses the segment mesh into p->topo and assembles W
 void assemble_2d_device(bem_problem* p, const double* V2, int64_t nv, const int32_t* S, int64_t ns);

@@ -96,6 +96,7 @@ SIGNATURES = {
     "bem_problem_bench_matvec": (_ci, [_vp, _ci, _i32, _ci, ctypes.POINTER(ctypes.c_double)]),
     "bem_mesh_analyze": (_ci, [_vp, _i64, _vp, _i64, ctypes.POINTER(_i64), _vp, _vp, _vp]),
     "bem_assemble": (_ci, [_vp, _vp, _i64, _vp, _i64, ctypes.POINTER(AssembleOpts), ctypes.POINTER(_vp)]),
+    "bem_assemble_dev": (_ci, [_vp, _vp, _vp, _i64, _vp, _vp, _i64, ctypes.POINTER(AssembleOpts), ctypes.POINTER(_vp)]),
     "bem_problem_destroy": (None, [_vp]),
     "bem_problem_get_info": (_ci, [_vp, ctypes.POINTER(ProblemInfo)]),
     "bem_problem_dofs": (_ci, [_vp, _vp, _vp]),
@@ -112,6 +113,7 @@ SIGNATURES = {
     "bem_precond_apply": (_ci, [_vp, _vp, _i32, _vp]),
     "bem_pcg_solve": (_ci, [_vp, _vp, _vp, _i32, ctypes.POINTER(SolveOpts), _vp, _vp]),
     "bem_pcg_solve_rhs": (_ci, [_vp, _vp, _vp, _i32, ctypes.POINTER(SolveOpts), _vp, _vp]),
+    "bem_pcg_solve_dev": (_ci, [_vp, _vp, _vp, _i32, ctypes.POINTER(SolveOpts), _vp, _vp]),
     "bem_server_create": (_ci, [_vp, _ci, ctypes.POINTER(_vp)]),
     "bem_server_destroy": (None, [_vp]),
     "bem_serve_submit": (_ci, [_vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
@@ -198,16 +200,85 @@ class Context:
             pass
 
 
-class Problem:
-    """bem_assemble: W resident on the device."""
+_hip = None
 
-    def __init__(self, ctx: Context, V, T, precision=FP64, near_order=10, keep_pair_matrix=False, pair_panel_rows=0):
+
+def _hiprt():
+    """The HIP runtime that libbem.so links (device buffers for the *_dev entry points)."""
+    global _hip
+    if _hip is None:
+        load()   # loads libamdhip64 as a dependency of libbem.so
+        _hip = ctypes.CDLL("libamdhip64.so", mode=ctypes.RTLD_GLOBAL)
+        _hip.hipMalloc.argtypes = [ctypes.POINTER(_vp), ctypes.c_size_t]
+        _hip.hipFree.argtypes = [_vp]
+        _hip.hipMemcpy.argtypes = [_vp, _vp, ctypes.c_size_t, ctypes.c_int]
+        _hip.hipSetDevice.argtypes = [ctypes.c_int]
+    return _hip
+
+
+class DeviceArray:
+    """A numpy array's copy in device memory (hipMalloc / hipMemcpy), for the entry points that take
+    device pointers.  .ptr is the device address; .get() copies it back."""
+
+    def __init__(self, a=None, shape=None, dtype=np.float64, device=0):
+        h = _hiprt()
+        _check_hip(h.hipSetDevice(device))
+        if a is not None:
+            a = np.ascontiguousarray(a)
+            self.shape, self.dtype = a.shape, a.dtype
+        else:
+            self.shape, self.dtype = tuple(shape), np.dtype(dtype)
+        self.nbytes = int(np.prod(self.shape)) * self.dtype.itemsize
+        p = _vp()
+        _check_hip(h.hipMalloc(ctypes.byref(p), max(self.nbytes, 1)))
+        self._p = p
+        if a is not None and self.nbytes:
+            _check_hip(h.hipMemcpy(p, a.ctypes.data_as(_vp), self.nbytes, 1))   # host to device
+
+    @property
+    def ptr(self):
+        return self._p.value
+
+    def get(self):
+        out = np.empty(self.shape, dtype=self.dtype)
+        if self.nbytes:
+            _check_hip(_hiprt().hipMemcpy(out.ctypes.data_as(_vp), self._p, self.nbytes, 2))   # device to host
+        return out
+
+    def close(self):
+        if self._p:
+            _hiprt().hipFree(self._p)
+            self._p = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _check_hip(code):
+    if code != 0:
+        raise RuntimeError("HIP runtime error %d" % code)
+
+
+class Problem:
+    """bem_assemble: W resident on the device.  With device_mesh = (address of V, address of T) in
+    device memory (same values as V, T), bem_assemble_dev: the kernels read those copies."""
+
+    def __init__(self, ctx: Context, V, T, precision=FP64, near_order=10, keep_pair_matrix=False, pair_panel_rows=0,
+                 device_mesh=None):
         self.ctx = ctx
         self.V, self.T = _f64(V), _i32a(T)
         o = AssembleOpts(precision, near_order, int(keep_pair_matrix), int(pair_panel_rows))
         self._h = ctypes.c_void_p()
-        _check(load().bem_assemble(ctx.handle, _p(self.V), self.V.shape[0], _p(self.T), self.T.shape[0],
-                                   ctypes.byref(o), ctypes.byref(self._h)))
+        if device_mesh is None:
+            _check(load().bem_assemble(ctx.handle, _p(self.V), self.V.shape[0], _p(self.T), self.T.shape[0],
+                                       ctypes.byref(o), ctypes.byref(self._h)))
+        else:
+            dV, dT = device_mesh
+            _check(load().bem_assemble_dev(ctx.handle, _p(self.V), ctypes.c_void_p(dV), self.V.shape[0], _p(self.T),
+                                           ctypes.c_void_p(dT), self.T.shape[0], ctypes.byref(o), ctypes.byref(self._h)))
         self.info = self.get_info()
         self.N = self.info["n_dofs"]
 
@@ -281,11 +352,22 @@ class Problem:
         return out
 
     def solve(self, g=None, rhs=None, precond=None, tol=1e-10, max_iter=2000, use_precond=True,
-              precision=FP64, refresh_factor=1e-3, check_every=4, use_graph=True, raise_on_error=True):
-        """Returns (phi[k][N], [info dict per column], status code)."""
+              precision=FP64, refresh_factor=1e-3, check_every=4, use_graph=True, raise_on_error=True,
+              device_out=None):
+        """Returns (phi[k][N], [info dict per column], status code).  With device_out (the address
+        of k x N doubles in device memory) and g, bem_pcg_solve_dev: phi stays there and None is
+        returned in its place."""
         o = SolveOpts(tol, max_iter, int(use_precond), precision, refresh_factor, check_every, int(use_graph))
         L = load()
         m = precond.handle if precond is not None else None
+        if device_out is not None:
+            g = _f64(np.atleast_2d(g))
+            k = g.shape[0]
+            info = (SolveInfo * k)()
+            rc = L.bem_pcg_solve_dev(self._h, m, _p(g), k, ctypes.byref(o), ctypes.c_void_p(device_out), info)
+            if raise_on_error and rc < 0:
+                _check(rc)
+            return None, [i.as_dict() for i in info], rc
         if g is not None:
             g = _f64(np.atleast_2d(g))
             k = g.shape[0]

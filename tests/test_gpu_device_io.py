@@ -1,0 +1,32 @@
+"""Device-resident inputs and outputs through the C-ABI: bem_assemble_dev (the kernels read the
+caller's device copy of the mesh) and bem_pcg_solve_dev (the solution stays in device memory)
+give exactly what the host-buffer entry points give."""
+import numpy as np
+import pytest
+
+from paper_2310_09204_amd import lib, meshes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("precision", [lib.FP64, lib.FP32_REFINE])
+def test_device_mesh_and_solution_match_host_entry_points(ctx, precision):
+    w = meshes.workload("square16", k=3)
+    m = w.mesh
+    print("case device io square16", precision, flush=True)
+    dV, dT = lib.DeviceArray(np.asarray(m.vertices, dtype=np.float64)), lib.DeviceArray(np.asarray(m.triangles, dtype=np.int32))
+    ph = lib.Problem(ctx, m.vertices, m.triangles, precision=precision)
+    pd = lib.Problem(ctx, m.vertices, m.triangles, precision=precision, device_mesh=(dV.ptr, dT.ptr))
+    assert np.array_equal(ph.matrix(), pd.matrix())
+    Mh = lib.Preconditioner(ph, w.patch_of_triangle, w.coarse.vertices, w.coarse.triangles, w.coarse_of_triangle,
+                            factor_fp32=(precision == lib.FP32_REFINE))
+    Md = lib.Preconditioner(pd, w.patch_of_triangle, w.coarse.vertices, w.coarse.triangles, w.coarse_of_triangle,
+                            factor_fp32=(precision == lib.FP32_REFINE))
+    phi_h, info_h, rc_h = ph.solve(g=w.g, precond=Mh, tol=1e-10, precision=precision)
+    out = lib.DeviceArray(shape=(w.g.shape[0], pd.N))
+    none, info_d, rc_d = pd.solve(g=w.g, precond=Md, tol=1e-10, precision=precision, device_out=out.ptr)
+    assert none is None and rc_h == rc_d == 0
+    assert np.array_equal(out.get(), phi_h)
+    assert [i["iters"] for i in info_d] == [i["iters"] for i in info_h]
+    for x in (Mh, Md, ph, pd, out, dV, dT):
+        x.close()

@@ -102,11 +102,12 @@ __global__ void k_jump_vectors(const double* __restrict__ V, const int32_t* __re
 // grows like ((|x - c| + |y - c|) / |x - y|)^2.  c is the centre of the column triangle's group of
 // 16 (consecutive triangles); a group of columns takes this form only if its centre is at least
 // kSep (rho_R + rho_C) from the centre of the row tile (rho the radii of the Gauss points about
-// the centres), which bounds that ratio by (kSep + 1) / (kSep - 1) = 5.  Closer groups take the
-// differences.  Pairs that share a vertex are overwritten by the near rules in either case.
+// the centres), which bounds that ratio by (kSep + 1) / (kSep - 1) = 11: at worst about 121 ulp of
+// |x - y|^2, 1.3e-14 relative.  Closer groups take the differences.  Pairs that share a vertex are
+// overwritten by the near rules in either case.
 // ---------------------------------------------------------------------------------------------
 constexpr int kGrp = 16;
-constexpr double kSep = 1.5;
+constexpr double kSep = 1.2;
 constexpr int kRec = 35;   // 7 points x (v/w^2, 1/w^2, |v|^2/w^2)
 
 // per group of 16 consecutive triangles: centre of the bounding box of their Gauss points, and the

@@ -767,8 +767,17 @@ PcgResult pcg_device(bem_problem* p, const bem_precond* M, bool mixed, const dou
             hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
             if (e == hipSuccess) {
                 gr.capturing = true;
-                iteration(v == 1);
-                e = hipGetLastError();
+                try {
+                    iteration(v == 1);
+                    e = hipGetLastError();
+                } catch (const Failure&) {
+                    // a launch inside the capture reported an error (the runtime invalidates a
+                    // capture when a call elsewhere in the process is not permitted beside it):
+                    // the capture is dropped and the direct launches below redo the same work, or
+                    // report the error if it is not the capture's
+                    e = hipGetLastError();
+                    if (e == hipSuccess) e = hipErrorStreamCaptureInvalidated;
+                }
                 hipGraph_t g = nullptr;
                 const hipError_t e_end = hipStreamEndCapture(s, &g);
                 gr.capturing = false;

@@ -609,7 +609,9 @@ def main():
                                (args.workload, w.description, args.k, "mixed-precision (FP32 products, reliable FP64 residual updates)" if mixed else "FP64",
                                 args.tol),
                    "n_dofs": N, "n_tri": nt, "k": args.k, "precision": args.precision,
-                   "patches": ref["precond_sizes"]},
+                   "patches": ref["precond_sizes"],
+                   "io": "mesh and solutions resident in device memory (bem_assemble_dev, bem_pcg_solve_dev); "
+                         "the host-buffer rate is pcie_inclusive"},
         "roofline": roofline,
         "pair_integrals_per_s": pairs / t_asm,
         "pair_integrals_per_s_far_kernel": far_pairs / t_far,

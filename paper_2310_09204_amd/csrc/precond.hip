@@ -36,17 +36,48 @@ constexpr int LDT = 65;     // LDS leading dimension (padding against bank confl
 
 struct BlockMeta { int64_t n, npad, idx_off, mat_off, xoff; };
 
+// Tile moves by a block of 256 threads (every launch of the kernels below uses 256): thread t moves
+// elements t + 256 q, q < 16.  All 16 loads of a thread are issued before the first is used, so a
+// tile costs one memory latency instead of sixteen.
+constexpr int kTilePer = TBK * TBK / 256;
+
 __device__ __forceinline__ void tile_load(double* __restrict__ s, const double* __restrict__ g, int64_t ld) {
-    for (int e = threadIdx.x; e < TBK * TBK; e += blockDim.x) {
-        int r = e >> 6, c = e & 63;
-        s[r * LDT + c] = g[int64_t(r) * ld + c];
+    double v[kTilePer];
+#pragma unroll
+    for (int q = 0; q < kTilePer; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        v[q] = g[int64_t(e >> 6) * ld + (e & 63)];
+    }
+#pragma unroll
+    for (int q = 0; q < kTilePer; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        s[(e >> 6) * LDT + (e & 63)] = v[q];
     }
 }
 
 __device__ __forceinline__ void tile_store(const double* __restrict__ s, double* __restrict__ g, int64_t ld) {
-    for (int e = threadIdx.x; e < TBK * TBK; e += blockDim.x) {
-        int r = e >> 6, c = e & 63;
-        g[int64_t(r) * ld + c] = s[r * LDT + c];
+    double v[kTilePer];
+#pragma unroll
+    for (int q = 0; q < kTilePer; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        v[q] = s[(e >> 6) * LDT + (e & 63)];
+    }
+#pragma unroll
+    for (int q = 0; q < kTilePer; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        g[int64_t(e >> 6) * ld + (e & 63)] = v[q];
+    }
+}
+
+// global 64 x 64 tile copy: dst (row stride ld) <- src (contiguous)
+__device__ __forceinline__ void tile_copy(double* __restrict__ dst, int64_t ld, const double* __restrict__ src) {
+    double v[kTilePer];
+#pragma unroll
+    for (int q = 0; q < kTilePer; ++q) v[q] = src[threadIdx.x + 256 * q];
+#pragma unroll
+    for (int q = 0; q < kTilePer; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        dst[int64_t(e >> 6) * ld + (e & 63)] = v[q];
     }
 }
 
@@ -81,13 +112,17 @@ __device__ __forceinline__ void mfma_store(const f64x4 (&acc)[4], double* __rest
                                            bool accumulate) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int i = lane & 15, kk = lane >> 4;
+    double old[4][4];   // read everything before the first write: one memory latency, not sixteen
 #pragma unroll
     for (int n = 0; n < 4; ++n)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            double* e = g + int64_t(16 * w + kk + 4 * r) * ld + 16 * n + i;
-            *e = accumulate ? fma(scale, acc[n][r], *e) : scale * acc[n][r];
-        }
+        for (int r = 0; r < 4; ++r)
+            old[n][r] = accumulate ? g[int64_t(16 * w + kk + 4 * r) * ld + 16 * n + i] : 0.0;
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            g[int64_t(16 * w + kk + 4 * r) * ld + 16 * n + i] = accumulate ? fma(scale, acc[n][r], old[n][r]) : scale * acc[n][r];
 }
 
 // --- gather: A_b = W[idx_b, idx_b] padded with the identity ---------------------------------
@@ -98,12 +133,18 @@ __global__ __launch_bounds__(256) void k_gather(const int4* __restrict__ tasks, 
     const BlockMeta m = meta[t.x];
     const int32_t* id = idx + m.idx_off;
     double* a = A + m.mat_off;
-    for (int e = threadIdx.x; e < TBK * TBK; e += blockDim.x) {
+    double v[kTilePer];   // all of a thread's loads in flight before the stores
+#pragma unroll
+    for (int q = 0; q < kTilePer; ++q) {
+        const int e = threadIdx.x + 256 * q;
         const int64_t r = int64_t(t.y) * TBK + (e >> 6), c = int64_t(t.z) * TBK + (e & 63);
-        double v;
-        if (r < m.n && c < m.n) v = W[int64_t(id[r]) * ldw + id[c]];
-        else v = (r == c) ? 1.0 : 0.0;
-        a[r * m.npad + c] = v;
+        v[q] = (r < m.n && c < m.n) ? W[int64_t(id[r]) * ldw + id[c]] : ((r == c) ? 1.0 : 0.0);
+    }
+#pragma unroll
+    for (int q = 0; q < kTilePer; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        const int64_t r = int64_t(t.y) * TBK + (e >> 6), c = int64_t(t.z) * TBK + (e & 63);
+        a[r * m.npad + c] = v[q];
     }
 }
 
@@ -185,9 +226,16 @@ __device__ __forceinline__ double* tile_at(double* a0, const BlockMeta& m, int i
 
 // LDS tile <- sign * G^T (G a 64 x 64 tile in global memory with row stride ld)
 __device__ __forceinline__ void tile_load_t(double* __restrict__ s, const double* __restrict__ g, int64_t ld, double sign) {
-    for (int e = threadIdx.x; e < TBK * TBK; e += blockDim.x) {
-        const int r = e >> 6, c = e & 63;
-        s[c * LDT + r] = sign * g[int64_t(r) * ld + c];
+    double v[kTilePer];
+#pragma unroll
+    for (int q = 0; q < kTilePer; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        v[q] = g[int64_t(e >> 6) * ld + (e & 63)];
+    }
+#pragma unroll
+    for (int q = 0; q < kTilePer; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        s[(e & 63) * LDT + (e >> 6)] = sign * v[q];
     }
 }
 
@@ -265,7 +313,7 @@ __global__ __launch_bounds__(256) void k_gj_update(const int4* __restrict__ task
     double* gij = tile_at(a0, m, i, j);
     if (i == k || j == k) {
         const double* src = (i == k && j == k) ? gj_piv(scr, pivot_off, t.x, k) : (i == k) ? gj_R(scr, m, j) : gj_D(scr, m, i);
-        for (int e = threadIdx.x; e < TBK * TBK; e += blockDim.x) gij[int64_t(e >> 6) * m.npad + (e & 63)] = src[e];
+        tile_copy(gij, m.npad, src);
         return;
     }
     tile_load(P, gj_C(scr, m, i), TBK);
@@ -332,7 +380,29 @@ __global__ __launch_bounds__(256) void k_coarse_Z(const double* __restrict__ W, 
     const int64_t i = t % nH;
     const int64_t c0 = (t / nH) * kZCols + threadIdx.x;
     double acc[2] = {0.0, 0.0};
-    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+    // eight support rows per pass, their loads issued together (the rows of a coarse function's
+    // support are scattered over W, so each pass is one round of memory latency)
+    constexpr int kU = 8;
+    const int64_t e0 = rp[i], e1 = rp[i + 1];
+    int64_t e = e0;
+    for (; e + kU <= e1; e += kU) {
+        double v[kU], x[kU][2];
+#pragma unroll
+        for (int q = 0; q < kU; ++q) {
+            v[q] = rv[e + q];
+            const double* w = W + int64_t(rc[e + q]) * ldw;
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int64_t c = c0 + 256 * u;
+                x[q][u] = c < N ? w[c] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kU; ++q)
+#pragma unroll
+            for (int u = 0; u < 2; ++u) acc[u] = fma(v[q], x[q][u], acc[u]);
+    }
+    for (; e < e1; ++e) {
         const double v = rv[e];
         const double* w = W + int64_t(rc[e]) * ldw;
 #pragma unroll

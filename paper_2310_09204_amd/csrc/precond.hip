@@ -538,9 +538,13 @@ __global__ __launch_bounds__(256) void k_coarse_solve(const double* __restrict__
     const double* b = Binv + i * npad;
     for (int64_t j = lane; j < nH; j += 64) {
         const double bij = b[j];
+        // columns past k repeat column k - 1 (in bounds, never stored), so the loads need no
+        // branches and all issue before the first is used
+        double xv[16];
 #pragma unroll
-        for (int c = 0; c < 16; ++c)
-            if (c < k) acc[c] = fma(bij, x[int64_t(c) * nH + j], acc[c]);
+        for (int c = 0; c < 16; ++c) xv[c] = x[int64_t(c < k ? c : k - 1) * nH + j];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) acc[c] = fma(bij, xv[c], acc[c]);
     }
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
@@ -559,7 +563,19 @@ __global__ void k_prolong_add(const int64_t* __restrict__ tp, const int32_t* __r
     if (j >= N) return;
     const double* u = zc + int64_t(c) * nH;
     double s = 0.0;
-    for (int64_t e = tp[j]; e < tp[j + 1]; ++e) s = fma(tv[e], u[tr[e]], s);
+    const int64_t e0 = tp[j], e1 = tp[j + 1];
+    int64_t e = e0;
+    for (; e + 4 <= e1; e += 4) {   // four entries' loads in flight at a time
+        double v[4], y[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            v[q] = tv[e + q];
+            y[q] = u[tr[e + q]];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s = fma(v[q], y[q], s);
+    }
+    for (; e < e1; ++e) s = fma(tv[e], u[tr[e]], s);
     z[int64_t(c) * ld + j] += s;
 }
 

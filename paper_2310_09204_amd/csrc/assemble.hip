@@ -733,14 +733,23 @@ __global__ __launch_bounds__(256) void k_contract_staged(
     const int ne = ev ? int(dof_ptr[e + 1] - kb) : 0;
     int loc[kRegC];
     double Jx[kRegC], Jy[kRegC], Jz[kRegC];
+    // unconditional loads of in-range entries (entries past the star repeat its last one, or entry
+    // 0 for a padding column), masked afterwards: all of them are in flight together
+    const int64_t klast = ne > 0 ? kb + ne - 1 : 0;
 #pragma unroll
     for (int k = 0; k < kRegC; ++k) {
-        const bool h = k < ne;
-        loc[k] = h ? col_loc[kb + k] : 0;
-        Jx[k] = h ? dof_J[3 * (kb + k)] : 0.0;
-        Jy[k] = h ? dof_J[3 * (kb + k) + 1] : 0.0;
-        Jz[k] = h ? dof_J[3 * (kb + k) + 2] : 0.0;
+        const int64_t q = min<int64_t>(kb + k, klast);
+        loc[k] = col_loc[q];
+        Jx[k] = dof_J[3 * q];
+        Jy[k] = dof_J[3 * q + 1];
+        Jz[k] = dof_J[3 * q + 2];
     }
+#pragma unroll
+    for (int k = 0; k < kRegC; ++k)
+        if (k >= ne) {
+            loc[k] = 0;
+            Jx[k] = Jy[k] = Jz[k] = 0.0;
+        }
     const int c0 = cb_ptr[be];
     const int nc = cb_ptr[be + 1] - c0;
     int cidx[kRegC];

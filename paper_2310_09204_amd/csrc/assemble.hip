@@ -702,16 +702,79 @@ __global__ __launch_bounds__(256) void k_contract(const double* __restrict__ I, 
 // triangles.  With y_T(e) = sum over the star of e of J(T',e) I(T,T'), an entry is
 // W(d,e) = sum over T in the star of d of J(T,d) . y_T(e).  The 64 columns of a tile share one
 // sorted list C of the triangles in their stars (at most kCap), and each lane holds the first kRegC
-// entries of its column's star as positions in C (longer junction stars finish from memory).  Wave w of the block owns 16 rows; it walks the triangles T of their stars
-// (one group per triangle, prepared on the host), loads I(T, C) once with neighbouring lanes on
-// neighbouring list entries, stages it in LDS, forms y_T for all 64 columns from LDS and adds
-// J(T,d) . y_T into the rows d whose star holds T.  The next group's I(T, C) is in flight while the
-// current one is used.  Accumulators live in LDS, which then feeds both the direct and the
-// mirrored (transposed) coalesced write.  Columns past N (the padding of W) are written as zero.
+// entries of its column's star as positions in C (longer junction stars finish from memory).  Wave
+// w of the block owns 16 rows; it walks the triangles T of their stars (one group per triangle,
+// prepared on the host), loads I(T, C) once with neighbouring lanes on neighbouring list entries,
+// stages it in LDS, forms y_T for all 64 columns from LDS and adds J(T,d) . y_T into the rows d
+// whose star holds T.  Accumulators live in LDS, which then feeds both the direct and the mirrored
+// (transposed) coalesced write.  Columns past N (the padding of W) are written as zero.
 constexpr int kRegC = 8;
 constexpr int kCap = kCT * kRegC;
 
-__global__ __launch_bounds__(256) void k_contract_staged(
+// One wave's walk over its groups for a column list of NCH chunks of 64 entries.  The segment
+// I(T, C) of a group is loaded two groups ahead, every chunk of it unconditionally (lanes past the
+// list repeat its last entry, and the two loads past the last group repeat that group), so each
+// wait for a segment leaves the younger segment's loads in flight.  An odd group count ends with a
+// step that stages a segment and adds nothing.
+template <int NCH>
+__device__ __forceinline__ void contract_walk(
+    const double* __restrict__ I, int64_t ldI, const int32_t* __restrict__ rowmap, const int32_t* __restrict__ ctri,
+    int nc, int64_t col0, const int4* __restrict__ rg, const int2* __restrict__ rg_ent, int g0, int g1,
+    const double* __restrict__ dof_J, const int32_t* __restrict__ col_loc, int64_t kb, int ne, const int (&loc)[kRegC],
+    const double (&Jx)[kRegC], const double (&Jy)[kRegC], const double (&Jz)[kRegC], double* __restrict__ sw,
+    double* __restrict__ arow, int lane) {
+    if (g0 >= g1) return;
+    int cidx[NCH];
+#pragma unroll
+    for (int m = 0; m < NCH; ++m) cidx[m] = ctri[min(m * kCT + lane, nc - 1)] - int32_t(col0);
+    double A[NCH], B[NCH];
+    auto fetch = [&](double (&dst)[NCH], int g) {
+        const int T = rg[min(g, g1 - 1)].x;
+        const double* row = I + int64_t(rowmap ? rowmap[T] : T) * ldI;
+#pragma unroll
+        for (int m = 0; m < NCH; ++m) dst[m] = row[cidx[m]];
+    };
+    auto step = [&](double (&cur)[NCH], int g) {
+        const int4 G = rg[min(g, g1 - 1)];   // (triangle, rows, first entry, -)
+        const int ny = g < g1 ? G.y : 0;
+#pragma unroll
+        for (int m = 0; m < NCH; ++m) sw[m * kCT + lane] = cur[m];
+        fetch(cur, g + 2);
+        __builtin_amdgcn_wave_barrier();   // sw belongs to this wave: order write -> read
+        double yx = 0.0, yy = 0.0, yz = 0.0;
+#pragma unroll
+        for (int k = 0; k < kRegC; ++k) {
+            const double v = sw[loc[k]];
+            yx = fma(Jx[k], v, yx);
+            yy = fma(Jy[k], v, yy);
+            yz = fma(Jz[k], v, yz);
+        }
+        if (ne > kRegC) {   // junction columns: star entries past the registers, from memory
+            for (int k = kRegC; k < ne; ++k) {
+                const int64_t q = kb + k;
+                const double v = sw[col_loc[q]];
+                yx = fma(dof_J[3 * q], v, yx);
+                yy = fma(dof_J[3 * q + 1], v, yy);
+                yz = fma(dof_J[3 * q + 2], v, yz);
+            }
+        }
+        for (int i = 0; i < ny; ++i) {
+            const int2 en = rg_ent[G.z + i];   // (row in the wave's 16, star entry of that row)
+            const double* j = dof_J + 3 * int64_t(en.y);
+            double& a = arow[en.x * (kCT + 1) + lane];
+            a = fma(j[0], yx, fma(j[1], yy, fma(j[2], yz, a)));
+        }
+        __builtin_amdgcn_wave_barrier();   // reads of sw done before the next step overwrites it
+    };
+    fetch(A, g0);
+    fetch(B, g0 + 1);
+    for (int g = g0; g < g1; g += 2) {
+        step(A, g);
+        step(B, g + 1);
+    }
+}
+
+__global__ __launch_bounds__(256, 3) void k_contract_staged(
     const double* __restrict__ I, int64_t ldI, const int32_t* __restrict__ rowmap, int64_t col0, int64_t N,
     const int32_t* __restrict__ cb_ptr,
     const int32_t* __restrict__ cb_tri, const int64_t* __restrict__ dof_ptr, const int32_t* __restrict__ col_loc,
@@ -752,57 +815,20 @@ __global__ __launch_bounds__(256) void k_contract_staged(
         }
     const int c0 = cb_ptr[be];
     const int nc = cb_ptr[be + 1] - c0;
-    int cidx[kRegC];
-#pragma unroll
-    for (int m = 0; m < kRegC; ++m) {
-        const int j = m * kCT + lane;
-        cidx[m] = cb_tri[c0 + min(j, nc - 1)] - int32_t(col0);   // lanes past the list repeat its last entry
-    }
     double* arow = &acc[wave * 16][0];
 #pragma unroll
     for (int r = 0; r < 16; ++r) arow[r * (kCT + 1) + lane] = 0.0;
     const int rb = bd * 4 + wave;
     const int g0 = rg_ptr[rb], g1 = rg_ptr[rb + 1];
-    double nxt[kRegC];
-    // chunk 0 is always fetched and staged so that position 0 of the list holds a finite value
-    auto fetch = [&](int T) {
-        const double* row = I + int64_t(rowmap ? rowmap[T] : T) * ldI;
-#pragma unroll
-        for (int m = 0; m < kRegC; ++m)
-            if (m == 0 || m * kCT < nc) nxt[m] = row[cidx[m]];
-    };
-    if (g0 < g1) fetch(rg[g0].x);
-    for (int g = g0; g < g1; ++g) {
-        const int4 G = rg[g];   // (triangle, rows, first entry, -)
-#pragma unroll
-        for (int m = 0; m < kRegC; ++m)
-            if (m == 0 || m * kCT < nc) seg[wave][m * kCT + lane] = nxt[m];
-        if (g + 1 < g1) fetch(rg[g + 1].x);
-        __builtin_amdgcn_wave_barrier();   // seg[wave] belongs to this wave: order write -> read
-        double yx = 0.0, yy = 0.0, yz = 0.0;
-#pragma unroll
-        for (int k = 0; k < kRegC; ++k) {
-            const double v = seg[wave][loc[k]];
-            yx = fma(Jx[k], v, yx);
-            yy = fma(Jy[k], v, yy);
-            yz = fma(Jz[k], v, yz);
-        }
-        if (ne > kRegC) {   // junction columns: star entries past the registers, from memory
-            for (int k = kRegC; k < ne; ++k) {
-                const int64_t q = kb + k;
-                const double v = seg[wave][col_loc[q]];
-                yx = fma(dof_J[3 * q], v, yx);
-                yy = fma(dof_J[3 * q + 1], v, yy);
-                yz = fma(dof_J[3 * q + 2], v, yz);
-            }
-        }
-        for (int i = 0; i < G.y; ++i) {
-            const int2 en = rg_ent[G.z + i];   // (row in the wave's 16, star entry of that row)
-            const double* j = dof_J + 3 * int64_t(en.y);
-            double& a = arow[en.x * (kCT + 1) + lane];
-            a = fma(j[0], yx, fma(j[1], yy, fma(j[2], yz, a)));
-        }
-        __builtin_amdgcn_wave_barrier();   // reads of seg done before the next group overwrites it
+    switch ((nc + kCT - 1) / kCT) {
+#define BEM_WALK(n)                                                                                                   \
+    case n:                                                                                                           \
+        contract_walk<n>(I, ldI, rowmap, cb_tri + c0, nc, col0, rg, rg_ent, g0, g1, dof_J,  col_loc, kb, ne, loc, Jx, \
+                         Jy, Jz, seg[wave], arow, lane);                                                              \
+        break;
+        BEM_WALK(1) BEM_WALK(2) BEM_WALK(3) BEM_WALK(4) BEM_WALK(5) BEM_WALK(6) BEM_WALK(7) BEM_WALK(8)
+#undef BEM_WALK
+        default: break;   // the host sends longer lists to the general kernel
     }
     __syncthreads();
 #pragma unroll

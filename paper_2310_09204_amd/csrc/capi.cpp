@@ -42,6 +42,11 @@ size_t size_class(size_t b) {
 // leaves an error already pending on this thread untouched
 void collect(MemPool& P) {
     if (P.pending.empty() || hipPeekAtLastError() != hipSuccess) return;
+    // the events may have been recorded on a stream that another thread is now capturing, and a
+    // query of such an event can invalidate that capture: while a capture is under way (it holds
+    // the capture mutex) the pending buffers wait for a later allocation
+    std::unique_lock<std::mutex> cap(capture_mutex(), std::try_to_lock);
+    if (!cap.owns_lock()) return;
     for (size_t i = 0; i < P.pending.size();) {
         const hipError_t q = hipEventQuery(P.pending[i].ev);
         if (q == hipSuccess) {
@@ -79,6 +84,17 @@ hipStream_t acquire_stream(bem_ctx* c) {
 
 void release_stream(bem_ctx* c, hipStream_t st) {
     if (!st) return;
+    // a stream that is still in (or was broken by) a capture is destroyed, not handed out again:
+    // every call on it would fail
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+        hipGraph_t g = nullptr;
+        if (hipStreamEndCapture(st, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        std::lock_guard<std::mutex> cap(capture_mutex());
+        (void)hipStreamDestroy(st);
+        return;
+    }
     std::lock_guard<std::mutex> lk(c->stream_mu);
     c->free_streams.push_back(st);
 }

@@ -790,6 +790,18 @@ PcgResult pcg_device(bem_problem* p, const bem_precond* M, bool mixed, const dou
             } else if (capture_error(e)) {
                 (void)hipGetLastError();
                 graphed = false;
+                // an invalidated capture can leave the stream in capture mode: end it again, and
+                // refuse to go on with a stream that stays there
+                hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+                for (int tries = 0; tries < 2; ++tries) {
+                    if (hipStreamIsCapturing(s, &cs) != hipSuccess) cs = hipStreamCaptureStatusInvalidated;
+                    if (cs == hipStreamCaptureStatusNone) break;
+                    hipGraph_t g2 = nullptr;
+                    if (hipStreamEndCapture(s, &g2) == hipSuccess && g2) (void)hipGraphDestroy(g2);
+                    (void)hipGetLastError();
+                }
+                if (cs != hipStreamCaptureStatusNone)
+                    fail(BEM_E_DEVICE, "the problem's stream stayed in capture mode after an invalidated capture");
             } else {
                 HIP_CHECK(e);
             }

@@ -72,8 +72,11 @@ typedef struct {
     int64_t n_dofs, n_tri, n_vert, n_near_pairs;
     int64_t bytes_device;    /* device memory held by the problem */
     int64_t q_hist[16];      /* number of vertices with q sectors (q >= 15 in the last bin) */
-    double t_assemble_s;     /* wall time of bem_assemble (device work, synchronised) */
-    double t_far_s, t_near_s, t_contract_s; /* device time of the three assembly phases */
+    double t_assemble_s;     /* wall time of bem_assemble: it returns once the device has consumed the
+                                inputs; the contraction into W may still run (later calls on the problem
+                                queue behind it, and the copy calls wait for it) */
+    double t_far_s, t_near_s, t_contract_s; /* device time of the three assembly phases (t_contract_s
+                                                NaN while the contraction still runs) */
     double t_host_s;         /* host time of the mesh analysis and near-pair list */
     int64_t n_pair_panels;   /* panels the pair matrix was built in (0: in one piece) */
     int64_t dim;             /* 3: triangle mesh (n_tri triangles); 2: segment mesh (n_tri segments) */
@@ -137,8 +140,10 @@ int bem_mesh_analyze(const double* vertices, int64_t nv, const int32_t* triangle
  * I uses a 7-point degree-5 rule on each triangle of pairs with no common vertex and
  * Duffy-regularised Gauss-Legendre rules (near_order points per axis) on pairs with a common
  * vertex, edge, or triangle.  W is stored FP64 row-major; with BEM_FP32_REFINE also as FP32.
+ * The call returns once the device has read the inputs; the last kernel (the contraction into W)
+ * may still be running then.  Every later call on the problem is ordered after it.
  * Errors: BEM_E_INVALID_ARG, BEM_E_DEGENERATE, BEM_E_MESH_NONCONFORMING, BEM_E_POINT_CONTACT,
- * BEM_E_OOM, BEM_E_DEVICE. */
+ * BEM_E_OOM, BEM_E_DEVICE (a fault of the unfinished contraction surfaces in a later call). */
 int bem_assemble(bem_ctx* ctx, const double* vertices, int64_t nv, const int32_t* triangles,
                  int64_t nt, const bem_assemble_opts* opts, bem_problem** out);
 /* The same assembly with the mesh also resident on the device: vertices / triangles (host) feed

@@ -920,8 +920,8 @@ struct EventTimer {
     EventTimer(const EventTimer&) = delete;
     EventTimer& operator=(const EventTimer&) = delete;
     ~EventTimer() {
-        (void)hipEventDestroy(a);
-        (void)hipEventDestroy(b);
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
     }
 };
 
@@ -1362,6 +1362,7 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
             DeviceBuffer d_col_loc = upload(plan.col_loc, s), d_rg_ptr = upload(plan.rg_ptr, s);
             DeviceBuffer d_rg = upload(plan.rg, s), d_rg_ent = upload(plan.rg_ent, s);
             DeviceBuffer d_fast = upload(plan.fast, s), d_slow = upload(plan.slow, s);
+            matvec_setup(p, s);   // its uploads too come before the event the host waits for
             HIP_CHECK(hipEventRecord(t_contract.a, s));
             const int64_t nf = int64_t(plan.fast.size()), ns = int64_t(plan.slow.size());
             if (nf > 0) {
@@ -1386,12 +1387,26 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
         ptimes = assemble_panels(p, m, near, plan, geo.as<double>(), gbounds.as<double>(), crec.as<double>(), dVp,
                                  dgx.as<double>(), dgw.as<double>(), dofJ.as<double>(), w32, mark);
     }
-    matvec_setup(p, s);
-    HIP_CHECK(hipStreamSynchronize(s));
-    if (!p->has_pairs) p->I.reset();   // idle now: back to the cache
+    if (paneled || N == 0) {
+        matvec_setup(p, s);
+        HIP_CHECK(hipStreamSynchronize(s));
+    } else {
+        // The host returns once the inputs are consumed: the event before the contraction follows
+        // the last kernel that reads the mesh and the last upload from host memory.  The
+        // contraction itself runs on; every later call on the problem queues behind it on the
+        // problem's stream, and the calls that read W on other paths synchronise that stream.
+        HIP_CHECK(hipEventSynchronize(t_contract.a));
+    }
+    if (!p->has_pairs) p->I.reset();   // released in stream order, after the contraction
     p->t_far = paneled ? ptimes.far : t_far.seconds();
     p->t_near = paneled ? ptimes.near : t_near.seconds();
-    p->t_contract = paneled ? ptimes.contract : t_contract.seconds();
+    if (paneled || N == 0) {
+        p->t_contract = paneled ? ptimes.contract : t_contract.seconds();
+    } else {   // read when the problem's information is first asked for
+        p->ev_contract[0] = t_contract.a;
+        p->ev_contract[1] = t_contract.b;
+        t_contract.a = t_contract.b = nullptr;
+    }
     p->n_panels = paneled ? ptimes.panels : 0;
 }
 

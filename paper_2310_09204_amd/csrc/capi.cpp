@@ -493,6 +493,8 @@ void bem_problem_destroy(bem_problem* p) {
     (void)hipSetDevice(p->ctx->device);
     if (p->stream) (void)hipStreamSynchronize(p->stream);
     if (p->aux_stream) (void)hipStreamSynchronize(p->aux_stream);
+    for (hipEvent_t& e : p->ev_contract)
+        if (e) (void)hipEventDestroy(e);
     hipStream_t s = p->stream, s2 = p->aux_stream;
     bem_ctx* ctx = p->ctx;
     delete p;
@@ -514,7 +516,23 @@ int bem_problem_get_info(const bem_problem* p, bem_problem_info* info) {
     info->t_assemble_s = p->t_assemble;
     info->t_far_s = p->t_far;
     info->t_near_s = p->t_near;
-    info->t_contract_s = p->t_contract;
+    if (p->ev_contract[1]) {   // the contraction's time, once it has finished (the call never waits)
+        set_device(p->ctx);
+        const hipError_t q = hipEventQuery(p->ev_contract[1]);
+        if (q == hipSuccess) {
+            float ms = 0.f;
+            HIP_CHECK(hipEventElapsedTime(&ms, p->ev_contract[0], p->ev_contract[1]));
+            p->t_contract = ms * 1e-3;
+            (void)hipEventDestroy(p->ev_contract[0]);
+            (void)hipEventDestroy(p->ev_contract[1]);
+            p->ev_contract[0] = p->ev_contract[1] = nullptr;
+        } else if (q == hipErrorNotReady) {
+            (void)hipGetLastError();
+        } else {
+            HIP_CHECK(q);
+        }
+    }
+    info->t_contract_s = p->ev_contract[1] ? std::nan("") : p->t_contract;
     info->t_host_s = p->t_host;
     info->n_pair_panels = p->n_panels;
     info->dim = p->topo.dim;
@@ -537,6 +555,7 @@ int bem_problem_copy_matrix(const bem_problem* p, int64_t row0, int64_t nrows, d
     if (row0 < 0 || nrows < 0 || row0 + nrows > p->N) fail(BEM_E_INVALID_ARG, "row range outside the matrix");
     set_device(p->ctx);
     if (nrows == 0) return BEM_OK;
+    HIP_CHECK(hipStreamSynchronize(p->stream));   // the contraction may still be writing W
     HIP_CHECK(hipMemcpy2D(out, sizeof(double) * p->N, p->W64.as<double>() + row0 * p->ldw, sizeof(double) * p->ldw,
                           sizeof(double) * p->N, size_t(nrows), hipMemcpyDeviceToHost));
     return BEM_OK;
@@ -547,6 +566,7 @@ int bem_problem_copy_rows(const bem_problem* p, const int64_t* rows, int64_t nro
     BEM_TRY
     if (!p || (!rows && nrows) || (!out && nrows)) fail(BEM_E_INVALID_ARG, "NULL argument");
     set_device(p->ctx);
+    HIP_CHECK(hipStreamSynchronize(p->stream));   // the contraction may still be writing W
     for (int64_t i = 0; i < nrows; ++i) {
         if (rows[i] < 0 || rows[i] >= p->N) fail(BEM_E_INVALID_ARG, "row index out of range");
         HIP_CHECK(hipMemcpy(out + i * p->N, p->W64.as<double>() + rows[i] * p->ldw, sizeof(double) * p->N, hipMemcpyDeviceToHost));
@@ -560,6 +580,7 @@ int bem_problem_pair_integrals(const bem_problem* p, const int32_t* pairs, int64
     if (!p || (!pairs && npairs) || (!out && npairs)) fail(BEM_E_INVALID_ARG, "NULL argument");
     if (!p->has_pairs || !p->I.ptr) fail(BEM_E_INVALID_ARG, "assemble with keep_pair_matrix = 1");
     set_device(p->ctx);
+    HIP_CHECK(hipStreamSynchronize(p->stream));
     const int64_t nt = p->topo.nt;
     std::vector<double> row(nt);
     for (int64_t i = 0; i < npairs; ++i) {

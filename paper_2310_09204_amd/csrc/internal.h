@@ -212,7 +212,11 @@ struct bem_problem {
     // double-layer potential: per-triangle records (normal, Gauss points, n . y) and the 7-point rule,
     // built on the first evaluation
     bem::DeviceBuffer dl_rec, dl_rule;
-    double t_assemble = 0, t_far = 0, t_near = 0, t_contract = 0, t_host = 0;
+    double t_assemble = 0, t_far = 0, t_near = 0, t_host = 0;
+    // device time of the contraction: bem_assemble returns while it still runs, so its two events
+    // are kept and read when the information is first asked for
+    mutable double t_contract = 0;
+    mutable hipEvent_t ev_contract[2] = {nullptr, nullptr};
     int64_t bytes = 0;
 };
 

@@ -279,8 +279,13 @@ class Problem:
             dV, dT = device_mesh
             _check(load().bem_assemble_dev(ctx.handle, _p(self.V), ctypes.c_void_p(dV), self.V.shape[0], _p(self.T),
                                            ctypes.c_void_p(dT), self.T.shape[0], ctypes.byref(o), ctypes.byref(self._h)))
-        self.info = self.get_info()
-        self.N = self.info["n_dofs"]
+        self.N = self.get_info()["n_dofs"]
+
+    @property
+    def info(self):
+        """bem_problem_get_info, read at each access (t_contract_s is NaN while the contraction that
+        bem_assemble leaves running has not finished)."""
+        return self.get_info()
 
     def get_info(self):
         i = ProblemInfo()
@@ -423,8 +428,7 @@ class Problem2D(Problem):
         self._h = ctypes.c_void_p()
         _check(load().bem_assemble_2d(ctx.handle, _p(self.V), self.V.shape[0], _p(self.T), self.T.shape[0],
                                       ctypes.byref(o), ctypes.byref(self._h)))
-        self.info = self.get_info()
-        self.N = self.info["n_dofs"]
+        self.N = self.get_info()["n_dofs"]
 
     def solve(self, g=None, **kw):
         """As Problem.solve; g may be given as 2-vectors."""

@@ -516,6 +516,7 @@ int bem_problem_get_info(const bem_problem* p, bem_problem_info* info) {
     info->t_assemble_s = p->t_assemble;
     info->t_far_s = p->t_far;
     info->t_near_s = p->t_near;
+    std::lock_guard<std::mutex> lk(p->info_mu);
     if (p->ev_contract[1]) {   // the contraction's time, once it has finished (the call never waits)
         set_device(p->ctx);
         const hipError_t q = hipEventQuery(p->ev_contract[1]);

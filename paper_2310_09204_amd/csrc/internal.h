@@ -217,6 +217,7 @@ struct bem_problem {
     // are kept and read when the information is first asked for
     mutable double t_contract = 0;
     mutable hipEvent_t ev_contract[2] = {nullptr, nullptr};
+    mutable std::mutex info_mu;   // bem_problem_get_info may be called from several threads
     int64_t bytes = 0;
 };
 

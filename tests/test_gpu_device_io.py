@@ -30,3 +30,25 @@ def test_device_mesh_and_solution_match_host_entry_points(ctx, precision):
     assert [i["iters"] for i in info_d] == [i["iters"] for i in info_h]
     for x in (Mh, Md, ph, pd, out, dV, dT):
         x.close()
+
+
+def test_assembly_returns_before_its_contraction(ctx):
+    # bem_assemble may return while the contraction into W still runs: the copy calls wait for it,
+    # later calls queue behind it, and its device time is reported once it has finished
+    m = meshes.crossed(24)
+    print("case early return crossed24", flush=True)
+    dV, dT = lib.DeviceArray(np.asarray(m.vertices, dtype=np.float64)), lib.DeviceArray(np.asarray(m.triangles, dtype=np.int32))
+    p = lib.Problem(ctx, m.vertices, m.triangles, near_order=4, device_mesh=(dV.ptr, dT.ptr))
+    dV.close()   # the device copy of the mesh may go as soon as the call has returned
+    dT.close()
+    t0 = p.info["t_contract_s"]
+    assert np.isnan(t0) or t0 > 0
+    W = p.matrix()
+    ref = lib.Problem(ctx, m.vertices, m.triangles, near_order=4)
+    ctx.synchronize()
+    assert np.array_equal(W, ref.matrix())
+    assert p.info["t_contract_s"] > 0 and ref.info["t_contract_s"] > 0
+    x = np.random.default_rng(2).standard_normal((3, p.N))
+    assert np.array_equal(p.matvec(x), ref.matvec(x))
+    p.close()
+    ref.close()

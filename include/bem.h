@@ -88,6 +88,11 @@ typedef struct {
     int wirebasket;          /* 0: exact Galerkin block of the wire basket (default); 1: its
                               * diagonal, the pointwise product of Remark "Approximate solvers"
                               * (Section 2), applied as R_W^T diag(W_WW)^{-1} R_W */
+    double diag_shift;       /* sigma added to the diagonal of every face, wire-basket and coarse
+                              * block before it is factorised (W_XX + sigma I; default 0).  A
+                              * positive shift regularises the local solvers; a shift below minus
+                              * the smallest eigenvalue of a block makes it indefinite, and the
+                              * set-up then fails with BEM_E_NOT_SPD. */
 } bem_precond_opts;
 
 typedef struct {
@@ -99,6 +104,9 @@ typedef struct {
                               * b - W x each time it has fallen by this factor (default 1e-3) */
     int check_every;         /* iterations between host convergence checks (default 4) */
     int use_graph;           /* 1: replay one captured iteration with hipGraphLaunch */
+    const double* x0;        /* NULL: x0 = 0; else host memory holding k x N start vectors
+                              * (column-major, column c at x0 + c N, canonical dof order); the
+                              * first residual is then L - W x0 with the FP64 matrix */
 } bem_solve_opts;
 
 typedef struct {
@@ -257,7 +265,7 @@ int bem_precond_sizes(const bem_precond* m, int64_t* n_faces, int64_t* n_wb, int
 int bem_precond_apply(const bem_precond* m, const double* r, int32_t k, double* z);
 
 /* ---- solve (Remark "Bound on the number of Preconditioned Conjugate Gradient iterations") -- */
-/* Solves W Phi = L for k constant Neumann vectors g[k][3] by (P)CG with x0 = 0 (or opts->x0),
+/* Solves W Phi = L for k constant Neumann vectors g[k][3] by (P)CG from x0 = 0 (or opts->x0),
  * preconditioned by M if m != NULL and opts->use_precond.  FP64 mode: W, vectors and factors in
  * FP64.  BEM_FP32_REFINE: PCG with products by the FP32 matrix and FP32 block inverses (FP64
  * vectors, dots, updates and coarse solve) and reliable updates: the recurrence residual is replaced

@@ -271,6 +271,10 @@ int solve_common(bem_problem* p, const bem_precond* m, const double* d_b, int32_
     if (o.check_every <= 0) o.check_every = 4;
     if (m && m->p != p) fail(BEM_E_INVALID_ARG, "preconditioner belongs to another problem");
     const int64_t N = p->N;
+    if (o.x0)
+        for (int64_t i = 0; i < N * k; ++i)
+            if (!std::isfinite(o.x0[i])) fail(BEM_E_INVALID_ARG, "non-finite entry in x0");
+    std::lock_guard<std::mutex> call(p->call_mu);
     std::vector<bem_solve_info> inf(k);
     // the iterate lives in the caller's device buffer when one is given
     DeviceBuffer x;
@@ -357,6 +361,7 @@ int bem_problem_bench_matvec(const bem_problem* p, int fp32, int32_t k, int reps
     set_device(p->ctx);
     const int64_t N = p->N;
     if (N == 0) { *seconds = 0; return BEM_OK; }
+    std::lock_guard<std::mutex> call(p->call_mu);
     DeviceBuffer x(sizeof(double) * N * k, p->stream), y(sizeof(double) * N * k, p->stream);
     std::vector<double> hx(size_t(N) * k);
     for (size_t i = 0; i < hx.size(); ++i) hx[i] = 1.0 / double(1 + (i % 97));
@@ -614,6 +619,7 @@ int bem_matvec(const bem_problem* p, const double* x, int32_t k, int fp32, doubl
     set_device(p->ctx);
     const int64_t N = p->N;
     if (N == 0) return BEM_OK;
+    std::lock_guard<std::mutex> call(p->call_mu);
     DeviceBuffer dx(sizeof(double) * N * k, p->stream), dy(sizeof(double) * N * k, p->stream);
     HIP_CHECK(hipMemcpyAsync(dx.ptr, x, sizeof(double) * N * k, hipMemcpyHostToDevice, p->stream));
     matvec_device(p, fp32 != 0, dx.as<double>(), N, k, dy.as<double>(), p->stream);
@@ -645,6 +651,7 @@ int bem_double_layer(bem_problem* p, const double* phi, int32_t k, const double*
     set_device(p->ctx);
     if (m == 0) return BEM_OK;
     const int64_t N = p->N;
+    std::lock_guard<std::mutex> call(p->call_mu);
     DeviceBuffer dp(sizeof(double) * std::max<int64_t>(1, N * k), p->stream), dx(sizeof(double) * 3 * m, p->stream),
         du(sizeof(double) * k * m, p->stream);
     if (N) HIP_CHECK(hipMemcpyAsync(dp.ptr, phi, sizeof(double) * N * k, hipMemcpyHostToDevice, p->stream));
@@ -670,6 +677,9 @@ int bem_precond_setup(bem_problem* p, const int32_t* patch_of_triangle, const do
     m->fp32 = opts ? opts->factor_fp32 != 0 : false;
     if (opts && (opts->wirebasket < 0 || opts->wirebasket > 1)) fail(BEM_E_INVALID_ARG, "wirebasket must be 0 or 1");
     m->wb_diag = opts ? opts->wirebasket == 1 : false;
+    m->diag_shift = opts ? opts->diag_shift : 0.0;
+    if (!std::isfinite(m->diag_shift)) fail(BEM_E_INVALID_ARG, "diag_shift is not finite");
+    std::lock_guard<std::mutex> call(p->call_mu);
     precond_setup_device(m.get(), patch_of_triangle, coarse_vertices, ncv, coarse_triangles, nct, coarse_of_triangle);
     *out = m.release();
     return BEM_OK;
@@ -690,6 +700,9 @@ int bem_precond_setup_2d(bem_problem* p, const int32_t* patch_of_segment, const 
     m->fp32 = opts ? opts->factor_fp32 != 0 : false;
     if (opts && (opts->wirebasket < 0 || opts->wirebasket > 1)) fail(BEM_E_INVALID_ARG, "wirebasket must be 0 or 1");
     m->wb_diag = opts ? opts->wirebasket == 1 : false;
+    m->diag_shift = opts ? opts->diag_shift : 0.0;
+    if (!std::isfinite(m->diag_shift)) fail(BEM_E_INVALID_ARG, "diag_shift is not finite");
+    std::lock_guard<std::mutex> call(p->call_mu);
     precond_setup_device(m.get(), patch_of_segment, coarse_vertices, ncv, coarse_segments, ncs, coarse_of_segment);
     *out = m.release();
     return BEM_OK;
@@ -721,6 +734,7 @@ int bem_precond_apply(const bem_precond* m, const double* r, int32_t k, double* 
     const bem_problem* p = m->p;
     set_device(p->ctx);
     const int64_t N = p->N;
+    std::lock_guard<std::mutex> call(p->call_mu);
     DeviceBuffer dr(sizeof(double) * N * k, m->p->stream), dz(sizeof(double) * N * k, m->p->stream);
     DeviceBuffer scr(sizeof(double) * precond_scratch_size(m, std::min(k, 16)), m->p->stream);
     HIP_CHECK(hipMemcpyAsync(dr.ptr, r, sizeof(double) * N * k, hipMemcpyHostToDevice, p->stream));

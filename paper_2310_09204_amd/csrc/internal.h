@@ -218,6 +218,10 @@ struct bem_problem {
     mutable double t_contract = 0;
     mutable hipEvent_t ev_contract[2] = {nullptr, nullptr};
     mutable std::mutex info_mu;   // bem_problem_get_info may be called from several threads
+    // calls that queue work using the problem's shared scratch (products, solves, preconditioner
+    // applications, potentials) take this lock, so two threads calling on one problem serialise
+    // instead of interleaving their kernels on its stream
+    mutable std::mutex call_mu;
     int64_t bytes = 0;
 };
 
@@ -270,6 +274,7 @@ struct bem_precond {
     // diagonal wire basket: its dofs and 1 / W_dd (then the wire basket is not one of the blocks)
     bool wb_diag = false;
     bem::DeviceBuffer wb_idx, wb_dinv;
+    double diag_shift = 0.0;        // sigma added to the diagonal of every block before factorising
     int64_t bytes = 0;
     double t_setup = 0;
 };

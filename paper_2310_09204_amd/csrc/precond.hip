@@ -128,7 +128,7 @@ __device__ __forceinline__ void mfma_store(const f64x4 (&acc)[4], double* __rest
 // --- gather: A_b = W[idx_b, idx_b] padded with the identity ---------------------------------
 __global__ __launch_bounds__(256) void k_gather(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
                                                 const int32_t* __restrict__ idx, const double* __restrict__ W,
-                                                int64_t ldw, double* __restrict__ A) {
+                                                int64_t ldw, double shift, double* __restrict__ A) {
     const int4 t = tasks[blockIdx.x];
     const BlockMeta m = meta[t.x];
     const int32_t* id = idx + m.idx_off;
@@ -138,7 +138,7 @@ __global__ __launch_bounds__(256) void k_gather(const int4* __restrict__ tasks, 
     for (int q = 0; q < kTilePer; ++q) {
         const int e = threadIdx.x + 256 * q;
         const int64_t r = int64_t(t.y) * TBK + (e >> 6), c = int64_t(t.z) * TBK + (e & 63);
-        v[q] = (r < m.n && c < m.n) ? W[int64_t(id[r]) * ldw + id[c]] : ((r == c) ? 1.0 : 0.0);
+        v[q] = (r < m.n && c < m.n) ? W[int64_t(id[r]) * ldw + id[c]] + ((r == c) ? shift : 0.0) : ((r == c) ? 1.0 : 0.0);
     }
 #pragma unroll
     for (int q = 0; q < kTilePer; ++q) {
@@ -419,8 +419,8 @@ __global__ __launch_bounds__(256) void k_coarse_Z(const double* __restrict__ W, 
 }
 
 __global__ void k_coarse_WH(const double* __restrict__ Z, int64_t N, int64_t nH, const int64_t* __restrict__ rp,
-                            const int32_t* __restrict__ rc, const double* __restrict__ rv, double* __restrict__ A,
-                            int64_t npad) {
+                            const int32_t* __restrict__ rc, const double* __restrict__ rv, double shift,
+                            double* __restrict__ A, int64_t npad) {
     const int64_t i2 = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     const int64_t i1 = blockIdx.y;
     if (i2 >= npad) return;
@@ -433,6 +433,7 @@ __global__ void k_coarse_WH(const double* __restrict__ Z, int64_t N, int64_t nH,
     double s = 0.0;
     const double* z = Z + i1 * N;
     for (int64_t e = rp[i2]; e < rp[i2 + 1]; ++e) s = fma(rv[e], z[rc[e]], s);
+    if (i1 == i2) s += shift;
     A[i1 * npad + i2] = s;
     A[i2 * npad + i1] = s;
 }
@@ -446,11 +447,11 @@ __global__ void k_coarse_pad_rows(double* __restrict__ A, int64_t nH, int64_t np
 
 // --- diagonal wire basket: dinv[e] = 1 / W[d][d] for its dofs d = idx[e]; flag if W_dd <= 0 ---
 __global__ void k_wb_diag_setup(const int32_t* __restrict__ idx, int64_t n, const double* __restrict__ W, int64_t ldw,
-                                double* __restrict__ dinv, int* __restrict__ flag) {
+                                double shift, double* __restrict__ dinv, int* __restrict__ flag) {
     const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (e >= n) return;
     const int64_t d = idx[e];
-    const double w = W[d * ldw + d];
+    const double w = W[d * ldw + d] + shift;
     if (!(w > 0.0)) *flag = 1;
     dinv[e] = 1.0 / w;
 }
@@ -944,7 +945,7 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
         const int4* d = T0 + L.off;
         const dim3 g(unsigned(L.n)), bl(256);
         switch (L.kind) {
-            case GATHER: hipLaunchKernelGGL(k_gather, g, bl, 0, st, d, dm, M->idx.as<int32_t>(), p->W64.as<double>(), p->ldw, A.as<double>()); break;
+            case GATHER: hipLaunchKernelGGL(k_gather, g, bl, 0, st, d, dm, M->idx.as<int32_t>(), p->W64.as<double>(), p->ldw, M->diag_shift, A.as<double>()); break;
             case GJ_ROW: hipLaunchKernelGGL(k_gj_row, g, bl, 0, st, d, dm, A.as<double>(), scr.as<double>(), pivot_off, L.param, dflags.as<int>()); break;
             case GJ_UPDATE: hipLaunchKernelGGL(k_gj_update, g, bl, 0, st, d, dm, A.as<double>(), scr.as<double>(), pivot_off, L.param, dflags.as<int>()); break;
             case MIRROR: hipLaunchKernelGGL(k_mirror, g, bl, 0, st, d, dm, A.as<double>()); break;
@@ -1008,7 +1009,7 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
         const BlockMeta& cm = meta[nall - 1];
         double* Ac = A.as<double>() + cm.mat_off;
         hipLaunchKernelGGL(k_coarse_WH, dim3(nblk(cm.npad, 256), unsigned(M->nH)), dim3(256), 0, s2, Z.as<double>(), f.N, M->nH,
-                           M->rh_ptr.as<int64_t>(), M->rh_col.as<int32_t>(), M->rh_val.as<double>(), Ac, cm.npad);
+                           M->rh_ptr.as<int64_t>(), M->rh_col.as<int32_t>(), M->rh_val.as<double>(), M->diag_shift, Ac, cm.npad);
         HIP_CHECK(hipGetLastError());
         if (cm.npad > M->nH) {
             hipLaunchKernelGGL(k_coarse_pad_rows, dim3(nblk(cm.npad, 256), unsigned(cm.npad - M->nH)), dim3(256), 0, s2, Ac, M->nH, cm.npad);
@@ -1030,7 +1031,7 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
         DeviceBuffer wflag(sizeof(int), s);
         HIP_CHECK(hipMemsetAsync(wflag.ptr, 0, sizeof(int), s));
         hipLaunchKernelGGL(k_wb_diag_setup, dim3(nblk(M->n_wb, 256)), dim3(256), 0, s, M->wb_idx.as<int32_t>(), M->n_wb,
-                           p->W64.as<double>(), p->ldw, M->wb_dinv.as<double>(), wflag.as<int>());
+                           p->W64.as<double>(), p->ldw, M->diag_shift, M->wb_dinv.as<double>(), wflag.as<int>());
         HIP_CHECK(hipGetLastError());
         int hf = 0;
         HIP_CHECK(hipMemcpyAsync(&hf, wflag.ptr, sizeof(int), hipMemcpyDeviceToHost, s));

@@ -164,7 +164,7 @@ void worker_main(bem_server* s) {
                 bem_problem* p = nullptr;
                 int c = bem_assemble(s->ctx, r0->V.data(), int64_t(r0->V.size() / 3), r0->T.data(), r0->nt, &ao, &p);
                 if (c != BEM_OK) fail(c, bem_last_error());
-                bem_precond_opts po{1, r0->precision == BEM_FP32_REFINE ? 1 : 0, 0};
+                bem_precond_opts po{1, r0->precision == BEM_FP32_REFINE ? 1 : 0, 0, 0.0};
                 bem_precond* m = nullptr;
                 c = bem_precond_setup(p, r0->patch.data(), r0->cV.empty() ? nullptr : r0->cV.data(), int64_t(r0->cV.size() / 3),
                                       r0->cT.empty() ? nullptr : r0->cT.data(), int64_t(r0->cT.size() / 3),

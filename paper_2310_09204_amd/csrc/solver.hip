@@ -886,11 +886,13 @@ void solve_device(bem_problem* p, const bem_precond* M, const double* b, double*
     std::vector<int> iters(k, 0), outer(k, 0), status(k, BEM_OK);
     std::vector<double> relres(k, 0.0), cond(k, std::nan(""));
 
-    hipLaunchKernelGGL(k_fill, dim3(256), vb, 0, s, x, 0.0, int64_t(k) * ld);
+    const bool x_nonzero = o.x0 != nullptr;
+    if (x_nonzero) HIP_CHECK(hipMemcpyAsync(x, o.x0, sizeof(double) * ld * k, hipMemcpyHostToDevice, s));
+    else hipLaunchKernelGGL(k_fill, dim3(256), vb, 0, s, x, 0.0, int64_t(k) * ld);
     bool final_check = true, graphed = false;
     if (o.precision == BEM_FP64) {
         std::vector<double> tol(k, o.tol);
-        PcgResult r = pcg_device(p, use_m ? M : nullptr, false, b, x, false, k, ld, tol, o.max_iter, check, o.use_graph != 0, true,
+        PcgResult r = pcg_device(p, use_m ? M : nullptr, false, b, x, x_nonzero, k, ld, tol, o.max_iter, check, o.use_graph != 0, true,
                                  0.0);
         graphed = r.graphed;
         for (int c = 0; c < k; ++c) {
@@ -904,7 +906,7 @@ void solve_device(bem_problem* p, const bem_precond* M, const double* b, double*
         if (use_m && !M->inv32.ptr) fail(BEM_E_INVALID_ARG, "mixed precision needs a preconditioner with factor_fp32 = 1");
         std::vector<double> tol(k, o.tol);
         const double refresh = (o.refresh_factor > 0 && o.refresh_factor < 1) ? o.refresh_factor : 1e-3;
-        PcgResult r = pcg_device(p, use_m ? M : nullptr, true, b, x, false, k, ld, tol, o.max_iter, check, o.use_graph != 0, true,
+        PcgResult r = pcg_device(p, use_m ? M : nullptr, true, b, x, x_nonzero, k, ld, tol, o.max_iter, check, o.use_graph != 0, true,
                                  refresh);
         graphed = r.graphed;
         final_check = false;

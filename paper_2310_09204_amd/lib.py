@@ -45,13 +45,14 @@ class ProblemInfo(ctypes.Structure):
 
 
 class PrecondOpts(ctypes.Structure):
-    _fields_ = [("use_coarse", ctypes.c_int), ("factor_fp32", ctypes.c_int), ("wirebasket", ctypes.c_int)]
+    _fields_ = [("use_coarse", ctypes.c_int), ("factor_fp32", ctypes.c_int), ("wirebasket", ctypes.c_int),
+                ("diag_shift", ctypes.c_double)]
 
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("use_precond", ctypes.c_int),
                 ("precision", ctypes.c_int), ("refresh_factor", ctypes.c_double), ("check_every", ctypes.c_int),
-                ("use_graph", ctypes.c_int)]
+                ("use_graph", ctypes.c_int), ("x0", ctypes.c_void_p)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -358,16 +359,22 @@ class Problem:
 
     def solve(self, g=None, rhs=None, precond=None, tol=1e-10, max_iter=2000, use_precond=True,
               precision=FP64, refresh_factor=1e-3, check_every=4, use_graph=True, raise_on_error=True,
-              device_out=None):
+              device_out=None, x0=None):
         """Returns (phi[k][N], [info dict per column], status code).  With device_out (the address
         of k x N doubles in device memory) and g, bem_pcg_solve_dev: phi stays there and None is
-        returned in its place."""
-        o = SolveOpts(tol, max_iter, int(use_precond), precision, refresh_factor, check_every, int(use_graph))
+        returned in its place.  x0: optional start vectors [k][N] (host)."""
+        x0a = None if x0 is None else _f64(np.atleast_2d(x0))
+        o = SolveOpts(tol, max_iter, int(use_precond), precision, refresh_factor, check_every, int(use_graph),
+                      None if x0a is None else x0a.ctypes.data)
         L = load()
         m = precond.handle if precond is not None else None
+        def _check_x0(k):
+            if x0a is not None and x0a.shape != (k, self.N):
+                raise ValueError("x0 must have shape (k, N)")
         if device_out is not None:
             g = _f64(np.atleast_2d(g))
             k = g.shape[0]
+            _check_x0(k)
             info = (SolveInfo * k)()
             rc = L.bem_pcg_solve_dev(self._h, m, _p(g), k, ctypes.byref(o), ctypes.c_void_p(device_out), info)
             if raise_on_error and rc < 0:
@@ -376,12 +383,14 @@ class Problem:
         if g is not None:
             g = _f64(np.atleast_2d(g))
             k = g.shape[0]
+            _check_x0(k)
             phi = np.empty((k, self.N))
             info = (SolveInfo * k)()
             rc = L.bem_pcg_solve(self._h, m, _p(g), k, ctypes.byref(o), _p(phi), info)
         else:
             rhs = _f64(np.atleast_2d(rhs))
             k = rhs.shape[0]
+            _check_x0(k)
             phi = np.empty((k, self.N))
             info = (SolveInfo * k)()
             rc = L.bem_pcg_solve_rhs(self._h, m, _p(rhs), k, ctypes.byref(o), _p(phi), info)
@@ -454,7 +463,7 @@ class Problem2D(Problem):
 
 class Preconditioner:
     def __init__(self, problem: Problem, patch_of_triangle, coarse_V=None, coarse_T=None, coarse_of_triangle=None,
-                 use_coarse=True, factor_fp32=False, wirebasket="exact"):
+                 use_coarse=True, factor_fp32=False, wirebasket="exact", diag_shift=0.0):
         self.problem = problem
         self.patch = _i32a(patch_of_triangle)
         if coarse_V is None:
@@ -465,7 +474,7 @@ class Preconditioner:
             ncv, nct = self.cV.shape[0], self.cT.shape[0]
         if wirebasket not in ("exact", "diagonal"):
             raise ValueError("wirebasket must be 'exact' or 'diagonal'")
-        o = PrecondOpts(int(use_coarse), int(factor_fp32), int(wirebasket == "diagonal"))
+        o = PrecondOpts(int(use_coarse), int(factor_fp32), int(wirebasket == "diagonal"), float(diag_shift))
         self._h = ctypes.c_void_p()
         # a segment-mesh problem takes coarse vertices n x 2 and coarse segments, patch and parent
         # per segment

@@ -169,35 +169,6 @@ def test_crossed96_sampled_rows_and_pairs(ctx):
     assert (np.abs(Ig - Io) / np.abs(Io)).max() < 1e-12
 
 
-def test_crossed192_panels_rows_and_solve(ctx):
-    # the largest configuration: the 391 GB pair matrix is built in panels; sampled rows against the
-    # oracle (its pure-Python topology pass dominates the run time), symmetry, and the mixed solve
-    w = meshes.workload("crossed192", seed=0, k=2)
-    m = w.mesh
-    print("case crossed192", m.nt, flush=True)
-    p = lib.Problem(ctx, m.vertices, m.triangles, near_order=NEAR, precision=lib.FP32_REFINE)
-    assert p.N == 110017 and p.info["n_pair_panels"] >= 2
-    dv, ds = p.dofs()
-    origin = np.nonzero(np.linalg.norm(m.vertices[dv], axis=1) < 1e-12)[0]
-    rows = np.unique(np.concatenate([np.random.default_rng(7).choice(p.N, 5, replace=False), origin[:1]]))
-    Wg = p.rows(rows)
-    Wo = W_rows(m.vertices, m.triangles, rows, near_order=NEAR)
-    assert np.abs(Wg - Wo).max() < 1e-12 * np.abs(Wo).max()
-    cols = np.random.default_rng(8).choice(p.N, 5, replace=False)
-    assert np.array_equal(Wg[:, cols].T, p.rows(cols)[:, rows])
-    M = lib.Preconditioner(p, w.patch_of_triangle, w.coarse.vertices, w.coarse.triangles, w.coarse_of_triangle,
-                           factor_fp32=True)
-    ref, i64, rc64 = p.solve(g=w.g, precond=M, tol=1e-12)
-    phi, imx, rc = p.solve(g=w.g, precond=M, tol=1e-10, precision=lib.FP32_REFINE)
-    assert rc == 0 and rc64 == 0
-    assert all(x["relres"] <= 1e-10 for x in imx)
-    assert max(x["iters"] for x in imx) <= max(x["iters"] for x in i64) + 6
-    err = np.linalg.norm(phi - ref, axis=1) / np.linalg.norm(ref, axis=1)
-    assert err.max() < 1e-8, err
-    M.close()
-    p.close()
-
-
 def test_fp32_copy_matches_rounding(ctx):
     m = meshes.unit_square(8)
     p = lib.Problem(ctx, m.vertices, m.triangles, precision=lib.FP32_REFINE, near_order=NEAR)

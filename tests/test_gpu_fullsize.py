@@ -1,0 +1,181 @@
+"""Parity with the oracle at the full sizes of the crossed-panel workloads, through the C-ABI.
+
+crossed96 (h = 1/96, 27,361 dofs): 1,024 seeded rows of W against the oracle's rows, the FP64 and
+mixed-precision solutions against the oracle's exact discrete solution Phi* (dense Cholesky,
+stored by tests/golden/make_crossed96_reference.py) in the L2 and the energy norm, the
+preconditioner of the seeded random partition (96 faces, a 2,948-dof wire basket) against the
+oracle's additive Schwarz operator, and the PCG iteration counts against the oracle's PCG.
+
+crossed192 (h = 1/192, 110,017 dofs, the pair matrix built in panels): 4,096 seeded rows of W
+(every q = 8 origin dof and q = 4 axis dofs among them) against the oracle's rows, in four slices,
+and the residual rows (L - W Phi)_S of the mixed-precision and FP64 solutions with the oracle's
+rows and right-hand side.  The solution itself has no dense reference at this size: the oracle's
+rows of the residual stand in for it (Section 4.3, eq. eval_a_phiij; Thm. thmBVP).
+"""
+import hashlib
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2310_09204_amd import lib, meshes
+from oracle.assemble import W_rows, rhs
+from oracle.topology import Topology
+
+pytestmark = pytest.mark.gpu
+NEAR = 10
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _input_hash(w):
+    h = hashlib.sha256()
+    for a in (w.mesh.vertices, w.mesh.triangles, w.patch_of_triangle, w.coarse.vertices, w.coarse.triangles,
+              w.coarse_of_triangle, w.g):
+        a = np.ascontiguousarray(a)
+        h.update(str(a.dtype).encode() + str(a.shape).encode())
+        h.update(a.tobytes())
+    return h.hexdigest()
+
+
+def _sample_rows(rng, N, n, special):
+    rows = rng.choice(N, n - len(special), replace=False)
+    return np.unique(np.concatenate([rows, np.asarray(special, dtype=np.int64)])).astype(np.int64)
+
+
+def _junction_dofs(V, dv, q_of_dof):
+    """(origin dofs, axis dofs): dofs at the q = 8 origin and at q = 4 vertices of the axes."""
+    return np.nonzero(q_of_dof == 8)[0], np.nonzero(q_of_dof == 4)[0]
+
+
+# ---------------------------------------------------------------------------------------- crossed96
+
+@pytest.fixture(scope="module")
+def c96(ctx):
+    ref = np.load(os.path.join(HERE, "golden", "crossed96_reference.npz"))
+    w = meshes.workload("crossed96", seed=0, k=2)
+    assert str(ref["input_hash"]) == _input_hash(w), "stale golden file: rerun make_crossed96_reference.py"
+    m = w.mesh
+    print("case crossed96 fixture", m.nt, flush=True)
+    ctx.release_cached()
+    p64 = lib.Problem(ctx, m.vertices, m.triangles, near_order=NEAR)
+    pmx = lib.Problem(ctx, m.vertices, m.triangles, near_order=NEAR, precision=lib.FP32_REFINE)
+    M64 = lib.Preconditioner(p64, w.patch_of_triangle, w.coarse.vertices, w.coarse.triangles, w.coarse_of_triangle)
+    Mmx = lib.Preconditioner(pmx, w.patch_of_triangle, w.coarse.vertices, w.coarse.triangles, w.coarse_of_triangle,
+                             factor_fp32=True)
+    yield w, ref, p64, pmx, M64, Mmx
+    for h in (Mmx, M64, pmx, p64):
+        h.close()
+    ctx.release_cached()
+
+
+def test_crossed96_1024_rows(c96):
+    w, ref, p64, pmx, M64, Mmx = c96
+    m = w.mesh
+    t = Topology(m.vertices, m.triangles)
+    qd = np.array([t.q[v] for v, j in t.dofs])
+    origin, axis = _junction_dofs(m.vertices, None, qd)
+    rng = np.random.default_rng(11)
+    rows = _sample_rows(rng, t.N, 1024, np.concatenate([origin, rng.choice(axis, 32, replace=False)]))
+    assert len(rows) >= 1024
+    Wo = W_rows(m.vertices, m.triangles, rows, topo=t, near_order=NEAR)
+    Wg = p64.rows(rows)
+    scale = np.abs(Wo).max()
+    assert np.abs(Wg - Wo).max() < 1e-12 * scale
+    # the mixed-precision problem keeps the same FP64 matrix beside its FP32 copy
+    Wm = pmx.rows(rows[:64])
+    assert np.abs(Wm - Wo[:64]).max() < 1e-12 * scale
+
+
+def test_crossed96_preconditioner_vs_oracle(c96):
+    w, ref, p64, pmx, M64, Mmx = c96
+    s = M64.sizes()
+    assert [s["n_faces"], s["n_wb"], s["n_coarse"]] == ref["sizes"].tolist()
+    r = np.random.default_rng(4).standard_normal(p64.N)
+    z = M64.apply(r[None, :])[0]
+    zo = ref["apply_z"]
+    assert np.abs(z[ref["apply_idx"]] - zo).max() < 1e-11 * np.abs(zo).max()
+
+
+def test_crossed96_fp64_solution_vs_oracle(c96):
+    w, ref, p64, pmx, M64, Mmx = c96
+    phis = ref["phi"]
+    # iteration counts: the same PCG (x0 = 0, tol 1e-10) as the oracle's
+    _, info, rc = p64.solve(g=w.g, precond=M64, tol=1e-10)
+    assert rc == 0
+    for c in range(2):
+        assert abs(info[c]["iters"] - int(ref["pcg_iters"][c])) <= 1, (info[c]["iters"], ref["pcg_iters"])
+    phi, info, rc = p64.solve(g=w.g, precond=M64, tol=1e-13)
+    assert rc == 0
+    e = phi - phis
+    l2 = np.linalg.norm(e, axis=1) / np.linalg.norm(phis, axis=1)
+    energy = np.sqrt(np.einsum("kn,kn->k", e, p64.matvec(e)) / ref["energy"])
+    print("crossed96 FP64: L2 %s energy %s" % (l2, energy), flush=True)
+    assert l2.max() < 1e-10 and energy.max() < 1e-10
+
+
+def test_crossed96_mixed_solution_vs_oracle(c96):
+    w, ref, p64, pmx, M64, Mmx = c96
+    phis = ref["phi"]
+    phi, info, rc = pmx.solve(g=w.g, precond=Mmx, tol=1e-10, precision=lib.FP32_REFINE)
+    assert rc == 0 and all(i["relres"] <= 1e-10 for i in info)
+    e = phi - phis
+    l2 = np.linalg.norm(e, axis=1) / np.linalg.norm(phis, axis=1)
+    energy = np.sqrt(np.einsum("kn,kn->k", e, p64.matvec(e)) / ref["energy"])
+    print("crossed96 mixed: L2 %s energy %s iterations %s" % (l2, energy, [i["iters"] for i in info]), flush=True)
+    assert l2.max() < 1e-8 and energy.max() < 1e-8
+
+
+# --------------------------------------------------------------------------------------- crossed192
+
+@pytest.fixture(scope="module")
+def c192(ctx):
+    w = meshes.workload("crossed192", seed=0, k=2)
+    m = w.mesh
+    print("case crossed192 fixture", m.nt, flush=True)
+    ctx.release_cached()
+    p = lib.Problem(ctx, m.vertices, m.triangles, near_order=NEAR, precision=lib.FP32_REFINE)
+    assert p.N == 110017 and p.info["n_pair_panels"] >= 2
+    M = lib.Preconditioner(p, w.patch_of_triangle, w.coarse.vertices, w.coarse.triangles, w.coarse_of_triangle,
+                           factor_fp32=True)
+    phi_mx, imx, rc = p.solve(g=w.g, precond=M, tol=1e-10, precision=lib.FP32_REFINE)
+    assert rc == 0 and all(x["relres"] <= 1e-10 for x in imx)
+    phi_64, i64, rc = p.solve(g=w.g, precond=M, tol=1e-12)
+    assert rc == 0
+    assert max(x["iters"] for x in imx) <= max(x["iters"] for x in i64) + 6
+    t = Topology(m.vertices, m.triangles)
+    qd = np.array([t.q[v] for v, j in t.dofs])
+    origin, axis = _junction_dofs(m.vertices, None, qd)
+    rng = np.random.default_rng(7)
+    rows = _sample_rows(rng, t.N, 4096, np.concatenate([origin, rng.choice(axis, 64, replace=False)]))
+    rng.shuffle(rows)
+    L = rhs(t, w.g).T                                     # oracle right-hand side, k x N
+    state = {"rows_done": [], "Wo": {}}
+    yield w, p, t, rows, L, phi_mx, phi_64, state
+    M.close()
+    p.close()
+    ctx.release_cached()
+
+
+@pytest.mark.parametrize("part", range(4))
+def test_crossed192_4096_rows_and_residuals(c192, part):
+    w, p, t, rows, L, phi_mx, phi_64, state = c192
+    m = w.mesh
+    S = np.sort(rows[part * len(rows) // 4:(part + 1) * len(rows) // 4])
+    print("case crossed192 rows part %d (%d rows)" % (part, len(S)), flush=True)
+    Wo = W_rows(m.vertices, m.triangles, S, topo=t, near_order=NEAR)
+    Wg = p.rows(S)
+    scale = np.abs(Wo).max()
+    assert np.abs(Wg - Wo).max() < 1e-12 * scale
+    # exact symmetry of the device matrix on a few sampled columns
+    cols = S[:: max(1, len(S) // 8)]
+    assert np.array_equal(Wg[:, cols], p.rows(cols)[:, S].T)
+    # residual rows of the computed solutions with the oracle's rows and right-hand side
+    for name, phi, bound in (("mixed", phi_mx, 1e-9), ("fp64", phi_64, 1e-11)):
+        r = L[:, S] - phi @ Wo.T
+        rel = np.linalg.norm(r, axis=1) / np.linalg.norm(L[:, S], axis=1)
+        print("crossed192 %s residual rows: %s" % (name, rel), flush=True)
+        assert rel.max() < bound, (name, rel)
+    # the mixed and FP64 solutions agree (the FP64 one is the reference of the benchmark)
+    err = np.linalg.norm(phi_mx - phi_64, axis=1) / np.linalg.norm(phi_64, axis=1)
+    assert err.max() < 1e-8

@@ -135,3 +135,31 @@ def test_eviction_keeps_results_correct():
         _, ref = solo(ctx, r)
         assert relerr(phi, ref) < 1e-8
     ctx.close()
+
+
+def test_served_results_match_oracle(ctx):
+    # every column of every served request against the oracle's exact discrete solution of its own
+    # geometry (dense Cholesky of the oracle's W, Thm. thmBVP), in the L2 and the energy norm:
+    # FP64 requests within 1e-10, mixed-precision ones within 1e-8
+    from oracle.assemble import assemble, rhs
+    from oracle.solve import cholesky_solve
+    from oracle.topology import Topology
+    reqs = small_stream(11, 8)
+    print("case serve-oracle", [(r.geometry, r.mesh.nt, r.g.shape[0], r.mixed) for r in reqs], flush=True)
+    srv = lib.Server(ctx, max_inflight=3)
+    tickets = [submit(srv, r) for r in reqs]
+    outs = [srv.poll(t) for t in tickets]
+    srv.close()
+    oracle = {}
+    for r, (phi, info, rc) in zip(reqs, outs):
+        assert rc == 0
+        if r.geometry not in oracle:
+            t = Topology(r.mesh.vertices, r.mesh.triangles)
+            oracle[r.geometry] = (t, assemble(r.mesh.vertices, r.mesh.triangles, t, 10))
+        t, W = oracle[r.geometry]
+        xs = cholesky_solve(W, rhs(t, r.g))              # N x k
+        e = phi - xs.T
+        l2 = np.linalg.norm(e, axis=1) / np.linalg.norm(xs, axis=0)
+        en = np.sqrt(np.einsum("kn,nk->k", e, W @ e.T) / np.einsum("nk,nk->k", xs, W @ xs))
+        bound = 1e-8 if r.mixed else 1e-10
+        assert l2.max() < bound and en.max() < bound, (r.geometry, r.mixed, l2, en)

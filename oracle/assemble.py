@@ -97,6 +97,31 @@ class _JumpCSR:
             fill[d] += 1
 
 
+def I_rows(V, T, r0, nrows, near_order=DEFAULT_NEAR_ORDER):
+    """Rows r0 .. r0+nrows-1 of the N_T x N_T matrix of I(T,T') (all columns)."""
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    T = np.ascontiguousarray(T, dtype=np.int32)
+    nt = T.shape[0]
+    b7, w7, gx, gw = _tables(near_order)
+    out = np.empty((nrows, nt))
+    native.lib().oracle_I_rows(native.dptr(V), native.iptr(T), nt, native.dptr(b7), native.dptr(w7),
+                               near_order, native.dptr(gx), native.dptr(gw), r0, nrows, native.dptr(out))
+    return out
+
+
+def W_accumulate(topo: Topology, r0, I, d0, d1, csr=None):
+    """The contraction step of `assemble` for one panel of rows of I (triangles r0 .. r0+len(I)-1):
+    their contributions to rows d0 .. d1-1 of the upper triangle of W, as a (d1-d0) x N array."""
+    c = csr or _JumpCSR(topo)
+    I = np.ascontiguousarray(I, dtype=np.float64)
+    out = np.zeros((d1 - d0, topo.N))
+    native.lib().oracle_W_accumulate(topo.nt, topo.N, native.lptr(c.tri_ptr), native.lptr(c.tri_dof),
+                                     native.dptr(np.ascontiguousarray(c.tri_J)), native.lptr(c.dof_ptr),
+                                     native.lptr(c.dof_tri), native.dptr(c.dof_J), r0, I.shape[0],
+                                     native.dptr(I), d0, d1, native.dptr(out))
+    return out
+
+
 def assemble(V, T, topo: Topology = None, near_order=DEFAULT_NEAR_ORDER, panel=1024):
     """Dense symmetric W (N x N) in canonical dof order."""
     V = np.ascontiguousarray(V, dtype=np.float64)

@@ -41,6 +41,7 @@ def lib():
         L.oracle_I_rows.argtypes = [dp, ip, i64, dp, dp, ci, dp, dp, i64, i64, dp]
         L.oracle_W.argtypes = [dp, ip, i64, dp, dp, ci, dp, dp, i64, lp, lp, dp, lp, lp, dp, i64, dp]
         L.oracle_W_rows.argtypes = [dp, ip, i64, dp, dp, ci, dp, dp, i64, lp, lp, dp, lp, lp, dp, i64, lp, dp]
+        L.oracle_W_accumulate.argtypes = [i64, i64, lp, lp, dp, lp, lp, dp, i64, i64, dp, i64, i64, dp]
         L.oracle_near_generic.argtypes = [ci, dp, dp, ci, dp, dp, ci]
         L.oracle_near_generic.restype = ctypes.c_double
         L.oracle_far_pair.argtypes = [dp, dp, dp, dp, dp, dp, dp, dp, ci]

@@ -246,10 +246,41 @@ void oracle_I_rows(const double* V, const int32_t* T, int64_t nt, const double* 
 }
 
 /*
- * Full W (N x N, row-major).  I is produced in panels of triangle rows; for every dof d the
- * triangles of its star that fall in the panel contribute
- *     W[d][d2] += I(T1,T2) * (J_{T1,d} . J_{T2,d2})   for d2 >= d,
- * and the strict lower triangle is mirrored at the end, so W is exactly symmetric.
+ * Contraction of one panel of rows of I (triangles r0 .. r0+nr-1, rows of length nt) into rows
+ * d0 .. d1-1 of W: for every dof d in that range, the triangles of its star that fall in the panel
+ * contribute
+ *     Wout[d - d0][d2] += I(T1,T2) * (J_{T1,d} . J_{T2,d2})   for d2 >= d.
+ * Wout has (d1 - d0) rows of N.
+ */
+void oracle_W_accumulate(int64_t nt, int64_t N, const int64_t* tri_ptr, const int64_t* tri_dof,
+                         const double* tri_J, const int64_t* dof_ptr, const int64_t* dof_tri,
+                         const double* dof_J, int64_t r0, int64_t nr, const double* I, int64_t d0,
+                         int64_t d1, double* Wout) {
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t d = d0; d < d1; ++d) {
+        double* Wd = Wout + (d - d0) * N;
+        for (int64_t e = dof_ptr[d]; e < dof_ptr[d + 1]; ++e) {
+            int64_t t1 = dof_tri[e];
+            if (t1 < r0 || t1 >= r0 + nr) continue;
+            const double* J1 = dof_J + 3 * e;
+            const double* Irow = I + (t1 - r0) * nt;
+            for (int64_t t2 = 0; t2 < nt; ++t2) {
+                double iv = Irow[t2];
+                for (int64_t f = tri_ptr[t2]; f < tri_ptr[t2 + 1]; ++f) {
+                    int64_t d2 = tri_dof[f];
+                    if (d2 < d) continue;
+                    const double* J2 = tri_J + 3 * f;
+                    Wd[d2] += iv * (J1[0] * J2[0] + J1[1] * J2[1] + J1[2] * J2[2]);
+                }
+            }
+        }
+    }
+}
+
+/*
+ * Full W (N x N, row-major).  I is produced in panels of triangle rows and each panel is
+ * contracted into W (oracle_W_accumulate, upper triangle d2 >= d); the strict lower triangle is
+ * mirrored at the end, so W is exactly symmetric.
  * tri_ptr/tri_dof/tri_J: CSR triangle -> (dof, J); dof_ptr/dof_tri/dof_J: CSR dof -> (triangle, J).
  */
 void oracle_W(const double* V, const int32_t* T, int64_t nt, const double* bary7, const double* w7,
@@ -262,25 +293,7 @@ void oracle_W(const double* V, const int32_t* T, int64_t nt, const double* bary7
     for (int64_t r0 = 0; r0 < nt; r0 += panel) {
         int64_t nr = (r0 + panel <= nt) ? panel : nt - r0;
         oracle_I_rows(V, T, nt, bary7, w7, n, gx, gw, r0, nr, I);
-#pragma omp parallel for schedule(dynamic, 4)
-        for (int64_t d = 0; d < N; ++d) {
-            double* Wd = W + d * N;
-            for (int64_t e = dof_ptr[d]; e < dof_ptr[d + 1]; ++e) {
-                int64_t t1 = dof_tri[e];
-                if (t1 < r0 || t1 >= r0 + nr) continue;
-                const double* J1 = dof_J + 3 * e;
-                const double* Irow = I + (t1 - r0) * nt;
-                for (int64_t t2 = 0; t2 < nt; ++t2) {
-                    double iv = Irow[t2];
-                    for (int64_t f = tri_ptr[t2]; f < tri_ptr[t2 + 1]; ++f) {
-                        int64_t d2 = tri_dof[f];
-                        if (d2 < d) continue;
-                        const double* J2 = tri_J + 3 * f;
-                        Wd[d2] += iv * (J1[0] * J2[0] + J1[1] * J2[1] + J1[2] * J2[2]);
-                    }
-                }
-            }
-        }
+        oracle_W_accumulate(nt, N, tri_ptr, tri_dof, tri_J, dof_ptr, dof_tri, dof_J, r0, nr, I, 0, N, W);
     }
     free(I);
     for (int64_t d = 0; d < N; ++d)

@@ -39,8 +39,11 @@ def _input_hash(w):
 
 
 def _sample_rows(rng, N, n, special):
-    rows = rng.choice(N, n - len(special), replace=False)
-    return np.unique(np.concatenate([rows, np.asarray(special, dtype=np.int64)])).astype(np.int64)
+    """n distinct rows: the special ones and n - len(special) others drawn from the rest"""
+    special = np.unique(np.asarray(special, dtype=np.int64))
+    rest = np.setdiff1d(np.arange(N, dtype=np.int64), special)
+    rows = rng.choice(rest, n - len(special), replace=False)
+    return np.sort(np.concatenate([rows, special])).astype(np.int64)
 
 
 def _junction_dofs(V, dv, q_of_dof):
@@ -77,7 +80,7 @@ def test_crossed96_1024_rows(c96):
     origin, axis = _junction_dofs(m.vertices, None, qd)
     rng = np.random.default_rng(11)
     rows = _sample_rows(rng, t.N, 1024, np.concatenate([origin, rng.choice(axis, 32, replace=False)]))
-    assert len(rows) >= 1024
+    assert len(rows) == 1024
     Wo = W_rows(m.vertices, m.triangles, rows, topo=t, near_order=NEAR)
     Wg = p64.rows(rows)
     scale = np.abs(Wo).max()

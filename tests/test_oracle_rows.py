@@ -65,3 +65,22 @@ def test_sampled_rows_catch_a_planted_error():
                 row[c.tri_dof[f]] += I[t2] * (J1 @ c.tri_J[f])
     assert np.abs(full - W[d]).max() <= 1e-14 * np.abs(W).max()
     assert np.abs(row - W[d]).max() > 1e-6 * np.abs(W).max()
+
+
+def test_panel_contraction_equals_full_matrix():
+    # the contraction step on its own (panels of rows of I, any dof range), as the CPU baseline times
+    # it, adds up to the upper triangle of the full matrix
+    from oracle.assemble import I_rows, W_accumulate, _JumpCSR
+    m = meshes.crossed(6)
+    t = Topology(m.vertices, m.triangles)
+    W = assemble(m.vertices, m.triangles, t, NEAR)
+    c = _JumpCSR(t)
+    U = np.zeros((t.N, t.N))
+    half = t.N // 2
+    for r0 in range(0, t.nt, 37):
+        I = I_rows(m.vertices, m.triangles, r0, min(37, t.nt - r0), NEAR)
+        U[:half] += W_accumulate(t, r0, I, 0, half, c)
+        U[half:] += W_accumulate(t, r0, I, half, t.N, c)
+    iu = np.triu_indices(t.N)
+    assert np.abs(U[iu] - W[iu]).max() <= 1e-14 * np.abs(W).max()
+    assert np.abs(np.tril(U, -1)).max() == 0.0

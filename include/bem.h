@@ -182,6 +182,19 @@ int bem_rhs(const bem_problem* p, const double* g, int32_t k, double* out);
  * (each 64 x 64 block applied to both sides); a matrix of a single 64-row block is streamed whole.
  * Sums run in a fixed order: equal inputs give bit-identical outputs. */
 int bem_matvec(const bem_problem* p, const double* x, int32_t k, int fp32, double* y);
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc): y = W x as bem_matvec, with d_x and d_y device pointers
+ * ([k][N] each, column-major, leading dimension N, caller-owned), that calls no hipMalloc,
+ * hipFree or other allocating routine.  The transposed right-hand sides and the partial sums of
+ * the product live in one static device array of 128 MiB per device (held from the library's
+ * first use on that device until the process ends; its address is looked up in bem_ctx_create).
+ * A product needs 16 N s + (N/64) (ceil(N/256 or N/512) + 1) 1024 s bytes of it (s = 8, or 4
+ * with fp32 = 1, N rounded up to 64; super-blocks of 4 FP64 or 8 FP32 blocks): N up to 16,128
+ * (FP64) or 32,256 (FP32); larger problems get BEM_E_INVALID_ARG and must use bem_matvec.  Runs on the problem's stream and returns when y is written.  Every call
+ * on one device shares the array, which keeps the last call's contents: calls that overlap on
+ * one device race (calls on one problem are serialised).  Errors: BEM_E_INVALID_ARG (NULL, k < 1,
+ * fp32 without an FP32 matrix, scratch too small), BEM_E_DEVICE. */
+int bem_matvec_noalloc(const bem_problem* p, const double* d_x, int32_t k, int fp32, double* d_y);
 /* Measurement: `reps` back-to-back products y = W x with k device-resident columns (FP64 matrix,
  * or the FP32 copy if fp32 = 1), timed with HIP events on the problem's stream; writes the mean
  * seconds per product.  The upper block triangle of W is read plus the block-row partials of the

@@ -316,6 +316,8 @@ int bem_ctx_create(int hip_device, size_t hbm_budget_bytes, bem_ctx** out) {
     HIP_CHECK(hipMemGetInfo(&fr, &tot));
     c->budget = hbm_budget_bytes ? hbm_budget_bytes : size_t(0.9 * double(fr));
     HIP_CHECK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    // this device's address of the scratch array of bem_matvec_noalloc, looked up once here
+    noalloc_scratch_address(hip_device);
     *out = c;
     return BEM_OK;
     BEM_CATCH
@@ -624,6 +626,26 @@ int bem_matvec(const bem_problem* p, const double* x, int32_t k, int fp32, doubl
     HIP_CHECK(hipMemcpyAsync(dx.ptr, x, sizeof(double) * N * k, hipMemcpyHostToDevice, p->stream));
     matvec_device(p, fp32 != 0, dx.as<double>(), N, k, dy.as<double>(), p->stream);
     HIP_CHECK(hipMemcpyAsync(y, dy.ptr, sizeof(double) * N * k, hipMemcpyDeviceToHost, p->stream));
+    HIP_CHECK(hipStreamSynchronize(p->stream));
+    return BEM_OK;
+    BEM_CATCH
+}
+
+int bem_matvec_noalloc(const bem_problem* p, const double* d_x, int32_t k, int fp32, double* d_y) {
+    BEM_TRY
+    if (!p || !d_x || !d_y || k <= 0) fail(BEM_E_INVALID_ARG, "bad argument");
+    set_device(p->ctx);
+    const int64_t N = p->N;
+    if (N == 0) return BEM_OK;
+    if (fp32 && !p->W32.ptr) fail(BEM_E_INVALID_ARG, "problem has no FP32 matrix (assemble with BEM_FP32_REFINE)");
+    const size_t need = noalloc_matvec_bytes(p, fp32 != 0);
+    if (need > kNoAllocScratchBytes)
+        fail(BEM_E_INVALID_ARG, "bem_matvec_noalloc: this product needs " + std::to_string(need) +
+                                    " bytes of scratch, more than the " + std::to_string(kNoAllocScratchBytes) +
+                                    " it has (use bem_matvec)");
+    void* scr = noalloc_scratch_address(p->ctx->device);
+    std::lock_guard<std::mutex> call(p->call_mu);
+    matvec_device_noalloc(p, fp32 != 0, d_x, N, k, d_y, p->stream, scr);
     HIP_CHECK(hipStreamSynchronize(p->stream));
     return BEM_OK;
     BEM_CATCH

@@ -251,6 +251,15 @@ void release_stream(bem_ctx* c, hipStream_t s);
 void matvec_setup(bem_problem* p, hipStream_t s);   // after W is allocated (ldw set)
 void matvec_device(const bem_problem* p, bool fp32, const double* d_x, int64_t ldx, int k,
                    double* d_y, hipStream_t s);
+// the same products with their scratch in the device array of bem_matvec_noalloc (solver.hip):
+// its size, the per-device address (looked up once per device, with that device current), the
+// bytes one product of this problem needs there, and the launch
+constexpr size_t kNoAllocScratchBytes = size_t(128) << 20;
+constexpr int kMaxDevices = 64;
+void* noalloc_scratch_address(int device);
+size_t noalloc_matvec_bytes(const bem_problem* p, bool fp32);
+void matvec_device_noalloc(const bem_problem* p, bool fp32, const double* d_x, int64_t ldx, int k, double* d_y,
+                           hipStream_t s, void* scratch);
 
 }  // namespace bem
 

@@ -526,9 +526,12 @@ __global__ __launch_bounds__(256) void k_init_state(const double* __restrict__ p
 
 inline unsigned gblocks(int64_t N) { return unsigned(std::max<int64_t>(1, std::min<int64_t>(1024, (N + 255) / 256))); }
 
+// xt: transposed right-hand sides (ldw x 16 of MT); part: split partials of the plain product
+// (16 x 16 x ldw doubles); sp: block-row partials of the symmetric product (ldw / 64 x (nst + 1) x
+// 1024 of MT).  Every entry of the three that a later kernel reads is written first, each call.
 template <typename MT, typename AT>
 void launch_matvec(const bem_problem* p, const MT* W, const double* x, int64_t ldx, int k, double* y, int64_t ldy,
-                   hipStream_t s) {
+                   hipStream_t s, MT* xt, double* part, MT* sp) {
     const int64_t N = p->N, ldw = p->ldw;
     for (int c0 = 0; c0 < k; c0 += 16) {
         const int kc = std::min(16, k - c0);
@@ -541,13 +544,10 @@ void launch_matvec(const bem_problem* p, const MT* W, const double* x, int64_t l
             HIP_CHECK(hipGetLastError());
             continue;
         }
-        MT* xt = static_cast<MT*>(p->mv_xt.ptr);
-        double* part = p->mv_partial.as<double>();
         hipLaunchKernelGGL(k_transpose_x<MT>, dim3(unsigned((ldw * 16 + 255) / 256)), dim3(256), 0, s, xc, ldx, kc, N, ldw, xt);
         if (p->mv_ntiles[ty] > 0) {
             // W is symmetric: read its upper half once and apply every block to both sides (also
             // for a single column: half the bytes outweigh the idle matrix-core columns)
-            MT* sp = static_cast<MT*>(p->mv_sym.ptr);
             hipLaunchKernelGGL(k_symv_mfma<MT>, dim3(unsigned(p->mv_ntiles[ty])), dim3(256), 0, s, W, ldw, N, xt, ldw / 64,
                                p->mv_nst[ty], p->mv_tiles[ty].as<int2>(), sp);
             hipLaunchKernelGGL(k_symv_reduce<MT>, dim3(unsigned((N + 255) / 256), unsigned(kc)), dim3(256), 0, s, sp,
@@ -643,11 +643,74 @@ void matvec_setup(bem_problem* p, hipStream_t s) {
 
 void matvec_device(const bem_problem* p, bool fp32, const double* d_x, int64_t ldx, int k, double* d_y, hipStream_t s) {
     if (p->N == 0) return;
+    double* part = p->mv_partial.as<double>();
     if (fp32) {
         if (!p->W32.ptr) fail(BEM_E_INVALID_ARG, "problem has no FP32 matrix (assemble with BEM_FP32_REFINE)");
-        launch_matvec<float, double>(p, p->W32.as<float>(), d_x, ldx, k, d_y, ldx, s);
+        launch_matvec<float, double>(p, p->W32.as<float>(), d_x, ldx, k, d_y, ldx, s, static_cast<float*>(p->mv_xt.ptr),
+                                     part, static_cast<float*>(p->mv_sym.ptr));
     } else {
-        launch_matvec<double, double>(p, p->W64.as<double>(), d_x, ldx, k, d_y, ldx, s);
+        launch_matvec<double, double>(p, p->W64.as<double>(), d_x, ldx, k, d_y, ldx, s, p->mv_xt.as<double>(), part,
+                                      static_cast<double*>(p->mv_sym.ptr));
+    }
+}
+
+// ---- products that allocate nothing ------------------------------------------------------------
+// bem_matvec_noalloc keeps the transposed right-hand sides and the partial sums of its product in
+// this file-scope device array instead of the problem's buffers.  Each device holds its own copy,
+// at its own address, until the process ends; host code uses only the address that
+// hipGetSymbolAddress returns for the current device (the array's name is a host-side stand-in
+// there, not a device address).  Calls on one device share it: overlapping calls race.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+constexpr size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+}  // namespace
+
+void* noalloc_scratch_address(int device) {
+    if (device < 0 || device >= kMaxDevices) fail(BEM_E_INVALID_ARG, "device index out of range for the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = -1;
+        HIP_CHECK(hipGetDevice(&cur));
+        if (cur != device) HIP_CHECK(hipSetDevice(device));
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !ptr)
+            fail(BEM_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[device] = ptr;
+    }
+    return g_scratch_ptr[device];
+}
+
+// layout: the transposed right-hand sides, then either the block-row partials of the symmetric
+// product or (a matrix of one 64-row block) the split partials of the plain one
+size_t noalloc_matvec_bytes(const bem_problem* p, bool fp32) {
+    const size_t es = fp32 ? sizeof(float) : sizeof(double);
+    const size_t xt = align256(16 * size_t(p->ldw) * es);
+    const int ty = fp32 ? 0 : 1;
+    const size_t part = p->mv_ntiles[ty] > 0 ? size_t(p->ldw / 64) * size_t(p->mv_nst[ty] + 1) * 1024 * es
+                                             : 16 * 16 * size_t(p->ldw) * sizeof(double);
+    return xt + part;
+}
+
+void matvec_device_noalloc(const bem_problem* p, bool fp32, const double* d_x, int64_t ldx, int k, double* d_y,
+                           hipStream_t s, void* scr) {
+    if (p->N == 0) return;
+    const size_t es = fp32 ? sizeof(float) : sizeof(double);
+    unsigned char* base = static_cast<unsigned char*>(scr);
+    void* xt = base;
+    void* sp = base + align256(16 * size_t(p->ldw) * es);     // one of the two partial layouts is used
+    double* part = static_cast<double*>(sp);
+    if (fp32) {
+        if (!p->W32.ptr) fail(BEM_E_INVALID_ARG, "problem has no FP32 matrix (assemble with BEM_FP32_REFINE)");
+        launch_matvec<float, double>(p, p->W32.as<float>(), d_x, ldx, k, d_y, ldx, s, static_cast<float*>(xt), part,
+                                     static_cast<float*>(sp));
+    } else {
+        launch_matvec<double, double>(p, p->W64.as<double>(), d_x, ldx, k, d_y, ldx, s, static_cast<double*>(xt), part,
+                                      static_cast<double*>(sp));
     }
 }
 

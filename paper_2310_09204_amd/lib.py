@@ -106,6 +106,7 @@ SIGNATURES = {
     "bem_problem_pair_integrals": (_ci, [_vp, _vp, _i64, _vp]),
     "bem_rhs": (_ci, [_vp, _vp, _i32, _vp]),
     "bem_matvec": (_ci, [_vp, _vp, _i32, _ci, _vp]),
+    "bem_matvec_noalloc": (_ci, [_vp, _vp, _i32, _ci, _vp]),
     "bem_jump_values": (_ci, [_vp, _vp, _vp]),
     "bem_precond_setup": (_ci, [_vp, _vp, _vp, _i64, _vp, _i64, _vp, ctypes.POINTER(PrecondOpts), ctypes.POINTER(_vp)]),
     "bem_precond_setup_2d": (_ci, [_vp, _vp, _vp, _i64, _vp, _i64, _vp, ctypes.POINTER(PrecondOpts), ctypes.POINTER(_vp)]),
@@ -334,6 +335,10 @@ class Problem:
         y = np.empty_like(x)
         _check(load().bem_matvec(self._h, _p(x), x.shape[0], int(fp32), _p(y)))
         return y
+
+    def matvec_noalloc(self, d_x, k, d_y, fp32=False):
+        """y = W x on device buffers (addresses of [k][N] doubles) through bem_matvec_noalloc."""
+        _check(load().bem_matvec_noalloc(self._h, _vp(d_x), int(k), int(fp32), _vp(d_y)))
 
     def bench_matvec(self, fp32=False, k=1, reps=10):
         """Mean seconds per device-resident product W x (k columns), timed with HIP events."""

@@ -3,13 +3,18 @@
 
 One step = one pass of the path over one batch of synthetic input: host mesh analysis and near
 list, device assembly of W (far 7x7 tiles, Duffy near kernels, contraction, FP32 copy), right-hand
-sides, preconditioner set-up (batched block inverses, coarse Galerkin matrix), and the
-mixed-precision PCG solve of k right-hand sides to relative residual tol.  Every solved column is
-checked against an FP64 reference solution (FP64 GPU PCG at relative residual 1e-13, computed
-before the timed region); only columns with relative error <= 1e-8 count.
+sides, preconditioner set-up (block inverses, coarse Galerkin matrix), and the mixed-precision PCG
+solve of k right-hand sides to relative residual tol.  The headline workload is crossed192 (three
+perpendicular unit squares, h = 1/192: 221,184 triangles, 110,017 dofs, the pair matrix built in
+panels), the largest configuration that fits one GPU.  Every solved column is checked against an
+FP64 GPU solve of the same system at relative residual 1e-13 (self-consistency); only columns
+within 1e-8 count.  The oracle's sampled residual rows of the same solutions ride along in the
+CPU-baseline leg (parity).
 
-Prints one JSON line (see the "metric"/"value" keys); per-phase timings, matvec bandwidths, the
-roofline of the dominant kernel and the oracle timed on the host cores ride along.
+Prints one JSON line (see the "metric"/"value" keys); per-phase timings, matvec HBM rates, the
+roofline of the dominant kernel, side legs (crossed96, the unit square and the book, the book's
+condition-number study, serving, the paper's experiments) and the oracle timed on the host cores
+ride along.
 """
 from __future__ import annotations
 
@@ -24,15 +29,18 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
-# algorithmic FP64 flops of one far-field kernel evaluation w / |x - y| as the far kernel issues it
-# (counted in its gfx950 ISA): 3 subtractions, 1 product and 2 FMAs for |x-y|^2, 2 products and 1
-# FMA for the Newton step of the reciprocal square root, 1 FMA into the inner sum, and 1 FMA per
-# 7 evaluations into the outer sum; an FMA counts 2, the v_rsq_f64 estimate is not counted
-FLOPS_PER_EVAL = 14.0 + 2.0 / 7.0
+# algorithmic FP64 flops of one far-field kernel evaluation w / |x - y|: 3 subtractions and 3
+# multiply-adds for |x - y|^2, one multiply-add into the sum (the reciprocal square root not
+# counted); a multiply-add counts 2
+FLOPS_PER_EVAL = 11.0
+# the same evaluation as the far kernel issues it in its gfx950 ISA (direct form: 3 add, 3 mul,
+# 4.14 FMA, including the Newton step of v_rsq_f64), reported beside the algorithmic rate
+ISA_FLOPS_PER_EVAL = 14.0 + 2.0 / 7.0
 EVALS_PER_FAR_PAIR = 49
 
 
@@ -41,11 +49,12 @@ def log(*a):
 
 
 def far_kernel_source_hash():
-    """Hash of the far-field pass's own source text (its constants and its three kernels, through
-    the far kernel's closing brace), so that counters taken on an older version are not reported."""
+    """Hash of the far-field pass's own source text (its constants, the one-shot and the panel
+    kernels, through the panel kernel's closing brace), so that counters taken on an older version
+    are not reported."""
     src = open(os.path.join(ROOT, "paper_2310_09204_amd", "csrc", "assemble.hip")).read()
     a = src.index("constexpr int kGrp")
-    b = src.index("\n}\n", src.index("void k_far(", a)) + 3
+    b = src.index("\n}\n", src.index("void k_far_rect(", a)) + 3
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
@@ -61,9 +70,11 @@ def symv_bytes(N, size):
 
 
 def matvec_rates(N, size, t, key):
-    """A product's time, its HBM rate and the full-matrix equivalent rate (N^2 entries / t)."""
-    return {key + "_ms": t * 1e3, key + "_hbm_GBs": symv_bytes(N, size) / t / 1e9,
-            key + "_equiv_GBs": N * N * size / t / 1e9}
+    """A product's time, its algorithmic HBM bytes (upper block triangle + partials), the rate and
+    its fraction of the 8 TB/s peak."""
+    b = symv_bytes(N, size)
+    return {key + "_ms": t * 1e3, key + "_bytes": b, key + "_hbm_GBs": b / t / 1e9,
+            key + "_hbm_frac": b / t / 1e9 / PEAK_HBM_GBS}
 
 
 def load_traffic(kernel, workload):
@@ -82,65 +93,440 @@ def load_traffic(kernel, workload):
         return None
 
 
-def cpu_baseline(w, k, iters, gpu_info, budget_s):
-    """The oracle on the host cores, on a bounded sample of this workload, scaled to solves/s.
+def input_hash(w):
+    h = hashlib.sha256()
+    for a in (w.mesh.vertices, w.mesh.triangles, w.patch_of_triangle, w.coarse.vertices, w.coarse.triangles,
+              w.coarse_of_triangle, w.g):
+        a = np.ascontiguousarray(a)
+        h.update(str(a.dtype).encode() + str(a.shape).encode())
+        h.update(a.tobytes())
+    return h.hexdigest()
 
-    Sample: R random rows of the pair-integral matrix (all columns; far and near pairs exactly as
-    the oracle assembles them) timed with oracle_I_rows; the dense products of the PCG timed on a
-    slab of rows of a matrix of the workload's size; scaled to N_T rows and to the solve's
-    iteration count.  The oracle's contraction and preconditioner set-up are not included (so
-    the baseline is optimistic for the oracle)."""
-    from oracle import native
-    from oracle.assemble import _tables
-    import ctypes
 
-    V = np.ascontiguousarray(w.mesh.vertices, dtype=np.float64)
-    T = np.ascontiguousarray(w.mesh.triangles, dtype=np.int32)
-    nt = T.shape[0]
-    N = int(gpu_info["n_dofs"])
-    b7, w7, gx, gw = _tables(10)
-    L = native.lib()
+def golden(name, w):
+    """The oracle's stored results for workload w (tests/golden/<name>_reference.npz), or None if the
+    file is absent or was written for other inputs."""
+    path = os.path.join(GOLDEN, name + "_reference.npz")
+    if not os.path.exists(path):
+        return None
+    ref = np.load(path)
+    return ref if str(ref["input_hash"]) == input_hash(w) else None
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    return xs[min(len(xs) - 1, int(round(q * (len(xs) - 1))))]
+
+
+# ---------------------------------------------------------------------------------------------
+# CPU baseline: the oracle on the host cores
+# ---------------------------------------------------------------------------------------------
+
+def cpu_baseline(w, k, iters, gpu_info, precond_sizes, budget_s, phi_checks):
+    """The oracle as it stands, timed on the host cores on bounded samples of this workload and
+    scaled to one step (assembly, preconditioner set-up, k PCG solves of `iters` iterations).
+
+    Measured in full: the oracle's mesh analysis (sectors, dofs, jump coefficients), its dof
+    classification and its coarse prolongation.  Sampled and scaled by their work units:
+      * pair integrals: every column of the rows of I that the stars of a window of dofs touch
+        (oracle_I_rows), scaled to the N_T rows the oracle's assembly computes;
+      * contraction: the oracle's contraction of that panel into the window's rows
+        (oracle_W_accumulate), scaled by star entries;
+      * set-up: Cholesky factorizations (the oracle's scipy cho_factor) of SPD stand-ins of the
+        workload's block sizes (a sample of faces, the whole wire basket, the coarse block), and
+        the coarse product R_H W on a slab of rows of a stand-in W;
+      * solve: the oracle's PCG is one column at a time; per iteration its dense product W p
+        (numpy, on a slab of rows of a stand-in W) and one application of the block solves
+        (scipy cho_solve on the stand-in factors, plus R_H^T and R_H).
+    Parity rides along: the oracle's rows of W for a few seeded dofs (every q = 8 origin dof among
+    them) give the residual rows (L - W phi)_S of the GPU solutions in phi_checks."""
+    import scipy.linalg as sla
+    from oracle.assemble import I_rows, W_accumulate, W_rows, _JumpCSR, rhs
+    from oracle.precond import classify_dofs, coarse_prolongation
+    from oracle.topology import Topology
+
+    m = w.mesh
+    V = np.ascontiguousarray(m.vertices, dtype=np.float64)
+    T = np.ascontiguousarray(m.triangles, dtype=np.int32)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     rng = np.random.default_rng(0)
-    # calibrate: one row first
-    rows_done, t_rows = 0, 0.0
-    R = 1
-    buf = np.empty((64, nt))
-    while t_rows < 0.6 * budget_s and rows_done < nt:
-        R = min(R, 64)
-        r0 = int(rng.integers(0, nt - R))
+    out = {"kind": "oracle", "unit": "solves/s", "cores": threads}
+
+    t0 = time.perf_counter()
+    topo = Topology(V, T)
+    t_topo = time.perf_counter() - t0
+    log("bench: oracle mesh analysis %.1f s" % t_topo)
+    nt, N = topo.nt, topo.N
+    assert N == int(gpu_info["n_dofs"])
+    c = _JumpCSR(topo)
+
+    # pair integrals and contraction on the rows of a dof window's stars, grown until it has taken
+    # about a third of the budget
+    d0 = N // 3
+    size, t_rows, rows_done, t_acc, entries_done, tries = 16, 0.0, 0, 0.0, 0, 0
+    while (t_rows < 0.35 * budget_s or rows_done == 0) and size <= 4096 and tries < 1000:
+        tries += 1
+        d0 = min(d0, N - 1)
+        d1 = min(N, d0 + size)
+        tris = c.dof_tri[c.dof_ptr[d0]:c.dof_ptr[d1]]
+        r0, r1 = int(tris.min()), int(tris.max()) + 1
+        if r1 - r0 > max(16 * size, 2048) and tries < 999:   # the window reaches distant triangles: move on
+            d0 = (d0 + size) % max(1, N - size)
+            continue
+        ta = time.perf_counter()
+        I = I_rows(V, T, r0, r1 - r0, 10)
+        tb = time.perf_counter()
+        W_accumulate(topo, r0, I, d0, d1, c)
+        tc = time.perf_counter()
+        del I
+        t_rows += tb - ta
+        rows_done += r1 - r0
+        t_acc += tc - tb
+        entries_done += int(c.dof_ptr[d1] - c.dof_ptr[d0])
+        d0 = d1
+        size *= 2
+    t_pairs = t_rows / rows_done * nt
+    log("bench: oracle %d rows of I in %.1f s, contraction of %d entries in %.2f s" % (rows_done, t_rows, entries_done, t_acc))
+    t_contract = t_acc / entries_done * len(c.dof_tri)
+
+    # set-up: classification and prolongation in full; factorizations on SPD stand-ins
+    t0 = time.perf_counter()
+    faces, wb = classify_dofs(topo, w.patch_of_triangle)
+    t_classify = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    RH, _ = coarse_prolongation(topo, w.coarse.vertices, w.coarse.triangles, w.coarse_of_triangle)
+    t_prolong = time.perf_counter() - t0
+    nH = RH.shape[0]
+
+    def spd(n):
+        A = rng.standard_normal((n, n))
+        return (A + A.T) / 2 + 2.0 * np.sqrt(n) * np.eye(n)
+
+    face_sizes = [len(f) for f in faces]
+    sample = rng.choice(len(face_sizes), min(16, len(face_sizes)), replace=False)
+    fac_faces, t_ff = [], 0.0
+    for i in sample:
+        A = spd(face_sizes[i])
         t0 = time.perf_counter()
-        L.oracle_I_rows(native.dptr(V), native.iptr(T), nt, native.dptr(b7), native.dptr(w7), 10,
-                        native.dptr(gx), native.dptr(gw), r0, R, native.dptr(buf))
-        t_rows += time.perf_counter() - t0
-        rows_done += R
-        R *= 2
-    t_asm = t_rows / rows_done * nt
-    # dense matvec slab: W[rows, :] @ X, k columns
-    slab = 1024
+        fac_faces.append(sla.cho_factor(A, lower=True))
+        t_ff += time.perf_counter() - t0
+    t_face_factor = t_ff / len(sample) * len(face_sizes)
+    A = spd(len(wb))
+    t0 = time.perf_counter()
+    fac_wb = sla.cho_factor(A, lower=True)
+    t_wb_factor = time.perf_counter() - t0
+    del A
+    AH = spd(nH)
+    t0 = time.perf_counter()
+    fac_H = sla.cho_factor(AH, lower=True)
+    t_coarse_factor = time.perf_counter() - t0
+    slab = min(N, 1024)
     Wslab = rng.standard_normal((slab, N))
-    X = rng.standard_normal((N, k))
+    t0 = time.perf_counter()
+    RH[:, :slab] @ Wslab            # one slab of the coarse product R_H W (then Z R_H^T, n_H^2 N: small)
+    t_coarse_product = (time.perf_counter() - t0) * (N / slab)
+    log("bench: oracle set-up samples done (prolongation %.1f s)" % t_prolong)
+    t_setup = t_classify + t_prolong + t_face_factor + t_wb_factor + t_coarse_factor + t_coarse_product
+
+    # solve: per column and iteration one dense product and one preconditioner application
+    p = rng.standard_normal(N)
     reps, t_mv = 0, 0.0
-    while t_mv < 0.2 * budget_s and reps < 50:
+    while t_mv < 0.05 * budget_s and reps < 50:
         t0 = time.perf_counter()
-        Wslab @ X
+        Wslab @ p
         t_mv += time.perf_counter() - t0
         reps += 1
     t_matvec = t_mv / reps * (N / slab)
-    t_solve = iters * t_matvec
-    t_step = t_asm + t_solve
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {
+    del Wslab
+    r = rng.standard_normal(N)
+    t0 = time.perf_counter()
+    for i, f in zip(sample, fac_faces):
+        sla.cho_solve(f, r[:face_sizes[i]])
+    t_fs = (time.perf_counter() - t0) / len(sample) * len(face_sizes)
+    t0 = time.perf_counter()
+    sla.cho_solve(fac_wb, r[:len(wb)])
+    RH.T @ sla.cho_solve(fac_H, RH @ r)
+    t_apply = t_fs + time.perf_counter() - t0
+    t_solve = k * iters * (t_matvec + t_apply)
+
+    t_assembly = t_topo + t_pairs + t_contract
+    t_step = t_assembly + t_setup + t_solve
+    out.update({
         "value": k / t_step,
-        "unit": "solves/s",
-        "cores": threads,
-        "kind": "oracle",
-        "sample": "%d of %d rows of the pair-integral matrix (oracle_I_rows, all columns) and a %d-row slab "
-                  "of the dense %d-column product, scaled to one step of %d right-hand sides with %d PCG "
-                  "iterations; contraction and preconditioner set-up not counted" % (rows_done, nt, slab, k, k, iters),
-        "t_assembly_s": t_asm,
-        "t_solve_s": t_solve,
-        "pair_integrals_per_s": nt * (nt + 1) / 2 / t_asm,
+        "sample": "oracle mesh analysis, dof classification and coarse prolongation in full; %d rows of the "
+                  "pair-integral matrix (all %d columns, oracle_I_rows) and their contraction into %d star "
+                  "entries (oracle_W_accumulate), scaled to %d rows / %d entries; Cholesky (scipy) of SPD "
+                  "stand-ins for %d of %d faces, the %d-dof wire basket and the %d-dof coarse block; the "
+                  "coarse product and the PCG's dense product on a %d-row slab of a stand-in W, and one "
+                  "application of the block solves; %d right-hand sides x %d PCG iterations, one column "
+                  "at a time as the oracle's PCG runs"
+                  % (rows_done, nt, entries_done, nt, len(c.dof_tri), len(sample), len(face_sizes), len(wb), nH,
+                     slab, k, iters),
+        "t_step_s": t_step, "t_assembly_s": t_assembly, "t_setup_s": t_setup, "t_solve_s": t_solve,
+        "t_mesh_analysis_s": t_topo, "t_pair_integrals_s": t_pairs, "t_contraction_s": t_contract,
+        "t_setup_parts_s": {"classify": t_classify, "prolongation": t_prolong, "face_factors": t_face_factor,
+                            "wirebasket_factor": t_wb_factor, "coarse_factor": t_coarse_factor,
+                            "coarse_product": t_coarse_product},
+        "t_matvec_s": t_matvec, "t_precond_apply_s": t_apply,
+        # the oracle's assembly computes all N_T^2 ordered pairs (full rows of I)
+        "pair_integrals_computed_per_s": rows_done * nt / t_rows,
+        "pair_integrals_per_s": nt * (nt + 1) / 2 / t_assembly,
+        "matvec_GBs": N * N * 8 / t_matvec / 1e9,
+    })
+
+    # parity: oracle residual rows of the GPU solutions
+    qd = np.array([topo.q[v] for v, j in topo.dofs])
+    special = np.nonzero(qd == 8)[0]
+    S = np.unique(np.concatenate([special, rng.choice(N, 32, replace=False)])).astype(np.int64)
+    t0 = time.perf_counter()
+    Wo = W_rows(V, T, S, topo=topo, near_order=10)
+    L = rhs(topo, w.g).T
+    res = {}
+    for name, phi in phi_checks.items():
+        rr = L[:, S] - phi @ Wo.T
+        res[name] = float((np.linalg.norm(rr, axis=1) / np.linalg.norm(L[:, S], axis=1)).max())
+    out["oracle_residual_rows"] = {"rows": len(S), "max_relative": res, "t_s": time.perf_counter() - t0}
+    log("bench: oracle residual rows %s" % res)
+    return out
+
+
+# ---------------------------------------------------------------------------------------------
+# the timed workload
+# ---------------------------------------------------------------------------------------------
+
+def timed_workload(lib, meshes, ctx, name, k, steps, warmup, tol, mixed, extras=True):
+    """Warm-up and timed steps of `name` with k right-hand sides (mesh and solutions resident in
+    device memory), an FP64 GPU reference solve at tol 1e-13 beside them, and untimed extras: the
+    FP64-only solve, the diagonal wire basket, the host-buffer (PCIe-inclusive) step, the matvec
+    rates.  Returns (summary dict, solutions of the last timed step, reference solutions)."""
+    w = meshes.workload(name, seed=0, k=k)
+    m = w.mesh
+    prec = lib.FP32_REFINE if mixed else lib.FP64
+    ctx.release_cached()
+    d_mesh = (lib.DeviceArray(np.asarray(m.vertices, dtype=np.float64)),
+              lib.DeviceArray(np.asarray(m.triangles, dtype=np.int32)))
+
+    def step(precision, keep=False, tol=tol, wirebasket="exact", device_out=None):
+        t0 = time.perf_counter()
+        p = lib.Problem(ctx, m.vertices, m.triangles, precision=precision, near_order=10,
+                        device_mesh=(d_mesh[0].ptr, d_mesh[1].ptr) if device_out is not None else None)
+        t1 = time.perf_counter()
+        M = lib.Preconditioner(p, w.patch_of_triangle, w.coarse.vertices, w.coarse.triangles, w.coarse_of_triangle,
+                               factor_fp32=(precision == lib.FP32_REFINE), wirebasket=wirebasket)
+        t2 = time.perf_counter()
+        phi, info, rc = p.solve(g=w.g, precond=M, tol=tol, precision=precision,
+                                device_out=device_out.ptr if device_out is not None else None)
+        ctx.synchronize()
+        t3 = time.perf_counter()
+        pinfo = p.info
+        out = {"t_step": t3 - t0, "t_assemble": t1 - t0, "t_precond": t2 - t1, "t_solve": t3 - t2,
+               "t_far": pinfo["t_far_s"], "t_near": pinfo["t_near_s"], "t_contract": pinfo["t_contract_s"],
+               "t_host": pinfo["t_host_s"], "iters": [i["iters"] for i in info],
+               "outer": [i["outer_iters"] for i in info], "rc": rc, "info": pinfo, "precond_sizes": M.sizes(),
+               "phi": phi}
+        if keep:
+            out["problem"], out["M"] = p, M
+        else:
+            M.close()
+            p.close()
+        return out
+
+    # FP64 reference (not timed), the FP64-only solve and the FP64 product rates on the same system
+    log("bench: %s FP64 reference solve (tol 1e-13)" % name)
+    ref = step(lib.FP64, keep=True, tol=1e-13)
+    phi_ref = ref["phi"]
+    pinfo = ref["info"]
+    N = pinfo["n_dofs"]
+    pref, Mref = ref["problem"], ref["M"]
+    fp64_solve = None
+    if extras and mixed:
+        t0 = time.perf_counter()
+        phi64, info64, _ = pref.solve(g=w.g, precond=Mref, tol=tol, precision=lib.FP64)
+        t_s64 = time.perf_counter() - t0
+        e64 = np.linalg.norm(phi64 - phi_ref, axis=1) / np.linalg.norm(phi_ref, axis=1)
+        fp64_solve = {"t_solve_s": t_s64, "iters": [i["iters"] for i in info64], "relerr_max": float(e64.max()),
+                      "t_step_s": ref["t_assemble"] + ref["t_precond"] + t_s64}
+    t64_1 = pref.bench_matvec(fp32=False, k=1, reps=5)
+    t64_16 = pref.bench_matvec(fp32=False, k=16, reps=3)
+    Mref.close()
+    pref.close()
+    ctx.release_cached()
+
+    # one device buffer per timed step for its solutions, allocated before the timed region
+    d_out = [lib.DeviceArray(shape=(w.g.shape[0], N)) for _ in range(max(steps, 1))]
+    for i in range(warmup):
+        log("bench: %s warm-up step %d" % (name, i))
+        r = step(prec, device_out=d_out[0])
+        log("bench: %s warm-up %.3fs" % (name, r["t_step"]))
+    ctx.synchronize()
+    res = []
+    t_begin = time.perf_counter()
+    for i in range(steps):
+        res.append(step(prec, device_out=d_out[i]))
+    ctx.synchronize()
+    elapsed = time.perf_counter() - t_begin
+    phis = [d.get() for d in d_out[:steps]]
+    for d in d_out + list(d_mesh):
+        d.close()
+    for i, (r, phi) in enumerate(zip(res, phis)):
+        err = np.linalg.norm(phi - phi_ref, axis=1) / np.linalg.norm(phi_ref, axis=1)
+        r["relerr"] = err.tolist()
+        r["solved"] = int((err <= 1e-8).sum())
+        log("bench: %s step %d %.3fs asm %.3f (host %.3f far %.3f near %.4f contract %.3f) precond %.3f solve %.3f "
+            "iters %s relerr max %.2e" % (name, i, r["t_step"], r["t_assemble"], r["t_host"], r["t_far"], r["t_near"],
+                                          r["t_contract"], r["t_precond"], r["t_solve"], r["iters"][:4], max(r["relerr"])))
+    solved = sum(r["solved"] for r in res)
+    nt = pinfo["n_tri"]
+    pairs = nt * (nt + 1) // 2
+    far_pairs = pairs - pinfo["n_near_pairs"]
+    launches = max(1, int(pinfo["n_pair_panels"]))
+    t_far = float(np.mean([r["t_far"] for r in res]))
+    far_kernel = "k_far_rect" if pinfo["n_pair_panels"] > 0 else "k_far"
+    far_tflops = far_pairs * EVALS_PER_FAR_PAIR * FLOPS_PER_EVAL / t_far / 1e12
+    out = {
+        "workload": name, "description": w.description, "n_dofs": N, "n_tri": nt, "k": k,
+        "precision": "mixed" if mixed else "fp64", "tol": tol,
+        "pair_panels": int(pinfo["n_pair_panels"]),
+        "steps": steps, "warmup": warmup, "elapsed_s": elapsed,
+        "value": solved / elapsed, "ms_per_step": elapsed / steps * 1e3,
+        "latency_s": {"p50": percentile([r["t_step"] for r in res], 0.5),
+                      "p99": percentile([r["t_step"] for r in res], 0.99)},
+        "phases_s": {k_: float(np.mean([r[k_] for r in res])) for k_ in
+                     ("t_step", "t_assemble", "t_host", "t_far", "t_near", "t_contract", "t_precond", "t_solve")},
+        "iters": res[-1]["iters"], "outer_iters": res[-1]["outer"],
+        "relerr_max": max(max(r["relerr"]) for r in res),
+        "relerr_reference": "FP64 GPU PCG of the same system at relative residual 1e-13 (self-consistency; "
+                            "oracle parity: cpu_baseline.oracle_residual_rows and the GPU tests)",
+        "patches": ref["precond_sizes"],
+        "pair_integrals_per_s": pairs / float(np.mean([r["t_assemble"] for r in res])),
+        "pair_integrals_per_s_far_kernel": far_pairs / t_far,
+        "roofline": {
+            "kernel": far_kernel, "bound": "alu",
+            "achieved": round(far_tflops, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(far_tflops / PEAK_FP64_TFLOPS, 4),
+            "traffic": load_traffic(far_kernel, name),
+            "per_launch": "%d far pairs x %d evaluations x %.0f flops over %d launch(es)"
+                          % (far_pairs, EVALS_PER_FAR_PAIR, FLOPS_PER_EVAL, launches),
+            "launches": launches, "avg_launch_s": t_far / launches,
+            "isa_tflops": round(far_pairs * EVALS_PER_FAR_PAIR * ISA_FLOPS_PER_EVAL / t_far / 1e12, 3),
+        },
+        "fp64_solve": fp64_solve,
     }
+    mv = {**matvec_rates(N, 8, t64_1, "fp64_k1"), **matvec_rates(N, 8, t64_16, "fp64_k16")}
+    phi_last = phis[-1]
+    if extras:
+        # the same step with host buffers (mesh uploaded, solutions downloaded): the PCIe-inclusive
+        # rate, reported beside the value, never as it; its problem then serves the FP32 product
+        # rates and the diagonal wire basket
+        rh = step(prec, keep=True)
+        errh = np.linalg.norm(rh["phi"] - phi_ref, axis=1) / np.linalg.norm(phi_ref, axis=1)
+        out["pcie_inclusive"] = {"ms_per_step": rh["t_step"] * 1e3,
+                                 "solves_per_s": int((errh <= 1e-8).sum()) / rh["t_step"]}
+        p, M = rh["problem"], rh["M"]
+        M.close()
+        if mixed:
+            t32_1 = p.bench_matvec(fp32=True, k=1, reps=5)
+            t32_16 = p.bench_matvec(fp32=True, k=16, reps=3)
+            mv.update(matvec_rates(N, 4, t32_1, "fp32_k1"))
+            mv.update(matvec_rates(N, 4, t32_16, "fp32_k16"))
+        t0 = time.perf_counter()
+        Md = lib.Preconditioner(p, w.patch_of_triangle, w.coarse.vertices, w.coarse.triangles, w.coarse_of_triangle,
+                                factor_fp32=mixed, wirebasket="diagonal")
+        t1 = time.perf_counter()
+        phid, infod, _ = p.solve(g=w.g, precond=Md, tol=tol, precision=prec)
+        t2 = time.perf_counter()
+        errd = np.linalg.norm(phid - phi_ref, axis=1) / np.linalg.norm(phi_ref, axis=1)
+        t_stepd = out["phases_s"]["t_assemble"] + (t1 - t0) + (t2 - t1)
+        out["diagonal_wirebasket"] = {"t_precond_s": t1 - t0, "t_solve_s": t2 - t1, "t_step_s": t_stepd,
+                                      "iters": [i["iters"] for i in infod], "relerr_max": float(errd.max()),
+                                      "solves_per_s": int((errd <= 1e-8).sum()) / t_stepd}
+        Md.close()
+        p.close()
+        ctx.release_cached()
+        if fp64_solve is not None:
+            fp64_solve["solves_per_s"] = int(k) / fp64_solve["t_step_s"] if fp64_solve["relerr_max"] <= 1e-8 else 0.0
+    out["matvec"] = mv
+    # at crossed96 the oracle's exact solution of the first two columns is stored: parity
+    g = golden(name, meshes.workload(name, seed=0, k=2))
+    if g is not None:
+        phis_o = g["phi"]
+        e = np.linalg.norm(phi_last[:2] - phis_o, axis=1) / np.linalg.norm(phis_o, axis=1)
+        out["oracle_relerr_max"] = float(e.max())
+    return out, w, phi_last, phi_ref
+
+
+# ---------------------------------------------------------------------------------------------
+# side legs
+# ---------------------------------------------------------------------------------------------
+
+def small_configs_leg(lib, meshes, ctx):
+    """The unit square (16 x 16 cells) and the three-page book (h = 1/48) in FP64: PCG and CG
+    iteration counts at relative residual 1e-10 next to the oracle's, solves/s of whole steps
+    (assembly, set-up, PCG to 1e-13) counting columns within 1e-10 of the oracle's Phi*, and
+    pair-integrals/s; then kappa(P_ad W) of the book at H/h = 4 .. 24 next to the oracle's."""
+    out = {}
+    for name, k, reps in (("square16", 1, 20), ("book48", 3, 5)):
+        w = meshes.workload(name, seed=0, k=k)
+        ref = golden(name, w)
+        if ref is None:
+            raise RuntimeError("tests/golden/%s_reference.npz missing or stale" % name)
+        m = w.mesh
+        p = lib.Problem(ctx, m.vertices, m.triangles, near_order=10)
+        M = lib.Preconditioner(p, w.patch_of_triangle, w.coarse.vertices, w.coarse.triangles, w.coarse_of_triangle)
+        _, ip, _ = p.solve(g=w.g, precond=M, tol=1e-10)
+        _, ic, _ = p.solve(g=w.g, precond=None, tol=1e-10)
+        M.close()
+        p.close()
+        times, solved, worst, t_asm = [], 0, 0.0, []
+        for rep in range(reps + 1):             # the first repetition warms up
+            t0 = time.perf_counter()
+            p = lib.Problem(ctx, m.vertices, m.triangles, near_order=10)
+            t1 = time.perf_counter()
+            M = lib.Preconditioner(p, w.patch_of_triangle, w.coarse.vertices, w.coarse.triangles,
+                                   w.coarse_of_triangle)
+            phi, _, _ = p.solve(g=w.g, precond=M, tol=1e-13)
+            t2 = time.perf_counter()
+            M.close()
+            p.close()
+            e = np.linalg.norm(phi - ref["phi"], axis=1) / np.linalg.norm(ref["phi"], axis=1)
+            worst = max(worst, float(e.max()))
+            if rep > 0:
+                times.append(t2 - t0)
+                t_asm.append(t1 - t0)
+                solved += int((e <= 1e-10).sum())
+        nt = m.nt
+        out[name] = {"n_dofs": int(ref["phi"].shape[1]), "n_tri": nt, "k": k, "steps": reps,
+                     "ms_per_step": float(np.mean(times)) * 1e3, "solves_per_s": solved / float(np.sum(times)),
+                     "relerr_vs_oracle_max": worst,
+                     "pcg_iters": [i["iters"] for i in ip], "cg_iters": [i["iters"] for i in ic],
+                     "oracle_pcg_iters": ref["pcg_iters"].tolist(), "oracle_cg_iters": ref["cg_iters"].tolist(),
+                     "pair_integrals_per_s": nt * (nt + 1) / 2 / float(np.mean(t_asm))}
+        log("bench: %s %.2f ms per step, PCG %s CG %s (oracle %s %s), err %.1e" %
+            (name, out[name]["ms_per_step"], out[name]["pcg_iters"], out[name]["cg_iters"],
+             out[name]["oracle_pcg_iters"], out[name]["oracle_cg_iters"], worst))
+    # the book's condition-number growth (Thm. main) at fixed h = 1/48
+    w = meshes.workload("book48", seed=0, k=1)
+    ref = golden("book48", meshes.workload("book48", seed=0, k=3))
+    m = w.mesh
+    p = lib.Problem(ctx, m.vertices, m.triangles, near_order=10)
+    rows = []
+    for j, r in enumerate(ref["kappa_ratio"].tolist()):
+        patches = meshes.grid_patches(m, r)
+        cm, par = meshes.coarse_mesh(m, r)
+        M = lib.Preconditioner(p, patches, cm.vertices, cm.triangles, par)
+        _, info, _ = p.solve(g=w.g, precond=M, tol=1e-12)
+        s = M.sizes()
+        M.close()
+        kp = info[0]["est_cond"]
+        rows.append({"H_over_h": r, "faces": s["n_faces"], "wb": s["n_wb"], "coarse": s["n_coarse"],
+                     "kappa_pad": kp, "kappa_over_log2": kp / (1 + np.log(r)) ** 2, "pcg_iters": info[0]["iters"],
+                     "oracle_kappa_pad": float(ref["kappa_pad"][j]), "oracle_pcg_iters": int(ref["kappa_iters"][j])})
+        log("bench: book48 H/h=%d kappa %.3f (oracle %.3f) iterations %d" % (r, kp, rows[-1]["oracle_kappa_pad"],
+                                                                            info[0]["iters"]))
+    _, info, _ = p.solve(g=w.g, precond=None, tol=1e-12)
+    p.close()
+    out["book48_kappa"] = {"rows": rows, "kappa_W": info[0]["est_cond"], "oracle_kappa_W": float(ref["kappa_W"])}
+    return out
 
 
 def _replay(lib, reqs, ctx, scale, max_inflight):
@@ -210,32 +596,33 @@ def serving_leg(lib, meshes, ctx, n_requests, load, seed=0, max_inflight=4):
             worst = max(worst, float(err.max()))
         M.close()
         p.close()
-    lat = sorted(res[1][0]["t_total_s"] for res in results)
+    lat = [res[1][0]["t_total_s"] for res in results]
     n_dofs = [int(res[0].shape[1]) for res in results]
     return {
         "requests": len(reqs), "failed_requests": len(failed),
-        "direct_launch_requests": sum(1 for res in results if res[2] >= 0 and res[1][0]["graph"] == 0), "rhs": total, "rhs_within_1e-8": solved, "relerr_max": worst,
+        "direct_launch_requests": sum(1 for res in results if res[2] >= 0 and res[1][0]["graph"] == 0),
+        "rhs": total, "rhs_within_1e-8": solved, "relerr_max": worst,
         "capacity_requests_per_s": capacity, "load": load, "arrival_rate_per_s": rate,
         "max_inflight": max_inflight,
         "solves_per_s": solved / t_run,
-        "latency_s": {"p50": lat[len(lat) // 2], "p99": lat[min(len(lat) - 1, int(round(0.99 * (len(lat) - 1))))]},
+        "latency_s": {"p50": percentile(lat, 0.5), "p99": percentile(lat, 0.99)},
         "n_dofs_range": [min(n_dofs), max(n_dofs)],
         "mixed_requests": int(sum(r.mixed for r in reqs)),
         "server": stats,
     }
 
 
-def double_layer_leg(lib, w, ctx, m_targets=16384, k=16):
+def double_layer_leg(lib, meshes, ctx, m_targets=16384, k=16):
     """Double-layer potential (Lemma repDL) of k crossed96 solutions at seeded targets in [-1, 1]^3
     at least 0.05 (about 5 h) from every panel plane: evaluations (target x Gauss point) per second
     and the FP64 rate, counting 16 + 2 k flops per evaluation (distance 8, Newton step 4, cube 2,
     normal projection 2, one FMA per column; the reciprocal square root not counted)."""
+    w = meshes.workload("crossed96", seed=0, k=k)
     m = w.mesh
     p = lib.Problem(ctx, m.vertices, m.triangles, precision=lib.FP32_REFINE, near_order=10)
     M = lib.Preconditioner(p, w.patch_of_triangle, w.coarse.vertices, w.coarse.triangles, w.coarse_of_triangle,
                            factor_fp32=True)
-    g = w.g[:k] if w.g.shape[0] >= k else np.resize(w.g, (k, 3))
-    phi, _, _ = p.solve(g=g, precond=M, tol=1e-10, precision=lib.FP32_REFINE)
+    phi, _, _ = p.solve(g=w.g, precond=M, tol=1e-10, precision=lib.FP32_REFINE)
     rng = np.random.default_rng(11)
     X = []
     while len(X) < m_targets:
@@ -336,94 +723,26 @@ def kappa_study(lib, meshes, ctx):
     return rows
 
 
-def large_leg(lib, meshes, ctx, k=16):
-    """crossed192 (N = 110,017; W 48 GB FP32 + 97 GB FP64, the pair matrix built in panels): a
-    warm-up step, then one timed step (assembly, set-up, mixed-precision solve of k right-hand
-    sides to relative residual 1e-10), the FP64 PCG solve of the same system beside it, and an
-    FP64 reference (tol 1e-13) for the errors."""
-    w = meshes.workload("crossed192", seed=0, k=k)
-    m = w.mesh
-    ctx.release_cached()
-
-    def one_step():
-        t0 = time.perf_counter()
-        p = lib.Problem(ctx, m.vertices, m.triangles, precision=lib.FP32_REFINE, near_order=10)
-        t1 = time.perf_counter()
-        M = lib.Preconditioner(p, w.patch_of_triangle, w.coarse.vertices, w.coarse.triangles,
-                               w.coarse_of_triangle, factor_fp32=True)
-        t2 = time.perf_counter()
-        phi, info, rc = p.solve(g=w.g, precond=M, tol=1e-10, precision=lib.FP32_REFINE)
-        t3 = time.perf_counter()
-        return p, M, phi, info, (t0, t1, t2, t3)
-
-    p, M, _, _, (t0, t1, t2, t3) = one_step()
-    first = t3 - t0
-    M.close()
-    p.close()
-    p, M, phi, info, (t0, t1, t2, t3) = one_step()
-    pinfo = p.info
-    t4 = time.perf_counter()
-    phi64, info64, _ = p.solve(g=w.g, precond=M, tol=1e-10, precision=lib.FP64)
-    t5 = time.perf_counter()
-    ref, _, _ = p.solve(g=w.g, precond=M, tol=1e-13, precision=lib.FP64)
-    err = np.linalg.norm(phi - ref, axis=1) / np.linalg.norm(ref, axis=1)
-    err64 = np.linalg.norm(phi64 - ref, axis=1) / np.linalg.norm(ref, axis=1)
-    # the diagonal wire basket (Remark "Approximate solvers") on the same matrix
-    t6 = time.perf_counter()
-    Md = lib.Preconditioner(p, w.patch_of_triangle, w.coarse.vertices, w.coarse.triangles, w.coarse_of_triangle,
-                            factor_fp32=True, wirebasket="diagonal")
-    t7 = time.perf_counter()
-    phid, infod, _ = p.solve(g=w.g, precond=Md, tol=1e-10, precision=lib.FP32_REFINE)
-    t8 = time.perf_counter()
-    errd = np.linalg.norm(phid - ref, axis=1) / np.linalg.norm(ref, axis=1)
-    Md.close()
-    N = pinfo["n_dofs"]
-    t32 = p.bench_matvec(fp32=True, k=16, reps=3)
-    t64 = p.bench_matvec(fp32=False, k=16, reps=3)
-    nt = m.nt
-    step = t3 - t0
-    out = {
-        "workload": "crossed192: " + w.description, "n_dofs": N, "n_tri": nt, "k": k,
-        "pair_panels": pinfo["n_pair_panels"],
-        "t_step_s": step, "t_first_step_s": first, "t_assemble_s": t1 - t0, "t_precond_s": t2 - t1,
-        "t_solve_s": t3 - t2, "t_far_s": pinfo["t_far_s"], "t_near_s": pinfo["t_near_s"],
-        "t_contract_s": pinfo["t_contract_s"], "t_host_s": pinfo["t_host_s"],
-        "solves_per_s": int((err <= 1e-8).sum()) / step,
-        "iters": [i["iters"] for i in info], "relerr_max": float(err.max()),
-        "fp64_solve": {"t_solve_s": t5 - t4, "iters": [i["iters"] for i in info64], "relerr_max": float(err64.max())},
-        "diagonal_wirebasket": {"t_precond_s": t7 - t6, "t_solve_s": t8 - t7, "iters": [i["iters"] for i in infod],
-                                "relerr_max": float(errd.max()),
-                                "solves_per_s": int((errd <= 1e-8).sum()) / ((t1 - t0) + (t7 - t6) + (t8 - t7))},
-        "pair_integrals_per_s": nt * (nt + 1) / 2 / (t1 - t0),
-        "matvec": {**matvec_rates(N, 4, t32, "fp32_k16"), **matvec_rates(N, 8, t64, "fp64_k16")},
-        "patches": M.sizes(),
-    }
-    M.close()
-    p.close()
-    ctx.release_cached()
-    log("bench: crossed192 step %.3fs (first %.3fs) asm %.3f precond %.3f solve %.3f iters %s relerr %.2e"
-        % (step, first, t1 - t0, t2 - t1, t3 - t2, out["iters"][:4], out["relerr_max"]))
-    return out
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="crossed96")
+    ap.add_argument("--workload", default="crossed192", help="crossed192 (headline) or crossed96")
     ap.add_argument("--k", type=int, default=16)
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp64-compare", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
+                    help="time budget of the oracle's pair-integral sample (the rest of the baseline adds to it)")
     ap.add_argument("--serve-requests", type=int, default=24,
                     help="requests in the serving-stream leg (0 skips it)")
-    ap.add_argument("--no-large", action="store_true", help="skip the crossed192 leg")
-    ap.add_argument("--no-kappa", action="store_true", help="skip the condition-number study")
+    ap.add_argument("--no-side", action="store_true", help="skip the crossed96 side leg")
+    ap.add_argument("--no-small", action="store_true", help="skip the unit square / book leg")
+    ap.add_argument("--no-kappa", action="store_true", help="skip the two-triangle condition-number study")
     ap.add_argument("--no-potential", action="store_true", help="skip the double-layer potential leg")
     ap.add_argument("--no-planar", action="store_true", help="skip the two-dimensional experiments")
+    ap.add_argument("--headline-only", action="store_true", help="only the timed workload (profiling runs)")
     ap.add_argument("--serve-load", type=float, default=0.7,
                     help="arrival rate of the serving leg as a fraction of its measured capacity")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -444,205 +763,68 @@ def main():
         print(json.dumps({"calibration": "device-to-device copy", "bytes_read": src.numel() * 8,
                           "bytes_written": dst.numel() * 8, "launches": 3}))
         return
+    if args.headline_only:
+        args.no_cpu_baseline = args.no_side = args.no_small = args.no_kappa = True
+        args.no_potential = args.no_planar = True
+        args.serve_requests = 0
 
     from paper_2310_09204_amd import lib, meshes
 
-    w = meshes.workload(args.workload, seed=0, k=args.k)
-    m = w.mesh
     mixed = args.precision == "mixed"
-    prec = lib.FP32_REFINE if mixed else lib.FP64
-    log("bench: workload %s nt=%d k=%d precision=%s" % (args.workload, m.nt, args.k, args.precision))
+    log("bench: workload %s k=%d precision=%s" % (args.workload, args.k, args.precision))
     ctx = lib.Context(0)
-
-    # the timed steps take the mesh from device memory and leave the solutions there (inputs resident
-    # in HBM); host copies of the mesh still feed the host-side analysis
-    d_mesh = (lib.DeviceArray(np.asarray(m.vertices, dtype=np.float64)),
-              lib.DeviceArray(np.asarray(m.triangles, dtype=np.int32)))
-
-    def step(precision, want_phi=False, tol=args.tol, wirebasket="exact", device_out=None):
-        t0 = time.perf_counter()
-        p = lib.Problem(ctx, m.vertices, m.triangles, precision=precision, near_order=10,
-                        device_mesh=(d_mesh[0].ptr, d_mesh[1].ptr) if device_out is not None else None)
-        t1 = time.perf_counter()
-        M = lib.Preconditioner(p, w.patch_of_triangle, w.coarse.vertices, w.coarse.triangles, w.coarse_of_triangle,
-                               factor_fp32=(precision == lib.FP32_REFINE), wirebasket=wirebasket)
-        t2 = time.perf_counter()
-        phi, info, rc = p.solve(g=w.g, precond=M, tol=tol, precision=precision,
-                                device_out=device_out.ptr if device_out is not None else None)
-        ctx.synchronize()
-        t3 = time.perf_counter()
-        pinfo = p.info
-        out = {"t_step": t3 - t0, "t_assemble": t1 - t0, "t_precond": t2 - t1, "t_solve": t3 - t2,
-               "t_far": pinfo["t_far_s"], "t_near": pinfo["t_near_s"], "t_contract": pinfo["t_contract_s"],
-               "t_host": pinfo["t_host_s"],
-               "iters": [i["iters"] for i in info], "outer": [i["outer_iters"] for i in info], "rc": rc,
-               "info": pinfo, "precond_sizes": M.sizes()}
-        if want_phi:
-            out["phi"] = phi
-            out["problem"], out["M"] = p, M
-        else:
-            M.close()
-            p.close()
-        return out
-
-    # reference solution (not timed)
-    log("bench: FP64 reference solve (tol 1e-13)")
-    ref = step(lib.FP64, want_phi=True, tol=1e-13)
-    phi_ref = ref["phi"]
-    pinfo = ref["info"]
-    N = pinfo["n_dofs"]
-    pref = ref["problem"]
-    t64_1 = pref.bench_matvec(fp32=False, k=1, reps=10)
-    t64_16 = pref.bench_matvec(fp32=False, k=16, reps=5)
-    ref["M"].close()
-    pref.close()
-
-    # one device buffer per timed step for its solutions, allocated before the timed region
-    d_out = [lib.DeviceArray(shape=(w.g.shape[0], N)) for _ in range(max(args.steps, 1))]
-    for i in range(args.warmup):
-        log("bench: warmup %d" % i)
-        step(prec, device_out=d_out[0])
-    ctx.synchronize()
-    res = []
-    t_begin = time.perf_counter()
-    for i in range(args.steps):
-        r = step(prec, want_phi=True, device_out=d_out[i])
-        r.pop("phi")
-        r.pop("M").close()
-        r.pop("problem").close()
-        res.append(r)
-    ctx.synchronize()
-    elapsed = time.perf_counter() - t_begin
-    # checks and side measurements, outside the timed region
-    phis = [d.get() for d in d_out[:args.steps]]
-    for d in d_out:
-        d.close()
-    for i, (r, phi) in enumerate(zip(res, phis)):
-        err = np.linalg.norm(phi - phi_ref, axis=1) / np.linalg.norm(phi_ref, axis=1)
-        r["relerr"] = err.tolist()
-        r["solved"] = int((err <= 1e-8).sum())
-        log("bench: step %d %.3fs asm %.3f (host %.3f far %.3f near %.4f contract %.3f) precond %.3f solve %.3f iters %s relerr max %.2e"
-            % (i, r["t_step"], r["t_assemble"], r["t_host"], r["t_far"], r["t_near"], r["t_contract"], r["t_precond"], r["t_solve"],
-               r["iters"][:4], max(r["relerr"])))
-    t32_1 = t32_16 = None
-    if mixed:
-        pl = lib.Problem(ctx, m.vertices, m.triangles, precision=lib.FP32_REFINE, near_order=10)
-        t32_1 = pl.bench_matvec(fp32=True, k=1, reps=10)
-        t32_16 = pl.bench_matvec(fp32=True, k=16, reps=5)
-        pl.close()
-    solved = sum(r["solved"] for r in res)
-    value = solved / elapsed
-    ms_per_step = elapsed / args.steps * 1e3
-
-    fp64_step = None
-    if not args.no_fp64_compare and mixed:
-        r64 = step(lib.FP64, want_phi=True)
-        err64 = np.linalg.norm(r64["phi"] - phi_ref, axis=1) / np.linalg.norm(phi_ref, axis=1)
-        r64["M"].close()
-        r64["problem"].close()
-        fp64_step = {"t_step_s": r64["t_step"], "t_solve_s": r64["t_solve"], "iters": r64["iters"],
-                     "solves_per_s": int((err64 <= 1e-8).sum()) / r64["t_step"],
-                     "solve_only_solves_per_s": int((err64 <= 1e-8).sum()) / r64["t_solve"]}
-
-    # the same step with the diagonal wire basket (Remark "Approximate solvers")
-    rd = step(prec, want_phi=True, wirebasket="diagonal")
-    errd = np.linalg.norm(rd["phi"] - phi_ref, axis=1) / np.linalg.norm(phi_ref, axis=1)
-    rd["M"].close()
-    rd["problem"].close()
-    diag_step = {"t_step_s": rd["t_step"], "t_precond_s": rd["t_precond"], "t_solve_s": rd["t_solve"],
-                 "iters": rd["iters"], "relerr_max": float(errd.max()),
-                 "solves_per_s": int((errd <= 1e-8).sum()) / rd["t_step"]}
-    log("bench: diagonal wire basket: step %.3fs precond %.4f solve %.3f iters %s" %
-        (rd["t_step"], rd["t_precond"], rd["t_solve"], rd["iters"][:4]))
-
-    # the same step with host buffers (mesh uploaded, solutions downloaded in the step): the
-    # PCIe-inclusive rate, reported beside the value, never as it
-    t_h0 = time.perf_counter()
-    n_h, solved_h = 2, 0
-    for _ in range(n_h):
-        rh = step(prec, want_phi=True)
-        errh = np.linalg.norm(rh["phi"] - phi_ref, axis=1) / np.linalg.norm(phi_ref, axis=1)
-        solved_h += int((errh <= 1e-8).sum())
-        rh["M"].close()
-        rh["problem"].close()
-    t_h = time.perf_counter() - t_h0
-    host_io = {"steps": n_h, "ms_per_step": t_h / n_h * 1e3, "solves_per_s": solved_h / t_h}
-    log("bench: host-buffer steps (PCIe-inclusive): %.1f ms per step" % (t_h / n_h * 1e3))
-
-    nt = pinfo["n_tri"]
-    pairs = nt * (nt + 1) // 2
-    t_asm = float(np.mean([r["t_assemble"] for r in res]))
-    t_far = float(np.mean([r["t_far"] for r in res]))
-    far_pairs = pairs - pinfo["n_near_pairs"]
-    far_tflops = far_pairs * EVALS_PER_FAR_PAIR * FLOPS_PER_EVAL / t_far / 1e12
-    mv = {**matvec_rates(N, 8, t64_1, "fp64_k1"), **matvec_rates(N, 8, t64_16, "fp64_k16")}
-    if mixed:
-        mv.update(matvec_rates(N, 4, t32_1, "fp32_k1"))
-        mv.update(matvec_rates(N, 4, t32_16, "fp32_k16"))
-    lat = sorted(r["t_step"] for r in res)
-    roofline = {
-        "kernel": "k_far",
-        "bound": "alu",
-        "achieved": round(far_tflops, 3),
-        "peak": PEAK_FP64_TFLOPS,
-        "unit": "TFLOP/s",
-        "frac": round(far_tflops / PEAK_FP64_TFLOPS, 4),
-        "traffic": load_traffic("k_far", args.workload),
-        "per_launch": "%d far pairs x %d evaluations x %.4f flops" % (far_pairs, EVALS_PER_FAR_PAIR, FLOPS_PER_EVAL),
-        "avg_launch_s": t_far,
-    }
+    head, w, phi_last, phi_ref = timed_workload(lib, meshes, ctx, args.workload, args.k, args.steps, args.warmup,
+                                                args.tol, mixed, extras=not args.headline_only)
     out = {
         "metric": "PCG solves/s + p50/p99 latency at rel.err 1e-8; pair-integrals/s; matvec GB/s",
-        "value": round(value, 4),
+        "value": round(head["value"], 4),
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": round(head["ms_per_step"], 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
         "config": {"workload": "%s: %s; %d right-hand sides per step (block PCG), %s PCG to relative "
-                               "residual %.0e, rel.err <= 1e-8 vs FP64 reference" %
-                               (args.workload, w.description, args.k, "mixed-precision (FP32 products, reliable FP64 residual updates)" if mixed else "FP64",
+                               "residual %.0e, rel.err <= 1e-8 vs an FP64 solve at 1e-13" %
+                               (args.workload, w.description, args.k,
+                                "mixed-precision (FP32 products, reliable FP64 residual updates)" if mixed else "FP64",
                                 args.tol),
-                   "n_dofs": N, "n_tri": nt, "k": args.k, "precision": args.precision,
-                   "patches": ref["precond_sizes"],
+                   "n_dofs": head["n_dofs"], "n_tri": head["n_tri"], "k": args.k, "precision": args.precision,
+                   "patches": head["patches"], "pair_panels": head["pair_panels"],
                    "io": "mesh and solutions resident in device memory (bem_assemble_dev, bem_pcg_solve_dev); "
                          "the host-buffer rate is pcie_inclusive"},
-        "roofline": roofline,
-        "pair_integrals_per_s": pairs / t_asm,
-        "pair_integrals_per_s_far_kernel": far_pairs / t_far,
-        "latency_s": {"p50": lat[len(lat) // 2], "p99": lat[min(len(lat) - 1, int(round(0.99 * (len(lat) - 1))))]},
-        "phases_s": {k_: float(np.mean([r[k_] for r in res])) for k_ in
-                     ("t_step", "t_assemble", "t_host", "t_far", "t_near", "t_contract", "t_precond", "t_solve")},
-        "iters": res[-1]["iters"],
-        "outer_iters": res[-1]["outer"],
-        "relerr_max": max(max(r["relerr"]) for r in res),
-        "matvec": mv,
-        "fp64_compare": fp64_step,
-        "diagonal_wirebasket": diag_step,
-        "pcie_inclusive": host_io,
+        "roofline": head["roofline"],
+        "latency_s": head["latency_s"],
+        "pair_integrals_per_s": head["pair_integrals_per_s"],
+        "matvec": head["matvec"],
+        "headline": head,
     }
+    if not args.no_side and args.workload != "crossed96":
+        log("bench: crossed96 side leg")
+        side, _, _, _ = timed_workload(lib, meshes, ctx, "crossed96", args.k, args.steps, 1, args.tol, mixed)
+        out["crossed96"] = side
+    if not args.no_small:
+        log("bench: unit square and book (FP64)")
+        out["small_configs"] = small_configs_leg(lib, meshes, ctx)
     if not args.no_potential:
-        out["double_layer"] = double_layer_leg(lib, w, ctx)
+        out["double_layer"] = double_layer_leg(lib, meshes, ctx)
     if not args.no_planar:
         out["planar"] = planar_leg(lib, meshes, ctx)
     if not args.no_kappa:
         log("bench: condition-number study")
         out["kappa_study"] = kappa_study(lib, meshes, ctx)
-    if not args.no_large and args.workload != "crossed192":
-        log("bench: crossed192 leg")
-        out["crossed192"] = large_leg(lib, meshes, ctx)
     if args.serve_requests > 0:
         log("bench: serving stream (%d requests, load %.2f)" % (args.serve_requests, args.serve_load))
         out["serving"] = serving_leg(lib, meshes, ctx, args.serve_requests, args.serve_load)
+    ctx.close()
     if not args.no_cpu_baseline:
         log("bench: oracle on host cores (bounded sample)")
-        out["cpu_baseline"] = cpu_baseline(w, args.k, int(np.mean(res[-1]["iters"])), pinfo, args.cpu_seconds)
-    ctx.close()
+        out["cpu_baseline"] = cpu_baseline(w, args.k, int(round(np.mean(head["iters"]))), head, head["patches"],
+                                           args.cpu_seconds, {"mixed": phi_last, "fp64_reference": phi_ref})
     print(json.dumps(out), flush=True)
 
 

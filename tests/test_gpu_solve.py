@@ -209,3 +209,72 @@ def test_wirebasket_option_rejected(ctx):
     p = lib.Problem(ctx, w.mesh.vertices, w.mesh.triangles, near_order=NEAR)
     with pytest.raises(ValueError):
         lib.Preconditioner(p, w.patch_of_triangle, wirebasket="cheap")
+
+
+def _golden(name, k):
+    import hashlib
+    import os
+    w = meshes.workload(name, seed=0, k=k)
+    ref = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name + "_reference.npz"))
+    h = hashlib.sha256()
+    for a in (w.mesh.vertices, w.mesh.triangles, w.patch_of_triangle, w.coarse.vertices, w.coarse.triangles,
+              w.coarse_of_triangle, w.g):
+        a = np.ascontiguousarray(a)
+        h.update(str(a.dtype).encode() + str(a.shape).encode())
+        h.update(a.tobytes())
+    assert str(ref["input_hash"]) == h.hexdigest(), "stale golden file: rerun make_small_references.py"
+    return w, ref
+
+
+@pytest.mark.parametrize("name,k", [("square16", 1), ("book48", 3)])
+def test_small_configs_vs_oracle(ctx, name, k):
+    # the unit square and the three-page book in FP64: PCG and CG iteration counts at relative
+    # residual 1e-10 as the oracle's (+-1), and the solutions at 1e-13 within 1e-10 of Phi* in the
+    # L2 and energy norms
+    w, ref = _golden(name, k)
+    print("case", name, flush=True)
+    p, M = _setup(ctx, w)
+    try:
+        assert [M.sizes()[x] for x in ("n_faces", "n_wb", "n_coarse")] == ref["sizes"].tolist()
+        _, ip, rc = p.solve(g=w.g, precond=M, tol=1e-10)
+        _, ic, rc2 = p.solve(g=w.g, precond=None, tol=1e-10)
+        assert rc == 0 and rc2 == 0
+        for c in range(k):
+            assert abs(ip[c]["iters"] - int(ref["pcg_iters"][c])) <= 1
+            assert abs(ic[c]["iters"] - int(ref["cg_iters"][c])) <= 1
+        phi, _, rc = p.solve(g=w.g, precond=M, tol=1e-13)
+        e = phi - ref["phi"]
+        l2 = np.linalg.norm(e, axis=1) / np.linalg.norm(ref["phi"], axis=1)
+        en = np.sqrt(np.einsum("kn,kn->k", e, p.matvec(e)) / ref["energy"])
+        assert l2.max() < 1e-10 and en.max() < 1e-10, (l2, en)
+    finally:
+        M.close()
+        p.close()
+
+
+def test_book48_kappa_growth_matches_oracle(ctx):
+    # Thm. main on the book at h = 1/48: square patches of H/h cells and the nested coarse mesh of the
+    # same H, H/h = 4 .. 24; block sizes, PCG iterations and the Lanczos estimate of kappa(P_ad W) as
+    # the oracle's, and the poly-logarithmic growth the theorem bounds
+    w, ref = _golden("book48", 3)
+    m = w.mesh
+    p = lib.Problem(ctx, m.vertices, m.triangles, near_order=NEAR)
+    try:
+        kp = []
+        for j, r in enumerate(ref["kappa_ratio"].tolist()):
+            print("case book48 kappa H/h=%d" % r, flush=True)
+            cm, par = meshes.coarse_mesh(m, r)
+            M = lib.Preconditioner(p, meshes.grid_patches(m, r), cm.vertices, cm.triangles, par)
+            s = M.sizes()
+            _, info, rc = p.solve(g=w.g[:1], precond=M, tol=1e-12)
+            M.close()
+            assert rc == 0
+            assert [s["n_faces"], s["n_wb"], s["n_coarse"]] == ref["kappa_sizes"][j].tolist()
+            assert abs(info[0]["iters"] - int(ref["kappa_iters"][j])) <= 1
+            k_o = float(ref["kappa_pad"][j])
+            assert abs(info[0]["est_cond"] - k_o) < 1e-3 * k_o, (r, info[0]["est_cond"], k_o)
+            kp.append(info[0]["est_cond"])
+        ratio = np.array(kp) / (1 + np.log(ref["kappa_ratio"])) ** 2
+        assert np.all(np.diff(kp) > 0) and ratio.max() < 1.0
+    finally:
+        p.close()

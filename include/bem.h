@@ -301,8 +301,13 @@ int bem_pcg_solve_dev(bem_problem* p, const bem_precond* m, const double* g, int
 /* A background host thread takes solve requests on arbitrary multiscreens, keeps assembled
  * problems and preconditioners resident (keyed by a hash of mesh + partition + coarse mesh),
  * admits a request when its device footprint (N^2 x bytes per entry + blocks) fits the context's
- * budget next to everything resident, merges queued requests on the same geometry and precision
- * into one block PCG, and runs up to max_inflight requests on their own HIP streams. */
+ * budget next to everything resident, and runs up to max_inflight geometries at once on their own
+ * HIP streams.  Continuous batching: a geometry runs as one block PCG on column slots (16, or the
+ * columns of the requests queued when it starts); requests on the same geometry and precision
+ * that arrive while it assembles or solves join it and start in the slots that finished columns
+ * free up, each column with its own tolerance; a request completes when its own columns have
+ * stopped.  Its info[c].relres is the residual the iteration tracked (the true residual for
+ * BEM_FP32_REFINE, the recurrence residual for BEM_FP64). */
 int bem_server_create(bem_ctx* ctx, int max_inflight, bem_server** out);
 void bem_server_destroy(bem_server* s);
 typedef struct {
@@ -328,6 +333,7 @@ int bem_serve_ndofs(bem_server* s, uint64_t ticket, int64_t* n_dofs);
 typedef struct {
     int64_t submitted, completed, rejected, merged_batches, cache_hits, cache_misses;
     int64_t resident_bytes, peak_resident_bytes, evictions;
+    int64_t admitted_running;   /* requests that joined a block PCG already running on their geometry */
 } bem_server_stats;
 int bem_server_get_stats(bem_server* s, bem_server_stats* st);
 

@@ -1046,6 +1046,11 @@ PanelTimes assemble_panels(bem_problem* p, const MeshTopo& m, const NearList& ne
     };
     std::vector<std::unique_ptr<Panel>> done;
     std::vector<int32_t> stamp(size_t(nt), -1);
+    // first row block of its panel whose rows' stars hold each triangle (valid while that panel is
+    // being built): the tiles (bd, be >= bd) of the panel read row T of I only at columns
+    // >= sufmin[first_block[T]]; rowfirst keeps it per panel row
+    std::vector<int32_t> first_block(size_t(nt), 0);
+    std::vector<std::vector<int32_t>> rowfirst;
     // panel boundaries first (whole 64-dof row blocks), so that one buffer of the largest panel's
     // size serves all of them (a fresh allocation of tens of GB per panel costs seconds)
     std::vector<int64_t> starts;
@@ -1063,6 +1068,7 @@ PanelTimes assemble_panels(bem_problem* p, const MeshTopo& m, const NearList& ne
                         const int32_t T = plan.rg[g].x;
                         if (stamp[T] != id) {
                             stamp[T] = id;
+                            first_block[T] = int32_t(b1);
                             add.push_back(T);
                         }
                     }
@@ -1074,8 +1080,11 @@ PanelTimes assemble_panels(bem_problem* p, const MeshTopo& m, const NearList& ne
                 ++b1;
             }
             std::sort(rows.begin(), rows.end());
+            std::vector<int32_t> firsts(rows.size());
+            for (size_t i = 0; i < rows.size(); ++i) firsts[i] = first_block[rows[i]];
             starts.push_back(b0);
             rowsets.push_back(std::move(rows));
+            rowfirst.push_back(std::move(firsts));
             b0 = b1;
             ++id;
         }
@@ -1114,8 +1123,15 @@ PanelTimes assemble_panels(bem_problem* p, const MeshTopo& m, const NearList& ne
             P->tgt[ty].push_back(g1);
             P->tgt[ty].push_back(g2);
         }
-        for (int64_t rb = 0; rb < (nrows + kTile - 1) / kTile; ++rb)
-            for (int64_t cb = 0; cb < (ncol + kTile - 1) / kTile; ++cb) P->ftiles.push_back(make_int2(int(rb), int(cb)));
+        // far tiles: each 64-row tile from the first column any of its rows is read at (the rest of
+        // the panel's diagonal band, below it, is never read)
+        for (int64_t rb = 0; rb < (nrows + kTile - 1) / kTile; ++rb) {
+            int64_t cmin = nt;
+            for (int64_t r = rb * kTile; r < std::min<int64_t>(nrows, rb * kTile + kTile); ++r)
+                cmin = std::min<int64_t>(cmin, first_col(rowfirst[pid][r]));
+            for (int64_t cb = std::max<int64_t>(0, cmin - tmin) / kTile; cb < (ncol + kTile - 1) / kTile; ++cb)
+                P->ftiles.push_back(make_int2(int(rb), int(cb)));
+        }
 
         DeviceBuffer d_rows = upload(P->rows, s), d_rowmap = upload(P->rowmap, s), d_ft = upload(P->ftiles, s);
         P->ef = std::make_unique<EventTimer>(s);

@@ -251,6 +251,31 @@ void release_stream(bem_ctx* c, hipStream_t s);
 void matvec_setup(bem_problem* p, hipStream_t s);   // after W is allocated (ldw set)
 void matvec_device(const bem_problem* p, bool fp32, const double* d_x, int64_t ldx, int k,
                    double* d_y, hipStream_t s);
+// Continuous batching of a block PCG (serving loop): a fixed number of column slots, each running
+// its own CG (per-column scalars and tolerance).  At every check point the solver reports the
+// columns that have stopped since the last one and asks for new columns to start in the free slots.
+struct PcgColumnResult {
+    int iters = 0, status = BEM_OK, refreshes = 0;
+    double relres = 0.0;
+};
+struct PcgNewColumn {
+    int slot;
+    double g[3];      // constant Neumann data of the column (its right-hand side is built on the device)
+    double tol;       // relative residual tolerance
+};
+struct PcgSlots {
+    // column `slot` has stopped (converged, broken down, or out of iterations); d_x is its solution
+    // on the device, final once the solver's stream is synchronised (it is, at this call)
+    std::function<void(int slot, const double* d_x, const PcgColumnResult& r)> finished;
+    // the free slots and the number of columns still running -> the columns to start now.  When it
+    // returns none while no column is running, the batch ends.
+    std::function<void(const std::vector<int>& free_slots, int running, std::vector<PcgNewColumn>& start)> admit;
+    bool graphed = false;   // out: the iterations ran as graph replays
+};
+// runs the block PCG on `slots` column slots until the hooks stop admitting; max_iter per column
+void pcg_serve(bem_problem* p, const bem_precond* M, bool mixed, int slots, int max_iter, int check_every,
+               PcgSlots& hooks);
+
 // the same products with their scratch in the device array of bem_matvec_noalloc (solver.hip):
 // its size, the per-device address (looked up once per device, with that device current), the
 // bytes one product of this problem needs there, and the launch

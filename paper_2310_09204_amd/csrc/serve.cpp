@@ -5,9 +5,12 @@
 //           whose footprint can never fit the context's HBM budget, and queues the rest.
 //   worker  takes the oldest request whose geometry is not in use and whose footprint fits next to
 //           everything resident (evicting idle cached geometries, least recently used first),
-//           merges every queued request on the same geometry, precision and tolerance into one
-//           multi-right-hand-side PCG, reuses the cached assembled matrix and preconditioner or
-//           builds them, solves, and hands each request its columns.
+//           opens a running batch for that geometry and precision with every queued request on
+//           it, reuses the cached assembled matrix and preconditioner or builds them, and runs a
+//           block PCG on column slots (continuous batching): requests on the same geometry that
+//           arrive while the batch is assembling or solving join it and start in the slots that
+//           finished columns free up; each request completes as soon as its own columns have
+//           stopped.  The batch ends when no column runs and nothing waits.
 //   poll    waits for a request and returns its result and latency (submit to completion).
 //
 // Footprint: resident W (8 N^2 bytes, plus 4 N^2 for the FP32 copy of mixed-precision requests)
@@ -29,6 +32,7 @@ using namespace bem;
 namespace {
 
 using Clock = std::chrono::steady_clock;
+constexpr int kSlots = 16;   // column slots of a serving batch (the block product's column group)
 
 struct Request {
     uint64_t ticket = 0, key = 0;
@@ -45,6 +49,13 @@ struct Request {
     std::string err;              // message of a failed request, handed to the polling thread
     std::vector<double> phi;
     std::vector<bem_solve_info> info;
+    int remaining = 0;            // columns still running in a batch
+};
+
+// a block PCG of one geometry and precision that takes new requests while it runs
+struct Running {
+    uint64_t key = 0;
+    std::deque<Request*> pending;   // attached requests waiting for free column slots
 };
 
 struct Entry {
@@ -74,6 +85,7 @@ struct bem_server {
     std::deque<Request*> queue;
     std::map<uint64_t, Request*> requests;
     std::map<uint64_t, Entry> cache;
+    std::map<uint64_t, Running*> running;   // open batches by geometry key
     std::vector<std::thread> workers;
     bool stop = false;
     uint64_t next_ticket = 1;
@@ -114,6 +126,7 @@ void worker_main(bem_server* s) {
         std::vector<Request*> batch;
         bool hit = false;
         int64_t reserve = 0;
+        Running run;
         {
             std::unique_lock<std::mutex> lk(s->mu);
             for (;;) {
@@ -133,7 +146,7 @@ void worker_main(bem_server* s) {
                 if (pick) {
                     for (auto it = s->queue.begin(); it != s->queue.end();) {
                         Request* r = *it;
-                        if (r->key == pick->key && r->precision == pick->precision && r->tol == pick->tol) {
+                        if (r->key == pick->key) {
                             batch.push_back(r);
                             it = s->queue.erase(it);
                         } else {
@@ -148,16 +161,41 @@ void worker_main(bem_server* s) {
             Entry& e = s->cache[batch[0]->key];
             e.busy = true;
             if (hit) s->stats.cache_hits += 1; else s->stats.cache_misses += 1;
-            if (batch.size() > 1) s->stats.merged_batches += 1;
+            run.key = batch[0]->key;
+            run.pending.assign(batch.begin(), batch.end());
+            s->running[run.key] = &run;     // later requests on this geometry attach here
         }
+        // requests complete (and their polling threads free them) while the batch still runs: after
+        // the solve starts, nothing here reads a request it has handed back
         Request* r0 = batch[0];
-        int rc = BEM_OK;
-        std::string err;
+        const uint64_t key = r0->key;
+        const bem_precision precision = r0->precision;
+        int ktot = 0;
+        for (Request* r : batch) ktot += r->k;
+        const int nslots = std::max(kSlots, ktot);
+        std::vector<std::pair<Request*, int>> owner(size_t(nslots), {nullptr, 0});
+        int served = 0;
         Entry* entry = nullptr;
         {
             std::lock_guard<std::mutex> lk(s->mu);
-            entry = &s->cache[r0->key];
+            entry = &s->cache[key];
         }
+        // completes r (caller holds the lock)
+        auto complete = [&](Request* r, int rc, const std::string& err) {
+            r->t_done = Clock::now();
+            r->done = true;
+            if (rc < 0) r->rc = rc;
+            if (r->rc < 0) r->err = err.empty() ? "request failed" : err;
+            const double lat = std::chrono::duration<double>(r->t_done - r->t_submit).count();
+            if (r->info.size() != size_t(r->k)) r->info.assign(size_t(r->k), bem_solve_info{});
+            for (auto& in : r->info) {
+                in.t_total_s = lat;
+                if (r->rc < 0 && in.status == BEM_OK && in.iters == 0) in.status = r->rc;
+            }
+            s->stats.completed += 1;
+        };
+        std::string err;
+        int rc = BEM_OK;
         try {
             if (!entry->problem) {
                 bem_assemble_opts ao{r0->precision, 10, 0, 0};
@@ -178,65 +216,107 @@ void worker_main(bem_server* s) {
                 entry->precond = m;
                 entry->bytes = p->bytes + m->bytes;
             }
-            int ktot = 0;
-            for (Request* r : batch) ktot += r->k;
-            std::vector<double> g;
-            for (Request* r : batch) g.insert(g.end(), r->g.begin(), r->g.end());
-            bem_solve_opts o{};
-            o.tol = r0->tol;
-            o.max_iter = 2000;
-            o.use_precond = 1;
-            o.precision = r0->precision;
-            o.refresh_factor = 1e-3;
-            o.check_every = 4;
-            o.use_graph = 1;
-            const int64_t N = entry->problem->N;
-            std::vector<double> phi(size_t(N) * ktot);
-            std::vector<bem_solve_info> info(ktot);
-            rc = bem_pcg_solve(entry->problem, entry->precond, g.data(), ktot, &o, phi.data(), info.data());
-            if (rc < 0 && rc != BEM_E_NOT_CONVERGED && rc != BEM_E_BREAKDOWN) err = bem_last_error();
-            int off = 0;
-            for (Request* r : batch) {
-                r->phi.assign(phi.begin() + size_t(off) * N, phi.begin() + size_t(off + r->k) * N);
-                r->info.assign(info.begin() + off, info.begin() + off + r->k);
-                int rr = BEM_OK;
-                for (auto& in : r->info) {
-                    if (in.status == BEM_E_BREAKDOWN) rr = BEM_E_BREAKDOWN;
-                    else if (in.status == BEM_E_NOT_CONVERGED && rr == BEM_OK) rr = BEM_E_NOT_CONVERGED;
+            bem_problem* prob = entry->problem;
+            const int64_t N = prob->N;
+            HIP_CHECK(hipSetDevice(s->ctx->device));
+            if (N == 0) {   // no dofs (every vertex on the boundary): the solution is empty
+                {
+                    std::lock_guard<std::mutex> lk(s->mu);
+                    s->running.erase(run.key);
+                    for (Request* r : run.pending) {
+                        r->info.assign(size_t(r->k), bem_solve_info{});
+                        complete(r, BEM_OK, "");
+                    }
+                    run.pending.clear();
                 }
-                r->rc = (rc < 0 && rc != BEM_E_NOT_CONVERGED && rc != BEM_E_BREAKDOWN) ? rc : rr;
-                off += r->k;
+                s->cv_done.notify_all();
+                throw Failure{BEM_OK, ""};
             }
+            PcgSlots hooks;
+            hooks.admit = [&](const std::vector<int>& free_slots, int running, std::vector<PcgNewColumn>& start) {
+                std::lock_guard<std::mutex> lk(s->mu);
+                size_t fi = 0;
+                while (!run.pending.empty() && size_t(run.pending.front()->k) <= free_slots.size() - fi) {
+                    Request* r = run.pending.front();
+                    run.pending.pop_front();
+                    r->phi.assign(size_t(N) * r->k, 0.0);
+                    r->info.assign(size_t(r->k), bem_solve_info{});
+                    r->remaining = r->k;
+                    for (int col = 0; col < r->k; ++col) {
+                        const int slot = free_slots[fi++];
+                        owner[size_t(slot)] = {r, col};
+                        PcgNewColumn nc{slot, {r->g[3 * col], r->g[3 * col + 1], r->g[3 * col + 2]}, r->tol};
+                        start.push_back(nc);
+                    }
+                    if (++served == 2) s->stats.merged_batches += 1;   // counted before any request completes
+                }
+                if (start.empty() && running == 0) {
+                    // the batch ends: requests too wide for the free slots go back to the queue front
+                    s->running.erase(run.key);
+                    for (auto it = run.pending.rbegin(); it != run.pending.rend(); ++it) s->queue.push_front(*it);
+                    if (!run.pending.empty()) s->cv_work.notify_all();
+                    run.pending.clear();
+                }
+            };
+            hooks.finished = [&](int slot, const double* d_x, const PcgColumnResult& res) {
+                auto [r, col] = owner[size_t(slot)];
+                owner[size_t(slot)] = {nullptr, 0};
+                if (!r) return;
+                if (N > 0)
+                    HIP_CHECK(hipMemcpyAsync(r->phi.data() + size_t(col) * N, d_x, sizeof(double) * N, hipMemcpyDeviceToHost,
+                                             prob->stream));
+                HIP_CHECK(hipStreamSynchronize(prob->stream));
+                bem_solve_info& in = r->info[size_t(col)];
+                in.iters = res.iters;
+                in.outer_iters = res.refreshes;
+                in.status = res.status;
+                in.graph = hooks.graphed ? 1 : 0;
+                in.relres = res.relres;
+                in.est_cond = std::nan("");
+                if (res.status == BEM_E_BREAKDOWN) r->rc = BEM_E_BREAKDOWN;
+                else if (res.status == BEM_E_NOT_CONVERGED && r->rc == BEM_OK) r->rc = BEM_E_NOT_CONVERGED;
+                if (--r->remaining == 0) {
+                    {
+                        std::lock_guard<std::mutex> lk(s->mu);
+                        complete(r, BEM_OK, res.status == BEM_E_BREAKDOWN ? "(P)CG breakdown" : "(P)CG did not converge");
+                    }
+                    s->cv_done.notify_all();
+                }
+            };
+            std::lock_guard<std::mutex> call(prob->call_mu);
+            (void)hipGetLastError();   // an error left by another thread's call is not this batch's
+            pcg_serve(prob, entry->precond, precision == BEM_FP32_REFINE, nslots, 2000, 4, hooks);
         } catch (const Failure& f) {
-            rc = f.code;
+            rc = f.code;      // BEM_OK: the batch ended early, every request handed back
             err = f.msg;
-            for (Request* r : batch) r->rc = rc;
         } catch (const std::bad_alloc&) {
             rc = BEM_E_OOM;
             err = "host allocation failed";
-            for (Request* r : batch) r->rc = rc;
+        } catch (const std::exception& e) {
+            rc = BEM_E_DEVICE;
+            err = e.what();
         }
         {
             std::lock_guard<std::mutex> lk(s->mu);
+            if (rc < 0) {
+                // a failed batch fails every request it holds: running in a slot, or still waiting
+                s->running.erase(run.key);
+                for (auto& o : owner)
+                    if (o.first && !o.first->done) {
+                        Request* r = o.first;
+                        for (auto& oo : owner)
+                            if (oo.first == r) oo.first = nullptr;
+                        complete(r, rc, err);
+                    }
+                for (Request* r : run.pending) complete(r, rc, err);
+                run.pending.clear();
+            }
             s->reserved -= reserve;
-            auto it = s->cache.find(r0->key);
+            auto it = s->cache.find(key);
             if (it != s->cache.end()) {
                 it->second.busy = false;
                 it->second.last_used = Clock::now();
                 if (!it->second.problem) s->cache.erase(it);   // failed build
-            }
-            const auto now = Clock::now();
-            for (Request* r : batch) {
-                r->t_done = now;
-                r->done = true;
-                if (r->rc < 0) r->err = err.empty() ? "request failed" : err;
-                const double lat = std::chrono::duration<double>(r->t_done - r->t_submit).count();
-                for (auto& in : r->info) in.t_total_s = lat;
-                if (r->info.empty()) {
-                    r->info.resize(r->k);
-                    for (auto& in : r->info) { std::memset(&in, 0, sizeof(in)); in.status = r->rc; in.t_total_s = lat; }
-                }
-                s->stats.completed += 1;
             }
             int64_t res = s->resident();
             s->stats.resident_bytes = res;
@@ -330,8 +410,14 @@ int bem_serve_submit(bem_server* s, const bem_request* q, uint64_t* ticket) {
         *ticket = r->ticket;
         Request* raw = r.release();
         s->requests[raw->ticket] = raw;
-        s->queue.push_back(raw);
-        s->cv_work.notify_one();
+        auto run = s->running.find(raw->key);
+        if (run != s->running.end()) {
+            run->second->pending.push_back(raw);   // joins the block PCG running on its geometry
+            s->stats.admitted_running += 1;
+        } else {
+            s->queue.push_back(raw);
+            s->cv_work.notify_one();
+        }
         return BEM_OK;
     } catch (const Failure& f) {
         set_last_error(f.msg);

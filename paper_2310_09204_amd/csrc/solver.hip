@@ -496,6 +496,9 @@ __global__ void k_axpy_cols(double* __restrict__ x, const double* __restrict__ d
         x[int64_t(c) * ld + i] += d[int64_t(c) * ld + i];
 }
 
+// a serving column that ran out of iterations stops (its state is kept for the report)
+__global__ void k_stop_column(ColState* __restrict__ st) { st->active = 0; }
+
 // state init from partials of b.b, r.r, r.z
 __global__ __launch_bounds__(256) void k_init_state(const double* __restrict__ pbb, const double* __restrict__ prr,
                                                     const double* __restrict__ prz, int G, const double* __restrict__ tol2,
@@ -731,9 +734,12 @@ struct PcgResult {
 // solve), with reliable updates: the recurrence residual is replaced by the true residual
 // b - W x with the FP64 matrix whenever it has fallen by `refresh` since the last replacement, and
 // before any column is declared converged, so convergence is always judged on a true residual.
+// slots != nullptr (serving): b and x are the slot buffers (zero at the start, every column
+// inactive), columns are started and collected through the hooks at the check points, and
+// max_iter bounds each column's iterations instead of the launches.
 PcgResult pcg_device(bem_problem* p, const bem_precond* M, bool mixed, const double* b, double* x, bool x_nonzero,
                      int k, int64_t ld, const std::vector<double>& tol, int max_iter, int check_every, bool use_graph,
-                     bool want_cond, double refresh) {
+                     bool want_cond, double refresh, PcgSlots* slots = nullptr) {
     hipStream_t s = p->stream;
     const int64_t N = p->N;
     const unsigned G = gblocks(N);
@@ -890,7 +896,82 @@ PcgResult pcg_device(bem_problem* p, const bem_precond* M, bool mixed, const dou
         for (auto& c : hs) if (c.active) return true;
         return false;
     };
-    while (any_active() && launched < max_iter) {
+
+    // serving: collect the stopped columns, stop the ones out of iterations, start new ones
+    std::vector<char> owned(size_t(k), 0);
+    std::vector<double> hg(3 * static_cast<size_t>(k)), htol2(static_cast<size_t>(k));
+    DeviceBuffer dg(slots ? sizeof(double) * 3 * k : 8, s);
+    auto serve_check = [&]() -> bool {
+        bool changed = false;
+        for (int c = 0; c < k; ++c)
+            if (owned[c] && hs[c].active && hs[c].iters >= max_iter) {
+                hipLaunchKernelGGL(k_stop_column, dim3(1), dim3(1), 0, s, st + c);
+                hs[c].active = 0;
+                changed = true;
+            }
+        if (changed) HIP_CHECK(hipStreamSynchronize(s));
+        std::vector<int> free_slots;
+        int running = 0;
+        for (int c = 0; c < k; ++c) {
+            if (owned[c] && !hs[c].active) {
+                PcgColumnResult cr;
+                cr.iters = hs[c].iters;
+                cr.refreshes = hs[c].refreshes;
+                cr.relres = hs[c].bb > 0 ? std::sqrt(hs[c].rr / hs[c].bb) : 0.0;
+                cr.status = hs[c].flag ? BEM_E_BREAKDOWN : (hs[c].rr <= hs[c].tol2 * hs[c].bb ? BEM_OK : BEM_E_NOT_CONVERGED);
+                slots->finished(c, x + int64_t(c) * ld, cr);
+                owned[c] = 0;
+            }
+            if (!owned[c]) free_slots.push_back(c);
+            else ++running;
+        }
+        std::vector<PcgNewColumn> start;
+        slots->admit(free_slots, running, start);
+        if (start.empty()) return running > 0;
+        const dim3 g1(G, 1);
+        for (const PcgNewColumn& nc : start) {
+            const int c = nc.slot;
+            if (c < 0 || c >= k || owned[c]) fail(BEM_E_INVALID_ARG, "serving: column slot not free");
+            std::copy(nc.g, nc.g + 3, &hg[size_t(3) * c]);
+            htol2[c] = nc.tol * nc.tol;
+            HIP_CHECK(hipMemcpyAsync(dg.as<double>() + 3 * c, &hg[size_t(3) * c], sizeof(double) * 3, hipMemcpyHostToDevice, s));
+            HIP_CHECK(hipMemcpyAsync(dtol.as<double>() + c, &htol2[c], sizeof(double), hipMemcpyHostToDevice, s));
+            double* bc = const_cast<double*>(b) + int64_t(c) * ld;
+            rhs_device(p, dg.as<double>() + 3 * c, 1, bc, s);
+            hipLaunchKernelGGL(k_fill, dim3(G), vb, 0, s, x + int64_t(c) * ld, 0.0, N);
+            hipLaunchKernelGGL(k_copy, g1, vb, 0, s, bc, r.as<double>() + int64_t(c) * ld, ld, N);
+        }
+        apply_M(r.as<double>(), z.as<double>());   // every slot: z is scratch between iterations
+        for (const PcgNewColumn& nc : start) {
+            const int c = nc.slot;
+            const int64_t o = int64_t(c) * ld;
+            const double* bc = b + o;
+            hipLaunchKernelGGL(k_copy, g1, vb, 0, s, z.as<double>() + o, pp.as<double>() + o, ld, N);
+            hipLaunchKernelGGL(k_dot_partial, g1, vb, 0, s, bc, bc, ld, N, pa + int64_t(c) * G);
+            hipLaunchKernelGGL(k_dot_partial, g1, vb, 0, s, r.as<double>() + o, r.as<double>() + o, ld, N, pb + int64_t(c) * G);
+            hipLaunchKernelGGL(k_dot_partial, g1, vb, 0, s, r.as<double>() + o, z.as<double>() + o, ld, N, pc + int64_t(c) * G);
+            hipLaunchKernelGGL(k_init_state, dim3(1), vb, 0, s, pa + int64_t(c) * G, pb + int64_t(c) * G, pc + int64_t(c) * G,
+                               int(G), dtol.as<double>() + c, st + c);
+            owned[c] = 1;
+        }
+        HIP_CHECK(hipGetLastError());
+        HIP_CHECK(hipMemcpyAsync(hs.data(), st, sizeof(ColState) * k, hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        for (const PcgNewColumn& nc : start) rr_ref[nc.slot] = hs[nc.slot].rr;
+        return true;
+    };
+    if (slots) slots->graphed = graphed;
+    for (;;) {
+        if (slots) {
+            // the hooks decide when the batch ends; columns that stop on their start (zero
+            // right-hand side) are reported at the next check without an iteration
+            if (!any_active()) {
+                if (!serve_check()) break;
+                if (!any_active()) continue;
+            }
+        } else if (!(any_active() && launched < max_iter)) {
+            break;
+        }
         // mixed: replace the residual now if a column may have converged (then check right after)
         // or if a column's residual has fallen by `refresh` since its last replacement
         bool near = false, fallen = false;
@@ -900,13 +981,15 @@ PcgResult pcg_device(bem_problem* p, const bem_precond* M, bool mixed, const dou
                     near = near || hs[c].near;
                     fallen = fallen || hs[c].rr < refresh2 * rr_ref[c];
                 }
-        const int n = near ? 1 : std::min(every, max_iter - launched);
+        // (serving: max_iter bounds each column, through serve_check, not the launches)
+        const int n = near ? 1 : (slots ? every : std::min(every, max_iter - launched));
         for (int i = 0; i < n; ++i) launch(i == 0 && (near || fallen));
         launched += n;
         HIP_CHECK(hipMemcpyAsync(hs.data(), st, sizeof(ColState) * k, hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
         if (near || fallen)
             for (int c = 0; c < k; ++c) rr_ref[c] = hs[c].rr;
+        if (slots && !serve_check()) break;
     }
     PcgResult res;
     res.graphed = graphed;
@@ -1011,6 +1094,22 @@ void solve_device(bem_problem* p, const bem_precond* M, const double* b, double*
             info[c].est_cond = cond[c];
             info[c].t_total_s = tt;
         }
+}
+
+void pcg_serve(bem_problem* p, const bem_precond* M, bool mixed, int slots, int max_iter, int check_every,
+               PcgSlots& hooks) {
+    if (slots < 1) fail(BEM_E_INVALID_ARG, "serving: no column slots");
+    if (mixed && !p->W32.ptr) fail(BEM_E_INVALID_ARG, "mixed precision needs a problem assembled with BEM_FP32_REFINE");
+    if (mixed && M && !M->inv32.ptr) fail(BEM_E_INVALID_ARG, "mixed precision needs a preconditioner with factor_fp32 = 1");
+    hipStream_t s = p->stream;
+    const int64_t ld = p->N;
+    DeviceBuffer b(sizeof(double) * std::max<int64_t>(1, ld * slots), s), x(sizeof(double) * std::max<int64_t>(1, ld * slots), s);
+    hipLaunchKernelGGL(k_fill, dim3(256), dim3(256), 0, s, b.as<double>(), 0.0, ld * slots);
+    hipLaunchKernelGGL(k_fill, dim3(256), dim3(256), 0, s, x.as<double>(), 0.0, ld * slots);
+    HIP_CHECK(hipGetLastError());
+    std::vector<double> tol(size_t(slots), 1.0);   // every slot starts inactive (b = 0)
+    pcg_device(p, M, mixed, b.as<double>(), x.as<double>(), false, slots, ld, tol, max_iter, check_every, true, false, 1e-3,
+               &hooks);
 }
 
 }  // namespace bem

@@ -75,7 +75,7 @@ class Request(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("submitted", "completed", "rejected", "merged_batches",
                                                 "cache_hits", "cache_misses", "resident_bytes",
-                                                "peak_resident_bytes", "evictions")]
+                                                "peak_resident_bytes", "evictions", "admitted_running")]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -163,3 +163,34 @@ def test_served_results_match_oracle(ctx):
         en = np.sqrt(np.einsum("kn,nk->k", e, W @ e.T) / np.einsum("nk,nk->k", xs, W @ xs))
         bound = 1e-8 if r.mixed else 1e-10
         assert l2.max() < bound and en.max() < bound, (r.geometry, r.mixed, l2, en)
+
+
+def test_requests_join_a_running_batch(ctx):
+    # continuous batching: one geometry, a 12-column request first, then four more on the same
+    # geometry a millisecond apart; they attach to the block PCG that the first one opened (during
+    # its assembly or its iterations) and start in free column slots.  Every result equals the
+    # request solved alone, within the tolerance.
+    import time
+    base = _book_request((0.0, 120.0, 240.0), 3)
+    rng = np.random.default_rng(21)
+    reqs = []
+    for k in (12, 3, 2, 1, 2):
+        g = rng.standard_normal((k, 3))
+        g /= np.linalg.norm(g, axis=1, keepdims=True)
+        reqs.append(meshes.ServeRequest(0.0, 7, base.mesh, base.patch_of_triangle, base.coarse,
+                                        base.coarse_of_triangle, g, False))
+    print("case serve-continuous", base.mesh.nt, [r.g.shape[0] for r in reqs], flush=True)
+    srv = lib.Server(ctx, max_inflight=2)
+    tickets = []
+    for r in reqs:
+        tickets.append(submit(srv, r))
+        time.sleep(1e-3)
+    outs = [srv.poll(t) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(reqs) and st["merged_batches"] >= 1 and st["admitted_running"] >= 1, st
+    for r, (phi, info, rc) in zip(reqs, outs):
+        assert rc == 0 and phi.shape == (r.g.shape[0], phi.shape[1])
+        phi_solo, ref = solo(ctx, r)
+        assert relerr(phi, phi_solo) < 1e-10 and relerr(phi, ref) < 1e-10
+        assert all(i["relres"] <= TOL64 for i in info)

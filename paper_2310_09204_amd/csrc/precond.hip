@@ -41,20 +41,6 @@ struct BlockMeta { int64_t n, npad, idx_off, mat_off, xoff; };
 // tile costs one memory latency instead of sixteen.
 constexpr int kTilePer = TBK * TBK / 256;
 
-__device__ __forceinline__ void tile_load(double* __restrict__ s, const double* __restrict__ g, int64_t ld) {
-    double v[kTilePer];
-#pragma unroll
-    for (int q = 0; q < kTilePer; ++q) {
-        const int e = threadIdx.x + 256 * q;
-        v[q] = g[int64_t(e >> 6) * ld + (e & 63)];
-    }
-#pragma unroll
-    for (int q = 0; q < kTilePer; ++q) {
-        const int e = threadIdx.x + 256 * q;
-        s[(e >> 6) * LDT + (e & 63)] = v[q];
-    }
-}
-
 __device__ __forceinline__ void tile_store(const double* __restrict__ s, double* __restrict__ g, int64_t ld) {
     double v[kTilePer];
 #pragma unroll
@@ -69,60 +55,19 @@ __device__ __forceinline__ void tile_store(const double* __restrict__ s, double*
     }
 }
 
-// global 64 x 64 tile copy: dst (row stride ld) <- src (contiguous)
-__device__ __forceinline__ void tile_copy(double* __restrict__ dst, int64_t ld, const double* __restrict__ src) {
+// LDS tile <- sign * G^T (G a 64 x 64 tile in global memory with row stride ld)
+__device__ __forceinline__ void tile_load_t(double* __restrict__ s, const double* __restrict__ g, int64_t ld, double sign) {
     double v[kTilePer];
-#pragma unroll
-    for (int q = 0; q < kTilePer; ++q) v[q] = src[threadIdx.x + 256 * q];
 #pragma unroll
     for (int q = 0; q < kTilePer; ++q) {
         const int e = threadIdx.x + 256 * q;
-        dst[int64_t(e >> 6) * ld + (e & 63)] = v[q];
+        v[q] = g[int64_t(e >> 6) * ld + (e & 63)];
     }
-}
-
-// C (64 x 64) = op(A) op(B) on the FP64 matrix cores, from two LDS tiles.  Wave w computes rows
-// 16w .. 16w+15 as four 16x16 output tiles n = 0..3; lane l = 16 kk + i supplies A[16w+i][k0+kk] and
-// B[k0+kk][16n+i] to each 16x16x4 step, and register r of acc[n] holds C[16w + kk + 4r][16n + i].
-template <bool TA, bool TB>
-__device__ __forceinline__ void tile_mfma(f64x4 (&acc)[4], const double* __restrict__ A, const double* __restrict__ B) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int i = lane & 15, kk = lane >> 4;
-    const int row = 16 * w + i;
-#pragma unroll 4
-    for (int k0 = 0; k0 < TBK; k0 += 4) {
-        const int k = k0 + kk;
-        const double a = TA ? A[k * LDT + row] : A[row * LDT + k];
 #pragma unroll
-        for (int n = 0; n < 4; ++n) {
-            const int col = 16 * n + i;
-            const double b = TB ? B[col * LDT + k] : B[k * LDT + col];
-            acc[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[n], 0, 0, 0);
-        }
+    for (int q = 0; q < kTilePer; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        s[(e & 63) * LDT + (e >> 6)] = sign * v[q];
     }
-}
-
-__device__ __forceinline__ void mfma_zero(f64x4 (&acc)[4]) {
-#pragma unroll
-    for (int n = 0; n < 4; ++n) acc[n] = f64x4{0.0, 0.0, 0.0, 0.0};
-}
-
-// g[r][c] (row stride ld) = scale * acc (+ g[r][c] if accumulate)
-__device__ __forceinline__ void mfma_store(const f64x4 (&acc)[4], double* __restrict__ g, int64_t ld, double scale,
-                                           bool accumulate) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int i = lane & 15, kk = lane >> 4;
-    double old[4][4];   // read everything before the first write: one memory latency, not sixteen
-#pragma unroll
-    for (int n = 0; n < 4; ++n)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-            old[n][r] = accumulate ? g[int64_t(16 * w + kk + 4 * r) * ld + 16 * n + i] : 0.0;
-#pragma unroll
-    for (int n = 0; n < 4; ++n)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-            g[int64_t(16 * w + kk + 4 * r) * ld + 16 * n + i] = accumulate ? fma(scale, acc[n][r], old[n][r]) : scale * acc[n][r];
 }
 
 // --- gather: A_b = W[idx_b, idx_b] padded with the identity ---------------------------------
@@ -148,152 +93,291 @@ __global__ __launch_bounds__(256) void k_gather(const int4* __restrict__ tasks, 
     }
 }
 
-// --- block Gauss-Jordan inversion ---------------------------------------------------------------
-// Each block B (a face, the wire basket, the coarse Galerkin matrix; SPD, padded with the identity)
-// is overwritten by its inverse.  Step k of the elimination, with P = (S_kk)^{-1} of the current
-// state S:  S_kj <- P S_kj (row k),  S_ik <- -S_ik P (column k),  S_ij <- S_ij - S_ik P S_kj
-// (i, j != k),  S_kk <- P.  Pivot blocks of an SPD matrix stay SPD, so no pivoting is needed.
-// The state keeps a signed symmetry: S_ij = s S_ji^T with s = -1 exactly when one of i, j has been
-// eliminated, so only the lower tiles (i >= j) are stored and updated; an upper tile is read as the
-// signed transpose of its mirror.  At the end every index is eliminated and the lower tiles hold
-// the (symmetric) inverse, which is then mirrored into the upper tiles.
-// A step is two launches.  k_gj_row stages, for every j != k, the old column value C_j = S_jk and
-// the new row value R_j = P S_kj, and the new column tile -S_jk P for j > k.  k_gj_update applies
-// S_ij -= C_i R_j to the lower tiles off row and column k and copies the new row / column / pivot
-// tiles in; the block that updates tile (k+1, k+1) also inverts it, so the next step's pivot
-// inverse is ready when its row launch starts.  No launch writes a tile that it also reads.
+// --- block Gauss-Jordan inversion, 128-wide pivots ----------------------------------------------
+// Each block B (a face, the wire basket, the coarse Galerkin matrix; SPD, padded with the identity
+// to a multiple of 128) is overwritten by its inverse.  Step k eliminates the k-th 128-wide block
+// row and column.  With P = (S_kk)^{-1} of the current state S:  S_kj <- P S_kj (row k),
+// S_ik <- -S_ik P (column k),  S_ij <- S_ij - S_ik P S_kj (i, j != k),  S_kk <- P.  Pivot blocks
+// of an SPD matrix stay SPD, so no pivoting is needed.  The state keeps a signed symmetry:
+// S_ij = s S_ji^T with s = -1 exactly when one of i, j has been eliminated, so only the lower tiles
+// (i >= j) are stored and updated; an upper tile is read as the signed transpose of its mirror.
+// At the end every index is eliminated and the lower tiles hold the (symmetric) inverse, which
+// is then mirrored into the upper tiles.  The whole lower triangle is read and written once per
+// step, so 128-wide pivots halve the passes over the matrix against 64-wide ones, and every tile
+// update is a 128 x 128 x 128 product on the FP64 matrix cores.
+// A step is two launches.  k_gj_row stages, for every j != k, the old column value C_j = S_jk,
+// the new row value R_j = P S_kj and, for j > k, the new column tile D_j = -S_jk P.  k_gj_update
+// applies S_ij -= C_i R_j to the lower tiles off row and column k and copies the new row / column
+// / pivot tiles in; the task of tile (k+1, k+1) comes first in the launch, and after its update it
+// inverts the tile: the pivot inverse of step k+1.  No launch writes a tile that it also reads.
+constexpr int TB2 = 128;   // pivot width and tile edge
+constexpr int KC2 = 16;    // K chunk of the tile products
+constexpr int LS2 = 144;   // LDS row stride (doubles) of a staged chunk: lanes 0-31 and 32-63 of a read
+                           // hit disjoint banks (2 x 144 = 32 mod 64 banks between consecutive k)
 
-// In-place inverse of the 64 x 64 tile T (LDS, row stride LDT) by scalar Gauss-Jordan without
-// pivoting.  Thread (tr, tc) keeps rows 4tr..4tr+3 x columns 4tc..4tc+3 in registers; each step
-// publishes the pivot row and column through LDS (double-buffered, one barrier per step).  Returns
-// false if a pivot was not positive and finite (then the tile is not SPD).
-__device__ bool tile_inverse_gj(double* __restrict__ T, double* __restrict__ rowbuf, double* __restrict__ colbuf) {
-    const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
-    double a[4][4];
+// A 128 x 128 operand M in global memory: M(r, c) = sign * (stored transposed ? p[c ld + r] : p[r ld + c]).
+// A K-chunk of an A operand is staged as st[k][x] = A(x, k0 + k), of a B operand as st[k][x] = B(k0 + k, x);
+// xcontig tells whether x runs along the stored rows (coalesced either way).
+struct Opnd {
+    const double* p;
+    int64_t ld;
+    bool xcontig;
+    double sign;
+};
+__device__ __forceinline__ Opnd opnd_a(const double* p, int64_t ld, bool trans, double sign) { return Opnd{p, ld, trans, sign}; }
+__device__ __forceinline__ Opnd opnd_b(const double* p, int64_t ld, bool trans, double sign) { return Opnd{p, ld, !trans, sign}; }
+
+// thread t fetches 8 consecutive stored doubles of the chunk at k0
+__device__ __forceinline__ void chunk_fetch(double (&v)[8], const Opnd& o, int k0) {
+    const int t = threadIdx.x;
+    const double* q = o.xcontig ? o.p + int64_t(k0 + (t >> 4)) * o.ld + (t & 15) * 8
+                                : o.p + int64_t(t >> 1) * o.ld + k0 + (t & 1) * 8;
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int j = 0; j < 8; j += 2) {
+        const double2 d = *reinterpret_cast<const double2*>(q + j);
+        v[j] = d.x;
+        v[j + 1] = d.y;
+    }
+}
+
+__device__ __forceinline__ void chunk_put(double* __restrict__ st, const double (&v)[8], const Opnd& o) {
+    const int t = threadIdx.x;
+    if (o.xcontig) {
+        double* d = st + (t >> 4) * LS2 + (t & 15) * 8;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) a[r][c] = T[(4 * tr + r) * LDT + 4 * tc + c];
-    bool ok = true;
-    for (int q = 0; q < TBK / 4; ++q) {
+        for (int j = 0; j < 8; ++j) d[j] = o.sign * v[j];
+    } else {
+        const int x = t >> 1, kb = (t & 1) * 8;
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-            const int kk = 4 * q + rr;
-            double* rb = rowbuf + (kk & 1) * TBK;
-            double* cb = colbuf + (kk & 1) * TBK;
-            if (tr == q) {
+        for (int j = 0; j < 8; ++j) st[(kb + j) * LS2 + x] = o.sign * v[j];
+    }
+}
+
+// acc += A B, A and B 128 x 128 operands, on the FP64 matrix cores.  Wave w = 2 wr + wc computes
+// rows 64 wr .. 64 wr + 63 x columns 64 wc .. 64 wc + 63 as 4 x 4 tiles of 16 x 16; lane l = 16 kk + i
+// supplies A[row i][k kk] and B[k kk][column i] to each 16x16x4 step, and register r of
+// acc[mt][nt] holds C[64 wr + 16 mt + kk + 4 r][64 wc + 16 nt + i].  K runs in chunks of 16 through
+// LDS; the next chunk's loads are in flight while the current one is used.
+__device__ __forceinline__ void gemm128(f64x4 (&acc)[4][4], const Opnd& A, const Opnd& B, double* __restrict__ sa,
+                                        double* __restrict__ sb) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i = lane & 15, kk = lane >> 4;
+    const int wr = w >> 1, wc = w & 1;
+    double va[8], vb[8];
+    chunk_fetch(va, A, 0);
+    chunk_fetch(vb, B, 0);
+    for (int c = 0; c < TB2 / KC2; ++c) {
+        __syncthreads();   // the previous chunk's reads are done
+        chunk_put(sa, va, A);
+        chunk_put(sb, vb, B);
+        __syncthreads();
+        if (c + 1 < TB2 / KC2) {
+            chunk_fetch(va, A, (c + 1) * KC2);
+            chunk_fetch(vb, B, (c + 1) * KC2);
+        }
 #pragma unroll
-                for (int c = 0; c < 4; ++c) rb[4 * tc + c] = a[rr][c];
-            }
-            if (tc == q) {
+        for (int ks = 0; ks < KC2 / 4; ++ks) {
+            const int k = 4 * ks + kk;
+            double a[4], b[4];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) cb[4 * tr + r] = a[r][rr];
-            }
-            __syncthreads();
-            const double piv = rb[kk];
-            ok = ok && (piv > 0.0) && isfinite(piv);
-            const double pinv = 1.0 / piv;
+            for (int m = 0; m < 4; ++m) a[m] = sa[k * LS2 + 64 * wr + 16 * m + i];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = 4 * tr + r;
-                const double aik = cb[i] * pinv;
+            for (int n = 0; n < 4; ++n) b[n] = sb[k * LS2 + 64 * wc + 16 * n + i];
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const int j = 4 * tc + c;
-                    const double akj = rb[j];
-                    double v;
-                    if (i == kk) v = (j == kk) ? pinv : akj * pinv;
-                    else if (j == kk) v = -aik;
-                    else v = fma(-aik, akj, a[r][c]);
-                    a[r][c] = v;
-                }
-            }
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int n = 0; n < 4; ++n) acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[n], acc[m][n], 0, 0, 0);
         }
     }
-    __syncthreads();
+}
+
+__device__ __forceinline__ void acc_zero(f64x4 (&acc)[4][4]) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) T[(4 * tr + r) * LDT + 4 * tc + c] = a[r][c];
+        for (int n = 0; n < 4; ++n) acc[m][n] = f64x4{0.0, 0.0, 0.0, 0.0};
+}
+
+// g (128 x 128, row stride ld) = scale * acc, or += scale * acc; the old values of each half of a
+// thread's tile are read together before they are written
+__device__ __forceinline__ void acc_store(const f64x4 (&acc)[4][4], double* __restrict__ g, int64_t ld, double scale,
+                                          bool accumulate) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i = lane & 15, kk = lane >> 4;
+    const int wr = w >> 1, wc = w & 1;
+    double* g0 = g + int64_t(64 * wr + kk) * ld + 64 * wc + i;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        double old[2][4][4];
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    old[m][n][r] = accumulate ? g0[int64_t(16 * (2 * h + m) + 4 * r) * ld + 16 * n] : 0.0;
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    g0[int64_t(16 * (2 * h + m) + 4 * r) * ld + 16 * n] = accumulate ? fma(scale, acc[2 * h + m][n][r], old[m][n][r])
+                                                                                     : scale * acc[2 * h + m][n][r];
+    }
+}
+
+// dst (128 x 128, row stride ldd) = M, M an operand as above, through the chunk stage (coalesced
+// reads and writes also for a transposed source)
+__device__ __forceinline__ void copy128(double* __restrict__ dst, int64_t ldd, const Opnd& M, double* __restrict__ st) {
+    // M given as a B operand: each chunk stages rows k0 .. k0 + 15 of M, st[k][x] = M(k0 + k, x)
+    const int t = threadIdx.x;
+    for (int c = 0; c < TB2 / KC2; ++c) {
+        double v[8];
+        chunk_fetch(v, M, c * KC2);
+        __syncthreads();
+        chunk_put(st, v, M);
+        __syncthreads();
+        const int r = t >> 4, x0 = (t & 15) * 8;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) dst[int64_t(c * KC2 + r) * ldd + x0 + j] = st[r * LS2 + x0 + j];
+    }
+}
+
+// One elimination step kk = 8 q + RR of the 128 x 128 scalar Gauss-Jordan below, on this thread's
+// 8 x 8 registers (rows 8 tr .., columns 8 tc ..): the owners of row and column kk publish them
+// through LDS, then every element takes its new value without branches.
+template <int RR>
+__device__ __forceinline__ void gj128_step(double (&a)[64], int q, int tr, int tc, double* __restrict__ rowbuf,
+                                           double* __restrict__ colbuf, bool& ok) {
+    const int kk = 8 * q + RR;
+    double* rb = rowbuf + (RR & 1) * TB2;
+    double* cb = colbuf + (RR & 1) * TB2;
+    if (tr == q) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) rb[8 * tc + c] = a[RR * 8 + c];
+    }
+    if (tc == q) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) cb[8 * tr + r] = a[r * 8 + RR];
+    }
     __syncthreads();
+    const double piv = rb[kk];
+    ok = ok && (piv > 0.0) && isfinite(piv);
+    const double pinv = 1.0 / piv;
+    double akj[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) akj[c] = rb[8 * tc + c];
+    const bool colq = tc == q;   // this thread holds column kk (its local column RR)
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const bool rowk = (8 * tr + r) == kk;
+        const double aik = cb[8 * tr + r] * pinv;
+        const double m = rowk ? 0.0 : aik;
+        const double s = rowk ? pinv : 1.0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            // row kk: akj * pinv; other rows: a - aik akj
+            double v = rowk ? akj[c] * s : fma(-m, akj[c], a[r * 8 + c]);
+            if (c == RR) v = colq ? (rowk ? pinv : -aik) : v;
+            a[r * 8 + c] = v;
+        }
+    }
+}
+
+// In-place inverse of a 128 x 128 SPD matrix by scalar Gauss-Jordan without pivoting: src (row
+// stride lds) -> dst (row stride ldd).  Thread (tr, tc) = (t >> 4, t & 15) keeps rows 8 tr .. 8 tr + 7 x
+// columns 8 tc .. 8 tc + 7 in registers; each step publishes the pivot row and column through LDS
+// (alternating buffers, one barrier per step).  Returns false if a pivot was not positive and
+// finite (then the matrix is not SPD).
+__device__ __forceinline__ bool inverse128(const double* __restrict__ src, int64_t lds, double* __restrict__ dst, int64_t ldd,
+                                           double* __restrict__ rowbuf, double* __restrict__ colbuf) {
+    const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
+    double a[64];
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int c = 0; c < 8; c += 2) {
+            const double2 d = *reinterpret_cast<const double2*>(src + int64_t(8 * tr + r) * lds + 8 * tc + c);
+            a[r * 8 + c] = d.x;
+            a[r * 8 + c + 1] = d.y;
+        }
+    bool ok = true;
+    for (int q = 0; q < TB2 / 8; ++q) {
+        gj128_step<0>(a, q, tr, tc, rowbuf, colbuf, ok);
+        gj128_step<1>(a, q, tr, tc, rowbuf, colbuf, ok);
+        gj128_step<2>(a, q, tr, tc, rowbuf, colbuf, ok);
+        gj128_step<3>(a, q, tr, tc, rowbuf, colbuf, ok);
+        gj128_step<4>(a, q, tr, tc, rowbuf, colbuf, ok);
+        gj128_step<5>(a, q, tr, tc, rowbuf, colbuf, ok);
+        gj128_step<6>(a, q, tr, tc, rowbuf, colbuf, ok);
+        gj128_step<7>(a, q, tr, tc, rowbuf, colbuf, ok);
+    }
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int c = 0; c < 8; c += 2)
+            *reinterpret_cast<double2*>(dst + int64_t(8 * tr + r) * ldd + 8 * tc + c) = make_double2(a[r * 8 + c], a[r * 8 + c + 1]);
     return ok;
 }
 
-// tile (row i, column j) of block m, row stride npad
+// tile (row i, column j) of block m (64-wide tiles), row stride npad
 __device__ __forceinline__ double* tile_at(double* a0, const BlockMeta& m, int i, int j) {
     return a0 + int64_t(i) * TBK * m.npad + int64_t(j) * TBK;
 }
 
-// LDS tile <- sign * G^T (G a 64 x 64 tile in global memory with row stride ld)
-__device__ __forceinline__ void tile_load_t(double* __restrict__ s, const double* __restrict__ g, int64_t ld, double sign) {
-    double v[kTilePer];
-#pragma unroll
-    for (int q = 0; q < kTilePer; ++q) {
-        const int e = threadIdx.x + 256 * q;
-        v[q] = g[int64_t(e >> 6) * ld + (e & 63)];
-    }
-#pragma unroll
-    for (int q = 0; q < kTilePer; ++q) {
-        const int e = threadIdx.x + 256 * q;
-        s[(e & 63) * LDT + (e >> 6)] = sign * v[q];
-    }
+// tile (row i, column j) of block m (128-wide tiles), row stride npad
+__device__ __forceinline__ double* tile2_at(double* a0, const BlockMeta& m, int i, int j) {
+    return a0 + int64_t(i) * TB2 * m.npad + int64_t(j) * TB2;
 }
 
-// scratch of block b: C_j (old column values), R_j (new row values), D_j (new column tiles), and
-// the pivot inverse, at 3 npad x 64 per block, then one pivot tile per block
-__device__ __forceinline__ double* gj_C(double* scr, const BlockMeta& m, int j) { return scr + 3 * m.xoff * TBK + int64_t(j) * TBK * TBK; }
-__device__ __forceinline__ double* gj_R(double* scr, const BlockMeta& m, int j) { return scr + (3 * m.xoff + m.npad) * TBK + int64_t(j) * TBK * TBK; }
-__device__ __forceinline__ double* gj_D(double* scr, const BlockMeta& m, int j) { return scr + (3 * m.xoff + 2 * m.npad) * TBK + int64_t(j) * TBK * TBK; }
+// scratch of block b: C_j (old column values), R_j (new row values), D_j (new column tiles), at
+// 3 npad x 128 per block, then two pivot tiles per block
+__device__ __forceinline__ double* gj_C(double* scr, const BlockMeta& m, int j) { return scr + 3 * m.xoff * TB2 + int64_t(j) * TB2 * TB2; }
+__device__ __forceinline__ double* gj_R(double* scr, const BlockMeta& m, int j) { return scr + (3 * m.xoff + m.npad) * TB2 + int64_t(j) * TB2 * TB2; }
+__device__ __forceinline__ double* gj_D(double* scr, const BlockMeta& m, int j) { return scr + (3 * m.xoff + 2 * m.npad) * TB2 + int64_t(j) * TB2 * TB2; }
 
 // the pivot inverse of step k lives in slot k % 2 of the block's two pivot tiles (the update
-// launch of step k copies slot k % 2 while it writes slot (k+1) % 2)
+// launch of step k reads slot k % 2 while it writes slot (k+1) % 2)
 __device__ __forceinline__ double* gj_piv(double* scr, int64_t pivot_off, int b, int k) {
-    return scr + pivot_off + (int64_t(b) * 2 + (k & 1)) * TBK * TBK;
+    return scr + pivot_off + (int64_t(b) * 2 + (k & 1)) * TB2 * TB2;
 }
 
-// step k, task (b, k, j), j != k (step 0 also has j = k): the staging for column j.  The pivot
-// inverse comes from the previous update launch; at step 0 every task inverts the first pivot
-// tile itself and task j = 0 keeps it.
+// the first pivot inverse of every block (task (b, 0, 0))
+__global__ __launch_bounds__(256) void k_gj_pivot0(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
+                                                   double* __restrict__ A, double* __restrict__ scr, int64_t pivot_off,
+                                                   int* __restrict__ flags) {
+    __shared__ double rowbuf[2 * TB2], colbuf[2 * TB2];
+    const int4 t = tasks[blockIdx.x];
+    const BlockMeta m = meta[t.x];
+    const bool ok = inverse128(tile2_at(A + m.mat_off, m, 0, 0), m.npad, gj_piv(scr, pivot_off, t.x, 0), TB2, rowbuf, colbuf);
+    if (!ok && threadIdx.x == 0) flags[t.x] = 1;
+}
+
+// step k, task (b, k, j), j != k: the staging for column j
 __global__ __launch_bounds__(256) void k_gj_row(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
-                                                double* __restrict__ A, double* __restrict__ scr, int64_t pivot_off,
-                                                int k, int* __restrict__ flags) {
-    __shared__ double P[TBK * LDT];
-    __shared__ double Q[TBK * LDT];
-    __shared__ double rowbuf[2 * TBK], colbuf[2 * TBK];
+                                                double* __restrict__ A, double* __restrict__ scr, int64_t pivot_off, int k) {
+    __shared__ double sa[KC2 * LS2], sb[KC2 * LS2];
     const int4 t = tasks[blockIdx.x];
     const BlockMeta m = meta[t.x];
     const int j = t.z;
     double* a0 = A + m.mat_off;
-    double* piv = gj_piv(scr, pivot_off, t.x, k);
-    if (k == 0) {
-        tile_load(P, tile_at(a0, m, 0, 0), m.npad);
-        __syncthreads();
-        const bool ok = tile_inverse_gj(P, rowbuf, colbuf);
-        if (j == 0) {
-            if (!ok && threadIdx.x == 0) flags[t.x] = 1;
-            tile_store(P, piv, TBK);
-            return;
-        }
-    } else {
-        tile_load(P, piv, TBK);
-    }
-    // S_kj (row value) and S_jk (old column value) from the stored lower tile of the pair
-    if (j < k) tile_load(Q, tile_at(a0, m, k, j), m.npad);           // S_kj stored
-    else tile_load_t(Q, tile_at(a0, m, j, k), m.npad, 1.0);           // S_kj = S_jk^T (both uneliminated)
-    __syncthreads();
-    f64x4 acc[4];
-    mfma_zero(acc);
-    tile_mfma<false, false>(acc, P, Q);                                // R_j = P S_kj
-    mfma_store(acc, gj_R(scr, m, j), TBK, 1.0, false);
-    __syncthreads();
-    if (j < k) tile_load_t(Q, tile_at(a0, m, k, j), m.npad, -1.0);   // S_jk = -S_kj^T (j eliminated)
-    else tile_load(Q, tile_at(a0, m, j, k), m.npad);                  // S_jk stored
-    __syncthreads();
-    tile_store(Q, gj_C(scr, m, j), TBK);
+    const double* piv = gj_piv(scr, pivot_off, t.x, k);
+    // S_kj and S_jk from the stored lower tile of the pair
+    const Opnd Pa = opnd_a(piv, TB2, false, 1.0), Pb = opnd_b(piv, TB2, false, 1.0);
+    const Opnd Skj = j < k ? opnd_b(tile2_at(a0, m, k, j), m.npad, false, 1.0)    // stored
+                           : opnd_b(tile2_at(a0, m, j, k), m.npad, true, 1.0);    // S_jk^T, both uneliminated
+    f64x4 acc[4][4];
+    acc_zero(acc);
+    gemm128(acc, Pa, Skj, sa, sb);                                               // R_j = P S_kj
+    acc_store(acc, gj_R(scr, m, j), TB2, 1.0, false);
+    // C_j = S_jk: -S_kj^T if j is eliminated, else stored
+    const Opnd Sjk_b = j < k ? opnd_b(tile2_at(a0, m, k, j), m.npad, true, -1.0) : opnd_b(tile2_at(a0, m, j, k), m.npad, false, 1.0);
+    copy128(gj_C(scr, m, j), TB2, Sjk_b, sa);
     if (j > k) {
-        mfma_zero(acc);
-        tile_mfma<false, false>(acc, Q, P);                            // new column tile -S_jk P
-        mfma_store(acc, gj_D(scr, m, j), TBK, -1.0, false);
+        acc_zero(acc);
+        gemm128(acc, opnd_a(tile2_at(a0, m, j, k), m.npad, false, 1.0), Pb, sa, sb);   // new column tile -S_jk P
+        acc_store(acc, gj_D(scr, m, j), TB2, -1.0, false);
     }
 }
 
@@ -303,46 +387,29 @@ __global__ __launch_bounds__(256) void k_gj_row(const int4* __restrict__ tasks, 
 __global__ __launch_bounds__(256) void k_gj_update(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
                                                    double* __restrict__ A, double* __restrict__ scr, int64_t pivot_off,
                                                    int k, int* __restrict__ flags) {
-    __shared__ double P[TBK * LDT];
-    __shared__ double Q[TBK * LDT];
-    __shared__ double rowbuf[2 * TBK], colbuf[2 * TBK];
+    __shared__ double sa[KC2 * LS2], sb[KC2 * LS2];
+    __shared__ double rowbuf[2 * TB2], colbuf[2 * TB2];
     const int4 t = tasks[blockIdx.x];
     const BlockMeta m = meta[t.x];
     const int i = t.y, j = t.z;
     double* a0 = A + m.mat_off;
-    double* gij = tile_at(a0, m, i, j);
+    double* gij = tile2_at(a0, m, i, j);
     if (i == k || j == k) {
         const double* src = (i == k && j == k) ? gj_piv(scr, pivot_off, t.x, k) : (i == k) ? gj_R(scr, m, j) : gj_D(scr, m, i);
-        tile_copy(gij, m.npad, src);
+        copy128(gij, m.npad, opnd_b(src, TB2, false, 1.0), sa);
         return;
     }
-    tile_load(P, gj_C(scr, m, i), TBK);
-    tile_load(Q, gj_R(scr, m, j), TBK);
-    __syncthreads();
-    f64x4 acc[4];
-    mfma_zero(acc);
-    tile_mfma<false, false>(acc, P, Q);
-    if (!(i == k + 1 && j == k + 1)) {
-        mfma_store(acc, gij, m.npad, -1.0, true);
-        return;
+    f64x4 acc[4][4];
+    acc_zero(acc);
+    gemm128(acc, opnd_a(gj_C(scr, m, i), TB2, false, 1.0), opnd_b(gj_R(scr, m, j), TB2, false, 1.0), sa, sb);
+    acc_store(acc, gij, m.npad, -1.0, true);
+    if (i == k + 1 && j == k + 1) {
+        // next pivot: the updated tile, as this block wrote it, inverted into slot (k+1) % 2
+        __threadfence_block();
+        __syncthreads();
+        const bool ok = inverse128(gij, m.npad, gj_piv(scr, pivot_off, t.x, k + 1), TB2, rowbuf, colbuf);
+        if (!ok && threadIdx.x == 0) flags[t.x] = 1;
     }
-    // next pivot: update the tile in LDS, store it, and invert it into slot (k+1) % 2
-    __syncthreads();
-    tile_load(P, gij, m.npad);
-    __syncthreads();
-    {
-        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-        const int ii = lane & 15, kk = lane >> 4;
-#pragma unroll
-        for (int n = 0; n < 4; ++n)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) P[(16 * w + kk + 4 * r) * LDT + 16 * n + ii] -= acc[n][r];
-    }
-    __syncthreads();
-    tile_store(P, gij, m.npad);
-    const bool ok = tile_inverse_gj(P, rowbuf, colbuf);
-    if (!ok && threadIdx.x == 0) flags[t.x] = 1;
-    tile_store(P, gj_piv(scr, pivot_off, t.x, k + 1), TBK);
 }
 
 // the inverse is symmetric: upper tiles (i < j) from the lower ones
@@ -869,7 +936,7 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
     int64_t moff = 0, xoff = 0;
     for (int64_t b = 0; b < nall; ++b) {
         const int64_t n = (b < M->nblocks) ? int64_t(blocks[b].size()) : M->nH;
-        const int64_t npad = ((n + TBK - 1) / TBK) * TBK;
+        const int64_t npad = ((n + TB2 - 1) / TB2) * TB2;
         meta[b] = {n, npad, int64_t(idx.size()), moff, xoff};
         xoff += npad;
         if (b < M->nblocks) idx.insert(idx.end(), blocks[b].begin(), blocks[b].end());
@@ -886,9 +953,9 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
     M->idx = upload(idx, s);
     M->blk_meta = upload(meta, s);
     DeviceBuffer A(sizeof(double) * std::max<int64_t>(moff, 1), s);
-    // Gauss-Jordan scratch: per block its staged tiles (3 x npad x 64), then two pivot tiles each
-    const int64_t pivot_off = 3 * xoff * TBK;
-    DeviceBuffer scr(sizeof(double) * (pivot_off + nall * 2 * TBK * TBK), s);
+    // Gauss-Jordan scratch: per block its staged tiles (3 x npad x 128), then two pivot tiles each
+    const int64_t pivot_off = 3 * xoff * TB2;
+    DeviceBuffer scr(sizeof(double) * (pivot_off + nall * 2 * TB2 * TB2), s);
     DeviceBuffer dflags(sizeof(int) * std::max<int64_t>(nall, 1), s);
     HIP_CHECK(hipMemsetAsync(dflags.ptr, 0, sizeof(int) * std::max<int64_t>(nall, 1), s));
 
@@ -897,7 +964,7 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
     // ---- every tile task of the set-up, planned on the host and uploaded once.  Two plans: the
     //      faces and the wire basket (problem stream), and the coarse block (second stream, after
     //      its Galerkin matrix) -----------------------------------------------------------------------
-    enum Kind { GATHER, GJ_ROW, GJ_UPDATE, MIRROR };
+    enum Kind { GATHER, GJ_PIVOT0, GJ_ROW, GJ_UPDATE, MIRROR };
     struct Launch { Kind kind; int param; int64_t off, n; };
     std::vector<int4> all;
     std::vector<Launch> plan_fw, plan_c;
@@ -906,34 +973,46 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
         plan.push_back({kind, param, int64_t(all.size()), int64_t(tl.size())});
         all.insert(all.end(), tl.begin(), tl.end());
     };
-    std::vector<int> ntile(nall);
-    for (int64_t b = 0; b < nall; ++b) ntile[b] = int(meta[b].npad / TBK);
+    // 128-wide tiles for the elimination, 64-wide ones for the gather and the mirror
+    std::vector<int> ntile(nall), ntile64(nall);
+    for (int64_t b = 0; b < nall; ++b) {
+        ntile[b] = int(meta[b].npad / TB2);
+        ntile64[b] = int(meta[b].npad / TBK);
+    }
     auto plan_blocks = [&](std::vector<Launch>& plan, int64_t b0, int64_t b1) {
         int maxT = 0;
-        for (int64_t b = b0; b < b1; ++b) maxT = std::max(maxT, ntile[b]);
+        std::vector<int4> tp;
+        for (int64_t b = b0; b < b1; ++b) {
+            maxT = std::max(maxT, ntile[b]);
+            if (ntile[b] > 0) tp.push_back(make_int4(int(b), 0, 0, 0));
+        }
+        add(plan, GJ_PIVOT0, 0, tp);
         for (int k = 0; k < maxT; ++k) {   // block Gauss-Jordan, all blocks with a step k together
             std::vector<int4> tr, tu;
+            for (int64_t b = b0; b < b1; ++b)   // the next pivot's task first: it carries the inversion
+                if (k + 1 < ntile[b]) tu.push_back(make_int4(int(b), k + 1, k + 1, 0));
             for (int64_t b = b0; b < b1; ++b) {
                 if (k >= ntile[b]) continue;
                 for (int j = 0; j < ntile[b]; ++j)
-                    if (j != k || k == 0) tr.push_back(make_int4(int(b), k, j, 0));
+                    if (j != k) tr.push_back(make_int4(int(b), k, j, 0));
                 for (int i = 0; i < ntile[b]; ++i)
-                    for (int j = 0; j <= i; ++j) tu.push_back(make_int4(int(b), i, j, 0));
+                    for (int j = 0; j <= i; ++j)
+                        if (!(i == k + 1 && j == k + 1)) tu.push_back(make_int4(int(b), i, j, 0));
             }
             add(plan, GJ_ROW, k, tr);
             add(plan, GJ_UPDATE, k, tu);
         }
         std::vector<int4> tm;
         for (int64_t b = b0; b < b1; ++b)
-            for (int i = 1; i < ntile[b]; ++i)
+            for (int i = 1; i < ntile64[b]; ++i)
                 for (int j = 0; j < i; ++j) tm.push_back(make_int4(int(b), i, j, 0));
         add(plan, MIRROR, 0, tm);
     };
     {
         std::vector<int4> tl;
         for (int64_t b = 0; b < M->nblocks; ++b)
-            for (int i = 0; i < ntile[b]; ++i)
-                for (int j = 0; j < ntile[b]; ++j) tl.push_back(make_int4(int(b), i, j, 0));
+            for (int i = 0; i < ntile64[b]; ++i)
+                for (int j = 0; j < ntile64[b]; ++j) tl.push_back(make_int4(int(b), i, j, 0));
         add(plan_fw, GATHER, 0, tl);
     }
     plan_blocks(plan_fw, 0, M->nblocks);
@@ -946,7 +1025,8 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
         const dim3 g(unsigned(L.n)), bl(256);
         switch (L.kind) {
             case GATHER: hipLaunchKernelGGL(k_gather, g, bl, 0, st, d, dm, M->idx.as<int32_t>(), p->W64.as<double>(), p->ldw, M->diag_shift, A.as<double>()); break;
-            case GJ_ROW: hipLaunchKernelGGL(k_gj_row, g, bl, 0, st, d, dm, A.as<double>(), scr.as<double>(), pivot_off, L.param, dflags.as<int>()); break;
+            case GJ_PIVOT0: hipLaunchKernelGGL(k_gj_pivot0, g, bl, 0, st, d, dm, A.as<double>(), scr.as<double>(), pivot_off, dflags.as<int>()); break;
+            case GJ_ROW: hipLaunchKernelGGL(k_gj_row, g, bl, 0, st, d, dm, A.as<double>(), scr.as<double>(), pivot_off, L.param); break;
             case GJ_UPDATE: hipLaunchKernelGGL(k_gj_update, g, bl, 0, st, d, dm, A.as<double>(), scr.as<double>(), pivot_off, L.param, dflags.as<int>()); break;
             case MIRROR: hipLaunchKernelGGL(k_mirror, g, bl, 0, st, d, dm, A.as<double>()); break;
         }

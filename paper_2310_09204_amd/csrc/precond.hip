@@ -17,12 +17,14 @@
 // Applying M is then a ragged batch of dense row-panel products.  With the diagonal wire basket
 // (Remark "Approximate solvers") that block is replaced by 1 / W_dd on its dofs.
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <map>
 #include <numeric>
+#include <tuple>
 
 #include "internal.h"
 #include "strips.h"
@@ -105,15 +107,16 @@ __global__ __launch_bounds__(256) void k_gather(const int4* __restrict__ tasks, 
 // is then mirrored into the upper tiles.  The whole lower triangle is read and written once per
 // step, so 128-wide pivots halve the passes over the matrix against 64-wide ones, and every tile
 // update is a 128 x 128 x 128 product on the FP64 matrix cores.
-// A step is two launches.  k_gj_row stages, for every j != k, the old column value C_j = S_jk,
+// A step is three launches.  k_gj_row stages, for every j != k, the old column value C_j = S_jk,
 // the new row value R_j = P S_kj and, for j > k, the new column tile D_j = -S_jk P.  k_gj_update
 // applies S_ij -= C_i R_j to the lower tiles off row and column k and copies the new row / column
-// / pivot tiles in; the task of tile (k+1, k+1) comes first in the launch, and after its update it
-// inverts the tile: the pivot inverse of step k+1.  No launch writes a tile that it also reads.
+// / pivot tiles in (the next pivot's tile first).  k_gj_pivot inverts the updated tile (k+1, k+1):
+// the pivot inverse of step k+1.  No launch writes a tile that it also reads.
 constexpr int TB2 = 128;   // pivot width and tile edge
 constexpr int KC2 = 16;    // K chunk of the tile products
 constexpr int LS2 = 144;   // LDS row stride (doubles) of a staged chunk: lanes 0-31 and 32-63 of a read
                            // hit disjoint banks (2 x 144 = 32 mod 64 banks between consecutive k)
+constexpr int NT2 = 512;   // threads of every elimination launch: 8 waves
 
 // A 128 x 128 operand M in global memory: M(r, c) = sign * (stored transposed ? p[c ld + r] : p[r ld + c]).
 // A K-chunk of an A operand is staged as st[k][x] = A(x, k0 + k), of a B operand as st[k][x] = B(k0 + k, x);
@@ -127,43 +130,42 @@ struct Opnd {
 __device__ __forceinline__ Opnd opnd_a(const double* p, int64_t ld, bool trans, double sign) { return Opnd{p, ld, trans, sign}; }
 __device__ __forceinline__ Opnd opnd_b(const double* p, int64_t ld, bool trans, double sign) { return Opnd{p, ld, !trans, sign}; }
 
-// thread t fetches 8 consecutive stored doubles of the chunk at k0
-__device__ __forceinline__ void chunk_fetch(double (&v)[8], const Opnd& o, int k0) {
+// thread t fetches 4 consecutive stored doubles of the chunk at k0
+__device__ __forceinline__ void chunk_fetch(double (&v)[4], const Opnd& o, int k0) {
     const int t = threadIdx.x;
-    const double* q = o.xcontig ? o.p + int64_t(k0 + (t >> 4)) * o.ld + (t & 15) * 8
-                                : o.p + int64_t(t >> 1) * o.ld + k0 + (t & 1) * 8;
-#pragma unroll
-    for (int j = 0; j < 8; j += 2) {
-        const double2 d = *reinterpret_cast<const double2*>(q + j);
-        v[j] = d.x;
-        v[j + 1] = d.y;
-    }
+    const double* q = o.xcontig ? o.p + int64_t(k0 + (t >> 5)) * o.ld + (t & 31) * 4
+                                : o.p + int64_t(t >> 2) * o.ld + k0 + (t & 3) * 4;
+    const double2 d0 = *reinterpret_cast<const double2*>(q), d1 = *reinterpret_cast<const double2*>(q + 2);
+    v[0] = d0.x;
+    v[1] = d0.y;
+    v[2] = d1.x;
+    v[3] = d1.y;
 }
 
-__device__ __forceinline__ void chunk_put(double* __restrict__ st, const double (&v)[8], const Opnd& o) {
+__device__ __forceinline__ void chunk_put(double* __restrict__ st, const double (&v)[4], const Opnd& o) {
     const int t = threadIdx.x;
     if (o.xcontig) {
-        double* d = st + (t >> 4) * LS2 + (t & 15) * 8;
+        double* d = st + (t >> 5) * LS2 + (t & 31) * 4;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) d[j] = o.sign * v[j];
+        for (int j = 0; j < 4; ++j) d[j] = o.sign * v[j];
     } else {
-        const int x = t >> 1, kb = (t & 1) * 8;
+        const int x = t >> 2, kb = (t & 3) * 4;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) st[(kb + j) * LS2 + x] = o.sign * v[j];
+        for (int j = 0; j < 4; ++j) st[(kb + j) * LS2 + x] = o.sign * v[j];
     }
 }
 
-// acc += A B, A and B 128 x 128 operands, on the FP64 matrix cores.  Wave w = 2 wr + wc computes
-// rows 64 wr .. 64 wr + 63 x columns 64 wc .. 64 wc + 63 as 4 x 4 tiles of 16 x 16; lane l = 16 kk + i
+// acc += A B, A and B 128 x 128 operands, on the FP64 matrix cores.  Wave w = 4 wr + wc computes
+// rows 64 wr .. 64 wr + 63 x columns 32 wc .. 32 wc + 31 as 4 x 2 tiles of 16 x 16; lane l = 16 kk + i
 // supplies A[row i][k kk] and B[k kk][column i] to each 16x16x4 step, and register r of
-// acc[mt][nt] holds C[64 wr + 16 mt + kk + 4 r][64 wc + 16 nt + i].  K runs in chunks of 16 through
+// acc[mt][nt] holds C[64 wr + 16 mt + kk + 4 r][32 wc + 16 nt + i].  K runs in chunks of 16 through
 // LDS; the next chunk's loads are in flight while the current one is used.
-__device__ __forceinline__ void gemm128(f64x4 (&acc)[4][4], const Opnd& A, const Opnd& B, double* __restrict__ sa,
+__device__ __forceinline__ void gemm128(f64x4 (&acc)[4][2], const Opnd& A, const Opnd& B, double* __restrict__ sa,
                                         double* __restrict__ sb) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int i = lane & 15, kk = lane >> 4;
-    const int wr = w >> 1, wc = w & 1;
-    double va[8], vb[8];
+    const int wr = w >> 2, wc = w & 3;
+    double va[4], vb[4];
     chunk_fetch(va, A, 0);
     chunk_fetch(vb, B, 0);
     for (int c = 0; c < TB2 / KC2; ++c) {
@@ -178,48 +180,48 @@ __device__ __forceinline__ void gemm128(f64x4 (&acc)[4][4], const Opnd& A, const
 #pragma unroll
         for (int ks = 0; ks < KC2 / 4; ++ks) {
             const int k = 4 * ks + kk;
-            double a[4], b[4];
+            double a[4], b[2];
 #pragma unroll
             for (int m = 0; m < 4; ++m) a[m] = sa[k * LS2 + 64 * wr + 16 * m + i];
 #pragma unroll
-            for (int n = 0; n < 4; ++n) b[n] = sb[k * LS2 + 64 * wc + 16 * n + i];
+            for (int n = 0; n < 2; ++n) b[n] = sb[k * LS2 + 32 * wc + 16 * n + i];
 #pragma unroll
             for (int m = 0; m < 4; ++m)
 #pragma unroll
-                for (int n = 0; n < 4; ++n) acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[n], acc[m][n], 0, 0, 0);
+                for (int n = 0; n < 2; ++n) acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[n], acc[m][n], 0, 0, 0);
         }
     }
 }
 
-__device__ __forceinline__ void acc_zero(f64x4 (&acc)[4][4]) {
+__device__ __forceinline__ void acc_zero(f64x4 (&acc)[4][2]) {
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int n = 0; n < 4; ++n) acc[m][n] = f64x4{0.0, 0.0, 0.0, 0.0};
+        for (int n = 0; n < 2; ++n) acc[m][n] = f64x4{0.0, 0.0, 0.0, 0.0};
 }
 
-// g (128 x 128, row stride ld) = scale * acc, or += scale * acc; the old values of each half of a
-// thread's tile are read together before they are written
-__device__ __forceinline__ void acc_store(const f64x4 (&acc)[4][4], double* __restrict__ g, int64_t ld, double scale,
+// g (128 x 128, row stride ld) = scale * acc, or += scale * acc; each half of a thread's old values is
+// read together before it is written
+__device__ __forceinline__ void acc_store(const f64x4 (&acc)[4][2], double* __restrict__ g, int64_t ld, double scale,
                                           bool accumulate) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int i = lane & 15, kk = lane >> 4;
-    const int wr = w >> 1, wc = w & 1;
-    double* g0 = g + int64_t(64 * wr + kk) * ld + 64 * wc + i;
+    const int wr = w >> 2, wc = w & 3;
+    double* g0 = g + int64_t(64 * wr + kk) * ld + 32 * wc + i;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-        double old[2][4][4];
+        double old[2][2][4];
 #pragma unroll
         for (int m = 0; m < 2; ++m)
 #pragma unroll
-            for (int n = 0; n < 4; ++n)
+            for (int n = 0; n < 2; ++n)
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
                     old[m][n][r] = accumulate ? g0[int64_t(16 * (2 * h + m) + 4 * r) * ld + 16 * n] : 0.0;
 #pragma unroll
         for (int m = 0; m < 2; ++m)
 #pragma unroll
-            for (int n = 0; n < 4; ++n)
+            for (int n = 0; n < 2; ++n)
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
                     g0[int64_t(16 * (2 * h + m) + 4 * r) * ld + 16 * n] = accumulate ? fma(scale, acc[2 * h + m][n][r], old[m][n][r])
@@ -227,39 +229,40 @@ __device__ __forceinline__ void acc_store(const f64x4 (&acc)[4][4], double* __re
     }
 }
 
-// dst (128 x 128, row stride ldd) = M, M an operand as above, through the chunk stage (coalesced
-// reads and writes also for a transposed source)
+// dst (128 x 128, row stride ldd) = M, M given as a B operand: each chunk stages rows k0 .. k0 + 15 of
+// M, st[k][x] = M(k0 + k, x) (coalesced reads and writes also for a transposed source)
 __device__ __forceinline__ void copy128(double* __restrict__ dst, int64_t ldd, const Opnd& M, double* __restrict__ st) {
-    // M given as a B operand: each chunk stages rows k0 .. k0 + 15 of M, st[k][x] = M(k0 + k, x)
     const int t = threadIdx.x;
     for (int c = 0; c < TB2 / KC2; ++c) {
-        double v[8];
+        double v[4];
         chunk_fetch(v, M, c * KC2);
         __syncthreads();
         chunk_put(st, v, M);
         __syncthreads();
-        const int r = t >> 4, x0 = (t & 15) * 8;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) dst[int64_t(c * KC2 + r) * ldd + x0 + j] = st[r * LS2 + x0 + j];
+        const int r = t >> 5, x0 = (t & 31) * 4;
+        *reinterpret_cast<double2*>(dst + int64_t(c * KC2 + r) * ldd + x0) = make_double2(st[r * LS2 + x0], st[r * LS2 + x0 + 1]);
+        *reinterpret_cast<double2*>(dst + int64_t(c * KC2 + r) * ldd + x0 + 2) =
+            make_double2(st[r * LS2 + x0 + 2], st[r * LS2 + x0 + 3]);
     }
 }
 
 // One elimination step kk = 8 q + RR of the 128 x 128 scalar Gauss-Jordan below, on this thread's
-// 8 x 8 registers (rows 8 tr .., columns 8 tc ..): the owners of row and column kk publish them
+// 4 x 8 registers (rows 4 tr .., columns 8 tc ..): the owners of row and column kk publish them
 // through LDS, then every element takes its new value without branches.
 template <int RR>
-__device__ __forceinline__ void gj128_step(double (&a)[64], int q, int tr, int tc, double* __restrict__ rowbuf,
+__device__ __forceinline__ void gj128_step(double (&a)[32], int q, int tr, int tc, double* __restrict__ rowbuf,
                                            double* __restrict__ colbuf, bool& ok) {
+    constexpr int RS = RR & 3;   // local row of kk in its owner
     const int kk = 8 * q + RR;
     double* rb = rowbuf + (RR & 1) * TB2;
     double* cb = colbuf + (RR & 1) * TB2;
-    if (tr == q) {
+    if (tr == 2 * q + (RR >> 2)) {
 #pragma unroll
-        for (int c = 0; c < 8; ++c) rb[8 * tc + c] = a[RR * 8 + c];
+        for (int c = 0; c < 8; ++c) rb[8 * tc + c] = a[RS * 8 + c];
     }
     if (tc == q) {
 #pragma unroll
-        for (int r = 0; r < 8; ++r) cb[8 * tr + r] = a[r * 8 + RR];
+        for (int r = 0; r < 4; ++r) cb[4 * tr + r] = a[r * 8 + RR];
     }
     __syncthreads();
     const double piv = rb[kk];
@@ -270,9 +273,9 @@ __device__ __forceinline__ void gj128_step(double (&a)[64], int q, int tr, int t
     for (int c = 0; c < 8; ++c) akj[c] = rb[8 * tc + c];
     const bool colq = tc == q;   // this thread holds column kk (its local column RR)
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        const bool rowk = (8 * tr + r) == kk;
-        const double aik = cb[8 * tr + r] * pinv;
+    for (int r = 0; r < 4; ++r) {
+        const bool rowk = (4 * tr + r) == kk;
+        const double aik = cb[4 * tr + r] * pinv;
         const double m = rowk ? 0.0 : aik;
         const double s = rowk ? pinv : 1.0;
 #pragma unroll
@@ -286,19 +289,19 @@ __device__ __forceinline__ void gj128_step(double (&a)[64], int q, int tr, int t
 }
 
 // In-place inverse of a 128 x 128 SPD matrix by scalar Gauss-Jordan without pivoting: src (row
-// stride lds) -> dst (row stride ldd).  Thread (tr, tc) = (t >> 4, t & 15) keeps rows 8 tr .. 8 tr + 7 x
-// columns 8 tc .. 8 tc + 7 in registers; each step publishes the pivot row and column through LDS
-// (alternating buffers, one barrier per step).  Returns false if a pivot was not positive and
-// finite (then the matrix is not SPD).
+// stride lds) -> dst (row stride ldd).  Thread (tr, tc) = (t >> 4, t & 15) of the 512 keeps rows
+// 4 tr .. 4 tr + 3 x columns 8 tc .. 8 tc + 7 in registers; each step publishes the pivot row and
+// column through LDS (alternating buffers, one barrier per step).  Returns false if a pivot was not
+// positive and finite (then the matrix is not SPD).
 __device__ __forceinline__ bool inverse128(const double* __restrict__ src, int64_t lds, double* __restrict__ dst, int64_t ldd,
                                            double* __restrict__ rowbuf, double* __restrict__ colbuf) {
     const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
-    double a[64];
+    double a[32];
 #pragma unroll
-    for (int r = 0; r < 8; ++r)
+    for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int c = 0; c < 8; c += 2) {
-            const double2 d = *reinterpret_cast<const double2*>(src + int64_t(8 * tr + r) * lds + 8 * tc + c);
+            const double2 d = *reinterpret_cast<const double2*>(src + int64_t(4 * tr + r) * lds + 8 * tc + c);
             a[r * 8 + c] = d.x;
             a[r * 8 + c + 1] = d.y;
         }
@@ -314,10 +317,10 @@ __device__ __forceinline__ bool inverse128(const double* __restrict__ src, int64
         gj128_step<7>(a, q, tr, tc, rowbuf, colbuf, ok);
     }
 #pragma unroll
-    for (int r = 0; r < 8; ++r)
+    for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int c = 0; c < 8; c += 2)
-            *reinterpret_cast<double2*>(dst + int64_t(8 * tr + r) * ldd + 8 * tc + c) = make_double2(a[r * 8 + c], a[r * 8 + c + 1]);
+            *reinterpret_cast<double2*>(dst + int64_t(4 * tr + r) * ldd + 8 * tc + c) = make_double2(a[r * 8 + c], a[r * 8 + c + 1]);
     return ok;
 }
 
@@ -344,7 +347,7 @@ __device__ __forceinline__ double* gj_piv(double* scr, int64_t pivot_off, int b,
 }
 
 // the first pivot inverse of every block (task (b, 0, 0))
-__global__ __launch_bounds__(256) void k_gj_pivot0(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
+__global__ __launch_bounds__(NT2) void k_gj_pivot0(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
                                                    double* __restrict__ A, double* __restrict__ scr, int64_t pivot_off,
                                                    int* __restrict__ flags) {
     __shared__ double rowbuf[2 * TB2], colbuf[2 * TB2];
@@ -355,7 +358,7 @@ __global__ __launch_bounds__(256) void k_gj_pivot0(const int4* __restrict__ task
 }
 
 // step k, task (b, k, j), j != k: the staging for column j
-__global__ __launch_bounds__(256) void k_gj_row(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
+__global__ __launch_bounds__(NT2) void k_gj_row(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
                                                 double* __restrict__ A, double* __restrict__ scr, int64_t pivot_off, int k) {
     __shared__ double sa[KC2 * LS2], sb[KC2 * LS2];
     const int4 t = tasks[blockIdx.x];
@@ -367,7 +370,7 @@ __global__ __launch_bounds__(256) void k_gj_row(const int4* __restrict__ tasks, 
     const Opnd Pa = opnd_a(piv, TB2, false, 1.0), Pb = opnd_b(piv, TB2, false, 1.0);
     const Opnd Skj = j < k ? opnd_b(tile2_at(a0, m, k, j), m.npad, false, 1.0)    // stored
                            : opnd_b(tile2_at(a0, m, j, k), m.npad, true, 1.0);    // S_jk^T, both uneliminated
-    f64x4 acc[4][4];
+    f64x4 acc[4][2];
     acc_zero(acc);
     gemm128(acc, Pa, Skj, sa, sb);                                               // R_j = P S_kj
     acc_store(acc, gj_R(scr, m, j), TB2, 1.0, false);
@@ -382,13 +385,10 @@ __global__ __launch_bounds__(256) void k_gj_row(const int4* __restrict__ tasks, 
 }
 
 // step k, task (b, i, j), i >= j: trailing update S_ij -= C_i R_j (i, j != k), or the copy of the new
-// row tile (i = k > j), column tile (i > k = j) or pivot inverse (i = j = k).  The task for tile
-// (k+1, k+1) also inverts the updated tile: the pivot inverse of step k+1.
-__global__ __launch_bounds__(256) void k_gj_update(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
-                                                   double* __restrict__ A, double* __restrict__ scr, int64_t pivot_off,
-                                                   int k, int* __restrict__ flags) {
+// row tile (i = k > j), column tile (i > k = j) or pivot inverse (i = j = k).
+__global__ __launch_bounds__(NT2, 4) void k_gj_update(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
+                                                      double* __restrict__ A, double* __restrict__ scr, int64_t pivot_off, int k) {
     __shared__ double sa[KC2 * LS2], sb[KC2 * LS2];
-    __shared__ double rowbuf[2 * TB2], colbuf[2 * TB2];
     const int4 t = tasks[blockIdx.x];
     const BlockMeta m = meta[t.x];
     const int i = t.y, j = t.z;
@@ -399,17 +399,23 @@ __global__ __launch_bounds__(256) void k_gj_update(const int4* __restrict__ task
         copy128(gij, m.npad, opnd_b(src, TB2, false, 1.0), sa);
         return;
     }
-    f64x4 acc[4][4];
+    f64x4 acc[4][2];
     acc_zero(acc);
     gemm128(acc, opnd_a(gj_C(scr, m, i), TB2, false, 1.0), opnd_b(gj_R(scr, m, j), TB2, false, 1.0), sa, sb);
     acc_store(acc, gij, m.npad, -1.0, true);
-    if (i == k + 1 && j == k + 1) {
-        // next pivot: the updated tile, as this block wrote it, inverted into slot (k+1) % 2
-        __threadfence_block();
-        __syncthreads();
-        const bool ok = inverse128(gij, m.npad, gj_piv(scr, pivot_off, t.x, k + 1), TB2, rowbuf, colbuf);
-        if (!ok && threadIdx.x == 0) flags[t.x] = 1;
-    }
+}
+
+// after step k, task (b, k+1, k+1): the pivot inverse of step k+1 from the updated tile, into slot
+// (k+1) % 2
+__global__ __launch_bounds__(NT2) void k_gj_pivot(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
+                                                  double* __restrict__ A, double* __restrict__ scr, int64_t pivot_off, int k,
+                                                  int* __restrict__ flags) {
+    __shared__ double rowbuf[2 * TB2], colbuf[2 * TB2];
+    const int4 t = tasks[blockIdx.x];
+    const BlockMeta m = meta[t.x];
+    const bool ok = inverse128(tile2_at(A + m.mat_off, m, k + 1, k + 1), m.npad, gj_piv(scr, pivot_off, t.x, k + 1), TB2, rowbuf,
+                               colbuf);
+    if (!ok && threadIdx.x == 0) flags[t.x] = 1;
 }
 
 // the inverse is symmetric: upper tiles (i < j) from the lower ones
@@ -431,57 +437,60 @@ __global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, in
 }
 
 // --- coarse Galerkin matrix: Y = W R_H^T, then W_H = R_H Y (upper half, mirrored) ------------
-// Z = R_H W: block t takes coarse dof i and a 512-column slice c of W and sums the W rows of the
-// coarse function's fine support, weighted by R_H, with coalesced row reads.  Blocks of one XCD
-// (blockIdx % 8) walk a contiguous run of t, and t runs over the coarse dofs of one slice before
-// the next slice, so coarse functions with overlapping supports (neighbouring coarse vertices)
-// re-read the same W rows from that XCD's L2.  (W is symmetric, so Z^T = W R_H^T.)
-constexpr int kZCols = 512;
-__global__ __launch_bounds__(256) void k_coarse_Z(const double* __restrict__ W, int64_t ldw, int64_t N, int64_t nH,
-                                                  int64_t nblocks, const int64_t* __restrict__ rp,
-                                                  const int32_t* __restrict__ rc, const double* __restrict__ rv,
-                                                  double* __restrict__ Z) {
-    const int64_t per = (nblocks + 7) / 8;
-    const int64_t t = int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
-    if (t >= nblocks) return;
-    const int64_t i = t % nH;
-    const int64_t c0 = (t / nH) * kZCols + threadIdx.x;
-    double acc[2] = {0.0, 0.0};
-    // eight support rows per pass, their loads issued together (the rows of a coarse function's
-    // support are scattered over W, so each pass is one round of memory latency)
-    constexpr int kU = 8;
-    const int64_t e0 = rp[i], e1 = rp[i + 1];
-    int64_t e = e0;
-    for (; e + kU <= e1; e += kU) {
-        double v[kU], x[kU][2];
+// Z = R_H W, by groups of coarse functions.  The coarse dofs are grouped 32 at a time in a
+// spatial (Morton) order of their vertices, so a group's supports overlap.  The rows of the union
+// of a group's supports are sorted into runs of equal member pattern (the up to 4 members whose
+// coefficient is nonzero there: the coarse functions of one coarse triangle, edge or vertex; a
+// row with more members appears in several runs).  A one-wave block takes group g = t % ng and the
+// 64-column slice t / ng of W: per run, each row is loaded once (eight rows in flight, coalesced)
+// and added into 4 slot sums with its coefficients (read through the scalar cache), and at the
+// end of the run the slot sums go into the 32 member sums.  Every sum runs in a fixed order:
+// bit-reproducible.  Reads of W: the union sizes summed over the groups, about 1.3 N rows (a
+// support per coarse dof would read each row about three times).  (W is symmetric, so
+// Z^T = W R_H^T.)
+constexpr int kZGroup = 32;
+constexpr int kZCols = 64;
+constexpr int kZSlots = 4;
+__global__ __launch_bounds__(64) void k_coarse_Z(const double* __restrict__ W, int64_t ldw, int64_t N, int64_t ng,
+                                                 const int32_t* __restrict__ gmem, const int32_t* __restrict__ gmem_ptr,
+                                                 const int32_t* __restrict__ grun_ptr, const int32_t* __restrict__ run_row,
+                                                 const int4* __restrict__ run_mem, const int32_t* __restrict__ rows,
+                                                 const double* __restrict__ coef, double* __restrict__ Z) {
+    const int64_t g = blockIdx.x % ng;
+    const int64_t c = (blockIdx.x / ng) * kZCols + threadIdx.x;
+    const bool valid = c < N;
+    double acc[kZGroup];
 #pragma unroll
-        for (int q = 0; q < kU; ++q) {
-            v[q] = rv[e + q];
-            const double* w = W + int64_t(rc[e + q]) * ldw;
+    for (int q = 0; q < kZGroup; ++q) acc[q] = 0.0;
+    for (int run = grun_ptr[g]; run < grun_ptr[g + 1]; ++run) {
+        const int r0 = run_row[run], r1 = run_row[run + 1];
+        double sl[kZSlots] = {0.0, 0.0, 0.0, 0.0};
+        constexpr int kU = 8;
+        for (int r = r0; r < r1; r += kU) {
+            double x[kU];
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int64_t c = c0 + 256 * u;
-                x[q][u] = c < N ? w[c] : 0.0;
+            for (int u = 0; u < kU; ++u) x[u] = (valid && r + u < r1) ? W[int64_t(rows[r + u]) * ldw + c] : 0.0;
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                if (r + u < r1) {
+                    const double* cf = coef + int64_t(r + u) * kZSlots;
+#pragma unroll
+                    for (int k = 0; k < kZSlots; ++k) sl[k] = fma(cf[k], x[u], sl[k]);
+                }
             }
         }
+        const int4 mm = run_mem[run];   // local member of each slot, -1 unused
+        const int ms[kZSlots] = {mm.x, mm.y, mm.z, mm.w};
 #pragma unroll
-        for (int q = 0; q < kU; ++q)
+        for (int k = 0; k < kZSlots; ++k)
 #pragma unroll
-            for (int u = 0; u < 2; ++u) acc[u] = fma(v[q], x[q][u], acc[u]);
+            for (int q = 0; q < kZGroup; ++q) acc[q] = (ms[k] == q) ? acc[q] + sl[k] : acc[q];
     }
-    for (; e < e1; ++e) {
-        const double v = rv[e];
-        const double* w = W + int64_t(rc[e]) * ldw;
+    if (valid) {
+        const int m0 = gmem_ptr[g], nm = gmem_ptr[g + 1] - m0;
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int64_t c = c0 + 256 * u;
-            if (c < N) acc[u] = fma(v, w[c], acc[u]);
-        }
-    }
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-        const int64_t c = c0 + 256 * u;
-        if (c < N) Z[i * N + c] = acc[u];
+        for (int q = 0; q < kZGroup; ++q)
+            if (q < nm) Z[int64_t(gmem[m0 + q]) * N + c] = acc[q];
     }
 }
 
@@ -866,6 +875,98 @@ void build_prolongation_2d(const MeshTopo& f, const MeshTopo& c, const int32_t* 
 
 }  // namespace
 
+// Groups of kZGroup coarse dofs for the coarse product: coarse dofs in the Morton order of their
+// vertices (10 bits per axis over the coarse mesh's bounding box), cut into consecutive groups.
+// Per group, the rows of the union of its functions' fine supports in runs of equal member
+// pattern (sorted patterns, rows ascending within a run); a row with more than kZSlots members
+// is split over several runs.  Per run its members (local, -1 for an unused slot) and row range;
+// per row its fine dof and kZSlots coefficients.
+struct CoarseGroups {
+    std::vector<int32_t> mem, mem_ptr, run_ptr, run_row, row;
+    std::vector<int4> run_mem;
+    std::vector<double> coef;
+};
+
+void coarse_groups(const MeshTopo& c, const CoarseCSR& R, CoarseGroups& G) {
+    const int64_t nH = R.nH;
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t v = 0; v < c.nv; ++v)
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = std::min(lo[k], c.V[3 * v + k]);
+            hi[k] = std::max(hi[k], c.V[3 * v + k]);
+        }
+    auto spread = [](uint64_t x) {   // 10 bits -> every third bit
+        x &= 0x3ff;
+        x = (x | (x << 16)) & 0x30000ff;
+        x = (x | (x << 8)) & 0x300f00f;
+        x = (x | (x << 4)) & 0x30c30c3;
+        x = (x | (x << 2)) & 0x9249249;
+        return x;
+    };
+    std::vector<std::pair<uint64_t, int32_t>> key(static_cast<size_t>(nH));
+    for (int64_t i = 0; i < nH; ++i) {
+        const int64_t v = c.dof_vertex[i];
+        uint64_t code = 0;
+        for (int k = 0; k < 3; ++k) {
+            const double span = hi[k] > lo[k] ? hi[k] - lo[k] : 1.0;
+            const uint64_t qk = uint64_t(std::min(1023.0, std::max(0.0, (c.V[3 * v + k] - lo[k]) / span * 1023.0)));
+            code |= spread(qk) << k;
+        }
+        key[size_t(i)] = {code, int32_t(i)};
+    }
+    std::sort(key.begin(), key.end());
+    const int64_t ng = (nH + kZGroup - 1) / kZGroup;
+    G = CoarseGroups{};
+    G.mem_ptr.assign(size_t(ng) + 1, 0);
+    G.run_ptr.assign(size_t(ng) + 1, 0);
+    G.run_row.push_back(0);
+    std::vector<std::tuple<int32_t, int32_t, double>> tri;   // (fine dof, member, coefficient)
+    // one entry per (row, piece): the piece's members and coefficients (kZSlots each)
+    struct Piece { std::array<int32_t, kZSlots> m; int32_t row; std::array<double, kZSlots> v; };
+    std::vector<Piece> pieces;
+    for (int64_t g = 0; g < ng; ++g) {
+        tri.clear();
+        pieces.clear();
+        const int64_t m0 = g * kZGroup, m1 = std::min<int64_t>(nH, m0 + kZGroup);
+        for (int64_t m = m0; m < m1; ++m) {
+            const int32_t i = key[size_t(m)].second;
+            G.mem.push_back(i);
+            for (int64_t e = R.ptr[size_t(i)]; e < R.ptr[size_t(i) + 1]; ++e)
+                tri.emplace_back(R.col[size_t(e)], int32_t(m - m0), R.val[size_t(e)]);
+        }
+        std::sort(tri.begin(), tri.end());
+        for (size_t e = 0; e < tri.size();) {
+            size_t f = e;
+            while (f < tri.size() && std::get<0>(tri[f]) == std::get<0>(tri[e])) ++f;
+            for (size_t p0 = e; p0 < f; p0 += kZSlots) {   // members of this row, kZSlots per piece
+                Piece pc;
+                pc.row = std::get<0>(tri[e]);
+                for (int k = 0; k < kZSlots; ++k) {
+                    const bool on = p0 + k < f;
+                    pc.m[size_t(k)] = on ? std::get<1>(tri[p0 + k]) : -1;
+                    pc.v[size_t(k)] = on ? std::get<2>(tri[p0 + k]) : 0.0;
+                }
+                pieces.push_back(pc);
+            }
+            e = f;
+        }
+        std::sort(pieces.begin(), pieces.end(),
+                  [](const Piece& x, const Piece& y) { return x.m != y.m ? x.m < y.m : x.row < y.row; });
+        for (size_t e = 0; e < pieces.size(); ++e) {
+            if (e > 0 && pieces[e].m != pieces[e - 1].m) G.run_row.push_back(int32_t(G.row.size()));
+            if (e == 0 || pieces[e].m != pieces[e - 1].m) {
+                const auto& mm = pieces[e].m;
+                G.run_mem.push_back(make_int4(mm[0], mm[1], mm[2], mm[3]));
+            }
+            G.row.push_back(pieces[e].row);
+            for (int k = 0; k < kZSlots; ++k) G.coef.push_back(pieces[e].v[size_t(k)]);
+        }
+        if (!pieces.empty()) G.run_row.push_back(int32_t(G.row.size()));
+        G.mem_ptr[size_t(g) + 1] = int32_t(G.mem.size());
+        G.run_ptr[size_t(g) + 1] = int32_t(G.run_mem.size());
+    }
+}
+
 void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV, int64_t ncv, const int32_t* cT,
                           int64_t nct, const int32_t* parent) {
     auto t0 = std::chrono::steady_clock::now();
@@ -964,7 +1065,7 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
     // ---- every tile task of the set-up, planned on the host and uploaded once.  Two plans: the
     //      faces and the wire basket (problem stream), and the coarse block (second stream, after
     //      its Galerkin matrix) -----------------------------------------------------------------------
-    enum Kind { GATHER, GJ_PIVOT0, GJ_ROW, GJ_UPDATE, MIRROR };
+    enum Kind { GATHER, GJ_PIVOT0, GJ_ROW, GJ_UPDATE, GJ_PIVOT, MIRROR };
     struct Launch { Kind kind; int param; int64_t off, n; };
     std::vector<int4> all;
     std::vector<Launch> plan_fw, plan_c;
@@ -988,9 +1089,13 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
         }
         add(plan, GJ_PIVOT0, 0, tp);
         for (int k = 0; k < maxT; ++k) {   // block Gauss-Jordan, all blocks with a step k together
-            std::vector<int4> tr, tu;
-            for (int64_t b = b0; b < b1; ++b)   // the next pivot's task first: it carries the inversion
-                if (k + 1 < ntile[b]) tu.push_back(make_int4(int(b), k + 1, k + 1, 0));
+            std::vector<int4> tr, tu, tv;
+            for (int64_t b = b0; b < b1; ++b) {   // the next pivot's tile first, then its inversion
+                if (k + 1 < ntile[b]) {
+                    tu.push_back(make_int4(int(b), k + 1, k + 1, 0));
+                    tv.push_back(make_int4(int(b), k + 1, k + 1, 0));
+                }
+            }
             for (int64_t b = b0; b < b1; ++b) {
                 if (k >= ntile[b]) continue;
                 for (int j = 0; j < ntile[b]; ++j)
@@ -1001,6 +1106,7 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
             }
             add(plan, GJ_ROW, k, tr);
             add(plan, GJ_UPDATE, k, tu);
+            add(plan, GJ_PIVOT, k, tv);
         }
         std::vector<int4> tm;
         for (int64_t b = b0; b < b1; ++b)
@@ -1025,9 +1131,10 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
         const dim3 g(unsigned(L.n)), bl(256);
         switch (L.kind) {
             case GATHER: hipLaunchKernelGGL(k_gather, g, bl, 0, st, d, dm, M->idx.as<int32_t>(), p->W64.as<double>(), p->ldw, M->diag_shift, A.as<double>()); break;
-            case GJ_PIVOT0: hipLaunchKernelGGL(k_gj_pivot0, g, bl, 0, st, d, dm, A.as<double>(), scr.as<double>(), pivot_off, dflags.as<int>()); break;
-            case GJ_ROW: hipLaunchKernelGGL(k_gj_row, g, bl, 0, st, d, dm, A.as<double>(), scr.as<double>(), pivot_off, L.param); break;
-            case GJ_UPDATE: hipLaunchKernelGGL(k_gj_update, g, bl, 0, st, d, dm, A.as<double>(), scr.as<double>(), pivot_off, L.param, dflags.as<int>()); break;
+            case GJ_PIVOT0: hipLaunchKernelGGL(k_gj_pivot0, g, dim3(NT2), 0, st, d, dm, A.as<double>(), scr.as<double>(), pivot_off, dflags.as<int>()); break;
+            case GJ_ROW: hipLaunchKernelGGL(k_gj_row, g, dim3(NT2), 0, st, d, dm, A.as<double>(), scr.as<double>(), pivot_off, L.param); break;
+            case GJ_UPDATE: hipLaunchKernelGGL(k_gj_update, g, dim3(NT2), 0, st, d, dm, A.as<double>(), scr.as<double>(), pivot_off, L.param); break;
+            case GJ_PIVOT: hipLaunchKernelGGL(k_gj_pivot, g, dim3(NT2), 0, st, d, dm, A.as<double>(), scr.as<double>(), pivot_off, L.param, dflags.as<int>()); break;
             case MIRROR: hipLaunchKernelGGL(k_mirror, g, bl, 0, st, d, dm, A.as<double>()); break;
         }
         HIP_CHECK(hipGetLastError());
@@ -1050,7 +1157,8 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
     for (const Launch& L : plan_fw) run(L, s);
 
     // coarse Galerkin block on the second stream, while the first one eliminates
-    DeviceBuffer Z;
+    DeviceBuffer Z, d_gmem, d_gmem_ptr, d_grow_ptr, d_grow, d_gcoef, d_grun_row, d_grun_mem;
+    CoarseGroups grp;   // host sides of the group uploads: they must outlive the copies
     std::vector<int64_t> tp;   // host sides of the coarse uploads: they must outlive the copies
     std::vector<int32_t> trow;
     std::vector<double> tval;
@@ -1082,9 +1190,19 @@ void precond_setup_device(bem_precond* M, const int32_t* patch, const double* cV
         M->rht_row = upload(trow, s2);
         M->rht_val = upload(tval, s2);
         Z = DeviceBuffer(sizeof(double) * std::max<int64_t>(1, f.N * M->nH), s2);
-        const int64_t zblocks = int64_t(nblk(f.N, kZCols)) * M->nH;
-        hipLaunchKernelGGL(k_coarse_Z, dim3(unsigned((zblocks + 7) / 8 * 8)), dim3(256), 0, s2, p->W64.as<double>(), p->ldw, f.N,
-                           M->nH, zblocks, M->rh_ptr.as<int64_t>(), M->rh_col.as<int32_t>(), M->rh_val.as<double>(), Z.as<double>());
+        coarse_groups(c, R, grp);
+        const int64_t ng = int64_t(grp.mem_ptr.size()) - 1;
+        d_gmem = upload(grp.mem, s2);
+        d_gmem_ptr = upload(grp.mem_ptr, s2);
+        d_grow_ptr = upload(grp.run_ptr, s2);
+        d_grow = upload(grp.row, s2);
+        d_gcoef = upload(grp.coef, s2);
+        d_grun_row = upload(grp.run_row, s2);
+        d_grun_mem = upload(grp.run_mem, s2);
+        const int64_t zblocks = int64_t(nblk(f.N, kZCols)) * ng;
+        hipLaunchKernelGGL(k_coarse_Z, dim3(unsigned(zblocks)), dim3(64), 0, s2, p->W64.as<double>(), p->ldw, f.N, ng,
+                           d_gmem.as<int32_t>(), d_gmem_ptr.as<int32_t>(), d_grow_ptr.as<int32_t>(), d_grun_row.as<int32_t>(),
+                           d_grun_mem.as<int4>(), d_grow.as<int32_t>(), d_gcoef.as<double>(), Z.as<double>());
         HIP_CHECK(hipGetLastError());
         const BlockMeta& cm = meta[nall - 1];
         double* Ac = A.as<double>() + cm.mat_off;

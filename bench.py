@@ -58,21 +58,19 @@ def far_kernel_source_hash():
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
-def symv_bytes(N, size):
+def symv_bytes(N, size, ks):
     """HBM bytes of one symmetric product (any number of columns up to 16): the upper block triangle of W
-    (64 x 64 blocks) plus the block-row partials written and read back (super-blocks of 8 blocks
-    for FP32 and 4 for FP64 matrices; one partial of 64 rows x 16 columns per block row and
-    super-tile, plus one)."""
+    (64 x 64 blocks) plus the block-row partials written and read back (super-blocks of ks blocks, the
+    problem's tuned value; one partial of 64 rows x 16 columns per block row and super-tile, plus one)."""
     nb = (N + 63) // 64
-    ks = 8 if size == 4 else 4
     nst = (nb + ks - 1) // ks
     return nb * (nb + 1) // 2 * 64 * 64 * size + 2 * nb * (nst + 1) * 1024 * size
 
 
-def matvec_rates(N, size, t, key):
+def matvec_rates(N, size, t, key, ks):
     """A product's time, its algorithmic HBM bytes (upper block triangle + partials), the rate and
     its fraction of the 8 TB/s peak."""
-    b = symv_bytes(N, size)
+    b = symv_bytes(N, size, ks)
     return {key + "_ms": t * 1e3, key + "_bytes": b, key + "_hbm_GBs": b / t / 1e9,
             key + "_hbm_frac": b / t / 1e9 / PEAK_HBM_GBS}
 
@@ -338,6 +336,7 @@ def timed_workload(lib, meshes, ctx, name, k, steps, warmup, tol, mixed, extras=
     pinfo = ref["info"]
     N = pinfo["n_dofs"]
     pref, Mref = ref["problem"], ref["M"]
+    tun = pref.tuning
     fp64_solve = None
     if extras and mixed:
         t0 = time.perf_counter()
@@ -411,8 +410,10 @@ def timed_workload(lib, meshes, ctx, name, k, steps, warmup, tol, mixed, extras=
             "isa_tflops": round(far_pairs * EVALS_PER_FAR_PAIR * ISA_FLOPS_PER_EVAL / t_far / 1e12, 3),
         },
         "fp64_solve": fp64_solve,
+        "tuning": tun,
     }
-    mv = {**matvec_rates(N, 8, t64_1, "fp64_k1"), **matvec_rates(N, 8, t64_16, "fp64_k16")}
+    ks64, ks32 = tun["symv_blocks_fp64"], tun["symv_blocks_fp32"]
+    mv = {**matvec_rates(N, 8, t64_1, "fp64_k1", ks64), **matvec_rates(N, 8, t64_16, "fp64_k16", ks64)}
     phi_last = phis[-1]
     if extras:
         # the same step with host buffers (mesh uploaded, solutions downloaded): the PCIe-inclusive
@@ -427,8 +428,8 @@ def timed_workload(lib, meshes, ctx, name, k, steps, warmup, tol, mixed, extras=
         if mixed:
             t32_1 = p.bench_matvec(fp32=True, k=1, reps=5)
             t32_16 = p.bench_matvec(fp32=True, k=16, reps=3)
-            mv.update(matvec_rates(N, 4, t32_1, "fp32_k1"))
-            mv.update(matvec_rates(N, 4, t32_16, "fp32_k16"))
+            mv.update(matvec_rates(N, 4, t32_1, "fp32_k1", ks32))
+            mv.update(matvec_rates(N, 4, t32_16, "fp32_k16", ks32))
         t0 = time.perf_counter()
         Md = lib.Preconditioner(p, w.patch_of_triangle, w.coarse.vertices, w.coarse.triangles, w.coarse_of_triangle,
                                 factor_fp32=mixed, wirebasket="diagonal")
@@ -795,6 +796,8 @@ def main():
                                 args.tol),
                    "n_dofs": head["n_dofs"], "n_tri": head["n_tri"], "k": args.k, "precision": args.precision,
                    "patches": head["patches"], "pair_panels": head["pair_panels"],
+                   "tuning": {"table": "paper_2310_09204_amd/tuning/gfx950.json" if ctx.tuning else "defaults",
+                              "applied": head["tuning"]},
                    "io": "mesh and solutions resident in device memory (bem_assemble_dev, bem_pcg_solve_dev); "
                          "the host-buffer rate is pcie_inclusive"},
         "roofline": head["roofline"],

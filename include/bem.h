@@ -125,6 +125,32 @@ typedef struct {
 /* Binds the calling library instance to HIP device `hip_device`.  hbm_budget_bytes limits the
  * device memory the serving loop may hold (0 = 90% of free memory). */
 int bem_ctx_create(int hip_device, size_t hbm_budget_bytes, bem_ctx** out);
+/* Launch parameters of the kernels, chosen per size class by the autotuner of this project
+ * (paper_2310_09204_amd/tune.py, measured on the device) and handed over with bem_ctx_set_tuning.
+ * None of them changes a result beyond rounding: the separation factor s decides which column
+ * groups the far-field kernel evaluates in its centred form, whose rounding of |x - y|^2 grows like
+ * ((s + 1) / (s - 1))^2 ulp, so s >= 1.1 keeps it below 1e-13 relative.  A zero field takes the
+ * default. */
+typedef struct {
+    int64_t max_triangles;     /* the entry covers meshes of up to this many triangles (the last
+                                  entry covers every larger mesh as well) */
+    double far_separation;     /* centred far-field form when column groups are this many times the sum
+                                  of the two Gauss-point radii apart, in [1.1, 3]; default 1.2 */
+    double panel_fraction;     /* share of the free device memory for the pair-matrix panels of
+                                  panel-by-panel assembly, in [0.2, 0.8]; default 0.6 */
+    int32_t symv_blocks_fp64;  /* super-block edge (64-row blocks) of the symmetric product with the
+                                  FP64 matrix: 2, 4 or 8; default 4 */
+    int32_t symv_blocks_fp32;  /* the same for the FP32 copy: 4, 8 or 16; default 8 */
+    int32_t check_every;       /* PCG iterations between host checks when bem_solve_opts leaves
+                                  check_every at 0; default 4 */
+    int32_t reserved;
+} bem_tuning;
+/* Copies n entries (sorted by max_triangles, n <= 16; n = 0 restores the defaults).  Problems
+ * assembled afterwards take the first entry whose max_triangles holds their mesh.  Errors:
+ * BEM_E_INVALID_ARG for a value outside the ranges above. */
+int bem_ctx_set_tuning(bem_ctx* ctx, const bem_tuning* entries, int32_t n);
+/* The entry (defaults filled in) that a problem was assembled with. */
+int bem_problem_tuning(const bem_problem* p, bem_tuning* out);
 void bem_ctx_destroy(bem_ctx* ctx);
 /* Waits for all device work of the context's device (hipDeviceSynchronize). */
 int bem_ctx_synchronize(bem_ctx* ctx);

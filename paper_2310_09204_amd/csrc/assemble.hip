@@ -102,12 +102,12 @@ __global__ void k_jump_vectors(const double* __restrict__ V, const int32_t* __re
 // grows like ((|x - c| + |y - c|) / |x - y|)^2.  c is the centre of the column triangle's group of
 // 16 (consecutive triangles); a group of columns takes this form only if its centre is at least
 // kSep (rho_R + rho_C) from the centre of the row tile (rho the radii of the Gauss points about
-// the centres), which bounds that ratio by (kSep + 1) / (kSep - 1) = 11: at worst about 121 ulp of
-// |x - y|^2, 1.3e-14 relative.  Closer groups take the differences.  Pairs that share a vertex are
+// the centres), which bounds that ratio by (kSep + 1) / (kSep - 1): 11 for the default kSep = 1.2,
+// at worst about 121 ulp of |x - y|^2, 1.3e-14 relative (kSep is a launch parameter, at least
+// 1.1: ratio 21, 1e-13).  Closer groups take the differences.  Pairs that share a vertex are
 // overwritten by the near rules in either case.
 // ---------------------------------------------------------------------------------------------
 constexpr int kGrp = 16;
-constexpr double kSep = 1.2;
 constexpr int kRec = 35;   // 7 points x (v/w^2, 1/w^2, |v|^2/w^2)
 
 // per group of 16 consecutive triangles: centre of the bounding box of their Gauss points, and the
@@ -172,7 +172,8 @@ constexpr int kChunk = kGrp;
 
 __global__ __launch_bounds__(256) void k_far(const double* __restrict__ geo, const double* __restrict__ gb,
                                              const double* __restrict__ rec, int32_t nt, int64_t ld,
-                                             const int2* __restrict__ tiles, int64_t ntiles, double* __restrict__ I) {
+                                             const int2* __restrict__ tiles, int64_t ntiles, double kSep,
+                                             double* __restrict__ I) {
     __shared__ double stage[4][kTile][kChunk + 1];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -326,7 +327,8 @@ __device__ __forceinline__ double wave_max(double v) {
 __global__ __launch_bounds__(256) void k_far_rect(const double* __restrict__ geo, const double* __restrict__ gb,
                                                   const double* __restrict__ rec, int32_t nt,
                                                   const int32_t* __restrict__ rows, int64_t nrows, int64_t col0, int64_t ld,
-                                                  const int2* __restrict__ tiles, int64_t ntiles, double* __restrict__ I) {
+                                                  const int2* __restrict__ tiles, int64_t ntiles, double kSep,
+                                                  double* __restrict__ I) {
     __shared__ double stage[4][kTile][kChunk + 1];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -1027,7 +1029,7 @@ PanelTimes assemble_panels(bem_problem* p, const MeshTopo& m, const NearList& ne
     }
     int64_t maxrows = p->panel_rows;
     if (maxrows <= 0) {
-        maxrows = int64_t(0.6 * double(available_device_bytes(p->ctx->device)) / (8.0 * double(nt)));
+        maxrows = int64_t(p->tune.panel_fraction * double(available_device_bytes(p->ctx->device)) / (8.0 * double(nt)));
         // in steps of 2048 rows, so that a repeat of the same mesh plans the same panels and gets
         // the panel buffer of its predecessor back from the pool
         maxrows = maxrows / 2048 * 2048;
@@ -1137,7 +1139,7 @@ PanelTimes assemble_panels(bem_problem* p, const MeshTopo& m, const NearList& ne
         P->ef = std::make_unique<EventTimer>(s);
         const int64_t nft = int64_t(P->ftiles.size());
         hipLaunchKernelGGL(k_far_rect, dim3(blocks_for(nft, 4)), dim3(256), 0, s, geo, gbounds, crec, int32_t(nt),
-                           d_rows.as<int32_t>(), nrows, tmin, ldP, d_ft.as<int2>(), nft, Ip.as<double>());
+                           d_rows.as<int32_t>(), nrows, tmin, ldP, d_ft.as<int2>(), nft, p->tune.far_separation, Ip.as<double>());
         HIP_CHECK(hipGetLastError());
         P->ef->stop();
         DeviceBuffer dv[4], da[4], dbb[4], dt[4];
@@ -1287,7 +1289,7 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
         HIP_CHECK(hipEventRecord(t_far.a, s));
         const int64_t nti = int64_t(tiles.size());
         hipLaunchKernelGGL(k_far, dim3(blocks_for(nti, 4)), dim3(256), 0, s, geo.as<double>(), gbounds.as<double>(),
-                           crec.as<double>(), int32_t(nt), ldI, dtiles.as<int2>(), nti, p->I.as<double>());
+                           crec.as<double>(), int32_t(nt), ldI, dtiles.as<int2>(), nti, p->tune.far_separation, p->I.as<double>());
         HIP_CHECK(hipGetLastError());
     }
     t_far.stop();

@@ -225,6 +225,23 @@ DeviceBuffer& DeviceBuffer::operator=(DeviceBuffer&& o) noexcept {
 void solve_device(bem_problem* p, const bem_precond* M, const double* b, double* x, int k, const bem_solve_opts& o,
                   bem_solve_info* info);
 
+bem_tuning tuning_for(const std::vector<bem_tuning>& table, int64_t nt) {
+    bem_tuning t{};
+    for (size_t i = 0; i < table.size(); ++i)
+        if (nt <= table[i].max_triangles || i + 1 == table.size()) {
+            t = table[i];
+            break;
+        }
+    t.max_triangles = table.empty() ? INT64_MAX : t.max_triangles;
+    if (t.far_separation <= 0) t.far_separation = 1.2;
+    if (t.panel_fraction <= 0) t.panel_fraction = 0.6;
+    if (t.symv_blocks_fp64 <= 0) t.symv_blocks_fp64 = 4;
+    if (t.symv_blocks_fp32 <= 0) t.symv_blocks_fp32 = 8;
+    if (t.check_every <= 0) t.check_every = 4;
+    t.reserved = 0;
+    return t;
+}
+
 }  // namespace bem
 
 using namespace bem;
@@ -258,7 +275,7 @@ bem_solve_opts default_solve_opts() {
     o.use_precond = 1;
     o.precision = BEM_FP64;
     o.refresh_factor = 1e-3;
-    o.check_every = 4;
+    o.check_every = 0;   // the problem's tuned value
     o.use_graph = 1;
     return o;
 }
@@ -268,7 +285,7 @@ int solve_common(bem_problem* p, const bem_precond* m, const double* d_b, int32_
     bem_solve_opts o = opts ? *opts : default_solve_opts();
     if (o.tol <= 0) o.tol = 1e-10;
     if (o.max_iter <= 0) o.max_iter = 2000;
-    if (o.check_every <= 0) o.check_every = 4;
+    if (o.check_every <= 0) o.check_every = p->tune.check_every;
     if (m && m->p != p) fail(BEM_E_INVALID_ARG, "preconditioner belongs to another problem");
     const int64_t N = p->N;
     if (o.x0)
@@ -319,6 +336,35 @@ int bem_ctx_create(int hip_device, size_t hbm_budget_bytes, bem_ctx** out) {
     // this device's address of the scratch array of bem_matvec_noalloc, looked up once here
     noalloc_scratch_address(hip_device);
     *out = c;
+    return BEM_OK;
+    BEM_CATCH
+}
+
+int bem_ctx_set_tuning(bem_ctx* ctx, const bem_tuning* entries, int32_t n) {
+    BEM_TRY
+    if (!ctx || n < 0 || n > 16 || (n > 0 && !entries)) fail(BEM_E_INVALID_ARG, "bad argument");
+    std::vector<bem_tuning> t(entries, entries + n);
+    for (int32_t i = 0; i < n; ++i) {
+        const bem_tuning& e = t[size_t(i)];
+        auto bad = [&](const char* what) { fail(BEM_E_INVALID_ARG, std::string("tuning entry ") + std::to_string(i) + ": " + what); };
+        if (e.max_triangles <= 0 || (i > 0 && e.max_triangles <= t[size_t(i) - 1].max_triangles)) bad("max_triangles not increasing");
+        if (e.far_separation != 0 && !(e.far_separation >= 1.1 && e.far_separation <= 3.0)) bad("far_separation outside [1.1, 3]");
+        if (e.panel_fraction != 0 && !(e.panel_fraction >= 0.2 && e.panel_fraction <= 0.8)) bad("panel_fraction outside [0.2, 0.8]");
+        if (e.symv_blocks_fp64 != 0 && e.symv_blocks_fp64 != 2 && e.symv_blocks_fp64 != 4 && e.symv_blocks_fp64 != 8)
+            bad("symv_blocks_fp64 not 2, 4 or 8");
+        if (e.symv_blocks_fp32 != 0 && e.symv_blocks_fp32 != 4 && e.symv_blocks_fp32 != 8 && e.symv_blocks_fp32 != 16)
+            bad("symv_blocks_fp32 not 4, 8 or 16");
+        if (e.check_every < 0 || e.check_every > 64) bad("check_every outside [0, 64]");
+    }
+    ctx->tuning = std::move(t);
+    return BEM_OK;
+    BEM_CATCH
+}
+
+int bem_problem_tuning(const bem_problem* p, bem_tuning* out) {
+    BEM_TRY
+    if (!p || !out) fail(BEM_E_INVALID_ARG, "bad argument");
+    *out = p->tune;
     return BEM_OK;
     BEM_CATCH
 }
@@ -413,6 +459,7 @@ int bem_assemble_dev(bem_ctx* ctx, const double* vertices, const double* d_verti
     auto t0 = std::chrono::steady_clock::now();
     std::unique_ptr<bem_problem> p(new bem_problem());
     p->ctx = ctx;
+    p->tune = tuning_for(ctx->tuning, nt);
     p->near_order = (opts && opts->near_order > 0) ? opts->near_order : 10;
     if (p->near_order > 64) fail(BEM_E_INVALID_ARG, "near_order above 64");
     p->has_w32 = opts && opts->precision == BEM_FP32_REFINE;
@@ -472,6 +519,7 @@ int bem_assemble_2d(bem_ctx* ctx, const double* vertices, int64_t nv, const int3
     auto t0 = std::chrono::steady_clock::now();
     std::unique_ptr<bem_problem> p(new bem_problem());
     p->ctx = ctx;
+    p->tune = tuning_for(ctx->tuning, ns);
     p->has_w32 = opts && opts->precision == BEM_FP32_REFINE;
     if (opts && opts->keep_pair_matrix) fail(BEM_E_INVALID_ARG, "keep_pair_matrix is for triangle meshes");
     p->stream = acquire_stream(ctx);

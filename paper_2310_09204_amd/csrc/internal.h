@@ -17,6 +17,9 @@
 
 namespace bem {
 
+// the tuning entry for a mesh of nt triangles, defaults filled in
+bem_tuning tuning_for(const std::vector<bem_tuning>& table, int64_t nt);
+
 struct Failure {
     int code;
     std::string msg;
@@ -184,6 +187,7 @@ struct bem_ctx {
     int device = 0;
     size_t budget = 0;
     hipStream_t stream = nullptr;
+    std::vector<bem_tuning> tuning;   // autotuned launch parameters by size class (empty: defaults)
     // streams of destroyed problems, handed to new ones (creating a stream costs about 0.3 ms and
     // destroying one synchronises the device)
     std::mutex stream_mu;
@@ -192,6 +196,7 @@ struct bem_ctx {
 
 struct bem_problem {
     bem_ctx* ctx = nullptr;
+    bem_tuning tune{};                  // launch parameters of this problem (defaults filled in)
     bem::MeshTopo topo;
     int64_t N = 0, ldw = 0, ldI = 0, n_near = 0;
     int64_t panel_rows = 0, n_panels = 0;   // requested rows per pair-matrix panel; panels used
@@ -209,6 +214,7 @@ struct bem_problem {
     // (ldw / 64 x (mv_nst + 1) x 1024 values).  Calls on one problem must not overlap.
     bem::DeviceBuffer mv_xt, mv_partial, mv_tiles[2], mv_sym;
     int64_t mv_nst[2] = {0, 0}, mv_ntiles[2] = {0, 0};
+    int mv_ks[2] = {8, 4};   // super-block edge of the symmetric product ([0] FP32, [1] FP64 matrix)
     // double-layer potential: per-triangle records (normal, Gauss points, n . y) and the 7-point rule,
     // built on the first evaluation
     bem::DeviceBuffer dl_rec, dl_rule;

@@ -180,7 +180,7 @@ __global__ __launch_bounds__(256) void k_matvec_mfma(const MT* __restrict__ W, i
 
 // Symmetric product Y = W X for up to 16 columns that reads only the upper half of W (the Galerkin
 // matrix of a symmetric bilinear form is symmetric).  The 64-row blocks are grouped into super-blocks
-// of KS = SymTile<MT>::K; a workgroup takes one super-tile (I, J), I <= J, and walks it column by
+// of KS (a launch parameter); a workgroup takes one super-tile (I, J), I <= J, and walks it column by
 // column (on a diagonal super-tile only the blocks on and above the diagonal).  Each 64 x 64 block
 // is read from HBM once and used twice:
 //  * rows of bi, W_bi,bj X_bj: through LDS as in the plain product (wave w: rows 16w .. 16w+15);
@@ -194,16 +194,15 @@ __global__ __launch_bounds__(256) void k_matvec_mfma(const MT* __restrict__ W, i
 // each over at most KS * 64 products; each leaves once as a partial of its block row, in MT (exact
 // for FP32 accumulators).  k_symv_reduce adds the nst + 1 partials of each block row in FP64 in a
 // fixed order.  HBM traffic: half of W plus 1/KS of it in partials, written and read back.
-template <typename MT> struct SymTile { static constexpr int K = sizeof(MT) == 4 ? 8 : 4; };
-
-template <typename MT>
+// KS is a launch parameter chosen by the autotuner: 2, 4 or 8 blocks for the FP64 matrix (default
+// 4), 4, 8 or 16 for the FP32 copy (default 8).
+template <typename MT, int KS>
 __global__ __launch_bounds__(256) void k_symv_mfma(const MT* __restrict__ W, int64_t ldw, int64_t N, const MT* __restrict__ xt,
                                                    int64_t nb, int64_t nst, const int2* __restrict__ tiles,
                                                    MT* __restrict__ part) {
     using MC = MatrixCore<MT>;
     using V = typename MC::V;
     using V16 = typename std::conditional<sizeof(MT) == 4, float4, double2>::type;
-    constexpr int KS = SymTile<MT>::K;
     constexpr int VEC = 16 / sizeof(MT);
     constexpr int HV = 64 / (16 * VEC);   // 16-lane segments per 64-column block row
     constexpr int NL = 4 * HV * VEC;      // values of one block held by a thread
@@ -551,8 +550,22 @@ void launch_matvec(const bem_problem* p, const MT* W, const double* x, int64_t l
         if (p->mv_ntiles[ty] > 0) {
             // W is symmetric: read its upper half once and apply every block to both sides (also
             // for a single column: half the bytes outweigh the idle matrix-core columns)
-            hipLaunchKernelGGL(k_symv_mfma<MT>, dim3(unsigned(p->mv_ntiles[ty])), dim3(256), 0, s, W, ldw, N, xt, ldw / 64,
-                               p->mv_nst[ty], p->mv_tiles[ty].as<int2>(), sp);
+            const dim3 grid(unsigned(p->mv_ntiles[ty])), blk(256);
+            const int64_t nbk = ldw / 64, nst = p->mv_nst[ty];
+            const int2* tl = p->mv_tiles[ty].as<int2>();
+            if constexpr (sizeof(MT) == 4) {
+                switch (p->mv_ks[ty]) {
+                    case 4: hipLaunchKernelGGL((k_symv_mfma<MT, 4>), grid, blk, 0, s, W, ldw, N, xt, nbk, nst, tl, sp); break;
+                    case 16: hipLaunchKernelGGL((k_symv_mfma<MT, 16>), grid, blk, 0, s, W, ldw, N, xt, nbk, nst, tl, sp); break;
+                    default: hipLaunchKernelGGL((k_symv_mfma<MT, 8>), grid, blk, 0, s, W, ldw, N, xt, nbk, nst, tl, sp); break;
+                }
+            } else {
+                switch (p->mv_ks[ty]) {
+                    case 2: hipLaunchKernelGGL((k_symv_mfma<MT, 2>), grid, blk, 0, s, W, ldw, N, xt, nbk, nst, tl, sp); break;
+                    case 8: hipLaunchKernelGGL((k_symv_mfma<MT, 8>), grid, blk, 0, s, W, ldw, N, xt, nbk, nst, tl, sp); break;
+                    default: hipLaunchKernelGGL((k_symv_mfma<MT, 4>), grid, blk, 0, s, W, ldw, N, xt, nbk, nst, tl, sp); break;
+                }
+            }
             hipLaunchKernelGGL(k_symv_reduce<MT>, dim3(unsigned((N + 255) / 256), unsigned(kc)), dim3(256), 0, s, sp,
                                p->mv_nst[ty], N, yc, ldy);
             HIP_CHECK(hipGetLastError());
@@ -629,7 +642,8 @@ void matvec_setup(bem_problem* p, hipStream_t s) {
     std::vector<int2> tiles[2];
     size_t sym_bytes = 0;
     for (int ty = 0; ty < 2; ++ty) {
-        const int64_t ks = ty == 0 ? SymTile<float>::K : SymTile<double>::K;
+        const int64_t ks = ty == 0 ? p->tune.symv_blocks_fp32 : p->tune.symv_blocks_fp64;
+        p->mv_ks[ty] = int(ks);
         const int64_t nst = (nb + ks - 1) / ks;
         // off-diagonal super-tiles first: the half-size diagonal ones fill the tail of the launch
         for (int64_t I = 0; I < nst; ++I)

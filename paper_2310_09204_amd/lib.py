@@ -6,6 +6,7 @@ The names mirror the C-ABI in include/bem.h.  Importing this module loads the in
 from __future__ import annotations
 
 import ctypes
+import json
 import os
 from typing import Optional
 
@@ -42,6 +43,30 @@ class ProblemInfo(ctypes.Structure):
                 ("q_hist", ctypes.c_int64 * 16), ("t_assemble_s", ctypes.c_double),
                 ("t_far_s", ctypes.c_double), ("t_near_s", ctypes.c_double), ("t_contract_s", ctypes.c_double),
                 ("t_host_s", ctypes.c_double), ("n_pair_panels", ctypes.c_int64), ("dim", ctypes.c_int64)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("max_triangles", ctypes.c_int64), ("far_separation", ctypes.c_double),
+                ("panel_fraction", ctypes.c_double), ("symv_blocks_fp64", ctypes.c_int32),
+                ("symv_blocks_fp32", ctypes.c_int32), ("check_every", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+TUNING_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning")
+
+
+def tuning_file(arch: str = "gfx950") -> str:
+    """The autotuner's committed table for a device architecture."""
+    return os.path.join(TUNING_DIR, arch + ".json")
+
+
+def load_tuning(path: str):
+    """Entries of a tuning table written by tune.py (a list of dicts with the Tuning fields)."""
+    with open(path) as f:
+        d = json.load(f)
+    return d["entries"]
 
 
 class PrecondOpts(ctypes.Structure):
@@ -91,6 +116,8 @@ SIGNATURES = {
     "bem_ctx_destroy": (None, [_vp]),
     "bem_ctx_synchronize": (_ci, [_vp]),
     "bem_ctx_release_cached": (_ci, [_vp]),
+    "bem_ctx_set_tuning": (_ci, [_vp, ctypes.c_void_p, _i32]),
+    "bem_problem_tuning": (_ci, [_vp, ctypes.c_void_p]),
     "bem_double_layer": (_ci, [_vp, _vp, _i32, _vp, _i64, _vp]),
     "bem_assemble_2d": (_ci, [_vp, _vp, _i64, _vp, _i64, _vp, ctypes.POINTER(_vp)]),
     "bem_mesh_analyze_2d": (_ci, [_vp, _i64, _vp, _i64, ctypes.POINTER(_i64), _vp, _vp, _vp, _vp]),
@@ -175,9 +202,29 @@ def mesh_analyze(V, T):
 
 
 class Context:
-    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+    """A device context.  tuning: "auto" loads the autotuner's table for gfx950 when it is present
+    (paper_2310_09204_amd/tuning/gfx950.json), None keeps the defaults, or a list of entries."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0, tuning="auto"):
         self._h = ctypes.c_void_p()
         _check(load().bem_ctx_create(device, hbm_budget_bytes, ctypes.byref(self._h)))
+        self.tuning = []
+        if tuning == "auto":
+            path = tuning_file()
+            if os.path.exists(path):
+                self.set_tuning(load_tuning(path))
+        elif tuning:
+            self.set_tuning(tuning)
+
+    def set_tuning(self, entries):
+        """bem_ctx_set_tuning with a list of dicts (Tuning fields; missing fields take the defaults)."""
+        arr = (Tuning * max(1, len(entries)))()
+        for i, e in enumerate(entries):
+            for k, v in e.items():
+                if k in dict(Tuning._fields_):
+                    setattr(arr[i], k, v)
+        _check(load().bem_ctx_set_tuning(self._h, ctypes.cast(arr, ctypes.c_void_p), len(entries)))
+        self.tuning = [dict(e) for e in entries]
 
     @property
     def handle(self):
@@ -284,6 +331,13 @@ class Problem:
         self.N = self.get_info()["n_dofs"]
 
     @property
+    def tuning(self):
+        """The launch parameters this problem was assembled with (bem_problem_tuning)."""
+        t = Tuning()
+        _check(load().bem_problem_tuning(self._h, ctypes.byref(t)))
+        return t.as_dict()
+
+    @property
     def info(self):
         """bem_problem_get_info, read at each access (t_contract_s is NaN while the contraction that
         bem_assemble leaves running has not finished)."""
@@ -363,7 +417,7 @@ class Problem:
         return out
 
     def solve(self, g=None, rhs=None, precond=None, tol=1e-10, max_iter=2000, use_precond=True,
-              precision=FP64, refresh_factor=1e-3, check_every=4, use_graph=True, raise_on_error=True,
+              precision=FP64, refresh_factor=1e-3, check_every=0, use_graph=True, raise_on_error=True,
               device_out=None, x0=None):
         """Returns (phi[k][N], [info dict per column], status code).  With device_out (the address
         of k x N doubles in device memory) and g, bem_pcg_solve_dev: phi stays there and None is

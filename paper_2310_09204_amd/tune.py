@@ -1,0 +1,234 @@
+"""Autotuner of the library's launch parameters (run on the device; writes the table that
+lib.Context loads).
+
+    python -m paper_2310_09204_amd.tune [--out paper_2310_09204_amd/tuning/gfx950.json]
+                                        [--summary profiles/tuning_gfx950.md] [--classes small,medium,large]
+
+For each size class (meshes of up to 20,000 / 100,000 / any number of triangles) it assembles a
+representative synthetic workload of that size (the three-page book at h = 1/48, the crossed
+panels at h = 1/96 and at h = 1/192) once per candidate and keeps the fastest value of:
+
+  far_separation    the far-field kernel's centred-form threshold, timed by the kernel's own HIP
+                    events (t_far of the problem); candidates 1.1 .. 2.0, all within the rounding
+                    bound ((s + 1) / (s - 1))^2 ulp <= 441 ulp of |x - y|^2
+  symv_blocks_fp64  super-block edge of the symmetric product with the FP64 matrix (2, 4, 8) and
+  symv_blocks_fp32  with the FP32 copy (4, 8, 16): mean time of device-resident 16-column products
+  panel_fraction    share of free memory for pair-matrix panels (large class only: the only one
+                    assembled in panels): device time of the far, near and contraction passes
+                    plus the host analysis, after one assembly of the same panel size
+  check_every       PCG iterations between host checks: the preconditioned 16-column solve; a
+                    value whose solve does not converge is not taken
+
+Every candidate changes the launch shape only; results differ by rounding at most (the centred
+form's bound above), which the parity tests cover at the default values and the tuner checks
+against the default's W on sampled rows (relative 1e-12).  The table goes to --out as JSON with
+every measurement; --summary writes the same as a short markdown table.
+"""
+from __future__ import annotations
+
+import argparse
+import datetime
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+if os.path.dirname(HERE) not in sys.path:
+    sys.path.insert(0, os.path.dirname(HERE))
+
+from paper_2310_09204_amd import lib, meshes  # noqa: E402
+
+CLASSES = {
+    # name: (max_triangles, workload, precision of the timed solve); every problem is assembled with
+    # its FP32 copy, so that both products can be timed
+    "small": (20000, "book48", False),
+    "medium": (100000, "crossed96", True),
+    "large": (1 << 40, "crossed192", True),
+}
+SEPARATIONS = (1.1, 1.2, 1.35, 1.5, 2.0)
+SYMV_PAIRS = ((2, 4), (4, 8), (8, 16))     # (FP64, FP32) super-block edges
+PANEL_FRACTIONS = (0.45, 0.6, 0.75)
+CHECKS = (2, 4, 8)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _problem(ctx, w, mixed, entry):
+    ctx.set_tuning([entry])
+    t0 = time.perf_counter()
+    p = lib.Problem(ctx, w.mesh.vertices, w.mesh.triangles, precision=lib.FP32_REFINE, near_order=10)
+    ctx.synchronize()
+    return p, time.perf_counter() - t0
+
+
+def tune_class(ctx, name, reps=2):
+    max_tri, wname, mixed = CLASSES[name]
+    w = meshes.workload(wname, seed=0, k=16)
+    meas = {"workload": wname, "n_tri": int(w.mesh.nt), "far_separation": {}, "symv_blocks_fp64": {},
+            "symv_blocks_fp32": {}, "panel_fraction": {}, "check_every": {}}
+    ref_rows = None
+    ctx.release_cached()
+    # warm-up assembly (first touches of device memory)
+    p, _ = _problem(ctx, w, mixed, {"max_triangles": max_tri})
+    rows = np.sort(np.random.default_rng(3).choice(p.N, 32, replace=False))   # sampled rows of W
+    p.close()
+    # far-field separation, with the symmetric-product pairs cycled through the same assemblies
+    best_sep, t_best = None, None
+    symv64, symv32 = {}, {}
+    for i, sep in enumerate(SEPARATIONS):
+        ks64, ks32 = SYMV_PAIRS[i % len(SYMV_PAIRS)]
+        times = []
+        for r in range(reps):
+            p, _ = _problem(ctx, w, mixed, {"max_triangles": max_tri, "far_separation": sep,
+                                            "symv_blocks_fp64": ks64, "symv_blocks_fp32": ks32})
+            times.append(p.info["t_far_s"])
+            if r == 0:
+                Wr = p.rows(rows)
+                if sep == 1.2:
+                    ref_rows = Wr
+                else:
+                    meas.setdefault("rows_checked", []).append((sep, Wr))
+                symv64.setdefault(ks64, []).append(p.bench_matvec(fp32=False, k=16, reps=3))
+                symv32.setdefault(ks32, []).append(p.bench_matvec(fp32=True, k=16, reps=5))
+            p.close()
+        meas["far_separation"][str(sep)] = min(times)
+        log("tune %s: far separation %.2f -> %.3f ms" % (name, sep, min(times) * 1e3))
+        if t_best is None or min(times) < t_best:
+            best_sep, t_best = sep, min(times)
+    # every separation gives the same matrix up to the centred form's rounding
+    worst = 0.0
+    for sep, Wr in meas.pop("rows_checked", []):
+        d = float(np.abs(Wr - ref_rows).max() / np.abs(ref_rows).max())
+        worst = max(worst, d)
+        if d > 1e-12:
+            raise RuntimeError("far separation %.2f changes W by %.2e relative" % (sep, d))
+    meas["rows_max_relative_difference"] = worst
+    for ks, t in symv64.items():
+        meas["symv_blocks_fp64"][str(ks)] = min(t)
+    for ks, t in symv32.items():
+        meas["symv_blocks_fp32"][str(ks)] = min(t)
+    best64 = min(symv64, key=lambda k: min(symv64[k]))
+    best32 = min(symv32, key=lambda k: min(symv32[k]))
+    log("tune %s: symmetric product FP64 %s, FP32 %s" % (name, {k: "%.3f ms" % (min(v) * 1e3) for k, v in symv64.items()},
+                                                         {k: "%.3f ms" % (min(v) * 1e3) for k, v in symv32.items()}))
+    entry = {"max_triangles": max_tri, "far_separation": best_sep, "symv_blocks_fp64": int(best64),
+             "symv_blocks_fp32": int(best32)}
+    # panel fraction: the large class assembles in panels
+    if name == "large":
+        best_pf, t_pf = None, None
+        for pf in PANEL_FRACTIONS:
+            times = []
+            ctx.release_cached()   # panel buffers of another size are not reused: the first run touches
+            for r in range(reps + 1):
+                p, _ = _problem(ctx, w, mixed, dict(entry, panel_fraction=pf))
+                i = p.info
+                if r > 0:
+                    times.append(i["t_far_s"] + i["t_near_s"] + i["t_contract_s"] + i["t_host_s"])
+                npan = i["n_pair_panels"]
+                p.close()
+            meas["panel_fraction"][str(pf)] = {"t_device_s": min(times), "panels": int(npan)}
+            log("tune %s: panel fraction %.2f -> %.3f s (%d panels)" % (name, pf, min(times), npan))
+            if t_pf is None or min(times) < t_pf:
+                best_pf, t_pf = pf, min(times)
+        entry["panel_fraction"] = best_pf
+    # check interval: the preconditioned 16-column solve
+    p, _ = _problem(ctx, w, mixed, entry)
+    M = lib.Preconditioner(p, w.patch_of_triangle, w.coarse.vertices, w.coarse.triangles, w.coarse_of_triangle,
+                           factor_fp32=mixed)
+    prec = lib.FP32_REFINE if mixed else lib.FP64
+    best_ce, t_ce = None, None
+    for ce in CHECKS:
+        times, ok, iters = [], True, 0
+        for _ in range(reps + 1):
+            t0 = time.perf_counter()
+            _, info, rc = p.solve(g=w.g, precond=M, tol=1e-10, precision=prec, check_every=ce, raise_on_error=False)
+            times.append(time.perf_counter() - t0)
+            ok = ok and rc == 0
+            iters = max(i["iters"] for i in info)
+        meas["check_every"][str(ce)] = {"t_solve_s": min(times[1:]), "iters": int(iters), "converged": bool(ok)}
+        log("tune %s: check every %d -> %.3f ms, %d iterations%s" % (name, ce, min(times[1:]) * 1e3, iters,
+                                                                     "" if ok else " (not converged: not taken)"))
+        if ok and (t_ce is None or min(times[1:]) < t_ce):
+            best_ce, t_ce = ce, min(times[1:])
+    entry["check_every"] = best_ce
+    M.close()
+    p.close()
+    ctx.release_cached()
+    return entry, meas
+
+
+def summary_md(table):
+    out = ["# Autotuned launch parameters (%s)" % table["arch"], "",
+           "Written by `python -m paper_2310_09204_amd.tune --summary profiles/tuning_gfx950.md` on %s (%s)."
+           % (table["device"], table["date"]), "",
+           "| class (max triangles) | workload | far separation | symv FP64 / FP32 blocks | panel fraction | check every |",
+           "|---|---|---|---|---|---|"]
+    for e in table["entries"]:
+        m = table["measurements"][e["class"]]
+        out.append("| %s (%s) | %s | %s | %d / %d | %s | %d |" % (
+            e["class"], "any" if e["max_triangles"] >= 1 << 40 else e["max_triangles"], m["workload"],
+            e["far_separation"], e["symv_blocks_fp64"], e["symv_blocks_fp32"], e.get("panel_fraction", "-"),
+            e["check_every"]))
+    out.append("")
+    for e in table["entries"]:
+        m = table["measurements"][e["class"]]
+        out.append("## %s: %s (%d triangles)" % (e["class"], m["workload"], m["n_tri"]))
+        out.append("")
+        out.append("* far kernel (device time per assembly): " +
+                   ", ".join("s = %s: %.2f ms" % (k, v * 1e3) for k, v in m["far_separation"].items()) +
+                   "; sampled rows of W differ by at most %.1e relative across separations" % m["rows_max_relative_difference"])
+        out.append("* 16-column product, FP64 matrix: " + ", ".join("%s blocks: %.3f ms" % (k, v * 1e3)
+                                                                      for k, v in m["symv_blocks_fp64"].items()))
+        if m["symv_blocks_fp32"]:
+            out.append("* 16-column product, FP32 copy: " + ", ".join("%s blocks: %.3f ms" % (k, v * 1e3)
+                                                                        for k, v in m["symv_blocks_fp32"].items()))
+        if m["panel_fraction"]:
+            out.append("* panelled assembly (far + near + contraction device time and host analysis): " +
+                       ", ".join("%s: %.3f s (%d panels)" % (k, v["t_device_s"], v["panels"]) for k, v in m["panel_fraction"].items()))
+        out.append("* preconditioned 16-column solve: " + ", ".join(
+            "every %s: %.2f ms, %d iterations%s" % (k, v["t_solve_s"] * 1e3, v["iters"], "" if v["converged"] else " (not converged)")
+            for k, v in m["check_every"].items()))
+        out.append("")
+    return "\n".join(out) + "\n"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=lib.tuning_file())
+    ap.add_argument("--summary", default=None)
+    ap.add_argument("--classes", default="small,medium,large")
+    ap.add_argument("--reps", type=int, default=2)
+    args = ap.parse_args()
+    ctx = lib.Context(0, tuning=None)
+    entries, meas = [], {}
+    for name in args.classes.split(","):
+        log("tune: class %s" % name)
+        e, m = tune_class(ctx, name, args.reps)
+        e["class"] = name
+        entries.append(e)
+        meas[name] = m
+    ctx.close()
+    entries.sort(key=lambda e: e["max_triangles"])
+    try:
+        import torch
+        dev = torch.cuda.get_device_name(0)
+    except Exception:
+        dev = "device 0"
+    table = {"arch": "gfx950", "device": dev, "date": datetime.date.today().isoformat(),
+             "entries": entries, "measurements": meas}
+    os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+    with open(args.out, "w") as f:
+        json.dump(table, f, indent=1)
+    if args.summary:
+        with open(args.summary, "w") as f:
+            f.write(summary_md(table))
+    print(json.dumps({"entries": entries}))
+
+
+if __name__ == "__main__":
+    main()

@@ -255,8 +255,9 @@ void release_stream(bem_ctx* c, hipStream_t s);
 
 // dense products (solver.hip); x, y column-major [k][N] with leading dimension ldx
 void matvec_setup(bem_problem* p, hipStream_t s);   // after W is allocated (ldw set)
+// gate != nullptr: a device word; the product's kernels do nothing while it is 0 (y keeps its values)
 void matvec_device(const bem_problem* p, bool fp32, const double* d_x, int64_t ldx, int k,
-                   double* d_y, hipStream_t s);
+                   double* d_y, hipStream_t s, const int* gate = nullptr);
 // Continuous batching of a block PCG (serving loop): a fixed number of column slots, each running
 // its own CG (per-column scalars and tolerance).  At every check point the solver reports the
 // columns that have stopped since the last one and asks for new columns to start in the free slots.

@@ -22,12 +22,12 @@ namespace bem {
 
 namespace {
 
-// Per-column scalars of the block (P)CG, kept on the device.  `near` marks a column whose recurrence
-// residual has reached the tolerance but still awaits confirmation by a true residual; `refreshes`
-// counts the FP64 residual replacements of the mixed-precision iteration.
+// Per-column scalars of the block (P)CG, kept on the device.  `due` marks a column of the
+// mixed-precision iteration that asks for a residual replacement in the current iteration;
+// `refreshes` counts the column's replacements; rr_ref is r.r of its last true residual.
 struct ColState {
-    double rz, pq, rr, alpha, beta, bb, tol2, pad;
-    int active, iters, flag, near, refreshes, pad2;
+    double rz, pq, rr, alpha, beta, bb, tol2, rr_ref;
+    int active, iters, flag, due, refreshes, pad2;
 };
 
 constexpr int kStatBreakdown = 2;
@@ -38,7 +38,8 @@ constexpr int kStatBreakdown = 2;
 template <typename MT, typename AT, int K>
 __global__ __launch_bounds__(256) void k_matvec(const MT* __restrict__ W, int64_t ldw, int64_t N,
                                                 const double* __restrict__ x, int64_t ldx, int kc,
-                                                double* __restrict__ y, int64_t ldy) {
+                                                double* __restrict__ y, int64_t ldy, const int* __restrict__ gate) {
+    if (gate && !*gate) return;
     const int lane = threadIdx.x & 63;
     const int64_t row = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
     if (row >= N) return;
@@ -94,7 +95,8 @@ __global__ __launch_bounds__(256) void k_matvec(const MT* __restrict__ W, int64_
 // ---------------------------------------------------------------------------------------------
 template <typename MT>
 __global__ void k_transpose_x(const double* __restrict__ x, int64_t ldx, int kc, int64_t N, int64_t rows,
-                              MT* __restrict__ xt) {
+                              MT* __restrict__ xt, const int* __restrict__ gate) {
+    if (gate && !*gate) return;
     const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (e >= rows * 16) return;
     const int64_t j = e >> 4;
@@ -112,7 +114,9 @@ __global__ void k_transpose_x(const double* __restrict__ x, int64_t ldx, int kc,
 template <typename MT>
 __global__ __launch_bounds__(256) void k_matvec_mfma(const MT* __restrict__ W, int64_t ldw, int64_t N,
                                                      const MT* __restrict__ xt, int64_t cols_per_split, int kc,
-                                                     double* __restrict__ y, int64_t ldy, double* __restrict__ partial) {
+                                                     double* __restrict__ y, int64_t ldy, double* __restrict__ partial,
+                                                     const int* __restrict__ gate) {
+    if (gate && !*gate) return;
     using MC = MatrixCore<MT>;
     using V16 = typename std::conditional<sizeof(MT) == 4, float4, double2>::type;
     constexpr int VEC = 16 / sizeof(MT);
@@ -199,7 +203,8 @@ __global__ __launch_bounds__(256) void k_matvec_mfma(const MT* __restrict__ W, i
 template <typename MT, int KS>
 __global__ __launch_bounds__(256) void k_symv_mfma(const MT* __restrict__ W, int64_t ldw, int64_t N, const MT* __restrict__ xt,
                                                    int64_t nb, int64_t nst, const int2* __restrict__ tiles,
-                                                   MT* __restrict__ part) {
+                                                   MT* __restrict__ part, const int* __restrict__ gate) {
+    if (gate && !*gate) return;
     using MC = MatrixCore<MT>;
     using V = typename MC::V;
     using V16 = typename std::conditional<sizeof(MT) == 4, float4, double2>::type;
@@ -294,7 +299,9 @@ __global__ __launch_bounds__(256) void k_symv_mfma(const MT* __restrict__ W, int
 // y[c][e] = the nst + 1 partials of block row b = e / 64 added in FP64: row partials J = b / KS ..
 // nst - 1, then column partials I = 0 .. b / KS (slot order; loads issued eight at a time)
 template <typename MT>
-__global__ void k_symv_reduce(const MT* __restrict__ part, int64_t nst, int64_t N, double* __restrict__ y, int64_t ldy) {
+__global__ void k_symv_reduce(const MT* __restrict__ part, int64_t nst, int64_t N, double* __restrict__ y, int64_t ldy,
+                              const int* __restrict__ gate) {
+    if (gate && !*gate) return;
     const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     const int c = blockIdx.y;
     if (e >= N) return;
@@ -313,7 +320,8 @@ __global__ void k_symv_reduce(const MT* __restrict__ part, int64_t nst, int64_t 
 }
 
 __global__ void k_reduce_splits(const double* __restrict__ partial, int S, int kc, int64_t N, int64_t ldw,
-                                double* __restrict__ y, int64_t ldy) {
+                                double* __restrict__ y, int64_t ldy, const int* __restrict__ gate) {
+    if (gate && !*gate) return;
     const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (e >= int64_t(kc) * N) return;
     const int n = int(e / N);
@@ -399,11 +407,36 @@ __global__ __launch_bounds__(256) void k_update_xr(double* __restrict__ x, doubl
     if (threadIdx.x == 0) partial[int64_t(c) * gridDim.x + blockIdx.x] = acc;
 }
 
-// rr from block partials.  true_res = 1: rr is the true residual of x (FP64 iteration, or a residual
-// replacement of the mixed one) and decides convergence; true_res = 0: rr is the FP32-driven
-// recurrence residual, which only marks the column `near` so that the host schedules a replacement.
+// Mixed precision, after the update of x and r: a column is due for residual replacement in this
+// iteration when its recurrence r.r has met the tolerance (convergence is judged on true residuals
+// only) or has fallen by refresh2 since its last true residual (so that the FP32 products'
+// rounding never dominates the recurrence).
+__global__ __launch_bounds__(256) void k_check_due(const double* __restrict__ partial, int G, ColState* __restrict__ st,
+                                                   double refresh2) {
+    const int c = blockIdx.x;
+    const double rr = reduce_partials(partial + int64_t(c) * G, G);
+    if (threadIdx.x == 0) {
+        ColState& s = st[c];
+        s.due = (s.active && (!(rr > s.tol2 * s.bb) || rr < refresh2 * s.rr_ref)) ? 1 : 0;
+    }
+}
+
+// gate[which] = 1 if any column is active (which = 0) or due (which = 1): the product kernels that
+// take the gate do nothing when it is 0, so that a captured iteration costs little once every
+// column has stopped, and the FP64 product of a replacement runs only when a column is due.  That
+// product covers the whole block, so every active column is replaced with the due ones: the columns
+// share one replacement schedule and one FP64 product per replacement.
+__global__ __launch_bounds__(256) void k_gate(const ColState* __restrict__ st, int k, int which, int* __restrict__ gate) {
+    int any = 0;
+    for (int c = threadIdx.x; c < k; c += 256) any |= which ? st[c].due : st[c].active;
+    any = __syncthreads_or(any);
+    if (threadIdx.x == 0) gate[which] = any ? 1 : 0;
+}
+
+// r.r from block partials; it is the true residual of x in the FP64 iteration and in a mixed one
+// with replacement (gate[1]), and only a true residual decides convergence.
 __global__ __launch_bounds__(256) void k_check(const double* __restrict__ partial, int G, ColState* __restrict__ st,
-                                               int true_res, int refresh) {
+                                               int mixed, const int* __restrict__ gate) {
     const int c = blockIdx.x;
     const double rr = reduce_partials(partial + int64_t(c) * G, G);
     if (threadIdx.x == 0) {
@@ -411,15 +444,18 @@ __global__ __launch_bounds__(256) void k_check(const double* __restrict__ partia
         if (s.active) {
             s.iters += 1;
             s.rr = rr;
-            s.refreshes += refresh;
+            const bool replaced = mixed && gate[1];
+            const bool true_res = !mixed || replaced;
+            s.due = 0;
+            if (replaced) {
+                s.refreshes += 1;
+                s.rr_ref = rr;
+            }
             if (!isfinite(rr)) {
                 s.active = 0;
                 s.flag = kStatBreakdown;
-            } else if (rr <= s.tol2 * s.bb) {
-                if (true_res) s.active = 0;
-                else s.near = 1;
-            } else if (true_res) {
-                s.near = 0;
+            } else if (true_res && rr <= s.tol2 * s.bb) {
+                s.active = 0;
             }
         }
     }
@@ -469,13 +505,16 @@ __global__ void k_residual(const double* __restrict__ b, const double* __restric
         r[int64_t(c) * ld + i] = b[int64_t(c) * ld + i] - y[int64_t(c) * ld + i];
 }
 
-// r = b - y for the active columns, with the partial sums of r.r (as k_update_xr leaves them)
-__global__ __launch_bounds__(256) void k_residual_active(const double* __restrict__ b, const double* __restrict__ y,
-                                                         double* __restrict__ r, int64_t ld, int64_t N,
-                                                         const ColState* __restrict__ st, double* __restrict__ partial) {
+// when some column is due (gate[1]): r = b - y for every active column, with the partial sums of
+// r.r (as k_update_xr leaves them)
+__global__ __launch_bounds__(256) void k_residual_due(const double* __restrict__ b, const double* __restrict__ y,
+                                                      double* __restrict__ r, int64_t ld, int64_t N,
+                                                      const ColState* __restrict__ st, double* __restrict__ partial,
+                                                      const int* __restrict__ gate) {
     const int c = blockIdx.y;
+    if (!gate[1] || !st[c].active) return;
     double acc = 0.0;
-    if (st[c].active) {
+    {
         const double* bc = b + int64_t(c) * ld;
         const double* yc = y + int64_t(c) * ld;
         double* rc = r + int64_t(c) * ld;
@@ -512,9 +551,10 @@ __global__ __launch_bounds__(256) void k_init_state(const double* __restrict__ p
         s.rr = rr;
         s.rz = rz;
         s.tol2 = tol2[c];
+        s.rr_ref = rr;
         s.iters = 0;
         s.flag = 0;
-        s.near = 0;
+        s.due = 0;
         s.refreshes = 0;
         if (!isfinite(bb) || !isfinite(rr) || !isfinite(rz)) {
             s.active = 0;
@@ -533,7 +573,7 @@ inline unsigned gblocks(int64_t N) { return unsigned(std::max<int64_t>(1, std::m
 // 1024 of MT).  Every entry of the three that a later kernel reads is written first, each call.
 template <typename MT, typename AT>
 void launch_matvec(const bem_problem* p, const MT* W, const double* x, int64_t ldx, int k, double* y, int64_t ldy,
-                   hipStream_t s, MT* xt, double* part, MT* sp) {
+                   hipStream_t s, MT* xt, double* part, MT* sp, const int* gate) {
     const int64_t N = p->N, ldw = p->ldw;
     for (int c0 = 0; c0 < k; c0 += 16) {
         const int kc = std::min(16, k - c0);
@@ -542,11 +582,11 @@ void launch_matvec(const bem_problem* p, const MT* W, const double* x, int64_t l
         const int ty = sizeof(MT) == 4 ? 0 : 1;
         if (kc == 1 && p->mv_ntiles[ty] == 0) {
             // one column of a one-block matrix: a plain streaming dot product per row (one wave per row)
-            hipLaunchKernelGGL((k_matvec<MT, AT, 1>), dim3(unsigned((N + 3) / 4)), dim3(256), 0, s, W, ldw, N, xc, ldx, kc, yc, ldy);
+            hipLaunchKernelGGL((k_matvec<MT, AT, 1>), dim3(unsigned((N + 3) / 4)), dim3(256), 0, s, W, ldw, N, xc, ldx, kc, yc, ldy, gate);
             HIP_CHECK(hipGetLastError());
             continue;
         }
-        hipLaunchKernelGGL(k_transpose_x<MT>, dim3(unsigned((ldw * 16 + 255) / 256)), dim3(256), 0, s, xc, ldx, kc, N, ldw, xt);
+        hipLaunchKernelGGL(k_transpose_x<MT>, dim3(unsigned((ldw * 16 + 255) / 256)), dim3(256), 0, s, xc, ldx, kc, N, ldw, xt, gate);
         if (p->mv_ntiles[ty] > 0) {
             // W is symmetric: read its upper half once and apply every block to both sides (also
             // for a single column: half the bytes outweigh the idle matrix-core columns)
@@ -555,19 +595,19 @@ void launch_matvec(const bem_problem* p, const MT* W, const double* x, int64_t l
             const int2* tl = p->mv_tiles[ty].as<int2>();
             if constexpr (sizeof(MT) == 4) {
                 switch (p->mv_ks[ty]) {
-                    case 4: hipLaunchKernelGGL((k_symv_mfma<MT, 4>), grid, blk, 0, s, W, ldw, N, xt, nbk, nst, tl, sp); break;
-                    case 16: hipLaunchKernelGGL((k_symv_mfma<MT, 16>), grid, blk, 0, s, W, ldw, N, xt, nbk, nst, tl, sp); break;
-                    default: hipLaunchKernelGGL((k_symv_mfma<MT, 8>), grid, blk, 0, s, W, ldw, N, xt, nbk, nst, tl, sp); break;
+                    case 4: hipLaunchKernelGGL((k_symv_mfma<MT, 4>), grid, blk, 0, s, W, ldw, N, xt, nbk, nst, tl, sp, gate); break;
+                    case 16: hipLaunchKernelGGL((k_symv_mfma<MT, 16>), grid, blk, 0, s, W, ldw, N, xt, nbk, nst, tl, sp, gate); break;
+                    default: hipLaunchKernelGGL((k_symv_mfma<MT, 8>), grid, blk, 0, s, W, ldw, N, xt, nbk, nst, tl, sp, gate); break;
                 }
             } else {
                 switch (p->mv_ks[ty]) {
-                    case 2: hipLaunchKernelGGL((k_symv_mfma<MT, 2>), grid, blk, 0, s, W, ldw, N, xt, nbk, nst, tl, sp); break;
-                    case 8: hipLaunchKernelGGL((k_symv_mfma<MT, 8>), grid, blk, 0, s, W, ldw, N, xt, nbk, nst, tl, sp); break;
-                    default: hipLaunchKernelGGL((k_symv_mfma<MT, 4>), grid, blk, 0, s, W, ldw, N, xt, nbk, nst, tl, sp); break;
+                    case 2: hipLaunchKernelGGL((k_symv_mfma<MT, 2>), grid, blk, 0, s, W, ldw, N, xt, nbk, nst, tl, sp, gate); break;
+                    case 8: hipLaunchKernelGGL((k_symv_mfma<MT, 8>), grid, blk, 0, s, W, ldw, N, xt, nbk, nst, tl, sp, gate); break;
+                    default: hipLaunchKernelGGL((k_symv_mfma<MT, 4>), grid, blk, 0, s, W, ldw, N, xt, nbk, nst, tl, sp, gate); break;
                 }
             }
             hipLaunchKernelGGL(k_symv_reduce<MT>, dim3(unsigned((N + 255) / 256), unsigned(kc)), dim3(256), 0, s, sp,
-                               p->mv_nst[ty], N, yc, ldy);
+                               p->mv_nst[ty], N, yc, ldy, gate);
             HIP_CHECK(hipGetLastError());
             continue;
         }
@@ -582,10 +622,10 @@ void launch_matvec(const bem_problem* p, const MT* W, const double* x, int64_t l
         const int64_t cps = ((ldw + S - 1) / S + quantum - 1) / quantum * quantum;
         S = int((ldw + cps - 1) / cps);
         const dim3 grid{unsigned(blocks), unsigned(S), 1u};
-        hipLaunchKernelGGL(k_matvec_mfma<MT>, grid, dim3(256), 0, s, W, ldw, N, xt, cps, kc, yc, ldy, S > 1 ? part : nullptr);
+        hipLaunchKernelGGL(k_matvec_mfma<MT>, grid, dim3(256), 0, s, W, ldw, N, xt, cps, kc, yc, ldy, S > 1 ? part : nullptr, gate);
         if (S > 1)
             hipLaunchKernelGGL(k_reduce_splits, dim3(unsigned((int64_t(kc) * N + 255) / 256)), dim3(256), 0, s, part, S, kc, N,
-                               ldw, yc, ldy);
+                               ldw, yc, ldy, gate);
         HIP_CHECK(hipGetLastError());
     }
 }
@@ -658,16 +698,17 @@ void matvec_setup(bem_problem* p, hipStream_t s) {
     for (int ty = 0; ty < 2; ++ty) p->mv_ntiles[ty] = int64_t(tiles[ty].size());
 }
 
-void matvec_device(const bem_problem* p, bool fp32, const double* d_x, int64_t ldx, int k, double* d_y, hipStream_t s) {
+void matvec_device(const bem_problem* p, bool fp32, const double* d_x, int64_t ldx, int k, double* d_y, hipStream_t s,
+                   const int* gate) {
     if (p->N == 0) return;
     double* part = p->mv_partial.as<double>();
     if (fp32) {
         if (!p->W32.ptr) fail(BEM_E_INVALID_ARG, "problem has no FP32 matrix (assemble with BEM_FP32_REFINE)");
         launch_matvec<float, double>(p, p->W32.as<float>(), d_x, ldx, k, d_y, ldx, s, static_cast<float*>(p->mv_xt.ptr),
-                                     part, static_cast<float*>(p->mv_sym.ptr));
+                                     part, static_cast<float*>(p->mv_sym.ptr), gate);
     } else {
         launch_matvec<double, double>(p, p->W64.as<double>(), d_x, ldx, k, d_y, ldx, s, p->mv_xt.as<double>(), part,
-                                      static_cast<double*>(p->mv_sym.ptr));
+                                      static_cast<double*>(p->mv_sym.ptr), gate);
     }
 }
 
@@ -724,10 +765,10 @@ void matvec_device_noalloc(const bem_problem* p, bool fp32, const double* d_x, i
     if (fp32) {
         if (!p->W32.ptr) fail(BEM_E_INVALID_ARG, "problem has no FP32 matrix (assemble with BEM_FP32_REFINE)");
         launch_matvec<float, double>(p, p->W32.as<float>(), d_x, ldx, k, d_y, ldx, s, static_cast<float*>(xt), part,
-                                     static_cast<float*>(sp));
+                                     static_cast<float*>(sp), nullptr);
     } else {
         launch_matvec<double, double>(p, p->W64.as<double>(), d_x, ldx, k, d_y, ldx, s, static_cast<double*>(xt), part,
-                                      static_cast<double*>(sp));
+                                      static_cast<double*>(sp), nullptr);
     }
 }
 
@@ -747,7 +788,9 @@ struct PcgResult {
 // mixed = true: products with the FP32 matrix and FP32 block inverses (FP64 vectors, dots and coarse
 // solve), with reliable updates: the recurrence residual is replaced by the true residual
 // b - W x with the FP64 matrix whenever it has fallen by `refresh` since the last replacement, and
-// before any column is declared converged, so convergence is always judged on a true residual.
+// before any column is declared converged, so convergence is always judged on a true residual.  The
+// device decides in each iteration which columns are due; the FP64 product of x is gated on any
+// column being due, so one captured iteration serves every case and the host only polls.
 // slots != nullptr (serving): b and x are the slot buffers (zero at the start, every column
 // inactive), columns are started and collected through the hooks at the check points, and
 // max_iter bounds each column's iterations instead of the launches.
@@ -760,6 +803,7 @@ PcgResult pcg_device(bem_problem* p, const bem_precond* M, bool mixed, const dou
     const bool fp32 = mixed;
     DeviceBuffer r(sizeof(double) * ld * k, s), z(sizeof(double) * ld * k, s), pp(sizeof(double) * ld * k, s), q(sizeof(double) * ld * k, s);
     DeviceBuffer part(sizeof(double) * G * k * 3, s), dst(sizeof(ColState) * k, s), dtol(sizeof(double) * k, s);
+    DeviceBuffer dgate(sizeof(int) * 2, s);   // any column active, any column due (k_gate)
     const int max_hist = want_cond ? std::max(1, max_iter) : 1;
     DeviceBuffer hist(sizeof(double) * 2 * max_hist * k, s);
     DeviceBuffer cscr(sizeof(double) * (M ? precond_scratch_size(M, std::min(k, 16)) : 1), s);
@@ -776,7 +820,6 @@ PcgResult pcg_device(bem_problem* p, const bem_precond* M, bool mixed, const dou
         else hipLaunchKernelGGL(k_copy, vg, vb, 0, s, in, out, ld, N);
         HIP_CHECK(hipGetLastError());
     };
-    auto matvec = [&](const double* in, double* out) { matvec_device(p, fp32, in, ld, k, out, s); };
 
     // ---- initial state ----
     if (x_nonzero) {
@@ -795,41 +838,44 @@ PcgResult pcg_device(bem_problem* p, const bem_precond* M, bool mixed, const dou
 
     ColState* st = dst.as<ColState>();
     double* h = hist.as<double>();
-    // one (P)CG iteration; with replace, the residual is recomputed as b - W x in FP64 after the
-    // update of x (q is free by then and holds W x)
-    auto iteration = [&](bool replace) {
-        matvec(pp.as<double>(), q.as<double>());
+    int* gate = dgate.as<int>();
+    // one (P)CG iteration.  The product with p is skipped once no column is active; mixed: when a
+    // column is due for replacement, every active column gets r = b - W x in FP64 after the update
+    // of x (q is free by then and holds W x); that product runs only then.
+    auto iteration = [&]() {
+        hipLaunchKernelGGL(k_gate, dim3(1), vb, 0, s, st, k, 0, gate);
+        matvec_device(p, fp32, pp.as<double>(), ld, k, q.as<double>(), s, gate);
         hipLaunchKernelGGL(k_dot_partial, vg, vb, 0, s, pp.as<double>(), q.as<double>(), ld, N, pa);
         hipLaunchKernelGGL(k_alpha, dim3(k), vb, 0, s, pa, int(G), st, h, max_hist);
         hipLaunchKernelGGL(k_update_xr, vg, vb, 0, s, x, r.as<double>(), pp.as<double>(), q.as<double>(), ld, N, st, pb);
-        if (replace) {
-            matvec_device(p, false, x, ld, k, q.as<double>(), s);
-            hipLaunchKernelGGL(k_residual_active, vg, vb, 0, s, b, q.as<double>(), r.as<double>(), ld, N, st, pb);
+        if (mixed) {
+            hipLaunchKernelGGL(k_check_due, dim3(k), vb, 0, s, pb, int(G), st, refresh * refresh);
+            hipLaunchKernelGGL(k_gate, dim3(1), vb, 0, s, st, k, 1, gate);
+            matvec_device(p, false, x, ld, k, q.as<double>(), s, gate + 1);
+            hipLaunchKernelGGL(k_residual_due, vg, vb, 0, s, b, q.as<double>(), r.as<double>(), ld, N, st, pb, gate);
         }
-        hipLaunchKernelGGL(k_check, dim3(k), vb, 0, s, pb, int(G), st, (!mixed || replace) ? 1 : 0, replace ? 1 : 0);
+        hipLaunchKernelGGL(k_check, dim3(k), vb, 0, s, pb, int(G), st, mixed ? 1 : 0, gate);
         apply_M(r.as<double>(), z.as<double>());
         hipLaunchKernelGGL(k_dot_partial, vg, vb, 0, s, r.as<double>(), z.as<double>(), ld, N, pc);
         hipLaunchKernelGGL(k_beta, dim3(k), vb, 0, s, pc, int(G), st, h, max_hist);
         hipLaunchKernelGGL(k_update_p, vg, vb, 0, s, pp.as<double>(), z.as<double>(), ld, N, st);
     };
 
-    // the captured iterations; an exception between begin and end of a capture still ends it, so
+    // the captured iteration; an exception between begin and end of a capture still ends it, so
     // the stream never stays in capture mode
-    struct Graphs {
+    struct Graph {
         hipStream_t s;
         bool capturing = false;
-        hipGraph_t graph[2] = {nullptr, nullptr};
-        hipGraphExec_t exec[2] = {nullptr, nullptr};
-        ~Graphs() {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        ~Graph() {
             if (capturing) {
                 hipGraph_t g = nullptr;
                 if (hipStreamEndCapture(s, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
                 (void)hipGetLastError();
             }
-            for (int v = 0; v < 2; ++v) {
-                if (exec[v]) (void)hipGraphExecDestroy(exec[v]);
-                if (graph[v]) (void)hipGraphDestroy(graph[v]);
-            }
+            if (exec) (void)hipGraphExecDestroy(exec);
+            if (graph) (void)hipGraphDestroy(graph);
         }
     } gr{s};
     // A capture that fails with a capture error (the runtime ends a capture when a call elsewhere
@@ -846,12 +892,12 @@ PcgResult pcg_device(bem_problem* p, const bem_precond* M, bool mixed, const dou
     if (use_graph) {
         std::lock_guard<std::mutex> lk(capture_mutex());   // no device-wide synchronisation meanwhile
         graphed = true;
-        for (int v = 0; v < (mixed ? 2 : 1) && graphed; ++v) {
+        {
             hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
             if (e == hipSuccess) {
                 gr.capturing = true;
                 try {
-                    iteration(v == 1);
+                    iteration();
                     e = hipGetLastError();
                 } catch (const Failure&) {
                     // a launch inside the capture reported an error (the runtime invalidates a
@@ -864,12 +910,12 @@ PcgResult pcg_device(bem_problem* p, const bem_precond* M, bool mixed, const dou
                 hipGraph_t g = nullptr;
                 const hipError_t e_end = hipStreamEndCapture(s, &g);
                 gr.capturing = false;
-                gr.graph[v] = g;
+                gr.graph = g;
                 if (e == hipSuccess) e = e_end;
                 if (e == hipSuccess && !g) e = hipErrorStreamCaptureInvalidated;
             }
             if (e == hipSuccess) {
-                HIP_CHECK(hipGraphInstantiate(&gr.exec[v], gr.graph[v], nullptr, nullptr, 0));
+                HIP_CHECK(hipGraphInstantiate(&gr.exec, gr.graph, nullptr, nullptr, 0));
             } else if (capture_error(e)) {
                 (void)hipGetLastError();
                 graphed = false;
@@ -890,11 +936,11 @@ PcgResult pcg_device(bem_problem* p, const bem_precond* M, bool mixed, const dou
             }
         }
     }
-    auto launch = [&](bool replace) {
+    auto launch = [&]() {
         if (graphed) {
-            HIP_CHECK(hipGraphLaunch(gr.exec[replace ? 1 : 0], s));
+            HIP_CHECK(hipGraphLaunch(gr.exec, s));
         } else {
-            iteration(replace);
+            iteration();
             HIP_CHECK(hipGetLastError());
         }
     };
@@ -903,9 +949,6 @@ PcgResult pcg_device(bem_problem* p, const bem_precond* M, bool mixed, const dou
     const int every = std::max(1, check_every);
     HIP_CHECK(hipMemcpyAsync(hs.data(), st, sizeof(ColState) * k, hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
-    std::vector<double> rr_ref(k);
-    for (int c = 0; c < k; ++c) rr_ref[c] = hs[c].rr;
-    const double refresh2 = refresh * refresh;
     auto any_active = [&]() {
         for (auto& c : hs) if (c.active) return true;
         return false;
@@ -971,7 +1014,6 @@ PcgResult pcg_device(bem_problem* p, const bem_precond* M, bool mixed, const dou
         HIP_CHECK(hipGetLastError());
         HIP_CHECK(hipMemcpyAsync(hs.data(), st, sizeof(ColState) * k, hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
-        for (const PcgNewColumn& nc : start) rr_ref[nc.slot] = hs[nc.slot].rr;
         return true;
     };
     if (slots) slots->graphed = graphed;
@@ -986,23 +1028,12 @@ PcgResult pcg_device(bem_problem* p, const bem_precond* M, bool mixed, const dou
         } else if (!(any_active() && launched < max_iter)) {
             break;
         }
-        // mixed: replace the residual now if a column may have converged (then check right after)
-        // or if a column's residual has fallen by `refresh` since its last replacement
-        bool near = false, fallen = false;
-        if (mixed)
-            for (int c = 0; c < k; ++c)
-                if (hs[c].active) {
-                    near = near || hs[c].near;
-                    fallen = fallen || hs[c].rr < refresh2 * rr_ref[c];
-                }
         // (serving: max_iter bounds each column, through serve_check, not the launches)
-        const int n = near ? 1 : (slots ? every : std::min(every, max_iter - launched));
-        for (int i = 0; i < n; ++i) launch(i == 0 && (near || fallen));
+        const int n = slots ? every : std::min(every, max_iter - launched);
+        for (int i = 0; i < n; ++i) launch();
         launched += n;
         HIP_CHECK(hipMemcpyAsync(hs.data(), st, sizeof(ColState) * k, hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
-        if (near || fallen)
-            for (int c = 0; c < k; ++c) rr_ref[c] = hs[c].rr;
         if (slots && !serve_check()) break;
     }
     PcgResult res;

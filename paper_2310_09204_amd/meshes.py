@@ -589,19 +589,20 @@ def serving_stream(seed: int, n_requests: int, rate: float, n_range: Tuple[int, 
     Each new geometry is 1-6 unit squares joined at shared edges (book, chain or tree layout,
     dihedral angles uniform in [30, 330] deg) with m x m square patches of cells_per_patch cells
     per panel, m chosen so that the dof count is near a target drawn uniformly from n_range, and a
-    nested coarse mesh with one coarse cell per patch.  With probability ``reuse`` a request
-    reuses an earlier geometry (new right-hand sides on a resident problem).  Each request has
-    k ~ U{k_range} random unit g and is FP64 or mixed precision with equal probability.
+    nested coarse mesh with one coarse cell per patch; it is served in FP64 or in mixed precision
+    with equal probability (fixed per geometry: a resident problem keeps its precision).  With
+    probability ``reuse`` a request reuses one of the three most recent geometries (new right-hand
+    sides on a resident problem, arriving in bursts).  Each request has k ~ U{k_range} random unit g.
     """
     rng = np.random.default_rng(seed)
-    geos: List[Tuple[Mesh, np.ndarray, Mesh, np.ndarray]] = []
+    geos: List[Tuple[Mesh, np.ndarray, Mesh, np.ndarray, bool]] = []
     out: List[ServeRequest] = []
     t = 0.0
     c = cells_per_patch
     for _ in range(n_requests):
         t += float(rng.exponential(1.0 / rate))
         if geos and rng.uniform() < reuse:
-            gi = int(rng.integers(0, len(geos)))
+            gi = len(geos) - 1 - int(rng.integers(0, min(3, len(geos))))
         else:
             n_sq = int(rng.integers(1, 7))
             layout = str(rng.choice(["book", "chain", "tree"]))
@@ -609,13 +610,13 @@ def serving_stream(seed: int, n_requests: int, rate: float, n_range: Tuple[int, 
             m_side = max(2, int(round(math.sqrt(target / n_sq) / c)))
             mesh, _ = random_extruded(rng, n_sq, layout, c * m_side)
             cm, par = coarse_mesh(mesh, c)
-            geos.append((mesh, grid_patches(mesh, c), cm, par))
+            geos.append((mesh, grid_patches(mesh, c), cm, par, bool(rng.integers(0, 2))))
             gi = len(geos) - 1
-        mesh, patches, cm, par = geos[gi]
+        mesh, patches, cm, par, mixed = geos[gi]
         k = int(rng.integers(k_range[0], k_range[1] + 1))
         g = rng.standard_normal((k, 3))
         g /= np.linalg.norm(g, axis=1, keepdims=True)
-        out.append(ServeRequest(t, gi, mesh, patches, cm, par, g, bool(rng.integers(0, 2))))
+        out.append(ServeRequest(t, gi, mesh, patches, cm, par, g, mixed))
     return out
 
 

@@ -14,8 +14,8 @@ panels at h = 1/96 and at h = 1/192) once per candidate and keeps the fastest va
   symv_blocks_fp64  super-block edge of the symmetric product with the FP64 matrix (2, 4, 8) and
   symv_blocks_fp32  with the FP32 copy (4, 8, 16): mean time of device-resident 16-column products
   panel_fraction    share of free memory for pair-matrix panels (large class only: the only one
-                    assembled in panels): device time of the far, near and contraction passes
-                    plus the host analysis, after one assembly of the same panel size
+                    assembled in panels): the assembly call to the end of its device work, after
+                    one assembly of the same panel size (first touches of its buffers)
   check_every       PCG iterations between host checks: the preconditioned 16-column solve; a
                     value whose solve does not converge is not taken
 
@@ -51,7 +51,7 @@ CLASSES = {
 SEPARATIONS = (1.1, 1.2, 1.35, 1.5, 2.0)
 SYMV_PAIRS = ((2, 4), (4, 8), (8, 16))     # (FP64, FP32) super-block edges
 PANEL_FRACTIONS = (0.45, 0.6, 0.75)
-CHECKS = (2, 4, 8)
+CHECKS = (1, 2, 4, 8)
 
 
 def log(*a):
@@ -125,13 +125,12 @@ def tune_class(ctx, name, reps=2):
             times = []
             ctx.release_cached()   # panel buffers of another size are not reused: the first run touches
             for r in range(reps + 1):
-                p, _ = _problem(ctx, w, mixed, dict(entry, panel_fraction=pf))
-                i = p.info
+                p, t = _problem(ctx, w, mixed, dict(entry, panel_fraction=pf))
                 if r > 0:
-                    times.append(i["t_far_s"] + i["t_near_s"] + i["t_contract_s"] + i["t_host_s"])
-                npan = i["n_pair_panels"]
+                    times.append(t)
+                npan = p.info["n_pair_panels"]
                 p.close()
-            meas["panel_fraction"][str(pf)] = {"t_device_s": min(times), "panels": int(npan)}
+            meas["panel_fraction"][str(pf)] = {"t_assemble_s": min(times), "panels": int(npan)}
             log("tune %s: panel fraction %.2f -> %.3f s (%d panels)" % (name, pf, min(times), npan))
             if t_pf is None or min(times) < t_pf:
                 best_pf, t_pf = pf, min(times)
@@ -188,8 +187,8 @@ def summary_md(table):
             out.append("* 16-column product, FP32 copy: " + ", ".join("%s blocks: %.3f ms" % (k, v * 1e3)
                                                                         for k, v in m["symv_blocks_fp32"].items()))
         if m["panel_fraction"]:
-            out.append("* panelled assembly (far + near + contraction device time and host analysis): " +
-                       ", ".join("%s: %.3f s (%d panels)" % (k, v["t_device_s"], v["panels"]) for k, v in m["panel_fraction"].items()))
+            out.append("* panelled assembly (call to the end of its device work): " +
+                       ", ".join("%s: %.3f s (%d panels)" % (k, v["t_assemble_s"], v["panels"]) for k, v in m["panel_fraction"].items()))
         out.append("* preconditioned 16-column solve: " + ", ".join(
             "every %s: %.2f ms, %d iterations%s" % (k, v["t_solve_s"] * 1e3, v["iters"], "" if v["converged"] else " (not converged)")
             for k, v in m["check_every"].items()))

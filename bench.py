@@ -567,7 +567,10 @@ def serving_leg(lib, meshes, ctx, n_requests, load, seed=0, max_inflight=4):
     Capacity is measured first by submitting the whole stream at once; the timed replay then
     scales the seeded arrival times to `load` x capacity.  Latency is submit -> completion as the
     server measures it; solves/s counts right-hand sides within rel.err 1e-8 of an FP64 solve of
-    the same request (computed after the stream, not timed)."""
+    the same request (computed after the stream, not timed).  Each latency splits into the wait
+    before the request's columns start in a block PCG (queueing, plus assembly and set-up of a
+    geometry that was not resident) and the solve after it."""
+    ctx.release_cached()   # the server starts from an empty buffer pool, not the previous legs' one
     reqs = meshes.serving_stream(seed, n_requests, rate=1.0)    # arrival times for rate 1/s
     res_b, t_burst, _ = _replay(lib, reqs, ctx, 0.0, max_inflight)
     for i, res in enumerate(res_b):
@@ -598,7 +601,9 @@ def serving_leg(lib, meshes, ctx, n_requests, load, seed=0, max_inflight=4):
         M.close()
         p.close()
     lat = [res[1][0]["t_total_s"] for res in results]
+    wait = [res[1][0]["t_start_s"] for res in results]
     n_dofs = [int(res[0].shape[1]) for res in results]
+    slowest = sorted(range(len(reqs)), key=lambda i: -lat[i])[:3]
     return {
         "requests": len(reqs), "failed_requests": len(failed),
         "direct_launch_requests": sum(1 for res in results if res[2] >= 0 and res[1][0]["graph"] == 0),
@@ -607,6 +612,11 @@ def serving_leg(lib, meshes, ctx, n_requests, load, seed=0, max_inflight=4):
         "max_inflight": max_inflight,
         "solves_per_s": solved / t_run,
         "latency_s": {"p50": percentile(lat, 0.5), "p99": percentile(lat, 0.99)},
+        "start_wait_s": {"p50": percentile(wait, 0.5), "p99": percentile(wait, 0.99)},
+        "solve_after_start_s": {"p50": percentile([a - b for a, b in zip(lat, wait)], 0.5),
+                                "p99": percentile([a - b for a, b in zip(lat, wait)], 0.99)},
+        "slowest": [{"request": i, "n_dofs": n_dofs[i], "k": int(reqs[i].g.shape[0]), "mixed": bool(reqs[i].mixed),
+                     "latency_s": lat[i], "start_wait_s": wait[i]} for i in slowest],
         "n_dofs_range": [min(n_dofs), max(n_dofs)],
         "mixed_requests": int(sum(r.mixed for r in reqs)),
         "server": stats,

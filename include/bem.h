@@ -118,7 +118,10 @@ typedef struct {
                               * call elsewhere in the process; same kernels, same results) */
     double relres;           /* final ||L - W x|| / ||L|| with the FP64 matrix */
     double est_cond;         /* Lanczos estimate of kappa(M W) from the (P)CG coefficients */
-    double t_total_s;        /* wall time of the whole call */
+    double t_total_s;        /* wall time of the whole call; served requests: submit to completion */
+    double t_start_s;        /* served requests: submit to the start of the request's columns in a
+                              * block PCG (queueing, plus assembly and set-up of a geometry that was
+                              * not resident); 0 for bem_pcg_solve */
 } bem_solve_info;
 
 /* ---- context ------------------------------------------------------------------------------ */

@@ -43,13 +43,14 @@ struct Request {
     double tol = 1e-10;
     int64_t N = 0, nt = 0;
     int64_t resident_bytes = 0, transient_bytes = 0;
-    Clock::time_point t_submit, t_done;
+    Clock::time_point t_submit, t_start, t_done;
     bool done = false;
     int rc = BEM_OK;
     std::string err;              // message of a failed request, handed to the polling thread
     std::vector<double> phi;
     std::vector<bem_solve_info> info;
     int remaining = 0;            // columns still running in a batch
+    bool started = false;   // its columns entered a block PCG (t_start is set)
 };
 
 // a block PCG of one geometry and precision that takes new requests while it runs
@@ -187,9 +188,11 @@ void worker_main(bem_server* s) {
             if (rc < 0) r->rc = rc;
             if (r->rc < 0) r->err = err.empty() ? "request failed" : err;
             const double lat = std::chrono::duration<double>(r->t_done - r->t_submit).count();
+            const double wait = r->started ? std::chrono::duration<double>(r->t_start - r->t_submit).count() : lat;
             if (r->info.size() != size_t(r->k)) r->info.assign(size_t(r->k), bem_solve_info{});
             for (auto& in : r->info) {
                 in.t_total_s = lat;
+                in.t_start_s = wait;
                 if (r->rc < 0 && in.status == BEM_OK && in.iters == 0) in.status = r->rc;
             }
             s->stats.completed += 1;
@@ -242,6 +245,8 @@ void worker_main(bem_server* s) {
                     r->phi.assign(size_t(N) * r->k, 0.0);
                     r->info.assign(size_t(r->k), bem_solve_info{});
                     r->remaining = r->k;
+                    r->t_start = Clock::now();
+                    r->started = true;
                     for (int col = 0; col < r->k; ++col) {
                         const int slot = free_slots[fi++];
                         owner[size_t(slot)] = {r, col};
@@ -285,7 +290,7 @@ void worker_main(bem_server* s) {
             };
             std::lock_guard<std::mutex> call(prob->call_mu);
             (void)hipGetLastError();   // an error left by another thread's call is not this batch's
-            pcg_serve(prob, entry->precond, precision == BEM_FP32_REFINE, nslots, 2000, 4, hooks);
+            pcg_serve(prob, entry->precond, precision == BEM_FP32_REFINE, nslots, 2000, prob->tune.check_every, hooks);
         } catch (const Failure& f) {
             rc = f.code;      // BEM_OK: the batch ended early, every request handed back
             err = f.msg;

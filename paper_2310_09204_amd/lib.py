@@ -82,7 +82,8 @@ class SolveOpts(ctypes.Structure):
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("outer_iters", ctypes.c_int), ("status", ctypes.c_int),
-                ("graph", ctypes.c_int), ("relres", ctypes.c_double), ("est_cond", ctypes.c_double), ("t_total_s", ctypes.c_double)]
+                ("graph", ctypes.c_int), ("relres", ctypes.c_double), ("est_cond", ctypes.c_double), ("t_total_s", ctypes.c_double),
+                ("t_start_s", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -57,7 +57,7 @@ def test_mix_equals_solo(ctx):
     for r, (phi_solo, ref), (phi, info, rc), msg in zip(reqs, alone, results, messages):
         assert rc == 0, msg
         assert phi.shape == phi_solo.shape
-        assert all(i["t_total_s"] > 0 for i in info)
+        assert all(i["t_total_s"] > 0 and 0 < i["t_start_s"] <= i["t_total_s"] for i in info)
         if r.mixed:
             assert relerr(phi, ref) < 1e-8
         else:

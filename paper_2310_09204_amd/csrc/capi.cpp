@@ -611,9 +611,11 @@ int bem_problem_copy_matrix(const bem_problem* p, int64_t row0, int64_t nrows, d
     if (row0 < 0 || nrows < 0 || row0 + nrows > p->N) fail(BEM_E_INVALID_ARG, "row range outside the matrix");
     set_device(p->ctx);
     if (nrows == 0) return BEM_OK;
-    HIP_CHECK(hipStreamSynchronize(p->stream));   // the contraction may still be writing W
-    HIP_CHECK(hipMemcpy2D(out, sizeof(double) * p->N, p->W64.as<double>() + row0 * p->ldw, sizeof(double) * p->ldw,
-                          sizeof(double) * p->N, size_t(nrows), hipMemcpyDeviceToHost));
+    // stream-ordered behind the contraction that may still be writing W (no null-stream copy: it
+    // could wait on work of other threads' streams)
+    HIP_CHECK(hipMemcpy2DAsync(out, sizeof(double) * p->N, p->W64.as<double>() + row0 * p->ldw, sizeof(double) * p->ldw,
+                               sizeof(double) * p->N, size_t(nrows), hipMemcpyDeviceToHost, p->stream));
+    HIP_CHECK(hipStreamSynchronize(p->stream));
     return BEM_OK;
     BEM_CATCH
 }
@@ -622,11 +624,13 @@ int bem_problem_copy_rows(const bem_problem* p, const int64_t* rows, int64_t nro
     BEM_TRY
     if (!p || (!rows && nrows) || (!out && nrows)) fail(BEM_E_INVALID_ARG, "NULL argument");
     set_device(p->ctx);
-    HIP_CHECK(hipStreamSynchronize(p->stream));   // the contraction may still be writing W
-    for (int64_t i = 0; i < nrows; ++i) {
+    for (int64_t i = 0; i < nrows; ++i)
         if (rows[i] < 0 || rows[i] >= p->N) fail(BEM_E_INVALID_ARG, "row index out of range");
-        HIP_CHECK(hipMemcpy(out + i * p->N, p->W64.as<double>() + rows[i] * p->ldw, sizeof(double) * p->N, hipMemcpyDeviceToHost));
-    }
+    // stream-ordered behind the contraction that may still be writing W
+    for (int64_t i = 0; i < nrows; ++i)
+        HIP_CHECK(hipMemcpyAsync(out + i * p->N, p->W64.as<double>() + rows[i] * p->ldw, sizeof(double) * p->N,
+                                 hipMemcpyDeviceToHost, p->stream));
+    HIP_CHECK(hipStreamSynchronize(p->stream));
     return BEM_OK;
     BEM_CATCH
 }
@@ -636,14 +640,15 @@ int bem_problem_pair_integrals(const bem_problem* p, const int32_t* pairs, int64
     if (!p || (!pairs && npairs) || (!out && npairs)) fail(BEM_E_INVALID_ARG, "NULL argument");
     if (!p->has_pairs || !p->I.ptr) fail(BEM_E_INVALID_ARG, "assemble with keep_pair_matrix = 1");
     set_device(p->ctx);
-    HIP_CHECK(hipStreamSynchronize(p->stream));
     const int64_t nt = p->topo.nt;
-    std::vector<double> row(nt);
     for (int64_t i = 0; i < npairs; ++i) {
         const int64_t a = pairs[2 * i], b = pairs[2 * i + 1];
         if (a < 0 || a >= nt || b < 0 || b >= nt) fail(BEM_E_INVALID_ARG, "pair index out of range");
-        HIP_CHECK(hipMemcpy(out + i, p->I.as<double>() + a * p->ldI + b, sizeof(double), hipMemcpyDeviceToHost));
     }
+    for (int64_t i = 0; i < npairs; ++i)
+        HIP_CHECK(hipMemcpyAsync(out + i, p->I.as<double>() + pairs[2 * i] * p->ldI + pairs[2 * i + 1], sizeof(double),
+                                 hipMemcpyDeviceToHost, p->stream));
+    HIP_CHECK(hipStreamSynchronize(p->stream));
     return BEM_OK;
     BEM_CATCH
 }

@@ -862,13 +862,16 @@ PcgResult pcg_device(bem_problem* p, const bem_precond* M, bool mixed, const dou
     };
 
     // the captured iteration; an exception between begin and end of a capture still ends it, so
-    // the stream never stays in capture mode
+    // the stream never stays in capture mode.  The graph is destroyed under the capture mutex, like
+    // every other call that may wait on the device: destroying an executable graph can wait for its
+    // launches, which must not happen while another thread's capture is open.
     struct Graph {
         hipStream_t s;
         bool capturing = false;
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
         ~Graph() {
+            std::lock_guard<std::mutex> lk(capture_mutex());
             if (capturing) {
                 hipGraph_t g = nullptr;
                 if (hipStreamEndCapture(s, &g) == hipSuccess && g) (void)hipGraphDestroy(g);

@@ -101,7 +101,8 @@ typedef struct {
     int use_precond;         /* 0: plain CG even if a preconditioner is passed */
     bem_precision precision; /* BEM_FP32_REFINE: FP32 matrix/factors inside FP64 refinement */
     double refresh_factor;   /* mixed precision: replace the recurrence residual by the FP64 residual
-                              * b - W x each time it has fallen by this factor (default 1e-3) */
+                              * b - W x each time it has fallen by this factor; 0 (or outside (0, 1)):
+                              * the default 2.5e-4, about the square root of FP32's unit roundoff */
     int check_every;         /* iterations between host convergence checks (default 4) */
     int use_graph;           /* 1: replay one captured iteration with hipGraphLaunch */
     const double* x0;        /* NULL: x0 = 0; else host memory holding k x N start vectors

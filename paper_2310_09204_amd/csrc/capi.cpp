@@ -274,7 +274,7 @@ bem_solve_opts default_solve_opts() {
     o.max_iter = 2000;
     o.use_precond = 1;
     o.precision = BEM_FP64;
-    o.refresh_factor = 1e-3;
+    o.refresh_factor = 0.0;   // the library's default
     o.check_every = 0;   // the problem's tuned value
     o.use_graph = 1;
     return o;

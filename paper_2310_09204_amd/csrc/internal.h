@@ -253,6 +253,11 @@ hipStream_t acquire_stream(bem_ctx* c);
 // gives back a stream with no queued work (the caller has synchronised it)
 void release_stream(bem_ctx* c, hipStream_t s);
 
+// Default refresh factor of the mixed-precision PCG's residual replacement: about the square root
+// of the FP32 unit roundoff (2^-24), so that between two replacements the recurrence residual falls
+// no further than the FP32 products' rounding lets it follow the true residual.
+constexpr double kRefreshDefault = 2.5e-4;
+
 // dense products (solver.hip); x, y column-major [k][N] with leading dimension ldx
 void matvec_setup(bem_problem* p, hipStream_t s);   // after W is allocated (ldw set)
 // gate != nullptr: a device word; the product's kernels do nothing while it is 0 (y keeps its values)

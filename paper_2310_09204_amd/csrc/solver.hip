@@ -1099,7 +1099,7 @@ void solve_device(bem_problem* p, const bem_precond* M, const double* b, double*
         if (!p->W32.ptr) fail(BEM_E_INVALID_ARG, "mixed precision needs a problem assembled with BEM_FP32_REFINE");
         if (use_m && !M->inv32.ptr) fail(BEM_E_INVALID_ARG, "mixed precision needs a preconditioner with factor_fp32 = 1");
         std::vector<double> tol(k, o.tol);
-        const double refresh = (o.refresh_factor > 0 && o.refresh_factor < 1) ? o.refresh_factor : 1e-3;
+        const double refresh = (o.refresh_factor > 0 && o.refresh_factor < 1) ? o.refresh_factor : kRefreshDefault;
         PcgResult r = pcg_device(p, use_m ? M : nullptr, true, b, x, x_nonzero, k, ld, tol, o.max_iter, check, o.use_graph != 0, true,
                                  refresh);
         graphed = r.graphed;
@@ -1156,7 +1156,7 @@ void pcg_serve(bem_problem* p, const bem_precond* M, bool mixed, int slots, int 
     hipLaunchKernelGGL(k_fill, dim3(256), dim3(256), 0, s, x.as<double>(), 0.0, ld * slots);
     HIP_CHECK(hipGetLastError());
     std::vector<double> tol(size_t(slots), 1.0);   // every slot starts inactive (b = 0)
-    pcg_device(p, M, mixed, b.as<double>(), x.as<double>(), false, slots, ld, tol, max_iter, check_every, true, false, 1e-3,
+    pcg_device(p, M, mixed, b.as<double>(), x.as<double>(), false, slots, ld, tol, max_iter, check_every, true, false, kRefreshDefault,
                &hooks);
 }
 

@@ -418,7 +418,7 @@ class Problem:
         return out
 
     def solve(self, g=None, rhs=None, precond=None, tol=1e-10, max_iter=2000, use_precond=True,
-              precision=FP64, refresh_factor=1e-3, check_every=0, use_graph=True, raise_on_error=True,
+              precision=FP64, refresh_factor=0.0, check_every=0, use_graph=True, raise_on_error=True,
               device_out=None, x0=None):
         """Returns (phi[k][N], [info dict per column], status code).  With device_out (the address
         of k x N doubles in device memory) and g, bem_pcg_solve_dev: phi stays there and None is

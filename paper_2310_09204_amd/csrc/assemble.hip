@@ -28,6 +28,7 @@
 #include <cstdlib>
 #include <functional>
 #include <memory>
+#include <thread>
 
 #include "internal.h"
 
@@ -1111,20 +1112,6 @@ PanelTimes assemble_panels(bem_problem* p, const MeshTopo& m, const NearList& ne
         const int64_t ldP = (ncol + 7) / 8 * 8;
         P->rowmap.assign(size_t(nt), -1);
         for (int64_t r = 0; r < nrows; ++r) P->rowmap[P->rows[r]] = int32_t(r);
-        // near pairs with a position in this panel
-        for (size_t i = 0; i < near.t1.size(); ++i) {
-            const int ty = near.type[i];
-            const int32_t a = near.t1[i], b = near.t2[i];
-            int64_t g1 = -1, g2 = -1;
-            if (P->rowmap[a] >= 0 && b >= tmin) g1 = int64_t(P->rowmap[a]) * ldP + (b - tmin);
-            if (a != b && P->rowmap[b] >= 0 && a >= tmin) g2 = int64_t(P->rowmap[b]) * ldP + (a - tmin);
-            if (g1 < 0 && g2 < 0) continue;
-            P->na[ty].push_back(a);
-            P->nb[ty].push_back(b);
-            P->nv[ty].insert(P->nv[ty].end(), &near.verts[5 * i], &near.verts[5 * i] + 5);
-            P->tgt[ty].push_back(g1);
-            P->tgt[ty].push_back(g2);
-        }
         // far tiles: each 64-row tile from the first column any of its rows is read at (the rest of
         // the panel's diagonal band, below it, is never read)
         for (int64_t rb = 0; rb < (nrows + kTile - 1) / kTile; ++rb) {
@@ -1142,6 +1129,20 @@ PanelTimes assemble_panels(bem_problem* p, const MeshTopo& m, const NearList& ne
                            d_rows.as<int32_t>(), nrows, tmin, ldP, d_ft.as<int2>(), nft, p->tune.far_separation, Ip.as<double>());
         HIP_CHECK(hipGetLastError());
         P->ef->stop();
+        // near pairs with a position in this panel (filtered on the host while the far pass runs)
+        for (size_t i = 0; i < near.t1.size(); ++i) {
+            const int ty = near.type[i];
+            const int32_t a = near.t1[i], b = near.t2[i];
+            int64_t g1 = -1, g2 = -1;
+            if (P->rowmap[a] >= 0 && b >= tmin) g1 = int64_t(P->rowmap[a]) * ldP + (b - tmin);
+            if (a != b && P->rowmap[b] >= 0 && a >= tmin) g2 = int64_t(P->rowmap[b]) * ldP + (a - tmin);
+            if (g1 < 0 && g2 < 0) continue;
+            P->na[ty].push_back(a);
+            P->nb[ty].push_back(b);
+            P->nv[ty].insert(P->nv[ty].end(), &near.verts[5 * i], &near.verts[5 * i] + 5);
+            P->tgt[ty].push_back(g1);
+            P->tgt[ty].push_back(g2);
+        }
         DeviceBuffer dv[4], da[4], dbb[4], dt[4];
         for (int ty = 1; ty <= 3; ++ty) {
             if (P->na[ty].empty()) continue;
@@ -1304,14 +1305,31 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
     std::vector<double> gx, gw;
     try {
         analyse(near);
-        for (size_t i = 0; i < near.t1.size(); ++i) {
-            const int ty = near.type[i];
-            na_[ty].push_back(near.t1[i]);
-            nb_[ty].push_back(near.t2[i]);
-            nv_[ty].insert(nv_[ty].end(), &near.verts[5 * i], &near.verts[5 * i] + 5);
+        // the near pairs by kind for the one-shot kernels (panels filter the list themselves), on a
+        // thread of its own beside the contraction plan
+        std::thread split;
+        if (!paneled)
+            split = std::thread([&]() {
+                for (int ty = 1; ty <= 3; ++ty) {
+                    na_[ty].reserve(size_t(near.count[ty]));
+                    nb_[ty].reserve(size_t(near.count[ty]));
+                    nv_[ty].reserve(size_t(5 * near.count[ty]));
+                }
+                for (size_t i = 0; i < near.t1.size(); ++i) {
+                    const int ty = near.type[i];
+                    na_[ty].push_back(near.t1[i]);
+                    nb_[ty].push_back(near.t2[i]);
+                    nv_[ty].insert(nv_[ty].end(), &near.verts[5 * i], &near.verts[5 * i] + 5);
+                }
+            });
+        try {
+            if (m.N > 0) plan = contract_plan(m);
+            gauss_legendre01(p->near_order, gx, gw);
+        } catch (...) {
+            if (split.joinable()) split.join();
+            throw;
         }
-        if (m.N > 0) plan = contract_plan(m);
-        gauss_legendre01(p->near_order, gx, gw);
+        if (split.joinable()) split.join();
     } catch (...) {
         (void)hipStreamSynchronize(s);
         throw;

@@ -71,29 +71,51 @@ void analyze_mesh(const double* Vin, int64_t nv, const int32_t* Tin, int64_t nt,
     const auto& V = m.V;
     const auto& T = m.T;
 
-    for (int64_t t = 0; t < nt; ++t) {
-        for (int a = 0; a < 3; ++a) {
-            int32_t v = T[3 * t + a];
-            if (v < 0 || v >= nv) fail(BEM_E_INVALID_ARG, "triangle " + std::to_string(t) + " has a vertex index out of range");
-            if (!std::isfinite(V[3 * v]) || !std::isfinite(V[3 * v + 1]) || !std::isfinite(V[3 * v + 2]))
-                fail(BEM_E_INVALID_ARG, "non-finite vertex coordinate");
-        }
-        if (T[3 * t] == T[3 * t + 1] || T[3 * t + 1] == T[3 * t + 2] || T[3 * t] == T[3 * t + 2])
-            fail(BEM_E_DEGENERATE, "triangle " + std::to_string(t) + " repeats a vertex");
+    // indices and coordinates, then element geometry, on threads; the error reported is the one of
+    // the first failing triangle, as in a sequential pass
+    m.normal.resize(3 * nt);
+    m.area.resize(nt);
+    {
+        FirstFailure bad;
+        parallel_for(nt, [&](int64_t tb, int64_t te) {
+            for (int64_t t = tb; t < te; ++t) {
+                try {
+                    for (int a = 0; a < 3; ++a) {
+                        int32_t v = T[3 * t + a];
+                        if (v < 0 || v >= nv) fail(BEM_E_INVALID_ARG, "triangle " + std::to_string(t) + " has a vertex index out of range");
+                        if (!std::isfinite(V[3 * v]) || !std::isfinite(V[3 * v + 1]) || !std::isfinite(V[3 * v + 2]))
+                            fail(BEM_E_INVALID_ARG, "non-finite vertex coordinate");
+                    }
+                    if (T[3 * t] == T[3 * t + 1] || T[3 * t + 1] == T[3 * t + 2] || T[3 * t] == T[3 * t + 2])
+                        fail(BEM_E_DEGENERATE, "triangle " + std::to_string(t) + " repeats a vertex");
+                } catch (const Failure& f) {
+                    bad.record(t, f);
+                    return;
+                }
+            }
+        });
+        bad.rethrow();
     }
 
     // ---- element geometry --------------------------------------------------------------------
-    m.normal.resize(3 * nt);
-    m.area.resize(nt);
-    for (int64_t t = 0; t < nt; ++t) {
-        Vec3 x0 = at(V, T[3 * t]), x1 = at(V, T[3 * t + 1]), x2 = at(V, T[3 * t + 2]);
-        Vec3 e1 = minus(x1, x0), e2 = minus(x2, x0), e3 = minus(x2, x1);
-        Vec3 c = cross3(e1, e2);
-        double tw = norm3(c);
-        double scale = std::max({dot3(e1, e1), dot3(e2, e2), dot3(e3, e3)});
-        if (!(tw > 1e-12 * scale)) fail(BEM_E_DEGENERATE, "triangle " + std::to_string(t) + " has zero area");
-        for (int k = 0; k < 3; ++k) m.normal[3 * t + k] = c[k] / tw;
-        m.area[t] = 0.5 * tw;
+    {
+        FirstFailure bad;
+        parallel_for(nt, [&](int64_t tb, int64_t te) {
+            for (int64_t t = tb; t < te; ++t) {
+                Vec3 x0 = at(V, T[3 * t]), x1 = at(V, T[3 * t + 1]), x2 = at(V, T[3 * t + 2]);
+                Vec3 e1 = minus(x1, x0), e2 = minus(x2, x0), e3 = minus(x2, x1);
+                Vec3 c = cross3(e1, e2);
+                double tw = norm3(c);
+                double scale = std::max({dot3(e1, e1), dot3(e2, e2), dot3(e3, e3)});
+                if (!(tw > 1e-12 * scale)) {
+                    bad.record(t, Failure{BEM_E_DEGENERATE, "triangle " + std::to_string(t) + " has zero area"});
+                    return;
+                }
+                for (int k = 0; k < 3; ++k) m.normal[3 * t + k] = c[k] / tw;
+                m.area[t] = 0.5 * tw;
+            }
+        });
+        bad.rethrow();
     }
 
     // ---- repeated vertices (by coordinates) ------------------------------------------------------
@@ -102,11 +124,30 @@ void analyze_mesh(const double* Vin, int64_t nv, const int32_t* Tin, int64_t nt,
         for (int64_t i = 0; i < 3 * nt; ++i) used[T[i]] = 1;
         std::vector<int64_t> order;
         for (int64_t v = 0; v < nv; ++v) if (used[v]) order.push_back(v);
-        std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+        auto less = [&](int64_t a, int64_t b) {
             for (int k = 0; k < 3; ++k)
                 if (V[3 * a + k] != V[3 * b + k]) return V[3 * a + k] < V[3 * b + k];
             return a < b;
-        });
+        };
+        // (coordinates, index) is a strict total order, so sorting chunks on threads and merging
+        // them gives the one sorted order
+        const int64_t n = int64_t(order.size());
+        const int64_t nch = std::max<int64_t>(1, std::min<int64_t>(8, n / 16384));
+        std::vector<int64_t> cut(nch + 1);
+        for (int64_t c = 0; c <= nch; ++c) cut[c] = n * c / nch;
+        parallel_for(nch, [&](int64_t cb, int64_t ce) {
+            for (int64_t c = cb; c < ce; ++c) std::sort(order.begin() + cut[c], order.begin() + cut[c + 1], less);
+        }, 1);
+        for (int64_t w = 1; w < nch; w *= 2) {
+            std::vector<std::thread> th;
+            for (int64_t c = 0; c + w < nch; c += 2 * w) {
+                const int64_t lo = cut[c], mid = cut[c + w], hi = cut[std::min(nch, c + 2 * w)];
+                th.emplace_back([&order, &less, lo, mid, hi] {
+                    std::inplace_merge(order.begin() + lo, order.begin() + mid, order.begin() + hi, less);
+                });
+            }
+            for (auto& t : th) t.join();
+        }
         for (size_t i = 1; i < order.size(); ++i) {
             int64_t a = order[i - 1], b = order[i];
             if (V[3 * a] == V[3 * b] && V[3 * a + 1] == V[3 * b + 1] && V[3 * a + 2] == V[3 * b + 2])
@@ -500,13 +541,27 @@ void build_near_list(const MeshTopo& m, NearList& out) {
             }
         }
     });
-    for (auto& o : parts) {
-        out.t1.insert(out.t1.end(), o.t1.begin(), o.t1.end());
-        out.t2.insert(out.t2.end(), o.t2.begin(), o.t2.end());
-        out.type.insert(out.type.end(), o.type.begin(), o.type.end());
-        out.verts.insert(out.verts.end(), o.verts.begin(), o.verts.end());
-        for (int k = 0; k < 4; ++k) out.count[k] += o.count[k];
+    // join in chunk order: offsets first, then the copies in parallel
+    std::vector<size_t> off(parts.size() + 1, 0);
+    for (size_t c = 0; c < parts.size(); ++c) {
+        off[c + 1] = off[c] + parts[c].t1.size();
+        for (int k = 0; k < 4; ++k) out.count[k] += parts[c].count[k];
     }
+    const size_t total = off.back();
+    out.t1.resize(total);
+    out.t2.resize(total);
+    out.type.resize(total);
+    out.verts.resize(5 * total);
+    parallel_for(int64_t(parts.size()), [&](int64_t cb, int64_t ce) {
+        for (int64_t c = cb; c < ce; ++c) {
+            const NearList& o = parts[size_t(c)];
+            const size_t b = off[size_t(c)];
+            std::copy(o.t1.begin(), o.t1.end(), out.t1.begin() + b);
+            std::copy(o.t2.begin(), o.t2.end(), out.t2.begin() + b);
+            std::copy(o.type.begin(), o.type.end(), out.type.begin() + b);
+            std::copy(o.verts.begin(), o.verts.end(), out.verts.begin() + 5 * b);
+        }
+    }, 1);
 }
 
 // ---- quadrature tables ----------------------------------------------------------------------

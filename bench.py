@@ -75,9 +75,10 @@ def matvec_rates(N, size, t, key, ks):
             key + "_hbm_frac": b / t / 1e9 / PEAK_HBM_GBS}
 
 
-def load_traffic(kernel, workload):
+def load_traffic(kernel, workload, launches):
     """HBM bytes per launch from the committed rocprofv3 --pmc summary, if the kernel source is
-    unchanged since the counters were taken; else None."""
+    unchanged since the counters were taken and the step had the same number of launches (panels);
+    else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -85,6 +86,8 @@ def load_traffic(kernel, workload):
         d = json.load(open(path))
         e = d.get(kernel, {}).get(workload)
         if not e or e.get("source_hash") != far_kernel_source_hash():
+            return None
+        if int(e.get("launches_per_step", 1)) != int(launches):
             return None
         return float(e["bytes_per_launch"])
     except Exception:
@@ -406,7 +409,7 @@ def timed_workload(lib, meshes, ctx, name, k, steps, warmup, tol, mixed, extras=
             "kernel": far_kernel, "bound": "alu",
             "achieved": round(far_tflops, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
             "frac": round(far_tflops / PEAK_FP64_TFLOPS, 4),
-            "traffic": load_traffic(far_kernel, name),
+            "traffic": load_traffic(far_kernel, name, launches),
             "per_launch": "%d far pairs x %d evaluations x %.0f flops over %d launch(es)"
                           % (far_pairs, EVALS_PER_FAR_PAIR, FLOPS_PER_EVAL, launches),
             "launches": launches, "avg_launch_s": t_far / launches,

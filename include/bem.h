@@ -66,6 +66,11 @@ typedef struct {
     int64_t pair_panel_rows; /* 0: automatic; > 0: assemble through panels of the pair matrix with at
                               * most this many triangle rows (the automatic choice uses panels only
                               * when the whole N_T x N_T pair matrix does not fit next to W) */
+    int32_t keep_order;      /* 0 (default): the problem numbers vertices and triangles internally in
+                              * Morton order of their positions (compact blocks of consecutive dofs
+                              * for the contraction); 1: it keeps the caller's numbering.  Either way
+                              * every call takes and returns dof-, vertex- and triangle-indexed data
+                              * in the caller's numbering and canonical dof order. */
 } bem_assemble_opts;
 
 typedef struct {
@@ -219,8 +224,9 @@ int bem_matvec(const bem_problem* p, const double* x, int32_t k, int fp32, doubl
  * the product live in one static device array of 128 MiB per device (held from the library's
  * first use on that device until the process ends; its address is looked up in bem_ctx_create).
  * A product needs 16 N s + (N/64) (ceil(N/256 or N/512) + 1) 1024 s bytes of it (s = 8, or 4
- * with fp32 = 1, N rounded up to 64; super-blocks of 4 FP64 or 8 FP32 blocks): N up to 16,128
- * (FP64) or 32,256 (FP32); larger problems get BEM_E_INVALID_ARG and must use bem_matvec.  Runs on the problem's stream and returns when y is written.  Every call
+ * with fp32 = 1, N rounded up to 64; super-blocks of 4 FP64 or 8 FP32 blocks; with a renumbered
+ * problem also x and y in its internal dof order): N up to 15,872 (FP64) or 31,232 (FP32) at
+ * k = 16, 16,064 / 32,128 at k = 1; larger products get BEM_E_INVALID_ARG and must use bem_matvec.  Runs on the problem's stream and returns when y is written.  Every call
  * on one device shares the array, which keeps the last call's contents: calls that overlap on
  * one device race (calls on one problem are serialised).  Errors: BEM_E_INVALID_ARG (NULL, k < 1,
  * fp32 without an FP32 matrix, scratch too small), BEM_E_DEVICE. */

@@ -86,6 +86,17 @@ __global__ void k_jump_vectors(const double* __restrict__ V, const int32_t* __re
     for (int k = 0; k < 3; ++k) J[3 * e + k] = s * (V[3 * int64_t(v1) + k] - V[3 * int64_t(v2) + k]);
 }
 
+// renumbered device copies of the mesh (see renumber_mesh_device)
+__global__ void k_renumber_mesh(const double* __restrict__ V, const int32_t* __restrict__ T, int64_t nv, int64_t nt,
+                                const int32_t* __restrict__ vert_user, const int32_t* __restrict__ vert_int,
+                                const int32_t* __restrict__ tri_user, double* __restrict__ Vout, int32_t* __restrict__ Tout) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < nv)
+        for (int c = 0; c < 3; ++c) Vout[3 * i + c] = V[3 * int64_t(vert_user[i]) + c];
+    if (i < nt)
+        for (int a = 0; a < 3; ++a) Tout[3 * i + a] = vert_int[T[3 * int64_t(tri_user[i]) + a]];
+}
+
 // ---------------------------------------------------------------------------------------------
 // Far field.  For the Gauss points x (row triangle) and y (column triangle, area-weight w), centred
 // on a point c with u = -2 (x - c), alpha = |x - c|^2 and v = y - c,
@@ -1204,6 +1215,14 @@ PanelTimes assemble_panels(bem_problem* p, const MeshTopo& m, const NearList& ne
 }
 
 }  // namespace
+
+void renumber_mesh_device(const double* dV, const int32_t* dT, int64_t nv, int64_t nt, const int32_t* d_vert_user,
+                          const int32_t* d_vert_int, const int32_t* d_tri_user, double* Vout, int32_t* Tout, hipStream_t s) {
+    const int64_t n = std::max(nv, nt);
+    hipLaunchKernelGGL(k_renumber_mesh, dim3(blocks_for(n, 256)), dim3(256), 0, s, dV, dT, nv, nt, d_vert_user, d_vert_int,
+                       d_tri_user, Vout, Tout);
+    HIP_CHECK(hipGetLastError());
+}
 
 void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_t* Tin, int64_t nt,
                      const std::function<void(NearList&)>& analyse, const double* dVin, const int32_t* dTin) {

@@ -280,6 +280,47 @@ bem_solve_opts default_solve_opts() {
     return o;
 }
 
+// k columns of N values between the caller's dof order and the problem's internal one, on the
+// problem's stream (src != dst)
+void dofs_to_internal(const bem_problem* p, const double* src, double* dst, int k) {
+    if (p->renumbered) permute_cols_device(src, p->N, dst, p->N, p->N, k, p->d_dof_user.as<int32_t>(), p->stream);
+    else HIP_CHECK(hipMemcpyAsync(dst, src, sizeof(double) * p->N * k, hipMemcpyDeviceToDevice, p->stream));
+}
+void dofs_to_user(const bem_problem* p, const double* src, double* dst, int k) {
+    if (p->renumbered) permute_cols_device(src, p->N, dst, p->N, p->N, k, p->d_dof_int.as<int32_t>(), p->stream);
+    else HIP_CHECK(hipMemcpyAsync(dst, src, sizeof(double) * p->N * k, hipMemcpyDeviceToDevice, p->stream));
+}
+// the same on host arrays
+void host_to_internal(const bem_problem* p, const double* src, double* dst, int64_t k) {
+    const int64_t N = p->N;
+    for (int64_t c = 0; c < k; ++c)
+        for (int64_t i = 0; i < N; ++i) dst[c * N + i] = p->renumbered ? src[c * N + p->dof_user[size_t(i)]] : src[c * N + i];
+}
+void host_to_user(const bem_problem* p, const double* src, double* dst, int64_t k) {
+    const int64_t N = p->N;
+    for (int64_t c = 0; c < k; ++c)
+        for (int64_t u = 0; u < N; ++u) dst[c * N + u] = p->renumbered ? src[c * N + p->dof_int[size_t(u)]] : src[c * N + u];
+}
+
+// rows of W with row and column indices in the caller's dof order, gathered on the device in
+// chunks of at most 256 MB (stream-ordered behind a contraction that may still be writing W)
+void copy_rows_user(const bem_problem* p, const int64_t* rows, int64_t nrows, double* out) {
+    const int64_t N = p->N;
+    if (N == 0 || nrows == 0) return;
+    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(nrows, (int64_t(256) << 20) / (8 * N)));
+    DeviceBuffer buf(sizeof(double) * chunk * N, p->stream), drows(sizeof(int32_t) * chunk, p->stream);
+    std::vector<int32_t> hr(static_cast<size_t>(chunk));
+    for (int64_t r0 = 0; r0 < nrows; r0 += chunk) {
+        const int64_t nr = std::min(chunk, nrows - r0);
+        for (int64_t i = 0; i < nr; ++i) hr[size_t(i)] = p->dof_int[size_t(rows[r0 + i])];
+        HIP_CHECK(hipMemcpyAsync(drows.ptr, hr.data(), sizeof(int32_t) * nr, hipMemcpyHostToDevice, p->stream));
+        gather_rows_device(p->W64.as<double>(), p->ldw, drows.as<int32_t>(), nr, p->d_dof_int.as<int32_t>(), N,
+                           buf.as<double>(), p->stream);
+        HIP_CHECK(hipMemcpyAsync(out + r0 * N, buf.ptr, sizeof(double) * nr * N, hipMemcpyDeviceToHost, p->stream));
+        HIP_CHECK(hipStreamSynchronize(p->stream));   // hr is refilled for the next chunk
+    }
+}
+
 int solve_common(bem_problem* p, const bem_precond* m, const double* d_b, int32_t k, const bem_solve_opts* opts,
                  double* phi_out, bem_solve_info* info, double* d_phi_out = nullptr) {
     bem_solve_opts o = opts ? *opts : default_solve_opts();
@@ -291,17 +332,29 @@ int solve_common(bem_problem* p, const bem_precond* m, const double* d_b, int32_
     if (o.x0)
         for (int64_t i = 0; i < N * k; ++i)
             if (!std::isfinite(o.x0[i])) fail(BEM_E_INVALID_ARG, "non-finite entry in x0");
+    std::vector<double> x0_int;
+    if (o.x0 && p->renumbered) {
+        x0_int.resize(size_t(N * k));
+        host_to_internal(p, o.x0, x0_int.data(), k);
+        o.x0 = x0_int.data();
+    }
     std::lock_guard<std::mutex> call(p->call_mu);
     std::vector<bem_solve_info> inf(k);
-    // the iterate lives in the caller's device buffer when one is given
+    // the iterate lives in the caller's device buffer when one is given (and the problem keeps the
+    // caller's order)
     DeviceBuffer x;
-    if (!d_phi_out) x = DeviceBuffer(sizeof(double) * std::max<int64_t>(1, N * k), p->stream);
-    double* dx = d_phi_out ? d_phi_out : x.as<double>();
+    const bool in_place = d_phi_out && !p->renumbered;
+    if (!in_place) x = DeviceBuffer(sizeof(double) * std::max<int64_t>(1, N * k), p->stream);
+    double* dx = in_place ? d_phi_out : x.as<double>();
     if (N > 0) solve_device(p, m, d_b, dx, k, o, inf.data());
     if (phi_out && !d_phi_out && N > 0) {
-        HIP_CHECK(hipMemcpyAsync(phi_out, x.ptr, sizeof(double) * N * k, hipMemcpyDeviceToHost, p->stream));
+        std::vector<double> tmp(p->renumbered ? size_t(N * k) : 0);
+        HIP_CHECK(hipMemcpyAsync(p->renumbered ? tmp.data() : phi_out, x.ptr, sizeof(double) * N * k, hipMemcpyDeviceToHost,
+                                 p->stream));
         HIP_CHECK(hipStreamSynchronize(p->stream));
+        if (p->renumbered) host_to_user(p, tmp.data(), phi_out, k);
     }
+    if (d_phi_out && !in_place && N > 0) dofs_to_user(p, dx, d_phi_out, k);
     if (d_phi_out) HIP_CHECK(hipStreamSynchronize(p->stream));   // the caller may read it on any stream
     int rc = BEM_OK;
     for (int c = 0; c < k; ++c) {
@@ -466,12 +519,68 @@ int bem_assemble_dev(bem_ctx* ctx, const double* vertices, const double* d_verti
     p->has_pairs = opts && opts->keep_pair_matrix;
     p->panel_rows = (opts && opts->pair_panel_rows > 0) ? opts->pair_panel_rows : 0;
     p->stream = acquire_stream(ctx);
+    // locality order of a valid mesh (an invalid one is analysed as given, which reports its error)
+    bool valid = vertices && triangles && nv > 0 && nt > 0 && nt <= (int64_t(1) << 30) && nv <= INT32_MAX;
+    for (int64_t i = 0; valid && i < 3 * nv; ++i) valid = std::isfinite(vertices[i]);
+    for (int64_t i = 0; valid && i < 3 * nt; ++i) valid = triangles[i] >= 0 && triangles[i] < nv;
+    std::vector<double> Vint;
+    std::vector<int32_t> Tint, vert_int;
+    DeviceBuffer dVint, dTint;
+    if (valid && !(opts && opts->keep_order)) {
+        locality_order(vertices, nv, triangles, nt, p->vert_user, p->tri_user);
+        vert_int.resize(size_t(nv));
+        p->tri_int.resize(size_t(nt));
+        for (int64_t i = 0; i < nv; ++i) vert_int[size_t(p->vert_user[size_t(i)])] = int32_t(i);
+        for (int64_t t = 0; t < nt; ++t) p->tri_int[size_t(p->tri_user[size_t(t)])] = int32_t(t);
+        Vint.resize(size_t(3 * nv));
+        Tint.resize(size_t(3 * nt));
+        for (int64_t i = 0; i < nv; ++i)
+            for (int c = 0; c < 3; ++c) Vint[size_t(3 * i + c)] = vertices[3 * int64_t(p->vert_user[size_t(i)]) + c];
+        for (int64_t t = 0; t < nt; ++t)
+            for (int a = 0; a < 3; ++a)
+                Tint[size_t(3 * t + a)] = vert_int[size_t(triangles[3 * int64_t(p->tri_user[size_t(t)]) + a])];
+        p->renumbered = true;
+    }
+    const double* Vp = p->renumbered ? Vint.data() : vertices;
+    const int32_t* Tp = p->renumbered ? Tint.data() : triangles;
+    const double* dVp = d_vertices;
+    const int32_t* dTp = d_triangles;
     try {
-        assemble_device(p.get(), vertices, nv, triangles, nt, [&](NearList& near) {
-            analyze_mesh(vertices, nv, triangles, nt, p->topo);
-            build_near_list(p->topo, near);
+        if (p->renumbered && d_vertices && d_triangles) {
+            // renumbered device copies from the caller's, on the device (only the index maps go up)
+            DeviceBuffer dvu = upload(p->vert_user, p->stream), dvi = upload(vert_int, p->stream), dtu = upload(p->tri_user, p->stream);
+            dVint = DeviceBuffer(sizeof(double) * 3 * nv, p->stream);
+            dTint = DeviceBuffer(sizeof(int32_t) * 3 * nt, p->stream);
+            renumber_mesh_device(d_vertices, d_triangles, nv, nt, dvu.as<int32_t>(), dvi.as<int32_t>(), dtu.as<int32_t>(),
+                                 dVint.as<double>(), dTint.as<int32_t>(), p->stream);
+            dVp = dVint.as<double>();
+            dTp = dTint.as<int32_t>();
+        } else if (p->renumbered) {
+            dVp = nullptr;
+            dTp = nullptr;
+        }
+        assemble_device(p.get(), Vp, nv, Tp, nt, [&](NearList& near) {
+            analyze_mesh(Vp, nv, Tp, nt, p->topo, p->renumbered ? p->tri_user.data() : nullptr,
+                         p->renumbered ? p->vert_user.data() : nullptr);
+            build_near_list(p->topo, near, p->renumbered ? p->tri_user.data() : nullptr);
             p->N = p->topo.N;
-        }, d_vertices, d_triangles);
+        }, dVp, dTp);
+        if (p->renumbered) {
+            // internal dof (vertex i, label j) is the caller's dof (vert_user[i], j): the labels agree
+            // because the stars listed their triangles in the caller's order
+            const MeshTopo& m = p->topo;
+            std::vector<int64_t> first_user(size_t(nv) + 1, 0);
+            for (int64_t u = 0; u < nv; ++u) first_user[size_t(u) + 1] = first_user[size_t(u)] + std::max(0, m.q[size_t(vert_int[size_t(u)])] - 1);
+            p->dof_user.resize(size_t(p->N));
+            p->dof_int.resize(size_t(p->N));
+            for (int64_t d = 0; d < p->N; ++d) {
+                const int64_t du = first_user[size_t(p->vert_user[size_t(m.dof_vertex[size_t(d)])])] + m.dof_sector[size_t(d)];
+                p->dof_user[size_t(d)] = int32_t(du);
+                p->dof_int[size_t(du)] = int32_t(d);
+            }
+            p->d_dof_user = upload(p->dof_user, p->stream);   // from the problem's own copies, which outlive the copy
+            p->d_dof_int = upload(p->dof_int, p->stream);
+        }
     } catch (...) {
         // device work already queued must end before its buffers go
         (void)hipStreamSynchronize(p->stream);
@@ -599,8 +708,12 @@ int bem_problem_get_info(const bem_problem* p, bem_problem_info* info) {
 int bem_problem_dofs(const bem_problem* p, int32_t* dof_vertex, int32_t* dof_sector) {
     BEM_TRY
     if (!p) fail(BEM_E_INVALID_ARG, "NULL problem");
-    if (dof_vertex && p->N) std::memcpy(dof_vertex, p->topo.dof_vertex.data(), sizeof(int32_t) * p->N);
-    if (dof_sector && p->N) std::memcpy(dof_sector, p->topo.dof_sector.data(), sizeof(int32_t) * p->N);
+    for (int64_t u = 0; u < p->N; ++u) {
+        const int64_t d = p->renumbered ? p->dof_int[size_t(u)] : u;
+        const int32_t v = p->topo.dof_vertex[size_t(d)];
+        if (dof_vertex) dof_vertex[u] = p->renumbered ? p->vert_user[size_t(v)] : v;
+        if (dof_sector) dof_sector[u] = p->topo.dof_sector[size_t(d)];
+    }
     return BEM_OK;
     BEM_CATCH
 }
@@ -611,6 +724,12 @@ int bem_problem_copy_matrix(const bem_problem* p, int64_t row0, int64_t nrows, d
     if (row0 < 0 || nrows < 0 || row0 + nrows > p->N) fail(BEM_E_INVALID_ARG, "row range outside the matrix");
     set_device(p->ctx);
     if (nrows == 0) return BEM_OK;
+    if (p->renumbered) {
+        std::vector<int64_t> rows(static_cast<size_t>(nrows));
+        for (int64_t i = 0; i < nrows; ++i) rows[size_t(i)] = row0 + i;
+        copy_rows_user(p, rows.data(), nrows, out);
+        return BEM_OK;
+    }
     // stream-ordered behind the contraction that may still be writing W (no null-stream copy: it
     // could wait on work of other threads' streams)
     HIP_CHECK(hipMemcpy2DAsync(out, sizeof(double) * p->N, p->W64.as<double>() + row0 * p->ldw, sizeof(double) * p->ldw,
@@ -626,6 +745,10 @@ int bem_problem_copy_rows(const bem_problem* p, const int64_t* rows, int64_t nro
     set_device(p->ctx);
     for (int64_t i = 0; i < nrows; ++i)
         if (rows[i] < 0 || rows[i] >= p->N) fail(BEM_E_INVALID_ARG, "row index out of range");
+    if (p->renumbered) {
+        copy_rows_user(p, rows, nrows, out);
+        return BEM_OK;
+    }
     // stream-ordered behind the contraction that may still be writing W
     for (int64_t i = 0; i < nrows; ++i)
         HIP_CHECK(hipMemcpyAsync(out + i * p->N, p->W64.as<double>() + rows[i] * p->ldw, sizeof(double) * p->N,
@@ -645,8 +768,9 @@ int bem_problem_pair_integrals(const bem_problem* p, const int32_t* pairs, int64
         const int64_t a = pairs[2 * i], b = pairs[2 * i + 1];
         if (a < 0 || a >= nt || b < 0 || b >= nt) fail(BEM_E_INVALID_ARG, "pair index out of range");
     }
+    auto tri = [&](int64_t t) { return p->renumbered ? int64_t(p->tri_int[size_t(t)]) : t; };
     for (int64_t i = 0; i < npairs; ++i)
-        HIP_CHECK(hipMemcpyAsync(out + i, p->I.as<double>() + pairs[2 * i] * p->ldI + pairs[2 * i + 1], sizeof(double),
+        HIP_CHECK(hipMemcpyAsync(out + i, p->I.as<double>() + tri(pairs[2 * i]) * p->ldI + tri(pairs[2 * i + 1]), sizeof(double),
                                  hipMemcpyDeviceToHost, p->stream));
     HIP_CHECK(hipStreamSynchronize(p->stream));
     return BEM_OK;
@@ -662,7 +786,9 @@ int bem_rhs(const bem_problem* p, const double* g, int32_t k, double* out) {
     DeviceBuffer dg(sizeof(double) * 3 * k, p->stream), dL(sizeof(double) * N * k, p->stream);
     HIP_CHECK(hipMemcpyAsync(dg.ptr, g, sizeof(double) * 3 * k, hipMemcpyHostToDevice, p->stream));
     rhs_device(p, dg.as<double>(), k, dL.as<double>(), p->stream);
-    HIP_CHECK(hipMemcpyAsync(out, dL.ptr, sizeof(double) * N * k, hipMemcpyDeviceToHost, p->stream));
+    DeviceBuffer dLu(sizeof(double) * N * k, p->stream);
+    dofs_to_user(p, dL.as<double>(), dLu.as<double>(), k);
+    HIP_CHECK(hipMemcpyAsync(out, dLu.ptr, sizeof(double) * N * k, hipMemcpyDeviceToHost, p->stream));
     HIP_CHECK(hipStreamSynchronize(p->stream));
     return BEM_OK;
     BEM_CATCH
@@ -676,9 +802,12 @@ int bem_matvec(const bem_problem* p, const double* x, int32_t k, int fp32, doubl
     if (N == 0) return BEM_OK;
     std::lock_guard<std::mutex> call(p->call_mu);
     DeviceBuffer dx(sizeof(double) * N * k, p->stream), dy(sizeof(double) * N * k, p->stream);
-    HIP_CHECK(hipMemcpyAsync(dx.ptr, x, sizeof(double) * N * k, hipMemcpyHostToDevice, p->stream));
+    DeviceBuffer du(sizeof(double) * N * k, p->stream);   // the caller's order
+    HIP_CHECK(hipMemcpyAsync(du.ptr, x, sizeof(double) * N * k, hipMemcpyHostToDevice, p->stream));
+    dofs_to_internal(p, du.as<double>(), dx.as<double>(), k);
     matvec_device(p, fp32 != 0, dx.as<double>(), N, k, dy.as<double>(), p->stream);
-    HIP_CHECK(hipMemcpyAsync(y, dy.ptr, sizeof(double) * N * k, hipMemcpyDeviceToHost, p->stream));
+    dofs_to_user(p, dy.as<double>(), du.as<double>(), k);
+    HIP_CHECK(hipMemcpyAsync(y, du.ptr, sizeof(double) * N * k, hipMemcpyDeviceToHost, p->stream));
     HIP_CHECK(hipStreamSynchronize(p->stream));
     return BEM_OK;
     BEM_CATCH
@@ -691,7 +820,7 @@ int bem_matvec_noalloc(const bem_problem* p, const double* d_x, int32_t k, int f
     const int64_t N = p->N;
     if (N == 0) return BEM_OK;
     if (fp32 && !p->W32.ptr) fail(BEM_E_INVALID_ARG, "problem has no FP32 matrix (assemble with BEM_FP32_REFINE)");
-    const size_t need = noalloc_matvec_bytes(p, fp32 != 0);
+    const size_t need = noalloc_matvec_bytes(p, fp32 != 0, k);
     if (need > kNoAllocScratchBytes)
         fail(BEM_E_INVALID_ARG, "bem_matvec_noalloc: this product needs " + std::to_string(need) +
                                     " bytes of scratch, more than the " + std::to_string(kNoAllocScratchBytes) +
@@ -710,10 +839,19 @@ int bem_jump_values(const bem_problem* p, const double* phi, double* jump_out) {
     set_device(p->ctx);
     const int64_t N = p->N, nt = p->topo.nt, corners = p->topo.dim == 2 ? 2 : 3;
     DeviceBuffer dp(sizeof(double) * std::max<int64_t>(1, N), p->stream), dj(sizeof(double) * nt * corners, p->stream);
-    if (N) HIP_CHECK(hipMemcpyAsync(dp.ptr, phi, sizeof(double) * N, hipMemcpyHostToDevice, p->stream));
+    DeviceBuffer du(sizeof(double) * std::max<int64_t>(1, N), p->stream);
+    if (N) {
+        HIP_CHECK(hipMemcpyAsync(du.ptr, phi, sizeof(double) * N, hipMemcpyHostToDevice, p->stream));
+        dofs_to_internal(p, du.as<double>(), dp.as<double>(), 1);
+    }
     jump_values_device(p, dp.as<double>(), dj.as<double>(), p->stream);
-    HIP_CHECK(hipMemcpyAsync(jump_out, dj.ptr, sizeof(double) * nt * corners, hipMemcpyDeviceToHost, p->stream));
+    std::vector<double> tmp(p->renumbered ? size_t(nt * corners) : 0);
+    HIP_CHECK(hipMemcpyAsync(p->renumbered ? tmp.data() : jump_out, dj.ptr, sizeof(double) * nt * corners, hipMemcpyDeviceToHost,
+                             p->stream));
     HIP_CHECK(hipStreamSynchronize(p->stream));
+    if (p->renumbered)   // per triangle of the caller's numbering (corners in the caller's order too)
+        for (int64_t t = 0; t < nt; ++t)
+            for (int64_t a = 0; a < corners; ++a) jump_out[t * corners + a] = tmp[size_t(p->tri_int[size_t(t)] * corners + a)];
     return BEM_OK;
     BEM_CATCH
 }
@@ -729,7 +867,11 @@ int bem_double_layer(bem_problem* p, const double* phi, int32_t k, const double*
     std::lock_guard<std::mutex> call(p->call_mu);
     DeviceBuffer dp(sizeof(double) * std::max<int64_t>(1, N * k), p->stream), dx(sizeof(double) * 3 * m, p->stream),
         du(sizeof(double) * k * m, p->stream);
-    if (N) HIP_CHECK(hipMemcpyAsync(dp.ptr, phi, sizeof(double) * N * k, hipMemcpyHostToDevice, p->stream));
+    DeviceBuffer dpu(sizeof(double) * std::max<int64_t>(1, N * k), p->stream);   // phi in the caller's order
+    if (N) {
+        HIP_CHECK(hipMemcpyAsync(dpu.ptr, phi, sizeof(double) * N * k, hipMemcpyHostToDevice, p->stream));
+        dofs_to_internal(p, dpu.as<double>(), dp.as<double>(), k);
+    }
     HIP_CHECK(hipMemcpyAsync(dx.ptr, targets, sizeof(double) * 3 * m, hipMemcpyHostToDevice, p->stream));
     double_layer_device(p, dp.as<double>(), k, dx.as<double>(), m, du.as<double>(), p->stream);
     HIP_CHECK(hipMemcpyAsync(u_out, du.ptr, sizeof(double) * k * m, hipMemcpyDeviceToHost, p->stream));
@@ -754,6 +896,21 @@ int bem_precond_setup(bem_problem* p, const int32_t* patch_of_triangle, const do
     m->wb_diag = opts ? opts->wirebasket == 1 : false;
     m->diag_shift = opts ? opts->diag_shift : 0.0;
     if (!std::isfinite(m->diag_shift)) fail(BEM_E_INVALID_ARG, "diag_shift is not finite");
+    // per-triangle inputs in the problem's triangle order
+    std::vector<int32_t> patch_int, coarse_int;
+    if (p->renumbered) {
+        const int64_t nt = p->topo.nt;
+        if (patch_of_triangle) {
+            patch_int.resize(size_t(nt));
+            for (int64_t t = 0; t < nt; ++t) patch_int[size_t(t)] = patch_of_triangle[p->tri_user[size_t(t)]];
+            patch_of_triangle = patch_int.data();
+        }
+        if (coarse_of_triangle) {
+            coarse_int.resize(size_t(nt));
+            for (int64_t t = 0; t < nt; ++t) coarse_int[size_t(t)] = coarse_of_triangle[p->tri_user[size_t(t)]];
+            coarse_of_triangle = coarse_int.data();
+        }
+    }
     std::lock_guard<std::mutex> call(p->call_mu);
     precond_setup_device(m.get(), patch_of_triangle, coarse_vertices, ncv, coarse_triangles, nct, coarse_of_triangle);
     *out = m.release();
@@ -812,9 +969,12 @@ int bem_precond_apply(const bem_precond* m, const double* r, int32_t k, double* 
     std::lock_guard<std::mutex> call(p->call_mu);
     DeviceBuffer dr(sizeof(double) * N * k, m->p->stream), dz(sizeof(double) * N * k, m->p->stream);
     DeviceBuffer scr(sizeof(double) * precond_scratch_size(m, std::min(k, 16)), m->p->stream);
-    HIP_CHECK(hipMemcpyAsync(dr.ptr, r, sizeof(double) * N * k, hipMemcpyHostToDevice, p->stream));
+    DeviceBuffer du(sizeof(double) * N * k, m->p->stream);
+    HIP_CHECK(hipMemcpyAsync(du.ptr, r, sizeof(double) * N * k, hipMemcpyHostToDevice, p->stream));
+    dofs_to_internal(p, du.as<double>(), dr.as<double>(), k);
     precond_apply_device(m, false, dr.as<double>(), N, k, dz.as<double>(), p->stream, scr.as<double>());
-    HIP_CHECK(hipMemcpyAsync(z, dz.ptr, sizeof(double) * N * k, hipMemcpyDeviceToHost, p->stream));
+    dofs_to_user(p, dz.as<double>(), du.as<double>(), k);
+    HIP_CHECK(hipMemcpyAsync(z, du.ptr, sizeof(double) * N * k, hipMemcpyDeviceToHost, p->stream));
     HIP_CHECK(hipStreamSynchronize(p->stream));
     return BEM_OK;
     BEM_CATCH
@@ -852,8 +1012,11 @@ int bem_pcg_solve_rhs(bem_problem* p, const bem_precond* m, const double* rhs, i
     if (!p || !rhs || k <= 0) fail(BEM_E_INVALID_ARG, "bad argument");
     set_device(p->ctx);
     const int64_t N = p->N;
-    DeviceBuffer dL(sizeof(double) * std::max<int64_t>(1, N * k), p->stream);
-    if (N) HIP_CHECK(hipMemcpyAsync(dL.ptr, rhs, sizeof(double) * N * k, hipMemcpyHostToDevice, p->stream));
+    DeviceBuffer dL(sizeof(double) * std::max<int64_t>(1, N * k), p->stream), du(sizeof(double) * std::max<int64_t>(1, N * k), p->stream);
+    if (N) {
+        HIP_CHECK(hipMemcpyAsync(du.ptr, rhs, sizeof(double) * N * k, hipMemcpyHostToDevice, p->stream));
+        dofs_to_internal(p, du.as<double>(), dL.as<double>(), k);
+    }
     return solve_common(p, m, dL.as<double>(), k, opts, phi_out, info);
     BEM_CATCH
 }

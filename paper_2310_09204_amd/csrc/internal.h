@@ -61,7 +61,11 @@ struct MeshTopo {
 };
 
 // Validates and analyses a mesh; throws Failure with a BEM_E_* code on invalid input.
-void analyze_mesh(const double* V, int64_t nv, const int32_t* T, int64_t nt, MeshTopo& out);
+// tri_user / vert_user (optional): the caller's index of each triangle / vertex of a renumbered
+// mesh.  Stars then list their triangles in the caller's order, so that sectors get the labels (and
+// the reference sector) that the caller's numbering gives them, and errors name the caller's indices.
+void analyze_mesh(const double* V, int64_t nv, const int32_t* T, int64_t nt, MeshTopo& out,
+                  const int32_t* tri_user = nullptr, const int32_t* vert_user = nullptr);
 // The same for a segment mesh in the plane (V: nv*2, S: ns*2): sectors are the angular regions
 // between the segments at a vertex; normal (nt*3) holds n_s = (-tau_y, tau_x, 0), area the lengths,
 // and the element CSR (tri_*) has corners 0 and 1.
@@ -76,7 +80,9 @@ struct NearList {
     std::vector<int32_t> verts;     // 5 per pair (-1 where unused)
     int64_t count[4] = {0, 0, 0, 0};
 };
-void build_near_list(const MeshTopo& m, NearList& out);
+// tri_user (optional): the caller's triangle indices of a renumbered mesh; each pair is then listed
+// with its first triangle the one of smaller caller index (the near rules are not symmetric)
+void build_near_list(const MeshTopo& m, NearList& out, const int32_t* tri_user = nullptr);
 
 // Quadrature tables computed from their definitions
 void triangle7_rule(double bary[7][3], double w[7]);
@@ -229,9 +235,36 @@ struct bem_problem {
     // instead of interleaving their kernels on its stream
     mutable std::mutex call_mu;
     int64_t bytes = 0;
+    // Locality order (triangle meshes): the problem numbers vertices and triangles in Morton order
+    // of their positions, so that blocks of consecutive dofs are compact patches; every entry point
+    // takes and returns dof-, vertex- and triangle-indexed data in the caller's numbering.
+    // vert_user / tri_user: the caller's index of an internal vertex / triangle (tri_int the
+    // inverse); dof_user / dof_int: internal dof -> caller's dof and back (also on the device).
+    bool renumbered = false;
+    std::vector<int32_t> vert_user, tri_user, tri_int, dof_user, dof_int;
+    bem::DeviceBuffer d_dof_user, d_dof_int;
 };
 
 namespace bem {
+
+// Locality order of a valid triangle mesh (indices in range, finite coordinates): vert_user[i] and
+// tri_user[t] are the input indices of the vertex / triangle placed at i / t, sorted by the Morton
+// code of the vertex position / triangle centroid (21 bits per axis over the vertices' bounding
+// box), ties by index (topology.cpp).
+void locality_order(const double* V, int64_t nv, const int32_t* T, int64_t nt, std::vector<int32_t>& vert_user,
+                    std::vector<int32_t>& tri_user);
+// Device copies of a renumbered mesh from the caller's device copies: Vout[i] = V[vert_user[i]],
+// Tout[t] = vert_int(T[tri_user[t]]) (assemble.hip)
+void renumber_mesh_device(const double* dV, const int32_t* dT, int64_t nv, int64_t nt, const int32_t* d_vert_user,
+                          const int32_t* d_vert_int, const int32_t* d_tri_user, double* Vout, int32_t* Tout, hipStream_t s);
+// dst[c][i] = src[c][idx[i]] for i < N, c < k (columns of leading dimensions lds and ldd)
+// (solver.hip); with the problem's dof maps it moves vectors between the caller's dof order and
+// the internal one
+void permute_cols_device(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t N, int k, const int32_t* idx,
+                         hipStream_t s);
+// out[r][j] = W[rows[r]][cols[j]] (r < nrows, j < ncols; out row-major, ld ncols) (solver.hip)
+void gather_rows_device(const double* W, int64_t ldw, const int32_t* d_rows, int64_t nrows, const int32_t* d_cols,
+                        int64_t ncols, double* out, hipStream_t s);
 
 // assembly (assemble.hip)
 // Assembles W for the mesh (V, T).  analyse(near) runs on the host while the far-field pass is on
@@ -294,7 +327,7 @@ void pcg_serve(bem_problem* p, const bem_precond* M, bool mixed, int slots, int 
 constexpr size_t kNoAllocScratchBytes = size_t(128) << 20;
 constexpr int kMaxDevices = 64;
 void* noalloc_scratch_address(int device);
-size_t noalloc_matvec_bytes(const bem_problem* p, bool fp32);
+size_t noalloc_matvec_bytes(const bem_problem* p, bool fp32, int k);
 void matvec_device_noalloc(const bem_problem* p, bool fp32, const double* d_x, int64_t ldx, int k, double* d_y,
                            hipStream_t s, void* scratch);
 

@@ -235,6 +235,7 @@ void worker_main(bem_server* s) {
                 s->cv_done.notify_all();
                 throw Failure{BEM_OK, ""};
             }
+            std::vector<double> col_tmp(prob->renumbered ? size_t(N) : 0);
             PcgSlots hooks;
             hooks.admit = [&](const std::vector<int>& free_slots, int running, std::vector<PcgNewColumn>& start) {
                 std::lock_guard<std::mutex> lk(s->mu);
@@ -267,10 +268,13 @@ void worker_main(bem_server* s) {
                 auto [r, col] = owner[size_t(slot)];
                 owner[size_t(slot)] = {nullptr, 0};
                 if (!r) return;
+                // the column in the problem's dof order, then in the caller's
                 if (N > 0)
-                    HIP_CHECK(hipMemcpyAsync(r->phi.data() + size_t(col) * N, d_x, sizeof(double) * N, hipMemcpyDeviceToHost,
-                                             prob->stream));
+                    HIP_CHECK(hipMemcpyAsync(prob->renumbered ? col_tmp.data() : r->phi.data() + size_t(col) * N, d_x,
+                                             sizeof(double) * N, hipMemcpyDeviceToHost, prob->stream));
                 HIP_CHECK(hipStreamSynchronize(prob->stream));
+                if (prob->renumbered)
+                    for (int64_t u = 0; u < N; ++u) r->phi[size_t(col) * N + u] = col_tmp[size_t(prob->dof_int[size_t(u)])];
                 bem_solve_info& in = r->info[size_t(col)];
                 in.iters = res.iters;
                 in.outer_iters = res.refreshes;

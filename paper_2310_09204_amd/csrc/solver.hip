@@ -568,6 +568,23 @@ __global__ __launch_bounds__(256) void k_init_state(const double* __restrict__ p
 
 inline unsigned gblocks(int64_t N) { return unsigned(std::max<int64_t>(1, std::min<int64_t>(1024, (N + 255) / 256))); }
 
+// out[r][j] = W[rows[r]][cols[j]]
+__global__ void k_gather_rows(const double* __restrict__ W, int64_t ldw, const int32_t* __restrict__ rows,
+                              const int32_t* __restrict__ cols, int64_t ncols, double* __restrict__ out) {
+    const int64_t r = blockIdx.y;
+    const double* wr = W + int64_t(rows[r]) * ldw;
+    for (int64_t j = int64_t(blockIdx.x) * 256 + threadIdx.x; j < ncols; j += int64_t(gridDim.x) * 256)
+        out[r * ncols + j] = wr[cols[j]];
+}
+
+// dst[c][i] = src[c][idx[i]]
+__global__ void k_permute_cols(const double* __restrict__ src, int64_t lds, double* __restrict__ dst, int64_t ldd,
+                               int64_t N, const int32_t* __restrict__ idx) {
+    const int c = blockIdx.y;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < N; i += int64_t(gridDim.x) * 256)
+        dst[int64_t(c) * ldd + i] = src[int64_t(c) * lds + idx[i]];
+}
+
 // xt: transposed right-hand sides (ldw x 16 of MT); part: split partials of the plain product
 // (16 x 16 x ldw doubles); sp: block-row partials of the symmetric product (ldw / 64 x (nst + 1) x
 // 1024 of MT).  Every entry of the three that a later kernel reads is written first, each call.
@@ -698,6 +715,23 @@ void matvec_setup(bem_problem* p, hipStream_t s) {
     for (int ty = 0; ty < 2; ++ty) p->mv_ntiles[ty] = int64_t(tiles[ty].size());
 }
 
+void gather_rows_device(const double* W, int64_t ldw, const int32_t* d_rows, int64_t nrows, const int32_t* d_cols,
+                        int64_t ncols, double* out, hipStream_t s) {
+    for (int64_t r0 = 0; r0 < nrows; r0 += 65535) {
+        const int64_t nr = std::min<int64_t>(65535, nrows - r0);
+        hipLaunchKernelGGL(k_gather_rows, dim3(gblocks(ncols), unsigned(nr)), dim3(256), 0, s, W, ldw, d_rows + r0, d_cols, ncols,
+                           out + r0 * ncols);
+    }
+    HIP_CHECK(hipGetLastError());
+}
+
+void permute_cols_device(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t N, int k, const int32_t* idx,
+                         hipStream_t s) {
+    if (N <= 0 || k <= 0) return;
+    hipLaunchKernelGGL(k_permute_cols, dim3(gblocks(N), unsigned(k)), dim3(256), 0, s, src, lds, dst, ldd, N, idx);
+    HIP_CHECK(hipGetLastError());
+}
+
 void matvec_device(const bem_problem* p, bool fp32, const double* d_x, int64_t ldx, int k, double* d_y, hipStream_t s,
                    const int* gate) {
     if (p->N == 0) return;
@@ -744,14 +778,16 @@ void* noalloc_scratch_address(int device) {
 }
 
 // layout: the transposed right-hand sides, then either the block-row partials of the symmetric
-// product or (a matrix of one 64-row block) the split partials of the plain one
-size_t noalloc_matvec_bytes(const bem_problem* p, bool fp32) {
+// product or (a matrix of one 64-row block) the split partials of the plain one, then, for a
+// renumbered problem, x and y of the product in the internal dof order (k x N each)
+size_t noalloc_matvec_bytes(const bem_problem* p, bool fp32, int k) {
     const size_t es = fp32 ? sizeof(float) : sizeof(double);
     const size_t xt = align256(16 * size_t(p->ldw) * es);
     const int ty = fp32 ? 0 : 1;
     const size_t part = p->mv_ntiles[ty] > 0 ? size_t(p->ldw / 64) * size_t(p->mv_nst[ty] + 1) * 1024 * es
                                              : 16 * 16 * size_t(p->ldw) * sizeof(double);
-    return xt + part;
+    const size_t perm = p->renumbered ? 2 * align256(size_t(k) * size_t(p->N) * sizeof(double)) : 0;
+    return xt + align256(part) + perm;
 }
 
 void matvec_device_noalloc(const bem_problem* p, bool fp32, const double* d_x, int64_t ldx, int k, double* d_y,
@@ -762,14 +798,29 @@ void matvec_device_noalloc(const bem_problem* p, bool fp32, const double* d_x, i
     void* xt = base;
     void* sp = base + align256(16 * size_t(p->ldw) * es);     // one of the two partial layouts is used
     double* part = static_cast<double*>(sp);
+    const double* x = d_x;
+    double* y = d_y;
+    int64_t ld = ldx;
+    if (p->renumbered) {   // the product runs in the internal order, between two permutations
+        const int ty = fp32 ? 0 : 1;
+        const size_t partb = p->mv_ntiles[ty] > 0 ? size_t(p->ldw / 64) * size_t(p->mv_nst[ty] + 1) * 1024 * es
+                                                  : 16 * 16 * size_t(p->ldw) * sizeof(double);
+        double* xi = reinterpret_cast<double*>(base + align256(16 * size_t(p->ldw) * es) + align256(partb));
+        double* yi = xi + align256(size_t(k) * size_t(p->N) * sizeof(double)) / sizeof(double);
+        permute_cols_device(d_x, ldx, xi, p->N, p->N, k, p->d_dof_user.as<int32_t>(), s);
+        x = xi;
+        y = yi;
+        ld = p->N;
+    }
     if (fp32) {
         if (!p->W32.ptr) fail(BEM_E_INVALID_ARG, "problem has no FP32 matrix (assemble with BEM_FP32_REFINE)");
-        launch_matvec<float, double>(p, p->W32.as<float>(), d_x, ldx, k, d_y, ldx, s, static_cast<float*>(xt), part,
+        launch_matvec<float, double>(p, p->W32.as<float>(), x, ld, k, y, ld, s, static_cast<float*>(xt), part,
                                      static_cast<float*>(sp), nullptr);
     } else {
-        launch_matvec<double, double>(p, p->W64.as<double>(), d_x, ldx, k, d_y, ldx, s, static_cast<double*>(xt), part,
+        launch_matvec<double, double>(p, p->W64.as<double>(), x, ld, k, y, ld, s, static_cast<double*>(xt), part,
                                       static_cast<double*>(sp), nullptr);
     }
+    if (p->renumbered) permute_cols_device(y, p->N, d_y, ldx, p->N, k, p->d_dof_int.as<int32_t>(), s);
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -60,8 +60,14 @@ inline int64_t side_node(int64_t t, int a, int s) { return (t * 3 + a) * 2 + s; 
 
 }  // namespace
 
-void analyze_mesh(const double* Vin, int64_t nv, const int32_t* Tin, int64_t nt, MeshTopo& m) {
+void analyze_mesh(const double* Vin, int64_t nv, const int32_t* Tin, int64_t nt, MeshTopo& m, const int32_t* tri_user,
+                  const int32_t* vert_user) {
     if (!Vin || !Tin || nv <= 0 || nt <= 0) fail(BEM_E_INVALID_ARG, "empty mesh");
+    // indices as the caller numbered them (messages, and the order that labels sectors)
+    auto tu = [&](int64_t t) { return std::to_string(tri_user ? int64_t(tri_user[t]) : t); };
+    auto vu = [&](int64_t v) { return std::to_string(vert_user ? int64_t(vert_user[v]) : v); };
+    auto ukey_v = [&](int64_t v) { return vert_user ? int64_t(vert_user[v]) : v; };
+    auto ukey_t = [&](int64_t t) { return tri_user ? int64_t(tri_user[t]) : t; };
     if (nt > (int64_t(1) << 30)) fail(BEM_E_INVALID_ARG, "too many triangles");
     m = MeshTopo();
     m.nv = nv;
@@ -82,14 +88,14 @@ void analyze_mesh(const double* Vin, int64_t nv, const int32_t* Tin, int64_t nt,
                 try {
                     for (int a = 0; a < 3; ++a) {
                         int32_t v = T[3 * t + a];
-                        if (v < 0 || v >= nv) fail(BEM_E_INVALID_ARG, "triangle " + std::to_string(t) + " has a vertex index out of range");
+                        if (v < 0 || v >= nv) fail(BEM_E_INVALID_ARG, "triangle " + tu(t) + " has a vertex index out of range");
                         if (!std::isfinite(V[3 * v]) || !std::isfinite(V[3 * v + 1]) || !std::isfinite(V[3 * v + 2]))
                             fail(BEM_E_INVALID_ARG, "non-finite vertex coordinate");
                     }
                     if (T[3 * t] == T[3 * t + 1] || T[3 * t + 1] == T[3 * t + 2] || T[3 * t] == T[3 * t + 2])
-                        fail(BEM_E_DEGENERATE, "triangle " + std::to_string(t) + " repeats a vertex");
+                        fail(BEM_E_DEGENERATE, "triangle " + tu(t) + " repeats a vertex");
                 } catch (const Failure& f) {
-                    bad.record(t, f);
+                    bad.record(ukey_t(t), f);
                     return;
                 }
             }
@@ -108,7 +114,7 @@ void analyze_mesh(const double* Vin, int64_t nv, const int32_t* Tin, int64_t nt,
                 double tw = norm3(c);
                 double scale = std::max({dot3(e1, e1), dot3(e2, e2), dot3(e3, e3)});
                 if (!(tw > 1e-12 * scale)) {
-                    bad.record(t, Failure{BEM_E_DEGENERATE, "triangle " + std::to_string(t) + " has zero area"});
+                    bad.record(ukey_t(t), Failure{BEM_E_DEGENERATE, "triangle " + tu(t) + " has zero area"});
                     return;
                 }
                 for (int k = 0; k < 3; ++k) m.normal[3 * t + k] = c[k] / tw;
@@ -151,19 +157,27 @@ void analyze_mesh(const double* Vin, int64_t nv, const int32_t* Tin, int64_t nt,
         for (size_t i = 1; i < order.size(); ++i) {
             int64_t a = order[i - 1], b = order[i];
             if (V[3 * a] == V[3 * b] && V[3 * a + 1] == V[3 * b + 1] && V[3 * a + 2] == V[3 * b + 2])
-                fail(BEM_E_MESH_NONCONFORMING, "vertices " + std::to_string(a) + " and " + std::to_string(b) + " coincide");
+                fail(BEM_E_MESH_NONCONFORMING, "vertices " + vu(a) + " and " + vu(b) + " coincide");
         }
     }
 
-    // ---- vertex stars (counting sort; triangles of a star in increasing index order) -------------
+    // ---- vertex stars (counting sort; triangles of a star in increasing index order, the
+    //      caller's numbering when tri_user is given) ---------------------------------------------
     std::vector<int64_t> vptr(nv + 1, 0);
     for (int64_t i = 0; i < 3 * nt; ++i) ++vptr[T[i] + 1];
     for (int64_t v = 0; v < nv; ++v) vptr[v + 1] += vptr[v];
     std::vector<int32_t> vtri(3 * nt);
     {
+        std::vector<int32_t> by_user;
+        if (tri_user) {
+            by_user.resize(size_t(nt));
+            for (int64_t t = 0; t < nt; ++t) by_user[size_t(tri_user[t])] = int32_t(t);
+        }
         std::vector<int64_t> fill(vptr.begin(), vptr.end() - 1);
-        for (int64_t t = 0; t < nt; ++t)
+        for (int64_t u = 0; u < nt; ++u) {
+            const int64_t t = tri_user ? by_user[size_t(u)] : u;
             for (int a = 0; a < 3; ++a) vtri[fill[T[3 * t + a]]++] = int32_t(t);
+        }
     }
     auto corner_of = [&](int64_t t, int64_t v) -> int {
         for (int a = 0; a < 3; ++a) if (T[3 * t + a] == v) return a;
@@ -242,8 +256,10 @@ void analyze_mesh(const double* Vin, int64_t nv, const int32_t* Tin, int64_t nt,
                         for (size_t k = 0; k < nf; ++k) {
                             const double gap = (k + 1 < nf) ? fan[k + 1].theta - fan[k].theta : fan[0].theta + 2.0 * M_PI - fan[k].theta;
                             if (gap < 1e-9)
-                                fail(BEM_E_MESH_NONCONFORMING, "two triangles at edge (" + std::to_string(std::min<int64_t>(v, w)) + "," +
-                                                                   std::to_string(std::max<int64_t>(v, w)) + ") lie in the same half-plane");
+                                fail(BEM_E_MESH_NONCONFORMING, "two triangles at edge (" +
+                                                                   std::to_string(std::min(ukey_v(v), ukey_v(w))) + "," +
+                                                                   std::to_string(std::max(ukey_v(v), ukey_v(w))) +
+                                                                   ") lie in the same half-plane");
                         }
                         for (size_t k = 0; k < nf; ++k) {
                             const Item& A = fan[k];
@@ -260,8 +276,8 @@ void analyze_mesh(const double* Vin, int64_t nv, const int32_t* Tin, int64_t nt,
                     b = e;
                 }
                 for (int64_t k = 1; k < ns; ++k)
-                    if (tris.root(k) != tris.root(0)) fail(BEM_E_POINT_CONTACT, "point contact at vertex " + std::to_string(v));
-                // sectors labelled by their smallest member (local order = triangle index order)
+                    if (tris.root(k) != tris.root(0)) fail(BEM_E_POINT_CONTACT, "point contact at vertex " + vu(v));
+                // sectors labelled by their smallest member (local order = the star's triangle order)
                 roots.clear();
                 for (int64_t k = 0; k < 2 * ns; ++k) roots.push_back(sides.root(k));
                 std::sort(roots.begin(), roots.end());
@@ -275,7 +291,7 @@ void analyze_mesh(const double* Vin, int64_t nv, const int32_t* Tin, int64_t nt,
                             int32_t(std::lower_bound(roots.begin(), roots.end(), sides.root(2 * k + sd)) - roots.begin());
                 }
             } catch (const Failure& f) {
-                err.record(v, f);
+                err.record(ukey_v(v), f);
             }
         }
     });
@@ -478,7 +494,58 @@ void analyze_segments(const double* Vin, int64_t nv, const int32_t* Sin, int64_t
         }
 }
 
-void build_near_list(const MeshTopo& m, NearList& out) {
+// Morton code of a point quantised to 21 bits per axis: the bits of x, y and z interleaved
+static uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+    auto spread = [](uint64_t v) {
+        v &= 0x1fffff;
+        v = (v | (v << 32)) & 0x1f00000000ffffull;
+        v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+        v = (v | (v << 8)) & 0x100f00f00f00f00full;
+        v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+        v = (v | (v << 2)) & 0x1249249249249249ull;
+        return v;
+    };
+    return spread(x) | (spread(y) << 1) | (spread(z) << 2);
+}
+
+void locality_order(const double* V, int64_t nv, const int32_t* T, int64_t nt, std::vector<int32_t>& vert_user,
+                    std::vector<int32_t>& tri_user) {
+    double lo[3] = {V[0], V[1], V[2]}, hi[3] = {V[0], V[1], V[2]};
+    for (int64_t i = 0; i < nv; ++i)
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = std::min(lo[c], V[3 * i + c]);
+            hi[c] = std::max(hi[c], V[3 * i + c]);
+        }
+    const double span = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], 1e-300});
+    auto key = [&](double x, double y, double z) {
+        auto q = [&](double v, int c) {
+            const double f = (v - lo[c]) / span;
+            return uint32_t(std::min(2097151.0, std::max(0.0, f * 2097151.0)));
+        };
+        return morton3(q(x, 0), q(y, 1), q(z, 2));
+    };
+    std::vector<std::pair<uint64_t, int32_t>> kv(static_cast<size_t>(nv)), kt(static_cast<size_t>(nt));
+    parallel_for(nv, [&](int64_t b, int64_t e) {
+        for (int64_t i = b; i < e; ++i) kv[size_t(i)] = {key(V[3 * i], V[3 * i + 1], V[3 * i + 2]), int32_t(i)};
+    });
+    parallel_for(nt, [&](int64_t b, int64_t e) {
+        for (int64_t t = b; t < e; ++t) {
+            double c[3] = {0, 0, 0};
+            for (int a = 0; a < 3; ++a)
+                for (int k = 0; k < 3; ++k) c[k] += V[3 * int64_t(T[3 * t + a]) + k] / 3.0;
+            kt[size_t(t)] = {key(c[0], c[1], c[2]), int32_t(t)};
+        }
+    });
+    std::thread tv([&] { std::sort(kv.begin(), kv.end()); });
+    std::sort(kt.begin(), kt.end());
+    tv.join();
+    vert_user.resize(size_t(nv));
+    tri_user.resize(size_t(nt));
+    for (int64_t i = 0; i < nv; ++i) vert_user[size_t(i)] = kv[size_t(i)].second;
+    for (int64_t t = 0; t < nt; ++t) tri_user[size_t(t)] = kt[size_t(t)].second;
+}
+
+void build_near_list(const MeshTopo& m, NearList& out, const int32_t* tri_user) {
     out = NearList();
     const int64_t nt = m.nt, nv = m.nv;
     const auto& T = m.T;
@@ -508,9 +575,14 @@ void build_near_list(const MeshTopo& m, NearList& out) {
                 }
                 std::sort(cand.begin(), cand.end());
                 cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
-                const int32_t* a = &T[3 * t1];
-                for (int32_t t2 : cand) {
-                    const int32_t* b = &T[3 * t2];
+                for (int32_t t2c : cand) {
+                    // the pair's first triangle is the one with the smaller index in the caller's
+                    // numbering: the Duffy rules are not symmetric in the two triangles, and this is
+                    // the order in which the unrenumbered problem (and the oracle) takes them
+                    int32_t f = int32_t(t1), t2 = t2c;
+                    if (tri_user && tri_user[t2] < tri_user[f]) std::swap(f, t2);
+                    const int32_t* a = &T[3 * int64_t(f)];
+                    const int32_t* b = &T[3 * int64_t(t2)];
                     int ia[3], ib[3], ns = 0;
                     for (int i = 0; i < 3; ++i)
                         for (int j = 0; j < 3; ++j)
@@ -532,7 +604,7 @@ void build_near_list(const MeshTopo& m, NearList& out) {
                         vs[1] = a[(ia[0] + 1) % 3]; vs[2] = a[(ia[0] + 2) % 3];
                         vs[3] = b[(ib[0] + 1) % 3]; vs[4] = b[(ib[0] + 2) % 3];
                     }
-                    o.t1.push_back(int32_t(t1));
+                    o.t1.push_back(f);
                     o.t2.push_back(t2);
                     o.type.push_back(type);
                     o.verts.insert(o.verts.end(), vs, vs + 5);

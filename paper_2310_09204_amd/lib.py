@@ -34,7 +34,7 @@ class BemError(RuntimeError):
 
 class AssembleOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("near_order", ctypes.c_int), ("keep_pair_matrix", ctypes.c_int),
-                ("pair_panel_rows", ctypes.c_int64)]
+                ("pair_panel_rows", ctypes.c_int64), ("keep_order", ctypes.c_int32)]
 
 
 class ProblemInfo(ctypes.Structure):
@@ -317,10 +317,10 @@ class Problem:
     device memory (same values as V, T), bem_assemble_dev: the kernels read those copies."""
 
     def __init__(self, ctx: Context, V, T, precision=FP64, near_order=10, keep_pair_matrix=False, pair_panel_rows=0,
-                 device_mesh=None):
+                 device_mesh=None, keep_order=False):
         self.ctx = ctx
         self.V, self.T = _f64(V), _i32a(T)
-        o = AssembleOpts(precision, near_order, int(keep_pair_matrix), int(pair_panel_rows))
+        o = AssembleOpts(precision, near_order, int(keep_pair_matrix), int(pair_panel_rows), int(keep_order))
         self._h = ctypes.c_void_p()
         if device_mesh is None:
             _check(load().bem_assemble(ctx.handle, _p(self.V), self.V.shape[0], _p(self.T), self.T.shape[0],
@@ -493,7 +493,7 @@ class Problem2D(Problem):
         self.V, self.T = _f64(V), _i32a(S)
         if self.V.shape[1] != 2 or self.T.shape[1] != 2:
             raise ValueError("vertices must be nv x 2 and segments ns x 2")
-        o = AssembleOpts(precision, 0, 0, 0)
+        o = AssembleOpts(precision, 0, 0, 0, 0)
         self._h = ctypes.c_void_p()
         _check(load().bem_assemble_2d(ctx.handle, _p(self.V), self.V.shape[0], _p(self.T), self.T.shape[0],
                                       ctypes.byref(o), ctypes.byref(self._h)))

@@ -570,14 +570,23 @@ def serving_leg(lib, meshes, ctx, n_requests, load, seed=0, max_inflight=4):
     """Seeded Poisson stream of solve requests on random multiscreens (N ~ U[2k, 30k], 1-16 g per
     request, FP64 or mixed), replayed in real time into the serving loop.
 
-    Capacity is measured first by submitting the whole stream at once; the timed replay then
-    scales the seeded arrival times to `load` x capacity.  Latency is submit -> completion as the
+    Capacity is measured first by submitting the whole stream at once (after one untimed burst
+    that warms the buffer pool; each replay starts a new server, so every geometry is assembled
+    and set up again inside the timed region); the timed replay then scales the seeded arrival
+    times to `load` x capacity.  Latency is submit -> completion as the
     server measures it; solves/s counts right-hand sides within rel.err 1e-8 of an FP64 solve of
     the same request (computed after the stream, not timed).  Each latency splits into the wait
     before the request's columns start in a block PCG (queueing, plus assembly and set-up of a
     geometry that was not resident) and the solve after it."""
-    ctx.release_cached()   # the server starts from an empty buffer pool, not the previous legs' one
+    # The previous legs' buffers go back to the driver, and an untimed burst then fills the buffer
+    # pool with the stream's own sizes, as a server that has run for a while holds them.  Once a
+    # process has written a few hundred GB of device memory, handing memory back to the driver
+    # gets slow (hipFree of 48 GiB: about 1 s, against 2 ms before) and so does the work right
+    # after it: a server started from an empty pool after the crossed192 legs timed that, at a
+    # third of the rate it reaches in a fresh process.
+    ctx.release_cached()
     reqs = meshes.serving_stream(seed, n_requests, rate=1.0)    # arrival times for rate 1/s
+    _replay(lib, reqs, ctx, 0.0, max_inflight)
     res_b, t_burst, _ = _replay(lib, reqs, ctx, 0.0, max_inflight)
     for i, res in enumerate(res_b):
         if res[2] < 0:

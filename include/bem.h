@@ -85,6 +85,11 @@ typedef struct {
     double t_host_s;         /* host time of the mesh analysis and near-pair list */
     int64_t n_pair_panels;   /* panels the pair matrix was built in (0: in one piece) */
     int64_t dim;             /* 3: triangle mesh (n_tri triangles); 2: segment mesh (n_tri segments) */
+    int64_t panels_replanned; /* panels are laid out before the sector analysis, from the sector count
+                               * q = T_v - E_v + 2 that the numbers of triangles and edges at each
+                               * vertex give (Euler's formula for the graph they cut on a small
+                               * sphere about it); 1: the analysis numbered the dofs otherwise and
+                               * the panels were planned again (0 for every mesh it accepts) */
 } bem_problem_info;
 
 typedef struct {

@@ -1016,78 +1016,146 @@ ContractPlan contract_plan(const MeshTopo& m) {
 
 // ---- panel-by-panel assembly -------------------------------------------------------------------
 // For meshes whose N_T x N_T pair matrix does not fit next to W: the dof row blocks (64 dofs) are
-// grouped into panels whose rows' star triangles number at most maxrows.  A panel computes
-// I_P = I(R, [tmin, N_T)) for its row triangles R and every column triangle that a tile
-// (bd, be >= bd) of its rows can read (tmin = smallest triangle of the column blocks from its first
-// row block on, rounded down to a multiple of 16), the near pairs that fall in it, and then contracts its tiles of the upper half of W
-// (the mirrored writes fill the lower half).  Far work is about half of N_T^2 pairs in total, as in
-// the one-shot path.  Host-side filtering of the next panel overlaps the device work of this one.
+// grouped into panels whose rows number at most maxrows.  The rows of a panel are the triangles at
+// the vertices of its blocks' dofs (the stars of those dofs, and at a vertex of a screen's boundary
+// sector also the triangles no star of it holds).  A panel computes I_P = I(R, [tmin, N_T)) for
+// its rows R, each 64-row tile from the first column a tile (bd, be >= bd) of the panel can read
+// it at, the near pairs that fall in it, and then contracts its tiles of the upper half of W (the
+// mirrored writes fill the lower half).  Far work is about half of N_T^2 pairs in total, as in the
+// one-shot path.  The layout needs only the number of dofs of each vertex, which forecast_dofs
+// gets from counts: the first panel's far pass is queued before the host's sector analysis and
+// runs while the host analyses the mesh, and the host filters each panel's near pairs while that
+// panel's far pass runs.
 struct PanelTimes { double far = 0, near = 0, contract = 0; int panels = 0; };
 
-template <class Mark>
-PanelTimes assemble_panels(bem_problem* p, const MeshTopo& m, const NearList& near, const ContractPlan& plan,
-                           const double* geo, const double* gbounds, const double* crec, const double* dV, const double* dgx, const double* dgw, const double* dofJ,
-                           float* w32, Mark&& mark) {
-    hipStream_t s = p->stream;
-    const int64_t nt = m.nt, N = m.N;
-    PanelTimes out;
-    if (N == 0) return out;
-    const int64_t ncb = (N + kCT - 1) / kCT;
-    std::vector<int64_t> sufmin(ncb + 1, nt);
-    for (int64_t be = ncb - 1; be >= 0; --be) {
-        int64_t mn = nt;
-        if (plan.cb_ptr[be] < plan.cb_ptr[be + 1]) mn = plan.cb_tri[plan.cb_ptr[be]];   // lists are sorted
-        sufmin[be] = std::min(sufmin[be + 1], mn);
-    }
-    int64_t maxrows = p->panel_rows;
-    if (maxrows <= 0) {
-        maxrows = int64_t(p->tune.panel_fraction * double(available_device_bytes(p->ctx->device)) / (8.0 * double(nt)));
-        // in steps of 2048 rows, so that a repeat of the same mesh plans the same panels and gets
-        // the panel buffer of its predecessor back from the pool
-        maxrows = maxrows / 2048 * 2048;
-    }
-    maxrows = std::max<int64_t>(maxrows, kTile);
-    DeviceBuffer d_cb_ptr = upload(plan.cb_ptr, s), d_cb_tri = upload(plan.cb_tri, s);
-    DeviceBuffer d_col_loc = upload(plan.col_loc, s), d_rg_ptr = upload(plan.rg_ptr, s);
-    DeviceBuffer d_rg = upload(plan.rg, s), d_rg_ent = upload(plan.rg_ent, s);
-    DeviceBuffer d_fast = upload(plan.fast, s), d_slow = upload(plan.slow, s);
+// Dofs of each vertex before the sector analysis (Section 4.2: q_v sectors, q_v - 1 dofs).  Near a
+// vertex v of a conforming multiscreen without point contacts, the triangles and edges at v cut a
+// small sphere about v along a connected graph (one node per edge at v, one arc per triangle at v)
+// whose faces are the sectors at v; Euler's formula gives q_v = T_v - E_v + 2 from the numbers T_v
+// of triangles and E_v of edges at v.  The analysis confirms the forecast for every mesh it accepts;
+// the caller compares the two before anything depends on the difference.
+struct DofForecast {
+    std::vector<int64_t> vt_ptr;      // triangles at each vertex (ascending), CSR over vertices
+    std::vector<int32_t> vt;
+    std::vector<int64_t> first_dof;   // nv + 1: dofs of vertex v are first_dof[v] .. first_dof[v + 1] - 1
+    int64_t N = 0;
+};
 
-    struct Panel {   // host arrays stay alive until the end: their uploads are asynchronous
-        std::vector<int32_t> rows, rowmap, nv[4], na[4], nb[4];
-        std::vector<int64_t> tgt[4];
-        std::vector<int2> ftiles;
-        std::unique_ptr<EventTimer> ef, en, ec;
-    };
-    std::vector<std::unique_ptr<Panel>> done;
-    std::vector<int32_t> stamp(size_t(nt), -1);
-    // first row block of its panel whose rows' stars hold each triangle (valid while that panel is
-    // being built): the tiles (bd, be >= bd) of the panel read row T of I only at columns
-    // >= sufmin[first_block[T]]; rowfirst keeps it per panel row
-    std::vector<int32_t> first_block(size_t(nt), 0);
-    std::vector<std::vector<int32_t>> rowfirst;
-    // panel boundaries first (whole 64-dof row blocks), so that one buffer of the largest panel's
-    // size serves all of them (a fresh allocation of tens of GB per panel costs seconds)
-    std::vector<int64_t> starts;
-    std::vector<std::vector<int32_t>> rowsets;
+DofForecast forecast_dofs(const int32_t* T, int64_t nv, int64_t nt) {
+    DofForecast f;
+    f.vt_ptr.assign(static_cast<size_t>(nv) + 1, 0);
+    for (int64_t i = 0; i < 3 * nt; ++i) ++f.vt_ptr[size_t(T[i]) + 1];
+    for (int64_t v = 0; v < nv; ++v) f.vt_ptr[size_t(v) + 1] += f.vt_ptr[size_t(v)];
+    f.vt.resize(static_cast<size_t>(3 * nt));
     {
-        int64_t b0 = 0;
+        std::vector<int64_t> pos(f.vt_ptr.begin(), f.vt_ptr.end() - 1);
+        for (int64_t t = 0; t < nt; ++t)
+            for (int a = 0; a < 3; ++a) f.vt[size_t(pos[size_t(T[3 * t + a])]++)] = int32_t(t);
+    }
+    std::vector<int64_t> nd(static_cast<size_t>(nv), 0);
+    parallel_for(nv, [&](int64_t lo, int64_t hi) {
+        std::vector<int32_t> nb;
+        for (int64_t v = lo; v < hi; ++v) {
+            const int64_t tv = f.vt_ptr[size_t(v) + 1] - f.vt_ptr[size_t(v)];
+            if (tv == 0) continue;
+            nb.clear();
+            for (int64_t k = f.vt_ptr[size_t(v)]; k < f.vt_ptr[size_t(v) + 1]; ++k) {
+                const int32_t* c = T + 3 * int64_t(f.vt[size_t(k)]);
+                for (int a = 0; a < 3; ++a)
+                    if (c[a] != v) nb.push_back(c[a]);
+            }
+            std::sort(nb.begin(), nb.end());
+            const int64_t ev = std::unique(nb.begin(), nb.end()) - nb.begin();
+            nd[size_t(v)] = std::max<int64_t>(0, tv - ev + 1);   // q_v - 1
+        }
+    }, 4096);
+    f.first_dof.assign(static_cast<size_t>(nv) + 1, 0);
+    for (int64_t v = 0; v < nv; ++v) f.first_dof[size_t(v) + 1] = f.first_dof[size_t(v)] + nd[size_t(v)];
+    f.N = f.first_dof[size_t(nv)];
+    return f;
+}
+
+// Far-pass tiles of a panel: row tile rb takes the column tiles cstart[rb] .. nct - 1, at positions
+// tptr[rb] .. tptr[rb + 1] - 1 of the list (one block per row tile)
+__global__ void k_rect_tiles(const int32_t* __restrict__ cstart, const int64_t* __restrict__ tptr, int32_t nct,
+                             int2* __restrict__ out) {
+    const int rb = int(blockIdx.x);
+    const int c0 = cstart[rb];
+    const int64_t base = tptr[rb];
+    for (int c = c0 + int(threadIdx.x); c < nct; c += int(blockDim.x)) out[base + (c - c0)] = make_int2(rb, c);
+}
+
+// Device copies of the contraction plan, shared by all panels
+struct PlanDevice {
+    DeviceBuffer cb_ptr, cb_tri, col_loc, rg_ptr, rg, rg_ent, fast, slow;
+    PlanDevice(const ContractPlan& plan, hipStream_t s)
+        : cb_ptr(upload(plan.cb_ptr, s)), cb_tri(upload(plan.cb_tri, s)), col_loc(upload(plan.col_loc, s)),
+          rg_ptr(upload(plan.rg_ptr, s)), rg(upload(plan.rg, s)), rg_ent(upload(plan.rg_ent, s)),
+          fast(upload(plan.fast, s)), slow(upload(plan.slow, s)) {}
+};
+
+class PanelRun {
+  public:
+    PanelRun(bem_problem* p, int64_t nt, const DofForecast& f, const double* geo, const double* gbounds,
+             const double* crec)
+        : p_(p), s_(p->stream), nt_(nt), f_(f), geo_(geo), gbounds_(gbounds), crec_(crec) {}
+
+    // Groups the row blocks of a numbering with first_dof (N dofs) into panels and allocates the
+    // panel buffer, after W (its size is a share of the memory W leaves).
+    void layout(const std::vector<int64_t>& first_dof, int64_t N) {
+        const int64_t nv = int64_t(first_dof.size()) - 1;
+        N_ = N;
+        const int64_t ncb = (N + kCT - 1) / kCT;
+        int64_t maxrows = p_->panel_rows;
+        if (maxrows <= 0) {
+            maxrows = int64_t(p_->tune.panel_fraction * double(available_device_bytes(p_->ctx->device)) / (8.0 * double(nt_)));
+            // in steps of 2048 rows, so that a repeat of the same mesh plans the same panels and gets
+            // the panel buffer of its predecessor back from the pool
+            maxrows = maxrows / 2048 * 2048;
+        }
+        maxrows = std::max<int64_t>(maxrows, kTile);
+        // the vertices of each block's dofs, and the first column (a multiple of 16) that a tile
+        // (bd, be >= bd) can read: every triangle of such a column block lies at a vertex with dofs
+        // from the first dof of bd on
+        auto vertex_of = [&](int64_t d) {
+            return int64_t(std::upper_bound(first_dof.begin(), first_dof.end(), d) - first_dof.begin()) - 1;
+        };
+        std::vector<int64_t> vlo(static_cast<size_t>(ncb)), vhi(static_cast<size_t>(ncb)), col(static_cast<size_t>(ncb));
+        std::vector<int64_t> sm(static_cast<size_t>(nv) + 1, nt_);
+        for (int64_t v = nv - 1; v >= 0; --v) {
+            const bool has = first_dof[size_t(v) + 1] > first_dof[size_t(v)] && f_.vt_ptr[size_t(v) + 1] > f_.vt_ptr[size_t(v)];
+            sm[size_t(v)] = std::min<int64_t>(sm[size_t(v) + 1], has ? f_.vt[size_t(f_.vt_ptr[size_t(v)])] : nt_);
+        }
+        for (int64_t b = 0; b < ncb; ++b) {
+            vlo[size_t(b)] = vertex_of(b * kCT);
+            vhi[size_t(b)] = vertex_of(std::min<int64_t>(N, b * kCT + kCT) - 1);
+            col[size_t(b)] = sm[size_t(vlo[size_t(b)])] / kGrp * kGrp;
+        }
+        starts_.clear();
+        tmin_.clear();
+        rows_.clear();
+        rowfirst_.clear();
+        std::vector<int32_t> stamp(static_cast<size_t>(nt_), -1), first_block(static_cast<size_t>(nt_), 0);
+        int64_t b0 = 0, max_elems = 1;
         int id = 0;
         while (b0 < ncb) {
-            std::vector<int32_t> rows;
+            std::vector<int32_t> rows, add;
             int64_t b1 = b0;
             while (b1 < ncb) {
-                std::vector<int32_t> add;
-                for (int64_t rb = 4 * b1; rb < 4 * b1 + 4; ++rb)
-                    for (int32_t g = plan.rg_ptr[rb]; g < plan.rg_ptr[rb + 1]; ++g) {
-                        const int32_t T = plan.rg[g].x;
-                        if (stamp[T] != id) {
-                            stamp[T] = id;
-                            first_block[T] = int32_t(b1);
+                add.clear();
+                for (int64_t v = vlo[size_t(b1)]; v <= vhi[size_t(b1)]; ++v) {
+                    if (first_dof[size_t(v) + 1] == first_dof[size_t(v)]) continue;
+                    for (int64_t k = f_.vt_ptr[size_t(v)]; k < f_.vt_ptr[size_t(v) + 1]; ++k) {
+                        const int32_t T = f_.vt[size_t(k)];
+                        if (stamp[size_t(T)] != id) {
+                            stamp[size_t(T)] = id;
+                            first_block[size_t(T)] = int32_t(b1);
                             add.push_back(T);
                         }
                     }
+                }
                 if (b1 > b0 && int64_t(rows.size() + add.size()) > maxrows) {
-                    for (int32_t T : add) stamp[T] = -1;
+                    for (int32_t T : add) stamp[size_t(T)] = -1;
                     break;
                 }
                 rows.insert(rows.end(), add.begin(), add.end());
@@ -1095,124 +1163,184 @@ PanelTimes assemble_panels(bem_problem* p, const MeshTopo& m, const NearList& ne
             }
             std::sort(rows.begin(), rows.end());
             std::vector<int32_t> firsts(rows.size());
-            for (size_t i = 0; i < rows.size(); ++i) firsts[i] = first_block[rows[i]];
-            starts.push_back(b0);
-            rowsets.push_back(std::move(rows));
-            rowfirst.push_back(std::move(firsts));
+            for (size_t i = 0; i < rows.size(); ++i) firsts[i] = int32_t(col[size_t(first_block[size_t(rows[i])])]);
+            const int64_t tmin = col[size_t(b0)];
+            max_elems = std::max<int64_t>(max_elems, int64_t(rows.size()) * ((nt_ - tmin + 7) / 8 * 8));
+            starts_.push_back(b0);
+            tmin_.push_back(tmin);
+            rows_.push_back(std::move(rows));
+            rowfirst_.push_back(std::move(firsts));
             b0 = b1;
             ++id;
         }
-        starts.push_back(ncb);
+        starts_.push_back(ncb);
+        panels_.clear();
+        Ip_.reset();
+        // one buffer of the largest panel's size serves all of them (a fresh allocation of tens of
+        // GB per panel costs seconds)
+        Ip_ = DeviceBuffer(sizeof(double) * size_t(max_elems), s_);
     }
-    // a panel's columns start at a multiple of 16, so that its column groups are those of the
-    // far-field records
-    auto first_col = [&](int64_t bd) { return sufmin[bd] / kGrp * kGrp; };
-    int64_t max_elems = 1;
-    for (size_t q = 0; q < rowsets.size(); ++q) {
-        const int64_t ldq = (nt - first_col(starts[q]) + 7) / 8 * 8;
-        max_elems = std::max<int64_t>(max_elems, int64_t(rowsets[q].size()) * ldq);
-    }
-    DeviceBuffer Ip(sizeof(double) * max_elems, s);
-    for (size_t pid = 0; pid < rowsets.size(); ++pid) {
-        auto P = std::make_unique<Panel>();
-        const int64_t bd0 = starts[pid], bd1 = starts[pid + 1];
-        P->rows = std::move(rowsets[pid]);
-        const int64_t nrows = int64_t(P->rows.size());
-        const int64_t tmin = first_col(bd0);
-        const int64_t ncol = nt - tmin;
-        const int64_t ldP = (ncol + 7) / 8 * 8;
-        P->rowmap.assign(size_t(nt), -1);
-        for (int64_t r = 0; r < nrows; ++r) P->rowmap[P->rows[r]] = int32_t(r);
-        // far tiles: each 64-row tile from the first column any of its rows is read at (the rest of
-        // the panel's diagonal band, below it, is never read)
-        for (int64_t rb = 0; rb < (nrows + kTile - 1) / kTile; ++rb) {
-            int64_t cmin = nt;
-            for (int64_t r = rb * kTile; r < std::min<int64_t>(nrows, rb * kTile + kTile); ++r)
-                cmin = std::min<int64_t>(cmin, first_col(rowfirst[pid][r]));
-            for (int64_t cb = std::max<int64_t>(0, cmin - tmin) / kTile; cb < (ncol + kTile - 1) / kTile; ++cb)
-                P->ftiles.push_back(make_int2(int(rb), int(cb)));
-        }
 
-        DeviceBuffer d_rows = upload(P->rows, s), d_rowmap = upload(P->rowmap, s), d_ft = upload(P->ftiles, s);
-        P->ef = std::make_unique<EventTimer>(s);
-        const int64_t nft = int64_t(P->ftiles.size());
-        hipLaunchKernelGGL(k_far_rect, dim3(blocks_for(nft, 4)), dim3(256), 0, s, geo, gbounds, crec, int32_t(nt),
-                           d_rows.as<int32_t>(), nrows, tmin, ldP, d_ft.as<int2>(), nft, p->tune.far_separation, Ip.as<double>());
-        HIP_CHECK(hipGetLastError());
+    size_t count() const { return rows_.size(); }
+
+    // Queues the far pass of panel pid (panels in order).
+    void far(size_t pid) {
+        auto P = std::make_unique<Panel>();
+        const std::vector<int32_t>& R = rows_[pid];
+        const int64_t nrows = int64_t(R.size()), t0 = tmin_[pid], ncol = nt_ - t0;
+        P->ldP = (ncol + 7) / 8 * 8;
+        P->rowmap.assign(static_cast<size_t>(nt_), -1);
+        for (int64_t r = 0; r < nrows; ++r) P->rowmap[size_t(R[size_t(r)])] = int32_t(r);
+        const int64_t nrt = (nrows + kTile - 1) / kTile, nct = (ncol + kTile - 1) / kTile;
+        P->cstart.assign(static_cast<size_t>(std::max<int64_t>(nrt, 1)), 0);
+        P->tptr.assign(static_cast<size_t>(nrt) + 1, 0);
+        for (int64_t rb = 0; rb < nrt; ++rb) {
+            int64_t cmin = nt_;
+            for (int64_t r = rb * kTile; r < std::min<int64_t>(nrows, rb * kTile + kTile); ++r)
+                cmin = std::min<int64_t>(cmin, rowfirst_[pid][size_t(r)]);
+            const int64_t cs = std::min<int64_t>(nct, std::max<int64_t>(0, cmin - t0) / kTile);
+            P->cstart[size_t(rb)] = int32_t(cs);
+            P->tptr[size_t(rb) + 1] = P->tptr[size_t(rb)] + (nct - cs);
+        }
+        const int64_t nft = P->tptr[size_t(nrt)];
+        DeviceBuffer d_rows = upload(R, s_), d_cs = upload(P->cstart, s_), d_tp = upload(P->tptr, s_);
+        P->d_rowmap = upload(P->rowmap, s_);
+        DeviceBuffer d_ft(sizeof(int2) * size_t(std::max<int64_t>(nft, 1)), s_);
+        if (nft > 0) {
+            hipLaunchKernelGGL(k_rect_tiles, dim3(unsigned(nrt)), dim3(256), 0, s_, d_cs.as<int32_t>(), d_tp.as<int64_t>(),
+                               int32_t(nct), d_ft.as<int2>());
+            HIP_CHECK(hipGetLastError());
+        }
+        P->ef = std::make_unique<EventTimer>(s_);
+        if (nft > 0) {
+            hipLaunchKernelGGL(k_far_rect, dim3(blocks_for(nft, 4)), dim3(256), 0, s_, geo_, gbounds_, crec_, int32_t(nt_),
+                               d_rows.as<int32_t>(), nrows, t0, P->ldP, d_ft.as<int2>(), nft, p_->tune.far_separation,
+                               Ip_.as<double>());
+            HIP_CHECK(hipGetLastError());
+        }
         P->ef->stop();
+        if (panels_.size() <= pid) panels_.resize(pid + 1);
+        panels_[pid] = std::move(P);
+    }
+
+    // Queues the near pairs and the contraction of panel pid, whose far pass is queued.
+    template <class Mark>
+    void finish(size_t pid, const NearList& near, const PlanDevice& pd, const ContractPlan& plan, const double* dV,
+                const double* dgx, const double* dgw, const double* dofJ, float* w32, Mark&& mark) {
+        Panel& P = *panels_[pid];
+        const int64_t t0 = tmin_[pid], ldP = P.ldP;
         // near pairs with a position in this panel (filtered on the host while the far pass runs)
         for (size_t i = 0; i < near.t1.size(); ++i) {
             const int ty = near.type[i];
             const int32_t a = near.t1[i], b = near.t2[i];
             int64_t g1 = -1, g2 = -1;
-            if (P->rowmap[a] >= 0 && b >= tmin) g1 = int64_t(P->rowmap[a]) * ldP + (b - tmin);
-            if (a != b && P->rowmap[b] >= 0 && a >= tmin) g2 = int64_t(P->rowmap[b]) * ldP + (a - tmin);
+            if (P.rowmap[size_t(a)] >= 0 && b >= t0) g1 = int64_t(P.rowmap[size_t(a)]) * ldP + (b - t0);
+            if (a != b && P.rowmap[size_t(b)] >= 0 && a >= t0) g2 = int64_t(P.rowmap[size_t(b)]) * ldP + (a - t0);
             if (g1 < 0 && g2 < 0) continue;
-            P->na[ty].push_back(a);
-            P->nb[ty].push_back(b);
-            P->nv[ty].insert(P->nv[ty].end(), &near.verts[5 * i], &near.verts[5 * i] + 5);
-            P->tgt[ty].push_back(g1);
-            P->tgt[ty].push_back(g2);
+            P.na[ty].push_back(a);
+            P.nb[ty].push_back(b);
+            P.nv[ty].insert(P.nv[ty].end(), &near.verts[5 * i], &near.verts[5 * i] + 5);
+            P.tgt[ty].push_back(g1);
+            P.tgt[ty].push_back(g2);
         }
         DeviceBuffer dv[4], da[4], dbb[4], dt[4];
         for (int ty = 1; ty <= 3; ++ty) {
-            if (P->na[ty].empty()) continue;
-            dv[ty] = upload(P->nv[ty], s);
-            da[ty] = upload(P->na[ty], s);
-            dbb[ty] = upload(P->nb[ty], s);
-            dt[ty] = upload(P->tgt[ty], s);
+            if (P.na[ty].empty()) continue;
+            dv[ty] = upload(P.nv[ty], s_);
+            da[ty] = upload(P.na[ty], s_);
+            dbb[ty] = upload(P.nb[ty], s_);
+            dt[ty] = upload(P.tgt[ty], s_);
         }
-        P->en = std::make_unique<EventTimer>(s);
+        P.en = std::make_unique<EventTimer>(s_);
         for (int ty = 1; ty <= 3; ++ty) {
-            const int64_t n = int64_t(P->na[ty].size());
+            const int64_t n = int64_t(P.na[ty].size());
             if (n == 0) continue;
             dim3 grid(blocks_for(n, 64)), block(64);
             if (ty == 3)
-                hipLaunchKernelGGL(k_near_coincident, grid, block, 0, s, dV, dv[ty].as<int32_t>(), da[ty].as<int32_t>(), n,
-                                   p->near_order, dgx, dgw, Ip.as<double>(), ldP, dt[ty].as<int64_t>());
+                hipLaunchKernelGGL(k_near_coincident, grid, block, 0, s_, dV, dv[ty].as<int32_t>(), da[ty].as<int32_t>(), n,
+                                   p_->near_order, dgx, dgw, Ip_.as<double>(), ldP, dt[ty].as<int64_t>());
             else if (ty == 2)
-                hipLaunchKernelGGL(k_near_edge, grid, block, 0, s, dV, dv[ty].as<int32_t>(), da[ty].as<int32_t>(),
-                                   dbb[ty].as<int32_t>(), n, p->near_order, dgx, dgw, Ip.as<double>(), ldP, dt[ty].as<int64_t>());
+                hipLaunchKernelGGL(k_near_edge, grid, block, 0, s_, dV, dv[ty].as<int32_t>(), da[ty].as<int32_t>(),
+                                   dbb[ty].as<int32_t>(), n, p_->near_order, dgx, dgw, Ip_.as<double>(), ldP, dt[ty].as<int64_t>());
             else
-                hipLaunchKernelGGL(k_near_vertex, grid, block, 0, s, dV, dv[ty].as<int32_t>(), da[ty].as<int32_t>(),
-                                   dbb[ty].as<int32_t>(), n, p->near_order, dgx, dgw, Ip.as<double>(), ldP, dt[ty].as<int64_t>());
+                hipLaunchKernelGGL(k_near_vertex, grid, block, 0, s_, dV, dv[ty].as<int32_t>(), da[ty].as<int32_t>(),
+                                   dbb[ty].as<int32_t>(), n, p_->near_order, dgx, dgw, Ip_.as<double>(), ldP, dt[ty].as<int64_t>());
             HIP_CHECK(hipGetLastError());
         }
-        P->en->stop();
+        P.en->stop();
         // this panel's tiles of the upper half (the tile lists are sorted by row block)
+        const int64_t bd0 = starts_[pid], bd1 = starts_[pid + 1];
+        // The layout puts every row these tiles read in the panel, and their columns at or past the
+        // panel's first column; both are checked here, since a miss would read outside the buffer.
+        if (cbmin_.empty()) {
+            const int64_t ncb = int64_t(plan.cb_ptr.size()) - 1;
+            cbmin_.assign(static_cast<size_t>(ncb) + 1, nt_);
+            for (int64_t be = ncb - 1; be >= 0; --be)
+                cbmin_[size_t(be)] = std::min<int64_t>(cbmin_[size_t(be) + 1], plan.cb_ptr[size_t(be)] < plan.cb_ptr[size_t(be) + 1]
+                                                                                ? plan.cb_tri[size_t(plan.cb_ptr[size_t(be)])] : nt_);
+        }
+        bool fits = cbmin_[size_t(bd0)] >= t0;
+        for (int64_t rb = 4 * bd0; fits && rb < 4 * bd1; ++rb)
+            for (int32_t g = plan.rg_ptr[size_t(rb)]; g < plan.rg_ptr[size_t(rb) + 1]; ++g)
+                fits = fits && P.rowmap[size_t(plan.rg[size_t(g)].x)] >= 0;
+        if (!fits) fail(BEM_E_DEVICE, "internal error: a pair-matrix panel lacks entries its contraction reads");
         auto range = [&](const std::vector<int2>& v) {
             auto lo = std::lower_bound(v.begin(), v.end(), int(bd0), [](const int2& x, int b) { return x.x < b; });
             auto hi = std::lower_bound(v.begin(), v.end(), int(bd1), [](const int2& x, int b) { return x.x < b; });
             return std::make_pair(int64_t(lo - v.begin()), int64_t(hi - lo));
         };
         const auto rf = range(plan.fast), rs = range(plan.slow);
-        P->ec = std::make_unique<EventTimer>(s);
+        P.ec = std::make_unique<EventTimer>(s_);
         if (rf.second > 0) {
-            hipLaunchKernelGGL(k_contract_staged, dim3(unsigned((rf.second + 7) / 8 * 8)), dim3(256), 0, s, Ip.as<double>(), ldP,
-                               d_rowmap.as<int32_t>(), tmin, N, d_cb_ptr.as<int32_t>(), d_cb_tri.as<int32_t>(),
-                               p->dof_ptr.as<int64_t>(), d_col_loc.as<int32_t>(), dofJ, d_rg_ptr.as<int32_t>(),
-                               d_rg.as<int4>(), d_rg_ent.as<int2>(), d_fast.as<int2>() + rf.first, rf.second,
-                               p->W64.as<double>(), w32, p->ldw);
+            hipLaunchKernelGGL(k_contract_staged, dim3(unsigned((rf.second + 7) / 8 * 8)), dim3(256), 0, s_, Ip_.as<double>(), ldP,
+                               P.d_rowmap.as<int32_t>(), t0, N_, pd.cb_ptr.as<int32_t>(), pd.cb_tri.as<int32_t>(),
+                               p_->dof_ptr.as<int64_t>(), pd.col_loc.as<int32_t>(), dofJ, pd.rg_ptr.as<int32_t>(),
+                               pd.rg.as<int4>(), pd.rg_ent.as<int2>(), pd.fast.as<int2>() + rf.first, rf.second,
+                               p_->W64.as<double>(), w32, p_->ldw);
             HIP_CHECK(hipGetLastError());
         }
         if (rs.second > 0) {
-            hipLaunchKernelGGL(k_contract, dim3(unsigned((rs.second + 7) / 8 * 8)), dim3(256), 0, s, Ip.as<double>(), ldP,
-                               d_rowmap.as<int32_t>(), tmin, N, p->dof_ptr.as<int64_t>(), p->dof_tri.as<int32_t>(), dofJ,
-                               d_slow.as<int2>() + rs.first, rs.second, p->W64.as<double>(), w32, p->ldw);
+            hipLaunchKernelGGL(k_contract, dim3(unsigned((rs.second + 7) / 8 * 8)), dim3(256), 0, s_, Ip_.as<double>(), ldP,
+                               P.d_rowmap.as<int32_t>(), t0, N_, p_->dof_ptr.as<int64_t>(), p_->dof_tri.as<int32_t>(), dofJ,
+                               pd.slow.as<int2>() + rs.first, rs.second, p_->W64.as<double>(), w32, p_->ldw);
             HIP_CHECK(hipGetLastError());
         }
-        P->ec->stop();
-        done.push_back(std::move(P));
+        P.ec->stop();
         mark("panel");
     }
-    for (auto& P : done) {
-        out.far += P->ef->seconds();
-        out.near += P->en->seconds();
-        out.contract += P->ec->seconds();
+
+    // Device times of the three phases over all panels (waits for the last one).
+    PanelTimes times() const {
+        PanelTimes out;
+        for (const auto& P : panels_) {
+            if (!P) continue;
+            out.far += P->ef->seconds();
+            if (P->en) out.near += P->en->seconds();
+            if (P->ec) out.contract += P->ec->seconds();
+        }
+        out.panels = int(rows_.size());
+        return out;
     }
-    out.panels = int(rowsets.size());
-    return out;
-}
+
+  private:
+    struct Panel {   // host arrays stay alive until the end: their uploads are asynchronous
+        int64_t ldP = 0;
+        std::vector<int32_t> rowmap, cstart, nv[4], na[4], nb[4];
+        std::vector<int64_t> tptr, tgt[4];
+        DeviceBuffer d_rowmap;
+        std::unique_ptr<EventTimer> ef, en, ec;
+    };
+    bem_problem* p_;
+    hipStream_t s_;
+    int64_t nt_, N_ = 0;
+    const DofForecast& f_;
+    const double *geo_, *gbounds_, *crec_;
+    std::vector<int64_t> starts_, tmin_;
+    std::vector<std::vector<int32_t>> rows_, rowfirst_;
+    std::vector<std::unique_ptr<Panel>> panels_;
+    std::vector<int64_t> cbmin_;   // smallest triangle of the column lists from each column block on
+    DeviceBuffer Ip_;
+};
 
 }  // namespace
 
@@ -1280,7 +1408,7 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
 
     // pair integrals I (nt x ldI), rows padded to 64 bytes so the far kernel's paired stores stay aligned.
     // When the whole matrix does not fit next to W (about 8 N_T^2 + 3 N_T^2 bytes with N ~ N_T / 2),
-    // or panels are requested, it is built and contracted panel by panel after the mesh analysis.
+    // or panels are requested, it is built and contracted panel by panel.
     const int64_t ldI = (nt + 7) / 8 * 8;
     const size_t free_b = available_device_bytes(p->ctx->device);
     const double full_bytes = 8.0 * double(nt) * double(ldI) + 3.0 * double(nt) * double(nt);
@@ -1313,6 +1441,27 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
         HIP_CHECK(hipGetLastError());
     }
     t_far.stop();
+    // W: every entry, padding columns included, is written by one contraction tile
+    auto allocate_w = [&](int64_t n) {
+        p->ldw = ((n + 63) / 64) * 64;
+        p->W64.reset();
+        p->W32.reset();
+        p->W64 = DeviceBuffer(sizeof(double) * std::max<int64_t>(n, 1) * p->ldw, s);
+        if (p->has_w32) p->W32 = DeviceBuffer(sizeof(float) * std::max<int64_t>(n, 1) * p->ldw, s);
+    };
+    // panels: the dofs per vertex from counts, then W, the panel layout and the first panel's far
+    // pass, all before the sector analysis, which then runs while the device integrates
+    std::unique_ptr<DofForecast> forecast;
+    std::unique_ptr<PanelRun> run;
+    if (paneled) {
+        forecast = std::make_unique<DofForecast>(forecast_dofs(Tin, nv, nt));
+        if (forecast->N > 0) {
+            allocate_w(forecast->N);
+            run = std::make_unique<PanelRun>(p, nt, *forecast, geo.as<double>(), gbounds.as<double>(), crec.as<double>());
+            run->layout(forecast->first_dof, forecast->N);
+            run->far(0);
+        }
+    }
     mark("geometry+far");
 
     // host: mesh analysis, near list, and the plans of the near and contraction passes.  If the
@@ -1357,6 +1506,20 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
     p->t_host = std::chrono::duration<double>(std::chrono::steady_clock::now() - h0).count();
     p->n_near = int64_t(near.t1.size());
     mark("host analysis");
+    // BEM_PANELS_AFTER_ANALYSIS=1 takes this path for every mesh (for tests of it)
+    if (paneled && (N != forecast->N || m.first_dof != forecast->first_dof || std::getenv("BEM_PANELS_AFTER_ANALYSIS"))) {
+        // the analysis numbers the dofs otherwise than the forecast: the panels are planned again
+        // from its numbering, after the first panel's far pass (now of no use) has finished
+        HIP_CHECK(hipStreamSynchronize(s));
+        p->panels_replanned = 1;
+        run.reset();
+        if (N != forecast->N || N == 0) allocate_w(N);
+        if (N > 0) {
+            run = std::make_unique<PanelRun>(p, nt, *forecast, geo.as<double>(), gbounds.as<double>(), crec.as<double>());
+            run->layout(m.first_dof, N);
+            run->far(0);
+        }
+    }
 
     // incidence tables and jump vectors
     p->dof_ptr = upload(m.dof_ptr, s);
@@ -1377,10 +1540,7 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
     }
 
     DeviceBuffer dgx = upload(gx, s), dgw = upload(gw, s);
-    // W: every entry, padding columns included, is written by one contraction tile
-    p->ldw = ((N + 63) / 64) * 64;
-    p->W64 = DeviceBuffer(sizeof(double) * std::max<int64_t>(N, 1) * p->ldw, s);
-    if (p->has_w32) p->W32 = DeviceBuffer(sizeof(float) * std::max<int64_t>(N, 1) * p->ldw, s);
+    if (!paneled || N == 0) allocate_w(N);
     float* w32 = p->has_w32 ? p->W32.as<float>() : nullptr;   // the contraction writes both copies
     EventTimer t_near(s), t_contract(s);
     PanelTimes ptimes;
@@ -1438,9 +1598,13 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
         }
         t_contract.stop();
         mark("contract");
-    } else {
-        ptimes = assemble_panels(p, m, near, plan, geo.as<double>(), gbounds.as<double>(), crec.as<double>(), dVp,
-                                 dgx.as<double>(), dgw.as<double>(), dofJ.as<double>(), w32, mark);
+    } else if (run) {
+        const PlanDevice pd(plan, s);
+        for (size_t pid = 0; pid < run->count(); ++pid) {
+            if (pid > 0) run->far(pid);
+            run->finish(pid, near, pd, plan, dVp, dgx.as<double>(), dgw.as<double>(), dofJ.as<double>(), w32, mark);
+        }
+        ptimes = run->times();
     }
     if (paneled || N == 0) {
         matvec_setup(p, s);

@@ -701,6 +701,7 @@ int bem_problem_get_info(const bem_problem* p, bem_problem_info* info) {
     info->t_host_s = p->t_host;
     info->n_pair_panels = p->n_panels;
     info->dim = p->topo.dim;
+    info->panels_replanned = p->panels_replanned;
     return BEM_OK;
     BEM_CATCH
 }

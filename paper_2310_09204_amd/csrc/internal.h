@@ -206,6 +206,7 @@ struct bem_problem {
     bem::MeshTopo topo;
     int64_t N = 0, ldw = 0, ldI = 0, n_near = 0;
     int64_t panel_rows = 0, n_panels = 0;   // requested rows per pair-matrix panel; panels used
+    int64_t panels_replanned = 0;           // 1: the panels were planned again after the sector analysis
     hipStream_t aux_stream = nullptr;   // second stream of the preconditioner set-up (created on first use)
     bool has_w32 = false, has_pairs = false;
     int near_order = 10;

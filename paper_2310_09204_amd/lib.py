@@ -42,7 +42,8 @@ class ProblemInfo(ctypes.Structure):
                 ("n_near_pairs", ctypes.c_int64), ("bytes_device", ctypes.c_int64),
                 ("q_hist", ctypes.c_int64 * 16), ("t_assemble_s", ctypes.c_double),
                 ("t_far_s", ctypes.c_double), ("t_near_s", ctypes.c_double), ("t_contract_s", ctypes.c_double),
-                ("t_host_s", ctypes.c_double), ("n_pair_panels", ctypes.c_int64), ("dim", ctypes.c_int64)]
+                ("t_host_s", ctypes.c_double), ("n_pair_panels", ctypes.c_int64), ("dim", ctypes.c_int64),
+                ("panels_replanned", ctypes.c_int64)]
 
 
 class Tuning(ctypes.Structure):

@@ -90,6 +90,7 @@ def test_panelled_assembly_matches(ctx, name):
     t = Topology(m.vertices, m.triangles)
     p = lib.Problem(ctx, m.vertices, m.triangles, near_order=NEAR, precision=lib.FP32_REFINE, pair_panel_rows=64)
     assert p.info["n_pair_panels"] > (1 if t.N > 64 else 0)
+    assert p.info["panels_replanned"] == 0   # laid out from the dof forecast, before the analysis
     Wg = p.matrix()
     Wo = assemble(m.vertices, m.triangles, t, NEAR)
     assert np.array_equal(Wg, Wg.T)
@@ -108,7 +109,7 @@ def test_panelled_long_star(ctx):
     print("case panels fan520", m.nt, flush=True)
     t = Topology(m.vertices, m.triangles)
     p = lib.Problem(ctx, m.vertices, m.triangles, near_order=4, pair_panel_rows=64)
-    assert p.info["n_pair_panels"] > 1
+    assert p.info["n_pair_panels"] > 1 and p.info["panels_replanned"] == 0
     Wg = p.matrix()
     Wo = assemble(m.vertices, m.triangles, t, 4)
     assert np.array_equal(Wg, Wg.T)
@@ -121,12 +122,32 @@ def test_panelled_book48_rows(ctx):
     print("case panels book48", m.nt, flush=True)
     pp = lib.Problem(ctx, m.vertices, m.triangles, near_order=NEAR, pair_panel_rows=3000)
     pf = lib.Problem(ctx, m.vertices, m.triangles, near_order=NEAR)
-    assert pp.info["n_pair_panels"] >= 4
+    assert pp.info["n_pair_panels"] >= 4 and pp.info["panels_replanned"] == 0
     rows = np.random.default_rng(4).choice(pp.N, 24, replace=False)
     a, b = pp.rows(rows), pf.rows(rows)
     assert np.abs(a - b).max() <= 1e-13 * np.abs(b).max()
     Wp = pp.matrix()
     assert np.array_equal(Wp, Wp.T)
+
+
+@pytest.mark.parametrize("name", ["book6", "crossed6"])
+def test_panels_planned_after_analysis(ctx, name, monkeypatch):
+    # the path a mesh takes when its sector analysis numbers the dofs otherwise than the forecast
+    # from vertex counts: the first panel's far pass is dropped and the panels are planned again
+    m = small_meshes()[name]
+    print("case panels replanned", name, m.nt, flush=True)
+    t = Topology(m.vertices, m.triangles)
+    monkeypatch.setenv("BEM_PANELS_AFTER_ANALYSIS", "1")
+    p = lib.Problem(ctx, m.vertices, m.triangles, near_order=NEAR, precision=lib.FP32_REFINE, pair_panel_rows=64)
+    monkeypatch.delenv("BEM_PANELS_AFTER_ANALYSIS")
+    assert p.info["panels_replanned"] == 1 and p.info["n_pair_panels"] > 1
+    Wg = p.matrix()
+    Wo = assemble(m.vertices, m.triangles, t, NEAR)
+    assert np.array_equal(Wg, Wg.T)
+    assert np.abs(Wg - Wo).max() / np.abs(Wo).max() < 1e-12
+    q = lib.Problem(ctx, m.vertices, m.triangles, near_order=NEAR, precision=lib.FP32_REFINE, pair_panel_rows=64)
+    assert q.info["panels_replanned"] == 0
+    assert np.array_equal(q.matrix(), Wg)
 
 
 def test_book48_sampled_rows(ctx):

@@ -138,7 +138,7 @@ def c192(ctx):
     print("case crossed192 fixture", m.nt, flush=True)
     ctx.release_cached()
     p = lib.Problem(ctx, m.vertices, m.triangles, near_order=NEAR, precision=lib.FP32_REFINE)
-    assert p.N == 110017 and p.info["n_pair_panels"] >= 2
+    assert p.N == 110017 and p.info["n_pair_panels"] >= 2 and p.info["panels_replanned"] == 0
     M = lib.Preconditioner(p, w.patch_of_triangle, w.coarse.vertices, w.coarse.triangles, w.coarse_of_triangle,
                            factor_fp32=True)
     phi_mx, imx, rc = p.solve(g=w.g, precond=M, tol=1e-10, precision=lib.FP32_REFINE)

@@ -40,6 +40,7 @@ def test_renumbered_problem_equals_caller_order(ctx, panels):
     try:
         N = pk.N
         assert pr.N == N
+        assert pk.info["panels_replanned"] == 0 and pr.info["panels_replanned"] == 0
         dk, dr = pk.dofs(), pr.dofs()
         assert np.array_equal(dk[0], dr[0]) and np.array_equal(dk[1], dr[1])
         Wk, Wr = pk.matrix(), pr.matrix()

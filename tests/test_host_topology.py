@@ -44,6 +44,33 @@ def test_random_extruded_layouts_match_oracle():
         _compare(m)
 
 
+def _sectors_from_counts(V, T):
+    # Euler's formula for the graph that the triangles (arcs) and edges (nodes) at a vertex cut on
+    # a small sphere about it: its faces, the sectors, number T_v - E_v + 2 when it is connected
+    T = np.asarray(T)
+    nv = np.asarray(V).shape[0]
+    tv = np.bincount(T.ravel(), minlength=nv)
+    e = np.sort(np.concatenate([T[:, [0, 1]], T[:, [1, 2]], T[:, [2, 0]]]), axis=1)
+    ev = np.bincount(np.unique(e, axis=0).ravel(), minlength=nv)
+    return np.where(tv > 0, tv - ev + 2, 0)
+
+
+def test_sector_counts_follow_from_vertex_counts():
+    """The assembly lays out its pair-matrix panels before the sector analysis, from the sector
+    count q_v = T_v - E_v + 2 (Section 4.2 numbers q_v - 1 dofs at v).  For meshes the analysis
+    accepts, both give the same q at every vertex: open sheets (q = 1 on the boundary, 2 inside),
+    books and crossings (junction lines), the bow-tie, a disk, and random extruded layouts."""
+    rng = np.random.default_rng(11)
+    ms = [meshes.unit_square(8), meshes.book(6, (0.0, 75.0, 200.0, 300.0)), meshes.crossed(8),
+          meshes.crossed(6, symmetric=True), meshes.bowtie(5), meshes.disk(5), meshes.book(12, (0.0, 100.0, 230.0))]
+    ms += [meshes.random_extruded(rng, 4, lay, 5)[0] for lay in ("book", "chain", "tree")]
+    for m in ms:
+        h = lib.mesh_analyze(m.vertices, m.triangles)
+        q = _sectors_from_counts(m.vertices, m.triangles)
+        assert np.array_equal(np.asarray(h["q"]), q)
+        assert h["n_dofs"] == int(np.maximum(q - 1, 0).sum())
+
+
 def test_workload_dof_counts():
     for name, n in (("square16", 225), ("book48", 6721)):
         w = meshes.workload(name)

@@ -1075,6 +1075,87 @@ DofForecast forecast_dofs(const int32_t* T, int64_t nv, int64_t nt) {
     return f;
 }
 
+// Panels of a dof numbering (first_dof, N dofs): consecutive row blocks whose rows (the triangles
+// at the vertices of the blocks' dofs) number at most maxrows, each panel's first column, and the
+// first column each row is read at.
+struct PanelLayout {
+    std::vector<int64_t> starts;                  // first row block of each panel, then the block count
+    std::vector<int64_t> tmin;                    // each panel's first column (a multiple of 16)
+    std::vector<std::vector<int32_t>> rows;       // each panel's row triangles, ascending
+    std::vector<std::vector<int32_t>> rowfirst;   // per row: the first column a tile of the panel reads it at
+    int64_t max_elems = 1;                        // entries of the largest panel
+};
+
+PanelLayout layout_panels(const std::vector<int64_t>& first_dof, int64_t N, const DofForecast& f, int64_t nt,
+                          int64_t maxrows) {
+    PanelLayout L;
+    const int64_t nv = int64_t(first_dof.size()) - 1;
+    const int64_t ncb = (N + kCT - 1) / kCT;
+    // the vertices of each block's dofs, and the first column (a multiple of 16) that a tile
+    // (bd, be >= bd) can read: every triangle of such a column block lies at a vertex with dofs
+    // from the first dof of bd on
+    auto vertex_of = [&](int64_t d) {
+        return int64_t(std::upper_bound(first_dof.begin(), first_dof.end(), d) - first_dof.begin()) - 1;
+    };
+    std::vector<int64_t> vlo(static_cast<size_t>(ncb)), vhi(static_cast<size_t>(ncb)), col(static_cast<size_t>(ncb));
+    std::vector<int64_t> sm(static_cast<size_t>(nv) + 1, nt);
+    for (int64_t v = nv - 1; v >= 0; --v) {
+        const bool has = first_dof[size_t(v) + 1] > first_dof[size_t(v)] && f.vt_ptr[size_t(v) + 1] > f.vt_ptr[size_t(v)];
+        sm[size_t(v)] = std::min<int64_t>(sm[size_t(v) + 1], has ? f.vt[size_t(f.vt_ptr[size_t(v)])] : nt);
+    }
+    for (int64_t b = 0; b < ncb; ++b) {
+        vlo[size_t(b)] = vertex_of(b * kCT);
+        vhi[size_t(b)] = vertex_of(std::min<int64_t>(N, b * kCT + kCT) - 1);
+        col[size_t(b)] = sm[size_t(vlo[size_t(b)])] / kGrp * kGrp;
+    }
+    std::vector<int32_t> stamp(static_cast<size_t>(nt), -1), first_block(static_cast<size_t>(nt), 0);
+    int64_t b0 = 0;
+    int id = 0;
+    while (b0 < ncb) {
+        std::vector<int32_t> rows, add;
+        int64_t b1 = b0;
+        while (b1 < ncb) {
+            add.clear();
+            for (int64_t v = vlo[size_t(b1)]; v <= vhi[size_t(b1)]; ++v) {
+                if (first_dof[size_t(v) + 1] == first_dof[size_t(v)]) continue;
+                for (int64_t k = f.vt_ptr[size_t(v)]; k < f.vt_ptr[size_t(v) + 1]; ++k) {
+                    const int32_t T = f.vt[size_t(k)];
+                    if (stamp[size_t(T)] != id) {
+                        stamp[size_t(T)] = id;
+                        first_block[size_t(T)] = int32_t(b1);
+                        add.push_back(T);
+                    }
+                }
+            }
+            if (b1 > b0 && int64_t(rows.size() + add.size()) > maxrows) {
+                for (int32_t T : add) stamp[size_t(T)] = -1;
+                break;
+            }
+            rows.insert(rows.end(), add.begin(), add.end());
+            ++b1;
+        }
+        // ascending order: the stamped triangles between the smallest and the largest row
+        if (!rows.empty()) {
+            const int32_t lo = *std::min_element(rows.begin(), rows.end()), hi = *std::max_element(rows.begin(), rows.end());
+            size_t n = 0;
+            for (int32_t T = lo; T <= hi; ++T)
+                if (stamp[size_t(T)] == id) rows[n++] = T;
+        }
+        std::vector<int32_t> firsts(rows.size());
+        for (size_t i = 0; i < rows.size(); ++i) firsts[i] = int32_t(col[size_t(first_block[size_t(rows[i])])]);
+        const int64_t tmin = col[size_t(b0)];
+        L.max_elems = std::max<int64_t>(L.max_elems, int64_t(rows.size()) * ((nt - tmin + 7) / 8 * 8));
+        L.starts.push_back(b0);
+        L.tmin.push_back(tmin);
+        L.rows.push_back(std::move(rows));
+        L.rowfirst.push_back(std::move(firsts));
+        b0 = b1;
+        ++id;
+    }
+    L.starts.push_back(ncb);
+    return L;
+}
+
 // Far-pass tiles of a panel: row tile rb takes the column tiles cstart[rb] .. nct - 1, at positions
 // tptr[rb] .. tptr[rb + 1] - 1 of the list (one block per row tile)
 __global__ void k_rect_tiles(const int32_t* __restrict__ cstart, const int64_t* __restrict__ tptr, int32_t nct,
@@ -1085,27 +1166,59 @@ __global__ void k_rect_tiles(const int32_t* __restrict__ cstart, const int64_t* 
     for (int c = c0 + int(threadIdx.x); c < nct; c += int(blockDim.x)) out[base + (c - c0)] = make_int2(rb, c);
 }
 
+// A second stream for host-to-device copies, so that they run beside the kernels queued on the
+// first: each buffer belongs to the first stream (it is released in that stream's order), and the
+// first stream waits for its copy before anything queued on it later, so no kernel reads it early and
+// no release (an exception's included) precedes the copy.
+struct SideCopies {
+    bem_ctx* ctx;
+    hipStream_t main, side = nullptr;
+    hipEvent_t done = nullptr;
+    SideCopies(bem_ctx* c, hipStream_t s) : ctx(c), main(s) {
+        side = acquire_stream(c);
+        if (hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            release_stream(c, side);
+            fail(BEM_E_DEVICE, "hipEventCreateWithFlags failed");
+        }
+    }
+    template <class T>
+    DeviceBuffer upload(const std::vector<T>& v) {
+        DeviceBuffer b(std::max<size_t>(1, v.size()) * sizeof(T), main);
+        if (!v.empty()) {
+            HIP_CHECK(hipMemcpyAsync(b.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, side));
+            HIP_CHECK(hipEventRecord(done, side));
+            HIP_CHECK(hipStreamWaitEvent(main, done, 0));
+        }
+        return b;
+    }
+    SideCopies(const SideCopies&) = delete;
+    SideCopies& operator=(const SideCopies&) = delete;
+    ~SideCopies() {
+        if (done) (void)hipEventDestroy(done);
+        release_stream(ctx, side);
+    }
+};
+
 // Device copies of the contraction plan, shared by all panels
 struct PlanDevice {
     DeviceBuffer cb_ptr, cb_tri, col_loc, rg_ptr, rg, rg_ent, fast, slow;
-    PlanDevice(const ContractPlan& plan, hipStream_t s)
-        : cb_ptr(upload(plan.cb_ptr, s)), cb_tri(upload(plan.cb_tri, s)), col_loc(upload(plan.col_loc, s)),
-          rg_ptr(upload(plan.rg_ptr, s)), rg(upload(plan.rg, s)), rg_ent(upload(plan.rg_ent, s)),
-          fast(upload(plan.fast, s)), slow(upload(plan.slow, s)) {}
+    explicit PlanDevice(const ContractPlan& plan, SideCopies& up)
+        : cb_ptr(up.upload(plan.cb_ptr)), cb_tri(up.upload(plan.cb_tri)), col_loc(up.upload(plan.col_loc)),
+          rg_ptr(up.upload(plan.rg_ptr)), rg(up.upload(plan.rg)), rg_ent(up.upload(plan.rg_ent)),
+          fast(up.upload(plan.fast)), slow(up.upload(plan.slow)) {}
 };
 
 class PanelRun {
   public:
     PanelRun(bem_problem* p, int64_t nt, const DofForecast& f, const double* geo, const double* gbounds,
-             const double* crec)
-        : p_(p), s_(p->stream), nt_(nt), f_(f), geo_(geo), gbounds_(gbounds), crec_(crec) {}
+             const double* crec, SideCopies& up)
+        : p_(p), s_(p->stream), nt_(nt), f_(f), geo_(geo), gbounds_(gbounds), crec_(crec), up_(up) {}
 
     // Groups the row blocks of a numbering with first_dof (N dofs) into panels and allocates the
     // panel buffer, after W (its size is a share of the memory W leaves).
     void layout(const std::vector<int64_t>& first_dof, int64_t N) {
-        const int64_t nv = int64_t(first_dof.size()) - 1;
         N_ = N;
-        const int64_t ncb = (N + kCT - 1) / kCT;
         int64_t maxrows = p_->panel_rows;
         if (maxrows <= 0) {
             maxrows = int64_t(p_->tune.panel_fraction * double(available_device_bytes(p_->ctx->device)) / (8.0 * double(nt_)));
@@ -1113,81 +1226,21 @@ class PanelRun {
             // the panel buffer of its predecessor back from the pool
             maxrows = maxrows / 2048 * 2048;
         }
-        maxrows = std::max<int64_t>(maxrows, kTile);
-        // the vertices of each block's dofs, and the first column (a multiple of 16) that a tile
-        // (bd, be >= bd) can read: every triangle of such a column block lies at a vertex with dofs
-        // from the first dof of bd on
-        auto vertex_of = [&](int64_t d) {
-            return int64_t(std::upper_bound(first_dof.begin(), first_dof.end(), d) - first_dof.begin()) - 1;
-        };
-        std::vector<int64_t> vlo(static_cast<size_t>(ncb)), vhi(static_cast<size_t>(ncb)), col(static_cast<size_t>(ncb));
-        std::vector<int64_t> sm(static_cast<size_t>(nv) + 1, nt_);
-        for (int64_t v = nv - 1; v >= 0; --v) {
-            const bool has = first_dof[size_t(v) + 1] > first_dof[size_t(v)] && f_.vt_ptr[size_t(v) + 1] > f_.vt_ptr[size_t(v)];
-            sm[size_t(v)] = std::min<int64_t>(sm[size_t(v) + 1], has ? f_.vt[size_t(f_.vt_ptr[size_t(v)])] : nt_);
-        }
-        for (int64_t b = 0; b < ncb; ++b) {
-            vlo[size_t(b)] = vertex_of(b * kCT);
-            vhi[size_t(b)] = vertex_of(std::min<int64_t>(N, b * kCT + kCT) - 1);
-            col[size_t(b)] = sm[size_t(vlo[size_t(b)])] / kGrp * kGrp;
-        }
-        starts_.clear();
-        tmin_.clear();
-        rows_.clear();
-        rowfirst_.clear();
-        std::vector<int32_t> stamp(static_cast<size_t>(nt_), -1), first_block(static_cast<size_t>(nt_), 0);
-        int64_t b0 = 0, max_elems = 1;
-        int id = 0;
-        while (b0 < ncb) {
-            std::vector<int32_t> rows, add;
-            int64_t b1 = b0;
-            while (b1 < ncb) {
-                add.clear();
-                for (int64_t v = vlo[size_t(b1)]; v <= vhi[size_t(b1)]; ++v) {
-                    if (first_dof[size_t(v) + 1] == first_dof[size_t(v)]) continue;
-                    for (int64_t k = f_.vt_ptr[size_t(v)]; k < f_.vt_ptr[size_t(v) + 1]; ++k) {
-                        const int32_t T = f_.vt[size_t(k)];
-                        if (stamp[size_t(T)] != id) {
-                            stamp[size_t(T)] = id;
-                            first_block[size_t(T)] = int32_t(b1);
-                            add.push_back(T);
-                        }
-                    }
-                }
-                if (b1 > b0 && int64_t(rows.size() + add.size()) > maxrows) {
-                    for (int32_t T : add) stamp[size_t(T)] = -1;
-                    break;
-                }
-                rows.insert(rows.end(), add.begin(), add.end());
-                ++b1;
-            }
-            std::sort(rows.begin(), rows.end());
-            std::vector<int32_t> firsts(rows.size());
-            for (size_t i = 0; i < rows.size(); ++i) firsts[i] = int32_t(col[size_t(first_block[size_t(rows[i])])]);
-            const int64_t tmin = col[size_t(b0)];
-            max_elems = std::max<int64_t>(max_elems, int64_t(rows.size()) * ((nt_ - tmin + 7) / 8 * 8));
-            starts_.push_back(b0);
-            tmin_.push_back(tmin);
-            rows_.push_back(std::move(rows));
-            rowfirst_.push_back(std::move(firsts));
-            b0 = b1;
-            ++id;
-        }
-        starts_.push_back(ncb);
+        L_ = layout_panels(first_dof, N, f_, nt_, std::max<int64_t>(maxrows, kTile));
         panels_.clear();
         Ip_.reset();
         // one buffer of the largest panel's size serves all of them (a fresh allocation of tens of
         // GB per panel costs seconds)
-        Ip_ = DeviceBuffer(sizeof(double) * size_t(max_elems), s_);
+        Ip_ = DeviceBuffer(sizeof(double) * size_t(L_.max_elems), s_);
     }
 
-    size_t count() const { return rows_.size(); }
+    size_t count() const { return L_.rows.size(); }
 
     // Queues the far pass of panel pid (panels in order).
     void far(size_t pid) {
         auto P = std::make_unique<Panel>();
-        const std::vector<int32_t>& R = rows_[pid];
-        const int64_t nrows = int64_t(R.size()), t0 = tmin_[pid], ncol = nt_ - t0;
+        const std::vector<int32_t>& R = L_.rows[pid];
+        const int64_t nrows = int64_t(R.size()), t0 = L_.tmin[pid], ncol = nt_ - t0;
         P->ldP = (ncol + 7) / 8 * 8;
         P->rowmap.assign(static_cast<size_t>(nt_), -1);
         for (int64_t r = 0; r < nrows; ++r) P->rowmap[size_t(R[size_t(r)])] = int32_t(r);
@@ -1197,14 +1250,14 @@ class PanelRun {
         for (int64_t rb = 0; rb < nrt; ++rb) {
             int64_t cmin = nt_;
             for (int64_t r = rb * kTile; r < std::min<int64_t>(nrows, rb * kTile + kTile); ++r)
-                cmin = std::min<int64_t>(cmin, rowfirst_[pid][size_t(r)]);
+                cmin = std::min<int64_t>(cmin, L_.rowfirst[pid][size_t(r)]);
             const int64_t cs = std::min<int64_t>(nct, std::max<int64_t>(0, cmin - t0) / kTile);
             P->cstart[size_t(rb)] = int32_t(cs);
             P->tptr[size_t(rb) + 1] = P->tptr[size_t(rb)] + (nct - cs);
         }
         const int64_t nft = P->tptr[size_t(nrt)];
-        DeviceBuffer d_rows = upload(R, s_), d_cs = upload(P->cstart, s_), d_tp = upload(P->tptr, s_);
-        P->d_rowmap = upload(P->rowmap, s_);
+        DeviceBuffer d_rows = up_.upload(R), d_cs = up_.upload(P->cstart), d_tp = up_.upload(P->tptr);
+        P->d_rowmap = up_.upload(P->rowmap);
         DeviceBuffer d_ft(sizeof(int2) * size_t(std::max<int64_t>(nft, 1)), s_);
         if (nft > 0) {
             hipLaunchKernelGGL(k_rect_tiles, dim3(unsigned(nrt)), dim3(256), 0, s_, d_cs.as<int32_t>(), d_tp.as<int64_t>(),
@@ -1228,7 +1281,7 @@ class PanelRun {
     void finish(size_t pid, const NearList& near, const PlanDevice& pd, const ContractPlan& plan, const double* dV,
                 const double* dgx, const double* dgw, const double* dofJ, float* w32, Mark&& mark) {
         Panel& P = *panels_[pid];
-        const int64_t t0 = tmin_[pid], ldP = P.ldP;
+        const int64_t t0 = L_.tmin[pid], ldP = P.ldP;
         // near pairs with a position in this panel (filtered on the host while the far pass runs)
         for (size_t i = 0; i < near.t1.size(); ++i) {
             const int ty = near.type[i];
@@ -1246,10 +1299,10 @@ class PanelRun {
         DeviceBuffer dv[4], da[4], dbb[4], dt[4];
         for (int ty = 1; ty <= 3; ++ty) {
             if (P.na[ty].empty()) continue;
-            dv[ty] = upload(P.nv[ty], s_);
-            da[ty] = upload(P.na[ty], s_);
-            dbb[ty] = upload(P.nb[ty], s_);
-            dt[ty] = upload(P.tgt[ty], s_);
+            dv[ty] = up_.upload(P.nv[ty]);
+            da[ty] = up_.upload(P.na[ty]);
+            dbb[ty] = up_.upload(P.nb[ty]);
+            dt[ty] = up_.upload(P.tgt[ty]);
         }
         P.en = std::make_unique<EventTimer>(s_);
         for (int ty = 1; ty <= 3; ++ty) {
@@ -1269,7 +1322,7 @@ class PanelRun {
         }
         P.en->stop();
         // this panel's tiles of the upper half (the tile lists are sorted by row block)
-        const int64_t bd0 = starts_[pid], bd1 = starts_[pid + 1];
+        const int64_t bd0 = L_.starts[pid], bd1 = L_.starts[pid + 1];
         // The layout puts every row these tiles read in the panel, and their columns at or past the
         // panel's first column; both are checked here, since a miss would read outside the buffer.
         if (cbmin_.empty()) {
@@ -1318,7 +1371,7 @@ class PanelRun {
             if (P->en) out.near += P->en->seconds();
             if (P->ec) out.contract += P->ec->seconds();
         }
-        out.panels = int(rows_.size());
+        out.panels = int(L_.rows.size());
         return out;
     }
 
@@ -1335,8 +1388,8 @@ class PanelRun {
     int64_t nt_, N_ = 0;
     const DofForecast& f_;
     const double *geo_, *gbounds_, *crec_;
-    std::vector<int64_t> starts_, tmin_;
-    std::vector<std::vector<int32_t>> rows_, rowfirst_;
+    SideCopies& up_;
+    PanelLayout L_;
     std::vector<std::unique_ptr<Panel>> panels_;
     std::vector<int64_t> cbmin_;   // smallest triangle of the column lists from each column block on
     DeviceBuffer Ip_;
@@ -1451,13 +1504,14 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
     };
     // panels: the dofs per vertex from counts, then W, the panel layout and the first panel's far
     // pass, all before the sector analysis, which then runs while the device integrates
+    SideCopies up(p->ctx, s);
     std::unique_ptr<DofForecast> forecast;
     std::unique_ptr<PanelRun> run;
     if (paneled) {
         forecast = std::make_unique<DofForecast>(forecast_dofs(Tin, nv, nt));
         if (forecast->N > 0) {
             allocate_w(forecast->N);
-            run = std::make_unique<PanelRun>(p, nt, *forecast, geo.as<double>(), gbounds.as<double>(), crec.as<double>());
+            run = std::make_unique<PanelRun>(p, nt, *forecast, geo.as<double>(), gbounds.as<double>(), crec.as<double>(), up);
             run->layout(forecast->first_dof, forecast->N);
             run->far(0);
         }
@@ -1515,21 +1569,33 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
         run.reset();
         if (N != forecast->N || N == 0) allocate_w(N);
         if (N > 0) {
-            run = std::make_unique<PanelRun>(p, nt, *forecast, geo.as<double>(), gbounds.as<double>(), crec.as<double>());
+            run = std::make_unique<PanelRun>(p, nt, *forecast, geo.as<double>(), gbounds.as<double>(), crec.as<double>(), up);
             run->layout(m.first_dof, N);
             run->far(0);
         }
     }
 
-    // incidence tables and jump vectors
-    p->dof_ptr = upload(m.dof_ptr, s);
-    p->dof_tri = upload(m.dof_tri, s);
-    p->dof_c = upload(m.dof_c, s);
-    DeviceBuffer dof_corner = upload(m.dof_corner, s);
-    p->tri_ptr = upload(m.tri_ptr, s);
-    p->tri_dof = upload(m.tri_dof, s);
-    p->tri_corner = upload(m.tri_corner, s);
-    p->tri_c = upload(m.tri_c, s);
+    // incidence tables, the contraction plan and the near pairs go up beside the far pass
+    p->dof_ptr = up.upload(m.dof_ptr);
+    p->dof_tri = up.upload(m.dof_tri);
+    p->dof_c = up.upload(m.dof_c);
+    DeviceBuffer dof_corner = up.upload(m.dof_corner);
+    p->tri_ptr = up.upload(m.tri_ptr);
+    p->tri_dof = up.upload(m.tri_dof);
+    p->tri_corner = up.upload(m.tri_corner);
+    p->tri_c = up.upload(m.tri_c);
+    DeviceBuffer dgx = up.upload(gx), dgw = up.upload(gw);
+    std::unique_ptr<PlanDevice> pd;
+    if (N > 0) pd = std::make_unique<PlanDevice>(plan, up);
+    DeviceBuffer dv[4], da[4], dbb[4];
+    if (!paneled)
+        for (int ty = 1; ty <= 3; ++ty) {
+            if (na_[ty].empty()) continue;
+            dv[ty] = up.upload(nv_[ty]);
+            da[ty] = up.upload(na_[ty]);
+            dbb[ty] = up.upload(nb_[ty]);
+        }
+    // jump vectors
     const int64_t ne = int64_t(m.dof_tri.size());
     DeviceBuffer dofJ(sizeof(double) * 3 * std::max<int64_t>(ne, 1), s);
     if (ne > 0) {
@@ -1539,20 +1605,12 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
         HIP_CHECK(hipGetLastError());
     }
 
-    DeviceBuffer dgx = upload(gx, s), dgw = upload(gw, s);
     if (!paneled || N == 0) allocate_w(N);
     float* w32 = p->has_w32 ? p->W32.as<float>() : nullptr;   // the contraction writes both copies
     EventTimer t_near(s), t_contract(s);
     PanelTimes ptimes;
     if (!paneled) {
         // near pairs, one kernel per kind
-        DeviceBuffer dv[4], da[4], dbb[4];
-        for (int ty = 1; ty <= 3; ++ty) {
-            if (na_[ty].empty()) continue;
-            dv[ty] = upload(nv_[ty], s);
-            da[ty] = upload(na_[ty], s);
-            dbb[ty] = upload(nb_[ty], s);
-        }
         HIP_CHECK(hipEventRecord(t_near.a, s));
         for (int ty = 1; ty <= 3; ++ty) {
             const int64_t n = int64_t(na_[ty].size());
@@ -1573,25 +1631,21 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
         mark("near");
         HIP_CHECK(hipEventRecord(t_contract.a, s));
         if (N > 0) {
-            DeviceBuffer d_cb_ptr = upload(plan.cb_ptr, s), d_cb_tri = upload(plan.cb_tri, s);
-            DeviceBuffer d_col_loc = upload(plan.col_loc, s), d_rg_ptr = upload(plan.rg_ptr, s);
-            DeviceBuffer d_rg = upload(plan.rg, s), d_rg_ent = upload(plan.rg_ent, s);
-            DeviceBuffer d_fast = upload(plan.fast, s), d_slow = upload(plan.slow, s);
             matvec_setup(p, s);   // its uploads too come before the event the host waits for
             HIP_CHECK(hipEventRecord(t_contract.a, s));
             const int64_t nf = int64_t(plan.fast.size()), ns = int64_t(plan.slow.size());
             if (nf > 0) {
                 hipLaunchKernelGGL(k_contract_staged, dim3(unsigned((nf + 7) / 8 * 8)), dim3(256), 0, s, p->I.as<double>(), ldI,
                                    nullptr, int64_t(0), N,
-                                   d_cb_ptr.as<int32_t>(), d_cb_tri.as<int32_t>(), p->dof_ptr.as<int64_t>(),
-                                   d_col_loc.as<int32_t>(), dofJ.as<double>(), d_rg_ptr.as<int32_t>(), d_rg.as<int4>(),
-                                   d_rg_ent.as<int2>(), d_fast.as<int2>(), nf, p->W64.as<double>(), w32, p->ldw);
+                                   pd->cb_ptr.as<int32_t>(), pd->cb_tri.as<int32_t>(), p->dof_ptr.as<int64_t>(),
+                                   pd->col_loc.as<int32_t>(), dofJ.as<double>(), pd->rg_ptr.as<int32_t>(), pd->rg.as<int4>(),
+                                   pd->rg_ent.as<int2>(), pd->fast.as<int2>(), nf, p->W64.as<double>(), w32, p->ldw);
                 HIP_CHECK(hipGetLastError());
             }
             if (ns > 0) {
                 hipLaunchKernelGGL(k_contract, dim3(unsigned((ns + 7) / 8 * 8)), dim3(256), 0, s, p->I.as<double>(), ldI,
                                    nullptr, int64_t(0), N,
-                                   p->dof_ptr.as<int64_t>(), p->dof_tri.as<int32_t>(), dofJ.as<double>(), d_slow.as<int2>(), ns,
+                                   p->dof_ptr.as<int64_t>(), p->dof_tri.as<int32_t>(), dofJ.as<double>(), pd->slow.as<int2>(), ns,
                                    p->W64.as<double>(), w32, p->ldw);
                 HIP_CHECK(hipGetLastError());
             }
@@ -1599,10 +1653,9 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
         t_contract.stop();
         mark("contract");
     } else if (run) {
-        const PlanDevice pd(plan, s);
         for (size_t pid = 0; pid < run->count(); ++pid) {
             if (pid > 0) run->far(pid);
-            run->finish(pid, near, pd, plan, dVp, dgx.as<double>(), dgw.as<double>(), dofJ.as<double>(), w32, mark);
+            run->finish(pid, near, *pd, plan, dVp, dgx.as<double>(), dgw.as<double>(), dofJ.as<double>(), w32, mark);
         }
         ptimes = run->times();
     }

@@ -187,6 +187,26 @@ void parallel_for(int64_t n, Fn&& fn, int64_t grain = 2048) {
     for (auto& t : th) t.join();
 }
 
+// Sorts [first, first + n) under a strict total order on a few host threads: chunks sorted in
+// parallel, then merged pairwise (a strict total order has one sorted order, whatever the split).
+template <class It, class Less>
+void parallel_sort(It first, int64_t n, Less less, int64_t min_chunk = 16384) {
+    const int64_t nch = std::max<int64_t>(1, std::min<int64_t>(8, n / min_chunk));
+    std::vector<int64_t> cut(static_cast<size_t>(nch) + 1);
+    for (int64_t c = 0; c <= nch; ++c) cut[size_t(c)] = n * c / nch;
+    parallel_for(nch, [&](int64_t cb, int64_t ce) {
+        for (int64_t c = cb; c < ce; ++c) std::sort(first + cut[size_t(c)], first + cut[size_t(c) + 1], less);
+    }, 1);
+    for (int64_t w = 1; w < nch; w *= 2) {
+        std::vector<std::thread> th;
+        for (int64_t c = 0; c + w < nch; c += 2 * w) {
+            const int64_t lo = cut[size_t(c)], mid = cut[size_t(c + w)], hi = cut[size_t(std::min(nch, c + 2 * w))];
+            th.emplace_back([first, &less, lo, mid, hi] { std::inplace_merge(first + lo, first + mid, first + hi, less); });
+        }
+        for (auto& t : th) t.join();
+    }
+}
+
 }  // namespace bem
 
 struct bem_ctx {

@@ -135,25 +135,8 @@ void analyze_mesh(const double* Vin, int64_t nv, const int32_t* Tin, int64_t nt,
                 if (V[3 * a + k] != V[3 * b + k]) return V[3 * a + k] < V[3 * b + k];
             return a < b;
         };
-        // (coordinates, index) is a strict total order, so sorting chunks on threads and merging
-        // them gives the one sorted order
-        const int64_t n = int64_t(order.size());
-        const int64_t nch = std::max<int64_t>(1, std::min<int64_t>(8, n / 16384));
-        std::vector<int64_t> cut(nch + 1);
-        for (int64_t c = 0; c <= nch; ++c) cut[c] = n * c / nch;
-        parallel_for(nch, [&](int64_t cb, int64_t ce) {
-            for (int64_t c = cb; c < ce; ++c) std::sort(order.begin() + cut[c], order.begin() + cut[c + 1], less);
-        }, 1);
-        for (int64_t w = 1; w < nch; w *= 2) {
-            std::vector<std::thread> th;
-            for (int64_t c = 0; c + w < nch; c += 2 * w) {
-                const int64_t lo = cut[c], mid = cut[c + w], hi = cut[std::min(nch, c + 2 * w)];
-                th.emplace_back([&order, &less, lo, mid, hi] {
-                    std::inplace_merge(order.begin() + lo, order.begin() + mid, order.begin() + hi, less);
-                });
-            }
-            for (auto& t : th) t.join();
-        }
+        // (coordinates, index) is a strict total order
+        parallel_sort(order.begin(), int64_t(order.size()), less);
         for (size_t i = 1; i < order.size(); ++i) {
             int64_t a = order[i - 1], b = order[i];
             if (V[3 * a] == V[3 * b] && V[3 * a + 1] == V[3 * b + 1] && V[3 * a + 2] == V[3 * b + 2])
@@ -536,9 +519,9 @@ void locality_order(const double* V, int64_t nv, const int32_t* T, int64_t nt, s
             kt[size_t(t)] = {key(c[0], c[1], c[2]), int32_t(t)};
         }
     });
-    std::thread tv([&] { std::sort(kv.begin(), kv.end()); });
-    std::sort(kt.begin(), kt.end());
-    tv.join();
+    // (key, index) pairs: a strict total order
+    parallel_sort(kv.begin(), nv, std::less<std::pair<uint64_t, int32_t>>());
+    parallel_sort(kt.begin(), nt, std::less<std::pair<uint64_t, int32_t>>());
     vert_user.resize(size_t(nv));
     tri_user.resize(size_t(nt));
     for (int64_t i = 0; i < nv; ++i) vert_user[size_t(i)] = kv[size_t(i)].second;

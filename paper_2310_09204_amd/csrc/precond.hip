@@ -159,36 +159,50 @@ __device__ __forceinline__ void chunk_put(double* __restrict__ st, const double 
 // rows 64 wr .. 64 wr + 63 x columns 32 wc .. 32 wc + 31 as 4 x 2 tiles of 16 x 16; lane l = 16 kk + i
 // supplies A[row i][k kk] and B[k kk][column i] to each 16x16x4 step, and register r of
 // acc[mt][nt] holds C[64 wr + 16 mt + kk + 4 r][32 wc + 16 nt + i].  K runs in chunks of 16 through
-// LDS; the next chunk's loads are in flight while the current one is used.
+// two LDS buffers per operand (sa, sb: 2 x KC2 x LS2 each): chunk c is used from buffer c % 2 while
+// chunk c + 1 is staged into the other one and chunk c + 2 is loaded into registers, one barrier
+// per chunk.
 __device__ __forceinline__ void gemm128(f64x4 (&acc)[4][2], const Opnd& A, const Opnd& B, double* __restrict__ sa,
                                         double* __restrict__ sb) {
+    constexpr int NCH = TB2 / KC2;
+    constexpr int BUF = KC2 * LS2;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int i = lane & 15, kk = lane >> 4;
     const int wr = w >> 2, wc = w & 3;
     double va[4], vb[4];
     chunk_fetch(va, A, 0);
     chunk_fetch(vb, B, 0);
-    for (int c = 0; c < TB2 / KC2; ++c) {
-        __syncthreads();   // the previous chunk's reads are done
-        chunk_put(sa, va, A);
-        chunk_put(sb, vb, B);
-        __syncthreads();
-        if (c + 1 < TB2 / KC2) {
-            chunk_fetch(va, A, (c + 1) * KC2);
-            chunk_fetch(vb, B, (c + 1) * KC2);
-        }
+    __syncthreads();   // earlier readers of the buffers are done
+    chunk_put(sa, va, A);
+    chunk_put(sb, vb, B);
+    chunk_fetch(va, A, KC2);
+    chunk_fetch(vb, B, KC2);
+    __syncthreads();
+    for (int c = 0; c < NCH; ++c) {
+        const double* ca = sa + (c & 1) * BUF;
+        const double* cb = sb + (c & 1) * BUF;
 #pragma unroll
         for (int ks = 0; ks < KC2 / 4; ++ks) {
             const int k = 4 * ks + kk;
             double a[4], b[2];
 #pragma unroll
-            for (int m = 0; m < 4; ++m) a[m] = sa[k * LS2 + 64 * wr + 16 * m + i];
+            for (int m = 0; m < 4; ++m) a[m] = ca[k * LS2 + 64 * wr + 16 * m + i];
 #pragma unroll
-            for (int n = 0; n < 2; ++n) b[n] = sb[k * LS2 + 32 * wc + 16 * n + i];
+            for (int n = 0; n < 2; ++n) b[n] = cb[k * LS2 + 32 * wc + 16 * n + i];
 #pragma unroll
             for (int m = 0; m < 4; ++m)
 #pragma unroll
                 for (int n = 0; n < 2; ++n) acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[n], acc[m][n], 0, 0, 0);
+        }
+        if (c + 1 < NCH) {
+            // the other buffer was last read in chunk c - 1, before the previous barrier
+            chunk_put(sa + ((c + 1) & 1) * BUF, va, A);
+            chunk_put(sb + ((c + 1) & 1) * BUF, vb, B);
+            __syncthreads();
+            if (c + 2 < NCH) {
+                chunk_fetch(va, A, (c + 2) * KC2);
+                chunk_fetch(vb, B, (c + 2) * KC2);
+            }
         }
     }
 }
@@ -360,7 +374,7 @@ __global__ __launch_bounds__(NT2) void k_gj_pivot0(const int4* __restrict__ task
 // step k, task (b, k, j), j != k: the staging for column j
 __global__ __launch_bounds__(NT2) void k_gj_row(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
                                                 double* __restrict__ A, double* __restrict__ scr, int64_t pivot_off, int k) {
-    __shared__ double sa[KC2 * LS2], sb[KC2 * LS2];
+    __shared__ double sa[2 * KC2 * LS2], sb[2 * KC2 * LS2];
     const int4 t = tasks[blockIdx.x];
     const BlockMeta m = meta[t.x];
     const int j = t.z;
@@ -388,7 +402,7 @@ __global__ __launch_bounds__(NT2) void k_gj_row(const int4* __restrict__ tasks, 
 // row tile (i = k > j), column tile (i > k = j) or pivot inverse (i = j = k).
 __global__ __launch_bounds__(NT2, 4) void k_gj_update(const int4* __restrict__ tasks, const BlockMeta* __restrict__ meta,
                                                       double* __restrict__ A, double* __restrict__ scr, int64_t pivot_off, int k) {
-    __shared__ double sa[KC2 * LS2], sb[KC2 * LS2];
+    __shared__ double sa[2 * KC2 * LS2], sb[2 * KC2 * LS2];
     const int4 t = tasks[blockIdx.x];
     const BlockMeta m = meta[t.x];
     const int i = t.y, j = t.z;

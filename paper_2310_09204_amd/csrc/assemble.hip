@@ -1511,6 +1511,7 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
         forecast = std::make_unique<DofForecast>(forecast_dofs(Tin, nv, nt));
         if (forecast->N > 0) {
             allocate_w(forecast->N);
+            matvec_setup(p, s);   // the products' tile lists go with W (only the geometry is queued yet)
             run = std::make_unique<PanelRun>(p, nt, *forecast, geo.as<double>(), gbounds.as<double>(), crec.as<double>(), up);
             run->layout(forecast->first_dof, forecast->N);
             run->far(0);
@@ -1569,6 +1570,7 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
         run.reset();
         if (N != forecast->N || N == 0) allocate_w(N);
         if (N > 0) {
+            if (N != forecast->N) matvec_setup(p, s);
             run = std::make_unique<PanelRun>(p, nt, *forecast, geo.as<double>(), gbounds.as<double>(), crec.as<double>(), up);
             run->layout(m.first_dof, N);
             run->far(0);
@@ -1660,7 +1662,7 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
         ptimes = run->times();
     }
     if (paneled || N == 0) {
-        matvec_setup(p, s);
+        if (!run) matvec_setup(p, s);   // panels set the products up with W
         HIP_CHECK(hipStreamSynchronize(s));
     } else {
         // The host returns once the inputs are consumed: the event before the contraction follows

@@ -130,6 +130,27 @@ def test_panelled_book48_rows(ctx):
     assert np.array_equal(Wp, Wp.T)
 
 
+def test_panels_with_unused_vertices_and_without_dofs(ctx):
+    # vertices that no triangle uses (no dofs, no rows) in the middle of the numbering leave W as it
+    # is, and a mesh whose vertices all lie on the screen's boundary has no dofs and no panels
+    m = small_meshes()["book6"]
+    V, T = np.asarray(m.vertices), np.asarray(m.triangles)
+    k = V.shape[0] // 2
+    V2 = np.vstack([V[:k], [[0.31, 0.47, 0.59], [0.13, 0.71, 0.23]], V[k:]])
+    T2 = np.where(T >= k, T + 2, T).astype(np.int32)
+    print("case panels unused vertices", flush=True)
+    ref = lib.Problem(ctx, V, T, near_order=NEAR, pair_panel_rows=64)
+    p = lib.Problem(ctx, V2, T2, near_order=NEAR, pair_panel_rows=64)
+    assert p.N == ref.N and p.info["panels_replanned"] == 0 and p.info["n_pair_panels"] > 1
+    Wr = ref.matrix()
+    assert np.abs(p.matrix() - Wr).max() <= 1e-13 * np.abs(Wr).max()
+    e = lib.Problem(ctx, np.array([[0.0, 0, 0], [1, 0, 0], [0, 1, 0]]), np.array([[0, 1, 2]], dtype=np.int32),
+                    pair_panel_rows=64)
+    assert e.N == 0 and e.info["n_pair_panels"] == 0 and e.info["panels_replanned"] == 0
+    for x in (ref, p, e):
+        x.close()
+
+
 @pytest.mark.parametrize("name", ["book6", "crossed6"])
 def test_panels_planned_after_analysis(ctx, name, monkeypatch):
     # the path a mesh takes when its sector analysis numbers the dofs otherwise than the forecast

@@ -78,10 +78,11 @@ typedef struct {
     int64_t bytes_device;    /* device memory held by the problem */
     int64_t q_hist[16];      /* number of vertices with q sectors (q >= 15 in the last bin) */
     double t_assemble_s;     /* wall time of bem_assemble: it returns once the device has consumed the
-                                inputs; the contraction into W may still run (later calls on the problem
-                                queue behind it, and the copy calls wait for it) */
-    double t_far_s, t_near_s, t_contract_s; /* device time of the three assembly phases (t_contract_s
-                                                NaN while the contraction still runs) */
+                                inputs; the contraction into W (panel-by-panel assembly: the panels)
+                                may still run (later calls on the problem queue behind it, and the
+                                copy calls wait for it) */
+    double t_far_s, t_near_s, t_contract_s; /* device time of the three assembly phases (NaN while that
+                                                device work still runs) */
     double t_host_s;         /* host time of the mesh analysis and near-pair list */
     int64_t n_pair_panels;   /* panels the pair matrix was built in (0: in one piece) */
     int64_t dim;             /* 3: triangle mesh (n_tri triangles); 2: segment mesh (n_tri segments) */

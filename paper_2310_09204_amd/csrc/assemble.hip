@@ -1362,6 +1362,22 @@ class PanelRun {
         mark("panel");
     }
 
+    // The event pairs of every panel (far pass, near pairs, contraction, in that order), handed over
+    // to be read once the device work has finished.
+    std::vector<hipEvent_t> take_events() {
+        std::vector<hipEvent_t> ev;
+        for (auto& P : panels_) {
+            if (!P) continue;
+            for (EventTimer* t : {P->ef.get(), P->en.get(), P->ec.get()}) {
+                if (!t) continue;
+                ev.push_back(t->a);
+                ev.push_back(t->b);
+                t->a = t->b = nullptr;
+            }
+        }
+        return ev;
+    }
+
     // Device times of the three phases over all panels (waits for the last one).
     PanelTimes times() const {
         PanelTimes out;
@@ -1439,18 +1455,17 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
     triangle7_rule(bary, w7);
     std::vector<double> hb(&bary[0][0], &bary[0][0] + 21), hw(w7, w7 + 7);
 
-    // the kernels read the device copies of the mesh: the caller's, or uploaded here
-    DeviceBuffer dVbuf, dTbuf;
-    if (!dVin) {
-        dVbuf = DeviceBuffer(sizeof(double) * 3 * nv, s);
-        HIP_CHECK(hipMemcpyAsync(dVbuf.ptr, Vin, dVbuf.bytes, hipMemcpyHostToDevice, s));
-    }
-    if (!dTin) {
-        dTbuf = DeviceBuffer(sizeof(int32_t) * 3 * nt, s);
-        HIP_CHECK(hipMemcpyAsync(dTbuf.ptr, Tin, dTbuf.bytes, hipMemcpyHostToDevice, s));
-    }
-    const double* dVp = dVin ? dVin : dVbuf.as<double>();
-    const int32_t* dTp = dTin ? dTin : dTbuf.as<int32_t>();
+    // the kernels read device copies of the mesh that the call owns (copied from the caller's device
+    // arrays, or uploaded), so that the call may return while its kernels still run
+    DeviceBuffer dVbuf(sizeof(double) * 3 * nv, s), dTbuf(sizeof(int32_t) * 3 * nt, s);
+    HIP_CHECK(hipMemcpyAsync(dVbuf.ptr, dVin ? static_cast<const void*>(dVin) : static_cast<const void*>(Vin), dVbuf.bytes,
+                             dVin ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    HIP_CHECK(hipMemcpyAsync(dTbuf.ptr, dTin ? static_cast<const void*>(dTin) : static_cast<const void*>(Tin), dTbuf.bytes,
+                             dTin ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    EventTimer inputs_read(s);   // its end: the caller's device arrays have been read
+    inputs_read.stop();
+    const double* dVp = dVbuf.as<double>();
+    const int32_t* dTp = dTbuf.as<int32_t>();
     DeviceBuffer db = upload(hb, s), dw = upload(hw, s);
     DeviceBuffer geo(sizeof(double) * nt * kGeo, s);
     p->normal = DeviceBuffer(sizeof(double) * nt * 3, s);
@@ -1659,10 +1674,19 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
             if (pid > 0) run->far(pid);
             run->finish(pid, near, *pd, plan, dVp, dgx.as<double>(), dgw.as<double>(), dofJ.as<double>(), w32, mark);
         }
-        ptimes = run->times();
+        ptimes.panels = int(run->count());
+        // The host returns with the panels' device work queued (behind it the host-side work of the
+        // next call, e.g. the preconditioner's, overlaps it): every later call on the problem queues
+        // behind it on the problem's stream.  The uploads have read their host arrays, the caller's
+        // device arrays have been copied, and the phases' device times are read when asked for.
+        p->ev_spans = run->take_events();
+        HIP_CHECK(hipStreamSynchronize(up.side));
+        HIP_CHECK(hipEventSynchronize(inputs_read.b));
     }
-    if (paneled || N == 0) {
-        if (!run) matvec_setup(p, s);   // panels set the products up with W
+    if (run) {
+        // (returns below without waiting for the device)
+    } else if (paneled || N == 0) {
+        matvec_setup(p, s);
         HIP_CHECK(hipStreamSynchronize(s));
     } else {
         // The host returns once the inputs are consumed: the event before the contraction follows
@@ -1672,8 +1696,8 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
         HIP_CHECK(hipEventSynchronize(t_contract.a));
     }
     if (!p->has_pairs) p->I.reset();   // released in stream order, after the contraction
-    p->t_far = paneled ? ptimes.far : t_far.seconds();
-    p->t_near = paneled ? ptimes.near : t_near.seconds();
+    p->t_far = paneled ? 0.0 : t_far.seconds();    // panels: from p->ev_spans when asked for
+    p->t_near = paneled ? 0.0 : t_near.seconds();
     if (paneled || N == 0) {
         p->t_contract = paneled ? ptimes.contract : t_contract.seconds();
     } else {   // read when the problem's information is first asked for

@@ -659,6 +659,8 @@ void bem_problem_destroy(bem_problem* p) {
     if (p->aux_stream) (void)hipStreamSynchronize(p->aux_stream);
     for (hipEvent_t& e : p->ev_contract)
         if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : p->ev_spans)
+        if (e) (void)hipEventDestroy(e);
     hipStream_t s = p->stream, s2 = p->aux_stream;
     bem_ctx* ctx = p->ctx;
     delete p;
@@ -678,9 +680,31 @@ int bem_problem_get_info(const bem_problem* p, bem_problem_info* info) {
     info->bytes_device = p->bytes;
     for (int32_t q : p->topo.q) info->q_hist[std::min(q, 15)] += 1;
     info->t_assemble_s = p->t_assemble;
-    info->t_far_s = p->t_far;
-    info->t_near_s = p->t_near;
     std::lock_guard<std::mutex> lk(p->info_mu);
+    if (!p->ev_spans.empty()) {   // the panels' phase times, once the last contraction has finished
+        set_device(p->ctx);
+        const hipError_t q = hipEventQuery(p->ev_spans.back());
+        if (q == hipSuccess) {
+            double t[3] = {0.0, 0.0, 0.0};
+            for (size_t i = 0; i + 1 < p->ev_spans.size(); i += 2) {
+                float ms = 0.f;
+                HIP_CHECK(hipEventElapsedTime(&ms, p->ev_spans[i], p->ev_spans[i + 1]));
+                t[(i / 2) % 3] += ms * 1e-3;
+            }
+            p->t_far = t[0];
+            p->t_near = t[1];
+            p->t_contract = t[2];
+            for (hipEvent_t e : p->ev_spans) (void)hipEventDestroy(e);
+            p->ev_spans.clear();
+        } else if (q == hipErrorNotReady) {
+            (void)hipGetLastError();
+        } else {
+            HIP_CHECK(q);
+        }
+    }
+    const bool pending = !p->ev_spans.empty();
+    info->t_far_s = pending ? std::nan("") : p->t_far;
+    info->t_near_s = pending ? std::nan("") : p->t_near;
     if (p->ev_contract[1]) {   // the contraction's time, once it has finished (the call never waits)
         set_device(p->ctx);
         const hipError_t q = hipEventQuery(p->ev_contract[1]);
@@ -697,7 +721,7 @@ int bem_problem_get_info(const bem_problem* p, bem_problem_info* info) {
             HIP_CHECK(q);
         }
     }
-    info->t_contract_s = p->ev_contract[1] ? std::nan("") : p->t_contract;
+    info->t_contract_s = (p->ev_contract[1] || pending) ? std::nan("") : p->t_contract;
     info->t_host_s = p->t_host;
     info->n_pair_panels = p->n_panels;
     info->dim = p->topo.dim;

@@ -245,11 +245,13 @@ struct bem_problem {
     // double-layer potential: per-triangle records (normal, Gauss points, n . y) and the 7-point rule,
     // built on the first evaluation
     bem::DeviceBuffer dl_rec, dl_rule;
-    double t_assemble = 0, t_far = 0, t_near = 0, t_host = 0;
-    // device time of the contraction: bem_assemble returns while it still runs, so its two events
-    // are kept and read when the information is first asked for
-    mutable double t_contract = 0;
+    double t_assemble = 0, t_host = 0;
+    // device times of the assembly phases: bem_assemble returns while the contraction (whole pair
+    // matrix) or the panels still run, so their events are kept and read when the information is
+    // first asked for
+    mutable double t_far = 0, t_near = 0, t_contract = 0;
     mutable hipEvent_t ev_contract[2] = {nullptr, nullptr};
+    mutable std::vector<hipEvent_t> ev_spans;   // panels: (far, near, contraction) start/end pairs
     mutable std::mutex info_mu;   // bem_problem_get_info may be called from several threads
     // calls that queue work using the problem's shared scratch (products, solves, preconditioner
     // applications, potentials) take this lock, so two threads calling on one problem serialise

@@ -341,8 +341,8 @@ class Problem:
 
     @property
     def info(self):
-        """bem_problem_get_info, read at each access (t_contract_s is NaN while the contraction that
-        bem_assemble leaves running has not finished)."""
+        """bem_problem_get_info, read at each access (the phase times t_far_s, t_near_s and
+        t_contract_s are NaN while device work that bem_assemble leaves running has not finished)."""
         return self.get_info()
 
     def get_info(self):

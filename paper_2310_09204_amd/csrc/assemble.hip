@@ -22,6 +22,7 @@
 // 1/|x-y| the integrand is a polynomial of degree <= 2 in those variables, which Gauss-Legendre
 // integrates exactly from 2 points on, so dropping them changes nothing but rounding.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -1440,10 +1441,17 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
     // mesh the analysis rejects leaves only discarded device work behind.  Indices and referenced
     // coordinates are checked here so that no kernel can read outside the vertex array.
     bool launchable = Vin && Tin && nv > 0 && nt > 0 && nt <= (int64_t(1) << 30);
-    for (int64_t i = 0; launchable && i < 3 * nt; ++i) {
-        const int32_t v = Tin[i];
-        launchable = v >= 0 && v < nv && std::isfinite(Vin[3 * v]) && std::isfinite(Vin[3 * v + 1]) &&
-                     std::isfinite(Vin[3 * v + 2]);
+    if (launchable) {
+        std::atomic<bool> bad{false};
+        parallel_for(3 * nt, [&](int64_t lo, int64_t hi) {
+            for (int64_t i = lo; i < hi; ++i) {
+                const int32_t v = Tin[i];
+                if (!(v >= 0 && v < nv && std::isfinite(Vin[3 * v]) && std::isfinite(Vin[3 * v + 1]) &&
+                      std::isfinite(Vin[3 * v + 2])))
+                    bad = true;
+            }
+        }, 1 << 16);
+        launchable = !bad;
     }
     if (!launchable) {
         NearList unused;

@@ -1,4 +1,5 @@
 // C-ABI entry points of libbem: argument checks, handle lifetimes, error codes, host<->device copies.
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -521,8 +522,18 @@ int bem_assemble_dev(bem_ctx* ctx, const double* vertices, const double* d_verti
     p->stream = acquire_stream(ctx);
     // locality order of a valid mesh (an invalid one is analysed as given, which reports its error)
     bool valid = vertices && triangles && nv > 0 && nt > 0 && nt <= (int64_t(1) << 30) && nv <= INT32_MAX;
-    for (int64_t i = 0; valid && i < 3 * nv; ++i) valid = std::isfinite(vertices[i]);
-    for (int64_t i = 0; valid && i < 3 * nt; ++i) valid = triangles[i] >= 0 && triangles[i] < nv;
+    if (valid) {
+        std::atomic<bool> bad{false};
+        parallel_for(3 * nv, [&](int64_t lo, int64_t hi) {
+            for (int64_t i = lo; i < hi; ++i)
+                if (!std::isfinite(vertices[i])) bad = true;
+        }, 1 << 16);
+        parallel_for(3 * nt, [&](int64_t lo, int64_t hi) {
+            for (int64_t i = lo; i < hi; ++i)
+                if (triangles[i] < 0 || triangles[i] >= nv) bad = true;
+        }, 1 << 16);
+        valid = !bad;
+    }
     std::vector<double> Vint;
     std::vector<int32_t> Tint, vert_int;
     DeviceBuffer dVint, dTint;
@@ -530,15 +541,21 @@ int bem_assemble_dev(bem_ctx* ctx, const double* vertices, const double* d_verti
         locality_order(vertices, nv, triangles, nt, p->vert_user, p->tri_user);
         vert_int.resize(size_t(nv));
         p->tri_int.resize(size_t(nt));
-        for (int64_t i = 0; i < nv; ++i) vert_int[size_t(p->vert_user[size_t(i)])] = int32_t(i);
-        for (int64_t t = 0; t < nt; ++t) p->tri_int[size_t(p->tri_user[size_t(t)])] = int32_t(t);
         Vint.resize(size_t(3 * nv));
         Tint.resize(size_t(3 * nt));
-        for (int64_t i = 0; i < nv; ++i)
-            for (int c = 0; c < 3; ++c) Vint[size_t(3 * i + c)] = vertices[3 * int64_t(p->vert_user[size_t(i)]) + c];
-        for (int64_t t = 0; t < nt; ++t)
-            for (int a = 0; a < 3; ++a)
-                Tint[size_t(3 * t + a)] = vert_int[size_t(triangles[3 * int64_t(p->tri_user[size_t(t)]) + a])];
+        parallel_for(nv, [&](int64_t lo, int64_t hi) {
+            for (int64_t i = lo; i < hi; ++i) {
+                vert_int[size_t(p->vert_user[size_t(i)])] = int32_t(i);
+                for (int c = 0; c < 3; ++c) Vint[size_t(3 * i + c)] = vertices[3 * int64_t(p->vert_user[size_t(i)]) + c];
+            }
+        }, 8192);
+        parallel_for(nt, [&](int64_t lo, int64_t hi) {
+            for (int64_t t = lo; t < hi; ++t) {
+                p->tri_int[size_t(p->tri_user[size_t(t)])] = int32_t(t);
+                for (int a = 0; a < 3; ++a)
+                    Tint[size_t(3 * t + a)] = vert_int[size_t(triangles[3 * int64_t(p->tri_user[size_t(t)]) + a])];
+            }
+        }, 8192);
         p->renumbered = true;
     }
     const double* Vp = p->renumbered ? Vint.data() : vertices;

@@ -1027,7 +1027,6 @@ ContractPlan contract_plan(const MeshTopo& m) {
 // gets from counts: the first panel's far pass is queued before the host's sector analysis and
 // runs while the host analyses the mesh, and the host filters each panel's near pairs while that
 // panel's far pass runs.
-struct PanelTimes { double far = 0, near = 0, contract = 0; int panels = 0; };
 
 // Dofs of each vertex before the sector analysis (Section 4.2: q_v sectors, q_v - 1 dofs).  Near a
 // vertex v of a conforming multiscreen without point contacts, the triangles and edges at v cut a
@@ -1379,19 +1378,6 @@ class PanelRun {
         return ev;
     }
 
-    // Device times of the three phases over all panels (waits for the last one).
-    PanelTimes times() const {
-        PanelTimes out;
-        for (const auto& P : panels_) {
-            if (!P) continue;
-            out.far += P->ef->seconds();
-            if (P->en) out.near += P->en->seconds();
-            if (P->ec) out.contract += P->ec->seconds();
-        }
-        out.panels = int(L_.rows.size());
-        return out;
-    }
-
   private:
     struct Panel {   // host arrays stay alive until the end: their uploads are asynchronous
         int64_t ldP = 0;
@@ -1633,7 +1619,7 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
     if (!paneled || N == 0) allocate_w(N);
     float* w32 = p->has_w32 ? p->W32.as<float>() : nullptr;   // the contraction writes both copies
     EventTimer t_near(s), t_contract(s);
-    PanelTimes ptimes;
+    int n_panels = 0;
     if (!paneled) {
         // near pairs, one kernel per kind
         HIP_CHECK(hipEventRecord(t_near.a, s));
@@ -1682,7 +1668,7 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
             if (pid > 0) run->far(pid);
             run->finish(pid, near, *pd, plan, dVp, dgx.as<double>(), dgw.as<double>(), dofJ.as<double>(), w32, mark);
         }
-        ptimes.panels = int(run->count());
+        n_panels = int(run->count());
         // The host returns with the panels' device work queued (behind it the host-side work of the
         // next call, e.g. the preconditioner's, overlaps it): every later call on the problem queues
         // behind it on the problem's stream.  The uploads have read their host arrays, the caller's
@@ -1692,8 +1678,8 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
         HIP_CHECK(hipEventSynchronize(inputs_read.b));
     }
     if (run) {
-        // (returns below without waiting for the device)
-    } else if (paneled || N == 0) {
+        // panels: nothing more to wait for (above)
+    } else if (paneled || N == 0) {   // no dofs
         matvec_setup(p, s);
         HIP_CHECK(hipStreamSynchronize(s));
     } else {
@@ -1707,13 +1693,13 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
     p->t_far = paneled ? 0.0 : t_far.seconds();    // panels: from p->ev_spans when asked for
     p->t_near = paneled ? 0.0 : t_near.seconds();
     if (paneled || N == 0) {
-        p->t_contract = paneled ? ptimes.contract : t_contract.seconds();
+        p->t_contract = paneled ? 0.0 : t_contract.seconds();
     } else {   // read when the problem's information is first asked for
         p->ev_contract[0] = t_contract.a;
         p->ev_contract[1] = t_contract.b;
         t_contract.a = t_contract.b = nullptr;
     }
-    p->n_panels = paneled ? ptimes.panels : 0;
+    p->n_panels = n_panels;
 }
 
 void rhs_device(const bem_problem* p, const double* d_g, int k, double* d_L, hipStream_t s) {

@@ -403,7 +403,8 @@ def timed_workload(lib, meshes, ctx, name, k, steps, warmup, tol, mixed, extras=
         "relerr_reference": "FP64 GPU PCG of the same system at relative residual 1e-13 (self-consistency; "
                             "oracle parity: cpu_baseline.oracle_residual_rows and the GPU tests)",
         "patches": ref["precond_sizes"],
-        "pair_integrals_per_s": pairs / float(np.mean([r["t_assemble"] for r in res])),
+        # pairs per second of the assembly's device time (the call returns before it ends)
+        "pair_integrals_per_s": pairs / float(np.mean([r["t_far"] + r["t_near"] + r["t_contract"] for r in res])),
         "pair_integrals_per_s_far_kernel": far_pairs / t_far,
         "roofline": {
             "kernel": far_kernel, "bound": "alu",
@@ -436,6 +437,15 @@ def timed_workload(lib, meshes, ctx, name, k, steps, warmup, tol, mixed, extras=
             t32_16 = p.bench_matvec(fp32=True, k=16, reps=3)
             mv.update(matvec_rates(N, 4, t32_1, "fp32_k1", ks32))
             mv.update(matvec_rates(N, 4, t32_16, "fp32_k16", ks32))
+        # both set-ups timed on the finished problem; the diagonal step is the timed step with the
+        # exact set-up and solve replaced by these (the timed steps' t_precond also holds the end of
+        # the assembly's device work)
+        ctx.synchronize()
+        te0 = time.perf_counter()
+        Me = lib.Preconditioner(p, w.patch_of_triangle, w.coarse.vertices, w.coarse.triangles, w.coarse_of_triangle,
+                                factor_fp32=mixed)
+        te1 = time.perf_counter()
+        Me.close()
         t0 = time.perf_counter()
         Md = lib.Preconditioner(p, w.patch_of_triangle, w.coarse.vertices, w.coarse.triangles, w.coarse_of_triangle,
                                 factor_fp32=mixed, wirebasket="diagonal")
@@ -443,7 +453,9 @@ def timed_workload(lib, meshes, ctx, name, k, steps, warmup, tol, mixed, extras=
         phid, infod, _ = p.solve(g=w.g, precond=Md, tol=tol, precision=prec)
         t2 = time.perf_counter()
         errd = np.linalg.norm(phid - phi_ref, axis=1) / np.linalg.norm(phi_ref, axis=1)
-        t_stepd = out["phases_s"]["t_assemble"] + (t1 - t0) + (t2 - t1)
+        ph = out["phases_s"]
+        t_stepd = ph["t_step"] - (te1 - te0) - ph["t_solve"] + (t1 - t0) + (t2 - t1)
+        out["exact_wirebasket_setup_s"] = te1 - te0
         out["diagonal_wirebasket"] = {"t_precond_s": t1 - t0, "t_solve_s": t2 - t1, "t_step_s": t_stepd,
                                       "iters": [i["iters"] for i in infod], "relerr_max": float(errd.max()),
                                       "solves_per_s": int((errd <= 1e-8).sum()) / t_stepd}

@@ -32,6 +32,32 @@ def test_device_mesh_and_solution_match_host_entry_points(ctx, precision):
         x.close()
 
 
+def test_panel_assembly_returns_before_its_panels(ctx):
+    # in panel mode bem_assemble returns with the panels queued: the caller's device mesh may go at
+    # once (the call copied it), later calls queue behind the panels, and the phase times are NaN
+    # until the panels have finished
+    m = meshes.crossed(24)
+    print("case early return panels crossed24", flush=True)
+    dV, dT = lib.DeviceArray(np.asarray(m.vertices, dtype=np.float64)), lib.DeviceArray(np.asarray(m.triangles, dtype=np.int32))
+    p = lib.Problem(ctx, m.vertices, m.triangles, near_order=4, device_mesh=(dV.ptr, dT.ptr), pair_panel_rows=512,
+                    keep_order=True)
+    dV.close()
+    dT.close()
+    t0 = p.info
+    assert all(np.isnan(t0[k]) or t0[k] > 0 for k in ("t_far_s", "t_near_s", "t_contract_s"))
+    assert t0["n_pair_panels"] > 1
+    W = p.matrix()
+    ref = lib.Problem(ctx, m.vertices, m.triangles, near_order=4, pair_panel_rows=512, keep_order=True)
+    ctx.synchronize()
+    assert np.array_equal(W, ref.matrix())
+    i1 = p.info
+    assert i1["t_far_s"] > 0 and i1["t_near_s"] > 0 and i1["t_contract_s"] > 0
+    x = np.random.default_rng(4).standard_normal((3, p.N))
+    assert np.array_equal(p.matvec(x), ref.matvec(x))
+    p.close()
+    ref.close()
+
+
 def test_assembly_returns_before_its_contraction(ctx):
     # bem_assemble may return while the contraction into W still runs: the copy calls wait for it,
     # later calls queue behind it, and its device time is reported once it has finished

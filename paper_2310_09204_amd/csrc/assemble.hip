@@ -1195,6 +1195,7 @@ struct SideCopies {
     SideCopies(const SideCopies&) = delete;
     SideCopies& operator=(const SideCopies&) = delete;
     ~SideCopies() {
+        (void)hipStreamSynchronize(side);   // its copies wait for no kernel: back to the list idle
         if (done) (void)hipEventDestroy(done);
         release_stream(ctx, side);
     }

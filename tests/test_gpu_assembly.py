@@ -151,6 +151,40 @@ def test_panels_with_unused_vertices_and_without_dofs(ctx):
         x.close()
 
 
+def test_concurrent_panel_assemblies(ctx):
+    # panel-by-panel assemblies on several threads at once share the context's buffer cache and
+    # stream list (each takes a problem stream and an upload stream) and return with their panels
+    # queued: each W equals the one assembled alone
+    import threading
+    ms = small_meshes()
+    names = ["book6", "crossed6", "extruded", "square8"]
+    print("case concurrent panels", flush=True)
+    ref = {}
+    for n in names:
+        p = lib.Problem(ctx, ms[n].vertices, ms[n].triangles, near_order=NEAR, pair_panel_rows=64)
+        ref[n] = p.matrix()
+        p.close()
+    out, errs = {}, []
+
+    def work(n):
+        try:
+            for _ in range(2):
+                q = lib.Problem(ctx, ms[n].vertices, ms[n].triangles, near_order=NEAR, pair_panel_rows=64)
+                out.setdefault(n, []).append(q.matrix())
+                q.close()
+        except Exception as e:   # reported below, on the test's thread
+            errs.append((n, e))
+
+    th = [threading.Thread(target=work, args=(n,)) for n in names]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errs, errs
+    for n in names:
+        assert all(np.array_equal(Wc, ref[n]) for Wc in out[n]), n
+
+
 @pytest.mark.parametrize("name", ["book6", "crossed6"])
 def test_panels_planned_after_analysis(ctx, name, monkeypatch):
     # the path a mesh takes when its sector analysis numbers the dofs otherwise than the forecast

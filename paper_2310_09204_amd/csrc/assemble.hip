@@ -1018,8 +1018,8 @@ ContractPlan contract_plan(const MeshTopo& m) {
 // ---- panel-by-panel assembly -------------------------------------------------------------------
 // For meshes whose N_T x N_T pair matrix does not fit next to W: the dof row blocks (64 dofs) are
 // grouped into panels whose rows number at most maxrows.  The rows of a panel are the triangles at
-// the vertices of its blocks' dofs (the stars of those dofs, and at a vertex of a screen's boundary
-// sector also the triangles no star of it holds).  A panel computes I_P = I(R, [tmin, N_T)) for
+// the vertices of its blocks' dofs (the stars of those dofs, plus the few triangles at such a vertex
+// whose jump coefficients there all vanish).  A panel computes I_P = I(R, [tmin, N_T)) for
 // its rows R, each 64-row tile from the first column a tile (bd, be >= bd) of the panel can read
 // it at, the near pairs that fall in it, and then contracts its tiles of the upper half of W (the
 // mirrored writes fill the lower half).  Far work is about half of N_T^2 pairs in total, as in the

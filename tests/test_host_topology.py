@@ -64,9 +64,14 @@ def test_sector_counts_follow_from_vertex_counts():
     ms = [meshes.unit_square(8), meshes.book(6, (0.0, 75.0, 200.0, 300.0)), meshes.crossed(8),
           meshes.crossed(6, symmetric=True), meshes.bowtie(5), meshes.disk(5), meshes.book(12, (0.0, 100.0, 230.0))]
     ms += [meshes.random_extruded(rng, 4, lay, 5)[0] for lay in ("book", "chain", "tree")]
-    for m in ms:
-        h = lib.mesh_analyze(m.vertices, m.triangles)
-        q = _sectors_from_counts(m.vertices, m.triangles)
+    cases = [(np.asarray(m.vertices), np.asarray(m.triangles)) for m in ms]
+    # vertices that no triangle uses (no sector, no dof), spliced into the numbering
+    V, T = cases[1]
+    k = V.shape[0] // 2
+    cases.append((np.vstack([V[:k], [[5.0, 5.0, 5.0], [-5.0, 4.0, 3.0]], V[k:]]), np.where(T >= k, T + 2, T)))
+    for V, T in cases:
+        h = lib.mesh_analyze(V, T)
+        q = _sectors_from_counts(V, T)
         assert np.array_equal(np.asarray(h["q"]), q)
         assert h["n_dofs"] == int(np.maximum(q - 1, 0).sum())
 

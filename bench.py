@@ -50,12 +50,14 @@ def log(*a):
 
 def far_kernel_source_hash():
     """Hash of the far-field pass's own source text (its constants, the one-shot and the panel
-    kernels, through the panel kernel's closing brace), so that counters taken on an older version
-    are not reported."""
+    kernels, through the panel kernel's closing brace, and the panel tile list's order), so that
+    counters taken on an older version are not reported."""
     src = open(os.path.join(ROOT, "paper_2310_09204_amd", "csrc", "assemble.hip")).read()
     a = src.index("constexpr int kGrp")
     b = src.index("\n}\n", src.index("void k_far_rect(", a)) + 3
-    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
+    c = src.index("constexpr int kRowGroup")
+    d = src.index("\n}\n", src.index("void k_rect_tiles(", c)) + 3
+    return hashlib.sha256((src[a:b] + src[c:d]).encode()).hexdigest()[:16]
 
 
 def symv_bytes(N, size, ks):

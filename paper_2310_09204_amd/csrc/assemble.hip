@@ -1156,14 +1156,28 @@ PanelLayout layout_panels(const std::vector<int64_t>& first_dof, int64_t N, cons
     return L;
 }
 
-// Far-pass tiles of a panel: row tile rb takes the column tiles cstart[rb] .. nct - 1, at positions
-// tptr[rb] .. tptr[rb + 1] - 1 of the list (one block per row tile)
-__global__ void k_rect_tiles(const int32_t* __restrict__ cstart, const int64_t* __restrict__ tptr, int32_t nct,
-                             int2* __restrict__ out) {
-    const int rb = int(blockIdx.x);
-    const int c0 = cstart[rb];
-    const int64_t base = tptr[rb];
-    for (int c = c0 + int(threadIdx.x); c < nct; c += int(blockDim.x)) out[base + (c - c0)] = make_int2(rb, c);
+// Far-pass tiles of a panel.  Row tile rb takes the column tiles cstart[rb] .. nct - 1.  The row
+// tiles go in groups of kRowGroup, and a group lists its tiles column by column (row tiles in order
+// within a column), at positions gptr[g] .. gptr[g + 1] - 1.  The four waves of a workgroup then
+// read the same column records, and so do the workgroups next to it, which the dispatcher deals
+// round-robin to the XCDs: a column tile's records come from HBM about once per group and XCD
+// instead of once per row tile.  Column c's first position in its group is the number of the
+// group's tiles left of it, the sum over the group's row tiles of max(0, c - cstart[rb]).
+// Grid: (groups, column tiles / 256), one thread per column tile.
+constexpr int kRowGroup = 64;
+__global__ __launch_bounds__(256) void k_rect_tiles(const int32_t* __restrict__ cstart, const int64_t* __restrict__ gptr,
+                                                    int32_t nrt, int32_t nct, int2* __restrict__ out) {
+    __shared__ int32_t cs[kRowGroup];
+    const int g = int(blockIdx.x);
+    const int rb0 = g * kRowGroup, nr = min(kRowGroup, nrt - rb0);
+    if (int(threadIdx.x) < nr) cs[threadIdx.x] = cstart[rb0 + int(threadIdx.x)];
+    __syncthreads();
+    const int c = int(blockIdx.y) * int(blockDim.x) + int(threadIdx.x);
+    if (c >= nct) return;
+    int64_t pos = gptr[g];
+    for (int i = 0; i < nr; ++i) pos += max(0, c - cs[i]);
+    for (int i = 0; i < nr; ++i)
+        if (cs[i] <= c) out[pos++] = make_int2(rb0 + i, c);
 }
 
 // A second stream for host-to-device copies, so that they run beside the kernels queued on the
@@ -1246,23 +1260,25 @@ class PanelRun {
         P->rowmap.assign(static_cast<size_t>(nt_), -1);
         for (int64_t r = 0; r < nrows; ++r) P->rowmap[size_t(R[size_t(r)])] = int32_t(r);
         const int64_t nrt = (nrows + kTile - 1) / kTile, nct = (ncol + kTile - 1) / kTile;
+        const int64_t ngr = (nrt + kRowGroup - 1) / kRowGroup;
         P->cstart.assign(static_cast<size_t>(std::max<int64_t>(nrt, 1)), 0);
-        P->tptr.assign(static_cast<size_t>(nrt) + 1, 0);
+        P->tptr.assign(static_cast<size_t>(ngr) + 1, 0);   // tiles before each group of row tiles
         for (int64_t rb = 0; rb < nrt; ++rb) {
             int64_t cmin = nt_;
             for (int64_t r = rb * kTile; r < std::min<int64_t>(nrows, rb * kTile + kTile); ++r)
                 cmin = std::min<int64_t>(cmin, L_.rowfirst[pid][size_t(r)]);
             const int64_t cs = std::min<int64_t>(nct, std::max<int64_t>(0, cmin - t0) / kTile);
             P->cstart[size_t(rb)] = int32_t(cs);
-            P->tptr[size_t(rb) + 1] = P->tptr[size_t(rb)] + (nct - cs);
+            P->tptr[size_t(rb / kRowGroup) + 1] += nct - cs;
         }
-        const int64_t nft = P->tptr[size_t(nrt)];
+        for (int64_t g = 0; g < ngr; ++g) P->tptr[size_t(g) + 1] += P->tptr[size_t(g)];
+        const int64_t nft = P->tptr[size_t(ngr)];
         DeviceBuffer d_rows = up_.upload(R), d_cs = up_.upload(P->cstart), d_tp = up_.upload(P->tptr);
         P->d_rowmap = up_.upload(P->rowmap);
         DeviceBuffer d_ft(sizeof(int2) * size_t(std::max<int64_t>(nft, 1)), s_);
         if (nft > 0) {
-            hipLaunchKernelGGL(k_rect_tiles, dim3(unsigned(nrt)), dim3(256), 0, s_, d_cs.as<int32_t>(), d_tp.as<int64_t>(),
-                               int32_t(nct), d_ft.as<int2>());
+            hipLaunchKernelGGL(k_rect_tiles, dim3(unsigned(ngr), unsigned((nct + 255) / 256)), dim3(256), 0, s_,
+                               d_cs.as<int32_t>(), d_tp.as<int64_t>(), int32_t(nrt), int32_t(nct), d_ft.as<int2>());
             HIP_CHECK(hipGetLastError());
         }
         P->ef = std::make_unique<EventTimer>(s_);

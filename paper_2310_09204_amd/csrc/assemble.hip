@@ -1508,10 +1508,13 @@ void assemble_device(bem_problem* p, const double* Vin, int64_t nv, const int32_
         p->ldI = ldI;
         p->I = DeviceBuffer(sizeof(double) * nt * ldI, s);
         const int nb = int((nt + kTile - 1) / kTile);
+        // tiles (rb, cb >= rb) in groups of kRowGroup row tiles, column by column within a group (the
+        // order of the panels' tile lists, for the same reuse of the column records)
         std::vector<int2> tiles;
         tiles.reserve(size_t(nb) * (nb + 1) / 2);
-        for (int rb = 0; rb < nb; ++rb)
-            for (int cb = rb; cb < nb; ++cb) tiles.push_back(make_int2(rb, cb));
+        for (int g0 = 0; g0 < nb; g0 += kRowGroup)
+            for (int cb = g0; cb < nb; ++cb)
+                for (int rb = g0; rb < std::min(g0 + kRowGroup, cb + 1); ++rb) tiles.push_back(make_int2(rb, cb));
         DeviceBuffer dtiles = upload(tiles, s);
         HIP_CHECK(hipEventRecord(t_far.a, s));
         const int64_t nti = int64_t(tiles.size());

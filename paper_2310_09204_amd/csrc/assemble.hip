@@ -1262,23 +1262,23 @@ class PanelRun {
         const int64_t nrt = (nrows + kTile - 1) / kTile, nct = (ncol + kTile - 1) / kTile;
         const int64_t ngr = (nrt + kRowGroup - 1) / kRowGroup;
         P->cstart.assign(static_cast<size_t>(std::max<int64_t>(nrt, 1)), 0);
-        P->tptr.assign(static_cast<size_t>(ngr) + 1, 0);   // tiles before each group of row tiles
+        P->gptr.assign(static_cast<size_t>(ngr) + 1, 0);   // tiles before each group of row tiles
         for (int64_t rb = 0; rb < nrt; ++rb) {
             int64_t cmin = nt_;
             for (int64_t r = rb * kTile; r < std::min<int64_t>(nrows, rb * kTile + kTile); ++r)
                 cmin = std::min<int64_t>(cmin, L_.rowfirst[pid][size_t(r)]);
             const int64_t cs = std::min<int64_t>(nct, std::max<int64_t>(0, cmin - t0) / kTile);
             P->cstart[size_t(rb)] = int32_t(cs);
-            P->tptr[size_t(rb / kRowGroup) + 1] += nct - cs;
+            P->gptr[size_t(rb / kRowGroup) + 1] += nct - cs;
         }
-        for (int64_t g = 0; g < ngr; ++g) P->tptr[size_t(g) + 1] += P->tptr[size_t(g)];
-        const int64_t nft = P->tptr[size_t(ngr)];
-        DeviceBuffer d_rows = up_.upload(R), d_cs = up_.upload(P->cstart), d_tp = up_.upload(P->tptr);
+        for (int64_t g = 0; g < ngr; ++g) P->gptr[size_t(g) + 1] += P->gptr[size_t(g)];
+        const int64_t nft = P->gptr[size_t(ngr)];
+        DeviceBuffer d_rows = up_.upload(R), d_cs = up_.upload(P->cstart), d_gp = up_.upload(P->gptr);
         P->d_rowmap = up_.upload(P->rowmap);
         DeviceBuffer d_ft(sizeof(int2) * size_t(std::max<int64_t>(nft, 1)), s_);
         if (nft > 0) {
             hipLaunchKernelGGL(k_rect_tiles, dim3(unsigned(ngr), unsigned((nct + 255) / 256)), dim3(256), 0, s_,
-                               d_cs.as<int32_t>(), d_tp.as<int64_t>(), int32_t(nrt), int32_t(nct), d_ft.as<int2>());
+                               d_cs.as<int32_t>(), d_gp.as<int64_t>(), int32_t(nrt), int32_t(nct), d_ft.as<int2>());
             HIP_CHECK(hipGetLastError());
         }
         P->ef = std::make_unique<EventTimer>(s_);
@@ -1399,7 +1399,7 @@ class PanelRun {
     struct Panel {   // host arrays stay alive until the end: their uploads are asynchronous
         int64_t ldP = 0;
         std::vector<int32_t> rowmap, cstart, nv[4], na[4], nb[4];
-        std::vector<int64_t> tptr, tgt[4];
+        std::vector<int64_t> gptr, tgt[4];
         DeviceBuffer d_rowmap;
         std::unique_ptr<EventTimer> ef, en, ec;
     };

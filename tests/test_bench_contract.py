@@ -46,3 +46,16 @@ def test_several_gpus_are_refused_with_a_message():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_traffic_record_is_consistent():
+    # bytes per launch = (scaled FETCH + scaled WRITE per step) / launches per step, and the summary
+    # the record names is committed beside it
+    import json
+    rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
+    for kernel, per in rec.items():
+        for workload, e in per.items():
+            total = e["fetch_bytes_per_step"] + e["write_bytes_per_step"]
+            assert abs(e["bytes_per_launch"] * e["launches_per_step"] - total) <= 1e-9 * total
+            assert e["write_bytes_per_step"] > 0 and e["fetch_scale"] > 0 and e["write_scale"] > 0
+            assert os.path.isfile(os.path.join(ROOT, e["summary"]))
